@@ -1,0 +1,125 @@
+"""Unit tests of the seeded input generators (graphs and fixed-point exponential shifts)."""
+import math
+
+import numpy as np
+import pytest
+import scipy.stats
+
+import inputs
+
+
+def check_csr(rp, ci):
+    n = rp.size - 1
+    assert rp[0] == 0 and np.all(np.diff(rp) >= 0) and rp[-1] == ci.size
+    if ci.size:
+        assert ci.min() >= 0 and ci.max() < n
+    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp))
+    assert not np.any(src == ci), "self-loop"
+    key = src * n + ci
+    # sorted ascending within each row and no duplicates
+    assert np.all(np.diff(key) > 0)
+    # symmetric: the reversed arc set equals the arc set
+    rkey = np.sort(ci.astype(np.int64) * n + src)
+    assert np.array_equal(rkey, key)
+
+
+def test_grid2d_counts():
+    rp, ci = inputs.grid2d(64, 64)
+    assert rp.size - 1 == 4096 and ci.size == 2 * 8064
+    check_csr(rp, ci)
+    rp, ci = inputs.grid2d(3, 5)
+    assert ci.size // 2 == 3 * 4 + 5 * 2
+    check_csr(rp, ci)
+
+
+def test_grid3d_counts():
+    rp, ci = inputs.grid3d(16, 16, 16)
+    assert rp.size - 1 == 4096 and ci.size // 2 == 3 * 16 * 16 * 15
+    check_csr(rp, ci)
+    rp, ci = inputs.grid3d(2, 3, 4)
+    assert ci.size // 2 == 1 * 3 * 4 + 2 * 2 * 4 + 2 * 3 * 3
+    check_csr(rp, ci)
+
+
+def test_rmat_structure_and_relabel_is_isomorphism():
+    rp, ci = inputs.rmat(12, 16, seed=7, relabel=True)
+    check_csr(rp, ci)
+    rp0, ci0 = inputs.rmat(12, 16, seed=7, relabel=False)
+    check_csr(rp0, ci0)
+    assert rp.size == rp0.size == 4097
+    # relabelling is a bijection of ids: same edge count and degree multiset
+    assert ci.size == ci0.size
+    assert np.array_equal(np.sort(np.diff(rp)), np.sort(np.diff(rp0)))
+    # unrelabelled RMAT puts the heaviest vertex at id 0 (quadrant a is the most likely)
+    assert np.argmax(np.diff(rp0)) == 0
+    # at most edgefactor * 2^scale undirected edges survive clean-up
+    assert ci.size // 2 <= 16 * 4096
+
+
+def test_rmat_deterministic():
+    a = inputs.rmat(10, 8, seed=3)
+    b = inputs.rmat(10, 8, seed=3)
+    c = inputs.rmat(10, 8, seed=4)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert not (a[1].size == c[1].size and np.array_equal(a[1], c[1]))
+
+
+def test_er_mean_degree():
+    n = 20000
+    rp, ci = inputs.er(n, 8.0, seed=11)
+    check_csr(rp, ci)
+    mean = ci.size / n
+    # number of edges ~ Binomial(n(n-1)/2, p): sd of the mean degree is about sqrt(8/n)*sqrt(2)
+    assert abs(mean - 8.0) < 6 * math.sqrt(2 * 8.0 / n)
+
+
+def test_rgg_mean_degree():
+    n = 20000
+    rp, ci = inputs.rgg(n, 6.0, seed=5)
+    check_csr(rp, ci)
+    r = math.sqrt(6.0 / (math.pi * n))
+    # expected area of a radius-r disk around a uniform point, clipped to the unit square
+    area = math.pi * r * r - 8.0 * r ** 3 / 3.0 + r ** 4 / 2.0
+    expect = (n - 1) * area
+    assert abs(ci.size / n - expect) < 0.15
+
+
+def test_from_edges_dedup_and_selfloops():
+    rp, ci = inputs.from_edges(4, [0, 1, 1, 2, 3, 0], [1, 0, 1, 3, 2, 1])
+    check_csr(rp, ci)
+    assert ci.tolist() == [1, 0, 3, 2]
+    assert rp.tolist() == [0, 1, 2, 3, 4]
+
+
+def test_shifts_exponential_distribution():
+    beta = 0.1
+    s = inputs.make_shifts(200_000, beta, seed=1)
+    assert s.dtype == np.int64 and s.min() >= 0
+    x = (s.astype(np.float64) + 0.5) / inputs.FIX_ONE
+    assert abs(x.mean() - 1 / beta) < 6 * (1 / beta) / math.sqrt(s.size)
+    stat = scipy.stats.kstest(x, "expon", args=(0, 1 / beta))
+    assert stat.pvalue > 1e-4
+
+
+def test_shifts_deterministic_and_prefix_stable():
+    a = inputs.make_shifts(1000, 0.05, seed=9)
+    b = inputs.make_shifts(2000, 0.05, seed=9)
+    assert np.array_equal(a, b[:1000])  # counter-based: draw i does not depend on n
+    c = inputs.make_shifts(1000, 0.05, seed=10)
+    assert not np.array_equal(a, c)
+    # beta only scales: floor(2^20 * E/beta) from the same uniforms
+    d = inputs.make_shifts(1000, 0.1, seed=9)
+    assert np.all(np.abs(d * 2 - a) <= 2)
+
+
+def test_batch_recipe_ranges():
+    rec = inputs.batch_recipe(512, seed=1)
+    assert len(rec) == 512
+    ns = np.array([r[1] for r in rec])
+    betas = np.array([r[2] for r in rec])
+    assert ns.min() >= 1000 and ns.max() <= 200_000
+    assert betas.min() >= 0.02 and betas.max() <= 0.3
+    assert [r[0] for r in rec[:4]] == ["er", "rgg", "er", "rgg"]
+    # log-uniform: the median of log n sits near the middle of the range
+    mid = 0.5 * (math.log(1000) + math.log(200_000))
+    assert abs(np.median(np.log(ns)) - mid) < 0.5

@@ -1,0 +1,399 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+The oracle (``oracle/``) computes, for every vertex v, the centre
+    argmin_u (2^20 * dist(u,v) - shift_fix[u], u)      (Algorithm 2, Sec. 4; Eq. (1), Sec. 3)
+and the cut of Def. 1.1.  These tests check it against
+  * brute force: all-pairs unweighted distances from scipy's csgraph plus a lexicographic
+    argmin in numpy -- the definition, computed by code the oracle does not use;
+  * closed forms for special shift patterns;
+  * the structural facts the paper proves: Lemma 4.1 (each vertex's shortest path to its
+    centre stays in the piece, so pieces are connected) and the radius bound used in the
+    proof of Theorem 1.1 (dist(c(v),v) <= delta_c - delta_v);
+  * the statistical claims of Lemma 4.2 (E[max shift] = H_n / beta, all shifts below
+    (d+1) ln n / beta w.h.p.) and Corollary 4.5 (an edge is cut with probability at most
+    1 - exp(-beta)).
+Planted mistakes in the oracle (a dropped tie-break, a sign, an edge length, truncated
+shifts) must each fail at least one of these pins.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse
+import scipy.sparse.csgraph
+
+import inputs
+import oracle
+
+S = 1 << 20
+
+
+# ------------------------------------------------------------------------------------------
+# independent brute force
+# ------------------------------------------------------------------------------------------
+def all_pairs(rp, ci):
+    n = rp.size - 1
+    if n == 0:
+        return np.zeros((0, 0))
+    a = scipy.sparse.csr_matrix((np.ones(ci.size), ci, rp), shape=(n, n))
+    return scipy.sparse.csgraph.shortest_path(a, method="D", unweighted=True, directed=False)
+
+
+def brute_force(rp, ci, s):
+    n = rp.size - 1
+    if n == 0:
+        return np.zeros(0, np.int32), 0
+    d = all_pairs(rp, ci)
+    big = np.int64(1) << 62
+    keys = np.where(np.isinf(d), big, S * np.nan_to_num(d, posinf=0).astype(np.int64) - s[:, None].astype(np.int64))
+    # keys[u, v]; argmin over u returns the first (smallest) u among equal minima
+    centre = np.argmin(keys, axis=0).astype(np.int32)
+    src = np.repeat(np.arange(n), np.diff(rp))
+    cut = int(np.count_nonzero(centre[src] != centre[ci]) // 2)
+    return centre, cut
+
+
+# ------------------------------------------------------------------------------------------
+# small graph and shift families
+# ------------------------------------------------------------------------------------------
+def path(n):
+    return inputs.from_edges(n, np.arange(n - 1), np.arange(1, n))
+
+
+def cycle(n):
+    return inputs.from_edges(n, np.arange(n), (np.arange(n) + 1) % n)
+
+
+def star(n):
+    return inputs.from_edges(n, np.zeros(n - 1, np.int32), np.arange(1, n))
+
+
+def complete(n):
+    iu = np.triu_indices(n, 1)
+    return inputs.from_edges(n, iu[0], iu[1])
+
+
+def random_graph(rng, n, p):
+    iu = np.triu_indices(n, 1)
+    keep = rng.random(iu[0].size) < p
+    return inputs.from_edges(n, iu[0][keep], iu[1][keep])
+
+
+def disjoint_union(*gs):
+    src, dst, off = [], [], 0
+    for rp, ci in gs:
+        n = rp.size - 1
+        s = np.repeat(np.arange(n), np.diff(rp))
+        src.append(s + off)
+        dst.append(ci + off)
+        off += n
+    return inputs.from_edges(off, np.concatenate(src), np.concatenate(dst))
+
+
+def shift_family(rng, n, kind):
+    if kind == "exp":
+        beta = rng.choice([0.05, 0.2, 0.5, 1.5])
+        return np.floor(rng.exponential(1 / beta, n) * S).astype(np.int64)
+    if kind == "integer":  # tie-heavy: whole multiples of the unit distance
+        return (rng.integers(0, 4, n) * S).astype(np.int64)
+    if kind == "equal":
+        return np.full(n, 3 * S + 17, np.int64)
+    if kind == "tiny":  # all below one unit of distance
+        return rng.integers(0, 3, n).astype(np.int64)
+    if kind == "mixed":  # integer parts plus a fraction from a two-element set
+        return (rng.integers(0, 3, n) * S + rng.integers(0, 2, n)).astype(np.int64)
+    raise ValueError(kind)
+
+
+KINDS = ("exp", "integer", "equal", "tiny", "mixed")
+
+
+def small_cases(seed=0, count=60):
+    rng = np.random.default_rng(seed)
+    fixed = [path(1), path(2), path(7), cycle(9), star(8), complete(6), inputs.grid2d(5, 7),
+             disjoint_union(path(4), cycle(5), complete(4)), inputs.from_edges(5, [], []),
+             disjoint_union(star(5), inputs.from_edges(3, [], []))]
+    graphs = list(fixed)
+    for _ in range(count):
+        n = int(rng.integers(2, 40))
+        graphs.append(random_graph(rng, n, float(rng.choice([0.05, 0.1, 0.3, 0.8]))))
+    cases = []
+    for i, (rp, ci) in enumerate(graphs):
+        for kind in KINDS:
+            cases.append((rp, ci, shift_family(rng, rp.size - 1, kind), f"g{i}-{kind}"))
+    return cases
+
+
+CASES = small_cases()
+
+
+# ------------------------------------------------------------------------------------------
+# brute force
+# ------------------------------------------------------------------------------------------
+def test_oracle_matches_brute_force():
+    for rp, ci, s, name in CASES:
+        c, length, cut = oracle.decompose(rp, ci, s)
+        bc, bcut = brute_force(rp, ci, s)
+        assert np.array_equal(c, bc), name
+        assert cut == bcut, name
+        # length[v] = Delta + 2^20 dist(c,v) - shift[c]
+        if s.size:
+            d = all_pairs(rp, ci)
+            expect = s.max() + S * d[c, np.arange(s.size)].astype(np.int64) - s[c]
+            assert np.array_equal(length, expect), name
+
+
+def test_centre_of_matches_brute_force():
+    for rp, ci, s, name in CASES[::3]:
+        n = rp.size - 1
+        bc, _ = brute_force(rp, ci, s)
+        for v in range(n):
+            c, val = oracle.centre_of(rp, ci, s, v)
+            assert c == bc[v], (name, v)
+
+
+def test_hypothesis_random_graphs():
+    hyp = pytest.importorskip("hypothesis")
+    st = hyp.strategies
+
+    @hyp.settings(max_examples=150, deadline=None, derandomize=True)
+    @hyp.given(st.integers(1, 24).flatmap(lambda n: st.tuples(
+        st.just(n),
+        st.lists(st.tuples(st.integers(0, n - 1), st.integers(0, n - 1)), max_size=3 * n),
+        st.lists(st.integers(0, 5 * S), min_size=n, max_size=n) |
+        st.lists(st.integers(0, 4).map(lambda k: k * S), min_size=n, max_size=n))))
+    def run(args):
+        n, edges, shifts = args
+        src = [e[0] for e in edges]
+        dst = [e[1] for e in edges]
+        rp, ci = inputs.from_edges(n, src, dst)
+        s = np.array(shifts, np.int64)
+        c, _, cut = oracle.decompose(rp, ci, s)
+        bc, bcut = brute_force(rp, ci, s)
+        assert np.array_equal(c, bc) and cut == bcut
+
+    run()
+
+
+# ------------------------------------------------------------------------------------------
+# closed forms
+# ------------------------------------------------------------------------------------------
+def test_no_edges_every_vertex_alone():
+    rp, ci = inputs.from_edges(50, [], [])
+    s = np.arange(50, dtype=np.int64) * 977
+    c, _, cut = oracle.decompose(rp, ci, s)
+    assert np.array_equal(c, np.arange(50)) and cut == 0
+
+
+def test_shifts_below_one_unit_give_singletons():
+    # every shift < 2^20: a neighbour's offer 2^20 - s_u > 0 >= -s_v, so each vertex keeps itself
+    rng = np.random.default_rng(3)
+    for rp, ci in (inputs.grid2d(9, 11), random_graph(rng, 40, 0.2), complete(7)):
+        s = rng.integers(0, S, rp.size - 1).astype(np.int64)
+        c, _, cut = oracle.decompose(rp, ci, s)
+        assert np.array_equal(c, np.arange(rp.size - 1))
+        assert cut == ci.size // 2
+
+
+def test_equal_shifts_give_singletons():
+    rp, ci = inputs.grid2d(6, 6)
+    c, _, cut = oracle.decompose(rp, ci, np.full(36, 5 * S, np.int64))
+    assert np.array_equal(c, np.arange(36)) and cut == ci.size // 2
+
+
+def test_dominant_shift_takes_connected_graph():
+    # delta_z >= 2^20 (ecc(z)+1) + max others: z's value beats every other vertex everywhere
+    rp, ci = inputs.grid2d(8, 8)
+    rng = np.random.default_rng(5)
+    s = rng.integers(0, 3 * S, 64).astype(np.int64)
+    z = 27
+    s[z] = S * (14 + 1) + s.max()  # eccentricity of any vertex of an 8x8 grid is at most 14
+    c, _, cut = oracle.decompose(rp, ci, s)
+    assert np.all(c == z) and cut == 0
+
+
+def test_tie_goes_to_smaller_id():
+    # two adjacent vertices with shifts differing by exactly one unit of distance tie
+    rp, ci = path(2)
+    c, _, _ = oracle.decompose(rp, ci, np.array([S + 5, 5], np.int64))
+    assert c.tolist() == [0, 0]  # vertex 1: (2^20 - s0, 0) == (-s1, 1) in key, 0 < 1 wins
+    c, _, _ = oracle.decompose(rp, ci, np.array([5, S + 5], np.int64))
+    assert c.tolist() == [0, 1]  # vertex 0: own (-s0, 0) ties with (2^20 - s1, 1); 0 < 1 keeps itself
+
+
+@pytest.mark.parametrize("length,z,D", [(12, 5, 3), (15, 0, 4), (15, 14, 6), (9, 4, 1), (20, 10, 0)])
+def test_path_single_bump(length, z, D):
+    # path 0-1-..-(L-1); shift D units at z, 0 elsewhere.  v joins z iff
+    # 2^20 |v-z| - D 2^20 < 0, or equal and z < v; otherwise v keeps itself.
+    rp, ci = path(length)
+    s = np.zeros(length, np.int64)
+    s[z] = D * S
+    c, _, cut = oracle.decompose(rp, ci, s)
+    expect = [z if (abs(v - z) < D or (abs(v - z) == D and z < v)) else v for v in range(length)]
+    assert c.tolist() == expect
+    assert cut == sum(expect[v] != expect[v + 1] for v in range(length - 1))
+
+
+def test_complete_graph_formula():
+    # K_n: every u != v is at distance 1.  Let u*(v) = lex-argmin over u != v of (-s_u, u).
+    # Then c(v) = u* when (2^20 - s_u*, u*) < (-s_v, v) lexicographically, else v.
+    rng = np.random.default_rng(8)
+    for trial in range(40):
+        n = int(rng.integers(2, 12))
+        rp, ci = complete(n)
+        s = (rng.integers(0, 4, n) * S + rng.integers(0, 2, n) * (trial % 2)).astype(np.int64)
+        c, _, _ = oracle.decompose(rp, ci, s)
+        for v in range(n):
+            others = [(-int(s[u]), u) for u in range(n) if u != v]
+            m = min(others)
+            ustar = m[1]
+            expect = ustar if (S - int(s[ustar]), ustar) < (-int(s[v]), v) else v
+            assert c[v] == expect
+
+
+# ------------------------------------------------------------------------------------------
+# structural facts (Lemma 4.1, the radius bound in the proof of Theorem 1.1)
+# ------------------------------------------------------------------------------------------
+def piece_distances(rp, ci, c):
+    """BFS distance from each centre inside its own piece (-1 if unreachable)."""
+    n = rp.size - 1
+    d = np.full(n, -1, np.int64)
+    q = [v for v in range(n) if c[v] == v]
+    for v in q:
+        d[v] = 0
+    head = 0
+    while head < len(q):
+        u = q[head]
+        head += 1
+        for w in ci[rp[u]:rp[u + 1]]:
+            if d[w] < 0 and c[w] == c[u]:
+                d[w] = d[u] + 1
+                q.append(w)
+    return d
+
+
+def test_pieces_connected_shortest_paths_inside_and_radius_bound():
+    for rp, ci, s, name in CASES:
+        n = rp.size - 1
+        if n == 0:
+            continue
+        c, _, _ = oracle.decompose(rp, ci, s)
+        assert np.all(c[c] == c), name  # each centre is in its own piece
+        dp = piece_distances(rp, ci, c)
+        assert np.all(dp >= 0), name  # strong connectivity of each piece
+        dg = all_pairs(rp, ci)[c, np.arange(n)]
+        assert np.array_equal(dp, dg.astype(np.int64)), name  # Lemma 4.1
+        assert np.all(S * dp <= s[c] - s), name  # dist(c,v) - delta_c <= -delta_v
+
+
+# ------------------------------------------------------------------------------------------
+# statistics (Lemma 4.2, Corollary 4.5) on the 64x64 grid at beta = 0.1
+# ------------------------------------------------------------------------------------------
+def test_statistical_claims_grid64():
+    beta, k = 0.1, 200
+    rp, ci = inputs.grid2d(64, 64)
+    n, m = 4096, ci.size // 2
+    maxes, fracs = [], []
+    for seed in range(1, k + 1):
+        s = inputs.make_shifts(n, beta, seed)
+        c, _, cut = oracle.decompose(rp, ci, s)
+        dmax = s.max() / S
+        maxes.append(dmax)
+        fracs.append(cut / m)
+        # all shifts below (d+1) ln n / beta with d = 2 (fails with probability <= n^-2)
+        assert dmax <= 3 * math.log(n) / beta
+        # radius of every piece at most its centre's shift
+        dp = piece_distances(rp, ci, c)
+        assert np.all(S * dp <= s[c])
+    h_n = sum(1.0 / i for i in range(1, n + 1))
+    sd = math.sqrt(sum(1.0 / i ** 2 for i in range(1, n + 1))) / beta
+    assert abs(np.mean(maxes) - h_n / beta) < 4 * sd / math.sqrt(k)
+    se = np.std(fracs, ddof=1) / math.sqrt(k)
+    assert np.mean(fracs) <= 1 - math.exp(-beta) + 4 * se
+
+
+def test_order_statistic_gap_fact():
+    # Fact 3.1 at rate beta: the top gap X(n) - X(n-1) is Exp(beta), mean 1/beta
+    beta, k = 0.2, 400
+    gaps = []
+    for seed in range(k):
+        s = np.sort(inputs.make_shifts(500, beta, 10_000 + seed))
+        gaps.append((s[-1] - s[-2]) / S)
+    assert abs(np.mean(gaps) - 1 / beta) < 4 * (1 / beta) / math.sqrt(k)
+
+
+# ------------------------------------------------------------------------------------------
+# certificate checker
+# ------------------------------------------------------------------------------------------
+def test_certificate_accepts_exact_and_rejects_everything_else():
+    rng = np.random.default_rng(21)
+    for rp, ci, s, name in CASES:
+        n = rp.size - 1
+        if n == 0:
+            continue
+        c, _, _ = oracle.decompose(rp, ci, s)
+        assert oracle.certify(rp, ci, s, c)[0] == oracle.OK, name
+        # every wrong assignment produced by a planted mistake is rejected
+        for mut in oracle.MUTATIONS:
+            cm, _, _ = oracle.decompose(rp, ci, s, mutation=mut)
+            ok = oracle.certify(rp, ci, s, cm)[0] == oracle.OK
+            assert ok == bool(np.array_equal(cm, c)), (name, mut)
+        # a single vertex moved to a neighbour's piece is rejected
+        src = np.repeat(np.arange(n), np.diff(rp))
+        diff = np.nonzero(c[src] != c[ci])[0]
+        if diff.size:
+            a = diff[rng.integers(0, diff.size)]
+            bad = c.copy()
+            bad[src[a]] = c[ci[a]]
+            assert oracle.certify(rp, ci, s, bad)[0] != oracle.OK, name
+
+
+def test_certificate_large_rmat():
+    rp, ci = inputs.rmat(16, 16, seed=2)
+    s = inputs.make_shifts(rp.size - 1, 0.05, 2)
+    c, _, cut = oracle.decompose(rp, ci, s)
+    assert oracle.certify(rp, ci, s, c)[0] == oracle.OK
+    assert oracle.cut(rp, ci, c) == cut
+    for v in np.random.default_rng(0).integers(0, rp.size - 1, 20):
+        assert oracle.centre_of(rp, ci, s, int(v))[0] == c[v]
+
+
+# ------------------------------------------------------------------------------------------
+# planted mistakes must fail a pin
+# ------------------------------------------------------------------------------------------
+def pins_fail(mutation):
+    failures = []
+    for rp, ci, s, name in CASES:
+        c, _, cut = oracle.decompose(rp, ci, s, mutation=mutation)
+        bc, bcut = brute_force(rp, ci, s)
+        if not np.array_equal(c, bc) or cut != bcut:
+            failures.append(("brute", name))
+            break
+    rp, ci = path(2)
+    c, _, _ = oracle.decompose(rp, ci, np.array([S + 5, 5], np.int64), mutation=mutation)
+    if c.tolist() != [0, 0]:
+        failures.append(("tie", ""))
+    rp, ci = path(12)
+    s = np.zeros(12, np.int64)
+    s[5] = 3 * S
+    c, _, _ = oracle.decompose(rp, ci, s, mutation=mutation)
+    if c.tolist() != [0, 1, 2, 5, 5, 5, 5, 5, 5, 9, 10, 11]:
+        failures.append(("bump", ""))
+    return failures
+
+
+def test_pins_pass_on_the_oracle():
+    assert pins_fail(oracle.MUT_NONE) == []
+
+
+@pytest.mark.parametrize("mutation", oracle.MUTATIONS)
+def test_planted_mistake_is_caught(mutation):
+    assert pins_fail(mutation), f"mutation {mutation} not caught"
+
+
+def test_bad_arguments_rejected():
+    rp, ci = path(3)
+    with pytest.raises(oracle.OracleError):
+        oracle.decompose(rp, ci, np.array([0, -1, 0], np.int64))
+    with pytest.raises(oracle.OracleError):
+        oracle.decompose(np.array([0, 1, 1, 5], np.int32), np.array([1, 0, 9, 9, 9], np.int32), np.zeros(3, np.int64))
