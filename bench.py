@@ -1,0 +1,169 @@
+"""Benchmark: exponential-shift low-diameter decomposition on one MI355X.
+
+One step = one whole decomposition (Delta reduction, wake-round sort, all rounds, centre
+extraction, cut count) of the RMAT scale-24 graph (edge factor 16, a,b,c = .57,.19,.19,
+symmetrised, relabelled; 16.7M vertices, 260M edges) with beta = 0.05 and seeded Exp
+shifts, inputs resident in HBM.  Prints one JSON line.
+
+  value        GTEPS = undirected edges / seconds per step (whole graph)
+  roofline     the round kernel: algorithmic bytes / its average duration (HIP events on the
+               launch stream), against 8 TB/s HBM3E
+  cpu_baseline the CPU oracle (single-threaded Dijkstra) on a bounded sample of the same
+               workload family (RMAT scale 22), on this host
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rmat-24] [--no-cpu-baseline]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "GTEPS + decompositions/s, p50/p99 latency; batched vs plain, bit-exact"
+GOLDEN = os.path.join(ROOT, "tests", "golden", "oracle_digests.json")
+TRAFFIC = os.path.join(ROOT, "profiles", "traffic_rounds.json")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(st):
+    """Bytes the round kernel must move: per arc read, its column id (4 B) and the far end's
+    label (8 B); per non-isolated vertex, its two row offsets (8 B), shift (8 B), label
+    written (8 B) and queue entry written and read back (16 B)."""
+    return 12 * st["arcs_examined"] + 40 * st["n_active"]
+
+
+def kernel_sources_sha():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1307_3692_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch of the round kernel from the committed rocprofv3 counter runs,
+    or None when they were taken on other kernel sources or another workload."""
+    if not os.path.exists(TRAFFIC):
+        return None
+    with open(TRAFFIC) as f:
+        t = json.load(f)
+    if t.get("kernel_sources_sha") != kernel_sources_sha() or t.get("workload") != workload:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(sample="rmat-22"):
+    import oracle  # the CPU leg only
+
+    import inputs
+    rp, ci, s, beta = inputs.workload(sample)
+    t = time.perf_counter()
+    oracle.decompose(rp, ci, s)
+    dt = time.perf_counter() - t
+    return {"value": round(ci.size / 2 / dt / 1e9, 6), "unit": "GTEPS", "cores": 1, "kind": "oracle",
+            "sample": f"{sample}: RMAT scale 22, same generator and beta, n={rp.size - 1}, m={ci.size // 2}, "
+                      f"1 run of {dt:.1f} s single-threaded"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="rmat-24")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--engine", type=int, default=0)
+    ap.add_argument("--direction", type=int, default=0)
+    ap.add_argument("--blocks", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the decomposition of one graph "
+              "is sized for one MI355X; see DESIGN.md for how it would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import inputs
+    import paper_1307_3692_amd as ldd
+
+    t = time.time()
+    rp, ci, s, beta = inputs.workload(args.workload)
+    n, nnz = rp.size - 1, ci.size
+    m = nnz // 2
+    log(f"workload {args.workload}: n={n} m={m} beta={beta} generated in {time.time() - t:.1f}s")
+    dev = torch.device("cuda:0")
+    d_rp, d_ci, d_s = (torch.from_numpy(a).to(dev) for a in (rp, ci, s))
+    centre = torch.empty(n, dtype=torch.int32, device=dev)
+    opts = dict(engine=args.engine, direction=args.direction, blocks=args.blocks)
+    for _ in range(args.warmup):
+        ldd.decompose(d_rp, d_ci, d_s, beta, centre=centre, **opts)
+    torch.cuda.synchronize()
+    lat, rounds_ms, stats = [], [], None
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        a = time.perf_counter()
+        _, cut, stats = ldd.decompose(d_rp, d_ci, d_s, beta, centre=centre, stats=True, **opts)
+        lat.append(time.perf_counter() - a)
+        rounds_ms.append(stats["ms_rounds"])
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    ms_step = total / args.steps * 1e3
+    log(f"steps {args.steps}: {ms_step:.3f} ms/step, rounds kernel {np.mean(rounds_ms):.3f} ms, stats {stats}")
+
+    bit_exact = None
+    if os.path.exists(GOLDEN):
+        with open(GOLDEN) as f:
+            gold = json.load(f).get(args.workload)
+        if gold:
+            got = centre.cpu().numpy()
+            bit_exact = bool(hashlib.sha256(got.view(np.uint8)).hexdigest() == gold["sha_centre"]
+                             and cut == gold["cut"])
+
+    t_rounds = float(np.mean(rounds_ms)) * 1e-3
+    alg = algorithmic_bytes(stats)
+    achieved = alg / t_rounds / 1e9 if t_rounds > 0 else 0.0
+    traffic = measured_traffic(args.workload)
+    out = {
+        "metric": METRIC,
+        "value": round(m / (ms_step * 1e-3) / 1e9, 4),
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "m": m, "beta": beta, "graph_seed": 1, "shift_seed": 1,
+                   "engine": ["auto(launch)", "persistent", "launch"][args.engine], "parallelism": "single-gpu"},
+        "decompositions_per_s": round(1e3 / ms_step, 3),
+        "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 4),
+        "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 4),
+        "bit_exact": bit_exact,
+        "rounds": stats["rounds"], "td_rounds": stats["td_rounds"], "bu_rounds": stats["bu_rounds"],
+        "tail_sweeps": stats["tail_iters"], "stage_ms": {k: round(stats[k], 4) for k in ("ms_prep", "ms_rounds", "ms_finalize", "ms_cut")},
+        "roofline": {"bound": "hbm", "kernel": "k_round_step", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "algorithmic_bytes": int(alg),
+                     "kernel_ms": round(t_rounds * 1e3, 4)},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle on rmat-22 ...")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,147 @@
+/*
+ * libldd -- exponential-shift low-diameter decomposition on AMD Instinct MI355X (gfx950).
+ *
+ * The operation (Miller, Peng, Xu, "Parallel Graph Decompositions Using Random Shifts"):
+ * given an undirected unweighted graph G = (V, E) and one shift delta_u >= 0 per vertex
+ * (drawn from Exp(beta) by the caller: Algorithm 1 step 1, Sec. 2), every vertex v joins the
+ * centre u that minimises the shifted distance dist(u,v) - delta_u of Eq. (1) (Sec. 3),
+ * ties broken by the smaller vertex id (Algorithm 2, Sec. 4).  The pieces {v : c(v) = u}
+ * form the partition of Def. 1.1 (Sec. 1); the library also returns the number of edges
+ * whose endpoints lie in different pieces.
+ *
+ * Shifts are passed in fixed point, shift_fix[u] = floor(delta_u * 2^20), so the result is
+ * exact and reproducible: c(v) = lexicographic argmin over u of (2^20 dist(u,v) - shift_fix[u], u).
+ * It depends only on the graph and shift_fix (beta is a hint and never changes it).
+ *
+ * The computation follows the breadth-first formulation of Sec. 5: a super source with an
+ * arc of length Delta - shift_fix[u] to every u (Delta = max shift), processed one integer
+ * distance ("round") at a time; u enters the search at round floor((Delta - shift_fix[u]) / 2^20)
+ * unless already reached, and the fractional parts break ties inside a round.
+ *
+ * Conventions for every entry point
+ *   - Device pointers point to memory of the current HIP device; the caller owns them and
+ *     must keep them alive until the call returns (single graph) or the request is polled
+ *     done (server).  Host pointers are ordinary host memory.
+ *   - Graphs are CSR with int32 indices: row_ptr[n+1] (row_ptr[0] = 0, non-decreasing,
+ *     row_ptr[n] = nnz) and col_idx[nnz] with 0 <= col_idx[a] < n.  The graph must be
+ *     symmetric (each edge stored as two arcs).  Self-loops are never cut; repeated arcs
+ *     count with multiplicity in the cut.
+ *   - Calls never abort and never throw; they return an ldd_status.  Argument errors are
+ *     detected before any device work where the check is O(1); malformed CSR content is
+ *     reported as LDD_ERR_INVALID_ARG by bounds checks inside the kernels (no out-of-range
+ *     access is made).  ldd_last_error() gives a thread-local detail string.
+ *   - hip_stream is a hipStream_t (NULL = default stream).  Work is ordered on that stream;
+ *     the single-graph and batch calls return after the stream has completed the call.
+ */
+#ifndef LDD_H
+#define LDD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LDD_OK = 0,
+  LDD_ERR_INVALID_ARG = 1, /* bad pointer, size, CSR content or negative shift            */
+  LDD_ERR_OOM = 2,         /* device workspace allocation failed                           */
+  LDD_ERR_OVERFLOW = 3,    /* (Delta + 2^20) << ceil(log2 n) does not fit 64 bits          */
+  LDD_ERR_HIP = 4,         /* a HIP runtime call failed (text in ldd_last_error)           */
+  LDD_ERR_BUDGET = 5,      /* server: request larger than the whole memory budget          */
+  LDD_ERR_CANCELLED = 6,   /* server: request cancelled before it ran                      */
+  LDD_ERR_INTERNAL = 7,    /* round watchdog or barrier time-out fired (a library bug)     */
+  LDD_ERR_PENDING = 8      /* server: request not finished yet                             */
+} ldd_status;
+
+/* One CSR graph in device memory (see conventions above). */
+typedef struct {
+  int32_t n;              /* vertices, >= 0                                               */
+  int64_t nnz;            /* arcs (twice the undirected edges), 0 <= nnz < 2^31            */
+  const int32_t* row_ptr; /* device [n+1]                                                 */
+  const int32_t* col_idx; /* device [nnz]                                                 */
+} ldd_csr;
+
+/* Traversal direction policy of a round (the result never depends on it). */
+enum { LDD_DIR_AUTO = 0, LDD_DIR_TOP_DOWN = 1, LDD_DIR_BOTTOM_UP = 2 };
+/* Round engine: one persistent kernel with grid barriers, or one launch per phase. */
+enum { LDD_ENGINE_AUTO = 0, LDD_ENGINE_PERSISTENT = 1, LDD_ENGINE_LAUNCH = 2 };
+
+typedef struct {
+  int32_t direction;      /* LDD_DIR_*                                                    */
+  int32_t engine;         /* LDD_ENGINE_*                                                 */
+  int32_t validate;       /* 1: check CSR monotonicity on the device before running       */
+  int32_t blocks;         /* workgroups of the round kernel (0 = 2 per CU; at most 1024) */
+  int32_t td_to_bu;       /* switch to bottom-up when frontier arcs * td_to_bu > unsettled arcs (0 = default 14) */
+  int32_t bu_to_td;       /* switch back when frontier vertices * bu_to_td < n (0 = default 24)                 */
+  int32_t tail_vertices;  /* finish by label correction once unsettled vertices * this <= active vertices
+                             (0 = default 64, -1 = never)                                                      */
+  int32_t reserved[9];
+} ldd_options;
+
+/* Counters of the last call (filled when a non-NULL pointer is passed). */
+typedef struct {
+  int32_t rounds;          /* rounds executed (empty rounds skipped are not counted)      */
+  int32_t rounds_bound;    /* floor(Delta / 2^20) + 1                                     */
+  int32_t td_rounds;       /* rounds expanded top-down                                    */
+  int32_t bu_rounds;       /* rounds expanded bottom-up                                   */
+  int32_t tail_iters;      /* label-correction sweeps after switching to the tail         */
+  int32_t tail_round;      /* first round the tail replaced (-1: rounds ran to the end)   */
+  int32_t blocks;          /* workgroups used by the round kernel                         */
+  int64_t delta;           /* max shift_fix                                               */
+  int64_t pieces;          /* number of centres                                           */
+  int64_t max_frontier;    /* largest frontier (vertices)                                 */
+  int64_t arcs_examined;   /* arcs read by the traversal (all of F's arcs top-down; the   */
+                           /* arcs scanned before the early exit bottom-up)               */
+  int64_t n_active;        /* vertices with at least one arc                              */
+  float ms_prep;           /* device time: init, Delta, wake-round sort (HIP events)      */
+  float ms_rounds;         /* device time: all rounds                                     */
+  float ms_finalize;       /* device time: centre extraction                              */
+  float ms_cut;            /* device time: cut count                                      */
+} ldd_stats;
+
+/*
+ * Decompose one graph (Algorithm 2 via the search of Sec. 5).
+ *   g          graph in device memory.
+ *   shift_fix  device int64[n], 0 <= shift_fix[u] <= 2^52, units of 2^-20.
+ *   beta       the Exp rate the shifts were drawn with (0 < beta); a hint only.
+ *   centre     device int32[n], OUT: centre id of every vertex.
+ *   cut_edges  host int64*, OUT (may be NULL): edges whose endpoints have different centres.
+ *   opt        NULL for defaults.
+ *   stats      host, OUT (may be NULL).
+ * Returns after the work on hip_stream has completed.
+ */
+ldd_status ldd_decompose(const ldd_csr* g, const int64_t* shift_fix, double beta, int32_t* centre,
+                         int64_t* cut_edges, const ldd_options* opt, ldd_stats* stats, void* hip_stream);
+
+/* Device bytes the library's workspace needs for one graph of this size (upper bound). */
+size_t ldd_workspace_bytes(int32_t n, int64_t nnz);
+
+/*
+ * Decompose many independent graphs in one pass (same operation per graph).
+ * The graphs are packed into one offset CSR with LOCAL vertex ids:
+ *   vtx_off   host int64[num_graphs+1], graph g owns vertices [vtx_off[g], vtx_off[g+1]).
+ *   arc_off   host int64[num_graphs+1], graph g owns arcs [arc_off[g], arc_off[g+1]).
+ *   row_ptr   device int32[vtx_off[G] + num_graphs]: graph g's row offsets (n_g+1 entries,
+ *             starting at 0) stored at row_ptr[vtx_off[g] + g].
+ *   col_idx   device int32[arc_off[G]]: local ids 0 <= col < n_g.
+ *   shift_fix device int64[vtx_off[G]]; centre device int32[vtx_off[G]] OUT (local ids).
+ *   cut_edges host int64[num_graphs] OUT (may be NULL).
+ * Each graph's result equals ldd_decompose on that graph alone, bit for bit.
+ */
+ldd_status ldd_decompose_batch(int32_t num_graphs, const int64_t* vtx_off, const int64_t* arc_off,
+                               const int32_t* row_ptr, const int32_t* col_idx, const int64_t* shift_fix,
+                               int32_t* centre, int64_t* cut_edges, const ldd_options* opt, void* hip_stream);
+
+/* Human-readable name of a status code (static string). */
+const char* ldd_status_string(ldd_status s);
+/* Detail of the last error on this thread (static thread-local buffer). */
+const char* ldd_last_error(void);
+/* Release cached device workspaces of the calling thread's current device. */
+void ldd_release_workspace(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LDD_H */

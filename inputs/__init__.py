@@ -167,3 +167,47 @@ def batch_graphs(num_graphs: int = 512, seed: int = 1, **kw):
         rp, ci = er(n, 8.0, gseed) if kind == "er" else rgg(n, 6.0, gseed)
         graphs.append((rp, ci, make_shifts(n, beta, sseed), beta))
     return graphs
+
+
+# ------------------------------------------------------------------------------------------
+# Named single-graph workloads
+# ------------------------------------------------------------------------------------------
+# name -> (generator, arguments, beta).  Graph seed and shift seed are both 1 unless given.
+WORKLOADS = {
+    "grid2d-64x64": ("grid2d", (64, 64), 0.1),
+    "rmat-24": ("rmat", (24,), 0.05),
+    "grid3d-256": ("grid3d", (256, 256, 256), 0.02),
+    # smaller members of the same families (parity and CPU-baseline samples)
+    "rmat-16": ("rmat", (16,), 0.05),
+    "rmat-18": ("rmat", (18,), 0.05),
+    "rmat-20": ("rmat", (20,), 0.05),
+    "rmat-21": ("rmat", (21,), 0.05),
+    "rmat-22": ("rmat", (22,), 0.05),
+    "grid3d-64": ("grid3d", (64, 64, 64), 0.02),
+    "grid3d-128": ("grid3d", (128, 128, 128), 0.02),
+    "grid2d-1000": ("grid2d", (1000, 1000), 0.01),
+}
+
+
+def workload(name: str, graph_seed: int = 1, shift_seed: int = 1, beta: float | None = None):
+    """Return ``(row_ptr, col_idx, shift_fix, beta)`` for a named workload.
+
+    ``rmat-<scale>``: RMAT edge factor 16, (a,b,c) = (0.57, 0.19, 0.19), relabelled;
+    ``grid2d-<r>x<c>`` / ``grid3d-<k>``: grids; shifts Exp(beta) from ``shift_seed``.
+    """
+    if name in WORKLOADS:
+        gen, args, b = WORKLOADS[name]
+    elif name.startswith("rmat-"):
+        gen, args, b = "rmat", (int(name[5:]),), 0.05
+    else:
+        raise KeyError(name)
+    if gen == "rmat":
+        rp, ci = rmat(args[0], 16, 0.57, 0.19, 0.19, seed=graph_seed, relabel=True)
+    elif gen == "grid2d":
+        rp, ci = grid2d(*args)
+    elif gen == "grid3d":
+        rp, ci = grid3d(*args)
+    else:
+        raise KeyError(name)
+    beta = b if beta is None else beta
+    return rp, ci, make_shifts(rp.size - 1, beta, shift_seed), beta

@@ -1,0 +1,191 @@
+"""Exponential-shift low-diameter decomposition on AMD MI355X: Python binding of libldd.
+
+Every vertex v joins the centre u minimising dist(u,v) - delta_u (Algorithm 2 of Miller,
+Peng and Xu; shifts delta_u ~ Exp(beta), Eq. (1)), ties to the smaller id; shifts are given
+in fixed point (int64, units of 2^-20) so the result is exact.  All computation runs in the
+HIP kernels of ``libldd.so``; this module only marshals torch device tensors and the current
+stream into the C ABI declared in ``include/ldd.h``.  There is no CPU fallback: if the
+library cannot be loaded the call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_ROOT = os.path.dirname(_HERE)
+SO_PATH = os.path.join(_HERE, "libldd.so")
+SOURCES = [os.path.join(_HERE, "csrc", f) for f in ("ldd_kernels.hip", "ldd_rounds.hip", "ldd_api.hip",
+                                                   "ldd_batch.hip")]
+HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall",
+               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+# status codes (ldd_status)
+OK, ERR_INVALID_ARG, ERR_OOM, ERR_OVERFLOW, ERR_HIP, ERR_BUDGET, ERR_CANCELLED, ERR_INTERNAL, ERR_PENDING = range(9)
+DIR_AUTO, DIR_TOP_DOWN, DIR_BOTTOM_UP = 0, 1, 2
+ENGINE_AUTO, ENGINE_PERSISTENT, ENGINE_LAUNCH = 0, 1, 2
+
+EXPORTED = ("ldd_decompose", "ldd_workspace_bytes", "ldd_decompose_batch", "ldd_status_string", "ldd_last_error",
+            "ldd_release_workspace")
+
+
+class LddError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"ldd status {status}: {msg}")
+        self.status = status
+
+
+class Csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col_idx", ctypes.c_void_p)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("direction", ctypes.c_int32), ("engine", ctypes.c_int32), ("validate", ctypes.c_int32),
+                ("blocks", ctypes.c_int32), ("td_to_bu", ctypes.c_int32), ("bu_to_td", ctypes.c_int32),
+                ("tail_vertices", ctypes.c_int32), ("reserved", ctypes.c_int32 * 9)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int32), ("rounds_bound", ctypes.c_int32), ("td_rounds", ctypes.c_int32),
+                ("bu_rounds", ctypes.c_int32), ("tail_iters", ctypes.c_int32), ("tail_round", ctypes.c_int32),
+                ("blocks", ctypes.c_int32),
+                ("delta", ctypes.c_int64), ("pieces", ctypes.c_int64), ("max_frontier", ctypes.c_int64),
+                ("arcs_examined", ctypes.c_int64), ("n_active", ctypes.c_int64),
+                ("ms_prep", ctypes.c_float), ("ms_rounds", ctypes.c_float), ("ms_finalize", ctypes.c_float),
+                ("ms_cut", ctypes.c_float)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def build() -> str:
+    """Compile the HIP sources into ``libldd.so`` for gfx950 (always recompiles)."""
+    tmp = SO_PATH + ".tmp"
+    subprocess.run(["hipcc", *HIPCC_FLAGS, *SOURCES, "-o", tmp], check=True)
+    os.replace(tmp, SO_PATH)
+    return SO_PATH
+
+
+_lib = None
+
+
+def lib():
+    """The loaded ``libldd.so`` (built first if it does not exist yet)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(SO_PATH):
+        build()
+    L = ctypes.CDLL(SO_PATH)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    L.ldd_decompose.argtypes = [ctypes.POINTER(Csr), vp, ctypes.c_double, vp, ctypes.POINTER(ctypes.c_int64),
+                                ctypes.POINTER(Options), ctypes.POINTER(Stats), vp]
+    L.ldd_decompose.restype = i32
+    L.ldd_decompose_batch.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(Options), vp]
+    L.ldd_decompose_batch.restype = i32
+    L.ldd_workspace_bytes.argtypes = [i32, i64]
+    L.ldd_workspace_bytes.restype = ctypes.c_size_t
+    L.ldd_status_string.argtypes = [i32]
+    L.ldd_status_string.restype = ctypes.c_char_p
+    L.ldd_last_error.argtypes = []
+    L.ldd_last_error.restype = ctypes.c_char_p
+    L.ldd_release_workspace.argtypes = []
+    L.ldd_release_workspace.restype = None
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != OK:
+        L = lib()
+        raise LddError(status, f"{L.ldd_status_string(status).decode()}: {L.ldd_last_error().decode()}")
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _device_tensor(t, dtype, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a torch tensor on the GPU")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor")
+    return t
+
+
+def make_options(direction=DIR_AUTO, engine=ENGINE_AUTO, validate=False, blocks=0, td_to_bu=0, bu_to_td=0,
+                 tail_vertices=0) -> Options:
+    o = Options()
+    o.direction, o.engine, o.validate, o.blocks = direction, engine, int(validate), blocks
+    o.td_to_bu, o.bu_to_td, o.tail_vertices = td_to_bu, bu_to_td, tail_vertices
+    return o
+
+
+def decompose(row_ptr, col_idx, shift_fix, beta: float, *, centre=None, stream=None, stats: bool = False, **opts):
+    """Decompose one graph held in device memory.
+
+    row_ptr int32[n+1], col_idx int32[nnz], shift_fix int64[n] (torch tensors on the GPU).
+    Returns ``(centre int32[n] tensor, cut_edges)`` or, with ``stats=True``,
+    ``(centre, cut_edges, stats dict)``.
+    """
+    import torch
+    _device_tensor(row_ptr, torch.int32, "row_ptr")
+    _device_tensor(col_idx, torch.int32, "col_idx")
+    _device_tensor(shift_fix, torch.int64, "shift_fix")
+    n = row_ptr.numel() - 1
+    if n < 0 or shift_fix.numel() != n:
+        raise ValueError("row_ptr and shift_fix sizes disagree")
+    if centre is None:
+        centre = torch.empty(n, dtype=torch.int32, device=row_ptr.device)
+    else:
+        _device_tensor(centre, torch.int32, "centre")
+        if centre.numel() != n:
+            raise ValueError("centre has the wrong size")
+    g = Csr(n, col_idx.numel(), row_ptr.data_ptr(), col_idx.data_ptr() if col_idx.numel() else None)
+    cut = ctypes.c_int64(0)
+    st = Stats()
+    o = make_options(**opts)
+    _check(lib().ldd_decompose(ctypes.byref(g), shift_fix.data_ptr(), float(beta), centre.data_ptr(),
+                               ctypes.byref(cut), ctypes.byref(o), ctypes.byref(st), _stream_handle(stream)))
+    if stats:
+        return centre, int(cut.value), st.as_dict()
+    return centre, int(cut.value)
+
+
+def decompose_batch(vtx_off, arc_off, row_ptr, col_idx, shift_fix, *, centre=None, stream=None, **opts):
+    """Decompose many graphs packed in one offset CSR (see ``ldd_decompose_batch``).
+
+    vtx_off / arc_off: host int64 sequences of length G+1; row_ptr int32[vtx_off[G] + G],
+    col_idx int32[arc_off[G]] (local ids), shift_fix int64[vtx_off[G]] on the GPU.
+    Returns ``(centre tensor with local ids, list of per-graph cut counts)``.
+    """
+    import numpy as np
+    import torch
+    vo = np.ascontiguousarray(vtx_off, dtype=np.int64)
+    ao = np.ascontiguousarray(arc_off, dtype=np.int64)
+    G = vo.size - 1
+    if G < 0 or ao.size != vo.size:
+        raise ValueError("vtx_off and arc_off must both have G+1 entries")
+    _device_tensor(row_ptr, torch.int32, "row_ptr")
+    _device_tensor(col_idx, torch.int32, "col_idx")
+    _device_tensor(shift_fix, torch.int64, "shift_fix")
+    nv = int(vo[-1]) if G >= 0 else 0
+    if row_ptr.numel() != nv + G or shift_fix.numel() != nv or col_idx.numel() != int(ao[-1]):
+        raise ValueError("packed array sizes disagree with the offsets")
+    if centre is None:
+        centre = torch.empty(nv, dtype=torch.int32, device=row_ptr.device)
+    cuts = np.zeros(max(G, 1), dtype=np.int64)
+    o = make_options(**opts)
+    _check(lib().ldd_decompose_batch(G, vo.ctypes.data, ao.ctypes.data, row_ptr.data_ptr(),
+                                     col_idx.data_ptr() if col_idx.numel() else None, shift_fix.data_ptr(),
+                                     centre.data_ptr(), cuts.ctypes.data, ctypes.byref(o), _stream_handle(stream)))
+    return centre, [int(x) for x in cuts[:G]]
+
+
+def workspace_bytes(n: int, nnz: int) -> int:
+    return int(lib().ldd_workspace_bytes(n, nnz))

@@ -1,0 +1,409 @@
+// Host side of libldd: argument checks, device workspace, kernel sequencing, error mapping.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "../../include/ldd.h"
+#include "ldd_internal.h"
+#include "ldd_kernels.h"
+
+using namespace ldd;
+
+// ------------------------------------------------------------------------------------------
+// errors
+// ------------------------------------------------------------------------------------------
+static thread_local char g_err[512];
+
+void ldd_set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+extern "C" const char* ldd_last_error(void) { return g_err; }
+
+extern "C" const char* ldd_status_string(ldd_status s) {
+  switch (s) {
+    case LDD_OK: return "ok";
+    case LDD_ERR_INVALID_ARG: return "invalid argument";
+    case LDD_ERR_OOM: return "out of device memory";
+    case LDD_ERR_OVERFLOW: return "label width overflow";
+    case LDD_ERR_HIP: return "HIP runtime error";
+    case LDD_ERR_BUDGET: return "request exceeds memory budget";
+    case LDD_ERR_CANCELLED: return "cancelled";
+    case LDD_ERR_INTERNAL: return "internal error";
+    case LDD_ERR_PENDING: return "pending";
+  }
+  return "unknown status";
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) {                                                             \
+      ldd_set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
+      return LDD_ERR_HIP;                                                               \
+    }                                                                                   \
+  } while (0)
+
+// ------------------------------------------------------------------------------------------
+// workspace: one per device, grown on demand, guarded by a mutex for the whole call
+// ------------------------------------------------------------------------------------------
+namespace {
+
+struct Buf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+ldd_status grow(Buf& b, size_t bytes) {
+  if (b.bytes >= bytes && b.p) return LDD_OK;
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+  size_t want = bytes < 256 ? 256 : bytes;
+  hipError_t e = hipMalloc(&b.p, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    ldd_set_error("hipMalloc(%zu) failed: %s", want, hipGetErrorString(e));
+    return LDD_ERR_OOM;
+  }
+  b.bytes = want;
+  return LDD_OK;
+}
+
+struct HostMirror {  // pinned copies of the device control block and round states
+  Ctrl ctrl;
+  RoundState st[2];
+};
+
+struct Workspace {
+  std::mutex mu;
+  Buf P, qv0, qv1, qa0, qa1, wake_ord, stamp;         // per vertex
+  Buf hist, cursor, wake_off, next_ne;                // per round
+  Buf ctrl, st, qcnt, lr_part;
+  HostMirror* host = nullptr;
+  hipEvent_t ev[6] = {};
+  int num_cu = 0;
+  int max_coresident = 0;  // co-resident blocks of the persistent round kernel
+};
+
+std::mutex g_ws_mu;
+std::vector<Workspace*> g_ws;
+
+Workspace* workspace_for(int dev) {
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  if ((int)g_ws.size() <= dev) g_ws.resize(dev + 1, nullptr);
+  if (!g_ws[dev]) g_ws[dev] = new Workspace();
+  return g_ws[dev];
+}
+
+ldd_status ws_setup(Workspace& w) {
+  if (!w.host) {
+    HIP_TRY(hipHostMalloc((void**)&w.host, sizeof(HostMirror), hipHostMallocDefault));
+    for (auto& e : w.ev) HIP_TRY(hipEventCreate(&e));
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&w.num_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    int per_cu = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_rounds_persistent),
+                                                         RT, 0));
+    // one block per CU at most: measured co-residency of large cooperative grids falls short
+    // of what the occupancy query reports, and barrier cost grows with the block count
+    w.max_coresident = w.num_cu * (per_cu < 1 ? 0 : 1);
+  }
+  ldd_status s;
+  if ((s = grow(w.ctrl, sizeof(Ctrl))) || (s = grow(w.st, 2 * sizeof(RoundState))) ||
+      (s = grow(w.qcnt, 3 * 16 * sizeof(u64))) || (s = grow(w.lr_part, 2 * (size_t)RT * sizeof(u64))))
+    return s;
+  return LDD_OK;
+}
+
+int ceil_log2(long long n) {
+  int b = 0;
+  while ((1ll << b) < n) ++b;
+  return b;
+}
+
+int grid_for(long long items, int threads, int cap) {
+  long long g = (items + threads - 1) / threads;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+}  // namespace
+
+extern "C" size_t ldd_workspace_bytes(int32_t n, int64_t nnz) {
+  (void)nnz;
+  const size_t nv = n > 0 ? (size_t)n : 1;
+  // labels 8 + two queues (4 + 4 each) + wake order 4 + tail stamp 4 = 32 bytes per vertex, plus rounds
+  // arrays sized by the shift range (bounded here by 2^16 rounds) and the control block
+  return nv * 32 + (size_t)(65536 + 2) * (4 * 4) + sizeof(Ctrl) + 2 * sizeof(RoundState) + 3 * 16 * 8 +
+         2 * (size_t)RT * 8;
+}
+
+extern "C" void ldd_release_workspace(void) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return;
+  Workspace* w = workspace_for(dev);
+  std::lock_guard<std::mutex> lk(w->mu);
+  for (Buf* b : {&w->P, &w->qv0, &w->qv1, &w->qa0, &w->qa1, &w->wake_ord, &w->stamp, &w->hist, &w->cursor,
+                 &w->wake_off, &w->next_ne, &w->ctrl, &w->st, &w->qcnt, &w->lr_part}) {
+    if (b->p) (void)hipFree(b->p);
+    b->p = nullptr;
+    b->bytes = 0;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// single graph
+// ------------------------------------------------------------------------------------------
+static ldd_status finish_error(unsigned err) {
+  if (err & (ERR_BAD_SHIFT | ERR_BAD_ROWPTR | ERR_BAD_COL)) {
+    ldd_set_error("invalid input:%s%s%s", (err & ERR_BAD_SHIFT) ? " shift out of [0, 2^52]" : "",
+                  (err & ERR_BAD_ROWPTR) ? " row_ptr not a valid offset array" : "",
+                  (err & ERR_BAD_COL) ? " column id out of range" : "");
+    return LDD_ERR_INVALID_ARG;
+  }
+  if (err) {
+    ldd_set_error("internal error flags 0x%x%s%s%s", err, (err & ERR_BARRIER) ? " barrier-timeout" : "",
+                  (err & ERR_WATCHDOG) ? " round-watchdog" : "", (err & ERR_QUEUE) ? " queue-overflow" : "");
+    return LDD_ERR_INTERNAL;
+  }
+  return LDD_OK;
+}
+
+extern "C" ldd_status ldd_decompose(const ldd_csr* g, const int64_t* shift_fix, double beta, int32_t* centre,
+                                    int64_t* cut_edges, const ldd_options* opt, ldd_stats* stats, void* hip_stream) {
+  g_err[0] = 0;
+  if (!g) {
+    ldd_set_error("graph is NULL");
+    return LDD_ERR_INVALID_ARG;
+  }
+  const int n = g->n;
+  const long long nnz = g->nnz;
+  if (n < 0 || nnz < 0 || nnz >= (1ll << 31)) {
+    ldd_set_error("bad sizes n=%d nnz=%lld (need n >= 0, 0 <= nnz < 2^31)", n, nnz);
+    return LDD_ERR_INVALID_ARG;
+  }
+  if (!(beta > 0.0)) {
+    ldd_set_error("beta must be positive");
+    return LDD_ERR_INVALID_ARG;
+  }
+  if (n > 0 && (!g->row_ptr || !shift_fix || !centre || (nnz > 0 && !g->col_idx))) {
+    ldd_set_error("NULL device pointer");
+    return LDD_ERR_INVALID_ARG;
+  }
+  ldd_options o{};
+  if (opt) o = *opt;
+  if (o.direction < 0 || o.direction > 2 || o.engine < 0 || o.engine > 2 || o.blocks < 0) {
+    ldd_set_error("bad options");
+    return LDD_ERR_INVALID_ARG;
+  }
+  if (stats) memset(stats, 0, sizeof(*stats));
+  if (n == 0) {
+    if (cut_edges) *cut_edges = 0;
+    return LDD_OK;
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  Workspace& w = *workspace_for(dev);
+  std::lock_guard<std::mutex> lk(w.mu);
+  ldd_status s = ws_setup(w);
+  if (s != LDD_OK) return s;
+  const size_t nv = (size_t)n;
+  if ((s = grow(w.P, nv * 8)) || (s = grow(w.qv0, nv * 4)) || (s = grow(w.qv1, nv * 4)) || (s = grow(w.qa0, nv * 4)) ||
+      (s = grow(w.qa1, nv * 4)) || (s = grow(w.wake_ord, nv * 4)) || (s = grow(w.stamp, nv * 4)))
+    return s;
+  Ctrl* ctrl = (Ctrl*)w.ctrl.p;
+  u64* P = (u64*)w.P.p;
+
+  HIP_TRY(hipEventRecord(w.ev[0], st));
+  HIP_TRY(hipMemsetAsync(ctrl, 0, sizeof(Ctrl), st));
+  const int g_n = grid_for(n, 256, 4096);
+  hipLaunchKernelGGL(k_init, dim3(g_n), dim3(256), 0, st, n, nnz, g->row_ptr, (const long long*)shift_fix, P, ctrl);
+  if (o.validate && nnz > 0)
+    hipLaunchKernelGGL(k_check_cols, dim3(grid_for(nnz, 256, 4096)), dim3(256), 0, st, n, nnz, g->col_idx, ctrl);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(&w.host->ctrl, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  {
+    ldd_status e = finish_error(w.host->ctrl.err);
+    if (e != LDD_OK) return e;
+  }
+  const u64 delta = w.host->ctrl.delta;
+  const u64 n_active = w.host->ctrl.n_active;
+  const int B = ceil_log2(n) < 1 ? 1 : ceil_log2(n);
+  // largest label: ((delta + 2^20) << B) | (n - 1) must stay below INF
+  if ((delta + (1ull << FIX)) >= (1ull << (64 - B))) {
+    ldd_set_error("labels need (Delta + 2^20) << %d < 2^64 (Delta = %llu)", B, (unsigned long long)delta);
+    return LDD_ERR_OVERFLOW;
+  }
+  const long long R = (long long)(delta >> FIX) + 1;
+  if (R > (1ll << 28)) {
+    ldd_set_error("shift range needs %lld rounds", R);
+    return LDD_ERR_OVERFLOW;
+  }
+  const size_t nr = (size_t)R + 2;
+  if ((s = grow(w.hist, nr * 4)) || (s = grow(w.cursor, nr * 4)) || (s = grow(w.wake_off, nr * 4)) ||
+      (s = grow(w.next_ne, nr * 4)))
+    return s;
+
+  HIP_TRY(hipMemsetAsync(w.hist.p, 0, nr * 4, st));
+  const int use_lds = R <= 8192;
+  hipLaunchKernelGGL(k_wake_count, dim3(g_n), dim3(256), use_lds ? (size_t)R * 4 : 0, st, n, B, g->row_ptr,
+                     (const long long*)shift_fix, (const Ctrl*)ctrl, P, (unsigned*)w.hist.p, (int)R, use_lds);
+  hipLaunchKernelGGL(k_wake_scan, dim3(1), dim3(1024), 0, st, (int)R, (const unsigned*)w.hist.p, (int*)w.wake_off.p,
+                     (int*)w.cursor.p, (int*)w.next_ne.p);
+  hipLaunchKernelGGL(k_wake_scatter, dim3(g_n), dim3(256), 0, st, n, g->row_ptr, (const long long*)shift_fix,
+                     (const Ctrl*)ctrl, (int*)w.cursor.p, (int*)w.wake_ord.p);
+  HIP_TRY(hipGetLastError());
+
+  const int tail_den = o.tail_vertices < 0 ? 0 : (o.tail_vertices > 0 ? o.tail_vertices : 64);
+  if (tail_den) HIP_TRY(hipMemsetAsync(w.stamp.p, 0, nv * 4, st));
+  HIP_TRY(hipMemsetAsync(w.qcnt.p, 0, 3 * 16 * sizeof(u64), st));
+  RoundState s0{};
+  s0.seq = 0;
+  s0.mode = MODE_ROUNDS;
+  s0.round = -1;
+  s0.dir = DIR_TD;
+  s0.unsettled_arcs = (u64)nnz;
+  s0.tail_round = -1;
+  w.host->st[0] = s0;
+  HIP_TRY(hipMemcpyAsync(w.st.p, &w.host->st[0], sizeof(RoundState), hipMemcpyHostToDevice, st));
+
+  RoundCtx c{};
+  c.n = n;
+  c.B = B;
+  c.R = (int)R;
+  c.nnz = nnz;
+  c.delta = delta;
+  c.n_active = n_active;
+  c.row_ptr = g->row_ptr;
+  c.col = g->col_idx;
+  c.shift = (const long long*)shift_fix;
+  c.P = P;
+  c.qv[0] = (int*)w.qv0.p;
+  c.qv[1] = (int*)w.qv1.p;
+  c.qa[0] = (unsigned*)w.qa0.p;
+  c.qa[1] = (unsigned*)w.qa1.p;
+  c.wake_ord = (const int*)w.wake_ord.p;
+  c.wake_off = (const int*)w.wake_off.p;
+  c.next_ne = (const int*)w.next_ne.p;
+  c.qcnt = (u64*)w.qcnt.p;
+  c.lr_part = (u64*)w.lr_part.p;
+  c.stamp = (unsigned*)w.stamp.p;
+  c.st = (RoundState*)w.st.p;
+  c.ctrl = ctrl;
+  c.dir_policy = o.direction;
+  c.td_to_bu = o.td_to_bu > 0 ? o.td_to_bu : 14;
+  c.bu_to_td = o.bu_to_td > 0 ? o.bu_to_td : 24;
+  c.tail_den = tail_den;
+  c.tail_min_left = 16;
+
+  const int engine = o.engine == LDD_ENGINE_AUTO ? LDD_ENGINE_LAUNCH : o.engine;
+  int blocks = o.blocks > 0 ? o.blocks : 2 * w.num_cu;
+  if (blocks > RT) blocks = RT;  // the per-block minima of a step are reduced by one block
+  if (engine == LDD_ENGINE_PERSISTENT && blocks > w.max_coresident) blocks = w.max_coresident;
+  const long long kmax = R + (long long)n + 2;
+  long long steps = 0;
+  HIP_TRY(hipEventRecord(w.ev[1], st));
+  if (n_active > 0) {
+    if (engine == LDD_ENGINE_PERSISTENT) {
+      void* args[] = {&c};
+      HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_rounds_persistent), dim3(blocks), dim3(RT),
+                                         args, 0, st));
+      HIP_TRY(hipMemcpyAsync(w.host->st, w.st.p, 2 * sizeof(RoundState), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+    } else {
+      // steps are enqueued in growing chunks; after each chunk the state is checked once
+      long long k = 1;
+      int chunk = 8;
+      for (;;) {
+        for (int j = 0; j < chunk; ++j, ++k) hipLaunchKernelGGL(k_round_step, dim3(blocks), dim3(RT), 0, st, c, (int)k);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(w.host->st, w.st.p, 2 * sizeof(RoundState), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        const RoundState& last = w.host->st[0].seq > w.host->st[1].seq ? w.host->st[0] : w.host->st[1];
+        if (last.mode == MODE_DONE) break;
+        if (k > kmax) {
+          ldd_set_error("round steps exceeded their bound (%lld)", kmax);
+          return LDD_ERR_INTERNAL;
+        }
+        chunk = chunk < 64 ? chunk * 2 : 64;
+      }
+      steps = k - 1;
+    }
+  }
+  (void)steps;
+  HIP_TRY(hipEventRecord(w.ev[2], st));
+  hipLaunchKernelGGL(k_finalize, dim3(g_n), dim3(256), 0, st, n, B, (const u64*)P, centre, ctrl);
+  HIP_TRY(hipEventRecord(w.ev[3], st));
+  if (nnz > 0)
+    hipLaunchKernelGGL(k_cut, dim3(grid_for(nnz, 256, 8192)), dim3(256), 0, st, n, nnz, g->row_ptr, g->col_idx,
+                       (const int*)centre, ctrl);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipEventRecord(w.ev[4], st));
+  HIP_TRY(hipMemcpyAsync(&w.host->ctrl, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  const Ctrl& h = w.host->ctrl;
+  {
+    ldd_status e = finish_error(h.err);
+    if (e != LDD_OK) return e;
+  }
+  const RoundState& fs = w.host->st[0].seq > w.host->st[1].seq ? w.host->st[0] : w.host->st[1];
+  if (h.unreached != 0 || (n_active > 0 && fs.mode != MODE_DONE)) {
+    ldd_set_error("rounds ended with %llu labels unset (mode %d)", (unsigned long long)h.unreached, fs.mode);
+    return LDD_ERR_INTERNAL;
+  }
+  if (cut_edges) *cut_edges = (int64_t)(h.cut_arcs / 2);
+  if (stats) {
+    stats->rounds = n_active ? fs.rounds : 0;
+    stats->rounds_bound = (int32_t)R;
+    stats->td_rounds = n_active ? fs.td_rounds : 0;
+    stats->bu_rounds = n_active ? fs.bu_rounds : 0;
+    stats->tail_iters = n_active ? fs.tail_iters : 0;
+    stats->tail_round = n_active ? fs.tail_round : -1;
+    stats->blocks = blocks;
+    stats->delta = (int64_t)delta;
+    stats->pieces = (int64_t)h.pieces;
+    stats->max_frontier = n_active ? (int64_t)fs.max_frontier : 0;
+    stats->arcs_examined = (int64_t)h.arcs_examined;
+    stats->n_active = (int64_t)n_active;
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, w.ev[0], w.ev[1]);
+    stats->ms_prep = ms;
+    (void)hipEventElapsedTime(&ms, w.ev[1], w.ev[2]);
+    stats->ms_rounds = ms;
+    (void)hipEventElapsedTime(&ms, w.ev[2], w.ev[3]);
+    stats->ms_finalize = ms;
+    (void)hipEventElapsedTime(&ms, w.ev[3], w.ev[4]);
+    stats->ms_cut = ms;
+  }
+  return LDD_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// many graphs, one after another (the one-graph-per-launch path)
+// ------------------------------------------------------------------------------------------
+ldd_status ldd_batch_sequential(int32_t num_graphs, const int64_t* vtx_off, const int64_t* arc_off,
+                                const int32_t* row_ptr, const int32_t* col_idx, const int64_t* shift_fix,
+                                int32_t* centre, int64_t* cut_edges, const ldd_options* opt, void* hip_stream) {
+  for (int32_t gi = 0; gi < num_graphs; ++gi) {
+    ldd_csr g{(int32_t)(vtx_off[gi + 1] - vtx_off[gi]), arc_off[gi + 1] - arc_off[gi], row_ptr + vtx_off[gi] + gi,
+              col_idx + arc_off[gi]};
+    int64_t cut = 0;
+    ldd_status s = ldd_decompose(&g, shift_fix + vtx_off[gi], 1.0, centre + vtx_off[gi], &cut, opt, nullptr,
+                                 hip_stream);
+    if (s != LDD_OK) return s;
+    if (cut_edges) cut_edges[gi] = cut;
+  }
+  return LDD_OK;
+}

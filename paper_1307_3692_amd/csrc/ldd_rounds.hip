@@ -1,0 +1,499 @@
+// Round kernels of the exponential-shift low-diameter decomposition (gfx950).
+//
+// The search of Sec. 5 runs one integer distance ("round") per step.  Step k reads the state
+// left by step k-1 (device memory, double-buffered by parity), so the host can enqueue steps
+// without waiting for them; a step whose state says "done" returns at once.  Every block
+// derives the same next state from the same counters, so no grid-wide agreement is needed
+// inside a step.  The same step function also runs inside one persistent kernel with grid
+// barriers between steps.
+//
+// Step kinds
+//   round r, top-down   wake bucket r; every arc of F_{r-1} offers P(u) + unit to its far end
+//   round r, bottom-up  wake bucket r; every vertex not settled before r pulls the best offer
+//                       of its neighbours in F_{r-1}, stopping at the lower bound L_r
+//   tail sweep          once few vertices remain, all remaining delayed source arcs are added
+//                       at once and offers are relaxed until nothing changes (the labels are
+//                       the unique fixpoint of P(v) = min(own arc, min_w P(w) + unit), so
+//                       relaxing in any order reaches the same, exact result)
+//
+// Frontier appends are staged per block in LDS and reserved in the global queue with one
+// 64-bit atomic (count << 32 | arcs) per flush, so the queue stays contiguous with a running
+// arc prefix that the next top-down step splits evenly over the grid.
+#include "ldd_device.h"
+#include "ldd_kernels.h"
+
+namespace ldd {
+
+constexpr int NW = RT / WAVE;
+
+struct AppendBuf {
+  int vert[ABUF];
+  unsigned off[ABUF];  // exclusive arc prefix inside the buffer
+  unsigned wave_cnt[NW];
+  unsigned wave_arcs[NW];
+  unsigned n;
+  unsigned arcs;
+  u64 base;
+};
+
+struct StepShared {
+  RoundState S;
+  u64 lr;
+  unsigned start;
+  u64 red[NW];
+  // top-down window: RT+1 queue entries (arc prefix, first arc in col_idx, offer)
+  unsigned w_pre[RT + 1];
+  int w_first[RT + 1];
+  u64 w_offer[RT + 1];
+};
+
+__device__ __forceinline__ u64* qcounter(const RoundCtx& c, int k) { return c.qcnt + (size_t)(k % 3) * 16; }
+
+// Copy the LDS buffer to the global queue of step k behind one reservation.
+__device__ void block_flush(AppendBuf& ab, const RoundCtx& c, int k) {
+  __syncthreads();
+  const unsigned cnt = ab.n, arcs = ab.arcs;
+  if (cnt == 0) return;
+  if (threadIdx.x == 0) ab.base = atomic_add_u64(qcounter(c, k), ((u64)cnt << 32) | arcs);
+  __syncthreads();
+  const u64 base = ab.base;
+  const unsigned b_cnt = (unsigned)(base >> 32), b_arcs = (unsigned)base;
+  int* qv = c.qv[k & 1];
+  unsigned* qa = c.qa[k & 1];
+  for (unsigned i = threadIdx.x; i < cnt; i += RT) {
+    const unsigned idx = b_cnt + i;
+    if (idx < (unsigned)c.n) {
+      qv[idx] = ab.vert[i];
+      qa[idx] = b_arcs + ab.off[i];
+    } else {
+      atomic_or_u32(&c.ctrl->err, ERR_QUEUE);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ab.n = 0;
+    ab.arcs = 0;
+  }
+  __syncthreads();
+}
+
+// Block-wide append of one tile: ballot and wave scans give each appending thread its slot
+// and arc offset; wave totals are combined through LDS.  Called by every thread of the block.
+__device__ void block_append(AppendBuf& ab, bool want, int v, unsigned deg, const RoundCtx& c, int k) {
+  const unsigned lane = lane_id(), wid = threadIdx.x / WAVE;
+  const u64 mask = __ballot(want);
+  const unsigned incl = wave_incl_scan(want ? deg : 0u);
+  if (lane == WAVE - 1) {
+    ab.wave_cnt[wid] = (unsigned)__popcll(mask);
+    ab.wave_arcs[wid] = incl;
+  }
+  __syncthreads();
+  unsigned wc = 0, wa = 0, tc = 0, ta = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    const unsigned a = ab.wave_cnt[w], b = ab.wave_arcs[w];
+    if (w < (int)wid) {
+      wc += a;
+      wa += b;
+    }
+    tc += a;
+    ta += b;
+  }
+  if (tc == 0) {
+    __syncthreads();
+    return;
+  }
+  if (ab.n + tc > (unsigned)ABUF) block_flush(ab, c, k);
+  const unsigned fill = ab.n, fill_arcs = ab.arcs;
+  if (want) {
+    const unsigned idx = fill + wc + rank_below(mask);
+    ab.vert[idx] = v;
+    ab.off[idx] = fill_arcs + wa + incl - deg;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ab.n = fill + tc;
+    ab.arcs = fill_arcs + ta;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ u64 block_min_u64(u64 v, StepShared& sh) {
+  v = wave_min_u64(v);
+  const unsigned wid = threadIdx.x / WAVE;
+  __syncthreads();
+  if (lane_id() == 0) sh.red[wid] = v;
+  __syncthreads();
+  u64 m = INF;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) m = sh.red[w] < m ? sh.red[w] : m;
+  __syncthreads();
+  return m;
+}
+
+__device__ __forceinline__ unsigned degree(const RoundCtx& c, int v) {
+  return (unsigned)(c.row_ptr[v + 1] - c.row_ptr[v]);
+}
+
+__device__ __forceinline__ u64 own_offer(const RoundCtx& c, int v) {
+  return ((c.delta - (u64)c.shift[v]) << c.B) | (u64)v;
+}
+
+// ---- round r: wake bucket r (the delayed source arcs of length in [r, r+1) units) ----------
+__device__ void phase_wake(const RoundCtx& c, int r, int k, AppendBuf& ab, u64& wmin) {
+  const int lo = c.wake_off[r], hi = c.wake_off[r + 1];
+  const int cnt = hi - lo;
+  for (long long base = (long long)blockIdx.x * RT; base < cnt; base += (long long)gridDim.x * RT) {
+    const long long i = base + threadIdx.x;
+    bool want = false;
+    int v = 0;
+    unsigned deg = 0;
+    if (i < cnt) {
+      v = c.wake_ord[lo + i];
+      const u64 self = own_offer(c, v);
+      if (c.P[v] > self) {
+        const u64 old = atomic_min_u64(&c.P[v], self);
+        if (old > self) {
+          wmin = self < wmin ? self : wmin;
+          if (old == INF) {
+            want = true;
+            deg = degree(c, v);
+          }
+        }
+      }
+    }
+    block_append(ab, want, v, deg, c, k);
+  }
+}
+
+// ---- top-down: the af arcs of queue (qv, qa, nf entries) split evenly over the grid ---------
+// Each block walks its arc range in tiles of RT arcs.  The RT+1 queue entries that can touch
+// a tile are staged in LDS (arc prefix, first arc in col_idx, offer); each thread finds its
+// arc's entry by binary search.  Entries have degree >= 1, so a tile whose first arc lies in
+// entry e only touches entries e .. e+RT-1.
+// TAIL = false: round step; an arc appends its far end if it is reached for the first time.
+// TAIL = true: tail sweep `sweep`; an arc appends its far end whenever it lowered the label
+// and the far end is not queued for the next sweep yet.
+template <bool TAIL>
+__device__ void phase_top_down(const RoundCtx& c, int k, const int* qv, const unsigned* qa, unsigned nf, unsigned af,
+                               AppendBuf& ab, StepShared& sh, u64& wmin, unsigned sweep) {
+  unsigned* w_pre = sh.w_pre;
+  int* w_first = sh.w_first;
+  u64* w_offer = sh.w_offer;
+  const u64 unit = (u64)1 << (FIX + c.B);
+  const unsigned G = gridDim.x;
+  const unsigned a_begin = (unsigned)(((u64)af * blockIdx.x) / G);
+  const unsigned a_end = (unsigned)(((u64)af * (blockIdx.x + 1)) / G);
+  if (a_begin >= a_end) return;
+  if (threadIdx.x == 0) {
+    unsigned lo = 0, hi = nf;  // last entry with qa <= a_begin
+    while (hi - lo > 1) {
+      const unsigned mid = (lo + hi) >> 1;
+      if (qa[mid] <= a_begin) lo = mid;
+      else hi = mid;
+    }
+    sh.start = lo;
+  }
+  __syncthreads();
+  unsigned ent = sh.start;
+  for (unsigned tile = a_begin; tile < a_end; tile += RT) {
+    for (int kk = threadIdx.x; kk <= RT; kk += RT) {
+      const unsigned e = ent + kk;
+      if (e < nf) {
+        const int u = qv[e];
+        w_pre[kk] = qa[e];
+        const bool ok = (unsigned)u < (unsigned)c.n;
+        w_first[kk] = ok ? c.row_ptr[u] : 0;
+        const u64 pu = ok ? load_u64_relaxed(&c.P[u]) : INF;
+        w_offer[kk] = pu == INF ? INF : pu + unit;
+      } else {
+        w_pre[kk] = af;
+        w_first[kk] = 0;
+        w_offer[kk] = INF;
+      }
+    }
+    __syncthreads();
+    const unsigned a = tile + threadIdx.x;
+    bool want = false;
+    int w = 0;
+    unsigned deg = 0;
+    if (a < a_end) {
+      int lo = 0, hi = RT;  // last kk in [0, RT) with w_pre[kk] <= a
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (w_pre[mid] <= a) lo = mid;
+        else hi = mid;
+      }
+      const u64 offer = w_offer[lo];
+      const unsigned j = a - w_pre[lo];
+      const long long arc = (long long)w_first[lo] + j;
+      // j < degree and arc < nnz hold for a symmetric CSR; checked so that malformed input
+      // cannot cause an out-of-range read
+      const bool in_range = j < w_pre[lo + 1] - w_pre[lo] && arc < c.nnz && offer != INF;
+      w = in_range ? c.col[arc] : -1;
+      if ((unsigned)w < (unsigned)c.n) {
+        if (c.P[w] > offer) {
+          const u64 old = atomic_min_u64(&c.P[w], offer);
+          if (old > offer) {
+            if (TAIL) {
+              if (__hip_atomic_fetch_max(&c.stamp[w], sweep + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+                  sweep + 1) {
+                want = true;
+                deg = degree(c, w);
+              }
+            } else {
+              wmin = offer < wmin ? offer : wmin;
+              if (old == INF) {
+                want = true;
+                deg = degree(c, w);
+              }
+            }
+          }
+        }
+      } else if (in_range) {
+        atomic_or_u32(&c.ctrl->err, ERR_BAD_COL);
+      }
+    }
+    block_append(ab, want, w, deg, c, k);
+    // the entry holding the next tile's first arc is one of ent .. ent+RT (all staged)
+    const unsigned next = tile + RT;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int lo = 0, hi = RT + 1;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (w_pre[mid] <= next) lo = mid;
+        else hi = mid;
+      }
+      sh.start = ent + lo;
+    }
+    __syncthreads();
+    ent = sh.start;
+  }
+}
+
+// ---- bottom-up: vertices not settled before round r pull from their neighbours in F_{r-1} ---
+// A neighbour u is in F_{r-1} iff its label lies in [base(r-1), base(r)).  L_r (the smallest
+// offer F_{r-1} makes) ends the scan as soon as it is attained.
+__device__ void phase_bottom_up(const RoundCtx& c, int r, int k, u64 Lr, AppendBuf& ab, u64& wmin, u64& examined) {
+  const int B = c.B;
+  const u64 unit = (u64)1 << (FIX + B);
+  const u64 base_r = (u64)r << (FIX + B);
+  const u64 prev_round = (u64)(r - 1);
+  for (long long base = (long long)blockIdx.x * RT; base < c.n; base += (long long)gridDim.x * RT) {
+    const long long vi = base + threadIdx.x;
+    bool want = false;
+    unsigned deg = 0;
+    const int v = (int)vi;
+    if (vi < c.n) {
+      const u64 pv = c.P[v];
+      if (pv >= base_r && pv > Lr) {
+        const int a0 = c.row_ptr[v], a1 = c.row_ptr[v + 1];
+        u64 best = pv;
+        for (int a = a0; a < a1; ++a) {
+          ++examined;
+          const int u = c.col[a];
+          if ((unsigned)u >= (unsigned)c.n) {
+            atomic_or_u32(&c.ctrl->err, ERR_BAD_COL);
+            break;
+          }
+          const u64 pu = load_u64_relaxed(&c.P[u]);
+          if ((pu >> (FIX + B)) == prev_round && pu != INF) {
+            const u64 offer = pu + unit;
+            if (offer < best) best = offer;
+            if (best <= Lr) break;
+          }
+        }
+        if (best < pv) {
+          const u64 old = atomic_min_u64(&c.P[v], best);
+          if (old > best) {
+            wmin = best < wmin ? best : wmin;
+            if (old == INF) {
+              want = true;
+              deg = (unsigned)(a1 - a0);
+            }
+          }
+        }
+      }
+    }
+    block_append(ab, want, v, deg, c, k);
+  }
+}
+
+// ---- tail seed: every vertex not settled before round r offers itself -----------------------
+__device__ void phase_tail_seed(const RoundCtx& c, int r, int k, AppendBuf& ab) {
+  const u64 base_r = (u64)r << (FIX + c.B);
+  for (long long base = (long long)blockIdx.x * RT; base < c.n; base += (long long)gridDim.x * RT) {
+    const long long vi = base + threadIdx.x;
+    bool want = false;
+    unsigned deg = 0;
+    const int v = (int)vi;
+    if (vi < c.n) {
+      const u64 pv = c.P[v];
+      deg = degree(c, v);
+      if (deg > 0 && pv >= base_r) {
+        const u64 self = own_offer(c, v);
+        if (pv > self) {
+          const u64 old = atomic_min_u64(&c.P[v], self);
+          if (old > self &&
+              __hip_atomic_fetch_max(&c.stamp[v], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < 1u)
+            want = true;
+        }
+      }
+    }
+    block_append(ab, want, v, deg, c, k);
+  }
+}
+
+__device__ __forceinline__ int choose_dir(const RoundCtx& c, int dir, u64 nf, u64 af, u64 unsettled_arcs) {
+  if (c.dir_policy == DIR_TD) return DIR_TD;
+  if (c.dir_policy == DIR_BU) return DIR_BU;
+  if (dir == DIR_TD) return (af * (u64)c.td_to_bu > unsettled_arcs) ? DIR_BU : DIR_TD;
+  return (nf * (u64)c.bu_to_td < (u64)c.n) ? DIR_TD : DIR_BU;
+}
+
+// State of step k from the state of step k-1 and what step k-1 appended.
+// The state is read with coherent loads: in the persistent kernel it was written by another
+// block during the previous step.
+__device__ RoundState load_state(const RoundState* p) {
+  static_assert(sizeof(RoundState) % 8 == 0, "state is copied as 64-bit words");
+  RoundState s;
+  u64* d = reinterpret_cast<u64*>(&s);
+  const u64* src = reinterpret_cast<const u64*>(p);
+  for (int i = 0; i < (int)(sizeof(RoundState) / 8); ++i) d[i] = load_u64_relaxed(src + i);
+  return s;
+}
+
+__device__ void store_state(RoundState* p, const RoundState& s) {
+  const u64* src = reinterpret_cast<const u64*>(&s);
+  u64* d = reinterpret_cast<u64*>(p);
+  for (int i = 0; i < (int)(sizeof(RoundState) / 8); ++i)
+    __hip_atomic_store(d + i, src[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ RoundState next_state(const RoundCtx& c, int k) {
+  const RoundState P = load_state(&c.st[(k - 1) & 1]);
+  const u64 out = load_u64_relaxed(qcounter(c, k - 1));
+  RoundState S = P;
+  S.seq = (u64)k;
+  if (P.mode == MODE_DONE) return S;
+  const unsigned nf = min((unsigned)(out >> 32), (unsigned)c.n), af = (unsigned)out;
+  if (P.mode == MODE_ROUNDS) {
+    int next_r;
+    if (k > 1) {
+      S.settled += nf;
+      S.unsettled_arcs -= af;
+      S.rounds += 1;
+      if (P.prev >> 32) {
+        S.td_rounds += P.dir == DIR_TD;
+        S.bu_rounds += P.dir == DIR_BU;
+      }
+      S.max_frontier = nf > S.max_frontier ? nf : S.max_frontier;
+      next_r = nf ? P.round + 1 : c.next_ne[P.round + 1];
+    } else {
+      next_r = c.next_ne[0];
+    }
+    S.prev = out;
+    const u64 left = c.n_active - S.settled;
+    if (S.settled >= c.n_active) {
+      S.mode = MODE_DONE;
+    } else if (next_r >= c.R) {
+      S.mode = MODE_DONE;
+      if (blockIdx.x == 0) atomic_or_u32(&c.ctrl->err, ERR_WATCHDOG);
+    } else if (c.tail_den > 0 && left * (u64)c.tail_den <= c.n_active && c.R - next_r > c.tail_min_left) {
+      S.mode = MODE_TAIL;
+      S.round = 0;
+      S.tail_round = next_r;
+    } else {
+      S.round = next_r;
+      S.dir = nf ? choose_dir(c, P.dir, nf, af, S.unsettled_arcs) : P.dir;
+    }
+  } else {  // MODE_TAIL: step k-1 ran sweep P.round and queued `out`
+    S.tail_iters += 1;
+    S.round = P.round + 1;
+    S.prev = out;
+    if (nf == 0) S.mode = MODE_DONE;
+  }
+  return S;
+}
+
+__device__ void add_examined(Ctrl* ctrl, u64 examined) {
+  examined = wave_sum_u64(examined);
+  if (lane_id() == 0 && examined) atomic_add_u64(&ctrl->arcs_examined, examined);
+}
+
+// One step; returns the mode it ran in (MODE_DONE: nothing was left to do).
+__device__ int round_step(const RoundCtx& c, int k, AppendBuf& ab, StepShared& sh) {
+  if (threadIdx.x == 0) {
+    sh.S = next_state(c, k);
+    ab.n = 0;
+    ab.arcs = 0;
+  }
+  __syncthreads();
+  const RoundState S = sh.S;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    store_state(&c.st[k & 1], S);
+    __hip_atomic_store(qcounter(c, k + 1), 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (S.mode == MODE_DONE) return MODE_DONE;
+  const unsigned nf = min((unsigned)(S.prev >> 32), (unsigned)c.n), af = (unsigned)S.prev;
+  const int* qv = c.qv[(k - 1) & 1];
+  const unsigned* qa = c.qa[(k - 1) & 1];
+  u64 wmin = INF, examined = 0;
+  if (S.mode == MODE_ROUNDS) {
+    const int r = S.round;
+    if (nf && S.dir == DIR_BU) {
+      // L_r from the per-block minima the previous step left
+      u64 m = INF;
+      for (unsigned b = threadIdx.x; b < gridDim.x; b += RT) {
+        const u64 x = load_u64_relaxed(&c.lr_part[(size_t)((k - 1) & 1) * gridDim.x + b]);
+        m = x < m ? x : m;
+      }
+      m = block_min_u64(m, sh);
+      if (threadIdx.x == 0) sh.lr = m == INF ? INF : m + ((u64)1 << (FIX + c.B));
+      __syncthreads();
+    }
+    phase_wake(c, r, k, ab, wmin);
+    if (nf) {
+      if (S.dir == DIR_BU) {
+        phase_bottom_up(c, r, k, sh.lr, ab, wmin, examined);
+      } else {
+        phase_top_down<false>(c, k, qv, qa, nf, af, ab, sh, wmin, 0);
+        if (blockIdx.x == 0 && threadIdx.x == 0) examined += af;
+      }
+    }
+  } else {
+    const unsigned sweep = (unsigned)S.round;
+    if (sweep == 0) phase_tail_seed(c, S.tail_round, k, ab);
+    if (nf) {
+      phase_top_down<true>(c, k, qv, qa, nf, af, ab, sh, wmin, sweep);
+      if (blockIdx.x == 0 && threadIdx.x == 0) examined += af;
+    }
+  }
+  block_flush(ab, c, k);
+  const u64 bm = block_min_u64(wmin, sh);
+  if (threadIdx.x == 0) c.lr_part[(size_t)(k & 1) * gridDim.x + blockIdx.x] = bm;
+  add_examined(c.ctrl, examined);
+  return S.mode;
+}
+
+__global__ __launch_bounds__(RT) void k_round_step(RoundCtx c, int k) {
+  __shared__ AppendBuf ab;
+  __shared__ StepShared sh;
+  round_step(c, k, ab, sh);
+}
+
+// All steps in one kernel with grid barriers between them (the grid must be co-resident).
+__global__ __launch_bounds__(RT) void k_rounds_persistent(RoundCtx c) {
+  __shared__ AppendBuf ab;
+  __shared__ StepShared sh;
+  u64 gen = 0;
+  const long long kmax = (long long)c.R + c.n + 2;
+  for (int k = 1; k <= kmax; ++k) {
+    if (round_step(c, k, ab, sh) == MODE_DONE) break;
+    grid_sync(&c.ctrl->bar, gridDim.x, gen, &c.ctrl->err);
+    if (__hip_atomic_load(&c.ctrl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & (ERR_BARRIER | ERR_QUEUE)) break;
+  }
+}
+
+}  // namespace ldd

@@ -1,0 +1,261 @@
+"""GPU parity: the HIP library against the CPU oracle, bit for bit.
+
+Every test calls the C ABI of libldd.so through the Python binding and compares the centre
+of every vertex and the cut count with the oracle on the same seeded inputs.  The result is
+unique (ties go to the smaller id), so the comparison is exact equality.  Full-size
+workloads are compared with stored oracle digests (written by
+tests/golden/make_oracle_digests.py, which calls only the oracle), the linear-time
+certificate, and per-vertex evaluations of the definition.
+"""
+import hashlib
+import json
+import os
+import time
+
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+from graphs import S, small_cases
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_digests.json")
+
+# schedules that must all give the same bits: direction policy, engine, grid size, and the
+# label-correcting tail (off, default, or from the very first step)
+MODES = [
+    dict(),
+    dict(direction=1),
+    dict(direction=2),
+    dict(engine=1),
+    dict(engine=1, direction=2),
+    dict(blocks=3),
+    dict(blocks=7, direction=2),
+    dict(tail_vertices=-1),
+    dict(tail_vertices=1),
+]
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ldd():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1307_3692_amd as m
+    m.lib()
+    return m
+
+
+def to_dev(*arrays):
+    import torch
+    return [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in arrays]
+
+
+def run(ldd, rp, ci, s, beta=0.1, **opts):
+    d_rp, d_ci, d_s = to_dev(rp, ci, s)
+    centre, cut, st = ldd.decompose(d_rp, d_ci, d_s, beta, stats=True, **opts)
+    return centre.cpu().numpy(), cut, st
+
+
+def sha(a):
+    return hashlib.sha256(np.ascontiguousarray(a).view(np.uint8)).hexdigest()
+
+
+def test_small_graph_families_all_modes(ldd):
+    cases = small_cases(seed=1, count=30)
+    log(f"{len(cases)} small cases x {len(MODES)} modes")
+    for rp, ci, s, name in cases:
+        want_c, _, want_cut = oracle.decompose(rp, ci, s)
+        for mode in MODES:
+            got, cut, _ = run(ldd, rp, ci, s, **mode)
+            assert np.array_equal(got, want_c), (name, mode, np.nonzero(got != want_c)[0][:10])
+            assert cut == want_cut, (name, mode)
+
+
+def test_grid64_beta01_seed1(ldd):
+    rp, ci, s, beta = inputs.workload("grid2d-64x64")
+    want_c, length, want_cut = oracle.decompose(rp, ci, s)
+    for mode in MODES:
+        got, cut, st = run(ldd, rp, ci, s, beta, **mode)
+        log(f"grid64 {mode}: rounds {st['rounds']} td {st['td_rounds']} bu {st['bu_rounds']} "
+            f"tail {st['tail_iters']} cut {cut}")
+        assert np.array_equal(got, want_c), mode
+        assert cut == want_cut
+    assert st["pieces"] == np.count_nonzero(want_c == np.arange(want_c.size))
+    assert st["rounds_bound"] == (int(s.max()) >> 20) + 1
+
+
+def test_deterministic_repeats(ldd):
+    rp, ci, s, beta = inputs.workload("rmat-16")
+    first = None
+    for _ in range(10):
+        got, cut, _ = run(ldd, rp, ci, s, beta)
+        if first is None:
+            first = (got.copy(), cut)
+        assert np.array_equal(got, first[0]) and cut == first[1]
+
+
+@pytest.mark.parametrize("name", ["rmat-16", "rmat-18", "grid3d-64", "grid2d-1000"])
+def test_medium_workloads_vs_oracle(ldd, name):
+    rp, ci, s, beta = inputs.workload(name)
+    t = time.time()
+    want_c, _, want_cut = oracle.decompose(rp, ci, s)
+    log(f"{name}: n={rp.size - 1} nnz={ci.size} oracle {time.time() - t:.2f}s")
+    for mode in (dict(), dict(direction=1), dict(direction=2), dict(engine=1), dict(tail_vertices=-1),
+                 dict(tail_vertices=1)):
+        got, cut, st = run(ldd, rp, ci, s, beta, **mode)
+        log(f"  {mode}: rounds {st['rounds']} td {st['td_rounds']} bu {st['bu_rounds']} tail {st['tail_iters']} "
+            f"from {st['tail_round']} rounds_ms {st['ms_rounds']:.3f}")
+        assert np.array_equal(got, want_c), (mode, np.count_nonzero(got != want_c))
+        assert cut == want_cut
+
+
+@pytest.mark.parametrize("kind,n", [("er", 3000), ("rgg", 5000), ("er", 150_000), ("rgg", 200_000)])
+def test_batch_graph_kinds_vs_oracle(ldd, kind, n):
+    rp, ci = inputs.er(n, 8.0, 77) if kind == "er" else inputs.rgg(n, 6.0, 77)
+    for beta in (0.02, 0.3):
+        s = inputs.make_shifts(n, beta, 78)
+        want_c, _, want_cut = oracle.decompose(rp, ci, s)
+        got, cut, _ = run(ldd, rp, ci, s, beta)
+        assert np.array_equal(got, want_c) and cut == want_cut
+
+
+def test_tie_heavy_shifts(ldd):
+    rng = np.random.default_rng(5)
+    rp, ci = inputs.rmat(14, 16, seed=3)
+    n = rp.size - 1
+    for s in ((rng.integers(0, 6, n) * S).astype(np.int64), np.full(n, 7 * S, np.int64),
+              (rng.integers(0, 3, n) * S + rng.integers(0, 2, n)).astype(np.int64)):
+        want_c, _, want_cut = oracle.decompose(rp, ci, s)
+        for mode in MODES[:3]:
+            got, cut, _ = run(ldd, rp, ci, s, **mode)
+            assert np.array_equal(got, want_c) and cut == want_cut
+
+
+def test_beta_does_not_change_result(ldd):
+    rp, ci, s, _ = inputs.workload("grid2d-64x64")
+    a, ca, _ = run(ldd, rp, ci, s, 0.1)
+    b, cb, _ = run(ldd, rp, ci, s, 0.9)
+    assert np.array_equal(a, b) and ca == cb
+
+
+def full_size(ldd, name, modes):
+    with open(GOLDEN) as f:
+        gold = json.load(f)[name]
+    t = time.time()
+    rp, ci, s, beta = inputs.workload(name)
+    log(f"{name}: generated n={rp.size - 1} nnz={ci.size} in {time.time() - t:.1f}s")
+    assert sha(rp) == gold["sha_row_ptr"] and sha(ci) == gold["sha_col_idx"] and sha(s) == gold["sha_shift"], \
+        "input generator output differs from the one the digests were made with"
+    for mode in modes:
+        got, cut, st = run(ldd, rp, ci, s, beta, **mode)
+        log(f"  {mode}: rounds {st['rounds']} td {st['td_rounds']} bu {st['bu_rounds']} tail {st['tail_iters']} "
+            f"rounds_ms {st['ms_rounds']:.3f} prep_ms {st['ms_prep']:.3f} cut_ms {st['ms_cut']:.3f}")
+        assert sha(got) == gold["sha_centre"], mode
+        assert cut == gold["cut"]
+    t = time.time()
+    code, bad = oracle.certify(rp, ci, s, got)
+    log(f"  certificate {code} in {time.time() - t:.1f}s")
+    assert code == oracle.OK, bad
+    rng = np.random.default_rng(1)
+    for v in rng.integers(0, rp.size - 1, 4):
+        assert oracle.centre_of(rp, ci, s, int(v))[0] == got[v]
+
+
+def test_full_size_rmat24(ldd):
+    full_size(ldd, "rmat-24", (dict(), dict(direction=1), dict(engine=1), dict(tail_vertices=-1)))
+
+
+def test_full_size_grid3d_256(ldd):
+    full_size(ldd, "grid3d-256", (dict(), dict(engine=1), dict(tail_vertices=-1)))
+
+
+# ------------------------------------------------------------------------------------------
+# edge cases and errors
+# ------------------------------------------------------------------------------------------
+def test_degenerate_graphs(ldd):
+    import torch
+    # n = 0
+    d = torch.zeros(1, dtype=torch.int32, device="cuda")
+    c, cut = ldd.decompose(d, torch.zeros(0, dtype=torch.int32, device="cuda"),
+                           torch.zeros(0, dtype=torch.int64, device="cuda"), 0.1)
+    assert c.numel() == 0 and cut == 0
+    # single vertex, no edges, all isolated
+    for n in (1, 2, 1000):
+        rp, ci = inputs.from_edges(n, [], [])
+        s = inputs.make_shifts(n, 0.1, 4)
+        got, cut, _ = run(ldd, rp, ci, s)
+        assert np.array_equal(got, np.arange(n)) and cut == 0
+    # one edge with an exact tie: vertex 1 goes to the smaller id 0
+    rp, ci = inputs.from_edges(2, [0], [1])
+    got, _, _ = run(ldd, rp, ci, np.array([S + 5, 5], np.int64))
+    assert got.tolist() == [0, 0]
+    got, _, _ = run(ldd, rp, ci, np.array([5, S + 5], np.int64))
+    assert got.tolist() == [0, 1]
+    # a star with a hub of high degree (whole-tile and multi-tile rows)
+    for leaves in (300, 70_000):
+        rp, ci = inputs.from_edges(leaves + 1, np.zeros(leaves, np.int32), np.arange(1, leaves + 1))
+        s = inputs.make_shifts(leaves + 1, 0.05, 9)
+        want_c, _, want_cut = oracle.decompose(rp, ci, s)
+        for mode in MODES[:3]:
+            got, cut, _ = run(ldd, rp, ci, s, **mode)
+            assert np.array_equal(got, want_c) and cut == want_cut
+
+
+def test_errors_are_reported(ldd):
+    rp, ci = inputs.grid2d(8, 8)
+    s = inputs.make_shifts(64, 0.1, 1)
+    bad = s.copy()
+    bad[5] = -1
+    with pytest.raises(ldd.LddError) as e:
+        run(ldd, rp, ci, bad)
+    assert e.value.status == ldd.ERR_INVALID_ARG
+    # row_ptr not monotone
+    rp2 = rp.copy()
+    rp2[10] = rp2[11] + 1
+    with pytest.raises(ldd.LddError) as e:
+        run(ldd, rp2, ci, s)
+    assert e.value.status == ldd.ERR_INVALID_ARG
+    # column id out of range: caught by the validation pass and by the kernels' own checks
+    ci2 = ci.copy()
+    ci2[7] = 64
+    for validate in (True, False):
+        with pytest.raises(ldd.LddError) as e:
+            run(ldd, rp, ci2, s, validate=validate)
+        assert e.value.status == ldd.ERR_INVALID_ARG
+    # label overflow: Delta too large for 64-bit labels with 6 id bits
+    big = s.copy()
+    big[0] = 1 << 52
+    with pytest.raises(ldd.LddError) as e:
+        run(ldd, rp, ci, big)
+    assert e.value.status in (ldd.ERR_OVERFLOW,)
+    with pytest.raises(ldd.LddError):
+        run(ldd, rp, ci, s, beta=0.0)
+    # the library still works after errors
+    got, cut, _ = run(ldd, rp, ci, s)
+    want_c, _, want_cut = oracle.decompose(rp, ci, s)
+    assert np.array_equal(got, want_c) and cut == want_cut
+
+
+def test_batch_entry_matches_single(ldd):
+    import torch
+    graphs = inputs.batch_graphs(12, seed=3, n_lo=500, n_hi=20_000)
+    vo, ao, rps, cis, ss = [0], [0], [], [], []
+    for rp, ci, s, beta in graphs:
+        vo.append(vo[-1] + rp.size - 1)
+        ao.append(ao[-1] + ci.size)
+        rps.append(rp)
+        cis.append(ci)
+        ss.append(s)
+    d_rp, d_ci, d_s = to_dev(np.concatenate(rps), np.concatenate(cis), np.concatenate(ss))
+    centre, cuts = ldd.decompose_batch(vo, ao, d_rp, d_ci, d_s)
+    centre = centre.cpu().numpy()
+    for g, (rp, ci, s, beta) in enumerate(graphs):
+        want_c, _, want_cut = oracle.decompose(rp, ci, s)
+        assert np.array_equal(centre[vo[g]:vo[g + 1]], want_c), g
+        assert cuts[g] == want_cut
