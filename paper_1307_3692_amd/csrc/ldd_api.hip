@@ -3,6 +3,7 @@
 
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -80,15 +81,27 @@ ldd_status grow(Buf& b, size_t bytes) {
 struct HostMirror {  // pinned copies of the device control block and round states
   Ctrl ctrl;
   RoundState st[2];
+  RoundState live;  // written by the step kernels as they run
+  LaunchBlock lb;   // staging for the device copy
+};
+
+constexpr int CHUNK = 8;  // steps per graph replay
+
+struct StepGraph {
+  int blocks = 0;
+  hipGraphExec_t exec = nullptr;
 };
 
 struct Workspace {
   std::mutex mu;
-  Buf P, qv0, qv1, qa0, qa1, wake_ord, stamp;         // per vertex
-  Buf hist, cursor, wake_off, next_ne;                // per round
-  Buf ctrl, st, qcnt, lr_part;
+  Buf P, qv0, qv1, qa0, qa1, wake_ord, stamp, hub_bits;  // per vertex
+  Buf hist, cursor, wake_off, next_ne, mat;              // per round (mat: per round and prep block)
+  Buf ctrl, st, qcnt, lr_part, lb;
   HostMirror* host = nullptr;
   hipEvent_t ev[6] = {};
+  hipEvent_t chunk_ev[2] = {};
+  hipStream_t capture = nullptr;
+  std::vector<StepGraph> graphs;
   int num_cu = 0;
   int max_coresident = 0;  // co-resident blocks of the persistent round kernel
 };
@@ -105,8 +118,10 @@ Workspace* workspace_for(int dev) {
 
 ldd_status ws_setup(Workspace& w) {
   if (!w.host) {
-    HIP_TRY(hipHostMalloc((void**)&w.host, sizeof(HostMirror), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc((void**)&w.host, sizeof(HostMirror), hipHostMallocMapped | hipHostMallocCoherent));
     for (auto& e : w.ev) HIP_TRY(hipEventCreate(&e));
+    for (auto& e : w.chunk_ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    HIP_TRY(hipStreamCreateWithFlags(&w.capture, hipStreamNonBlocking));
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&w.num_cu, hipDeviceAttributeMultiprocessorCount, dev));
@@ -119,8 +134,31 @@ ldd_status ws_setup(Workspace& w) {
   }
   ldd_status s;
   if ((s = grow(w.ctrl, sizeof(Ctrl))) || (s = grow(w.st, 2 * sizeof(RoundState))) ||
-      (s = grow(w.qcnt, 3 * 16 * sizeof(u64))) || (s = grow(w.lr_part, 2 * (size_t)RT * sizeof(u64))))
+      (s = grow(w.qcnt, 3 * 16 * sizeof(u64))) || (s = grow(w.lr_part, 2 * (size_t)RT * sizeof(u64))) ||
+      (s = grow(w.lb, sizeof(LaunchBlock))))
     return s;
+  return LDD_OK;
+}
+
+// A graph of CHUNK step launches (reading their arguments from the workspace's LaunchBlock)
+// followed by one k_advance; instantiated once per grid size and replayed for every call.
+ldd_status step_graph(Workspace& w, int blocks, hipGraphExec_t* out) {
+  for (auto& g : w.graphs)
+    if (g.blocks == blocks) {
+      *out = g.exec;
+      return LDD_OK;
+    }
+  const LaunchBlock* lbp = (const LaunchBlock*)w.lb.p;
+  hipGraph_t graph = nullptr;
+  HIP_TRY(hipStreamBeginCapture(w.capture, hipStreamCaptureModeThreadLocal));
+  for (int j = 0; j < CHUNK; ++j) hipLaunchKernelGGL(k_round_step_lb, dim3(blocks), dim3(RT), 0, w.capture, lbp, j);
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, w.capture, (LaunchBlock*)w.lb.p, CHUNK);
+  HIP_TRY(hipStreamEndCapture(w.capture, &graph));
+  hipGraphExec_t exec = nullptr;
+  HIP_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  HIP_TRY(hipGraphDestroy(graph));
+  w.graphs.push_back({blocks, exec});
+  *out = exec;
   return LDD_OK;
 }
 
@@ -153,8 +191,11 @@ extern "C" void ldd_release_workspace(void) {
   if (hipGetDevice(&dev) != hipSuccess) return;
   Workspace* w = workspace_for(dev);
   std::lock_guard<std::mutex> lk(w->mu);
-  for (Buf* b : {&w->P, &w->qv0, &w->qv1, &w->qa0, &w->qa1, &w->wake_ord, &w->stamp, &w->hist, &w->cursor,
-                 &w->wake_off, &w->next_ne, &w->ctrl, &w->st, &w->qcnt, &w->lr_part}) {
+  for (auto& g : w->graphs) (void)hipGraphExecDestroy(g.exec);  // they hold workspace pointers
+  w->graphs.clear();
+  for (Buf* b : {&w->P, &w->qv0, &w->qv1, &w->qa0, &w->qa1, &w->wake_ord, &w->stamp, &w->hub_bits, &w->hist,
+                 &w->cursor, &w->wake_off, &w->next_ne, &w->mat, &w->ctrl, &w->st, &w->qcnt, &w->lr_part,
+                 &w->lb}) {
     if (b->p) (void)hipFree(b->p);
     b->p = nullptr;
     b->bytes = 0;
@@ -220,14 +261,15 @@ extern "C" ldd_status ldd_decompose(const ldd_csr* g, const int64_t* shift_fix, 
   if (s != LDD_OK) return s;
   const size_t nv = (size_t)n;
   if ((s = grow(w.P, nv * 8)) || (s = grow(w.qv0, nv * 4)) || (s = grow(w.qv1, nv * 4)) || (s = grow(w.qa0, nv * 4)) ||
-      (s = grow(w.qa1, nv * 4)) || (s = grow(w.wake_ord, nv * 4)) || (s = grow(w.stamp, nv * 4)))
+      (s = grow(w.qa1, nv * 4)) || (s = grow(w.wake_ord, nv * 4)) || (s = grow(w.stamp, nv * 4)) ||
+      (s = grow(w.hub_bits, (nv + 63) / 64 * 8)))
     return s;
   Ctrl* ctrl = (Ctrl*)w.ctrl.p;
   u64* P = (u64*)w.P.p;
 
   HIP_TRY(hipEventRecord(w.ev[0], st));
   HIP_TRY(hipMemsetAsync(ctrl, 0, sizeof(Ctrl), st));
-  const int g_n = grid_for(n, 256, 4096);
+  const int g_n = grid_for(n, 256 * 4, 2048);
   hipLaunchKernelGGL(k_init, dim3(g_n), dim3(256), 0, st, n, nnz, g->row_ptr, (const long long*)shift_fix, P, ctrl);
   if (o.validate && nnz > 0)
     hipLaunchKernelGGL(k_check_cols, dim3(grid_for(nnz, 256, 4096)), dim3(256), 0, st, n, nnz, g->col_idx, ctrl);
@@ -256,14 +298,28 @@ extern "C" ldd_status ldd_decompose(const ldd_csr* g, const int64_t* shift_fix, 
       (s = grow(w.next_ne, nr * 4)))
     return s;
 
-  HIP_TRY(hipMemsetAsync(w.hist.p, 0, nr * 4, st));
-  const int use_lds = R <= 8192;
-  hipLaunchKernelGGL(k_wake_count, dim3(g_n), dim3(256), use_lds ? (size_t)R * 4 : 0, st, n, B, g->row_ptr,
-                     (const long long*)shift_fix, (const Ctrl*)ctrl, P, (unsigned*)w.hist.p, (int)R, use_lds);
-  hipLaunchKernelGGL(k_wake_scan, dim3(1), dim3(1024), 0, st, (int)R, (const unsigned*)w.hist.p, (int*)w.wake_off.p,
-                     (int*)w.cursor.p, (int*)w.next_ne.p);
-  hipLaunchKernelGGL(k_wake_scatter, dim3(g_n), dim3(256), 0, st, n, g->row_ptr, (const long long*)shift_fix,
-                     (const Ctrl*)ctrl, (int*)w.cursor.p, (int*)w.wake_ord.p);
+  if (R <= 8192) {
+    // block-local counting sort: no global atomics on the (few, hot) wake buckets
+    const int gp = (int)std::min<long long>(1024, std::max<long long>(1, n / 16384));
+    if ((s = grow(w.mat, (size_t)R * gp * 4))) return s;
+    hipLaunchKernelGGL(k_wake_hist_blocks, dim3(gp), dim3(1024), (size_t)R * 4, st, n, B, g->row_ptr,
+                       (const long long*)shift_fix, (const Ctrl*)ctrl, P, (unsigned*)w.mat.p, (int)R);
+    hipLaunchKernelGGL(k_wake_bucket_scan, dim3((unsigned)((R * WAVE + 255) / 256)), dim3(256), 0, st, (int)R, gp,
+                       (unsigned*)w.mat.p, (unsigned*)w.hist.p);
+    hipLaunchKernelGGL(k_wake_scan, dim3(1), dim3(1024), 0, st, (int)R, (const unsigned*)w.hist.p,
+                       (int*)w.wake_off.p, (int*)w.cursor.p, (int*)w.next_ne.p);
+    hipLaunchKernelGGL(k_wake_place, dim3(gp), dim3(1024), (size_t)R * 4, st, n, g->row_ptr,
+                       (const long long*)shift_fix, (const Ctrl*)ctrl, (const unsigned*)w.mat.p,
+                       (const int*)w.wake_off.p, (int*)w.wake_ord.p, (int)R);
+  } else {
+    HIP_TRY(hipMemsetAsync(w.hist.p, 0, nr * 4, st));
+    hipLaunchKernelGGL(k_wake_count, dim3(g_n), dim3(256), 0, st, n, B, g->row_ptr, (const long long*)shift_fix,
+                       (const Ctrl*)ctrl, P, (unsigned*)w.hist.p, (int)R, 0);
+    hipLaunchKernelGGL(k_wake_scan, dim3(1), dim3(1024), 0, st, (int)R, (const unsigned*)w.hist.p,
+                       (int*)w.wake_off.p, (int*)w.cursor.p, (int*)w.next_ne.p);
+    hipLaunchKernelGGL(k_wake_scatter, dim3(g_n), dim3(256), 0, st, n, g->row_ptr, (const long long*)shift_fix,
+                       (const Ctrl*)ctrl, (int*)w.cursor.p, (int*)w.wake_ord.p);
+  }
   HIP_TRY(hipGetLastError());
 
   const int tail_den = o.tail_vertices < 0 ? 0 : (o.tail_vertices > 0 ? o.tail_vertices : 64);
@@ -307,6 +363,7 @@ extern "C" ldd_status ldd_decompose(const ldd_csr* g, const int64_t* shift_fix, 
   c.bu_to_td = o.bu_to_td > 0 ? o.bu_to_td : 24;
   c.tail_den = tail_den;
   c.tail_min_left = 16;
+  c.host_st = nullptr;
 
   const int engine = o.engine == LDD_ENGINE_AUTO ? LDD_ENGINE_LAUNCH : o.engine;
   int blocks = o.blocks > 0 ? o.blocks : 2 * w.num_cu;
@@ -323,32 +380,58 @@ extern "C" ldd_status ldd_decompose(const ldd_csr* g, const int64_t* shift_fix, 
       HIP_TRY(hipMemcpyAsync(w.host->st, w.st.p, 2 * sizeof(RoundState), hipMemcpyDeviceToHost, st));
       HIP_TRY(hipStreamSynchronize(st));
     } else {
-      // steps are enqueued in growing chunks; after each chunk the state is checked once
-      long long k = 1;
-      int chunk = 8;
+      // Steps run as replays of a captured chunk graph.  Two chunks are kept in flight: the
+      // host waits for the older one, reads the state the steps publish to mapped host memory,
+      // and enqueues another chunk only if the decomposition is not done yet.
+      hipGraphExec_t exec = nullptr;
+      if ((s = step_graph(w, blocks, &exec))) return s;
+      void* host_st_dev = nullptr;
+      HIP_TRY(hipHostGetDevicePointer(&host_st_dev, &w.host->live, 0));
+      c.host_st = (RoundState*)host_st_dev;
+      w.host->lb.c = c;
+      w.host->lb.kbase = 1;
+      volatile RoundState* live = &w.host->live;
+      live->mode = MODE_ROUNDS;
+      live->seq = 0;
+      HIP_TRY(hipMemcpyAsync(w.lb.p, &w.host->lb, sizeof(LaunchBlock), hipMemcpyHostToDevice, st));
+      long long submitted = 0;
+      int inflight = 0, oldest = 0;
+      for (int i = 0; i < 2; ++i) {
+        HIP_TRY(hipGraphLaunch(exec, st));
+        HIP_TRY(hipEventRecord(w.chunk_ev[i], st));
+        submitted += CHUNK;
+        ++inflight;
+      }
       for (;;) {
-        for (int j = 0; j < chunk; ++j, ++k) hipLaunchKernelGGL(k_round_step, dim3(blocks), dim3(RT), 0, st, c, (int)k);
-        HIP_TRY(hipGetLastError());
-        HIP_TRY(hipMemcpyAsync(w.host->st, w.st.p, 2 * sizeof(RoundState), hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-        const RoundState& last = w.host->st[0].seq > w.host->st[1].seq ? w.host->st[0] : w.host->st[1];
-        if (last.mode == MODE_DONE) break;
-        if (k > kmax) {
+        HIP_TRY(hipEventSynchronize(w.chunk_ev[oldest]));
+        --inflight;
+        if (live->mode == MODE_DONE) break;
+        if (submitted > kmax) {
+          HIP_TRY(hipStreamSynchronize(st));
           ldd_set_error("round steps exceeded their bound (%lld)", kmax);
           return LDD_ERR_INTERNAL;
         }
-        chunk = chunk < 64 ? chunk * 2 : 64;
+        HIP_TRY(hipGraphLaunch(exec, st));
+        HIP_TRY(hipEventRecord(w.chunk_ev[oldest], st));
+        submitted += CHUNK;
+        ++inflight;
+        oldest ^= 1;
       }
-      steps = k - 1;
+      steps = submitted;
+      HIP_TRY(hipMemcpyAsync(w.host->st, w.st.p, 2 * sizeof(RoundState), hipMemcpyDeviceToHost, st));
     }
   }
   (void)steps;
   HIP_TRY(hipEventRecord(w.ev[2], st));
-  hipLaunchKernelGGL(k_finalize, dim3(g_n), dim3(256), 0, st, n, B, (const u64*)P, centre, ctrl);
+  HIP_TRY(hipMemsetAsync(w.hub_bits.p, 0, (nv + 63) / 64 * 8, st));
+  const int g_f = grid_for(n, 1024 * 16, 1024);
+  hipLaunchKernelGGL(k_finalize, dim3(g_f), dim3(1024), 0, st, n, B, g->row_ptr, (const u64*)P, centre,
+                     (u64*)w.hub_bits.p, (int*)w.qv0.p, (unsigned*)w.qa0.p, ctrl);
   HIP_TRY(hipEventRecord(w.ev[3], st));
   if (nnz > 0)
-    hipLaunchKernelGGL(k_cut, dim3(grid_for(nnz, 256, 8192)), dim3(256), 0, st, n, nnz, g->row_ptr, g->col_idx,
-                       (const int*)centre, ctrl);
+    hipLaunchKernelGGL(k_cut, dim3(grid_for(nnz, 256 * 8, 2048)), dim3(256), 0, st, n, g->row_ptr, g->col_idx,
+                       (const int*)centre, (const u64*)w.hub_bits.p, (const int*)w.qv0.p, (const unsigned*)w.qa0.p,
+                       ctrl);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipEventRecord(w.ev[4], st));
   HIP_TRY(hipMemcpyAsync(&w.host->ctrl, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
@@ -360,17 +443,17 @@ extern "C" ldd_status ldd_decompose(const ldd_csr* g, const int64_t* shift_fix, 
   }
   const RoundState& fs = w.host->st[0].seq > w.host->st[1].seq ? w.host->st[0] : w.host->st[1];
   if (h.unreached != 0 || (n_active > 0 && fs.mode != MODE_DONE)) {
-    ldd_set_error("rounds ended with %llu labels unset (mode %d)", (unsigned long long)h.unreached, fs.mode);
+    ldd_set_error("rounds ended with %llu labels unset (mode %lld)", (unsigned long long)h.unreached, fs.mode);
     return LDD_ERR_INTERNAL;
   }
   if (cut_edges) *cut_edges = (int64_t)(h.cut_arcs / 2);
   if (stats) {
-    stats->rounds = n_active ? fs.rounds : 0;
+    stats->rounds = n_active ? (int32_t)fs.rounds : 0;
     stats->rounds_bound = (int32_t)R;
-    stats->td_rounds = n_active ? fs.td_rounds : 0;
-    stats->bu_rounds = n_active ? fs.bu_rounds : 0;
-    stats->tail_iters = n_active ? fs.tail_iters : 0;
-    stats->tail_round = n_active ? fs.tail_round : -1;
+    stats->td_rounds = n_active ? (int32_t)fs.td_rounds : 0;
+    stats->bu_rounds = n_active ? (int32_t)fs.bu_rounds : 0;
+    stats->tail_iters = n_active ? (int32_t)fs.tail_iters : 0;
+    stats->tail_round = n_active ? (int32_t)fs.tail_round : -1;
     stats->blocks = blocks;
     stats->delta = (int64_t)delta;
     stats->pieces = (int64_t)h.pieces;

@@ -46,6 +46,8 @@ struct Ctrl {
   u64 cut_arcs;         // arcs whose endpoints have different centres
   u64 pieces;           // vertices that are their own centre
   u64 unreached;        // labels still INF after the rounds (must be 0)
+  u64 hub;              // (degree << 32 | id) of the highest-degree vertex
+  u64 list_cnt;         // (count << 32 | arcs) of the rows outside the hub's piece
   u64 arcs_examined;    // arcs read by the traversal (top-down and bottom-up)
 };
 

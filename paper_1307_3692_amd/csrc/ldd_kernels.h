@@ -12,20 +12,27 @@ constexpr int RT = 1024;    // threads per block of the round kernels (16 waves)
 constexpr int ABUF = 4096;  // entries of a block's LDS append buffer
 
 // State after round-kernel step k (k = 0 is the initial state written by the host).
+// All fields are 64-bit so that the state can be copied field by field with coherent
+// 64-bit loads and stores (kept in registers: no type punning, no scratch).
+#define LDD_STATE_FIELDS(X)                                                                 \
+  X(seq)            /* k */                                                                 \
+  X(prev)           /* (count << 32 | arcs) of the queue step k consumes */                 \
+  X(settled)        /* vertices with arcs settled by the rounds so far */                   \
+  X(unsettled_arcs) /* arcs of vertices not settled by the rounds yet */                    \
+  X(max_frontier)                                                                           \
+  X(round)          /* rounds: the round step k processes; tail: the sweep index */         \
+  X(mode)           /* MODE_* */                                                            \
+  X(dir)            /* direction of the round step k processes */                           \
+  X(rounds)         /* statistics */                                                        \
+  X(td_rounds)                                                                              \
+  X(bu_rounds)                                                                              \
+  X(tail_iters)                                                                             \
+  X(tail_round)     /* first round the tail replaced (-1: none) */
+
 struct RoundState {
-  u64 seq;             // k
-  u64 prev;            // (count << 32 | arcs) of the queue step k consumes
-  u64 settled;         // vertices with arcs settled by the rounds so far
-  u64 unsettled_arcs;  // arcs of vertices not settled by the rounds yet
-  u64 max_frontier;
-  int round;           // rounds: the round step k processes; tail: the sweep index
-  int mode;            // MODE_*
-  int dir;             // direction of the round step k processes
-  int rounds;          // statistics
-  int td_rounds;
-  int bu_rounds;
-  int tail_iters;
-  int tail_round;      // first round the tail replaced (-1: none)
+#define LDD_DECL(f) long long f;
+  LDD_STATE_FIELDS(LDD_DECL)
+#undef LDD_DECL
 };
 
 // Everything a round step needs, passed by value.
@@ -55,6 +62,13 @@ struct RoundCtx {
   int bu_to_td;
   int tail_den;     // enter the tail once unsettled * tail_den <= n_active (0: never)
   int tail_min_left;  // ... and more than this many rounds remain
+  RoundState* host_st;  // pinned host mirror of the latest state (may be null)
+};
+
+// Arguments of graph-launched steps: step k = kbase + j of a chunk; k_advance moves kbase.
+struct LaunchBlock {
+  RoundCtx c;
+  long long kbase;
 };
 
 __global__ void k_init(int n, long long nnz, const int* row_ptr, const long long* shift, u64* P, Ctrl* ctrl);
@@ -64,10 +78,18 @@ __global__ void k_wake_count(int n, int B, const int* row_ptr, const long long* 
 __global__ void k_wake_scan(int R, const unsigned* hist, int* wake_off, int* cursor, int* next_ne);
 __global__ void k_wake_scatter(int n, const int* row_ptr, const long long* shift, const Ctrl* ctrl, int* cursor,
                                int* wake_ord);
+__global__ void k_wake_hist_blocks(int n, int B, const int* row_ptr, const long long* shift, const Ctrl* ctrl, u64* P,
+                                   unsigned* mat, int R);
+__global__ void k_wake_bucket_scan(int R, int G, unsigned* mat, unsigned* tot);
+__global__ void k_wake_place(int n, const int* row_ptr, const long long* shift, const Ctrl* ctrl, const unsigned* mat,
+                             const int* wake_off, int* wake_ord, int R);
 __global__ void k_fill_u64(u64* p, long long count, u64 value);
-__global__ void k_round_step(RoundCtx c, int k);
+__global__ void k_round_step_lb(const LaunchBlock* lb, int j);
+__global__ void k_advance(LaunchBlock* lb, int C);
 __global__ void k_rounds_persistent(RoundCtx c);
-__global__ void k_finalize(int n, int B, const u64* P, int* centre, Ctrl* ctrl);
-__global__ void k_cut(int n, long long nnz, const int* row_ptr, const int* col, const int* centre, Ctrl* ctrl);
+__global__ void k_finalize(int n, int B, const int* row_ptr, const u64* P, int* centre, u64* hub_bits, int* lv,
+                           unsigned* la, Ctrl* ctrl);
+__global__ void k_cut(int n, const int* row_ptr, const int* col, const int* centre, const u64* hub_bits, const int* lv,
+                      const unsigned* la, Ctrl* ctrl);
 
 }  // namespace ldd

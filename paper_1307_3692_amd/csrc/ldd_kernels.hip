@@ -20,10 +20,28 @@ namespace ldd {
 // ------------------------------------------------------------------------------------------
 // prep
 // ------------------------------------------------------------------------------------------
+// Block-wide reductions for 256-thread blocks (one global atomic per block, not per wave:
+// same-address atomics serialise at ~12 ns each).
+__device__ __forceinline__ u64 block_max_256(u64 v, u64* red) {
+  v = wave_max_u64(v);
+  __syncthreads();
+  if (lane_id() == 0) red[threadIdx.x / WAVE] = v;
+  __syncthreads();
+  const u64 a = red[0] > red[1] ? red[0] : red[1], b = red[2] > red[3] ? red[2] : red[3];
+  return a > b ? a : b;
+}
+__device__ __forceinline__ u64 block_sum_256(u64 v, u64* red) {
+  v = wave_sum_u64(v);
+  __syncthreads();
+  if (lane_id() == 0) red[threadIdx.x / WAVE] = v;
+  __syncthreads();
+  return red[0] + red[1] + red[2] + red[3];
+}
+
 __global__ __launch_bounds__(256) void k_init(int n, long long nnz, const int* __restrict__ row_ptr,
                                               const long long* __restrict__ shift, u64* __restrict__ P,
                                               Ctrl* ctrl) {
-  u64 mx = 0, active = 0;
+  u64 mx = 0, active = 0, hub = 0;
   unsigned bad = 0;
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
@@ -35,13 +53,18 @@ __global__ __launch_bounds__(256) void k_init(int n, long long nnz, const int* _
     if (v == 0 && a != 0) bad |= ERR_BAD_ROWPTR;
     if (v == n - 1 && (long long)b != nnz) bad |= ERR_BAD_ROWPTR;
     active += (b > a);
+    const u64 key = ((u64)(unsigned)(b - a) << 32) | (u64)v;  // degree, then id
+    hub = key > hub ? key : hub;
     P[v] = INF;
   }
-  mx = wave_max_u64(mx);
-  active = wave_sum_u64(active);
-  if (lane_id() == 0) {
+  __shared__ u64 red[3][4];
+  mx = block_max_256(mx, red[0]);
+  active = block_sum_256(active, red[1]);
+  hub = block_max_256(hub, red[2]);
+  if (threadIdx.x == 0) {
     if (mx) atomic_max_u64(&ctrl->delta, mx);
     if (active) atomic_add_u64(&ctrl->n_active, active);
+    atomic_max_u64(&ctrl->hub, hub);
   }
   if (bad) atomic_or_u32(&ctrl->err, bad);
 }
@@ -153,6 +176,73 @@ __global__ __launch_bounds__(256) void k_wake_scatter(int n, const int* __restri
   }
 }
 
+// Counting sort of vertices by wake round without global atomics (used when the R rounds fit
+// LDS): block b owns the contiguous vertex chunk [b n / G, (b+1) n / G).
+//   k_wake_hist_blocks  per-block LDS histogram -> mat[r * G + b]; isolated vertices settle
+//   k_wake_bucket_scan  per bucket, exclusive scan over blocks (in place) and bucket totals
+//   k_wake_scan         bucket offsets and next-non-empty links from the totals
+//   k_wake_place        each vertex goes to wake_off[r] + mat[r * G + b] + its rank in the block
+__device__ __forceinline__ void chunk_of(long long n, long long& lo, long long& hi) {
+  lo = n * blockIdx.x / gridDim.x;
+  hi = n * (blockIdx.x + 1) / gridDim.x;
+}
+
+__global__ __launch_bounds__(1024) void k_wake_hist_blocks(int n, int B, const int* __restrict__ row_ptr,
+                                                          const long long* __restrict__ shift,
+                                                          const Ctrl* __restrict__ ctrl, u64* __restrict__ P,
+                                                          unsigned* __restrict__ mat, int R) {
+  extern __shared__ unsigned h[];
+  for (int i = threadIdx.x; i < R; i += blockDim.x) h[i] = 0;
+  __syncthreads();
+  const u64 delta = ctrl->delta;
+  long long lo, hi;
+  chunk_of(n, lo, hi);
+  for (long long v = lo + threadIdx.x; v < hi; v += blockDim.x) {
+    const u64 off = delta - (u64)shift[v];
+    if (row_ptr[v + 1] == row_ptr[v]) P[v] = (off << B) | (u64)v;
+    else atomicAdd(&h[(int)(off >> FIX)], 1u);
+  }
+  __syncthreads();
+  const unsigned G = gridDim.x;
+  for (int r = threadIdx.x; r < R; r += blockDim.x) mat[(size_t)r * G + blockIdx.x] = h[r];
+}
+
+// one wave per bucket: exclusive scan of its G block counts, 64 at a time
+__global__ __launch_bounds__(256) void k_wake_bucket_scan(int R, int G, unsigned* __restrict__ mat,
+                                                          unsigned* __restrict__ tot) {
+  const int r = (int)((blockIdx.x * blockDim.x + threadIdx.x) / WAVE);
+  if (r >= R) return;  // whole waves leave together
+  const unsigned lane = lane_id();
+  unsigned* row = mat + (size_t)r * G;
+  unsigned run = 0;
+  for (int b0 = 0; b0 < G; b0 += WAVE) {
+    const int b = b0 + (int)lane;
+    const unsigned x = b < G ? row[b] : 0u;
+    const unsigned incl = wave_incl_scan(x);
+    if (b < G) row[b] = run + incl - x;
+    run += __shfl(incl, WAVE - 1, WAVE);
+  }
+  if (lane == 0) tot[r] = run;
+}
+
+__global__ __launch_bounds__(1024) void k_wake_place(int n, const int* __restrict__ row_ptr,
+                                                    const long long* __restrict__ shift, const Ctrl* __restrict__ ctrl,
+                                                    const unsigned* __restrict__ mat, const int* __restrict__ wake_off,
+                                                    int* __restrict__ wake_ord, int R) {
+  extern __shared__ unsigned cur[];
+  const unsigned G = gridDim.x;
+  for (int r = threadIdx.x; r < R; r += blockDim.x) cur[r] = (unsigned)wake_off[r] + mat[(size_t)r * G + blockIdx.x];
+  __syncthreads();
+  const u64 delta = ctrl->delta;
+  long long lo, hi;
+  chunk_of(n, lo, hi);
+  for (long long v = lo + threadIdx.x; v < hi; v += blockDim.x) {
+    if (row_ptr[v + 1] == row_ptr[v]) continue;
+    const int w = (int)((delta - (u64)shift[v]) >> FIX);
+    wake_ord[atomicAdd(&cur[w], 1u)] = (int)v;
+  }
+}
+
 __global__ void k_fill_u64(u64* p, long long count, u64 value) {
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = value;
@@ -162,103 +252,222 @@ __global__ void k_fill_u64(u64* p, long long count, u64 value) {
 // ------------------------------------------------------------------------------------------
 // output
 // ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_finalize(int n, int B, const u64* __restrict__ P, int* __restrict__ centre,
-                                                  Ctrl* ctrl) {
+// Centre of every vertex (Algorithm 1 step 4: the origin of its shortest path), plus one bit
+// per vertex, "same centre as the highest-degree vertex" (piece H), and the list of vertices
+// with arcs outside H together with the running prefix of their degrees.
+//
+// Every cut edge has an endpoint outside H, so the cut is found from those rows alone:
+//   cut = #{arcs v->w : v not in H, w in H} + #{arcs v->w : v, w not in H, c(v) != c(w)} / 2
+// (an edge with one endpoint in H is seen once; one with both outside is seen twice).  On
+// graphs with one dominant piece that skips nearly every arc.
+constexpr int FT = 1024;     // threads per finalize block
+constexpr int FBUF = 4096;   // LDS list buffer entries
+
+__global__ __launch_bounds__(FT) void k_finalize(int n, int B, const int* __restrict__ row_ptr,
+                                                 const u64* __restrict__ P, int* __restrict__ centre,
+                                                 u64* __restrict__ hub_bits, int* __restrict__ lv,
+                                                 unsigned* __restrict__ la, Ctrl* ctrl) {
+  __shared__ int b_vert[FBUF];
+  __shared__ unsigned b_off[FBUF];
+  __shared__ unsigned w_cnt[FT / WAVE], w_arcs[FT / WAVE];
+  __shared__ unsigned b_n, b_arcs;
+  __shared__ u64 b_base;
+  __shared__ u64 red[2][FT / WAVE];
   const u64 mask = ((u64)1 << B) - 1;
+  const int hub = (int)(unsigned)ctrl->hub;
+  const int hub_c = (hub >= 0 && hub < n) ? (int)(P[hub] & mask) : -1;
+  if (threadIdx.x == 0) {
+    b_n = 0;
+    b_arcs = 0;
+  }
   u64 pieces = 0, unreached = 0;
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
-    const u64 p = P[v];
-    const int cv = (int)(p & mask);
-    centre[v] = cv;
-    pieces += (cv == (int)v);
-    unreached += (p == INF);
+  const unsigned wid = threadIdx.x / WAVE, lane = lane_id();
+  // contiguous chunk per block, walked 1024 vertices at a time (a wave covers 64 consecutive)
+  const long long lo = (long long)n * blockIdx.x / gridDim.x, hi = (long long)n * (blockIdx.x + 1) / gridDim.x;
+  const long long lo64 = lo & ~63ll;
+  for (long long base = lo64; base < hi; base += FT) {
+    const long long v = base + threadIdx.x;
+    const bool mine = v >= lo && v < hi;
+    bool in_hub = false, want = false;
+    unsigned deg = 0;
+    if (mine) {
+      const u64 p = P[v];
+      const int cv = (int)(p & mask);
+      centre[v] = cv;
+      pieces += (cv == (int)v);
+      unreached += (p == INF);
+      in_hub = cv == hub_c;
+      deg = (unsigned)(row_ptr[v + 1] - row_ptr[v]);
+      want = !in_hub && deg > 0;
+    }
+    // bitmap word of 64 consecutive vertices; a word straddling two chunks is split by atomics
+    const u64 bits = __ballot(in_hub);
+    if (lane == 0 && base + threadIdx.x < n) {
+      const long long w0 = (base + threadIdx.x) >> 6;
+      const long long first = base + threadIdx.x, last = first + 63;
+      if (first >= lo && last < hi) hub_bits[w0] = bits;
+      else if (bits) __hip_atomic_fetch_or(&hub_bits[w0], bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // block-aggregated append of the list entries
+    const u64 m = __ballot(want);
+    const unsigned incl = wave_incl_scan(want ? deg : 0u);
+    if (lane == WAVE - 1) {
+      w_cnt[wid] = (unsigned)__popcll(m);
+      w_arcs[wid] = incl;
+    }
+    __syncthreads();
+    unsigned wc = 0, wa = 0, tc = 0, ta = 0;
+    for (int w = 0; w < FT / WAVE; ++w) {
+      if (w < (int)wid) {
+        wc += w_cnt[w];
+        wa += w_arcs[w];
+      }
+      tc += w_cnt[w];
+      ta += w_arcs[w];
+    }
+    if (b_n + tc > (unsigned)FBUF) {  // flush (uniform: every thread reads the same b_n, tc)
+      if (threadIdx.x == 0) b_base = atomic_add_u64(&ctrl->list_cnt, ((u64)b_n << 32) | b_arcs);
+      __syncthreads();
+      for (unsigned i = threadIdx.x; i < b_n; i += FT) {
+        const unsigned idx = (unsigned)(b_base >> 32) + i;
+        if (idx < (unsigned)n) {
+          lv[idx] = b_vert[i];
+          la[idx] = (unsigned)b_base + b_off[i];
+        }
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        b_n = 0;
+        b_arcs = 0;
+      }
+      __syncthreads();
+    }
+    const unsigned fill = b_n, fill_arcs = b_arcs;
+    if (want) {
+      const unsigned idx = fill + wc + rank_below(m);
+      b_vert[idx] = (int)v;
+      b_off[idx] = fill_arcs + wa + incl - deg;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      b_n = fill + tc;
+      b_arcs = fill_arcs + ta;
+    }
+    __syncthreads();
+  }
+  if (b_n) {
+    if (threadIdx.x == 0) b_base = atomic_add_u64(&ctrl->list_cnt, ((u64)b_n << 32) | b_arcs);
+    __syncthreads();
+    for (unsigned i = threadIdx.x; i < b_n; i += FT) {
+      const unsigned idx = (unsigned)(b_base >> 32) + i;
+      if (idx < (unsigned)n) {
+        lv[idx] = b_vert[i];
+        la[idx] = (unsigned)b_base + b_off[i];
+      }
+    }
   }
   pieces = wave_sum_u64(pieces);
   unreached = wave_sum_u64(unreached);
-  if (lane_id() == 0 && pieces) atomic_add_u64(&ctrl->pieces, pieces);
-  if (lane_id() == 0 && unreached) atomic_add_u64(&ctrl->unreached, unreached);
+  __syncthreads();
+  if (lane == 0) {
+    red[0][wid] = pieces;
+    red[1][wid] = unreached;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    u64 p = 0, u = 0;
+    for (int w = 0; w < FT / WAVE; ++w) {
+      p += red[0][w];
+      u += red[1][w];
+    }
+    if (p) atomic_add_u64(&ctrl->pieces, p);
+    if (u) atomic_add_u64(&ctrl->unreached, u);
+  }
 }
 
-// Cut arcs: the nnz arcs are split evenly over the grid; each block walks its range in tiles
-// of 256 arcs with a window of row offsets in LDS (zero-degree rows may be skipped over, so
-// a window can end before the tile does; the loop then just advances the window).
-__global__ __launch_bounds__(256) void k_cut(int n, long long nnz, const int* __restrict__ row_ptr,
-                                             const int* __restrict__ col, const int* __restrict__ centre, Ctrl* ctrl) {
+__device__ __forceinline__ bool hub_bit(const u64* bits, int v) { return (bits[v >> 6] >> (v & 63)) & 1; }
+
+// Cut count over the list of rows outside H (see k_finalize): its arcs are split evenly over
+// the grid and walked in tiles of 256 with the list entries staged in LDS.
+__global__ __launch_bounds__(256) void k_cut(int n, const int* __restrict__ row_ptr, const int* __restrict__ col,
+                                             const int* __restrict__ centre, const u64* __restrict__ hub_bits,
+                                             const int* __restrict__ lv, const unsigned* __restrict__ la,
+                                             Ctrl* ctrl) {
   constexpr int T = 256;
-  __shared__ int w_rp[T + 1];
-  __shared__ int s_v;
-  const long long G = gridDim.x;
-  const long long a_begin = nnz * blockIdx.x / G;
-  const long long a_end = nnz * (blockIdx.x + 1) / G;
-  u64 cut = 0;
+  __shared__ unsigned w_pre[T + 1];
+  __shared__ int w_first[T + 1];
+  __shared__ int w_c[T + 1];
+  __shared__ unsigned s_start;
+  __shared__ u64 red[4];
+  const u64 lc = ctrl->list_cnt;
+  const unsigned nl = min((unsigned)(lc >> 32), (unsigned)n), al = (unsigned)lc;
+  const unsigned G = gridDim.x;
+  const unsigned a_begin = (unsigned)(((u64)al * blockIdx.x) / G);
+  const unsigned a_end = (unsigned)(((u64)al * (blockIdx.x + 1)) / G);
+  u64 one_side = 0, both = 0;
   if (a_begin < a_end) {
     if (threadIdx.x == 0) {
-      int lo = 0, hi = n;  // last v with row_ptr[v] <= a_begin
+      unsigned lo = 0, hi = nl;
       while (hi - lo > 1) {
-        const int mid = (int)(((unsigned)lo + (unsigned)hi) >> 1);
-        if (row_ptr[mid] <= a_begin) lo = mid;
+        const unsigned mid = (lo + hi) >> 1;
+        if (la[mid] <= a_begin) lo = mid;
         else hi = mid;
       }
-      s_v = lo;
+      s_start = lo;
     }
     __syncthreads();
-    int v0 = s_v;
-    long long a_cur = a_begin;
-    while (a_cur < a_end) {
-      for (int k = threadIdx.x; k <= T; k += T) w_rp[k] = (v0 + k <= n) ? row_ptr[v0 + k] : (int)nnz;
+    unsigned ent = s_start;
+    for (unsigned tile = a_begin; tile < a_end; tile += T) {
+      for (int kk = threadIdx.x; kk <= T; kk += T) {
+        const unsigned e = ent + kk;
+        if (e < nl) {
+          const int v = lv[e];
+          const bool ok = (unsigned)v < (unsigned)n;
+          w_pre[kk] = la[e];
+          w_first[kk] = ok ? row_ptr[v] : 0;
+          w_c[kk] = ok ? centre[v] : -1;
+        } else {
+          w_pre[kk] = al;
+          w_first[kk] = 0;
+          w_c[kk] = -1;
+        }
+      }
       __syncthreads();
-      const long long win_end = w_rp[T];  // arcs of rows v0 .. v0+T-1 end here
-      long long t_end = a_cur + T;
-      if (t_end > a_end) t_end = a_end;
-      if (t_end > win_end) t_end = win_end;
-      const long long a = a_cur + threadIdx.x;
-      if (a < t_end) {
-        int lo = 0, hi = T;  // last k with w_rp[k] <= a
+      const unsigned a = tile + threadIdx.x;
+      if (a < a_end) {
+        int lo = 0, hi = T;
         while (hi - lo > 1) {
           const int mid = (lo + hi) >> 1;
-          if (w_rp[mid] <= a) lo = mid;
+          if (w_pre[mid] <= a) lo = mid;
           else hi = mid;
         }
-        const int v = v0 + lo;
-        const int w = col[a];
-        if ((unsigned)w < (unsigned)n) cut += (centre[w] != centre[v]);
+        const unsigned j = a - w_pre[lo];
+        if (j < w_pre[lo + 1] - w_pre[lo]) {
+          const int w = col[(long long)w_first[lo] + j];
+          if ((unsigned)w < (unsigned)n) {
+            if (hub_bit(hub_bits, w)) one_side += 1;
+            else both += (centre[w] != w_c[lo]);
+          }
+        }
+      }
+      const unsigned next = tile + T;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        int lo = 0, hi = T + 1;
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (w_pre[mid] <= next) lo = mid;
+          else hi = mid;
+        }
+        s_start = ent + lo;
       }
       __syncthreads();
-      if (t_end >= win_end && t_end < a_end) {
-        v0 += T;  // window exhausted before the tile: move the window
-        // skip rows that end before t_end
-        if (threadIdx.x == 0) {
-          int lo = v0, hi = n;
-          while (hi - lo > 1) {
-            const int mid = (int)(((unsigned)lo + (unsigned)hi) >> 1);
-            if (row_ptr[mid] <= t_end) lo = mid;
-            else hi = mid;
-          }
-          s_v = lo;
-        }
-        __syncthreads();
-        v0 = s_v;
-        __syncthreads();
-      } else if (t_end < a_end) {
-        if (threadIdx.x == 0) {
-          int lo = 0, hi = T;
-          while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (w_rp[mid] <= t_end) lo = mid;
-            else hi = mid;
-          }
-          s_v = v0 + lo;
-        }
-        __syncthreads();
-        v0 = s_v;
-        __syncthreads();
-      }
-      a_cur = t_end;
+      ent = s_start;
     }
   }
-  cut = wave_sum_u64(cut);
-  if (lane_id() == 0 && cut) atomic_add_u64(&ctrl->cut_arcs, cut);
+  // cut_arcs accumulates 2 per one-sided arc and 1 per two-sided arc: cut = cut_arcs / 2
+  const u64 v = block_sum_256(2 * one_side + both, red);
+  if (threadIdx.x == 0 && v) atomic_add_u64(&ctrl->cut_arcs, v);
 }
 
 }  // namespace ldd

@@ -50,7 +50,7 @@ struct StepShared {
 __device__ __forceinline__ u64* qcounter(const RoundCtx& c, int k) { return c.qcnt + (size_t)(k % 3) * 16; }
 
 // Copy the LDS buffer to the global queue of step k behind one reservation.
-__device__ void block_flush(AppendBuf& ab, const RoundCtx& c, int k) {
+__device__ __forceinline__ void block_flush(AppendBuf& ab, const RoundCtx& c, int k) {
   __syncthreads();
   const unsigned cnt = ab.n, arcs = ab.arcs;
   if (cnt == 0) return;
@@ -79,7 +79,7 @@ __device__ void block_flush(AppendBuf& ab, const RoundCtx& c, int k) {
 
 // Block-wide append of one tile: ballot and wave scans give each appending thread its slot
 // and arc offset; wave totals are combined through LDS.  Called by every thread of the block.
-__device__ void block_append(AppendBuf& ab, bool want, int v, unsigned deg, const RoundCtx& c, int k) {
+__device__ __forceinline__ void block_append(AppendBuf& ab, bool want, int v, unsigned deg, const RoundCtx& c, int k) {
   const unsigned lane = lane_id(), wid = threadIdx.x / WAVE;
   const u64 mask = __ballot(want);
   const unsigned incl = wave_incl_scan(want ? deg : 0u);
@@ -140,7 +140,7 @@ __device__ __forceinline__ u64 own_offer(const RoundCtx& c, int v) {
 }
 
 // ---- round r: wake bucket r (the delayed source arcs of length in [r, r+1) units) ----------
-__device__ void phase_wake(const RoundCtx& c, int r, int k, AppendBuf& ab, u64& wmin) {
+__device__ __forceinline__ void phase_wake(const RoundCtx& c, int r, int k, AppendBuf& ab, u64& wmin) {
   const int lo = c.wake_off[r], hi = c.wake_off[r + 1];
   const int cnt = hi - lo;
   for (long long base = (long long)blockIdx.x * RT; base < cnt; base += (long long)gridDim.x * RT) {
@@ -175,7 +175,7 @@ __device__ void phase_wake(const RoundCtx& c, int r, int k, AppendBuf& ab, u64& 
 // TAIL = true: tail sweep `sweep`; an arc appends its far end whenever it lowered the label
 // and the far end is not queued for the next sweep yet.
 template <bool TAIL>
-__device__ void phase_top_down(const RoundCtx& c, int k, const int* qv, const unsigned* qa, unsigned nf, unsigned af,
+__device__ __forceinline__ void phase_top_down(const RoundCtx& c, int k, const int* qv, const unsigned* qa, unsigned nf, unsigned af,
                                AppendBuf& ab, StepShared& sh, u64& wmin, unsigned sweep) {
   unsigned* w_pre = sh.w_pre;
   int* w_first = sh.w_first;
@@ -275,7 +275,7 @@ __device__ void phase_top_down(const RoundCtx& c, int k, const int* qv, const un
 // ---- bottom-up: vertices not settled before round r pull from their neighbours in F_{r-1} ---
 // A neighbour u is in F_{r-1} iff its label lies in [base(r-1), base(r)).  L_r (the smallest
 // offer F_{r-1} makes) ends the scan as soon as it is attained.
-__device__ void phase_bottom_up(const RoundCtx& c, int r, int k, u64 Lr, AppendBuf& ab, u64& wmin, u64& examined) {
+__device__ __forceinline__ void phase_bottom_up(const RoundCtx& c, int r, int k, u64 Lr, AppendBuf& ab, u64& wmin, u64& examined) {
   const int B = c.B;
   const u64 unit = (u64)1 << (FIX + B);
   const u64 base_r = (u64)r << (FIX + B);
@@ -320,9 +320,16 @@ __device__ void phase_bottom_up(const RoundCtx& c, int r, int k, u64 Lr, AppendB
   }
 }
 
-// ---- tail seed: every vertex not settled before round r offers itself -----------------------
-__device__ void phase_tail_seed(const RoundCtx& c, int r, int k, AppendBuf& ab) {
-  const u64 base_r = (u64)r << (FIX + c.B);
+// ---- tail seed: every vertex not settled before round r takes the best of its own arc and
+// the offers of its neighbours in F_{r-1} (the only settled vertices whose offers have not
+// been propagated yet); the sweeps then relax to the fixpoint.  Pulling touches only the
+// rows of unsettled vertices, which are few when the tail starts.
+__device__ __forceinline__ void phase_tail_seed(const RoundCtx& c, int r, int k, u64 Lr, AppendBuf& ab,
+                                                u64& examined) {
+  const int B = c.B;
+  const u64 unit = (u64)1 << (FIX + B);
+  const u64 base_r = (u64)r << (FIX + B);
+  const u64 prev_round = (u64)(r - 1);
   for (long long base = (long long)blockIdx.x * RT; base < c.n; base += (long long)gridDim.x * RT) {
     const long long vi = base + threadIdx.x;
     bool want = false;
@@ -330,14 +337,25 @@ __device__ void phase_tail_seed(const RoundCtx& c, int r, int k, AppendBuf& ab) 
     const int v = (int)vi;
     if (vi < c.n) {
       const u64 pv = c.P[v];
-      deg = degree(c, v);
-      if (deg > 0 && pv >= base_r) {
-        const u64 self = own_offer(c, v);
-        if (pv > self) {
-          const u64 old = atomic_min_u64(&c.P[v], self);
-          if (old > self &&
-              __hip_atomic_fetch_max(&c.stamp[v], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < 1u)
-            want = true;
+      if (pv >= base_r) {
+        const int a0 = c.row_ptr[v], a1 = c.row_ptr[v + 1];
+        deg = (unsigned)(a1 - a0);
+        if (deg > 0) {
+          u64 best = own_offer(c, v);
+          for (int a = a0; a < a1 && best > Lr; ++a) {
+            ++examined;
+            const int u = c.col[a];
+            if ((unsigned)u >= (unsigned)c.n) {
+              atomic_or_u32(&c.ctrl->err, ERR_BAD_COL);
+              break;
+            }
+            const u64 pu = load_u64_relaxed(&c.P[u]);
+            if ((pu >> (FIX + B)) == prev_round && pu != INF && pu + unit < best) best = pu + unit;
+          }
+          if (best < pv) {
+            atomic_min_u64(&c.P[v], best);
+            want = __hip_atomic_fetch_max(&c.stamp[v], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < 1u;
+          }
         }
       }
     }
@@ -345,37 +363,41 @@ __device__ void phase_tail_seed(const RoundCtx& c, int r, int k, AppendBuf& ab) 
   }
 }
 
+// Direction of the next round.  Top-down touches every arc of the frontier (random accesses);
+// bottom-up reads every label once (sequential) plus at most the arcs of unsettled vertices,
+// usually far fewer thanks to the early exit.  Bottom-up is taken once the frontier's arcs
+// outweigh that work, and kept until the frontier is small again and top-down is cheaper.
 __device__ __forceinline__ int choose_dir(const RoundCtx& c, int dir, u64 nf, u64 af, u64 unsettled_arcs) {
   if (c.dir_policy == DIR_TD) return DIR_TD;
   if (c.dir_policy == DIR_BU) return DIR_BU;
-  if (dir == DIR_TD) return (af * (u64)c.td_to_bu > unsettled_arcs) ? DIR_BU : DIR_TD;
-  return (nf * (u64)c.bu_to_td < (u64)c.n) ? DIR_TD : DIR_BU;
+  const bool bu_better = af * (u64)c.td_to_bu > unsettled_arcs + (u64)c.n / 4;
+  if (dir == DIR_TD) return bu_better ? DIR_BU : DIR_TD;
+  return (bu_better || nf * (u64)c.bu_to_td >= (u64)c.n) ? DIR_BU : DIR_TD;
 }
 
 // State of step k from the state of step k-1 and what step k-1 appended.
 // The state is read with coherent loads: in the persistent kernel it was written by another
 // block during the previous step.
 __device__ RoundState load_state(const RoundState* p) {
-  static_assert(sizeof(RoundState) % 8 == 0, "state is copied as 64-bit words");
   RoundState s;
-  u64* d = reinterpret_cast<u64*>(&s);
-  const u64* src = reinterpret_cast<const u64*>(p);
-  for (int i = 0; i < (int)(sizeof(RoundState) / 8); ++i) d[i] = load_u64_relaxed(src + i);
+#define LDD_LOAD(f) s.f = __hip_atomic_load(&p->f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  LDD_STATE_FIELDS(LDD_LOAD)
+#undef LDD_LOAD
   return s;
 }
 
+template <int SCOPE>
 __device__ void store_state(RoundState* p, const RoundState& s) {
-  const u64* src = reinterpret_cast<const u64*>(&s);
-  u64* d = reinterpret_cast<u64*>(p);
-  for (int i = 0; i < (int)(sizeof(RoundState) / 8); ++i)
-    __hip_atomic_store(d + i, src[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#define LDD_STORE(f) __hip_atomic_store(&p->f, s.f, __ATOMIC_RELAXED, SCOPE);
+  LDD_STATE_FIELDS(LDD_STORE)
+#undef LDD_STORE
 }
 
-__device__ RoundState next_state(const RoundCtx& c, int k) {
+__device__ __forceinline__ RoundState next_state(const RoundCtx& c, int k) {
   const RoundState P = load_state(&c.st[(k - 1) & 1]);
   const u64 out = load_u64_relaxed(qcounter(c, k - 1));
   RoundState S = P;
-  S.seq = (u64)k;
+  S.seq = k;
   if (P.mode == MODE_DONE) return S;
   const unsigned nf = min((unsigned)(out >> 32), (unsigned)c.n), af = (unsigned)out;
   if (P.mode == MODE_ROUNDS) {
@@ -388,14 +410,14 @@ __device__ RoundState next_state(const RoundCtx& c, int k) {
         S.td_rounds += P.dir == DIR_TD;
         S.bu_rounds += P.dir == DIR_BU;
       }
-      S.max_frontier = nf > S.max_frontier ? nf : S.max_frontier;
-      next_r = nf ? P.round + 1 : c.next_ne[P.round + 1];
+      S.max_frontier = (long long)nf > S.max_frontier ? (long long)nf : S.max_frontier;
+      next_r = nf ? (int)P.round + 1 : c.next_ne[P.round + 1];
     } else {
       next_r = c.next_ne[0];
     }
-    S.prev = out;
-    const u64 left = c.n_active - S.settled;
-    if (S.settled >= c.n_active) {
+    S.prev = (long long)out;
+    const u64 left = c.n_active - (u64)S.settled;
+    if ((u64)S.settled >= c.n_active) {
       S.mode = MODE_DONE;
     } else if (next_r >= c.R) {
       S.mode = MODE_DONE;
@@ -406,12 +428,12 @@ __device__ RoundState next_state(const RoundCtx& c, int k) {
       S.tail_round = next_r;
     } else {
       S.round = next_r;
-      S.dir = nf ? choose_dir(c, P.dir, nf, af, S.unsettled_arcs) : P.dir;
+      S.dir = nf ? choose_dir(c, (int)P.dir, nf, af, (u64)S.unsettled_arcs) : P.dir;
     }
   } else {  // MODE_TAIL: step k-1 ran sweep P.round and queued `out`
     S.tail_iters += 1;
     S.round = P.round + 1;
-    S.prev = out;
+    S.prev = (long long)out;
     if (nf == 0) S.mode = MODE_DONE;
   }
   return S;
@@ -423,7 +445,7 @@ __device__ void add_examined(Ctrl* ctrl, u64 examined) {
 }
 
 // One step; returns the mode it ran in (MODE_DONE: nothing was left to do).
-__device__ int round_step(const RoundCtx& c, int k, AppendBuf& ab, StepShared& sh) {
+__device__ __forceinline__ int round_step(const RoundCtx& c, int k, AppendBuf& ab, StepShared& sh) {
   if (threadIdx.x == 0) {
     sh.S = next_state(c, k);
     ab.n = 0;
@@ -432,27 +454,32 @@ __device__ int round_step(const RoundCtx& c, int k, AppendBuf& ab, StepShared& s
   __syncthreads();
   const RoundState S = sh.S;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    store_state(&c.st[k & 1], S);
+    store_state<__HIP_MEMORY_SCOPE_AGENT>(&c.st[k & 1], S);
     __hip_atomic_store(qcounter(c, k + 1), 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // the host stops enqueueing steps once it reads "done"; written once per decomposition,
+    // since a store to host memory delays the completion of the kernel that makes it
+    if (c.host_st && S.mode == MODE_DONE && (S.seq == 1 || load_state(&c.st[(k - 1) & 1]).mode != MODE_DONE))
+      store_state<__HIP_MEMORY_SCOPE_SYSTEM>(c.host_st, S);
   }
   if (S.mode == MODE_DONE) return MODE_DONE;
-  const unsigned nf = min((unsigned)(S.prev >> 32), (unsigned)c.n), af = (unsigned)S.prev;
+  const unsigned nf = min((unsigned)((u64)S.prev >> 32), (unsigned)c.n), af = (unsigned)S.prev;
   const int* qv = c.qv[(k - 1) & 1];
   const unsigned* qa = c.qa[(k - 1) & 1];
   u64 wmin = INF, examined = 0;
-  if (S.mode == MODE_ROUNDS) {
-    const int r = S.round;
-    if (nf && S.dir == DIR_BU) {
-      // L_r from the per-block minima the previous step left
-      u64 m = INF;
-      for (unsigned b = threadIdx.x; b < gridDim.x; b += RT) {
-        const u64 x = load_u64_relaxed(&c.lr_part[(size_t)((k - 1) & 1) * gridDim.x + b]);
-        m = x < m ? x : m;
-      }
-      m = block_min_u64(m, sh);
-      if (threadIdx.x == 0) sh.lr = m == INF ? INF : m + ((u64)1 << (FIX + c.B));
-      __syncthreads();
+  const bool need_lr = nf && ((S.mode == MODE_ROUNDS && S.dir == DIR_BU) || (S.mode == MODE_TAIL && S.round == 0));
+  if (need_lr) {
+    // L_r: the smallest offer of F_{r-1}, from the per-block minima the previous step left
+    u64 m = INF;
+    for (unsigned b = threadIdx.x; b < gridDim.x; b += RT) {
+      const u64 x = load_u64_relaxed(&c.lr_part[(size_t)((k - 1) & 1) * gridDim.x + b]);
+      m = x < m ? x : m;
     }
+    m = block_min_u64(m, sh);
+    if (threadIdx.x == 0) sh.lr = m == INF ? INF : m + ((u64)1 << (FIX + c.B));
+    __syncthreads();
+  }
+  if (S.mode == MODE_ROUNDS) {
+    const int r = (int)S.round;
     phase_wake(c, r, k, ab, wmin);
     if (nf) {
       if (S.dir == DIR_BU) {
@@ -464,8 +491,9 @@ __device__ int round_step(const RoundCtx& c, int k, AppendBuf& ab, StepShared& s
     }
   } else {
     const unsigned sweep = (unsigned)S.round;
-    if (sweep == 0) phase_tail_seed(c, S.tail_round, k, ab);
-    if (nf) {
+    if (sweep == 0) {
+      phase_tail_seed(c, (int)S.tail_round, k, nf ? sh.lr : INF, ab, examined);
+    } else if (nf) {
       phase_top_down<true>(c, k, qv, qa, nf, af, ab, sh, wmin, sweep);
       if (blockIdx.x == 0 && threadIdx.x == 0) examined += af;
     }
@@ -474,13 +502,18 @@ __device__ int round_step(const RoundCtx& c, int k, AppendBuf& ab, StepShared& s
   const u64 bm = block_min_u64(wmin, sh);
   if (threadIdx.x == 0) c.lr_part[(size_t)(k & 1) * gridDim.x + blockIdx.x] = bm;
   add_examined(c.ctrl, examined);
-  return S.mode;
+  return (int)S.mode;
 }
 
-__global__ __launch_bounds__(RT) void k_round_step(RoundCtx c, int k) {
+// (RT, 8): eight waves per SIMD, i.e. two 1024-thread blocks per CU, which caps VGPRs at 64
+__global__ __launch_bounds__(RT, 8) void k_round_step_lb(const LaunchBlock* __restrict__ lb, int j) {
   __shared__ AppendBuf ab;
   __shared__ StepShared sh;
-  round_step(c, k, ab, sh);
+  round_step(lb->c, (int)(lb->kbase + j), ab, sh);
+}
+
+__global__ void k_advance(LaunchBlock* lb, int C) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) lb->kbase += C;
 }
 
 // All steps in one kernel with grid barriers between them (the grid must be co-resident).

@@ -259,3 +259,17 @@ def test_batch_entry_matches_single(ldd):
         want_c, _, want_cut = oracle.decompose(rp, ci, s)
         assert np.array_equal(centre[vo[g]:vo[g + 1]], want_c), g
         assert cuts[g] == want_cut
+
+
+def test_many_rounds_fallback_sort(ldd):
+    # more than 8192 rounds: the wake-round sort takes its global-atomic path
+    rng = np.random.default_rng(12)
+    rp, ci = inputs.rgg(20_000, 6.0, 5)
+    n = rp.size - 1
+    s = rng.integers(0, 3 * S, n).astype(np.int64)
+    s[rng.integers(0, n, 50)] = rng.integers(8000 * S, 12000 * S, 50)
+    want_c, _, want_cut = oracle.decompose(rp, ci, s)
+    for mode in (dict(), dict(tail_vertices=-1), dict(direction=2)):
+        got, cut, st = run(ldd, rp, ci, s, **mode)
+        assert st["rounds_bound"] > 8192
+        assert np.array_equal(got, want_c) and cut == want_cut, mode
