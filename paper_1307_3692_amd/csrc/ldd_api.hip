@@ -80,6 +80,7 @@ ldd_status grow(Buf& b, size_t bytes) {
 
 struct HostMirror {  // pinned copies of the device control block and round states
   Ctrl ctrl;
+  u64 ex_part[RT];
   RoundState st[2];
   RoundState live;  // written by the step kernels as they run
   LaunchBlock lb;   // staging for the device copy
@@ -95,8 +96,8 @@ struct StepGraph {
 struct Workspace {
   std::mutex mu;
   Buf P, qv0, qv1, qa0, qa1, wake_ord, stamp, hub_bits;  // per vertex
-  Buf hist, cursor, wake_off, next_ne, mat;              // per round (mat: per round and prep block)
-  Buf ctrl, st, qcnt, lr_part, lb;
+  Buf hist, cursor, wake_off, next_ne, mat, qmax;        // per round / q-bucket (mat: per bucket and prep block)
+  Buf ctrl, st, qcnt, lr_part, lb, ex_part;
   HostMirror* host = nullptr;
   hipEvent_t ev[6] = {};
   hipEvent_t chunk_ev[2] = {};
@@ -135,7 +136,7 @@ ldd_status ws_setup(Workspace& w) {
   ldd_status s;
   if ((s = grow(w.ctrl, sizeof(Ctrl))) || (s = grow(w.st, 2 * sizeof(RoundState))) ||
       (s = grow(w.qcnt, 3 * 16 * sizeof(u64))) || (s = grow(w.lr_part, 2 * (size_t)RT * sizeof(u64))) ||
-      (s = grow(w.lb, sizeof(LaunchBlock))))
+      (s = grow(w.lb, sizeof(LaunchBlock))) || (s = grow(w.ex_part, (size_t)RT * sizeof(u64))))
     return s;
   return LDD_OK;
 }
@@ -194,8 +195,8 @@ extern "C" void ldd_release_workspace(void) {
   for (auto& g : w->graphs) (void)hipGraphExecDestroy(g.exec);  // they hold workspace pointers
   w->graphs.clear();
   for (Buf* b : {&w->P, &w->qv0, &w->qv1, &w->qa0, &w->qa1, &w->wake_ord, &w->stamp, &w->hub_bits, &w->hist,
-                 &w->cursor, &w->wake_off, &w->next_ne, &w->mat, &w->ctrl, &w->st, &w->qcnt, &w->lr_part,
-                 &w->lb}) {
+                 &w->cursor, &w->wake_off, &w->next_ne, &w->mat, &w->qmax, &w->ctrl, &w->st, &w->qcnt, &w->lr_part,
+                 &w->lb, &w->ex_part}) {
     if (b->p) (void)hipFree(b->p);
     b->p = nullptr;
     b->bytes = 0;
@@ -268,9 +269,13 @@ extern "C" ldd_status ldd_decompose(const ldd_csr* g, const int64_t* shift_fix, 
   u64* P = (u64*)w.P.p;
 
   HIP_TRY(hipEventRecord(w.ev[0], st));
-  HIP_TRY(hipMemsetAsync(ctrl, 0, sizeof(Ctrl), st));
   const int g_n = grid_for(n, 256 * 4, 2048);
-  hipLaunchKernelGGL(k_init, dim3(g_n), dim3(256), 0, st, n, nnz, g->row_ptr, (const long long*)shift_fix, P, ctrl);
+  // preparation pass A: labels, Delta, checks and the q-bucket histogram (per block)
+  const int gp = (int)std::min<long long>(1024, std::max<long long>(1, n / 16384));
+  if ((s = grow(w.mat, (size_t)QCAP * gp * 4)) || (s = grow(w.qmax, (size_t)gp * 4))) return s;
+  HIP_TRY(hipMemsetAsync(ctrl, 0, sizeof(Ctrl), st));
+  hipLaunchKernelGGL(k_init, dim3(gp), dim3(1024), 0, st, n, nnz, g->row_ptr, (const long long*)shift_fix, P, ctrl,
+                     (unsigned*)w.mat.p, (int*)w.qmax.p);
   if (o.validate && nnz > 0)
     hipLaunchKernelGGL(k_check_cols, dim3(grid_for(nnz, 256, 4096)), dim3(256), 0, st, n, nnz, g->col_idx, ctrl);
   HIP_TRY(hipGetLastError());
@@ -298,20 +303,20 @@ extern "C" ldd_status ldd_decompose(const ldd_csr* g, const int64_t* shift_fix, 
       (s = grow(w.next_ne, nr * 4)))
     return s;
 
-  if (R <= 8192) {
-    // block-local counting sort: no global atomics on the (few, hot) wake buckets
-    const int gp = (int)std::min<long long>(1024, std::max<long long>(1, n / 16384));
-    if ((s = grow(w.mat, (size_t)R * gp * 4))) return s;
-    hipLaunchKernelGGL(k_wake_hist_blocks, dim3(gp), dim3(1024), (size_t)R * 4, st, n, B, g->row_ptr,
-                       (const long long*)shift_fix, (const Ctrl*)ctrl, P, (unsigned*)w.mat.p, (int)R);
-    hipLaunchKernelGGL(k_wake_bucket_scan, dim3((unsigned)((R * WAVE + 255) / 256)), dim3(256), 0, st, (int)R, gp,
-                       (unsigned*)w.mat.p, (unsigned*)w.hist.p);
-    hipLaunchKernelGGL(k_wake_scan, dim3(1), dim3(1024), 0, st, (int)R, (const unsigned*)w.hist.p,
-                       (int*)w.wake_off.p, (int*)w.cursor.p, (int*)w.next_ne.p);
-    hipLaunchKernelGGL(k_wake_place, dim3(gp), dim3(1024), (size_t)R * 4, st, n, g->row_ptr,
-                       (const long long*)shift_fix, (const Ctrl*)ctrl, (const unsigned*)w.mat.p,
-                       (const int*)w.wake_off.p, (int*)w.wake_ord.p, (int)R);
+  const long long D = (long long)(delta >> FIX);
+  int wake_q = 0;
+  if (!w.host->ctrl.wide && D < QCAP) {
+    // pass B: vertices sorted by the integer part of their shift, no global atomics
+    wake_q = 1;
+    hipLaunchKernelGGL(k_qbucket_scan, dim3((unsigned)(((D + 1) * WAVE + 255) / 256)), dim3(256), 0, st, (int)(D + 1),
+                       gp, (unsigned*)w.mat.p, (const int*)w.qmax.p, (unsigned*)w.hist.p);
+    hipLaunchKernelGGL(k_qscan, dim3(1), dim3(1024), 0, st, (int)D, (const unsigned*)w.hist.p, (int*)w.wake_off.p,
+                       (int*)w.next_ne.p);
+    hipLaunchKernelGGL(k_place, dim3(gp), dim3(1024), 0, st, n, B, g->row_ptr, (const long long*)shift_fix,
+                       (const Ctrl*)ctrl, (const unsigned*)w.mat.p, (const int*)w.qmax.p, (const int*)w.wake_off.p,
+                       (int*)w.wake_ord.p, P);
   } else {
+    // shifts spanning more than QCAP units: exact wake rounds via global atomics
     HIP_TRY(hipMemsetAsync(w.hist.p, 0, nr * 4, st));
     hipLaunchKernelGGL(k_wake_count, dim3(g_n), dim3(256), 0, st, n, B, g->row_ptr, (const long long*)shift_fix,
                        (const Ctrl*)ctrl, P, (unsigned*)w.hist.p, (int)R, 0);
@@ -332,8 +337,12 @@ extern "C" ldd_status ldd_decompose(const ldd_csr* g, const int64_t* shift_fix, 
   s0.dir = DIR_TD;
   s0.unsettled_arcs = (u64)nnz;
   s0.tail_round = -1;
+  // both slots: a step leaves as soon as either slot says "done", and slot 1 still holds the
+  // previous call's last state
   w.host->st[0] = s0;
-  HIP_TRY(hipMemcpyAsync(w.st.p, &w.host->st[0], sizeof(RoundState), hipMemcpyHostToDevice, st));
+  w.host->st[1] = s0;
+  w.host->st[1].seq = -1;
+  HIP_TRY(hipMemcpyAsync(w.st.p, &w.host->st[0], 2 * sizeof(RoundState), hipMemcpyHostToDevice, st));
 
   RoundCtx c{};
   c.n = n;
@@ -353,6 +362,7 @@ extern "C" ldd_status ldd_decompose(const ldd_csr* g, const int64_t* shift_fix, 
   c.wake_ord = (const int*)w.wake_ord.p;
   c.wake_off = (const int*)w.wake_off.p;
   c.next_ne = (const int*)w.next_ne.p;
+  c.wake_q = wake_q;
   c.qcnt = (u64*)w.qcnt.p;
   c.lr_part = (u64*)w.lr_part.p;
   c.stamp = (unsigned*)w.stamp.p;
@@ -364,6 +374,8 @@ extern "C" ldd_status ldd_decompose(const ldd_csr* g, const int64_t* shift_fix, 
   c.tail_den = tail_den;
   c.tail_min_left = 16;
   c.host_st = nullptr;
+  c.ex_part = (u64*)w.ex_part.p;
+  HIP_TRY(hipMemsetAsync(w.ex_part.p, 0, (size_t)RT * sizeof(u64), st));
 
   const int engine = o.engine == LDD_ENGINE_AUTO ? LDD_ENGINE_LAUNCH : o.engine;
   int blocks = o.blocks > 0 ? o.blocks : 2 * w.num_cu;
@@ -423,8 +435,7 @@ extern "C" ldd_status ldd_decompose(const ldd_csr* g, const int64_t* shift_fix, 
   }
   (void)steps;
   HIP_TRY(hipEventRecord(w.ev[2], st));
-  HIP_TRY(hipMemsetAsync(w.hub_bits.p, 0, (nv + 63) / 64 * 8, st));
-  const int g_f = grid_for(n, 1024 * 16, 1024);
+  const int g_f = grid_for((n + 63) / 64, 256, 1024);  // whole bitmap words per block
   hipLaunchKernelGGL(k_finalize, dim3(g_f), dim3(1024), 0, st, n, B, g->row_ptr, (const u64*)P, centre,
                      (u64*)w.hub_bits.p, (int*)w.qv0.p, (unsigned*)w.qa0.p, ctrl);
   HIP_TRY(hipEventRecord(w.ev[3], st));
@@ -435,6 +446,7 @@ extern "C" ldd_status ldd_decompose(const ldd_csr* g, const int64_t* shift_fix, 
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipEventRecord(w.ev[4], st));
   HIP_TRY(hipMemcpyAsync(&w.host->ctrl, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+  if (stats) HIP_TRY(hipMemcpyAsync(w.host->ex_part, w.ex_part.p, (size_t)blocks * sizeof(u64), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   const Ctrl& h = w.host->ctrl;
   {
@@ -458,7 +470,9 @@ extern "C" ldd_status ldd_decompose(const ldd_csr* g, const int64_t* shift_fix, 
     stats->delta = (int64_t)delta;
     stats->pieces = (int64_t)h.pieces;
     stats->max_frontier = n_active ? (int64_t)fs.max_frontier : 0;
-    stats->arcs_examined = (int64_t)h.arcs_examined;
+    u64 ex = 0;
+    for (int b = 0; b < blocks; ++b) ex += w.host->ex_part[b];
+    stats->arcs_examined = (int64_t)ex;
     stats->n_active = (int64_t)n_active;
     float ms = 0;
     (void)hipEventElapsedTime(&ms, w.ev[0], w.ev[1]);

@@ -25,6 +25,7 @@ typedef long long i64;
 constexpr int FIX = 20;
 constexpr u64 INF = ~0ull;
 constexpr int WAVE = 64;
+constexpr int QCAP = 8192;  // integer parts of shifts bucketed in LDS by the preparation
 
 // error bits raised by kernels (ctrl->err)
 enum : unsigned {
@@ -36,19 +37,19 @@ enum : unsigned {
   ERR_QUEUE = 32u         // queue overflow (more appends than vertices)
 };
 
-// Control block in device memory, one per decomposition in flight.
+// Control block in device memory, one per decomposition in flight.  Counters that many
+// blocks update get a 128-byte line each: atomics to one line serialise (~12 ns apiece).
 struct Ctrl {
-  u64 delta;            // max shift_fix (atomicMax target)
-  u64 n_active;         // vertices with at least one arc
-  unsigned err;         // ERR_* bits
-  unsigned pad0;
-  u64 bar;              // grid barrier arrival counter
-  u64 cut_arcs;         // arcs whose endpoints have different centres
-  u64 pieces;           // vertices that are their own centre
-  u64 unreached;        // labels still INF after the rounds (must be 0)
-  u64 hub;              // (degree << 32 | id) of the highest-degree vertex
-  u64 list_cnt;         // (count << 32 | arcs) of the rows outside the hub's piece
-  u64 arcs_examined;    // arcs read by the traversal (top-down and bottom-up)
+  alignas(128) u64 delta;   // max shift_fix (atomicMax target)
+  alignas(128) u64 n_active;  // vertices with at least one arc
+  alignas(128) u64 hub;     // (degree << 32 | id) of the highest-degree vertex
+  alignas(128) unsigned err;  // ERR_* bits
+  unsigned wide;              // some shift has an integer part >= QCAP
+  alignas(128) u64 bar;     // grid barrier arrival counter (persistent engine)
+  alignas(128) u64 cut_arcs;  // 2 per arc to H plus 1 per two-sided cut arc outside H
+  alignas(128) u64 pieces;  // vertices that are their own centre
+  alignas(128) u64 unreached;  // labels still INF after the rounds (must be 0)
+  alignas(128) u64 list_cnt;  // (count << 32 | arcs) of the rows outside the hub's piece
 };
 
 __device__ __forceinline__ unsigned lane_id() { return __lane_id(); }

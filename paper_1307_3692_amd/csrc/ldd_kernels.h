@@ -50,8 +50,9 @@ struct RoundCtx {
   int* qv[2];       // queues (double-buffered by step parity)
   unsigned* qa[2];  // arc prefix of each queue entry
   const int* wake_ord;
-  const int* wake_off;
+  const int* wake_off;  // wake_q: q-bucket offsets [D + 2]; else round offsets [R + 1]
   const int* next_ne;
+  int wake_q;           // 1: wake_ord is sorted by integer part of the shift (see k_init)
   u64* qcnt;        // 3 counters, 16 u64 apart: step k appends to counter k % 3
   u64* lr_part;     // [2][G]: per-block minimum label written by a step (parity of k)
   unsigned* stamp;  // per vertex: last tail sweep that queued it
@@ -63,6 +64,7 @@ struct RoundCtx {
   int tail_den;     // enter the tail once unsettled * tail_den <= n_active (0: never)
   int tail_min_left;  // ... and more than this many rounds remain
   RoundState* host_st;  // pinned host mirror of the latest state (may be null)
+  u64* ex_part;     // [G]: arcs examined by each block over all steps (statistics)
 };
 
 // Arguments of graph-launched steps: step k = kbase + j of a chunk; k_advance moves kbase.
@@ -71,18 +73,18 @@ struct LaunchBlock {
   long long kbase;
 };
 
-__global__ void k_init(int n, long long nnz, const int* row_ptr, const long long* shift, u64* P, Ctrl* ctrl);
+__global__ void k_init(int n, long long nnz, const int* row_ptr, const long long* shift, u64* P, Ctrl* ctrl,
+                       unsigned* mat, int* qmax);
+__global__ void k_qbucket_scan(int Qn, int G, unsigned* mat, const int* qmax, unsigned* tot);
+__global__ void k_qscan(int D, const unsigned* tot, int* qoff, int* next_ne);
+__global__ void k_place(int n, int B, const int* row_ptr, const long long* shift, const Ctrl* ctrl, const unsigned* mat,
+                        const int* qmax, const int* qoff, int* wake_ord, u64* P);
 __global__ void k_check_cols(int n, long long nnz, const int* col, Ctrl* ctrl);
 __global__ void k_wake_count(int n, int B, const int* row_ptr, const long long* shift, const Ctrl* ctrl, u64* P,
                              unsigned* hist, int R, int use_lds);
 __global__ void k_wake_scan(int R, const unsigned* hist, int* wake_off, int* cursor, int* next_ne);
 __global__ void k_wake_scatter(int n, const int* row_ptr, const long long* shift, const Ctrl* ctrl, int* cursor,
                                int* wake_ord);
-__global__ void k_wake_hist_blocks(int n, int B, const int* row_ptr, const long long* shift, const Ctrl* ctrl, u64* P,
-                                   unsigned* mat, int R);
-__global__ void k_wake_bucket_scan(int R, int G, unsigned* mat, unsigned* tot);
-__global__ void k_wake_place(int n, const int* row_ptr, const long long* shift, const Ctrl* ctrl, const unsigned* mat,
-                             const int* wake_off, int* wake_ord, int R);
 __global__ void k_fill_u64(u64* p, long long count, u64 value);
 __global__ void k_round_step_lb(const LaunchBlock* lb, int j);
 __global__ void k_advance(LaunchBlock* lb, int C);

@@ -22,51 +22,190 @@ namespace ldd {
 // ------------------------------------------------------------------------------------------
 // Block-wide reductions for 256-thread blocks (one global atomic per block, not per wave:
 // same-address atomics serialise at ~12 ns each).
-__device__ __forceinline__ u64 block_max_256(u64 v, u64* red) {
+// (any block size up to 1024 threads; red holds one entry per wave)
+__device__ __forceinline__ u64 block_max(u64 v, u64* red) {
   v = wave_max_u64(v);
   __syncthreads();
   if (lane_id() == 0) red[threadIdx.x / WAVE] = v;
   __syncthreads();
-  const u64 a = red[0] > red[1] ? red[0] : red[1], b = red[2] > red[3] ? red[2] : red[3];
-  return a > b ? a : b;
+  u64 m = 0;
+  for (unsigned w = 0; w < blockDim.x / WAVE; ++w) m = red[w] > m ? red[w] : m;
+  return m;
 }
-__device__ __forceinline__ u64 block_sum_256(u64 v, u64* red) {
+__device__ __forceinline__ u64 block_sum(u64 v, u64* red) {
   v = wave_sum_u64(v);
   __syncthreads();
   if (lane_id() == 0) red[threadIdx.x / WAVE] = v;
   __syncthreads();
-  return red[0] + red[1] + red[2] + red[3];
+  u64 t = 0;
+  for (unsigned w = 0; w < blockDim.x / WAVE; ++w) t += red[w];
+  return t;
 }
 
-__global__ __launch_bounds__(256) void k_init(int n, long long nnz, const int* __restrict__ row_ptr,
+// Pass A of the preparation.  Labels := INF, Delta := max shift (Algorithm 1 step 2),
+// vertices with arcs, the highest-degree vertex, CSR and shift bounds checks -- and, since
+// Delta is not known yet, a per-block LDS histogram of the integer part q = shift >> 20 of
+// the vertices with arcs.  The wake round of u is D - q or D - q - 1 (D = Delta >> 20),
+// depending on whether the fractional part of u's shift exceeds that of Delta, so q-buckets
+// ordered by q give every round's wakers in two adjacent segments.
+// Block b owns vertices [b n / G, (b+1) n / G); each wave takes 256 consecutive ones per
+// pass (four per lane at stride 64, coalesced).  mat[q * G + b] = count of block b in bucket
+// q for q <= qmax[b]; a q >= QCAP sets ctrl->wide and the sorted layout is not used.
+__global__ __launch_bounds__(1024) void k_init(int n, long long nnz, const int* __restrict__ row_ptr,
                                               const long long* __restrict__ shift, u64* __restrict__ P,
-                                              Ctrl* ctrl) {
-  u64 mx = 0, active = 0, hub = 0;
-  unsigned bad = 0;
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
-    const long long s = shift[v];
-    if (s < 0 || s > (1ll << 52)) bad |= ERR_BAD_SHIFT;
-    else mx = (u64)s > mx ? (u64)s : mx;
-    const int a = row_ptr[v], b = row_ptr[v + 1];
-    if (a < 0 || b < a || (long long)b > nnz) bad |= ERR_BAD_ROWPTR;
-    if (v == 0 && a != 0) bad |= ERR_BAD_ROWPTR;
-    if (v == n - 1 && (long long)b != nnz) bad |= ERR_BAD_ROWPTR;
-    active += (b > a);
-    const u64 key = ((u64)(unsigned)(b - a) << 32) | (u64)v;  // degree, then id
-    hub = key > hub ? key : hub;
-    P[v] = INF;
+                                              Ctrl* ctrl, unsigned* __restrict__ mat, int* __restrict__ qmax) {
+  __shared__ unsigned h[QCAP];
+  __shared__ u64 red[4][16];
+  for (int i = threadIdx.x; i < QCAP; i += blockDim.x) h[i] = 0;
+  __syncthreads();
+  u64 mx = 0, active = 0, hub = 0, qm = 0;
+  unsigned bad = 0, wide = 0;
+  const unsigned lane = lane_id(), wid = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+  const long long lo = (long long)n * blockIdx.x / gridDim.x, hi = (long long)n * (blockIdx.x + 1) / gridDim.x;
+  for (long long base = lo + 256ll * wid; base < hi; base += 256ll * nw) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const long long v = base + 64 * j + lane;
+      if (v < hi) {
+        const long long s = shift[v];
+        const bool s_ok = s >= 0 && s <= (1ll << 52);
+        if (!s_ok) bad |= ERR_BAD_SHIFT;
+        else mx = (u64)s > mx ? (u64)s : mx;
+        const int a = row_ptr[v], b = row_ptr[v + 1];
+        if (a < 0 || b < a || (long long)b > nnz) bad |= ERR_BAD_ROWPTR;
+        if (v == 0 && a != 0) bad |= ERR_BAD_ROWPTR;
+        if (v == n - 1 && (long long)b != nnz) bad |= ERR_BAD_ROWPTR;
+        active += (b > a);
+        const u64 key = ((u64)(unsigned)(b - a) << 32) | (u64)v;  // degree, then id
+        hub = key > hub ? key : hub;
+        P[v] = INF;
+        if (b > a && s_ok) {
+          const u64 q = (u64)s >> FIX;
+          if (q < (u64)QCAP) {
+            atomicAdd(&h[q], 1u);
+            qm = (q + 1) > qm ? (q + 1) : qm;  // q + 1 so that 0 means "no vertex"
+          } else {
+            wide = 1;
+          }
+        }
+      }
+    }
   }
-  __shared__ u64 red[3][4];
-  mx = block_max_256(mx, red[0]);
-  active = block_sum_256(active, red[1]);
-  hub = block_max_256(hub, red[2]);
+  mx = block_max(mx, red[0]);
+  active = block_sum(active, red[1]);
+  hub = block_max(hub, red[2]);
+  qm = block_max(qm, red[3]);
   if (threadIdx.x == 0) {
     if (mx) atomic_max_u64(&ctrl->delta, mx);
     if (active) atomic_add_u64(&ctrl->n_active, active);
     atomic_max_u64(&ctrl->hub, hub);
+    qmax[blockIdx.x] = (int)qm - 1;
   }
   if (bad) atomic_or_u32(&ctrl->err, bad);
+  if (wide) atomic_or_u32(&ctrl->wide, 1u);
+  const unsigned G = gridDim.x;
+  for (int q = threadIdx.x; q < (int)qm; q += blockDim.x) mat[(size_t)q * G + blockIdx.x] = h[q];
+}
+
+// One wave per q-bucket: exclusive scan of the per-block counts (in place) and the total.
+__global__ __launch_bounds__(256) void k_qbucket_scan(int Qn, int G, unsigned* __restrict__ mat,
+                                                      const int* __restrict__ qmax, unsigned* __restrict__ tot) {
+  const int q = (int)((blockIdx.x * blockDim.x + threadIdx.x) / WAVE);
+  if (q >= Qn) return;  // whole waves leave together
+  const unsigned lane = lane_id();
+  unsigned* row = mat + (size_t)q * G;
+  unsigned run = 0;
+  for (int b0 = 0; b0 < G; b0 += WAVE) {
+    const int b = b0 + (int)lane;
+    const bool has = b < G && q <= qmax[b];
+    const unsigned x = has ? row[b] : 0u;
+    const unsigned incl = wave_incl_scan(x);
+    if (has) row[b] = run + incl - x;
+    run += __shfl(incl, WAVE - 1, WAVE);
+  }
+  if (lane == 0) tot[q] = run;
+}
+
+// One block: bucket offsets qoff[0..D+1] and, per round r (R = D + 1 rounds), the next round
+// at or after r whose two q-buckets (D - r and D - r - 1) are not both empty.
+__global__ __launch_bounds__(1024) void k_qscan(int D, const unsigned* __restrict__ tot, int* __restrict__ qoff,
+                                                int* __restrict__ next_ne) {
+  __shared__ unsigned part[1024];
+  __shared__ int nxt[1024];
+  const int Qn = D + 1, R = D + 1;
+  const int t = threadIdx.x;
+  const int per = (Qn + 1023) / 1024;
+  const int lo = t * per, hi = min(Qn, lo + per);
+  unsigned s = 0;
+  int first = R;  // smallest round in this thread's range (rounds r = lo..hi-1) that may wake someone
+  for (int i = lo; i < hi; ++i) s += tot[i];
+  for (int r = lo; r < hi; ++r) {
+    const bool ne = tot[D - r] > 0 || (r < D && tot[D - r - 1] > 0);
+    if (ne && first == R) first = r;
+  }
+  part[t] = s;
+  nxt[t] = first;
+  __syncthreads();
+  if (t == 0) {
+    unsigned acc = 0;
+    for (int i = 0; i < 1024; ++i) {
+      const unsigned x = part[i];
+      part[i] = acc;
+      acc += x;
+    }
+    int nx = R;
+    for (int i = 1023; i >= 0; --i) {
+      if (nxt[i] != R) nx = nxt[i];
+      nxt[i] = nx;
+    }
+  }
+  __syncthreads();
+  unsigned acc = part[t];
+  for (int i = lo; i < hi; ++i) {
+    qoff[i] = (int)acc;
+    acc += tot[i];
+  }
+  int nx_after = (t + 1 < 1024) ? nxt[t + 1] : R;
+  for (int r = hi - 1; r >= lo; --r) {
+    const bool ne = tot[D - r] > 0 || (r < D && tot[D - r - 1] > 0);
+    if (ne) nx_after = r;
+    next_ne[r] = nx_after;
+  }
+  if (t == 1023) {
+    qoff[Qn] = (int)acc;
+    next_ne[R] = R;
+  }
+}
+
+// Pass B: each vertex with arcs goes to qoff[q] + mat[q * G + b] + its rank in block b's
+// bucket; isolated vertices settle (their only offer is their own arc).  Same chunks as k_init.
+__global__ __launch_bounds__(1024) void k_place(int n, int B, const int* __restrict__ row_ptr,
+                                               const long long* __restrict__ shift, const Ctrl* __restrict__ ctrl,
+                                               const unsigned* __restrict__ mat, const int* __restrict__ qmax,
+                                               const int* __restrict__ qoff, int* __restrict__ wake_ord,
+                                               u64* __restrict__ P) {
+  __shared__ unsigned cur[QCAP];
+  const unsigned G = gridDim.x;
+  const int qm = qmax[blockIdx.x];
+  for (int q = threadIdx.x; q <= qm; q += blockDim.x) cur[q] = (unsigned)qoff[q] + mat[(size_t)q * G + blockIdx.x];
+  __syncthreads();
+  const u64 delta = ctrl->delta;
+  const unsigned lane = lane_id(), wid = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+  const long long lo = (long long)n * blockIdx.x / gridDim.x, hi = (long long)n * (blockIdx.x + 1) / gridDim.x;
+  for (long long base = lo + 256ll * wid; base < hi; base += 256ll * nw) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const long long v = base + 64 * j + lane;
+      if (v < hi) {
+        const u64 s = (u64)shift[v];
+        if (row_ptr[v + 1] == row_ptr[v]) {
+          P[v] = ((delta - s) << B) | (u64)v;
+        } else {
+          wake_ord[atomicAdd(&cur[s >> FIX], 1u)] = (int)v;
+        }
+      }
+    }
+  }
 }
 
 // Optional O(nnz) check that every column id is in range (the round kernels also guard
@@ -176,73 +315,6 @@ __global__ __launch_bounds__(256) void k_wake_scatter(int n, const int* __restri
   }
 }
 
-// Counting sort of vertices by wake round without global atomics (used when the R rounds fit
-// LDS): block b owns the contiguous vertex chunk [b n / G, (b+1) n / G).
-//   k_wake_hist_blocks  per-block LDS histogram -> mat[r * G + b]; isolated vertices settle
-//   k_wake_bucket_scan  per bucket, exclusive scan over blocks (in place) and bucket totals
-//   k_wake_scan         bucket offsets and next-non-empty links from the totals
-//   k_wake_place        each vertex goes to wake_off[r] + mat[r * G + b] + its rank in the block
-__device__ __forceinline__ void chunk_of(long long n, long long& lo, long long& hi) {
-  lo = n * blockIdx.x / gridDim.x;
-  hi = n * (blockIdx.x + 1) / gridDim.x;
-}
-
-__global__ __launch_bounds__(1024) void k_wake_hist_blocks(int n, int B, const int* __restrict__ row_ptr,
-                                                          const long long* __restrict__ shift,
-                                                          const Ctrl* __restrict__ ctrl, u64* __restrict__ P,
-                                                          unsigned* __restrict__ mat, int R) {
-  extern __shared__ unsigned h[];
-  for (int i = threadIdx.x; i < R; i += blockDim.x) h[i] = 0;
-  __syncthreads();
-  const u64 delta = ctrl->delta;
-  long long lo, hi;
-  chunk_of(n, lo, hi);
-  for (long long v = lo + threadIdx.x; v < hi; v += blockDim.x) {
-    const u64 off = delta - (u64)shift[v];
-    if (row_ptr[v + 1] == row_ptr[v]) P[v] = (off << B) | (u64)v;
-    else atomicAdd(&h[(int)(off >> FIX)], 1u);
-  }
-  __syncthreads();
-  const unsigned G = gridDim.x;
-  for (int r = threadIdx.x; r < R; r += blockDim.x) mat[(size_t)r * G + blockIdx.x] = h[r];
-}
-
-// one wave per bucket: exclusive scan of its G block counts, 64 at a time
-__global__ __launch_bounds__(256) void k_wake_bucket_scan(int R, int G, unsigned* __restrict__ mat,
-                                                          unsigned* __restrict__ tot) {
-  const int r = (int)((blockIdx.x * blockDim.x + threadIdx.x) / WAVE);
-  if (r >= R) return;  // whole waves leave together
-  const unsigned lane = lane_id();
-  unsigned* row = mat + (size_t)r * G;
-  unsigned run = 0;
-  for (int b0 = 0; b0 < G; b0 += WAVE) {
-    const int b = b0 + (int)lane;
-    const unsigned x = b < G ? row[b] : 0u;
-    const unsigned incl = wave_incl_scan(x);
-    if (b < G) row[b] = run + incl - x;
-    run += __shfl(incl, WAVE - 1, WAVE);
-  }
-  if (lane == 0) tot[r] = run;
-}
-
-__global__ __launch_bounds__(1024) void k_wake_place(int n, const int* __restrict__ row_ptr,
-                                                    const long long* __restrict__ shift, const Ctrl* __restrict__ ctrl,
-                                                    const unsigned* __restrict__ mat, const int* __restrict__ wake_off,
-                                                    int* __restrict__ wake_ord, int R) {
-  extern __shared__ unsigned cur[];
-  const unsigned G = gridDim.x;
-  for (int r = threadIdx.x; r < R; r += blockDim.x) cur[r] = (unsigned)wake_off[r] + mat[(size_t)r * G + blockIdx.x];
-  __syncthreads();
-  const u64 delta = ctrl->delta;
-  long long lo, hi;
-  chunk_of(n, lo, hi);
-  for (long long v = lo + threadIdx.x; v < hi; v += blockDim.x) {
-    if (row_ptr[v + 1] == row_ptr[v]) continue;
-    const int w = (int)((delta - (u64)shift[v]) >> FIX);
-    wake_ord[atomicAdd(&cur[w], 1u)] = (int)v;
-  }
-}
-
 __global__ void k_fill_u64(u64* p, long long count, u64 value) {
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = value;
@@ -282,38 +354,49 @@ __global__ __launch_bounds__(FT) void k_finalize(int n, int B, const int* __rest
   }
   u64 pieces = 0, unreached = 0;
   const unsigned wid = threadIdx.x / WAVE, lane = lane_id();
-  // contiguous chunk per block, walked 1024 vertices at a time (a wave covers 64 consecutive)
-  const long long lo = (long long)n * blockIdx.x / gridDim.x, hi = (long long)n * (blockIdx.x + 1) / gridDim.x;
-  const long long lo64 = lo & ~63ll;
-  for (long long base = lo64; base < hi; base += FT) {
-    const long long v = base + threadIdx.x;
-    const bool mine = v >= lo && v < hi;
-    bool in_hub = false, want = false;
-    unsigned deg = 0;
-    if (mine) {
-      const u64 p = P[v];
-      const int cv = (int)(p & mask);
-      centre[v] = cv;
-      pieces += (cv == (int)v);
-      unreached += (p == INF);
-      in_hub = cv == hub_c;
-      deg = (unsigned)(row_ptr[v + 1] - row_ptr[v]);
-      want = !in_hub && deg > 0;
+  // block chunk [lo, hi) of whole 64-vertex words; each wave takes 256 vertices per pass,
+  // four per lane at stride 64, so that each ballot is one bitmap word
+  const long long words = ((long long)n + 63) / 64;
+  const long long lo = words * blockIdx.x / gridDim.x * 64, hi = min((long long)n, words * (blockIdx.x + 1) / gridDim.x * 64);
+  for (long long base = lo; base < hi; base += 4 * FT) {
+    bool want[4];
+    unsigned deg[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const long long v = base + 256 * wid + 64 * j + lane;
+      bool in_hub = false;
+      want[j] = false;
+      deg[j] = 0;
+      if (v < hi) {
+        const u64 p = P[v];
+        const int cv = (int)(p & mask);
+        centre[v] = cv;
+        pieces += (cv == (int)v);
+        unreached += (p == INF);
+        in_hub = cv == hub_c;
+        deg[j] = (unsigned)(row_ptr[v + 1] - row_ptr[v]);
+        want[j] = !in_hub && deg[j] > 0;
+      }
+      const u64 bits = __ballot(in_hub);
+      const long long w0 = base + 256 * wid + 64 * j;
+      if (lane == 0 && w0 < hi) hub_bits[w0 >> 6] = bits;
     }
-    // bitmap word of 64 consecutive vertices; a word straddling two chunks is split by atomics
-    const u64 bits = __ballot(in_hub);
-    if (lane == 0 && base + threadIdx.x < n) {
-      const long long w0 = (base + threadIdx.x) >> 6;
-      const long long first = base + threadIdx.x, last = first + 63;
-      if (first >= lo && last < hi) hub_bits[w0] = bits;
-      else if (bits) __hip_atomic_fetch_or(&hub_bits[w0], bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // list entries of this pass: per-wave counts over the four sub-tiles, then the block
+    unsigned my_cnt[4], my_arcs[4], wc_tot = 0, wa_tot = 0;
+    u64 m[4];
+    unsigned incl[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      m[j] = __ballot(want[j]);
+      incl[j] = wave_incl_scan(want[j] ? deg[j] : 0u);
+      my_cnt[j] = wc_tot;   // entries of sub-tiles before j in this wave
+      my_arcs[j] = wa_tot;
+      wc_tot += (unsigned)__popcll(m[j]);
+      wa_tot += __shfl(incl[j], WAVE - 1, WAVE);
     }
-    // block-aggregated append of the list entries
-    const u64 m = __ballot(want);
-    const unsigned incl = wave_incl_scan(want ? deg : 0u);
-    if (lane == WAVE - 1) {
-      w_cnt[wid] = (unsigned)__popcll(m);
-      w_arcs[wid] = incl;
+    if (lane == 0) {
+      w_cnt[wid] = wc_tot;
+      w_arcs[wid] = wa_tot;
     }
     __syncthreads();
     unsigned wc = 0, wa = 0, tc = 0, ta = 0;
@@ -325,33 +408,38 @@ __global__ __launch_bounds__(FT) void k_finalize(int n, int B, const int* __rest
       tc += w_cnt[w];
       ta += w_arcs[w];
     }
-    if (b_n + tc > (unsigned)FBUF) {  // flush (uniform: every thread reads the same b_n, tc)
-      if (threadIdx.x == 0) b_base = atomic_add_u64(&ctrl->list_cnt, ((u64)b_n << 32) | b_arcs);
-      __syncthreads();
-      for (unsigned i = threadIdx.x; i < b_n; i += FT) {
-        const unsigned idx = (unsigned)(b_base >> 32) + i;
-        if (idx < (unsigned)n) {
-          lv[idx] = b_vert[i];
-          la[idx] = (unsigned)b_base + b_off[i];
+    if (tc) {  // uniform
+      if (b_n + tc > (unsigned)FBUF) {
+        if (threadIdx.x == 0) b_base = atomic_add_u64(&ctrl->list_cnt, ((u64)b_n << 32) | b_arcs);
+        __syncthreads();
+        for (unsigned i = threadIdx.x; i < b_n; i += FT) {
+          const unsigned idx = (unsigned)(b_base >> 32) + i;
+          if (idx < (unsigned)n) {
+            lv[idx] = b_vert[i];
+            la[idx] = (unsigned)b_base + b_off[i];
+          }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+          b_n = 0;
+          b_arcs = 0;
+        }
+        __syncthreads();
+      }
+      const unsigned fill = b_n, fill_arcs = b_arcs;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (want[j]) {
+          const unsigned idx = fill + wc + my_cnt[j] + rank_below(m[j]);
+          b_vert[idx] = (int)(base + 256 * wid + 64 * j + lane);
+          b_off[idx] = fill_arcs + wa + my_arcs[j] + incl[j] - deg[j];
         }
       }
       __syncthreads();
       if (threadIdx.x == 0) {
-        b_n = 0;
-        b_arcs = 0;
+        b_n = fill + tc;
+        b_arcs = fill_arcs + ta;
       }
-      __syncthreads();
-    }
-    const unsigned fill = b_n, fill_arcs = b_arcs;
-    if (want) {
-      const unsigned idx = fill + wc + rank_below(m);
-      b_vert[idx] = (int)v;
-      b_off[idx] = fill_arcs + wa + incl - deg;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      b_n = fill + tc;
-      b_arcs = fill_arcs + ta;
     }
     __syncthreads();
   }
@@ -398,7 +486,7 @@ __global__ __launch_bounds__(256) void k_cut(int n, const int* __restrict__ row_
   __shared__ int w_first[T + 1];
   __shared__ int w_c[T + 1];
   __shared__ unsigned s_start;
-  __shared__ u64 red[4];
+  __shared__ u64 red[16];
   const u64 lc = ctrl->list_cnt;
   const unsigned nl = min((unsigned)(lc >> 32), (unsigned)n), al = (unsigned)lc;
   const unsigned G = gridDim.x;
@@ -466,7 +554,7 @@ __global__ __launch_bounds__(256) void k_cut(int n, const int* __restrict__ row_
     }
   }
   // cut_arcs accumulates 2 per one-sided arc and 1 per two-sided arc: cut = cut_arcs / 2
-  const u64 v = block_sum_256(2 * one_side + both, red);
+  const u64 v = block_sum(2 * one_side + both, red);
   if (threadIdx.x == 0 && v) atomic_add_u64(&ctrl->cut_arcs, v);
 }
 

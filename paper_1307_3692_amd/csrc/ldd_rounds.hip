@@ -140,8 +140,23 @@ __device__ __forceinline__ u64 own_offer(const RoundCtx& c, int v) {
 }
 
 // ---- round r: wake bucket r (the delayed source arcs of length in [r, r+1) units) ----------
+// With the q-layout, round r's wakers are the vertices of bucket q = D - r whose shift's
+// fractional part is <= that of Delta, and those of bucket D - r - 1 whose fractional part
+// is larger; the two buckets are adjacent in wake_ord.
 __device__ __forceinline__ void phase_wake(const RoundCtx& c, int r, int k, AppendBuf& ab, u64& wmin) {
-  const int lo = c.wake_off[r], hi = c.wake_off[r + 1];
+  constexpr u64 FMASK = ((u64)1 << FIX) - 1;
+  int lo, mid, hi;
+  const int D = (int)(c.delta >> FIX);
+  const u64 dfrac = c.delta & FMASK;
+  if (c.wake_q) {
+    const int qa = D - r;  // >= 0 for every round r < R
+    lo = c.wake_off[qa > 0 ? qa - 1 : 0];
+    mid = c.wake_off[qa];
+    hi = c.wake_off[qa + 1];
+  } else {
+    lo = mid = c.wake_off[r];
+    hi = c.wake_off[r + 1];
+  }
   const int cnt = hi - lo;
   for (long long base = (long long)blockIdx.x * RT; base < cnt; base += (long long)gridDim.x * RT) {
     const long long i = base + threadIdx.x;
@@ -150,8 +165,11 @@ __device__ __forceinline__ void phase_wake(const RoundCtx& c, int r, int k, Appe
     unsigned deg = 0;
     if (i < cnt) {
       v = c.wake_ord[lo + i];
-      const u64 self = own_offer(c, v);
-      if (c.P[v] > self) {
+      const u64 sv = (u64)c.shift[v];
+      // in bucket D - r: wakes now iff frac <= dfrac; in bucket D - r - 1: iff frac > dfrac
+      const bool wakes = !c.wake_q || ((lo + i >= mid) ? (sv & FMASK) <= dfrac : (sv & FMASK) > dfrac);
+      const u64 self = ((c.delta - sv) << c.B) | (u64)v;
+      if (wakes && c.P[v] > self) {
         const u64 old = atomic_min_u64(&c.P[v], self);
         if (old > self) {
           wmin = self < wmin ? self : wmin;
@@ -439,27 +457,44 @@ __device__ __forceinline__ RoundState next_state(const RoundCtx& c, int k) {
   return S;
 }
 
-__device__ void add_examined(Ctrl* ctrl, u64 examined) {
+// per-block statistics slot: no atomics (each block owns its slot for the whole call)
+__device__ __forceinline__ void add_examined(const RoundCtx& c, u64 examined, StepShared& sh) {
   examined = wave_sum_u64(examined);
-  if (lane_id() == 0 && examined) atomic_add_u64(&ctrl->arcs_examined, examined);
+  __syncthreads();
+  if (lane_id() == 0) sh.red[threadIdx.x / WAVE] = examined;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    u64 t = 0;
+    for (int w = 0; w < NW; ++w) t += sh.red[w];
+    if (t) c.ex_part[blockIdx.x] += t;
+  }
 }
 
 // One step; returns the mode it ran in (MODE_DONE: nothing was left to do).
 __device__ __forceinline__ int round_step(const RoundCtx& c, int k, AppendBuf& ab, StepShared& sh) {
   if (threadIdx.x == 0) {
-    sh.S = next_state(c, k);
+    // Once a step has written "done" into either slot no step writes a slot again, so later
+    // steps only need the two mode words to leave.
+    const bool done = __hip_atomic_load(&c.st[0].mode, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == MODE_DONE ||
+                      __hip_atomic_load(&c.st[1].mode, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == MODE_DONE;
+    if (done) {
+      sh.S.mode = MODE_DONE;
+      sh.S.seq = -1;
+    } else {
+      sh.S = next_state(c, k);
+    }
     ab.n = 0;
     ab.arcs = 0;
   }
   __syncthreads();
   const RoundState S = sh.S;
+  if (S.seq < 0) return MODE_DONE;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     store_state<__HIP_MEMORY_SCOPE_AGENT>(&c.st[k & 1], S);
     __hip_atomic_store(qcounter(c, k + 1), 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     // the host stops enqueueing steps once it reads "done"; written once per decomposition,
     // since a store to host memory delays the completion of the kernel that makes it
-    if (c.host_st && S.mode == MODE_DONE && (S.seq == 1 || load_state(&c.st[(k - 1) & 1]).mode != MODE_DONE))
-      store_state<__HIP_MEMORY_SCOPE_SYSTEM>(c.host_st, S);
+    if (c.host_st && S.mode == MODE_DONE) store_state<__HIP_MEMORY_SCOPE_SYSTEM>(c.host_st, S);
   }
   if (S.mode == MODE_DONE) return MODE_DONE;
   const unsigned nf = min((unsigned)((u64)S.prev >> 32), (unsigned)c.n), af = (unsigned)S.prev;
@@ -501,7 +536,7 @@ __device__ __forceinline__ int round_step(const RoundCtx& c, int k, AppendBuf& a
   block_flush(ab, c, k);
   const u64 bm = block_min_u64(wmin, sh);
   if (threadIdx.x == 0) c.lr_part[(size_t)(k & 1) * gridDim.x + blockIdx.x] = bm;
-  add_examined(c.ctrl, examined);
+  add_examined(c, examined, sh);
   return (int)S.mode;
 }
 
