@@ -74,6 +74,72 @@ def cpu_baseline(sample="rmat-22"):
                       f"1 run of {dt:.1f} s single-threaded"}
 
 
+def pack(graphs):
+    import numpy as np
+    vo, ao = [0], [0]
+    for rp, ci, s, _ in graphs:
+        vo.append(vo[-1] + rp.size - 1)
+        ao.append(ao[-1] + ci.size)
+    return (vo, ao, np.concatenate([g[0] for g in graphs]), np.concatenate([g[1] for g in graphs]),
+            np.concatenate([g[2] for g in graphs]))
+
+
+def run_batched(reps: int, plain_reps: int = 1):
+    """The batched workload (512 ER / random-geometric graphs, 1k-200k vertices each, own beta
+    and seeds): one ldd_decompose_batch call (all graphs advance together, one launch per round)
+    against the plain path (one ldd_decompose per graph), same inputs, same bits."""
+    import numpy as np
+    import torch
+
+    import inputs
+    import paper_1307_3692_amd as ldd
+
+    t = time.time()
+    graphs = inputs.batch_graphs(512, seed=1)
+    vo, ao, rp, ci, s = pack(graphs)
+    m = ao[-1] // 2
+    log(f"batch-512: {vo[-1]} vertices, {m} edges, generated in {time.time() - t:.1f}s")
+    dev = torch.device("cuda:0")
+    d_rp, d_ci, d_s = (torch.from_numpy(a).to(dev) for a in (rp, ci, s))
+    centre = torch.empty(vo[-1], dtype=torch.int32, device=dev)
+    ldd.decompose_batch(vo, ao, d_rp, d_ci, d_s, centre=centre)  # warm-up
+    torch.cuda.synchronize()
+    lat = []
+    for _ in range(reps):
+        a = time.perf_counter()
+        _, cuts = ldd.decompose_batch(vo, ao, d_rp, d_ci, d_s, centre=centre)
+        lat.append(time.perf_counter() - a)
+    union_centre = centre.cpu().numpy()
+    plain = []
+    for _ in range(plain_reps):
+        a = time.perf_counter()
+        _, pcuts = ldd.decompose_batch(vo, ao, d_rp, d_ci, d_s, centre=centre, batch_mode=ldd.BATCH_SEQUENTIAL)
+        plain.append(time.perf_counter() - a)
+    same = bool(np.array_equal(union_centre, centre.cpu().numpy()) and cuts == pcuts)
+    bit_exact = None
+    if os.path.exists(GOLDEN):
+        with open(GOLDEN) as f:
+            gold = json.load(f).get("batch-512")
+        if gold:
+            bit_exact = bool(hashlib.sha256(union_centre.view(np.uint8)).hexdigest() == gold["sha_centre"]
+                             and hashlib.sha256(np.array(cuts, np.int64).view(np.uint8)).hexdigest()
+                             == gold["sha_cuts"])
+    t_union, t_plain = float(np.median(lat)), float(np.median(plain))
+    out = {"workload": "batch-512: 512 graphs, n log-uniform 1k-200k, half Erdos-Renyi mean degree 8, half 2D "
+                       "random geometric mean degree 6, beta log-uniform [0.02, 0.3], seed 1",
+           "n": vo[-1], "m": m, "reps": reps,
+           "decompositions_per_s": round(512 / t_union, 1),
+           "gteps": round(m / t_union / 1e9, 3),
+           "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+           "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+           "plain_decompositions_per_s": round(512 / t_plain, 1),
+           "plain_ms": round(t_plain * 1e3, 3),
+           "speedup_vs_plain": round(t_plain / t_union, 2),
+           "identical_to_plain": same, "bit_exact": bit_exact}
+    log(f"batched: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,6 +147,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="rmat-24")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--engine", type=int, default=0)
     ap.add_argument("--direction", type=int, default=0)
     ap.add_argument("--blocks", type=int, default=0)
@@ -159,6 +226,10 @@ def main():
                      "traffic": traffic, "algorithmic_bytes": int(alg),
                      "kernel_ms": round(t_rounds * 1e3, 4)},
     }
+    if not args.no_batch:
+        del d_rp, d_ci, d_s, centre
+        torch.cuda.empty_cache()
+        out["batched"] = run_batched(reps=5)
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on rmat-22 ...")
         out["cpu_baseline"] = cpu_baseline()

@@ -77,8 +77,12 @@ typedef struct {
   int32_t bu_to_td;       /* switch back when frontier vertices * bu_to_td < n (0 = default 24)                 */
   int32_t tail_vertices;  /* finish by label correction once unsettled vertices * this <= active vertices
                              (0 = default 64, -1 = never)                                                      */
-  int32_t reserved[9];
+  int32_t batch_mode;     /* ldd_decompose_batch: LDD_BATCH_UNION (one launch per round for all graphs)  */
+                          /* or LDD_BATCH_SEQUENTIAL (one ldd_decompose per graph, for comparison)      */
+  int32_t reserved[8];
 } ldd_options;
+
+enum { LDD_BATCH_UNION = 0, LDD_BATCH_SEQUENTIAL = 1 };
 
 /* Counters of the last call (filled when a non-NULL pointer is passed). */
 typedef struct {

@@ -98,6 +98,8 @@ struct Workspace {
   Buf P, qv0, qv1, qa0, qa1, wake_ord, stamp, hub_bits;  // per vertex
   Buf hist, cursor, wake_off, next_ne, mat, qmax;        // per round / q-bucket (mat: per bucket and prep block)
   Buf ctrl, st, qcnt, lr_part, lb, ex_part;
+  // batch: union CSR with global ids, adjusted shifts, graph of each vertex, per-graph data
+  Buf b_rp, b_col, b_shift, b_gid, b_off, b_dg, b_cut;
   HostMirror* host = nullptr;
   hipEvent_t ev[6] = {};
   hipEvent_t chunk_ev[2] = {};
@@ -196,7 +198,8 @@ extern "C" void ldd_release_workspace(void) {
   w->graphs.clear();
   for (Buf* b : {&w->P, &w->qv0, &w->qv1, &w->qa0, &w->qa1, &w->wake_ord, &w->stamp, &w->hub_bits, &w->hist,
                  &w->cursor, &w->wake_off, &w->next_ne, &w->mat, &w->qmax, &w->ctrl, &w->st, &w->qcnt, &w->lr_part,
-                 &w->lb, &w->ex_part}) {
+                 &w->lb, &w->ex_part, &w->b_rp, &w->b_col, &w->b_shift, &w->b_gid, &w->b_off, &w->b_dg,
+                 &w->b_cut}) {
     if (b->p) (void)hipFree(b->p);
     b->p = nullptr;
     b->bytes = 0;
@@ -220,6 +223,16 @@ static ldd_status finish_error(unsigned err) {
   }
   return LDD_OK;
 }
+
+// Per-graph bookkeeping when the graph being decomposed is the disjoint union of a batch.
+struct BatchView {
+  const int* gid;          // device [n]: graph of every vertex
+  u64* cut_g;              // device [G]: 2 x cut edges per graph (see k_cut)
+};
+
+static ldd_status decompose_impl(Workspace& w, const ldd_csr* g, const int64_t* shift_fix, int32_t* centre,
+                                 int64_t* cut_edges, const ldd_options& o, ldd_stats* stats, hipStream_t st,
+                                 const BatchView* bv);
 
 extern "C" ldd_status ldd_decompose(const ldd_csr* g, const int64_t* shift_fix, double beta, int32_t* centre,
                                     int64_t* cut_edges, const ldd_options* opt, ldd_stats* stats, void* hip_stream) {
@@ -258,6 +271,14 @@ extern "C" ldd_status ldd_decompose(const ldd_csr* g, const int64_t* shift_fix, 
   HIP_TRY(hipGetDevice(&dev));
   Workspace& w = *workspace_for(dev);
   std::lock_guard<std::mutex> lk(w.mu);
+  return decompose_impl(w, g, shift_fix, centre, cut_edges, o, stats, st, nullptr);
+}
+
+static ldd_status decompose_impl(Workspace& w, const ldd_csr* g, const int64_t* shift_fix, int32_t* centre,
+                                 int64_t* cut_edges, const ldd_options& o, ldd_stats* stats, hipStream_t st,
+                                 const BatchView* bv) {
+  const int n = g->n;
+  const long long nnz = g->nnz;
   ldd_status s = ws_setup(w);
   if (s != LDD_OK) return s;
   const size_t nv = (size_t)n;
@@ -442,7 +463,7 @@ extern "C" ldd_status ldd_decompose(const ldd_csr* g, const int64_t* shift_fix, 
   if (nnz > 0)
     hipLaunchKernelGGL(k_cut, dim3(grid_for(nnz, 256 * 8, 2048)), dim3(256), 0, st, n, g->row_ptr, g->col_idx,
                        (const int*)centre, (const u64*)w.hub_bits.p, (const int*)w.qv0.p, (const unsigned*)w.qa0.p,
-                       ctrl);
+                       ctrl, bv ? bv->gid : nullptr, bv ? bv->cut_g : nullptr);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipEventRecord(w.ev[4], st));
   HIP_TRY(hipMemcpyAsync(&w.host->ctrl, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
@@ -502,5 +523,81 @@ ldd_status ldd_batch_sequential(int32_t num_graphs, const int64_t* vtx_off, cons
     if (s != LDD_OK) return s;
     if (cut_edges) cut_edges[gi] = cut;
   }
+  return LDD_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// many graphs at once: the disjoint union, one launch per round for all of them
+// ------------------------------------------------------------------------------------------
+// The batch is decomposed as one graph, the disjoint union, with global vertex ids.  Graph g's
+// shifts are raised by Delta_max - Delta_g, so that the union's per-vertex offset
+// Delta_max - shift' equals Delta_g - shift: every key is the one the graph has alone, and
+// global ids keep each graph's tie order.  So each graph's centres and cut equal those of
+// ldd_decompose on that graph, bit for bit, and all graphs advance one round per launch.
+ldd_status ldd_batch_union(int32_t G, const int64_t* vtx_off, const int64_t* arc_off, const int32_t* row_ptr,
+                           const int32_t* col_idx, const int64_t* shift_fix, int32_t* centre, int64_t* cut_edges,
+                           const ldd_options* opt, void* hip_stream) {
+  const long long N = vtx_off[G], M = arc_off[G];
+  if (N > INT32_MAX || M >= (1ll << 31)) {
+    ldd_set_error("batch too large for int32 ids (%lld vertices, %lld arcs)", N, M);
+    return LDD_ERR_INVALID_ARG;
+  }
+  if (N == 0) {
+    if (cut_edges)
+      for (int g = 0; g < G; ++g) cut_edges[g] = 0;
+    return LDD_OK;
+  }
+  ldd_options o{};
+  if (opt) o = *opt;
+  hipStream_t st = (hipStream_t)hip_stream;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  Workspace& w = *workspace_for(dev);
+  std::lock_guard<std::mutex> lk(w.mu);
+  ldd_status s = ws_setup(w);
+  if (s != LDD_OK) return s;
+  if ((s = grow(w.b_rp, (size_t)(N + 1) * 4)) || (s = grow(w.b_col, (size_t)(M > 0 ? M : 1) * 4)) ||
+      (s = grow(w.b_shift, (size_t)N * 8)) || (s = grow(w.b_gid, (size_t)N * 4)) ||
+      (s = grow(w.b_off, (size_t)(G + 1) * 16)) || (s = grow(w.b_dg, (size_t)(G + 1) * 128)) ||
+      (s = grow(w.b_cut, (size_t)G * 8)))
+    return s;
+  long long* d_vo = (long long*)w.b_off.p;
+  long long* d_ao = d_vo + (G + 1);
+  u64* d_dg = (u64*)w.b_dg.p;  // max shift of graph g at [16 g] (one line each), overall max at [16 G]
+  // offsets to the device through pinned staging
+  HIP_TRY(hipMemcpyAsync(d_vo, vtx_off, (size_t)(G + 1) * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(d_ao, arc_off, (size_t)(G + 1) * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemsetAsync(w.b_dg.p, 0, (size_t)(G + 1) * 128, st));
+  HIP_TRY(hipMemsetAsync(w.b_cut.p, 0, (size_t)G * 8, st));
+  HIP_TRY(hipMemsetAsync(w.ctrl.p, 0, sizeof(Ctrl), st));
+  Ctrl* ctrl = (Ctrl*)w.ctrl.p;
+  hipLaunchKernelGGL(k_batch_rows, dim3(grid_for(N, 256 * 4, 4096)), dim3(256), 0, st, G, (long long)N, d_vo, d_ao,
+                     row_ptr, (const long long*)shift_fix, (int*)w.b_rp.p, (int*)w.b_gid.p, d_dg, ctrl);
+  if (M > 0)
+    hipLaunchKernelGGL(k_batch_cols, dim3(grid_for(M, 256 * 4, 4096)), dim3(256), 0, st, G, (long long)M, d_vo, d_ao,
+                       col_idx, (int*)w.b_col.p, ctrl);
+  hipLaunchKernelGGL(k_batch_dmax, dim3(1), dim3(1024), 0, st, G, d_dg);
+  hipLaunchKernelGGL(k_batch_shift, dim3(grid_for(N, 256 * 4, 4096)), dim3(256), 0, st, G, (long long)N,
+                     (const int*)w.b_gid.p, (const long long*)shift_fix, (const u64*)d_dg, (long long*)w.b_shift.p);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(&w.host->ctrl, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (w.host->ctrl.err) {
+    (void)finish_error(w.host->ctrl.err);
+    ldd_set_error("batch: %s", ldd_last_error());
+    return LDD_ERR_INVALID_ARG;
+  }
+  ldd_csr ug{(int32_t)N, M, (const int32_t*)w.b_rp.p, (const int32_t*)w.b_col.p};
+  BatchView bv{(const int*)w.b_gid.p, (u64*)w.b_cut.p};
+  s = decompose_impl(w, &ug, (const int64_t*)w.b_shift.p, centre, nullptr, o, nullptr, st, &bv);
+  if (s != LDD_OK) return s;
+  hipLaunchKernelGGL(k_batch_localize, dim3(grid_for(N, 256 * 4, 4096)), dim3(256), 0, st, (long long)N,
+                     (const int*)w.b_gid.p, (const long long*)d_vo, centre);
+  HIP_TRY(hipGetLastError());
+  std::vector<u64> hc((size_t)G);
+  HIP_TRY(hipMemcpyAsync(hc.data(), w.b_cut.p, (size_t)G * 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (cut_edges)
+    for (int g = 0; g < G; ++g) cut_edges[g] = (int64_t)(hc[g] / 2);
   return LDD_OK;
 }

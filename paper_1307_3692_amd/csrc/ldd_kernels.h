@@ -92,6 +92,15 @@ __global__ void k_rounds_persistent(RoundCtx c);
 __global__ void k_finalize(int n, int B, const int* row_ptr, const u64* P, int* centre, u64* hub_bits, int* lv,
                            unsigned* la, Ctrl* ctrl);
 __global__ void k_cut(int n, const int* row_ptr, const int* col, const int* centre, const u64* hub_bits, const int* lv,
-                      const unsigned* la, Ctrl* ctrl);
+                      const unsigned* la, Ctrl* ctrl, const int* gid, u64* cut_g);
+// batch (disjoint union)
+__global__ void k_batch_rows(int G, long long N, const long long* vo, const long long* ao, const int* row_ptr,
+                             const long long* shift, int* rp_out, int* gid, u64* dg, Ctrl* ctrl);
+__global__ void k_batch_cols(int G, long long M, const long long* vo, const long long* ao, const int* col, int* col_out,
+                             Ctrl* ctrl);
+__global__ void k_batch_dmax(int G, u64* dg);
+__global__ void k_batch_shift(int G, long long N, const int* gid, const long long* shift, const u64* dg,
+                              long long* shift_out);
+__global__ void k_batch_localize(long long N, const int* gid, const long long* vo, int* centre);
 
 }  // namespace ldd

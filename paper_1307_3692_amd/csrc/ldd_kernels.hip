@@ -480,7 +480,7 @@ __device__ __forceinline__ bool hub_bit(const u64* bits, int v) { return (bits[v
 __global__ __launch_bounds__(256) void k_cut(int n, const int* __restrict__ row_ptr, const int* __restrict__ col,
                                              const int* __restrict__ centre, const u64* __restrict__ hub_bits,
                                              const int* __restrict__ lv, const unsigned* __restrict__ la,
-                                             Ctrl* ctrl) {
+                                             Ctrl* ctrl, const int* __restrict__ gid, u64* __restrict__ cut_g) {
   constexpr int T = 256;
   __shared__ unsigned w_pre[T + 1];
   __shared__ int w_first[T + 1];
@@ -522,6 +522,8 @@ __global__ __launch_bounds__(256) void k_cut(int n, const int* __restrict__ row_
       }
       __syncthreads();
       const unsigned a = tile + threadIdx.x;
+      unsigned contrib = 0;  // 2 per arc to H, 1 per two-sided cut arc
+      int row = -1;
       if (a < a_end) {
         int lo = 0, hi = T;
         while (hi - lo > 1) {
@@ -533,8 +535,25 @@ __global__ __launch_bounds__(256) void k_cut(int n, const int* __restrict__ row_
         if (j < w_pre[lo + 1] - w_pre[lo]) {
           const int w = col[(long long)w_first[lo] + j];
           if ((unsigned)w < (unsigned)n) {
-            if (hub_bit(hub_bits, w)) one_side += 1;
-            else both += (centre[w] != w_c[lo]);
+            if (hub_bit(hub_bits, w)) contrib = 2;
+            else contrib = centre[w] != w_c[lo] ? 1 : 0;
+          }
+          row = lv[ent + lo];
+        }
+      }
+      if (contrib == 2) one_side += 1;
+      else both += contrib;
+      if (cut_g) {  // per-graph totals (batch): one atomic per wave when all its arcs share a graph
+        const int g = (contrib && row >= 0) ? gid[row] : -1;
+        const u64 any = __ballot(g >= 0);
+        if (any) {
+          const int leader = __ffsll((long long)any) - 1;
+          const int g0 = __shfl(g, leader, WAVE);
+          if (__all(g < 0 || g == g0)) {
+            const u64 t = wave_sum_u64(g >= 0 ? contrib : 0);
+            if ((int)lane_id() == leader) atomic_add_u64(&cut_g[g0], t);
+          } else if (g >= 0) {
+            atomic_add_u64(&cut_g[g], contrib);
           }
         }
       }
@@ -556,6 +575,106 @@ __global__ __launch_bounds__(256) void k_cut(int n, const int* __restrict__ row_
   // cut_arcs accumulates 2 per one-sided arc and 1 per two-sided arc: cut = cut_arcs / 2
   const u64 v = block_sum(2 * one_side + both, red);
   if (threadIdx.x == 0 && v) atomic_add_u64(&ctrl->cut_arcs, v);
+}
+
+// ------------------------------------------------------------------------------------------
+// batch: the disjoint union of many graphs (packed CSR with local ids -> global ids)
+// ------------------------------------------------------------------------------------------
+// the last index g with off[g] <= x (graphs may be empty; the non-empty one containing x wins)
+__device__ __forceinline__ int graph_of(const long long* __restrict__ off, int G, long long x) {
+  int lo = 0, hi = G;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= x) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Global row offsets and the graph of every vertex; per-graph max shift (one 128-byte line per
+// graph, one atomic per wave when the wave lies in one graph); bounds checks of each graph.
+__global__ __launch_bounds__(256) void k_batch_rows(int G, long long N, const long long* __restrict__ vo,
+                                                    const long long* __restrict__ ao, const int* __restrict__ row_ptr,
+                                                    const long long* __restrict__ shift, int* __restrict__ rp_out,
+                                                    int* __restrict__ gid, u64* __restrict__ dg, Ctrl* ctrl) {
+  unsigned bad = 0;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long base = (long long)blockIdx.x * blockDim.x; base < N; base += stride) {
+    const long long v = base + threadIdx.x;
+    int g = -1;
+    u64 sv = 0;
+    if (v < N) {
+      g = graph_of(vo, G, v);
+      const long long lv = v - vo[g], ng = vo[g + 1] - vo[g], mg = ao[g + 1] - ao[g];
+      const long long at = vo[g] + g + lv;
+      const int a = row_ptr[at], b = row_ptr[at + 1];
+      if (a < 0 || b < a || b > mg || (lv == 0 && a != 0) || (lv == ng - 1 && b != mg)) bad |= ERR_BAD_ROWPTR;
+      rp_out[v] = (int)(ao[g] + a);
+      if (v == N - 1) rp_out[N] = (int)ao[G];
+      gid[v] = g;
+      const long long s = shift[v];
+      if (s < 0 || s > (1ll << 52)) bad |= ERR_BAD_SHIFT;
+      else sv = (u64)s;
+    }
+    const u64 any = __ballot(g >= 0);
+    if (any) {
+      const int leader = __ffsll((long long)any) - 1;
+      const int g0 = __shfl(g, leader, WAVE);
+      if (__all(g < 0 || g == g0)) {
+        const u64 m = wave_max_u64(sv);
+        if ((int)lane_id() == leader) atomic_max_u64(&dg[(size_t)g0 * 16], m);
+      } else if (g >= 0) {
+        atomic_max_u64(&dg[(size_t)g * 16], sv);
+      }
+    }
+  }
+  if (bad) atomic_or_u32(&ctrl->err, bad);
+}
+
+// Column ids to global ids; out-of-range local ids are reported and replaced by the graph's
+// first vertex so that no later access leaves the union.
+__global__ __launch_bounds__(256) void k_batch_cols(int G, long long M, const long long* __restrict__ vo,
+                                                    const long long* __restrict__ ao, const int* __restrict__ col,
+                                                    int* __restrict__ col_out, Ctrl* ctrl) {
+  unsigned bad = 0;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long a = (long long)blockIdx.x * blockDim.x + threadIdx.x; a < M; a += stride) {
+    const int g = graph_of(ao, G, a);
+    const int c = col[a];
+    const long long ng = vo[g + 1] - vo[g];
+    if (c < 0 || c >= ng) {
+      bad = ERR_BAD_COL;
+      col_out[a] = (int)vo[g];
+    } else {
+      col_out[a] = (int)(vo[g] + c);
+    }
+  }
+  if (bad) atomic_or_u32(&ctrl->err, bad);
+}
+
+__global__ __launch_bounds__(1024) void k_batch_dmax(int G, u64* dg) {
+  __shared__ u64 red[16];
+  u64 m = 0;
+  for (int g = threadIdx.x; g < G; g += blockDim.x) m = dg[(size_t)g * 16] > m ? dg[(size_t)g * 16] : m;
+  m = block_max(m, red);
+  if (threadIdx.x == 0) dg[(size_t)G * 16] = m;
+}
+
+// shift' = shift + (Delta_max - Delta_g): the union's offset Delta_max - shift' is Delta_g - shift
+__global__ __launch_bounds__(256) void k_batch_shift(int G, long long N, const int* __restrict__ gid,
+                                                     const long long* __restrict__ shift, const u64* __restrict__ dg,
+                                                     long long* __restrict__ shift_out) {
+  const u64 dmax = dg[(size_t)G * 16];
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < N; v += stride)
+    shift_out[v] = shift[v] + (long long)(dmax - dg[(size_t)gid[v] * 16]);
+}
+
+__global__ __launch_bounds__(256) void k_batch_localize(long long N, const int* __restrict__ gid,
+                                                        const long long* __restrict__ vo, int* __restrict__ centre) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < N; v += stride)
+    centre[v] -= (int)vo[gid[v]];
 }
 
 }  // namespace ldd

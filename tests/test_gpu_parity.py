@@ -273,3 +273,59 @@ def test_many_rounds_fallback_sort(ldd):
         got, cut, st = run(ldd, rp, ci, s, **mode)
         assert st["rounds_bound"] > 8192
         assert np.array_equal(got, want_c) and cut == want_cut, mode
+
+
+def pack(graphs):
+    vo, ao, rps, cis, ss = [0], [0], [], [], []
+    for rp, ci, s in graphs:
+        vo.append(vo[-1] + rp.size - 1)
+        ao.append(ao[-1] + ci.size)
+        rps.append(rp)
+        cis.append(ci)
+        ss.append(s)
+    return vo, ao, np.concatenate(rps), np.concatenate(cis) if ao[-1] else np.zeros(0, np.int32), np.concatenate(ss)
+
+
+def test_batch_union_equals_alone_and_oracle(ldd):
+    rng = np.random.default_rng(44)
+    graphs = [(rp, ci, s) for rp, ci, s, _ in inputs.batch_graphs(40, seed=7, n_lo=200, n_hi=30_000)]
+    # degenerate members: an empty graph, an edgeless graph, a single vertex, tie-heavy shifts
+    graphs.insert(3, (np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0, np.int64)))
+    rp, ci = inputs.from_edges(50, [], [])
+    graphs.insert(7, (rp, ci, inputs.make_shifts(50, 0.1, 3)))
+    graphs.insert(11, (np.array([0, 0], np.int32), np.zeros(0, np.int32), np.array([5], np.int64)))
+    rp, ci = inputs.grid2d(20, 20)
+    graphs.append((rp, ci, (rng.integers(0, 4, 400) * S).astype(np.int64)))
+    vo, ao, rp_all, ci_all, s_all = pack(graphs)
+    d_rp, d_ci, d_s = to_dev(rp_all, ci_all, s_all)
+    want = [oracle.decompose(rp, ci, s) for rp, ci, s in graphs]
+    for mode in (dict(), dict(batch_mode=1), dict(direction=2), dict(tail_vertices=-1), dict(engine=1)):
+        centre, cuts = ldd.decompose_batch(vo, ao, d_rp, d_ci, d_s, **mode)
+        centre = centre.cpu().numpy()
+        for g, (wc, _, wcut) in enumerate(want):
+            assert np.array_equal(centre[vo[g]:vo[g + 1]], wc), (mode, g)
+            assert cuts[g] == wcut, (mode, g)
+
+
+def test_batch_rejects_bad_local_ids(ldd):
+    rp, ci = inputs.grid2d(6, 6)
+    ci2 = ci.copy()
+    ci2[3] = 36  # local id out of range of its graph (would be valid in the union)
+    graphs = [(rp, ci, inputs.make_shifts(36, 0.1, 1)), (rp, ci2, inputs.make_shifts(36, 0.1, 2))]
+    vo, ao, rp_all, ci_all, s_all = pack(graphs)
+    d_rp, d_ci, d_s = to_dev(rp_all, ci_all, s_all)
+    with pytest.raises(ldd.LddError) as e:
+        ldd.decompose_batch(vo, ao, d_rp, d_ci, d_s)
+    assert e.value.status == ldd.ERR_INVALID_ARG
+
+
+def test_batch_512_workload_digest(ldd):
+    with open(GOLDEN) as f:
+        gold = json.load(f)["batch-512"]
+    graphs = [(rp, ci, s) for rp, ci, s, _ in inputs.batch_graphs(512, seed=1)]
+    vo, ao, rp_all, ci_all, s_all = pack(graphs)
+    log(f"batch-512: {vo[-1]} vertices, {ao[-1]} arcs")
+    d_rp, d_ci, d_s = to_dev(rp_all, ci_all, s_all)
+    centre, cuts = ldd.decompose_batch(vo, ao, d_rp, d_ci, d_s)
+    assert sha(centre.cpu().numpy()) == gold["sha_centre"]
+    assert sha(np.array(cuts, np.int64)) == gold["sha_cuts"]
