@@ -138,6 +138,99 @@ ldd_status ldd_decompose_batch(int32_t num_graphs, const int64_t* vtx_off, const
                                const int32_t* row_ptr, const int32_t* col_idx, const int64_t* shift_fix,
                                int32_t* centre, int64_t* cut_edges, const ldd_options* opt, void* hip_stream);
 
+/*
+ * Serving: a long-lived engine that decomposes a stream of independent requests (the same
+ * operation as ldd_decompose per request, bit for bit) with continuous batching.  Admitted
+ * requests share one device-resident arena and advance together, one launch per round over
+ * all of them; a request joins at the next round boundary and leaves as soon as its own last
+ * round has run, while others keep going.  The arena is sized once, from the memory budget;
+ * requests wait in a first-come-first-served queue until their vertices, arcs and a slot fit.
+ * A request whose round 0 runs at global round r0 is the search of Sec. 5 with every source
+ * arc lengthened by r0 units, which changes no comparison inside its component.
+ *
+ * Threads: one engine thread per server owns its device stream.  submit / poll / wait / cancel
+ * / query may be called from any thread.  All calls return an ldd_status.
+ */
+typedef struct ldd_server ldd_server;
+
+typedef struct {
+  int64_t hbm_budget_bytes; /* arena size in device bytes; split as 40 B per vertex + 4 B per   */
+                            /* arc for graphs of about 16 arcs per vertex unless max_* are set */
+  int64_t max_vertices;     /* arena vertices (a request takes n + 1); 0 = from the budget     */
+  int64_t max_arcs;         /* arena arcs (a request takes nnz); 0 = from the budget            */
+  int32_t max_slots;        /* requests on the device at once, 1..64 (0 = 64)                   */
+  int32_t chunk_steps;      /* rounds per replayed launch graph, 1..64 (0 = 8)                  */
+  int32_t blocks;           /* workgroups of the round kernel (0 = 2 per CU)                    */
+  int32_t direction;        /* LDD_DIR_* policy of every round                                   */
+  int32_t max_rounds;       /* testing: key range in rounds before keys are rebased (0 = the    */
+                            /* largest the label width allows); requests may need at most half */
+  int32_t reserved[7];
+} ldd_server_config;
+
+/* One request.  All buffers are device memory of the server's device, owned by the caller,
+ * and must stay alive and unchanged until the request is reported done (poll / wait). */
+typedef struct {
+  int32_t n;                /* vertices, >= 0                                                 */
+  int64_t nnz;              /* arcs, 0 <= nnz < 2^31, stored symmetric as for ldd_decompose   */
+  const int32_t* row_ptr;   /* device [n+1]                                                   */
+  const int32_t* col_idx;   /* device [nnz]                                                   */
+  const int64_t* shift_fix; /* device [n], in [0, 2^52], units of 2^-20                        */
+  int32_t* centre;          /* device [n], OUT: centre of every vertex (request-local ids)     */
+  void* hip_stream;         /* stream whose queued work produces the inputs (NULL = default)  */
+} ldd_request;
+
+typedef struct {
+  ldd_status status;        /* LDD_OK, LDD_ERR_CANCELLED, or the engine's failure             */
+  int32_t rounds;           /* floor(Delta / 2^20) + 1 of the request                          */
+  int64_t cut_edges;        /* edges whose endpoints have different centres                    */
+  int64_t first_round;      /* global round its round 0 ran at (numbering at admission)        */
+  double t_submit;          /* seconds since the server was created                            */
+  double t_admit;
+  double t_done;
+  double latency_ms;        /* t_done - t_submit                                               */
+} ldd_result;
+
+typedef struct {
+  int64_t arena_vertices;
+  int64_t arena_arcs;
+  int32_t max_rounds;       /* largest floor(Delta / 2^20) + 1 a request may have              */
+  int32_t max_slots;
+  int64_t admitted;
+  int64_t completed;
+  int64_t queued;
+  int64_t max_active;       /* most requests on the device at once so far                      */
+  int64_t steps;            /* rounds launched so far                                          */
+  int64_t rebases;
+} ldd_server_info;
+
+/* Create a server on the current HIP device.  LDD_ERR_BUDGET if the budget gives no usable
+ * arena, LDD_ERR_OOM if the arena cannot be allocated. */
+ldd_status ldd_server_create(const ldd_server_config* cfg, ldd_server** out);
+
+/* Validate a request (on the device, after the work queued on req->hip_stream) and queue it.
+ * Returns LDD_ERR_INVALID_ARG for bad CSR or shifts, LDD_ERR_BUDGET if it can never fit the
+ * arena, LDD_ERR_OVERFLOW if it needs more rounds than the server takes; on LDD_OK *ticket
+ * names the request until its result is collected. */
+ldd_status ldd_server_submit(ldd_server* srv, const ldd_request* req, uint64_t* ticket);
+
+/* LDD_ERR_PENDING while the request runs; otherwise fills *out, forgets the ticket and returns
+ * the request's status.  After a result is collected, req->centre holds the decomposition. */
+ldd_status ldd_server_poll(ldd_server* srv, uint64_t ticket, ldd_result* out);
+
+/* As poll, blocking until the request is done. */
+ldd_status ldd_server_wait(ldd_server* srv, uint64_t ticket, ldd_result* out);
+
+/* Cancel a request still in the queue (its result then has status LDD_ERR_CANCELLED and must
+ * still be collected); LDD_ERR_PENDING if it is already on the device. */
+ldd_status ldd_server_cancel(ldd_server* srv, uint64_t ticket);
+
+/* Counters and limits; returns the engine's failure status, if any. */
+ldd_status ldd_server_query(ldd_server* srv, ldd_server_info* out);
+
+/* Finish every queued and running request, then free the server (tickets not collected are
+ * dropped).  Returns the engine's failure status, if any. */
+ldd_status ldd_server_destroy(ldd_server* srv);
+
 /* Human-readable name of a status code (static string). */
 const char* ldd_status_string(ldd_status s);
 /* Detail of the last error on this thread (static thread-local buffer). */

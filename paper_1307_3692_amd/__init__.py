@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _ROOT = os.path.dirname(_HERE)
 SO_PATH = os.path.join(_HERE, "libldd.so")
 SOURCES = [os.path.join(_HERE, "csrc", f) for f in ("ldd_kernels.hip", "ldd_rounds.hip", "ldd_api.hip",
-                                                   "ldd_batch.hip")]
+                                                   "ldd_batch.hip", "ldd_server.hip")]
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
@@ -27,7 +27,8 @@ DIR_AUTO, DIR_TOP_DOWN, DIR_BOTTOM_UP = 0, 1, 2
 ENGINE_AUTO, ENGINE_PERSISTENT, ENGINE_LAUNCH = 0, 1, 2
 
 EXPORTED = ("ldd_decompose", "ldd_workspace_bytes", "ldd_decompose_batch", "ldd_status_string", "ldd_last_error",
-            "ldd_release_workspace")
+            "ldd_release_workspace", "ldd_server_create", "ldd_server_submit", "ldd_server_poll", "ldd_server_wait",
+            "ldd_server_cancel", "ldd_server_query", "ldd_server_destroy")
 
 
 class LddError(RuntimeError):
@@ -56,6 +57,37 @@ class Stats(ctypes.Structure):
                 ("arcs_examined", ctypes.c_int64), ("n_active", ctypes.c_int64),
                 ("ms_prep", ctypes.c_float), ("ms_rounds", ctypes.c_float), ("ms_finalize", ctypes.c_float),
                 ("ms_cut", ctypes.c_float)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_vertices", ctypes.c_int64), ("max_arcs", ctypes.c_int64),
+                ("max_slots", ctypes.c_int32), ("chunk_steps", ctypes.c_int32), ("blocks", ctypes.c_int32),
+                ("direction", ctypes.c_int32), ("max_rounds", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col_idx", ctypes.c_void_p), ("shift_fix", ctypes.c_void_p), ("centre", ctypes.c_void_p),
+                ("hip_stream", ctypes.c_void_p)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("rounds", ctypes.c_int32), ("cut_edges", ctypes.c_int64),
+                ("first_round", ctypes.c_int64), ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("latency_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServerInfo(ctypes.Structure):
+    _fields_ = [("arena_vertices", ctypes.c_int64), ("arena_arcs", ctypes.c_int64), ("max_rounds", ctypes.c_int32),
+                ("max_slots", ctypes.c_int32), ("admitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("queued", ctypes.c_int64), ("max_active", ctypes.c_int64), ("steps", ctypes.c_int64),
+                ("rebases", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -94,6 +126,15 @@ def lib():
     L.ldd_last_error.restype = ctypes.c_char_p
     L.ldd_release_workspace.argtypes = []
     L.ldd_release_workspace.restype = None
+    L.ldd_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
+    L.ldd_server_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
+    L.ldd_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(Result)]
+    L.ldd_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(Result)]
+    L.ldd_server_cancel.argtypes = [vp, ctypes.c_uint64]
+    L.ldd_server_query.argtypes = [vp, ctypes.POINTER(ServerInfo)]
+    L.ldd_server_destroy.argtypes = [vp]
+    for f in ("create", "submit", "poll", "wait", "cancel", "query", "destroy"):
+        getattr(L, "ldd_server_" + f).restype = i32
     _lib = L
     return L
 
@@ -193,3 +234,93 @@ def decompose_batch(vtx_off, arc_off, row_ptr, col_idx, shift_fix, *, centre=Non
 
 def workspace_bytes(n: int, nnz: int) -> int:
     return int(lib().ldd_workspace_bytes(n, nnz))
+
+
+class Server:
+    """Continuous-batching decomposition server (``ldd_server_*``): requests are queued, admitted
+    into one device-resident arena as room frees up, and advance together one round per step.
+
+    ``submit`` takes device tensors (kept referenced until the result is collected) and returns a
+    ticket; ``wait`` / ``poll`` give ``(centre tensor, cut_edges, info dict)``.
+    """
+
+    def __init__(self, hbm_budget_bytes: int = 1 << 30, max_vertices: int = 0, max_arcs: int = 0,
+                 max_slots: int = 0, chunk_steps: int = 0, blocks: int = 0, direction: int = DIR_AUTO,
+                 max_rounds: int = 0):
+        cfg = ServerConfig()
+        cfg.hbm_budget_bytes, cfg.max_vertices, cfg.max_arcs = hbm_budget_bytes, max_vertices, max_arcs
+        cfg.max_slots, cfg.chunk_steps, cfg.blocks = max_slots, chunk_steps, blocks
+        cfg.direction, cfg.max_rounds = direction, max_rounds
+        h = ctypes.c_void_p()
+        _check(lib().ldd_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._live = {}  # ticket -> (tensors kept alive, centre)
+
+    def submit(self, row_ptr, col_idx, shift_fix, *, centre=None, stream=None) -> int:
+        import torch
+        _device_tensor(row_ptr, torch.int32, "row_ptr")
+        _device_tensor(col_idx, torch.int32, "col_idx")
+        _device_tensor(shift_fix, torch.int64, "shift_fix")
+        n = row_ptr.numel() - 1
+        if n < 0 or shift_fix.numel() != n:
+            raise ValueError("row_ptr and shift_fix sizes disagree")
+        if centre is None:
+            centre = torch.empty(n, dtype=torch.int32, device=row_ptr.device)
+        else:
+            _device_tensor(centre, torch.int32, "centre")
+            if centre.numel() != n:
+                raise ValueError("centre has the wrong size")
+        q = Request(n, col_idx.numel(), row_ptr.data_ptr(), col_idx.data_ptr() if col_idx.numel() else None,
+                    shift_fix.data_ptr(), centre.data_ptr(), _stream_handle(stream).value)
+        t = ctypes.c_uint64(0)
+        _check(lib().ldd_server_submit(self._h, ctypes.byref(q), ctypes.byref(t)))
+        self._live[t.value] = ((row_ptr, col_idx, shift_fix), centre)
+        return t.value
+
+    def _collect(self, ticket, status, res):
+        if status == ERR_PENDING:
+            return None
+        _, centre = self._live.pop(ticket, (None, None))
+        _check(status)
+        return centre, int(res.cut_edges), res.as_dict()
+
+    def poll(self, ticket: int):
+        """``None`` while the request runs, else ``(centre, cut_edges, info)``."""
+        res = Result()
+        return self._collect(ticket, lib().ldd_server_poll(self._h, ticket, ctypes.byref(res)), res)
+
+    def wait(self, ticket: int):
+        res = Result()
+        return self._collect(ticket, lib().ldd_server_wait(self._h, ticket, ctypes.byref(res)), res)
+
+    def cancel(self, ticket: int) -> bool:
+        """True if the request was still queued (collect it: its status is cancelled)."""
+        s = lib().ldd_server_cancel(self._h, ticket)
+        if s == ERR_PENDING:
+            return False
+        _check(s)
+        return True
+
+    def info(self) -> dict:
+        out = ServerInfo()
+        _check(lib().ldd_server_query(self._h, ctypes.byref(out)))
+        return out.as_dict()
+
+    def close(self):
+        if self._h:
+            h, self._h = self._h, None
+            status = lib().ldd_server_destroy(h)  # runs what is queued: inputs must outlive it
+            self._live.clear()
+            _check(status)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -396,6 +396,9 @@ static ldd_status decompose_impl(Workspace& w, const ldd_csr* g, const int64_t* 
   c.tail_min_left = 16;
   c.host_st = nullptr;
   c.ex_part = (u64*)w.ex_part.p;
+  c.slots = nullptr;
+  c.nslots = 0;
+  c.wake_tab = nullptr;
   HIP_TRY(hipMemsetAsync(w.ex_part.p, 0, (size_t)RT * sizeof(u64), st));
 
   const int engine = o.engine == LDD_ENGINE_AUTO ? LDD_ENGINE_LAUNCH : o.engine;

@@ -35,6 +35,17 @@ struct RoundState {
 #undef LDD_DECL
 };
 
+// Server mode: one admitted request per slot, in its own vertex range of the arena.
+constexpr int MAX_SLOTS = 64;
+struct SlotInfo {
+  long long vbeg;   // first arena vertex of the slot
+  long long r0;     // global round of the request's round 0
+  int R;            // the request's rounds (its wake rounds are r0 .. r0 + R - 1)
+  int wbase;        // its round offsets start at wake_tab[wbase] (R + 1 entries)
+  int active;
+  int pad;
+};
+
 // Everything a round step needs, passed by value.
 struct RoundCtx {
   int n;
@@ -65,6 +76,11 @@ struct RoundCtx {
   int tail_min_left;  // ... and more than this many rounds remain
   RoundState* host_st;  // pinned host mirror of the latest state (may be null)
   u64* ex_part;     // [G]: arcs examined by each block over all steps (statistics)
+  // server mode (slots != null): every step is the next global round, no tail, never "done";
+  // round r's wakers are those of every active slot's local round r - r0
+  const SlotInfo* slots;
+  int nslots;
+  const int* wake_tab;
 };
 
 // Arguments of graph-launched steps: step k = kbase + j of a chunk; k_advance moves kbase.

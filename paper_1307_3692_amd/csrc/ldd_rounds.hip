@@ -41,6 +41,9 @@ struct StepShared {
   u64 lr;
   unsigned start;
   u64 red[NW];
+  // server mode: this round's wake segment of every slot (start in wake_ord, prefix of lengths)
+  long long seg_beg[MAX_SLOTS];
+  int seg_off[MAX_SLOTS + 1];
   // top-down window: RT+1 queue entries (arc prefix, first arc in col_idx, offer)
   unsigned w_pre[RT + 1];
   int w_first[RT + 1];
@@ -140,6 +143,62 @@ __device__ __forceinline__ u64 own_offer(const RoundCtx& c, int v) {
 }
 
 // ---- round r: wake bucket r (the delayed source arcs of length in [r, r+1) units) ----------
+// Server mode: the wakers of global round r are, for every active slot with r0 <= r < r0 + R,
+// the vertices of its local round r - r0 (a segment of its part of wake_ord).
+__device__ __forceinline__ void phase_wake_slots(const RoundCtx& c, int r, int k, AppendBuf& ab, StepShared& sh,
+                                                 u64& wmin) {
+  if (threadIdx.x < WAVE) {
+    const int t = threadIdx.x;
+    int len = 0;
+    long long beg = 0;
+    if (t < c.nslots) {
+      const SlotInfo sl = c.slots[t];
+      const long long rho = (long long)r - sl.r0;
+      if (sl.active && rho >= 0 && rho < sl.R) {
+        const int lo = c.wake_tab[sl.wbase + rho], hi = c.wake_tab[sl.wbase + rho + 1];
+        len = hi - lo;
+        beg = sl.vbeg + lo;
+      }
+    }
+    const unsigned incl = wave_incl_scan((unsigned)len);
+    if (t < MAX_SLOTS) {
+      sh.seg_beg[t] = beg;
+      sh.seg_off[t + 1] = (int)incl;
+    }
+    if (t == 0) sh.seg_off[0] = 0;
+  }
+  __syncthreads();
+  const int ns = c.nslots < MAX_SLOTS ? c.nslots : MAX_SLOTS;
+  const int cnt = sh.seg_off[ns];
+  for (long long base = (long long)blockIdx.x * RT; base < cnt; base += (long long)gridDim.x * RT) {
+    const long long i = base + threadIdx.x;
+    bool want = false;
+    int v = 0;
+    unsigned deg = 0;
+    if (i < cnt) {
+      int lo = 0, hi = ns;  // last slot with seg_off <= i
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (sh.seg_off[mid] <= i) lo = mid;
+        else hi = mid;
+      }
+      v = c.wake_ord[sh.seg_beg[lo] + (i - sh.seg_off[lo])];
+      const u64 self = own_offer(c, v);
+      if (c.P[v] > self) {
+        const u64 old = atomic_min_u64(&c.P[v], self);
+        if (old > self) {
+          wmin = self < wmin ? self : wmin;
+          if (old == INF) {
+            want = true;
+            deg = degree(c, v);
+          }
+        }
+      }
+    }
+    block_append(ab, want, v, deg, c, k);
+  }
+}
+
 // With the q-layout, round r's wakers are the vertices of bucket q = D - r whose shift's
 // fractional part is <= that of Delta, and those of bucket D - r - 1 whose fractional part
 // is larger; the two buckets are adjacent in wake_ord.
@@ -418,6 +477,20 @@ __device__ __forceinline__ RoundState next_state(const RoundCtx& c, int k) {
   S.seq = k;
   if (P.mode == MODE_DONE) return S;
   const unsigned nf = min((unsigned)(out >> 32), (unsigned)c.n), af = (unsigned)out;
+  if (c.slots) {  // server: the next global round, always
+    S.settled += nf;
+    S.unsettled_arcs -= af;
+    S.rounds += 1;
+    S.max_frontier = (long long)nf > S.max_frontier ? (long long)nf : S.max_frontier;
+    if (P.prev >> 32) {
+      S.td_rounds += P.dir == DIR_TD;
+      S.bu_rounds += P.dir == DIR_BU;
+    }
+    S.round = P.round + 1;
+    S.prev = (long long)out;
+    S.dir = nf ? choose_dir(c, (int)P.dir, nf, af, (u64)S.unsettled_arcs) : P.dir;
+    return S;
+  }
   if (P.mode == MODE_ROUNDS) {
     int next_r;
     if (k > 1) {
@@ -515,7 +588,8 @@ __device__ __forceinline__ int round_step(const RoundCtx& c, int k, AppendBuf& a
   }
   if (S.mode == MODE_ROUNDS) {
     const int r = (int)S.round;
-    phase_wake(c, r, k, ab, wmin);
+    if (c.slots) phase_wake_slots(c, r, k, ab, sh, wmin);
+    else phase_wake(c, r, k, ab, wmin);
     if (nf) {
       if (S.dir == DIR_BU) {
         phase_bottom_up(c, r, k, sh.lr, ab, wmin, examined);
