@@ -140,6 +140,173 @@ def run_batched(reps: int, plain_reps: int = 1):
     return out
 
 
+SERVE_SCALES = tuple(range(12, 23))
+SERVE_BETAS = (0.05, 0.1, 0.2)
+
+
+def serve_templates(dev):
+    """The request pool: RMAT scale 12..22 (edge factor 16, graph seed 1000 + scale), each with
+    beta in {0.05, 0.1, 0.2} and two shift seeds: 66 distinct (graph, beta, shifts) templates,
+    device-resident.  A request stream draws templates uniformly, so its scale is uniform in
+    12..22 and its beta uniform in the three values."""
+    import torch
+
+    import inputs
+    out = []
+    for scale in SERVE_SCALES:
+        rp, ci = inputs.rmat(scale, 16, seed=1000 + scale)
+        d_rp, d_ci = torch.from_numpy(rp).to(dev), torch.from_numpy(ci).to(dev)
+        for j, beta in enumerate(SERVE_BETAS):
+            for k in range(2):
+                seed = 1000 + 6 * (scale - 12) + 2 * j + k
+                d_s = torch.from_numpy(inputs.make_shifts(rp.size - 1, beta, seed)).to(dev)
+                out.append({"scale": scale, "beta": beta, "seed": seed, "n": rp.size - 1, "m": ci.size // 2,
+                            "rp": d_rp, "ci": d_ci, "s": d_s})
+    return out
+
+
+def fifo_latencies(arrivals, service):
+    """One worker, first come first served: latency of each request (same unit as inputs)."""
+    import numpy as np
+    done = np.empty_like(arrivals)
+    t = -np.inf
+    for i, (a, s) in enumerate(zip(arrivals, service)):
+        t = max(t, a) + s
+        done[i] = t
+    return done - arrivals
+
+
+def serve_run(ldd, srv, tm, req, outs, arrivals=None):
+    """Submit requests (all at once, or at the given arrival offsets in seconds), collect them
+    on a second thread; returns per-request latency (ms) and the run's wall span (s)."""
+    import threading
+
+    import numpy as np
+    N = len(req)
+    tickets = [None] * N
+    sub_py = np.zeros(N)
+    lag = np.zeros(N)
+    results = [None] * N
+    ready = [threading.Event() for _ in range(N)]
+
+    def collect():
+        for i in range(N):
+            ready[i].wait()
+            results[i] = srv.wait(tickets[i])
+
+    th = threading.Thread(target=collect)
+    th.start()
+    t0 = time.perf_counter()
+    for i, t in enumerate(req):
+        if arrivals is not None:
+            due = t0 + arrivals[i]
+            while True:
+                now = time.perf_counter()
+                if now >= due:
+                    break
+                if due - now > 2e-3:
+                    time.sleep(due - now - 1e-3)
+        sub_py[i] = time.perf_counter()
+        lag[i] = sub_py[i] - (t0 + arrivals[i]) if arrivals is not None else 0.0
+        tickets[i] = srv.submit(tm[t]["rp"], tm[t]["ci"], tm[t]["s"], centre=outs[i])
+        ready[i].set()
+    th.join()
+    lat = np.array([r[2]["latency_ms"] for r in results]) + lag * 1e3
+    done_py = sub_py + np.array([(r[2]["t_done"] - r[2]["t_submit"]) for r in results])
+    start = t0 if arrivals is not None else sub_py[0]
+    return lat, float(done_py.max() - start), results
+
+
+def run_serving(n_requests: int = 2000, budget_gib: float = 16.0, small_budget_gib: float = 1.0):
+    """Serving: a stream of RMAT 12-22 requests through ldd_server_* (continuous batching into
+    one device-resident arena) against the plain path (one ldd_decompose per request, FIFO).
+    Capacity comes from a saturating closed loop; latency from Poisson arrivals at 80% of it."""
+    import numpy as np
+    import torch
+
+    import paper_1307_3692_amd as ldd
+    dev = torch.device("cuda:0")
+    t = time.time()
+    tm = serve_templates(dev)
+    log(f"serve: {len(tm)} templates generated in {time.time() - t:.1f}s")
+    rng = np.random.default_rng(1)
+    req = rng.integers(0, len(tm), n_requests)
+    ref = []
+    for x in tm:  # plain results, the identity check for every served request
+        c, cut = ldd.decompose(x["rp"], x["ci"], x["s"], x["beta"])
+        ref.append((c, cut))
+    # plain: the request stream one ldd_decompose at a time
+    service = np.zeros(n_requests)
+    plain_out = {}
+    for i, ti in enumerate(req):
+        x = tm[ti]
+        buf = plain_out.setdefault(ti, torch.empty(x["n"], dtype=torch.int32, device=dev))
+        a = time.perf_counter()
+        ldd.decompose(x["rp"], x["ci"], x["s"], x["beta"], centre=buf)
+        service[i] = time.perf_counter() - a
+    plain_cap = n_requests / service.sum()
+    log(f"serve: plain {plain_cap:.1f} req/s, mean {service.mean() * 1e3:.3f} ms")
+    outs = [torch.empty(tm[ti]["n"], dtype=torch.int32, device=dev) for ti in req]
+    torch.cuda.synchronize()
+
+    def verify(results):
+        ok = True
+        for i, ti in enumerate(req):
+            c, cut, _ = results[i]
+            ok &= bool(torch.equal(c, ref[ti][0])) and cut == ref[ti][1]
+        return ok
+
+    out = {"workload": f"serving: {n_requests} requests, RMAT scale uniform 12-22 (edge factor 16, graph seed "
+                       "1000+scale), beta uniform in {0.05, 0.1, 0.2}, shift seeds 1000+6(scale-12)+2j+k "
+                       "(66 device-resident templates), template stream seed 1",
+           "requests": n_requests, "mean_edges": round(float(np.mean([tm[i]["m"] for i in req])), 1)}
+    with ldd.Server(hbm_budget_bytes=int(budget_gib * 2**30)) as srv:
+        serve_run(ldd, srv, tm, req[:64], outs[:64])  # warm-up
+        lat_c, span_c, res_c = serve_run(ldd, srv, tm, req, outs)
+        cap = n_requests / span_c
+        same_c = verify(res_c)
+        lam = 0.8 * cap
+        arr = np.cumsum(np.random.default_rng(2).exponential(1.0 / lam, n_requests))
+        lat_p, span_p, res_p = serve_run(ldd, srv, tm, req, outs, arrivals=arr)
+        same_p = verify(res_p)
+        info = srv.info()
+    log(f"serve: capacity {cap:.1f} req/s, poisson p50 {np.percentile(lat_p, 50):.3f} ms, info {info}")
+    plain_same = fifo_latencies(arr, service) * 1e3
+    arr_own = arr * (lam / (0.8 * plain_cap))
+    plain_own = fifo_latencies(arr_own, service) * 1e3
+    out.update({
+        "hbm_budget_gib": budget_gib, "arena_vertices": info["arena_vertices"], "arena_arcs": info["arena_arcs"],
+        "capacity_req_per_s": round(cap, 1),
+        "closed_loop_p50_ms": round(float(np.percentile(lat_c, 50)), 3),
+        "poisson_lambda_req_per_s": round(lam, 1),
+        "poisson_throughput_req_per_s": round(n_requests / span_p, 1),
+        "poisson_gteps": round(float(sum(tm[i]["m"] for i in req)) / span_p / 1e9, 3),
+        "p50_ms": round(float(np.percentile(lat_p, 50)), 3),
+        "p99_ms": round(float(np.percentile(lat_p, 99)), 3),
+        "max_active": info["max_active"], "rebases": info["rebases"],
+        "plain_capacity_req_per_s": round(plain_cap, 1),
+        "plain_mean_service_ms": round(float(service.mean()) * 1e3, 4),
+        "plain_at_same_lambda_p50_ms": round(float(np.percentile(plain_same, 50)), 3),
+        "plain_at_same_lambda_p99_ms": round(float(np.percentile(plain_same, 99)), 3),
+        "plain_at_own_80pct_p50_ms": round(float(np.percentile(plain_own, 50)), 3),
+        "plain_at_own_80pct_p99_ms": round(float(np.percentile(plain_own, 99)), 3),
+        "speedup_capacity_vs_plain": round(cap / plain_cap, 2),
+        "identical_to_plain": bool(same_c and same_p),
+    })
+    if small_budget_gib:
+        with ldd.Server(hbm_budget_bytes=int(small_budget_gib * 2**30)) as srv:
+            lat_s, span_s, res_s = serve_run(ldd, srv, tm, req, outs)
+            info_s = srv.info()
+        out["small_budget"] = {"hbm_budget_gib": small_budget_gib, "arena_vertices": info_s["arena_vertices"],
+                               "arena_arcs": info_s["arena_arcs"],
+                               "capacity_req_per_s": round(n_requests / span_s, 1),
+                               "closed_loop_p50_ms": round(float(np.percentile(lat_s, 50)), 3),
+                               "closed_loop_p99_ms": round(float(np.percentile(lat_s, 99)), 3),
+                               "max_active": info_s["max_active"], "identical_to_plain": verify(res_s)}
+    log(f"served: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,6 +315,8 @@ def main():
     ap.add_argument("--workload", default="rmat-24")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--engine", type=int, default=0)
     ap.add_argument("--direction", type=int, default=0)
     ap.add_argument("--blocks", type=int, default=0)
@@ -230,6 +399,9 @@ def main():
         del d_rp, d_ci, d_s, centre
         torch.cuda.empty_cache()
         out["batched"] = run_batched(reps=5)
+    if not args.no_serve:
+        torch.cuda.empty_cache()
+        out["served"] = run_serving(args.serve_requests)
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on rmat-22 ...")
         out["cpu_baseline"] = cpu_baseline()

@@ -154,8 +154,9 @@ ldd_status ldd_decompose_batch(int32_t num_graphs, const int64_t* vtx_off, const
 typedef struct ldd_server ldd_server;
 
 typedef struct {
-  int64_t hbm_budget_bytes; /* arena size in device bytes; split as 40 B per vertex + 4 B per   */
+  int64_t hbm_budget_bytes; /* arena size in device bytes; split as 41 B per vertex + 4 B per   */
                             /* arc for graphs of about 16 arcs per vertex unless max_* are set */
+                            /* (arcs at most 2^31 - 1, the rest to vertices, at most 2^30)     */
   int64_t max_vertices;     /* arena vertices (a request takes n + 1); 0 = from the budget     */
   int64_t max_arcs;         /* arena arcs (a request takes nnz); 0 = from the budget            */
   int32_t max_slots;        /* requests on the device at once, 1..64 (0 = 64)                   */
@@ -180,7 +181,8 @@ typedef struct {
 } ldd_request;
 
 typedef struct {
-  ldd_status status;        /* LDD_OK, LDD_ERR_CANCELLED, or the engine's failure             */
+  ldd_status status;        /* LDD_OK, LDD_ERR_INVALID_ARG / LDD_ERR_OVERFLOW (content),       */
+                            /* LDD_ERR_CANCELLED, or the engine's failure                      */
   int32_t rounds;           /* floor(Delta / 2^20) + 1 of the request                          */
   int64_t cut_edges;        /* edges whose endpoints have different centres                    */
   int64_t first_round;      /* global round its round 0 ran at (numbering at admission)        */
@@ -207,10 +209,14 @@ typedef struct {
  * arena, LDD_ERR_OOM if the arena cannot be allocated. */
 ldd_status ldd_server_create(const ldd_server_config* cfg, ldd_server** out);
 
-/* Validate a request (on the device, after the work queued on req->hip_stream) and queue it.
- * Returns LDD_ERR_INVALID_ARG for bad CSR or shifts, LDD_ERR_BUDGET if it can never fit the
- * arena, LDD_ERR_OVERFLOW if it needs more rounds than the server takes; on LDD_OK *ticket
- * names the request until its result is collected. */
+/* Queue a request.  Only O(1) checks happen here: LDD_ERR_INVALID_ARG for bad sizes or NULL
+ * pointers, LDD_ERR_BUDGET if it can never fit the arena.  On LDD_OK *ticket names the request
+ * until its result is collected.  An event recorded on req->hip_stream orders the request's
+ * admission after the work that stream has queued so far.  The content is checked on the
+ * device at admission: row offsets not non-decreasing from 0 to nnz, a shift outside
+ * [0, 2^52] or a column id outside [0, n) make the result's status LDD_ERR_INVALID_ARG, more
+ * rounds than the server takes (ldd_server_info.max_rounds) LDD_ERR_OVERFLOW; such a request
+ * never disturbs the others. */
 ldd_status ldd_server_submit(ldd_server* srv, const ldd_request* req, uint64_t* ticket);
 
 /* LDD_ERR_PENDING while the request runs; otherwise fills *out, forgets the ticket and returns

@@ -399,6 +399,10 @@ static ldd_status decompose_impl(Workspace& w, const ldd_csr* g, const int64_t* 
   c.slots = nullptr;
   c.nslots = 0;
   c.wake_tab = nullptr;
+  c.vslot = nullptr;
+  c.sst = nullptr;
+  c.s_cnt = nullptr;
+  c.s_lr = nullptr;
   HIP_TRY(hipMemsetAsync(w.ex_part.p, 0, (size_t)RT * sizeof(u64), st));
 
   const int engine = o.engine == LDD_ENGINE_AUTO ? LDD_ENGINE_LAUNCH : o.engine;

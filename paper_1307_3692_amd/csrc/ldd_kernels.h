@@ -43,7 +43,12 @@ struct SlotInfo {
   int R;            // the request's rounds (its wake rounds are r0 .. r0 + R - 1)
   int wbase;        // its round offsets start at wake_tab[wbase] (R + 1 entries)
   int active;
-  int pad;
+  int n;            // the request's vertices
+};
+// Per-slot traversal state after step k (double-buffered by parity, like RoundState).
+struct SlotState {
+  long long ua;   // arcs of the request's vertices not settled yet
+  long long dir;  // direction of the request's round in step k (DIR_TD / DIR_BU; 0 = TD)
 };
 
 // Everything a round step needs, passed by value.
@@ -77,10 +82,15 @@ struct RoundCtx {
   RoundState* host_st;  // pinned host mirror of the latest state (may be null)
   u64* ex_part;     // [G]: arcs examined by each block over all steps (statistics)
   // server mode (slots != null): every step is the next global round, no tail, never "done";
-  // round r's wakers are those of every active slot's local round r - r0
+  // round r's wakers are those of every active slot's local round r - r0; each slot takes its
+  // own direction from its own frontier
   const SlotInfo* slots;
   int nslots;
   const int* wake_tab;
+  const unsigned char* vslot;  // slot of every arena vertex
+  SlotState* sst;              // [2][MAX_SLOTS]
+  u64* s_cnt;                  // [3][MAX_SLOTS]: (count << 32 | arcs) appended by step k, at k % 3
+  u64* s_lr;                   // [3][MAX_SLOTS]: smallest label written by step k, at k % 3
 };
 
 // Arguments of graph-launched steps: step k = kbase + j of a chunk; k_advance moves kbase.
@@ -103,6 +113,7 @@ __global__ void k_wake_scatter(int n, const int* row_ptr, const long long* shift
                                int* wake_ord);
 __global__ void k_fill_u64(u64* p, long long count, u64 value);
 __global__ void k_round_step_lb(const LaunchBlock* lb, int j);
+__global__ void k_round_step_srv(const LaunchBlock* lb, int j);
 __global__ void k_advance(LaunchBlock* lb, int C);
 __global__ void k_rounds_persistent(RoundCtx c);
 __global__ void k_finalize(int n, int B, const int* row_ptr, const u64* P, int* centre, u64* hub_bits, int* lv,

@@ -41,9 +41,6 @@ struct StepShared {
   u64 lr;
   unsigned start;
   u64 red[NW];
-  // server mode: this round's wake segment of every slot (start in wake_ord, prefix of lengths)
-  long long seg_beg[MAX_SLOTS];
-  int seg_off[MAX_SLOTS + 1];
   // top-down window: RT+1 queue entries (arc prefix, first arc in col_idx, offer)
   unsigned w_pre[RT + 1];
   int w_first[RT + 1];
@@ -121,6 +118,44 @@ __device__ __forceinline__ void block_append(AppendBuf& ab, bool want, int v, un
   __syncthreads();
 }
 
+// Server mode: per-slot LDS state of a step.
+struct SrvShared {
+  int sdir[MAX_SLOTS];   // direction of each slot's round in this step
+  u64 sL[MAX_SLOTS];     // each slot's L_r (its smallest possible offer this round)
+  u64 s_cnt[MAX_SLOTS];  // this block's (count << 32 | arcs) appended per slot
+  u64 s_lr[MAX_SLOTS];   // this block's smallest label written per slot
+  // this round's wake segment of every slot (start in wake_ord, prefix of lengths)
+  long long seg_beg[MAX_SLOTS];
+  int seg_off[MAX_SLOTS + 1];
+  // vertex ranges of the slots that go bottom-up (start, prefix of lengths)
+  long long bseg_beg[MAX_SLOTS];
+  int bseg_off[MAX_SLOTS + 1];
+  unsigned char w_slot[RT + 1];  // slot of each staged top-down entry
+  int skip_to;
+  int any_td;  // some slot with a frontier goes top-down
+};
+
+// Per-slot notes of a tile (server mode): the count and arcs of the vertices appended and the
+// smallest label written, summed per slot over the wave, then one LDS atomic per slot present.
+// Called by every lane of the wave (the loop count is wave-uniform).
+__device__ __forceinline__ void slot_note(SrvShared& ss, bool wrote, bool want, int slot, unsigned deg, u64 label) {
+  const bool any = wrote || want;
+  u64 pending = __ballot(any);
+  while (pending) {
+    const int leader = (int)__builtin_ctzll(pending);
+    const int sl = __shfl(slot, leader, WAVE);
+    const bool mine = any && slot == sl;
+    const u64 m = __ballot(mine);
+    const u64 cnt = wave_sum_u64(mine && want ? (((u64)1 << 32) | deg) : 0);
+    const u64 lab = wave_min_u64(mine && wrote ? label : INF);
+    if ((int)lane_id() == leader) {
+      if (cnt) atomicAdd(&ss.s_cnt[sl], cnt);
+      if (lab != INF) atomicMin(&ss.s_lr[sl], lab);
+    }
+    pending &= ~m;
+  }
+}
+
 __device__ __forceinline__ u64 block_min_u64(u64 v, StepShared& sh) {
   v = wave_min_u64(v);
   const unsigned wid = threadIdx.x / WAVE;
@@ -145,8 +180,7 @@ __device__ __forceinline__ u64 own_offer(const RoundCtx& c, int v) {
 // ---- round r: wake bucket r (the delayed source arcs of length in [r, r+1) units) ----------
 // Server mode: the wakers of global round r are, for every active slot with r0 <= r < r0 + R,
 // the vertices of its local round r - r0 (a segment of its part of wake_ord).
-__device__ __forceinline__ void phase_wake_slots(const RoundCtx& c, int r, int k, AppendBuf& ab, StepShared& sh,
-                                                 u64& wmin) {
+__device__ __forceinline__ void phase_wake_slots(const RoundCtx& c, int r, int k, AppendBuf& ab, SrvShared& sh) {
   if (threadIdx.x < WAVE) {
     const int t = threadIdx.x;
     int len = 0;
@@ -172,9 +206,10 @@ __device__ __forceinline__ void phase_wake_slots(const RoundCtx& c, int r, int k
   const int cnt = sh.seg_off[ns];
   for (long long base = (long long)blockIdx.x * RT; base < cnt; base += (long long)gridDim.x * RT) {
     const long long i = base + threadIdx.x;
-    bool want = false;
-    int v = 0;
+    bool want = false, wrote = false;
+    int v = 0, slot = 0;
     unsigned deg = 0;
+    u64 self = INF;
     if (i < cnt) {
       int lo = 0, hi = ns;  // last slot with seg_off <= i
       while (hi - lo > 1) {
@@ -182,12 +217,13 @@ __device__ __forceinline__ void phase_wake_slots(const RoundCtx& c, int r, int k
         if (sh.seg_off[mid] <= i) lo = mid;
         else hi = mid;
       }
+      slot = lo;
       v = c.wake_ord[sh.seg_beg[lo] + (i - sh.seg_off[lo])];
-      const u64 self = own_offer(c, v);
+      self = own_offer(c, v);
       if (c.P[v] > self) {
         const u64 old = atomic_min_u64(&c.P[v], self);
         if (old > self) {
-          wmin = self < wmin ? self : wmin;
+          wrote = true;
           if (old == INF) {
             want = true;
             deg = degree(c, v);
@@ -195,6 +231,7 @@ __device__ __forceinline__ void phase_wake_slots(const RoundCtx& c, int r, int k
         }
       }
     }
+    slot_note(sh, wrote, want, slot, deg, self);
     block_append(ab, want, v, deg, c, k);
   }
 }
@@ -251,9 +288,11 @@ __device__ __forceinline__ void phase_wake(const RoundCtx& c, int r, int k, Appe
 // TAIL = false: round step; an arc appends its far end if it is reached for the first time.
 // TAIL = true: tail sweep `sweep`; an arc appends its far end whenever it lowered the label
 // and the far end is not queued for the next sweep yet.
-template <bool TAIL>
+// SRV: server mode; the entries of slots that go bottom-up this round are skipped, a whole
+// staged window at a time where they are contiguous.
+template <bool TAIL, bool SRV>
 __device__ __forceinline__ void phase_top_down(const RoundCtx& c, int k, const int* qv, const unsigned* qa, unsigned nf, unsigned af,
-                               AppendBuf& ab, StepShared& sh, u64& wmin, unsigned sweep) {
+                               AppendBuf& ab, StepShared& sh, u64& wmin, unsigned sweep, SrvShared* ss) {
   unsigned* w_pre = sh.w_pre;
   int* w_first = sh.w_first;
   u64* w_offer = sh.w_offer;
@@ -273,13 +312,19 @@ __device__ __forceinline__ void phase_top_down(const RoundCtx& c, int k, const i
   }
   __syncthreads();
   unsigned ent = sh.start;
-  for (unsigned tile = a_begin; tile < a_end; tile += RT) {
+  unsigned tile = a_begin;
+  while (tile < a_end) {
     for (int kk = threadIdx.x; kk <= RT; kk += RT) {
       const unsigned e = ent + kk;
       if (e < nf) {
         const int u = qv[e];
         w_pre[kk] = qa[e];
-        const bool ok = (unsigned)u < (unsigned)c.n;
+        bool ok = (unsigned)u < (unsigned)c.n;
+        if (SRV) {
+          const int sl = ok ? c.vslot[u] : 0;
+          ss->w_slot[kk] = (unsigned char)sl;
+          ok = ok && ss->sdir[sl] != DIR_BU;
+        }
         w_first[kk] = ok ? c.row_ptr[u] : 0;
         const u64 pu = ok ? load_u64_relaxed(&c.P[u]) : INF;
         w_offer[kk] = pu == INF ? INF : pu + unit;
@@ -291,9 +336,10 @@ __device__ __forceinline__ void phase_top_down(const RoundCtx& c, int k, const i
     }
     __syncthreads();
     const unsigned a = tile + threadIdx.x;
-    bool want = false;
-    int w = 0;
+    bool want = false, wrote = false;
+    int w = 0, slot = 0;
     unsigned deg = 0;
+    u64 offer = INF;
     if (a < a_end) {
       int lo = 0, hi = RT;  // last kk in [0, RT) with w_pre[kk] <= a
       while (hi - lo > 1) {
@@ -301,7 +347,8 @@ __device__ __forceinline__ void phase_top_down(const RoundCtx& c, int k, const i
         if (w_pre[mid] <= a) lo = mid;
         else hi = mid;
       }
-      const u64 offer = w_offer[lo];
+      offer = w_offer[lo];
+      if (SRV) slot = ss->w_slot[lo];
       const unsigned j = a - w_pre[lo];
       const long long arc = (long long)w_first[lo] + j;
       // j < degree and arc < nnz hold for a symmetric CSR; checked so that malformed input
@@ -320,6 +367,7 @@ __device__ __forceinline__ void phase_top_down(const RoundCtx& c, int k, const i
               }
             } else {
               wmin = offer < wmin ? offer : wmin;
+              wrote = true;
               if (old == INF) {
                 want = true;
                 deg = degree(c, w);
@@ -331,9 +379,10 @@ __device__ __forceinline__ void phase_top_down(const RoundCtx& c, int k, const i
         atomic_or_u32(&c.ctrl->err, ERR_BAD_COL);
       }
     }
+    if (SRV) slot_note(*ss, wrote, want, slot, deg, offer);
     block_append(ab, want, w, deg, c, k);
     // the entry holding the next tile's first arc is one of ent .. ent+RT (all staged)
-    const unsigned next = tile + RT;
+    unsigned next = tile + RT;
     __syncthreads();
     if (threadIdx.x == 0) {
       int lo = 0, hi = RT + 1;
@@ -342,10 +391,33 @@ __device__ __forceinline__ void phase_top_down(const RoundCtx& c, int k, const i
         if (w_pre[mid] <= next) lo = mid;
         else hi = mid;
       }
-      sh.start = ent + lo;
+      sh.start = lo;
+      if (SRV) ss->skip_to = RT;
     }
     __syncthreads();
-    ent = sh.start;
+    if (SRV) {
+      // skipped entries from there on: the next tile starts at the first entry that is not
+      // skipped (or at entry RT, the last one staged)
+      const int lo = (int)sh.start;
+      for (int kk = threadIdx.x; kk < RT; kk += RT)
+        if (kk >= lo && w_offer[kk] != INF) atomicMin(&ss->skip_to, kk);
+      __syncthreads();
+      const int to = ss->skip_to;
+      if (to > lo && w_pre[to] > next) next = w_pre[to];
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        int l2 = lo, h2 = RT + 1;  // the entry holding the (possibly moved) tile start
+        while (h2 - l2 > 1) {
+          const int mid = (l2 + h2) >> 1;
+          if (w_pre[mid] <= next) l2 = mid;
+          else h2 = mid;
+        }
+        sh.start = l2;
+      }
+      __syncthreads();
+    }
+    ent += sh.start;
+    tile = next;
   }
 }
 
@@ -393,6 +465,65 @@ __device__ __forceinline__ void phase_bottom_up(const RoundCtx& c, int r, int k,
         }
       }
     }
+    block_append(ab, want, v, deg, c, k);
+  }
+}
+
+// Server mode: the same pull over the vertex ranges of the slots that go bottom-up this round,
+// each with its own L_r.
+__device__ __forceinline__ void phase_bottom_up_slots(const RoundCtx& c, int r, int k, AppendBuf& ab, SrvShared& ss) {
+  const int B = c.B;
+  const u64 unit = (u64)1 << (FIX + B);
+  const u64 base_r = (u64)r << (FIX + B);
+  const u64 prev_round = (u64)(r - 1);
+  const int ns = c.nslots < MAX_SLOTS ? c.nslots : MAX_SLOTS;
+  const int cnt = ss.bseg_off[ns];
+  for (long long base = (long long)blockIdx.x * RT; base < cnt; base += (long long)gridDim.x * RT) {
+    const long long i = base + threadIdx.x;
+    bool want = false, wrote = false;
+    int v = 0, slot = 0;
+    unsigned deg = 0;
+    u64 best = INF;
+    if (i < cnt) {
+      int lo = 0, hi = ns;  // last slot with bseg_off <= i
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (ss.bseg_off[mid] <= i) lo = mid;
+        else hi = mid;
+      }
+      slot = lo;
+      v = (int)(ss.bseg_beg[lo] + (i - ss.bseg_off[lo]));
+      const u64 Lr = ss.sL[lo];
+      const u64 pv = c.P[v];
+      if (pv >= base_r && pv > Lr) {
+        const int a0 = c.row_ptr[v], a1 = c.row_ptr[v + 1];
+        best = pv;
+        for (int a = a0; a < a1; ++a) {
+          const int u = c.col[a];
+          if ((unsigned)u >= (unsigned)c.n) {
+            atomic_or_u32(&c.ctrl->err, ERR_BAD_COL);
+            break;
+          }
+          const u64 pu = load_u64_relaxed(&c.P[u]);
+          if ((pu >> (FIX + B)) == prev_round && pu != INF) {
+            const u64 offer = pu + unit;
+            if (offer < best) best = offer;
+            if (best <= Lr) break;
+          }
+        }
+        if (best < pv) {
+          const u64 old = atomic_min_u64(&c.P[v], best);
+          if (old > best) {
+            wrote = true;
+            if (old == INF) {
+              want = true;
+              deg = (unsigned)(a1 - a0);
+            }
+          }
+        }
+      }
+    }
+    slot_note(ss, wrote, want, slot, deg, best);
     block_append(ab, want, v, deg, c, k);
   }
 }
@@ -470,6 +601,7 @@ __device__ void store_state(RoundState* p, const RoundState& s) {
 #undef LDD_STORE
 }
 
+template <bool SRV>
 __device__ __forceinline__ RoundState next_state(const RoundCtx& c, int k) {
   const RoundState P = load_state(&c.st[(k - 1) & 1]);
   const u64 out = load_u64_relaxed(qcounter(c, k - 1));
@@ -477,18 +609,12 @@ __device__ __forceinline__ RoundState next_state(const RoundCtx& c, int k) {
   S.seq = k;
   if (P.mode == MODE_DONE) return S;
   const unsigned nf = min((unsigned)(out >> 32), (unsigned)c.n), af = (unsigned)out;
-  if (c.slots) {  // server: the next global round, always
+  if (SRV) {  // server: the next global round, always (directions are per slot)
     S.settled += nf;
-    S.unsettled_arcs -= af;
     S.rounds += 1;
     S.max_frontier = (long long)nf > S.max_frontier ? (long long)nf : S.max_frontier;
-    if (P.prev >> 32) {
-      S.td_rounds += P.dir == DIR_TD;
-      S.bu_rounds += P.dir == DIR_BU;
-    }
     S.round = P.round + 1;
     S.prev = (long long)out;
-    S.dir = nf ? choose_dir(c, (int)P.dir, nf, af, (u64)S.unsettled_arcs) : P.dir;
     return S;
   }
   if (P.mode == MODE_ROUNDS) {
@@ -543,22 +669,90 @@ __device__ __forceinline__ void add_examined(const RoundCtx& c, u64 examined, St
   }
 }
 
+// Server mode, start of step k (wave 0, one lane per slot): each slot's direction for this
+// round from its own frontier (the notes of step k-1), as choose_dir decides for one graph,
+// its L_r, the ranges that go bottom-up; block 0 records the slots' state after step k.
+__device__ __forceinline__ void slot_setup(const RoundCtx& c, int k, SrvShared& ss) {
+  if (threadIdx.x >= WAVE) return;
+  const int s = threadIdx.x;  // MAX_SLOTS == WAVE
+  int dir = DIR_TD, bu_len = 0;
+  long long bu_beg = 0;
+  u64 L = INF, nf = 0;
+  if (s < c.nslots) {
+    const SlotInfo sl = c.slots[s];
+    const SlotState p = c.sst[((k - 1) & 1) * MAX_SLOTS + s];
+    const u64 cnt = c.s_cnt[((k - 1) % 3) * MAX_SLOTS + s];
+    const u64 lr = c.s_lr[((k - 1) % 3) * MAX_SLOTS + s];
+    nf = cnt >> 32;
+    const u64 af = cnt & 0xffffffffull;
+    const long long ua = p.ua - (long long)af;
+    if (sl.active && nf) {
+      if (c.dir_policy == DIR_TD || c.dir_policy == DIR_BU) {
+        dir = c.dir_policy;
+      } else {
+        const u64 n = (u64)sl.n;
+        const bool bu_better = af * (u64)c.td_to_bu > (u64)(ua > 0 ? ua : 0) + n / 4;
+        dir = (p.dir == DIR_BU) ? ((bu_better || nf * (u64)c.bu_to_td >= n) ? DIR_BU : DIR_TD)
+                                : (bu_better ? DIR_BU : DIR_TD);
+      }
+    }
+    L = lr == INF ? INF : lr + ((u64)1 << (FIX + c.B));
+    if (dir == DIR_BU) {
+      bu_len = sl.n;
+      bu_beg = sl.vbeg;
+    }
+    if (blockIdx.x == 0) {
+      SlotState q;
+      q.ua = ua;
+      q.dir = dir;
+      c.sst[(k & 1) * MAX_SLOTS + s] = q;
+      c.s_cnt[((k + 1) % 3) * MAX_SLOTS + s] = 0;
+      c.s_lr[((k + 1) % 3) * MAX_SLOTS + s] = INF;
+    }
+  }
+  const u64 td_front = __ballot(dir == DIR_TD && nf > 0);
+  const unsigned incl = wave_incl_scan((unsigned)bu_len);
+  ss.sdir[s] = dir;
+  ss.sL[s] = L;
+  ss.s_cnt[s] = 0;
+  ss.s_lr[s] = INF;
+  ss.bseg_beg[s] = bu_beg;
+  ss.bseg_off[s + 1] = (int)incl;
+  if (s == 0) {
+    ss.bseg_off[0] = 0;
+    ss.any_td = td_front != 0;
+  }
+}
+
+// Server mode, end of step k: the block's per-slot notes into the step's counters.
+__device__ __forceinline__ void slot_flush(const RoundCtx& c, int k, SrvShared& ss) {
+  __syncthreads();
+  const int s = threadIdx.x;
+  if (s < MAX_SLOTS && s < c.nslots) {
+    if (ss.s_cnt[s]) atomic_add_u64(&c.s_cnt[(k % 3) * MAX_SLOTS + s], ss.s_cnt[s]);
+    if (ss.s_lr[s] != INF) atomic_min_u64(&c.s_lr[(k % 3) * MAX_SLOTS + s], ss.s_lr[s]);
+  }
+}
+
 // One step; returns the mode it ran in (MODE_DONE: nothing was left to do).
-__device__ __forceinline__ int round_step(const RoundCtx& c, int k, AppendBuf& ab, StepShared& sh) {
+// SRV: server mode (the next global round over all slots, each in its own direction).
+template <bool SRV>
+__device__ __forceinline__ int round_step(const RoundCtx& c, int k, AppendBuf& ab, StepShared& sh, SrvShared* ss) {
   if (threadIdx.x == 0) {
     // Once a step has written "done" into either slot no step writes a slot again, so later
     // steps only need the two mode words to leave.
-    const bool done = __hip_atomic_load(&c.st[0].mode, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == MODE_DONE ||
-                      __hip_atomic_load(&c.st[1].mode, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == MODE_DONE;
+    const bool done = !SRV && (__hip_atomic_load(&c.st[0].mode, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == MODE_DONE ||
+                               __hip_atomic_load(&c.st[1].mode, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == MODE_DONE);
     if (done) {
       sh.S.mode = MODE_DONE;
       sh.S.seq = -1;
     } else {
-      sh.S = next_state(c, k);
+      sh.S = next_state<SRV>(c, k);
     }
     ab.n = 0;
     ab.arcs = 0;
   }
+  if (SRV) slot_setup(c, k, *ss);
   __syncthreads();
   const RoundState S = sh.S;
   if (S.seq < 0) return MODE_DONE;
@@ -574,6 +768,15 @@ __device__ __forceinline__ int round_step(const RoundCtx& c, int k, AppendBuf& a
   const int* qv = c.qv[(k - 1) & 1];
   const unsigned* qa = c.qa[(k - 1) & 1];
   u64 wmin = INF, examined = 0;
+  if (SRV) {
+    const int r = (int)S.round;
+    phase_wake_slots(c, r, k, ab, *ss);
+    if (nf && ss->any_td) phase_top_down<false, true>(c, k, qv, qa, nf, af, ab, sh, wmin, 0, ss);
+    if (ss->bseg_off[MAX_SLOTS]) phase_bottom_up_slots(c, r, k, ab, *ss);
+    block_flush(ab, c, k);
+    slot_flush(c, k, *ss);
+    return MODE_ROUNDS;
+  }
   const bool need_lr = nf && ((S.mode == MODE_ROUNDS && S.dir == DIR_BU) || (S.mode == MODE_TAIL && S.round == 0));
   if (need_lr) {
     // L_r: the smallest offer of F_{r-1}, from the per-block minima the previous step left
@@ -588,13 +791,12 @@ __device__ __forceinline__ int round_step(const RoundCtx& c, int k, AppendBuf& a
   }
   if (S.mode == MODE_ROUNDS) {
     const int r = (int)S.round;
-    if (c.slots) phase_wake_slots(c, r, k, ab, sh, wmin);
-    else phase_wake(c, r, k, ab, wmin);
+    phase_wake(c, r, k, ab, wmin);
     if (nf) {
       if (S.dir == DIR_BU) {
         phase_bottom_up(c, r, k, sh.lr, ab, wmin, examined);
       } else {
-        phase_top_down<false>(c, k, qv, qa, nf, af, ab, sh, wmin, 0);
+        phase_top_down<false, false>(c, k, qv, qa, nf, af, ab, sh, wmin, 0, nullptr);
         if (blockIdx.x == 0 && threadIdx.x == 0) examined += af;
       }
     }
@@ -603,7 +805,7 @@ __device__ __forceinline__ int round_step(const RoundCtx& c, int k, AppendBuf& a
     if (sweep == 0) {
       phase_tail_seed(c, (int)S.tail_round, k, nf ? sh.lr : INF, ab, examined);
     } else if (nf) {
-      phase_top_down<true>(c, k, qv, qa, nf, af, ab, sh, wmin, sweep);
+      phase_top_down<true, false>(c, k, qv, qa, nf, af, ab, sh, wmin, sweep, nullptr);
       if (blockIdx.x == 0 && threadIdx.x == 0) examined += af;
     }
   }
@@ -618,7 +820,15 @@ __device__ __forceinline__ int round_step(const RoundCtx& c, int k, AppendBuf& a
 __global__ __launch_bounds__(RT, 8) void k_round_step_lb(const LaunchBlock* __restrict__ lb, int j) {
   __shared__ AppendBuf ab;
   __shared__ StepShared sh;
-  round_step(lb->c, (int)(lb->kbase + j), ab, sh);
+  round_step<false>(lb->c, (int)(lb->kbase + j), ab, sh, nullptr);
+}
+
+// The server's step: the next global round over every admitted request.
+__global__ __launch_bounds__(RT, 8) void k_round_step_srv(const LaunchBlock* __restrict__ lb, int j) {
+  __shared__ AppendBuf ab;
+  __shared__ StepShared sh;
+  __shared__ SrvShared ss;
+  round_step<true>(lb->c, (int)(lb->kbase + j), ab, sh, &ss);
 }
 
 __global__ void k_advance(LaunchBlock* lb, int C) {
@@ -632,7 +842,7 @@ __global__ __launch_bounds__(RT) void k_rounds_persistent(RoundCtx c) {
   u64 gen = 0;
   const long long kmax = (long long)c.R + c.n + 2;
   for (int k = 1; k <= kmax; ++k) {
-    if (round_step(c, k, ab, sh) == MODE_DONE) break;
+    if (round_step<false>(c, k, ab, sh, nullptr) == MODE_DONE) break;
     grid_sync(&c.ctrl->bar, gridDim.x, gen, &c.ctrl->err);
     if (__hip_atomic_load(&c.ctrl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & (ERR_BARRIER | ERR_QUEUE)) break;
   }

@@ -9,14 +9,16 @@
 // and its round rho runs at global round r0 + rho.  It is complete once global round r0 + R - 1,
 // its last wake round, has run.
 //
-// Requests join and leave between step chunks: admission (copy into the arena, wake-round sort),
-// slot-table changes and result extraction are enqueued on the engine stream between graph
-// replays, so they take effect at a round boundary without draining the device.  Keys grow with
-// the global round; when they approach the label's key range, all live keys are lowered by the
-// same number of rounds (a rebase), again between chunks.
+// Requests join and leave between step chunks.  Admission (validation, copy into the arena,
+// wake-round sort) and finishing (centres, cut, report) each run as a few kernels for a whole
+// batch of requests, their descriptors passed as kernel arguments, enqueued on the engine stream
+// between graph replays; results reach the host through mapped memory.  So the host cost per
+// engine iteration does not grow with the number of requests that join or leave.  Keys grow
+// with the global round; when they approach the label's key range, all live keys are lowered
+// by the same number of rounds (a rebase), again between chunks.
 //
-// One engine thread owns the engine stream; submit, poll, wait and cancel touch host queues (and
-// submit validates the request on a stream of its own).
+// One engine thread owns the engine stream; submit, poll, wait and cancel touch host queues
+// (submit also records an event on the caller's stream, which admission waits for).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -37,137 +39,289 @@
 namespace ldd {
 
 constexpr u64 S_ONE = (u64)1 << FIX;
-constexpr int CHECK_BLOCKS = 512;
+constexpr int MAX_BATCH = 16;         // requests per admission / finishing launch
+constexpr int ADM_T = 1024;           // threads of the admission kernels
+constexpr int FIN_T = 256;            // threads of the finishing kernel (its arc tile)
+constexpr unsigned ERR_ROUNDS = 64u;  // the request needs more rounds than the server takes
+constexpr unsigned ROW_ERRS = ERR_BAD_SHIFT | ERR_BAD_ROWPTR;
+
+// One request of an admission batch.  Block j of the item (j < nblk) owns vertices
+// [n j / nblk, n (j+1) / nblk) and arcs [nnz j / nblk, nnz (j+1) / nblk).
+struct AdmItem {
+  const int* rp;
+  const int* col;
+  const long long* shift;
+  long long vbeg, abeg, nnz, r0;
+  int n, slot, blk0, nblk;
+};
+struct AdmBatch {
+  AdmItem it[MAX_BATCH];
+  int count;
+};
+
+struct FinItem {
+  int* centre;
+  long long vbeg, abeg, nnz;
+  int n, slot, blk0, nblk;
+};
+struct FinBatch {
+  FinItem it[MAX_BATCH];
+  int count;
+};
+
+// Per-slot report in mapped host memory.  Admission writes adm_err then R (release), finishing
+// writes cut and fin_err then done (release); the host clears R and done before reuse.
+struct SlotReport {
+  long long R;     // rounds of the request once admitted (0: not runnable), -1 until then
+  long long cut;   // cut edges
+  long long done;  // 1 once cut and fin_err are written
+  unsigned adm_err, fin_err;
+};
+
+template <typename Batch>
+__device__ __forceinline__ int item_of(const Batch& b, int blk) {
+  int i = b.count - 1;
+  while (i > 0 && blk < b.it[i].blk0) --i;
+  return i;
+}
+
+__device__ __forceinline__ long long chunk(long long total, int j, int nb) { return total * j / nb; }
+
+// the request's rounds and whether its rows and shifts passed the check (column errors do not
+// stop a request: such columns were redirected inside the slot and only its status changes)
+__device__ __forceinline__ int request_rounds(u64 delta, unsigned err, int max_rounds) {
+  const u64 R = (delta >> FIX) + 1;
+  return ((err & ROW_ERRS) == 0 && R <= (u64)max_rounds) ? (int)R : 0;
+}
+
+__device__ __forceinline__ u64 block_max_or(u64 v, u64* red, bool is_or) {
+  if (is_or) {
+    v = wave_max_u64(v & ERR_BAD_SHIFT) | wave_max_u64(v & ERR_BAD_ROWPTR);
+  } else {
+    v = wave_max_u64(v);
+  }
+  if (lane_id() == 0) red[threadIdx.x / WAVE] = v;
+  __syncthreads();
+  u64 r = 0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x / WAVE); ++w) r = is_or ? (r | red[w]) : (red[w] > r ? red[w] : r);
+  __syncthreads();
+  return r;
+}
 
 // ------------------------------------------------------------------------------------------
-// slot kernels
+// admission: check -> load (+ round histogram) -> commit (round offsets, slot entry) -> place
 // ------------------------------------------------------------------------------------------
-// Validation of a request before it is queued: shifts in [0, 2^52], row offsets from 0 to nnz
-// and non-decreasing, column ids in [0, n).  Block b leaves its maximum shift and error bits in
-// part[2b], part[2b+1].
-__global__ __launch_bounds__(256) void k_req_check(int n, long long nnz, const int* __restrict__ rp,
-                                                   const int* __restrict__ col, const long long* __restrict__ shift,
-                                                   u64* __restrict__ part) {
-  __shared__ u64 red[2][4];
+// Rows non-decreasing from 0 to nnz, shifts in [0, 2^52]; the request's max shift.
+__global__ __launch_bounds__(ADM_T) void k_adm_check(AdmBatch b, u64* __restrict__ adm_max,
+                                                     unsigned* __restrict__ adm_err) {
+  __shared__ u64 red[ADM_T / WAVE];
+  const AdmItem& t = b.it[item_of(b, blockIdx.x)];
+  const int j = blockIdx.x - t.blk0;
+  const long long lo = chunk(t.n, j, t.nblk), hi = chunk(t.n, j + 1, t.nblk);
   u64 mx = 0, bad = 0;
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  const long long items = (long long)n > nnz ? (long long)n : nnz;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < items; i += stride) {
-    if (i < n) {
-      const int a = rp[i], b = rp[i + 1];
-      if (b < a || (i == 0 && a != 0) || (i == n - 1 && (long long)b != nnz)) bad |= ERR_BAD_ROWPTR;
-      const long long s = shift[i];
-      if (s < 0 || s > (1ll << 52)) bad |= ERR_BAD_SHIFT;
-      else mx = (u64)s > mx ? (u64)s : mx;
+  for (long long v = lo + threadIdx.x; v < hi; v += ADM_T) {
+    const int a = t.rp[v], e = t.rp[v + 1];
+    if (e < a || (v == 0 && a != 0) || (v == t.n - 1 && (long long)e != t.nnz)) bad |= ERR_BAD_ROWPTR;
+    const long long s = t.shift[v];
+    if (s < 0 || s > (1ll << 52)) bad |= ERR_BAD_SHIFT;
+    else mx = (u64)s > mx ? (u64)s : mx;
+  }
+  mx = block_max_or(mx, red, false);
+  bad = block_max_or(bad, red, true);
+  if (threadIdx.x == 0) {
+    if (mx) atomic_max_u64(&adm_max[t.slot], mx);
+    if (bad) atomic_or_u32(&adm_err[t.slot], (unsigned)bad);
+  }
+}
+
+// The request's CSR into the arena: global row offsets and column ids, shifts stored as
+// C - (Delta_g - shift + r0 2^20), so that the engine's C - shift is the request's source-arc
+// length; labels INF for vertices with arcs, their own offer for isolated ones.  Vertex n of
+// the slot is a separator closing the last row: settled (label 0) and never woken.  A column id
+// outside [0, n) is redirected to the separator (every access stays inside the slot) and flags
+// the request.  A request whose rows or shifts failed the check gets empty rows and settled
+// labels: it stays inert.  Also counts the request's vertices per wake round.
+__global__ __launch_bounds__(ADM_T) void k_adm_load(AdmBatch b, u64 C, int B, int max_rounds,
+                                                    const u64* __restrict__ adm_max, unsigned* __restrict__ adm_err,
+                                                    int* __restrict__ rp_g, int* __restrict__ col_g,
+                                                    long long* __restrict__ shift_g, u64* __restrict__ P,
+                                                    unsigned char* __restrict__ vslot, unsigned* __restrict__ cnt) {
+  __shared__ unsigned h[QCAP];
+  __shared__ int any_bad;
+  const AdmItem& t = b.it[item_of(b, blockIdx.x)];
+  const int j = blockIdx.x - t.blk0;
+  const u64 delta = adm_max[t.slot];
+  const int R = request_rounds(delta, adm_err[t.slot], max_rounds);
+  for (int r = threadIdx.x; r < R; r += ADM_T) h[r] = 0;
+  if (threadIdx.x == 0) any_bad = 0;
+  __syncthreads();
+  const long long lo = chunk(t.n, j, t.nblk), hi = chunk(t.n, j + 1, t.nblk);
+  for (long long v = lo + threadIdx.x; v < hi; v += ADM_T) {
+    const long long g = t.vbeg + v;
+    vslot[g] = (unsigned char)t.slot;
+    if (R) {
+      const int a = t.rp[v], e = t.rp[v + 1];
+      const u64 sv = (u64)t.shift[v];
+      const u64 off = delta - sv + (u64)t.r0 * S_ONE;
+      rp_g[g] = (int)(t.abeg + a);
+      shift_g[g] = (long long)(C - off);
+      P[g] = e > a ? INF : ((off << B) | (u64)g);
+      if (e > a) atomicAdd(&h[(delta - sv) >> FIX], 1u);
+    } else {
+      rp_g[g] = (int)t.abeg;
+      shift_g[g] = (long long)C;
+      P[g] = 0;
     }
-    if (i < nnz && (unsigned)col[i] >= (unsigned)n) bad |= ERR_BAD_COL;
   }
-  mx = wave_max_u64(mx);
-  // the OR over the wave, one error kind at a time (each a max over 0 / that bit)
-  const u64 bits = wave_max_u64(bad & ERR_BAD_SHIFT) | wave_max_u64(bad & ERR_BAD_ROWPTR) |
-                   wave_max_u64(bad & ERR_BAD_COL);
-  if (lane_id() == 0) {
-    red[0][threadIdx.x / WAVE] = mx;
-    red[1][threadIdx.x / WAVE] = bits;
+  if (j == t.nblk - 1 && threadIdx.x == 0) {
+    vslot[t.vbeg + t.n] = (unsigned char)t.slot;
+    rp_g[t.vbeg + t.n] = (int)(t.abeg + (R ? t.nnz : 0));
+    shift_g[t.vbeg + t.n] = (long long)C;
+    P[t.vbeg + t.n] = 0;
   }
+  if (R) {
+    const long long alo = chunk(t.nnz, j, t.nblk), ahi = chunk(t.nnz, j + 1, t.nblk);
+    for (long long a = alo + threadIdx.x; a < ahi; a += ADM_T) {
+      int c = t.col[a];
+      if ((unsigned)c >= (unsigned)t.n) {
+        c = t.n;
+        any_bad = 1;
+      }
+      col_g[t.abeg + a] = (int)(t.vbeg + c);
+    }
+  }
+  __syncthreads();
+  unsigned* row = cnt + (size_t)t.slot * max_rounds;
+  for (int r = threadIdx.x; r < R; r += ADM_T)
+    if (h[r]) atomicAdd(&row[r], h[r]);
+  if (threadIdx.x == 0 && any_bad) atomic_or_u32(&adm_err[t.slot], ERR_BAD_COL);
+}
+
+// One block per request: round offsets (wake_tab row of the slot, R + 1 entries) and the place
+// cursors from the counts (which are cleared for the next occupant), the slot's table entry,
+// the engine state's unsettled arcs, and the report (adm_err, then R).
+__global__ __launch_bounds__(ADM_T) void k_adm_commit(AdmBatch b, int max_rounds, const u64* __restrict__ adm_max,
+                                                      unsigned* __restrict__ adm_err, unsigned* __restrict__ cnt,
+                                                      unsigned* __restrict__ cur, int* __restrict__ wake_tab,
+                                                      SlotInfo* __restrict__ slots, RoundState* st, long long k_last,
+                                                      SlotState* __restrict__ sst, u64* __restrict__ s_cnt,
+                                                      u64* __restrict__ s_lr, SlotReport* rep) {
+  __shared__ unsigned part[ADM_T];
+  const AdmItem& t = b.it[blockIdx.x];
+  const u64 delta = adm_max[t.slot];
+  const unsigned err = adm_err[t.slot];
+  const int R = request_rounds(delta, err, max_rounds);
+  unsigned* crow = cnt + (size_t)t.slot * max_rounds;
+  unsigned* urow = cur + (size_t)t.slot * max_rounds;
+  int* wrow = wake_tab + (size_t)t.slot * (max_rounds + 1);
+  const int per = (R + ADM_T - 1) / ADM_T;
+  const int lo = threadIdx.x * per, hi = min(R, lo + per);
+  unsigned s = 0;
+  for (int r = lo; r < hi; ++r) s += crow[r];
+  part[threadIdx.x] = s;
   __syncthreads();
   if (threadIdx.x == 0) {
-    u64 m = 0, e = 0;
-    for (int w = 0; w < 4; ++w) {
-      m = red[0][w] > m ? red[0][w] : m;
-      e |= red[1][w];
+    unsigned acc = 0;
+    for (int i = 0; i < ADM_T; ++i) {
+      const unsigned x = part[i];
+      part[i] = acc;
+      acc += x;
     }
-    part[2 * blockIdx.x] = m;
-    part[2 * blockIdx.x + 1] = e;
+    wrow[R] = (int)acc;
+  }
+  __syncthreads();
+  unsigned acc = part[threadIdx.x];
+  for (int r = lo; r < hi; ++r) {
+    const unsigned x = crow[r];
+    wrow[r] = (int)acc;
+    urow[r] = acc;
+    crow[r] = 0;
+    acc += x;
+  }
+  if (threadIdx.x == 0) {
+    SlotInfo e;
+    e.vbeg = t.vbeg;
+    e.r0 = t.r0;
+    e.R = R;
+    e.wbase = t.slot * (max_rounds + 1);
+    e.active = R > 0;
+    e.n = t.n;
+    slots[t.slot] = e;
+    if (R) atomic_add_u64((u64*)&st[k_last & 1].unsettled_arcs, (u64)t.nnz);
+    // the slot's traversal state as step k_last + 1 reads it: all arcs unsettled, no frontier
+    SlotState q;
+    q.ua = t.nnz;
+    q.dir = DIR_TD;
+    sst[(k_last & 1) * MAX_SLOTS + t.slot] = q;
+    s_cnt[(k_last % 3) * MAX_SLOTS + t.slot] = 0;
+    s_lr[(k_last % 3) * MAX_SLOTS + t.slot] = INF;
+    // too many rounds: the request is inert, and its finishing reports why
+    const unsigned rerr = err | (((delta >> FIX) + 1 > (u64)max_rounds && !(err & ROW_ERRS)) ? ERR_ROUNDS : 0u);
+    if (rerr != err) adm_err[t.slot] = rerr;
+    __hip_atomic_store(&rep[t.slot].adm_err, rerr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&rep[t.slot].R, (long long)R, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
 
-// A request's CSR (local ids) into the arena: global row offsets and column ids, shifts stored
-// as C - (Delta_g - shift + r0 2^20), so that the engine's C - shift is the request's source-arc
-// length; labels INF for vertices with arcs and their own offer for isolated ones.  Vertex n of
-// the slot is a separator closing the last row: settled (label 0) and never woken.
-__global__ __launch_bounds__(256) void k_slot_load(long long vbeg, int n, long long abeg, long long nnz,
-                                                   const int* __restrict__ s_rp, const int* __restrict__ s_col,
-                                                   const long long* __restrict__ s_shift, u64 delta_s, long long r0,
-                                                   u64 C, int B, int* __restrict__ rp_g, int* __restrict__ col_g,
-                                                   long long* __restrict__ shift_g, u64* __restrict__ P) {
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  const long long items = (long long)n + 1 > nnz ? (long long)n + 1 : nnz;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < items; i += stride) {
-    if (i < n) {
-      const int a = s_rp[i], b = s_rp[i + 1];
-      const u64 off = delta_s - (u64)s_shift[i] + (u64)r0 * S_ONE;
-      rp_g[vbeg + i] = (int)(abeg + a);
-      shift_g[vbeg + i] = (long long)(C - off);
-      P[vbeg + i] = b > a ? INF : ((off << B) | (u64)(vbeg + i));
-    } else if (i == n) {
-      rp_g[vbeg + n] = (int)(abeg + nnz);
-      shift_g[vbeg + n] = (long long)C;
-      P[vbeg + n] = 0;
-    }
-    if (i < nnz) col_g[abeg + i] = (int)(vbeg + s_col[i]);
-  }
-}
-
-// Per-block LDS histogram of the local wake rounds rho = (Delta_g - shift) >> 20 of the slot's
-// vertices with arcs; block b owns [b n / G, (b+1) n / G).  mat[rho * G + b] as in k_init.
-__global__ __launch_bounds__(1024) void k_slot_hist(int n, int R, const int* __restrict__ s_rp,
-                                                    const long long* __restrict__ s_shift, u64 delta_s,
-                                                    unsigned* __restrict__ mat, int* __restrict__ qmax) {
-  __shared__ unsigned h[QCAP];
-  for (int i = threadIdx.x; i < R; i += blockDim.x) h[i] = 0;
-  __syncthreads();
-  const long long lo = (long long)n * blockIdx.x / gridDim.x, hi = (long long)n * (blockIdx.x + 1) / gridDim.x;
-  for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x)
-    if (s_rp[i + 1] > s_rp[i]) atomicAdd(&h[(delta_s - (u64)s_shift[i]) >> FIX], 1u);
-  __syncthreads();
-  const unsigned G = gridDim.x;
-  for (int r = threadIdx.x; r < R; r += blockDim.x) mat[(size_t)r * G + blockIdx.x] = h[r];
-  if (threadIdx.x == 0) qmax[blockIdx.x] = R - 1;
-}
-
-// Each vertex with arcs to its round's segment: roff[rho] + mat[rho * G + b] + rank in block b.
-__global__ __launch_bounds__(1024) void k_slot_place(int n, int R, long long vbeg, const int* __restrict__ s_rp,
-                                                     const long long* __restrict__ s_shift, u64 delta_s,
-                                                     const unsigned* __restrict__ mat, const int* __restrict__ roff,
+// Each vertex with arcs to its wake round's segment of the slot's part of wake_ord.
+__global__ __launch_bounds__(ADM_T) void k_adm_place(AdmBatch b, int max_rounds, const u64* __restrict__ adm_max,
+                                                     const unsigned* __restrict__ adm_err, unsigned* __restrict__ cur,
                                                      int* __restrict__ wake_ord) {
-  __shared__ unsigned cur[QCAP];
-  const unsigned G = gridDim.x;
-  for (int r = threadIdx.x; r < R; r += blockDim.x) cur[r] = (unsigned)roff[r] + mat[(size_t)r * G + blockIdx.x];
+  __shared__ unsigned h[QCAP];
+  const AdmItem& t = b.it[item_of(b, blockIdx.x)];
+  const int j = blockIdx.x - t.blk0;
+  const u64 delta = adm_max[t.slot];
+  const int R = request_rounds(delta, adm_err[t.slot], max_rounds);
+  if (R == 0) return;  // whole block leaves together
+  for (int r = threadIdx.x; r < R; r += ADM_T) h[r] = 0;
   __syncthreads();
-  const long long lo = (long long)n * blockIdx.x / gridDim.x, hi = (long long)n * (blockIdx.x + 1) / gridDim.x;
-  for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x)
-    if (s_rp[i + 1] > s_rp[i])
-      wake_ord[vbeg + atomicAdd(&cur[(delta_s - (u64)s_shift[i]) >> FIX], 1u)] = (int)(vbeg + i);
+  const long long lo = chunk(t.n, j, t.nblk), hi = chunk(t.n, j + 1, t.nblk);
+  for (long long v = lo + threadIdx.x; v < hi; v += ADM_T)
+    if (t.rp[v + 1] > t.rp[v]) atomicAdd(&h[(delta - (u64)t.shift[v]) >> FIX], 1u);
+  __syncthreads();
+  unsigned* urow = cur + (size_t)t.slot * max_rounds;
+  for (int r = threadIdx.x; r < R; r += ADM_T)
+    if (h[r]) h[r] = atomicAdd(&urow[r], h[r]);
+  __syncthreads();
+  for (long long v = lo + threadIdx.x; v < hi; v += ADM_T)
+    if (t.rp[v + 1] > t.rp[v]) {
+      const unsigned pos = atomicAdd(&h[(delta - (u64)t.shift[v]) >> FIX], 1u);
+      wake_ord[t.vbeg + pos] = (int)(t.vbeg + v);
+    }
 }
 
-// Centre (request-local id) of every vertex of a finished slot, into the caller's buffer.
-__global__ __launch_bounds__(256) void k_slot_final(long long vbeg, int n, int B, const u64* __restrict__ P,
-                                                    int* __restrict__ centre) {
-  const u64 mask = ((u64)1 << B) - 1;
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-    centre[i] = (int)((P[vbeg + i] & mask) - (u64)vbeg);
-}
-
-// Arcs of a finished slot whose ends have different centres (twice the cut edges).  The slot's
-// nnz arcs are split evenly over the grid; a block walks its range in tiles of 256 arcs with a
-// window of row offsets in LDS (rows of degree 0 can end a window before the tile; the walk
-// then moves the window).  Row offsets are arena arc indices.
-__global__ __launch_bounds__(256) void k_slot_cut(long long vbeg, int n, long long abeg, long long nnz,
-                                                  const int* __restrict__ rp_g, const int* __restrict__ col_g,
-                                                  const int* __restrict__ centre, u64* __restrict__ out) {
-  constexpr int T = 256;
+// ------------------------------------------------------------------------------------------
+// finishing: centres + cut -> report
+// ------------------------------------------------------------------------------------------
+// Centres (request-local ids) of the block's vertices into the caller's buffer, and the arcs
+// of the block's arc range whose ends have different centres.  The arc range is walked in tiles
+// of FIN_T arcs with a window of row offsets in LDS (rows of degree 0 can end a window before
+// the tile; the walk then moves the window).  Centres compare as the labels' id bits.
+__global__ __launch_bounds__(FIN_T) void k_fin(FinBatch b, int B, const u64* __restrict__ P,
+                                               const int* __restrict__ rp_g, const int* __restrict__ col_g,
+                                               const SlotInfo* __restrict__ slots, u64* __restrict__ cut_acc) {
+  constexpr int T = FIN_T;
   __shared__ long long w_rp[T + 1];
   __shared__ int s_v;
-  __shared__ u64 red[4];
-  const int* rp = rp_g + vbeg;  // n + 1 entries (the separator closes the last row)
-  const long long G = gridDim.x;
-  const long long a_begin = nnz * blockIdx.x / G, a_end = nnz * (blockIdx.x + 1) / G;
+  __shared__ u64 red[T / WAVE];
+  const FinItem& t = b.it[item_of(b, blockIdx.x)];
+  const int j = blockIdx.x - t.blk0;
+  const u64 mask = ((u64)1 << B) - 1;
+  const long long vlo = chunk(t.n, j, t.nblk), vhi = chunk(t.n, j + 1, t.nblk);
+  // a request that failed its check never ran (its columns were not even copied in)
+  const bool ran = slots[t.slot].active != 0;
+  for (long long v = vlo + threadIdx.x; v < vhi; v += T)
+    t.centre[v] = ran ? (int)((P[t.vbeg + v] & mask) - (u64)t.vbeg) : -1;
+  const int n = t.n;
+  const long long nnz = t.nnz, abeg = t.abeg;
+  const int* rp = rp_g + t.vbeg;  // n + 1 entries (the separator closes the last row)
+  const u64* Ps = P + t.vbeg;
+  const long long a_begin = ran ? chunk(nnz, j, t.nblk) : 0, a_end = ran ? chunk(nnz, j + 1, t.nblk) : 0;
   u64 cut = 0;
-  if (a_begin < a_end) {
+  if (a_begin < a_end) {  // uniform over the block
     if (threadIdx.x == 0) {
-      int lo = 0, hi = n;  // the last row v with start <= a_begin
+      int lo = 0, hi = n;  // the last row with start <= a_begin
       while (hi - lo > 1) {
         const int mid = (int)(((unsigned)lo + (unsigned)hi) >> 1);
         if (rp[mid] - abeg <= a_begin) lo = mid;
@@ -193,8 +347,7 @@ __global__ __launch_bounds__(256) void k_slot_cut(long long vbeg, int n, long lo
           if (w_rp[mid] <= a) lo = mid;
           else hi = mid;
         }
-        const int w = col_g[abeg + a] - (int)vbeg;
-        cut += centre[w] != centre[v0 + lo];
+        cut += (P[col_g[abeg + a]] & mask) != (Ps[v0 + lo] & mask);
       }
       __syncthreads();
       if (t_end >= win_end && t_end < a_end) {
@@ -232,18 +385,28 @@ __global__ __launch_bounds__(256) void k_slot_cut(long long vbeg, int n, long lo
   if (lane_id() == 0) red[threadIdx.x / WAVE] = cut;
   __syncthreads();
   if (threadIdx.x == 0) {
-    const u64 t = red[0] + red[1] + red[2] + red[3];
-    if (t) atomic_add_u64(out, t);
+    u64 s = 0;
+    for (int w = 0; w < T / WAVE; ++w) s += red[w];
+    if (s) atomic_add_u64(&cut_acc[t.slot], s);
   }
 }
 
-__global__ void k_set_slot(SlotInfo* table, int s, SlotInfo e) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) table[s] = e;
-}
-
-// The engine's latest state (after step k_last) gains a new request's arcs.
-__global__ void k_state_add(RoundState* st, long long k_last, long long arcs) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) st[k_last & 1].unsettled_arcs += arcs;
+// One thread per finished request: the report (cut, error bits, then done), and the slot's
+// per-request state cleared for the next occupant.
+__global__ void k_fin_out(FinBatch b, u64* __restrict__ cut_acc, unsigned* __restrict__ adm_err,
+                          u64* __restrict__ adm_max, const Ctrl* __restrict__ ctrl, SlotInfo* __restrict__ slots,
+                          SlotReport* rep) {
+  const int i = threadIdx.x;
+  if (blockIdx.x != 0 || i >= b.count) return;
+  const int s = b.it[i].slot;
+  const unsigned e = adm_err[s] | __hip_atomic_load(&ctrl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&rep[s].cut, (long long)(cut_acc[s] / 2), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __hip_atomic_store(&rep[s].fin_err, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  cut_acc[s] = 0;
+  adm_err[s] = 0;
+  adm_max[s] = 0;
+  slots[s].active = 0;
+  __hip_atomic_store(&rep[s].done, 1ll, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // Rebase: every live key drops by X rounds.  Keys below X rounds belong to vertices outside the
@@ -251,18 +414,28 @@ __global__ void k_state_add(RoundState* st, long long k_last, long long arcs) {
 // The slots' r0 and the host's round numbering move by the same X.
 __global__ __launch_bounds__(256) void k_rebase(long long V, int B, u64 C, long long X, u64* __restrict__ P,
                                                 long long* __restrict__ shift_g, u64* __restrict__ lr_part, int n_lr,
+                                                u64* __restrict__ s_lr, SlotInfo* __restrict__ slots, int nslots,
                                                 RoundState* st, long long k_last) {
   const u64 xf = (u64)X * S_ONE;
   const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < V; i += stride) {
-    const u64 p = P[i];
-    if (p != INF) P[i] = (p >> B) >= xf ? p - (xf << B) : 0;
-    const u64 off = C - (u64)shift_g[i];
-    shift_g[i] = (long long)(off >= xf ? C - (off - xf) : C);
+  long long items = V > n_lr ? V : n_lr;
+  items = items > 3 * MAX_SLOTS ? items : 3 * MAX_SLOTS;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < items; i += stride) {
+    if (i < V) {
+      const u64 p = P[i];
+      if (p != INF) P[i] = (p >> B) >= xf ? p - (xf << B) : 0;
+      const u64 off = C - (u64)shift_g[i];
+      shift_g[i] = (long long)(off >= xf ? C - (off - xf) : C);
+    }
     if (i < n_lr) {
       const u64 l = lr_part[i];
       if (l != INF) lr_part[i] = (l >> B) >= xf ? l - (xf << B) : 0;
     }
+    if (i < 3 * MAX_SLOTS) {
+      const u64 l = s_lr[i];
+      if (l != INF) s_lr[i] = (l >> B) >= xf ? l - (xf << B) : 0;
+    }
+    if (i < nslots) slots[i].r0 -= X;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) st[k_last & 1].round -= X;
 }
@@ -328,17 +501,16 @@ enum ReqState { RQ_QUEUED, RQ_ACTIVE, RQ_FINISHING, RQ_DONE };
 struct Request {
   uint64_t ticket = 0;
   ldd_request q{};  // the caller's buffers (device)
-  u64 delta = 0;    // max shift
-  int R = 1;        // rounds: (delta >> 20) + 1
+  hipEvent_t ready = nullptr;  // recorded on the caller's stream at submit
   int state = RQ_QUEUED;
   ldd_status status = LDD_ERR_PENDING;
   int slot = -1;
-  long long vbeg = 0, abeg = 0, wbase = 0;
-  long long r0 = 0;         // global round of its round 0 (numbering at admission)
-  long long done_step = 0;  // complete once this step has run
+  long long vbeg = 0, abeg = 0;
+  long long r0 = 0;          // global round of its round 0 (numbering at admission)
+  long long first_step = 0;  // the step that runs its round 0
+  int R = -1;                // rounds, once the admission has reported them
   int64_t cut = 0;
   double t_submit = 0, t_admit = 0, t_done = 0;
-  hipEvent_t ev = nullptr;  // result written and cut copied out
 };
 
 }  // namespace
@@ -351,26 +523,25 @@ struct ldd_server {
   u64 C = 0;                  // engine Delta: a vertex's source-arc length is C - shift_g
   long long round_limit = 0;  // keys stay below round_limit * 2^20
   int max_rounds = 0;         // largest R a request may have
-  hipStream_t stream = nullptr, check_stream = nullptr;
+  hipStream_t stream = nullptr;
   hipEvent_t chunk_ev[2] = {};
   hipGraphExec_t graph = nullptr;
   int blocks = 0;
   // arena and engine buffers (device)
   void *P = nullptr, *qv0 = nullptr, *qv1 = nullptr, *qa0 = nullptr, *qa1 = nullptr, *wake_ord = nullptr;
-  void *rp_g = nullptr, *col_g = nullptr, *shift_g = nullptr;
-  void *mat = nullptr, *qmax = nullptr, *tot = nullptr, *scratch_ne = nullptr, *wake_tab = nullptr;
+  void *rp_g = nullptr, *col_g = nullptr, *shift_g = nullptr, *wake_tab = nullptr, *cnt = nullptr, *cur = nullptr;
   void *slots = nullptr, *st = nullptr, *qcnt = nullptr, *lr_part = nullptr, *lb = nullptr, *ex_part = nullptr;
-  void *ctrl = nullptr, *cuts = nullptr, *check = nullptr;
-  u64* h_out = nullptr;    // pinned: per slot {cut arcs, engine error bits}
-  u64* h_check = nullptr;  // pinned: k_req_check's block results
-  int wake_tab_cap = 0;
-  RangeAlloc valloc, aalloc, walloc;
-  SlotInfo slot_tab[MAX_SLOTS] = {};
+  void *ctrl = nullptr, *adm_max = nullptr, *adm_err = nullptr, *cut_acc = nullptr;
+  void *vslot = nullptr, *sst = nullptr, *s_cnt = nullptr, *s_lr = nullptr;
+  SlotReport* rep = nullptr;      // mapped host memory
+  SlotReport* rep_dev = nullptr;  // its device address
+  RangeAlloc valloc, aalloc;
   Request* slot_req[MAX_SLOTS] = {};
   long long steps = 0;       // steps enqueued so far
   long long round_base = 0;  // global round of step 1 in the current numbering
-  std::mutex check_mu;       // k_req_check's buffers
-  std::mutex mu;             // everything below, and the allocators and slot_req
+  std::mutex ev_mu;          // the event pool
+  std::vector<hipEvent_t> ev_pool;
+  std::mutex mu;  // everything below, and the allocators and slot_req
   std::condition_variable cv_work, cv_done;
   std::deque<Request*> queue;
   std::map<uint64_t, Request*> all;
@@ -396,6 +567,25 @@ namespace {
 
 long long round_at(const ldd_server* srv, long long k) { return srv->round_base + (k - 1); }
 
+hipEvent_t get_event(ldd_server* srv) {
+  {
+    std::lock_guard<std::mutex> lk(srv->ev_mu);
+    if (!srv->ev_pool.empty()) {
+      hipEvent_t e = srv->ev_pool.back();
+      srv->ev_pool.pop_back();
+      return e;
+    }
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+  return e;
+}
+
+void put_event(ldd_server* srv, hipEvent_t e) {
+  std::lock_guard<std::mutex> lk(srv->ev_mu);
+  srv->ev_pool.push_back(e);
+}
+
 ldd_status srv_alloc(ldd_server* srv, void** p, size_t bytes) {
   hipError_t e = hipMalloc(p, bytes < 256 ? 256 : bytes);
   if (e != hipSuccess) {
@@ -408,45 +598,53 @@ ldd_status srv_alloc(ldd_server* srv, void** p, size_t bytes) {
 }
 
 // Device bytes per arena vertex (label, two queues with arc prefixes, wake order, row offset,
-// shift) and per arena arc (column id).
-constexpr long long BYTES_PER_VERTEX = 8 + 8 + 8 + 4 + 4 + 8;
+// shift, slot) and per arena arc (column id).
+constexpr long long BYTES_PER_VERTEX = 8 + 8 + 8 + 4 + 4 + 8 + 1;
 constexpr long long BYTES_PER_ARC = 4;
-constexpr int SORT_BLOCKS = 256;  // at most this many blocks in a slot's wake-round sort
 
 ldd_status srv_setup(ldd_server* srv) {
   SRV_TRY(hipSetDevice(srv->dev));
   SRV_TRY(hipStreamCreateWithFlags(&srv->stream, hipStreamNonBlocking));
-  SRV_TRY(hipStreamCreateWithFlags(&srv->check_stream, hipStreamNonBlocking));
   for (auto& e : srv->chunk_ev) SRV_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   const long long V = srv->vcap, A = srv->acap;
+  const size_t per_slot = (size_t)MAX_SLOTS * (srv->max_rounds + 1);
   ldd_status s;
   if ((s = srv_alloc(srv, &srv->P, V * 8)) || (s = srv_alloc(srv, &srv->qv0, V * 4)) ||
       (s = srv_alloc(srv, &srv->qv1, V * 4)) || (s = srv_alloc(srv, &srv->qa0, V * 4)) ||
       (s = srv_alloc(srv, &srv->qa1, V * 4)) || (s = srv_alloc(srv, &srv->wake_ord, V * 4)) ||
       (s = srv_alloc(srv, &srv->rp_g, (V + 1) * 4)) || (s = srv_alloc(srv, &srv->col_g, A * 4)) ||
-      (s = srv_alloc(srv, &srv->shift_g, V * 8)) || (s = srv_alloc(srv, &srv->mat, (size_t)QCAP * SORT_BLOCKS * 4)) ||
-      (s = srv_alloc(srv, &srv->qmax, SORT_BLOCKS * 4)) || (s = srv_alloc(srv, &srv->tot, QCAP * 4)) ||
-      (s = srv_alloc(srv, &srv->scratch_ne, (QCAP + 2) * 4)) ||
-      (s = srv_alloc(srv, &srv->wake_tab, (size_t)srv->wake_tab_cap * 4)) ||
+      (s = srv_alloc(srv, &srv->shift_g, V * 8)) || (s = srv_alloc(srv, &srv->wake_tab, per_slot * 4)) ||
+      (s = srv_alloc(srv, &srv->cnt, per_slot * 4)) || (s = srv_alloc(srv, &srv->cur, per_slot * 4)) ||
       (s = srv_alloc(srv, &srv->slots, sizeof(SlotInfo) * MAX_SLOTS)) ||
       (s = srv_alloc(srv, &srv->st, 2 * sizeof(RoundState))) || (s = srv_alloc(srv, &srv->qcnt, 3 * 16 * 8)) ||
       (s = srv_alloc(srv, &srv->lr_part, 2 * (size_t)RT * 8)) ||
       (s = srv_alloc(srv, &srv->lb, sizeof(LaunchBlock))) || (s = srv_alloc(srv, &srv->ex_part, (size_t)RT * 8)) ||
-      (s = srv_alloc(srv, &srv->ctrl, sizeof(Ctrl))) || (s = srv_alloc(srv, &srv->cuts, MAX_SLOTS * 8)) ||
-      (s = srv_alloc(srv, &srv->check, 2 * CHECK_BLOCKS * 8)))
+      (s = srv_alloc(srv, &srv->ctrl, sizeof(Ctrl))) || (s = srv_alloc(srv, &srv->adm_max, MAX_SLOTS * 8)) ||
+      (s = srv_alloc(srv, &srv->adm_err, MAX_SLOTS * 4)) || (s = srv_alloc(srv, &srv->cut_acc, MAX_SLOTS * 8)) ||
+      (s = srv_alloc(srv, &srv->vslot, V + 1)) || (s = srv_alloc(srv, &srv->sst, 2 * MAX_SLOTS * sizeof(SlotState))) ||
+      (s = srv_alloc(srv, &srv->s_cnt, 3 * MAX_SLOTS * 8)) || (s = srv_alloc(srv, &srv->s_lr, 3 * MAX_SLOTS * 8)))
     return s;
-  SRV_TRY(hipHostMalloc((void**)&srv->h_out, MAX_SLOTS * 2 * 8, hipHostMallocDefault));
-  SRV_TRY(hipHostMalloc((void**)&srv->h_check, 2 * CHECK_BLOCKS * 8, hipHostMallocDefault));
-  memset(srv->h_out, 0, MAX_SLOTS * 2 * 8);
+  SRV_TRY(hipHostMalloc((void**)&srv->rep, sizeof(SlotReport) * MAX_SLOTS,
+                        hipHostMallocMapped | hipHostMallocCoherent));
+  memset(srv->rep, 0, sizeof(SlotReport) * MAX_SLOTS);
+  SRV_TRY(hipHostGetDevicePointer((void**)&srv->rep_dev, srv->rep, 0));
   const hipStream_t q = srv->stream;
   // every vertex is settled (label 0) until a request claims it
   SRV_TRY(hipMemsetAsync(srv->P, 0, V * 8, q));
   SRV_TRY(hipMemsetAsync(srv->shift_g, 0, V * 8, q));
+  SRV_TRY(hipMemsetAsync(srv->cnt, 0, per_slot * 4, q));
   SRV_TRY(hipMemsetAsync(srv->slots, 0, sizeof(SlotInfo) * MAX_SLOTS, q));
   SRV_TRY(hipMemsetAsync(srv->qcnt, 0, 3 * 16 * 8, q));
   SRV_TRY(hipMemsetAsync(srv->ex_part, 0, (size_t)RT * 8, q));
   SRV_TRY(hipMemsetAsync(srv->ctrl, 0, sizeof(Ctrl), q));
+  SRV_TRY(hipMemsetAsync(srv->adm_max, 0, MAX_SLOTS * 8, q));
+  SRV_TRY(hipMemsetAsync(srv->adm_err, 0, MAX_SLOTS * 4, q));
+  SRV_TRY(hipMemsetAsync(srv->cut_acc, 0, MAX_SLOTS * 8, q));
   SRV_TRY(hipMemsetAsync(srv->lr_part, 0xff, 2 * (size_t)RT * 8, q));
+  SRV_TRY(hipMemsetAsync(srv->vslot, 0, V + 1, q));
+  SRV_TRY(hipMemsetAsync(srv->sst, 0, 2 * MAX_SLOTS * sizeof(SlotState), q));
+  SRV_TRY(hipMemsetAsync(srv->s_cnt, 0, 3 * MAX_SLOTS * 8, q));
+  SRV_TRY(hipMemsetAsync(srv->s_lr, 0xff, 3 * MAX_SLOTS * 8, q));
   RoundState pair[2] = {};
   for (auto& x : pair) {
     x.mode = MODE_ROUNDS;
@@ -458,7 +656,6 @@ ldd_status srv_setup(ldd_server* srv) {
   SRV_TRY(hipMemcpyAsync(srv->st, pair, sizeof(pair), hipMemcpyHostToDevice, q));
   srv->valloc.init(V);
   srv->aalloc.init(A);
-  srv->walloc.init(srv->wake_tab_cap);
 
   int ncu = 0;
   SRV_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, srv->dev));
@@ -499,6 +696,10 @@ ldd_status srv_setup(ldd_server* srv) {
   c.slots = (const SlotInfo*)srv->slots;
   c.nslots = srv->cfg.max_slots;
   c.wake_tab = (const int*)srv->wake_tab;
+  c.vslot = (const unsigned char*)srv->vslot;
+  c.sst = (SlotState*)srv->sst;
+  c.s_cnt = (u64*)srv->s_cnt;
+  c.s_lr = (u64*)srv->s_lr;
   lb.kbase = 1;
   SRV_TRY(hipMemcpyAsync(srv->lb, &lb, sizeof(LaunchBlock), hipMemcpyHostToDevice, q));
   SRV_TRY(hipStreamSynchronize(q));
@@ -508,7 +709,7 @@ ldd_status srv_setup(ldd_server* srv) {
   hipGraph_t g = nullptr;
   SRV_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
   for (int j = 0; j < srv->cfg.chunk_steps; ++j)
-    hipLaunchKernelGGL(k_round_step_lb, dim3(srv->blocks), dim3(RT), 0, cap, (const LaunchBlock*)srv->lb, j);
+    hipLaunchKernelGGL(k_round_step_srv, dim3(srv->blocks), dim3(RT), 0, cap, (const LaunchBlock*)srv->lb, j);
   hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, cap, (LaunchBlock*)srv->lb, srv->cfg.chunk_steps);
   SRV_TRY(hipStreamEndCapture(cap, &g));
   SRV_TRY(hipGraphInstantiate(&srv->graph, g, nullptr, nullptr, 0));
@@ -517,135 +718,166 @@ ldd_status srv_setup(ldd_server* srv) {
   return LDD_OK;
 }
 
-// Enqueue the admission of r (ranges already taken), its round 0 being global round r0.
-ldd_status srv_admit(ldd_server* srv, Request* r, int slot, long long r0) {
+volatile SlotReport& report(ldd_server* srv, int slot) { return ((volatile SlotReport*)srv->rep)[slot]; }
+
+// The slot's report is cleared before its admission is enqueued (the device writes it later).
+void rep_reset(ldd_server* srv, int slot) {
+  volatile SlotReport& rp = report(srv, slot);
+  rp.done = 0;
+  rp.R = -1;
+  rp.adm_err = 0;
+  rp.fin_err = 0;
+  rp.cut = 0;
+}
+
+int blocks_for(long long n, long long nnz, long long per_block) {
+  return (int)std::max<long long>(1, std::min<long long>(1024, (n + nnz / 8 + per_block - 1) / per_block));
+}
+
+// Enqueue the admission of a batch of requests (ranges and slots already taken).
+ldd_status srv_admit(ldd_server* srv, const std::vector<Request*>& rs) {
   const hipStream_t s = srv->stream;
-  const int n = r->q.n, R = r->R;
-  const long long nnz = r->q.nnz;
-  r->slot = slot;
-  r->r0 = r0;
-  const long long items = std::max<long long>((long long)n + 1, nnz);
-  hipLaunchKernelGGL(k_slot_load, dim3((unsigned)std::min<long long>(8192, (items + 255) / 256)), dim3(256), 0, s,
-                     r->vbeg, n, r->abeg, nnz, r->q.row_ptr, r->q.col_idx, (const long long*)r->q.shift_fix, r->delta, r0, srv->C,
-                     srv->B, (int*)srv->rp_g, (int*)srv->col_g, (long long*)srv->shift_g, (u64*)srv->P);
-  // wake-round counting sort into the slot's part of wake_ord; round offsets into wake_tab
-  const int gs = (int)std::max<long long>(1, std::min<long long>(SORT_BLOCKS, n / 8192));
-  int* roff = (int*)srv->wake_tab + r->wbase;
-  hipLaunchKernelGGL(k_slot_hist, dim3(gs), dim3(1024), 0, s, n, R, r->q.row_ptr, (const long long*)r->q.shift_fix, r->delta,
-                     (unsigned*)srv->mat, (int*)srv->qmax);
-  hipLaunchKernelGGL(k_qbucket_scan, dim3((unsigned)(((long long)R * WAVE + 255) / 256)), dim3(256), 0, s, R, gs,
-                     (unsigned*)srv->mat, (const int*)srv->qmax, (unsigned*)srv->tot);
-  hipLaunchKernelGGL(k_qscan, dim3(1), dim3(1024), 0, s, R - 1, (const unsigned*)srv->tot, roff,
-                     (int*)srv->scratch_ne);
-  hipLaunchKernelGGL(k_slot_place, dim3(gs), dim3(1024), 0, s, n, R, r->vbeg, r->q.row_ptr, (const long long*)r->q.shift_fix, r->delta,
-                     (const unsigned*)srv->mat, (const int*)roff, (int*)srv->wake_ord);
-  SlotInfo e{};
-  e.vbeg = r->vbeg;
-  e.r0 = r0;
-  e.R = R;
-  e.wbase = (int)r->wbase;
-  e.active = 1;
-  srv->slot_tab[slot] = e;
-  hipLaunchKernelGGL(k_set_slot, dim3(1), dim3(64), 0, s, (SlotInfo*)srv->slots, slot, e);
-  hipLaunchKernelGGL(k_state_add, dim3(1), dim3(64), 0, s, (RoundState*)srv->st, srv->steps, nnz);
-  SRV_TRY(hipGetLastError());
-  r->done_step = (r0 + R - 1) - srv->round_base + 1;  // the step that runs global round r0 + R - 1
+  for (size_t b0 = 0; b0 < rs.size(); b0 += MAX_BATCH) {
+    AdmBatch ab{};
+    int nblk = 0;
+    for (size_t i = b0; i < rs.size() && ab.count < MAX_BATCH; ++i) {
+      Request* r = rs[i];
+      if (r->ready) {
+        SRV_TRY(hipStreamWaitEvent(s, r->ready, 0));
+        put_event(srv, r->ready);  // the wait took the recorded state; the event may be reused
+        r->ready = nullptr;
+      }
+      AdmItem& t = ab.it[ab.count++];
+      t.rp = r->q.row_ptr;
+      t.col = r->q.col_idx;
+      t.shift = (const long long*)r->q.shift_fix;
+      t.vbeg = r->vbeg;
+      t.abeg = r->abeg;
+      t.nnz = r->q.nnz;
+      t.r0 = r->r0;
+      t.n = r->q.n;
+      t.slot = r->slot;
+      t.blk0 = nblk;
+      t.nblk = blocks_for(r->q.n, r->q.nnz, 16384);
+      nblk += t.nblk;
+      rep_reset(srv, r->slot);
+    }
+    hipLaunchKernelGGL(k_adm_check, dim3(nblk), dim3(ADM_T), 0, s, ab, (u64*)srv->adm_max, (unsigned*)srv->adm_err);
+    hipLaunchKernelGGL(k_adm_load, dim3(nblk), dim3(ADM_T), 0, s, ab, srv->C, srv->B, srv->max_rounds,
+                       (const u64*)srv->adm_max, (unsigned*)srv->adm_err, (int*)srv->rp_g, (int*)srv->col_g,
+                       (long long*)srv->shift_g, (u64*)srv->P, (unsigned char*)srv->vslot, (unsigned*)srv->cnt);
+    hipLaunchKernelGGL(k_adm_commit, dim3(ab.count), dim3(ADM_T), 0, s, ab, srv->max_rounds,
+                       (const u64*)srv->adm_max, (unsigned*)srv->adm_err, (unsigned*)srv->cnt,
+                       (unsigned*)srv->cur, (int*)srv->wake_tab, (SlotInfo*)srv->slots, (RoundState*)srv->st,
+                       srv->steps, (SlotState*)srv->sst, (u64*)srv->s_cnt, (u64*)srv->s_lr, srv->rep_dev);
+    hipLaunchKernelGGL(k_adm_place, dim3(nblk), dim3(ADM_T), 0, s, ab, srv->max_rounds, (const u64*)srv->adm_max,
+                       (const unsigned*)srv->adm_err, (unsigned*)srv->cur, (int*)srv->wake_ord);
+    SRV_TRY(hipGetLastError());
+  }
   return LDD_OK;
 }
 
-// Enqueue the result of a request whose last round has run: centres into the caller's buffer,
-// the cut, the slot leaves the table.  Its ranges are freed once the event has completed.
-ldd_status srv_finish(ldd_server* srv, Request* r) {
+// Enqueue the finishing of a batch of requests whose last round and the step after it are
+// enqueued: centres into the callers' buffers, cuts, reports.
+ldd_status srv_finish(ldd_server* srv, const std::vector<Request*>& rs) {
   const hipStream_t s = srv->stream;
-  const int n = r->q.n;
-  const long long nnz = r->q.nnz;
-  hipLaunchKernelGGL(k_slot_final, dim3((unsigned)std::max<long long>(1, std::min<long long>(4096, (n + 255) / 256))),
-                     dim3(256), 0, s, r->vbeg, n, srv->B, (const u64*)srv->P, r->q.centre);
-  SRV_TRY(hipMemsetAsync((u64*)srv->cuts + r->slot, 0, 8, s));
-  if (nnz)
-    hipLaunchKernelGGL(k_slot_cut, dim3((unsigned)std::max<long long>(1, std::min<long long>(2048, nnz / 4096))),
-                       dim3(256), 0, s, r->vbeg, n, r->abeg, nnz, (const int*)srv->rp_g, (const int*)srv->col_g,
-                       (const int*)r->q.centre, (u64*)srv->cuts + r->slot);
-  SlotInfo off{};
-  srv->slot_tab[r->slot] = off;
-  hipLaunchKernelGGL(k_set_slot, dim3(1), dim3(64), 0, s, (SlotInfo*)srv->slots, r->slot, off);
-  SRV_TRY(hipMemcpyAsync(srv->h_out + 2 * r->slot, (u64*)srv->cuts + r->slot, 8, hipMemcpyDeviceToHost, s));
-  SRV_TRY(hipMemcpyAsync(srv->h_out + 2 * r->slot + 1, &((Ctrl*)srv->ctrl)->err, 4, hipMemcpyDeviceToHost, s));
-  SRV_TRY(hipEventCreateWithFlags(&r->ev, hipEventDisableTiming));
-  SRV_TRY(hipEventRecord(r->ev, s));
-  SRV_TRY(hipGetLastError());
-  r->state = RQ_FINISHING;
+  for (size_t b0 = 0; b0 < rs.size(); b0 += MAX_BATCH) {
+    FinBatch fb{};
+    int nblk = 0;
+    for (size_t i = b0; i < rs.size() && fb.count < MAX_BATCH; ++i) {
+      Request* r = rs[i];
+      FinItem& t = fb.it[fb.count++];
+      t.centre = r->q.centre;
+      t.vbeg = r->vbeg;
+      t.abeg = r->abeg;
+      t.nnz = r->q.nnz;
+      t.n = r->q.n;
+      t.slot = r->slot;
+      t.blk0 = nblk;
+      t.nblk = (int)std::max<long long>(1, std::min<long long>(2048, (r->q.n + r->q.nnz + 8191) / 8192));
+      nblk += t.nblk;
+      r->state = RQ_FINISHING;
+    }
+    hipLaunchKernelGGL(k_fin, dim3(nblk), dim3(FIN_T), 0, s, fb, srv->B, (const u64*)srv->P, (const int*)srv->rp_g,
+                       (const int*)srv->col_g, (const SlotInfo*)srv->slots, (u64*)srv->cut_acc);
+    hipLaunchKernelGGL(k_fin_out, dim3(1), dim3(64), 0, s, fb, (u64*)srv->cut_acc, (unsigned*)srv->adm_err,
+                       (u64*)srv->adm_max, (const Ctrl*)srv->ctrl, (SlotInfo*)srv->slots, srv->rep_dev);
+    SRV_TRY(hipGetLastError());
+  }
   return LDD_OK;
 }
 
 // Lower the global round numbering by X rounds (X <= every active slot's r0).
 ldd_status srv_rebase(ldd_server* srv, long long X) {
-  hipLaunchKernelGGL(k_rebase, dim3((unsigned)std::min<long long>(8192, (srv->vcap + 255) / 256)), dim3(256), 0,
+  hipLaunchKernelGGL(k_rebase, dim3((unsigned)std::min<long long>(8192, (std::max<long long>(srv->vcap, 2 * RT) + 255) / 256)), dim3(256), 0,
                      srv->stream, srv->vcap, srv->B, srv->C, X, (u64*)srv->P, (long long*)srv->shift_g,
-                     (u64*)srv->lr_part, 2 * RT, (RoundState*)srv->st, srv->steps);
-  for (int i = 0; i < MAX_SLOTS; ++i) {
-    if (!srv->slot_tab[i].active) continue;
-    srv->slot_tab[i].r0 -= X;
-    hipLaunchKernelGGL(k_set_slot, dim3(1), dim3(64), 0, srv->stream, (SlotInfo*)srv->slots, i, srv->slot_tab[i]);
-  }
+                     (u64*)srv->lr_part, 2 * RT, (u64*)srv->s_lr, (SlotInfo*)srv->slots, MAX_SLOTS,
+                     (RoundState*)srv->st, srv->steps);
   SRV_TRY(hipGetLastError());
   srv->round_base -= X;
   ++srv->rebases;
   return LDD_OK;
 }
 
-// Hand a request whose event has completed back to its caller.
-ldd_status srv_complete(ldd_server* srv, Request* r) {
-  const u64 arcs = srv->h_out[2 * r->slot], err = srv->h_out[2 * r->slot + 1] & 0xffffffffull;
-  SRV_TRY(hipEventDestroy(r->ev));
-  r->ev = nullptr;
-  if (err) {
-    snprintf(srv->fatal_msg, sizeof(srv->fatal_msg), "round engine error flags 0x%llx", (unsigned long long)err);
-    return LDD_ERR_INTERNAL;
-  }
-  std::lock_guard<std::mutex> lk(srv->mu);
-  srv->valloc.give(r->vbeg, (long long)r->q.n + 1);
-  srv->aalloc.give(r->abeg, r->q.nnz);
-  srv->walloc.give(r->wbase, (long long)r->R + 1);
-  srv->slot_req[r->slot] = nullptr;
-  r->cut = (int64_t)(arcs / 2);
-  r->status = LDD_OK;
-  r->state = RQ_DONE;
-  r->t_done = now_s();
-  ++srv->completed;
+ldd_status status_of(unsigned err) {
+  if (err & (ERR_BARRIER | ERR_WATCHDOG | ERR_QUEUE)) return LDD_ERR_INTERNAL;
+  if (err & (ERR_BAD_SHIFT | ERR_BAD_ROWPTR | ERR_BAD_COL)) return LDD_ERR_INVALID_ARG;
+  if (err & ERR_ROUNDS) return LDD_ERR_OVERFLOW;
   return LDD_OK;
 }
 
 ldd_status engine_loop(ldd_server* srv) {
   SRV_TRY(hipSetDevice(srv->dev));
   const int nslots = srv->cfg.max_slots;
-  std::vector<Request*> finishing;
+  std::vector<Request*> finishing, batch;
   int inflight = 0, oldest = 0;
   for (;;) {
-    // 1. results whose copies have completed
+    // 1. finished requests whose reports have arrived go back to their callers
     bool handed = false;
     for (size_t i = 0; i < finishing.size();) {
-      const hipError_t e = hipEventQuery(finishing[i]->ev);
-      if (e == hipErrorNotReady) {
+      Request* r = finishing[i];
+      volatile SlotReport& rp = report(srv, r->slot);
+      if (__atomic_load_n(&rp.done, __ATOMIC_ACQUIRE) == 0) {
         ++i;
         continue;
       }
-      SRV_TRY(e);
-      const ldd_status st = srv_complete(srv, finishing[i]);
-      if (st != LDD_OK) return st;
+      const unsigned err = rp.fin_err;
+      if (status_of(err) == LDD_ERR_INTERNAL) {
+        snprintf(srv->fatal_msg, sizeof(srv->fatal_msg), "round engine error flags 0x%x", err);
+        return LDD_ERR_INTERNAL;
+      }
+      {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->valloc.give(r->vbeg, (long long)r->q.n + 1);
+        srv->aalloc.give(r->abeg, r->q.nnz);
+        srv->slot_req[r->slot] = nullptr;
+        r->status = status_of(err);
+        r->cut = r->status == LDD_OK ? (int64_t)rp.cut : 0;
+        r->state = RQ_DONE;
+        r->t_done = now_s();
+        ++srv->completed;
+      }
       handed = true;
       finishing[i] = finishing.back();
       finishing.pop_back();
     }
     if (handed) srv->cv_done.notify_all();
-    // 2. admission, first come first served, while the head of the queue fits
+    // 2. rounds of admitted requests, as their admission reports them
     int active = 0;
     long long min_r0 = -1;
-    for (int i = 0; i < nslots; ++i)
-      if (srv->slot_req[i] && srv->slot_req[i]->state == RQ_ACTIVE) {
-        ++active;
-        min_r0 = min_r0 < 0 ? srv->slot_tab[i].r0 : std::min(min_r0, srv->slot_tab[i].r0);
+    for (int i = 0; i < nslots; ++i) {
+      Request* r = srv->slot_req[i];
+      if (!r || r->state != RQ_ACTIVE) continue;
+      if (r->R < 0) {
+        volatile SlotReport& rp = report(srv, i);
+        const long long R = __atomic_load_n(&rp.R, __ATOMIC_ACQUIRE);
+        if (R >= 0) r->R = (int)R;
       }
+      ++active;
+      min_r0 = min_r0 < 0 ? r->r0 : std::min(min_r0, r->r0);
+    }
+    // 3. admission, first come first served, while the head of the queue fits
+    batch.clear();
     {
       std::unique_lock<std::mutex> lk(srv->mu);
       if (active == 0 && inflight == 0 && finishing.empty()) {
@@ -659,67 +891,74 @@ ldd_status engine_loop(ldd_server* srv) {
       if (!srv->queue.empty() && r_next + srv->max_rounds > srv->round_limit) {
         const long long X = min_r0 < 0 ? r_next : std::min(min_r0, r_next);
         if (X > 0) {
-          lk.unlock();
           const ldd_status st = srv_rebase(srv, X);
           if (st != LDD_OK) return st;
-          lk.lock();
+          for (int i = 0; i < nslots; ++i)
+            if (srv->slot_req[i] && srv->slot_req[i]->state == RQ_ACTIVE) srv->slot_req[i]->r0 -= X;
         }
       }
-      while (!srv->queue.empty()) {
+      const long long r0 = round_at(srv, srv->steps + 1);
+      while (!srv->queue.empty() && r0 + srv->max_rounds <= srv->round_limit) {
         Request* r = srv->queue.front();
         int slot = -1;
         for (int i = 0; i < nslots && slot < 0; ++i)
           if (!srv->slot_req[i]) slot = i;
-        const long long r0 = round_at(srv, srv->steps + 1);
-        if (slot < 0 || r0 + r->R > srv->round_limit) break;
+        if (slot < 0) break;
         const long long vb = srv->valloc.take((long long)r->q.n + 1);
         const long long ab = vb < 0 ? -1 : srv->aalloc.take(r->q.nnz);
-        const long long wb = ab < 0 ? -1 : srv->walloc.take((long long)r->R + 1);
-        if (wb < 0) {
-          if (ab >= 0) srv->aalloc.give(ab, r->q.nnz);
+        if (ab < 0) {
           if (vb >= 0) srv->valloc.give(vb, (long long)r->q.n + 1);
           break;
         }
         srv->queue.pop_front();
         r->vbeg = vb;
         r->abeg = ab;
-        r->wbase = wb;
+        r->slot = slot;
+        r->r0 = r0;
+        r->first_step = srv->steps + 1;
+        r->R = -1;
         r->state = RQ_ACTIVE;
         r->t_admit = now_s();
         srv->slot_req[slot] = r;
         ++srv->admitted;
         ++active;
         srv->max_active = std::max<long long>(srv->max_active, active);
-        lk.unlock();
-        const ldd_status st = srv_admit(srv, r, slot, r0);
-        lk.lock();
-        if (st != LDD_OK) return st;
+        batch.push_back(r);
       }
     }
-    // 3. one more step chunk while any request is active (two chunks in flight)
+    if (!batch.empty()) {
+      const ldd_status st = srv_admit(srv, batch);
+      if (st != LDD_OK) return st;
+    }
+    // 4. one more step chunk while any request is active (two chunks in flight)
     if (active > 0) {
       SRV_TRY(hipGraphLaunch(srv->graph, srv->stream));
       srv->steps += srv->cfg.chunk_steps;
       SRV_TRY(hipEventRecord(srv->chunk_ev[(oldest + inflight) & 1], srv->stream));
       ++inflight;
     }
-    // 4. requests whose last round is enqueued: their results follow in stream order
+    // 5. requests whose last round and the step after it are enqueued (that step consumes the
+    // last frontier, so no later step refers to their vertex ids once they are released)
+    batch.clear();
     for (int i = 0; i < nslots; ++i) {
       Request* r = srv->slot_req[i];
-      if (r && r->state == RQ_ACTIVE && r->done_step <= srv->steps) {
-        const ldd_status st = srv_finish(srv, r);
-        if (st != LDD_OK) return st;
+      if (r && r->state == RQ_ACTIVE && r->R >= 0 && r->first_step + std::max(r->R, 1) - 1 < srv->steps) {
+        batch.push_back(r);
         finishing.push_back(r);
         --active;
       }
     }
-    // 5. wait: for the older chunk once two are in flight, else for whatever is outstanding
+    if (!batch.empty()) {
+      const ldd_status st = srv_finish(srv, batch);
+      if (st != LDD_OK) return st;
+    }
+    // 6. wait: for the older chunk once two are in flight, else for whatever is outstanding
     if (inflight == 2 || (inflight > 0 && active == 0)) {
       SRV_TRY(hipEventSynchronize(srv->chunk_ev[oldest]));
       oldest ^= 1;
       --inflight;
     } else if (inflight == 0 && active == 0 && !finishing.empty()) {
-      SRV_TRY(hipEventSynchronize(finishing.front()->ev));
+      SRV_TRY(hipStreamSynchronize(srv->stream));
     }
   }
 }
@@ -740,7 +979,7 @@ void fail_all(ldd_server* srv, ldd_status st) {
 void fill_result(const ldd_server* srv, const Request* r, ldd_result* out) {
   out->status = r->status;
   out->cut_edges = r->cut;
-  out->rounds = r->R;
+  out->rounds = r->R > 0 ? r->R : 0;
   out->first_round = r->r0;
   out->t_submit = r->t_submit - srv->t0;
   out->t_admit = r->t_admit > 0 ? r->t_admit - srv->t0 : 0;
@@ -749,6 +988,7 @@ void fill_result(const ldd_server* srv, const Request* r, ldd_result* out) {
 }
 
 }  // namespace
+
 
 // ------------------------------------------------------------------------------------------
 // C ABI
@@ -779,6 +1019,10 @@ extern "C" ldd_status ldd_server_create(const ldd_server_config* cfg, ldd_server
   if (V <= 0 || A <= 0) {  // split the budget for graphs of about 16 arcs per vertex
     V = srv->cfg.hbm_budget_bytes / (BYTES_PER_VERTEX + 16 * BYTES_PER_ARC);
     A = 16 * V;
+    if (A >= (1ll << 31)) {  // arc ids are int32: the rest of the budget goes to vertices
+      A = (1ll << 31) - 1;
+      V = std::min<long long>(1ll << 30, (srv->cfg.hbm_budget_bytes - A * BYTES_PER_ARC) / BYTES_PER_VERTEX);
+    }
   }
   const long long used = V * BYTES_PER_VERTEX + A * BYTES_PER_ARC;
   if (V < 2 || V > (1ll << 30) || A < 1 || A >= (1ll << 31) ||
@@ -799,7 +1043,6 @@ extern "C" ldd_status ldd_server_create(const ldd_server_config* cfg, ldd_server
     ldd_set_error("max_rounds must be at least 4");
     return LDD_ERR_INVALID_ARG;
   }
-  srv->wake_tab_cap = srv->cfg.max_slots * (srv->max_rounds + 1);
   const ldd_status s = srv_setup(srv);
   if (s != LDD_OK) {
     ldd_set_error("%s", srv->fatal_msg);
@@ -829,55 +1072,19 @@ extern "C" ldd_status ldd_server_submit(ldd_server* srv, const ldd_request* req,
   Request* r = new Request();
   r->q = *req;
   r->t_submit = now_s();
-  if (req->n > 0) {
-    // validate on the check stream, after the work the caller's stream has queued so far
-    std::lock_guard<std::mutex> ck(srv->check_mu);
-    int prev = 0;
-    hipEvent_t ready = nullptr;
-    bool ok = hipGetDevice(&prev) == hipSuccess && hipSetDevice(srv->dev) == hipSuccess &&
-              hipEventCreateWithFlags(&ready, hipEventDisableTiming) == hipSuccess &&
-              hipEventRecord(ready, (hipStream_t)req->hip_stream) == hipSuccess &&
-              hipStreamWaitEvent(srv->check_stream, ready, 0) == hipSuccess;
-    const long long items = std::max<long long>(req->n, req->nnz);
-    const int gb = (int)std::max<long long>(1, std::min<long long>(CHECK_BLOCKS, (items + 1023) / 1024));
-    if (ok) {
-      hipLaunchKernelGGL(k_req_check, dim3(gb), dim3(256), 0, srv->check_stream, req->n, (long long)req->nnz,
-                         req->row_ptr, req->col_idx, (const long long*)req->shift_fix, (u64*)srv->check);
-      ok = hipGetLastError() == hipSuccess &&
-           hipMemcpyAsync(srv->h_check, srv->check, 2 * gb * 8, hipMemcpyDeviceToHost, srv->check_stream) ==
-               hipSuccess &&
-           hipStreamSynchronize(srv->check_stream) == hipSuccess;
-    }
-    if (ready) (void)hipEventDestroy(ready);
-    (void)hipSetDevice(prev);
-    if (!ok) {
+  if (req->n > 0) {  // admission waits for the work the caller's stream has queued so far
+    r->ready = get_event(srv);
+    if (!r->ready || hipEventRecord(r->ready, (hipStream_t)req->hip_stream) != hipSuccess) {
+      if (r->ready) put_event(srv, r->ready);
       delete r;
-      ldd_set_error("request check failed: %s", hipGetErrorString(hipGetLastError()));
+      ldd_set_error("recording the request's ready event failed: %s", hipGetErrorString(hipGetLastError()));
       return LDD_ERR_HIP;
     }
-    u64 mx = 0, bad = 0;
-    for (int b = 0; b < gb; ++b) {
-      mx = std::max(mx, srv->h_check[2 * b]);
-      bad |= srv->h_check[2 * b + 1];
-    }
-    if (bad) {
-      delete r;
-      ldd_set_error("invalid request:%s%s%s", (bad & ERR_BAD_SHIFT) ? " shift out of [0, 2^52]" : "",
-                    (bad & ERR_BAD_ROWPTR) ? " row offsets" : "", (bad & ERR_BAD_COL) ? " column id out of range" : "");
-      return LDD_ERR_INVALID_ARG;
-    }
-    r->delta = mx;
-    const long long R = (long long)(mx >> FIX) + 1;
-    if (R > srv->max_rounds) {
-      delete r;
-      ldd_set_error("request needs %lld rounds; this server takes at most %d", R, srv->max_rounds);
-      return LDD_ERR_OVERFLOW;
-    }
-    r->R = (int)R;
   }
   {
     std::lock_guard<std::mutex> lk(srv->mu);
     if (srv->fatal != LDD_OK || srv->stop) {
+      if (r->ready) put_event(srv, r->ready);
       delete r;
       ldd_set_error("server is not running: %s", srv->fatal_msg);
       return srv->fatal != LDD_OK ? srv->fatal : LDD_ERR_INVALID_ARG;
@@ -887,6 +1094,7 @@ extern "C" ldd_status ldd_server_submit(ldd_server* srv, const ldd_request* req,
     if (req->n == 0) {  // nothing to decompose
       r->status = LDD_OK;
       r->state = RQ_DONE;
+      r->R = 0;
       r->t_admit = r->t_done = now_s();
     } else {
       srv->queue.push_back(r);
@@ -895,6 +1103,19 @@ extern "C" ldd_status ldd_server_submit(ldd_server* srv, const ldd_request* req,
   srv->cv_work.notify_all();
   *ticket = r->ticket;
   return LDD_OK;
+}
+
+static ldd_status collect(ldd_server* srv, std::map<uint64_t, Request*>::iterator it, ldd_result* out) {
+  Request* r = it->second;
+  fill_result(srv, r, out);
+  srv->all.erase(it);
+  if (r->ready) put_event(srv, r->ready);
+  delete r;
+  if (out->status == LDD_ERR_INVALID_ARG) ldd_set_error("invalid request (row offsets, shifts or column ids)");
+  else if (out->status == LDD_ERR_OVERFLOW) ldd_set_error("request needs more than %d rounds", srv->max_rounds);
+  else if (out->status == LDD_ERR_CANCELLED) ldd_set_error("request cancelled");
+  else if (out->status != LDD_OK && srv->fatal != LDD_OK) ldd_set_error("server failed: %s", srv->fatal_msg);
+  return out->status;
 }
 
 extern "C" ldd_status ldd_server_poll(ldd_server* srv, uint64_t ticket, ldd_result* out) {
@@ -908,13 +1129,8 @@ extern "C" ldd_status ldd_server_poll(ldd_server* srv, uint64_t ticket, ldd_resu
     ldd_set_error("unknown ticket %llu", (unsigned long long)ticket);
     return LDD_ERR_INVALID_ARG;
   }
-  Request* r = it->second;
-  if (r->state != RQ_DONE) return LDD_ERR_PENDING;
-  fill_result(srv, r, out);
-  srv->all.erase(it);
-  delete r;
-  if (out->status != LDD_OK && srv->fatal != LDD_OK) ldd_set_error("server failed: %s", srv->fatal_msg);
-  return out->status;
+  if (it->second->state != RQ_DONE) return LDD_ERR_PENDING;
+  return collect(srv, it, out);
 }
 
 extern "C" ldd_status ldd_server_wait(ldd_server* srv, uint64_t ticket, ldd_result* out) {
@@ -930,11 +1146,7 @@ extern "C" ldd_status ldd_server_wait(ldd_server* srv, uint64_t ticket, ldd_resu
   }
   Request* r = it->second;
   srv->cv_done.wait(lk, [&] { return r->state == RQ_DONE; });
-  fill_result(srv, r, out);
-  srv->all.erase(it);
-  delete r;
-  if (out->status != LDD_OK && srv->fatal != LDD_OK) ldd_set_error("server failed: %s", srv->fatal_msg);
-  return out->status;
+  return collect(srv, it, out);
 }
 
 extern "C" ldd_status ldd_server_cancel(ldd_server* srv, uint64_t ticket) {
@@ -990,20 +1202,19 @@ extern "C" ldd_status ldd_server_destroy(ldd_server* srv) {
   if (srv->engine.joinable()) srv->engine.join();
   const ldd_status fatal = srv->fatal;
   if (srv->stream) (void)hipStreamSynchronize(srv->stream);
-  if (srv->check_stream) (void)hipStreamSynchronize(srv->check_stream);
   for (void* p : {srv->P, srv->qv0, srv->qv1, srv->qa0, srv->qa1, srv->wake_ord, srv->rp_g, srv->col_g, srv->shift_g,
-                  srv->mat, srv->qmax, srv->tot, srv->scratch_ne, srv->wake_tab, srv->slots, srv->st, srv->qcnt,
-                  srv->lr_part, srv->lb, srv->ex_part, srv->ctrl, srv->cuts, srv->check})
+                  srv->wake_tab, srv->cnt, srv->cur, srv->slots, srv->st, srv->qcnt, srv->lr_part, srv->lb,
+                  srv->ex_part, srv->ctrl, srv->adm_max, srv->adm_err, srv->cut_acc, srv->vslot, srv->sst,
+                  srv->s_cnt, srv->s_lr})
     if (p) (void)hipFree(p);
-  if (srv->h_out) (void)hipHostFree(srv->h_out);
-  if (srv->h_check) (void)hipHostFree(srv->h_check);
+  if (srv->rep) (void)hipHostFree(srv->rep);
   if (srv->graph) (void)hipGraphExecDestroy(srv->graph);
   for (auto& e : srv->chunk_ev)
     if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : srv->ev_pool) (void)hipEventDestroy(e);
   if (srv->stream) (void)hipStreamDestroy(srv->stream);
-  if (srv->check_stream) (void)hipStreamDestroy(srv->check_stream);
   for (auto& kv : srv->all) {
-    if (kv.second->ev) (void)hipEventDestroy(kv.second->ev);
+    if (kv.second->ready) (void)hipEventDestroy(kv.second->ready);
     delete kv.second;
   }
   delete srv;

@@ -169,33 +169,36 @@ def test_cancel_queued_request(ldd):
             srv.cancel(t_big)
 
 
-def test_bad_requests_are_rejected_at_submit(ldd):
+def test_bad_requests_fail_alone(ldd):
+    """Content errors come back as the request's status; requests beside them are unaffected."""
     import torch
     rp, ci = inputs.grid2d(10, 10)
     s = inputs.make_shifts(100, 0.2, 1)
-    with ldd.Server(max_vertices=1000, max_arcs=10000, max_rounds=256) as srv:
-        bad_ci = ci.copy()
-        bad_ci[17] = 100
-        with pytest.raises(ldd.LddError) as e:
-            srv.submit(*to_dev(rp, bad_ci, s))
-        assert e.value.status == ldd.ERR_INVALID_ARG
-        bad_rp = rp.copy()
-        bad_rp[50] = bad_rp[52]
-        with pytest.raises(ldd.LddError) as e:
-            srv.submit(*to_dev(bad_rp, ci, s))
-        assert e.value.status == ldd.ERR_INVALID_ARG
-        neg = s.copy()
-        neg[3] = -1
-        with pytest.raises(ldd.LddError) as e:
-            srv.submit(*to_dev(rp, ci, neg))
-        assert e.value.status == ldd.ERR_INVALID_ARG
-        far = s.copy()
-        far[0] = 300 * S
-        with pytest.raises(ldd.LddError) as e:
-            srv.submit(*to_dev(rp, ci, far))
-        assert e.value.status == ldd.ERR_OVERFLOW
+    bad_ci = ci.copy()
+    bad_ci[17] = 100
+    bad_rp = rp.copy()
+    bad_rp[50] = bad_rp[52]
+    neg = s.copy()
+    neg[3] = -1
+    far = s.copy()
+    far[0] = 300 * S
+    cases = [((rp, bad_ci, s), ldd.ERR_INVALID_ARG), ((bad_rp, ci, s), ldd.ERR_INVALID_ARG),
+             ((rp, ci, neg), ldd.ERR_INVALID_ARG), ((rp, ci, far), ldd.ERR_OVERFLOW)]
+    with ldd.Server(max_vertices=1000, max_arcs=10000, max_rounds=256, max_slots=3) as srv:
+        assert srv.info()["max_rounds"] == 127
+        good = [srv.submit(*to_dev(rp, ci, inputs.make_shifts(100, 0.2, 10 + i))) for i in range(3)]
+        bad = [(srv.submit(*to_dev(*arrays)), status) for arrays, status in cases]
+        more = [srv.submit(*to_dev(rp, ci, inputs.make_shifts(100, 0.2, 20 + i))) for i in range(3)]
+        for t, status in bad:
+            with pytest.raises(ldd.LddError) as e:
+                srv.wait(t)
+            assert e.value.status == status
+        for i, t in enumerate(good):
+            check(ldd, srv.wait(t), rp, ci, inputs.make_shifts(100, 0.2, 10 + i), f"good {i}")
+        for i, t in enumerate(more):
+            check(ldd, srv.wait(t), rp, ci, inputs.make_shifts(100, 0.2, 20 + i), f"after {i}")
         brp, bci = inputs.grid2d(40, 40)
-        with pytest.raises(ldd.LddError) as e:
+        with pytest.raises(ldd.LddError) as e:  # can never fit the arena: refused at submit
             srv.submit(*to_dev(brp, bci, inputs.make_shifts(1600, 0.2, 1)))
         assert e.value.status == ldd.ERR_BUDGET
         # an empty graph completes at once; the server still serves afterwards
