@@ -154,10 +154,10 @@ ldd_status ldd_decompose_batch(int32_t num_graphs, const int64_t* vtx_off, const
 typedef struct ldd_server ldd_server;
 
 typedef struct {
-  int64_t hbm_budget_bytes; /* arena size in device bytes; split as 41 B per vertex + 4 B per   */
+  int64_t hbm_budget_bytes; /* arena size in device bytes; split as 45 B per vertex + 4 B per   */
                             /* arc for graphs of about 16 arcs per vertex unless max_* are set */
                             /* (arcs at most 2^31 - 1, the rest to vertices, at most 2^30)     */
-  int64_t max_vertices;     /* arena vertices (a request takes n + 1); 0 = from the budget     */
+  int64_t max_vertices;     /* arena vertices (a request takes n + 1 rounded up to 64); 0 = from the budget */
   int64_t max_arcs;         /* arena arcs (a request takes nnz); 0 = from the budget            */
   int32_t max_slots;        /* requests on the device at once, 1..64 (0 = 64)                   */
   int32_t chunk_steps;      /* rounds per replayed launch graph, 1..64 (0 = 8)                  */
@@ -165,7 +165,9 @@ typedef struct {
   int32_t direction;        /* LDD_DIR_* policy of every round                                   */
   int32_t max_rounds;       /* testing: key range in rounds before keys are rebased (0 = the    */
                             /* largest the label width allows); requests may need at most half */
-  int32_t reserved[7];
+  int32_t tail_vertices;    /* a request finishes by label correction once its unreached       */
+                            /* vertices * this <= its vertices with arcs (0 = 64, -1 = never)   */
+  int32_t reserved[6];
 } ldd_server_config;
 
 /* One request.  All buffers are device memory of the server's device, owned by the caller,

@@ -65,7 +65,8 @@ class Stats(ctypes.Structure):
 class ServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_vertices", ctypes.c_int64), ("max_arcs", ctypes.c_int64),
                 ("max_slots", ctypes.c_int32), ("chunk_steps", ctypes.c_int32), ("blocks", ctypes.c_int32),
-                ("direction", ctypes.c_int32), ("max_rounds", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+                ("direction", ctypes.c_int32), ("max_rounds", ctypes.c_int32), ("tail_vertices", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 class Request(ctypes.Structure):
@@ -246,11 +247,11 @@ class Server:
 
     def __init__(self, hbm_budget_bytes: int = 1 << 30, max_vertices: int = 0, max_arcs: int = 0,
                  max_slots: int = 0, chunk_steps: int = 0, blocks: int = 0, direction: int = DIR_AUTO,
-                 max_rounds: int = 0):
+                 max_rounds: int = 0, tail_vertices: int = 0):
         cfg = ServerConfig()
         cfg.hbm_budget_bytes, cfg.max_vertices, cfg.max_arcs = hbm_budget_bytes, max_vertices, max_arcs
         cfg.max_slots, cfg.chunk_steps, cfg.blocks = max_slots, chunk_steps, blocks
-        cfg.direction, cfg.max_rounds = direction, max_rounds
+        cfg.direction, cfg.max_rounds, cfg.tail_vertices = direction, max_rounds, tail_vertices
         h = ctypes.c_void_p()
         _check(lib().ldd_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h

@@ -46,9 +46,19 @@ struct SlotInfo {
   int n;            // the request's vertices
 };
 // Per-slot traversal state after step k (double-buffered by parity, like RoundState).
+// A request runs rounds, then (once few of its vertices are left) one seed step and
+// label-correcting sweeps, then is done: its labels are final.
+enum { SM_ROUNDS = 0, SM_SEED = 1, SM_TAIL = 2, SM_DONE = 3 };
 struct SlotState {
-  long long ua;   // arcs of the request's vertices not settled yet
-  long long dir;  // direction of the request's round in step k (DIR_TD / DIR_BU; 0 = TD)
+  long long ua;       // arcs of the request's vertices not settled yet
+  long long dir;      // direction of the request's round in step k (DIR_TD / DIR_BU; 0 = TD)
+  long long mode;     // SM_* in step k
+  long long settled;  // vertices with arcs reached so far (rounds mode)
+};
+// Per-slot report the round step writes to mapped host memory: the step at whose start the
+// request was found done (its labels final as of the step before).
+struct SlotEnd {
+  long long step;
 };
 
 // Everything a round step needs, passed by value.
@@ -91,6 +101,7 @@ struct RoundCtx {
   SlotState* sst;              // [2][MAX_SLOTS]
   u64* s_cnt;                  // [3][MAX_SLOTS]: (count << 32 | arcs) appended by step k, at k % 3
   u64* s_lr;                   // [3][MAX_SLOTS]: smallest label written by step k, at k % 3
+  SlotEnd* s_end;              // [MAX_SLOTS], mapped host memory
 };
 
 // Arguments of graph-launched steps: step k = kbase + j of a chunk; k_advance moves kbase.

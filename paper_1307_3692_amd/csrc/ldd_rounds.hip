@@ -119,8 +119,12 @@ __device__ __forceinline__ void block_append(AppendBuf& ab, bool want, int v, un
 }
 
 // Server mode: per-slot LDS state of a step.
+// what the top-down phase does with a slot's queue entries
+enum { TD_SKIP = 0, TD_ROUND = 1, TD_SWEEP = 2 };
 struct SrvShared {
-  int sdir[MAX_SLOTS];   // direction of each slot's round in this step
+  int std_[MAX_SLOTS];   // TD_* of each slot in this step
+  int swake[MAX_SLOTS];  // the slot takes part in this round's wake
+  int sseed[MAX_SLOTS];  // the slot's pull in this step is its tail seed
   u64 sL[MAX_SLOTS];     // each slot's L_r (its smallest possible offer this round)
   u64 s_cnt[MAX_SLOTS];  // this block's (count << 32 | arcs) appended per slot
   u64 s_lr[MAX_SLOTS];   // this block's smallest label written per slot
@@ -188,7 +192,7 @@ __device__ __forceinline__ void phase_wake_slots(const RoundCtx& c, int r, int k
     if (t < c.nslots) {
       const SlotInfo sl = c.slots[t];
       const long long rho = (long long)r - sl.r0;
-      if (sl.active && rho >= 0 && rho < sl.R) {
+      if (sh.swake[t] && rho >= 0 && rho < sl.R) {
         const int lo = c.wake_tab[sl.wbase + rho], hi = c.wake_tab[sl.wbase + rho + 1];
         len = hi - lo;
         beg = sl.vbeg + lo;
@@ -323,7 +327,7 @@ __device__ __forceinline__ void phase_top_down(const RoundCtx& c, int k, const i
         if (SRV) {
           const int sl = ok ? c.vslot[u] : 0;
           ss->w_slot[kk] = (unsigned char)sl;
-          ok = ok && ss->sdir[sl] != DIR_BU;
+          ok = ok && ss->std_[sl] != TD_SKIP;
         }
         w_first[kk] = ok ? c.row_ptr[u] : 0;
         const u64 pu = ok ? load_u64_relaxed(&c.P[u]) : INF;
@@ -359,7 +363,14 @@ __device__ __forceinline__ void phase_top_down(const RoundCtx& c, int k, const i
         if (c.P[w] > offer) {
           const u64 old = atomic_min_u64(&c.P[w], offer);
           if (old > offer) {
-            if (TAIL) {
+            if (SRV && ss->std_[slot] == TD_SWEEP) {  // the slot's tail: queue on any lowering
+              wrote = true;
+              if (__hip_atomic_fetch_max(&c.stamp[w], (unsigned)k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+                  (unsigned)k) {
+                want = true;
+                deg = degree(c, w);
+              }
+            } else if (TAIL) {
               if (__hip_atomic_fetch_max(&c.stamp[w], sweep + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
                   sweep + 1) {
                 want = true;
@@ -494,9 +505,30 @@ __device__ __forceinline__ void phase_bottom_up_slots(const RoundCtx& c, int r, 
       slot = lo;
       v = (int)(ss.bseg_beg[lo] + (i - ss.bseg_off[lo]));
       const u64 Lr = ss.sL[lo];
+      const bool seed = ss.sseed[lo] != 0;
       const u64 pv = c.P[v];
-      if (pv >= base_r && pv > Lr) {
-        const int a0 = c.row_ptr[v], a1 = c.row_ptr[v + 1];
+      const int a0 = c.row_ptr[v], a1 = c.row_ptr[v + 1];
+      if (seed && pv >= base_r && a1 > a0) {
+        // tail seed: the vertex's own arc (whatever its wake round) and its neighbours in
+        // F_{r-1}; the sweeps relax the rest, queueing every vertex whose label drops
+        best = own_offer(c, v);
+        for (int a = a0; a < a1 && best > Lr; ++a) {
+          const int u = c.col[a];
+          if ((unsigned)u >= (unsigned)c.n) {
+            atomic_or_u32(&c.ctrl->err, ERR_BAD_COL);
+            break;
+          }
+          const u64 pu = load_u64_relaxed(&c.P[u]);
+          if ((pu >> (FIX + B)) == prev_round && pu != INF && pu + unit < best) best = pu + unit;
+        }
+        if (best < pv) {
+          atomic_min_u64(&c.P[v], best);
+          wrote = true;
+          want = __hip_atomic_fetch_max(&c.stamp[v], (unsigned)k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+                 (unsigned)k;
+          deg = (unsigned)(a1 - a0);
+        }
+      } else if (!seed && pv >= base_r && pv > Lr) {
         best = pv;
         for (int a = a0; a < a1; ++a) {
           const int u = c.col[a];
@@ -669,14 +701,15 @@ __device__ __forceinline__ void add_examined(const RoundCtx& c, u64 examined, St
   }
 }
 
-// Server mode, start of step k (wave 0, one lane per slot): each slot's direction for this
-// round from its own frontier (the notes of step k-1), as choose_dir decides for one graph,
-// its L_r, the ranges that go bottom-up; block 0 records the slots' state after step k.
-__device__ __forceinline__ void slot_setup(const RoundCtx& c, int k, SrvShared& ss) {
+// Server mode, start of step k (wave 0, one lane per slot), round r: each slot's mode and, in
+// rounds mode, its direction from its own frontier (the notes of step k-1), as next_state and
+// choose_dir decide for one graph; its L_r; the ranges that pull.  Block 0 records the slots'
+// state after step k and reports a slot found done (through mapped host memory).
+__device__ __forceinline__ void slot_setup(const RoundCtx& c, int k, int r, SrvShared& ss) {
   if (threadIdx.x >= WAVE) return;
   const int s = threadIdx.x;  // MAX_SLOTS == WAVE
-  int dir = DIR_TD, bu_len = 0;
-  long long bu_beg = 0;
+  int td = TD_SKIP, wake = 0, seed = 0, pull_len = 0;
+  long long pull_beg = 0;
   u64 L = INF, nf = 0;
   if (s < c.nslots) {
     const SlotInfo sl = c.slots[s];
@@ -685,38 +718,70 @@ __device__ __forceinline__ void slot_setup(const RoundCtx& c, int k, SrvShared& 
     const u64 lr = c.s_lr[((k - 1) % 3) * MAX_SLOTS + s];
     nf = cnt >> 32;
     const u64 af = cnt & 0xffffffffull;
-    const long long ua = p.ua - (long long)af;
-    if (sl.active && nf) {
-      if (c.dir_policy == DIR_TD || c.dir_policy == DIR_BU) {
-        dir = c.dir_policy;
+    SlotState q = p;
+    q.dir = DIR_TD;
+    bool report = false;
+    if (sl.active && p.mode == SM_ROUNDS) {
+      q.settled += (long long)nf;
+      q.ua -= (long long)af;
+      const long long n_act = c.wake_tab[sl.wbase + sl.R];
+      const long long left = n_act - q.settled;
+      const long long rho = (long long)r - sl.r0;
+      if (left <= 0) {  // every vertex reached: the round that reached the last one ended
+        q.mode = SM_DONE;
+        report = true;
+      } else if (c.tail_den > 0 && left * c.tail_den <= n_act && sl.R - rho > c.tail_min_left) {
+        q.mode = SM_SEED;
+        seed = 1;
+        pull_len = sl.n;
+        pull_beg = sl.vbeg;
       } else {
-        const u64 n = (u64)sl.n;
-        const bool bu_better = af * (u64)c.td_to_bu > (u64)(ua > 0 ? ua : 0) + n / 4;
-        dir = (p.dir == DIR_BU) ? ((bu_better || nf * (u64)c.bu_to_td >= n) ? DIR_BU : DIR_TD)
-                                : (bu_better ? DIR_BU : DIR_TD);
+        wake = 1;
+        int dir = DIR_TD;
+        if (nf) {
+          if (c.dir_policy == DIR_TD || c.dir_policy == DIR_BU) {
+            dir = c.dir_policy;
+          } else {
+            const u64 n = (u64)sl.n;
+            const bool bu_better = af * (u64)c.td_to_bu > (u64)(q.ua > 0 ? q.ua : 0) + n / 4;
+            dir = (p.dir == DIR_BU) ? ((bu_better || nf * (u64)c.bu_to_td >= n) ? DIR_BU : DIR_TD)
+                                    : (bu_better ? DIR_BU : DIR_TD);
+          }
+        }
+        q.dir = dir;
+        if (dir == DIR_BU) {
+          pull_len = sl.n;
+          pull_beg = sl.vbeg;
+        } else {
+          td = TD_ROUND;
+        }
+      }
+    } else if (sl.active && (p.mode == SM_SEED || p.mode == SM_TAIL)) {
+      if (nf == 0) {  // the last sweep lowered nothing: the labels are the fixpoint
+        q.mode = SM_DONE;
+        report = true;
+      } else {
+        q.mode = SM_TAIL;
+        td = TD_SWEEP;
       }
     }
     L = lr == INF ? INF : lr + ((u64)1 << (FIX + c.B));
-    if (dir == DIR_BU) {
-      bu_len = sl.n;
-      bu_beg = sl.vbeg;
-    }
     if (blockIdx.x == 0) {
-      SlotState q;
-      q.ua = ua;
-      q.dir = dir;
       c.sst[(k & 1) * MAX_SLOTS + s] = q;
       c.s_cnt[((k + 1) % 3) * MAX_SLOTS + s] = 0;
       c.s_lr[((k + 1) % 3) * MAX_SLOTS + s] = INF;
+      if (report) __hip_atomic_store(&c.s_end[s].step, (long long)k, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
   }
-  const u64 td_front = __ballot(dir == DIR_TD && nf > 0);
-  const unsigned incl = wave_incl_scan((unsigned)bu_len);
-  ss.sdir[s] = dir;
+  const u64 td_front = __ballot(td != TD_SKIP && nf > 0);
+  const unsigned incl = wave_incl_scan((unsigned)pull_len);
+  ss.std_[s] = td;
+  ss.swake[s] = wake;
+  ss.sseed[s] = seed;
   ss.sL[s] = L;
   ss.s_cnt[s] = 0;
   ss.s_lr[s] = INF;
-  ss.bseg_beg[s] = bu_beg;
+  ss.bseg_beg[s] = pull_beg;
   ss.bseg_off[s + 1] = (int)incl;
   if (s == 0) {
     ss.bseg_off[0] = 0;
@@ -752,8 +817,11 @@ __device__ __forceinline__ int round_step(const RoundCtx& c, int k, AppendBuf& a
     ab.n = 0;
     ab.arcs = 0;
   }
-  if (SRV) slot_setup(c, k, *ss);
   __syncthreads();
+  if (SRV) {
+    slot_setup(c, k, (int)sh.S.round, *ss);
+    __syncthreads();
+  }
   const RoundState S = sh.S;
   if (S.seq < 0) return MODE_DONE;
   if (blockIdx.x == 0 && threadIdx.x == 0) {

@@ -113,24 +113,28 @@ __device__ __forceinline__ u64 block_max_or(u64 v, u64* red, bool is_or) {
 // admission: check -> load (+ round histogram) -> commit (round offsets, slot entry) -> place
 // ------------------------------------------------------------------------------------------
 // Rows non-decreasing from 0 to nnz, shifts in [0, 2^52]; the request's max shift.
+// Also the request's hub, (degree << 32 | id) of a vertex of largest degree, for the cut.
 __global__ __launch_bounds__(ADM_T) void k_adm_check(AdmBatch b, u64* __restrict__ adm_max,
-                                                     unsigned* __restrict__ adm_err) {
+                                                     unsigned* __restrict__ adm_err, u64* __restrict__ adm_hub) {
   __shared__ u64 red[ADM_T / WAVE];
   const AdmItem& t = b.it[item_of(b, blockIdx.x)];
   const int j = blockIdx.x - t.blk0;
   const long long lo = chunk(t.n, j, t.nblk), hi = chunk(t.n, j + 1, t.nblk);
-  u64 mx = 0, bad = 0;
+  u64 mx = 0, bad = 0, hub = 0;
   for (long long v = lo + threadIdx.x; v < hi; v += ADM_T) {
     const int a = t.rp[v], e = t.rp[v + 1];
     if (e < a || (v == 0 && a != 0) || (v == t.n - 1 && (long long)e != t.nnz)) bad |= ERR_BAD_ROWPTR;
+    else if (e > a && (((u64)(unsigned)(e - a) << 32) | (u64)v) > hub) hub = ((u64)(unsigned)(e - a) << 32) | (u64)v;
     const long long s = t.shift[v];
     if (s < 0 || s > (1ll << 52)) bad |= ERR_BAD_SHIFT;
     else mx = (u64)s > mx ? (u64)s : mx;
   }
   mx = block_max_or(mx, red, false);
+  hub = block_max_or(hub, red, false);
   bad = block_max_or(bad, red, true);
   if (threadIdx.x == 0) {
     if (mx) atomic_max_u64(&adm_max[t.slot], mx);
+    if (hub) atomic_max_u64(&adm_hub[t.slot], hub);
     if (bad) atomic_or_u32(&adm_err[t.slot], (unsigned)bad);
   }
 }
@@ -253,6 +257,8 @@ __global__ __launch_bounds__(ADM_T) void k_adm_commit(AdmBatch b, int max_rounds
     SlotState q;
     q.ua = t.nnz;
     q.dir = DIR_TD;
+    q.mode = SM_ROUNDS;
+    q.settled = 0;
     sst[(k_last & 1) * MAX_SLOTS + t.slot] = q;
     s_cnt[(k_last % 3) * MAX_SLOTS + t.slot] = 0;
     s_lr[(k_last % 3) * MAX_SLOTS + t.slot] = INF;
@@ -292,93 +298,154 @@ __global__ __launch_bounds__(ADM_T) void k_adm_place(AdmBatch b, int max_rounds,
 }
 
 // ------------------------------------------------------------------------------------------
-// finishing: centres + cut -> report
+// finishing: centres, hub piece and rows outside it -> cut over those rows -> report
 // ------------------------------------------------------------------------------------------
-// Centres (request-local ids) of the block's vertices into the caller's buffer, and the arcs
-// of the block's arc range whose ends have different centres.  The arc range is walked in tiles
-// of FIN_T arcs with a window of row offsets in LDS (rows of degree 0 can end a window before
-// the tile; the walk then moves the window).  Centres compare as the labels' id bits.
-__global__ __launch_bounds__(FIN_T) void k_fin(FinBatch b, int B, const u64* __restrict__ P,
-                                               const int* __restrict__ rp_g, const int* __restrict__ col_g,
-                                               const SlotInfo* __restrict__ slots, u64* __restrict__ cut_acc) {
+// The cut counts the arcs whose ends have different centres, twice per cut edge.  With H the
+// piece of the request's hub, an edge between H and the rest is cut, an edge inside H is not:
+// so only the rows outside H are read.  An arc from outside H into H counts 2 (its reverse is
+// not read), an arc between two vertices outside H counts 1 if their centres differ (its
+// reverse counts the other 1).  RMAT-like requests have almost all arcs inside H.
+
+// Vertex chunks aligned to 64 vertices (the slot starts on a multiple of 64), so every bitmap
+// word belongs to one block of one request.
+__device__ __forceinline__ long long chunk64(long long n, int j, int nb) {
+  return j == nb ? n : (((n * j / nb) >> 6) << 6);
+}
+
+// Centres (request-local ids) into the caller's buffer, the bit of H of every vertex, and the
+// rows outside H with arcs, listed as (arc prefix << 32 | local id) in the slot's shift area
+// (shifts are not read once a request is done).
+__global__ __launch_bounds__(FIN_T) void k_fin_vertices(FinBatch b, int B, const u64* __restrict__ P,
+                                                        const int* __restrict__ rp_g, const SlotInfo* __restrict__ slots,
+                                                        const u64* __restrict__ adm_hub, u64* __restrict__ hbits,
+                                                        long long* __restrict__ list, u64* __restrict__ lcnt) {
+  constexpr int NWF = FIN_T / WAVE;
+  __shared__ unsigned w_cnt[NWF], w_arcs[NWF];
+  __shared__ u64 base;
+  const FinItem& t = b.it[item_of(b, blockIdx.x)];
+  const int j = blockIdx.x - t.blk0;
+  const u64 mask = ((u64)1 << B) - 1;
+  const bool ran = slots[t.slot].active != 0;
+  const long long lo = chunk64(t.n, j, t.nblk), hi = chunk64(t.n, j + 1, t.nblk);
+  const u64 hubc = P[t.vbeg + (long long)(adm_hub[t.slot] & 0xffffffffull)] & mask;
+  const unsigned lane = lane_id(), wid = threadIdx.x / WAVE;
+  for (long long v0 = lo; v0 < hi; v0 += FIN_T) {  // uniform trip count over the block
+    const long long v = v0 + threadIdx.x;
+    bool out = false;
+    unsigned deg = 0;
+    bool inH = false;
+    if (v < hi) {
+      const u64 c = P[t.vbeg + v] & mask;
+      t.centre[v] = ran ? (int)(c - (u64)t.vbeg) : -1;
+      deg = (unsigned)(rp_g[t.vbeg + v + 1] - rp_g[t.vbeg + v]);
+      inH = c == hubc;
+      out = ran && !inH && deg > 0;
+    }
+    const u64 hb = __ballot(inH);
+    if (lane == 0 && v0 + wid * WAVE < hi) hbits[(t.vbeg + v0 + wid * WAVE) >> 6] = hb;
+    const u64 om = __ballot(out);
+    const unsigned incl = wave_incl_scan(out ? deg : 0u);
+    if (lane == WAVE - 1) {
+      w_cnt[wid] = (unsigned)__popcll(om);
+      w_arcs[wid] = incl;
+    }
+    __syncthreads();
+    unsigned bc = 0, ba = 0, tc = 0, ta = 0;
+    for (int w = 0; w < NWF; ++w) {
+      if (w < (int)wid) {
+        bc += w_cnt[w];
+        ba += w_arcs[w];
+      }
+      tc += w_cnt[w];
+      ta += w_arcs[w];
+    }
+    if (tc) {  // uniform
+      if (threadIdx.x == 0) base = atomic_add_u64(&lcnt[t.slot], ((u64)tc << 32) | ta);
+      __syncthreads();
+      if (out) {
+        const unsigned idx = (unsigned)(base >> 32) + bc + rank_below(om);
+        const unsigned pre = (unsigned)base + ba + incl - deg;
+        list[t.vbeg + idx] = (long long)(((u64)pre << 32) | (u64)v);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// The listed rows' arcs, split evenly over the item's blocks, walked in tiles of FIN_T arcs with
+// a window of list entries in LDS.
+__global__ __launch_bounds__(FIN_T) void k_fin_cut(FinBatch b, int B, const u64* __restrict__ P,
+                                                   const int* __restrict__ rp_g, const int* __restrict__ col_g,
+                                                   const u64* __restrict__ hbits, const long long* __restrict__ list,
+                                                   const u64* __restrict__ lcnt, u64* __restrict__ cut_acc) {
   constexpr int T = FIN_T;
-  __shared__ long long w_rp[T + 1];
-  __shared__ int s_v;
+  __shared__ unsigned w_pre[T + 1];
+  __shared__ int w_first[T + 1];
+  __shared__ u64 w_c[T + 1];
+  __shared__ unsigned s_ent;
   __shared__ u64 red[T / WAVE];
   const FinItem& t = b.it[item_of(b, blockIdx.x)];
   const int j = blockIdx.x - t.blk0;
   const u64 mask = ((u64)1 << B) - 1;
-  const long long vlo = chunk(t.n, j, t.nblk), vhi = chunk(t.n, j + 1, t.nblk);
-  // a request that failed its check never ran (its columns were not even copied in)
-  const bool ran = slots[t.slot].active != 0;
-  for (long long v = vlo + threadIdx.x; v < vhi; v += T)
-    t.centre[v] = ran ? (int)((P[t.vbeg + v] & mask) - (u64)t.vbeg) : -1;
-  const int n = t.n;
-  const long long nnz = t.nnz, abeg = t.abeg;
-  const int* rp = rp_g + t.vbeg;  // n + 1 entries (the separator closes the last row)
+  const u64 lc = lcnt[t.slot];
+  const unsigned ne = (unsigned)(lc >> 32), na = (unsigned)lc;
+  const unsigned a_begin = (unsigned)(((u64)na * j) / t.nblk), a_end = (unsigned)(((u64)na * (j + 1)) / t.nblk);
+  const long long* L = list + t.vbeg;
   const u64* Ps = P + t.vbeg;
-  const long long a_begin = ran ? chunk(nnz, j, t.nblk) : 0, a_end = ran ? chunk(nnz, j + 1, t.nblk) : 0;
   u64 cut = 0;
-  if (a_begin < a_end) {  // uniform over the block
+  if (a_begin < a_end) {  // uniform
     if (threadIdx.x == 0) {
-      int lo = 0, hi = n;  // the last row with start <= a_begin
+      unsigned lo = 0, hi = ne;  // the last entry whose arcs start at or before a_begin
       while (hi - lo > 1) {
-        const int mid = (int)(((unsigned)lo + (unsigned)hi) >> 1);
-        if (rp[mid] - abeg <= a_begin) lo = mid;
+        const unsigned mid = (lo + hi) >> 1;
+        if ((unsigned)((u64)L[mid] >> 32) <= a_begin) lo = mid;
         else hi = mid;
       }
-      s_v = lo;
+      s_ent = lo;
     }
     __syncthreads();
-    int v0 = s_v;
-    long long a_cur = a_begin;
-    while (a_cur < a_end) {
-      for (int k = threadIdx.x; k <= T; k += T) w_rp[k] = (v0 + k <= n) ? (long long)rp[v0 + k] - abeg : nnz;
+    unsigned ent = s_ent;
+    for (unsigned tile = a_begin; tile < a_end; tile += T) {
+      for (int kk = threadIdx.x; kk <= T; kk += T) {
+        const unsigned e = ent + kk;
+        if (e < ne) {
+          const u64 x = (u64)L[e];
+          const int v = (int)(x & 0xffffffffull);
+          w_pre[kk] = (unsigned)(x >> 32);
+          w_first[kk] = rp_g[t.vbeg + v];
+          w_c[kk] = Ps[v] & mask;
+        } else {
+          w_pre[kk] = na;
+          w_first[kk] = 0;
+          w_c[kk] = 0;
+        }
+      }
       __syncthreads();
-      const long long win_end = w_rp[T];
-      long long t_end = a_cur + T;
-      if (t_end > a_end) t_end = a_end;
-      if (t_end > win_end) t_end = win_end;
-      const long long a = a_cur + threadIdx.x;
-      if (a < t_end) {
+      const unsigned a = tile + threadIdx.x;
+      if (a < a_end) {
         int lo = 0, hi = T;
         while (hi - lo > 1) {
           const int mid = (lo + hi) >> 1;
-          if (w_rp[mid] <= a) lo = mid;
+          if (w_pre[mid] <= a) lo = mid;
           else hi = mid;
         }
-        cut += (P[col_g[abeg + a]] & mask) != (Ps[v0 + lo] & mask);
+        const long long w = (long long)col_g[(long long)w_first[lo] + (a - w_pre[lo])];  // arena id
+        if ((hbits[w >> 6] >> (w & 63)) & 1) cut += 2;
+        else cut += (P[w] & mask) != w_c[lo];
+      }
+      const unsigned next = tile + T;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        int lo = 0, hi = T + 1;
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (w_pre[mid] <= next) lo = mid;
+          else hi = mid;
+        }
+        s_ent = ent + lo;
       }
       __syncthreads();
-      if (t_end >= win_end && t_end < a_end) {
-        v0 += T;
-        if (threadIdx.x == 0) {
-          int lo = v0, hi = n;
-          while (hi - lo > 1) {
-            const int mid = (int)(((unsigned)lo + (unsigned)hi) >> 1);
-            if (rp[mid] - abeg <= t_end) lo = mid;
-            else hi = mid;
-          }
-          s_v = lo;
-        }
-        __syncthreads();
-        v0 = s_v;
-        __syncthreads();
-      } else if (t_end < a_end) {
-        if (threadIdx.x == 0) {
-          int lo = 0, hi = T;
-          while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (w_rp[mid] <= t_end) lo = mid;
-            else hi = mid;
-          }
-          s_v = v0 + lo;
-        }
-        __syncthreads();
-        v0 = s_v;
-        __syncthreads();
-      }
-      a_cur = t_end;
+      ent = s_ent;
     }
   }
   cut = wave_sum_u64(cut);
@@ -394,8 +461,8 @@ __global__ __launch_bounds__(FIN_T) void k_fin(FinBatch b, int B, const u64* __r
 // One thread per finished request: the report (cut, error bits, then done), and the slot's
 // per-request state cleared for the next occupant.
 __global__ void k_fin_out(FinBatch b, u64* __restrict__ cut_acc, unsigned* __restrict__ adm_err,
-                          u64* __restrict__ adm_max, const Ctrl* __restrict__ ctrl, SlotInfo* __restrict__ slots,
-                          SlotReport* rep) {
+                          u64* __restrict__ adm_max, u64* __restrict__ adm_hub, u64* __restrict__ lcnt,
+                          const Ctrl* __restrict__ ctrl, SlotInfo* __restrict__ slots, SlotReport* rep) {
   const int i = threadIdx.x;
   if (blockIdx.x != 0 || i >= b.count) return;
   const int s = b.it[i].slot;
@@ -405,6 +472,8 @@ __global__ void k_fin_out(FinBatch b, u64* __restrict__ cut_acc, unsigned* __res
   cut_acc[s] = 0;
   adm_err[s] = 0;
   adm_max[s] = 0;
+  adm_hub[s] = 0;
+  lcnt[s] = 0;
   slots[s].active = 0;
   __hip_atomic_store(&rep[s].done, 1ll, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
@@ -532,7 +601,10 @@ struct ldd_server {
   void *rp_g = nullptr, *col_g = nullptr, *shift_g = nullptr, *wake_tab = nullptr, *cnt = nullptr, *cur = nullptr;
   void *slots = nullptr, *st = nullptr, *qcnt = nullptr, *lr_part = nullptr, *lb = nullptr, *ex_part = nullptr;
   void *ctrl = nullptr, *adm_max = nullptr, *adm_err = nullptr, *cut_acc = nullptr;
-  void *vslot = nullptr, *sst = nullptr, *s_cnt = nullptr, *s_lr = nullptr;
+  void *vslot = nullptr, *sst = nullptr, *s_cnt = nullptr, *s_lr = nullptr, *stamp = nullptr;
+  void *adm_hub = nullptr, *hbits = nullptr, *lcnt = nullptr;
+  SlotEnd* s_end = nullptr;      // mapped host memory: the step each slot was found done
+  SlotEnd* s_end_dev = nullptr;  // its device address
   SlotReport* rep = nullptr;      // mapped host memory
   SlotReport* rep_dev = nullptr;  // its device address
   RangeAlloc valloc, aalloc;
@@ -567,6 +639,10 @@ namespace {
 
 long long round_at(const ldd_server* srv, long long k) { return srv->round_base + (k - 1); }
 
+// A request's vertex range: its n vertices and the separator, rounded up to 64 vertices so that
+// every range starts on a bitmap word.
+long long vrange(int n) { return (((long long)n + 1 + 63) >> 6) << 6; }
+
 hipEvent_t get_event(ldd_server* srv) {
   {
     std::lock_guard<std::mutex> lk(srv->ev_mu);
@@ -598,8 +674,8 @@ ldd_status srv_alloc(ldd_server* srv, void** p, size_t bytes) {
 }
 
 // Device bytes per arena vertex (label, two queues with arc prefixes, wake order, row offset,
-// shift, slot) and per arena arc (column id).
-constexpr long long BYTES_PER_VERTEX = 8 + 8 + 8 + 4 + 4 + 8 + 1;
+// shift, slot, tail stamp) and per arena arc (column id).
+constexpr long long BYTES_PER_VERTEX = 8 + 8 + 8 + 4 + 4 + 8 + 1 + 4;
 constexpr long long BYTES_PER_ARC = 4;
 
 ldd_status srv_setup(ldd_server* srv) {
@@ -622,12 +698,17 @@ ldd_status srv_setup(ldd_server* srv) {
       (s = srv_alloc(srv, &srv->ctrl, sizeof(Ctrl))) || (s = srv_alloc(srv, &srv->adm_max, MAX_SLOTS * 8)) ||
       (s = srv_alloc(srv, &srv->adm_err, MAX_SLOTS * 4)) || (s = srv_alloc(srv, &srv->cut_acc, MAX_SLOTS * 8)) ||
       (s = srv_alloc(srv, &srv->vslot, V + 1)) || (s = srv_alloc(srv, &srv->sst, 2 * MAX_SLOTS * sizeof(SlotState))) ||
-      (s = srv_alloc(srv, &srv->s_cnt, 3 * MAX_SLOTS * 8)) || (s = srv_alloc(srv, &srv->s_lr, 3 * MAX_SLOTS * 8)))
+      (s = srv_alloc(srv, &srv->s_cnt, 3 * MAX_SLOTS * 8)) || (s = srv_alloc(srv, &srv->s_lr, 3 * MAX_SLOTS * 8)) ||
+      (s = srv_alloc(srv, &srv->stamp, V * 4)) || (s = srv_alloc(srv, &srv->adm_hub, MAX_SLOTS * 8)) ||
+      (s = srv_alloc(srv, &srv->hbits, (V / 64 + 2) * 8)) || (s = srv_alloc(srv, &srv->lcnt, MAX_SLOTS * 8)))
     return s;
   SRV_TRY(hipHostMalloc((void**)&srv->rep, sizeof(SlotReport) * MAX_SLOTS,
                         hipHostMallocMapped | hipHostMallocCoherent));
   memset(srv->rep, 0, sizeof(SlotReport) * MAX_SLOTS);
   SRV_TRY(hipHostGetDevicePointer((void**)&srv->rep_dev, srv->rep, 0));
+  SRV_TRY(hipHostMalloc((void**)&srv->s_end, sizeof(SlotEnd) * MAX_SLOTS, hipHostMallocMapped | hipHostMallocCoherent));
+  memset(srv->s_end, 0, sizeof(SlotEnd) * MAX_SLOTS);
+  SRV_TRY(hipHostGetDevicePointer((void**)&srv->s_end_dev, srv->s_end, 0));
   const hipStream_t q = srv->stream;
   // every vertex is settled (label 0) until a request claims it
   SRV_TRY(hipMemsetAsync(srv->P, 0, V * 8, q));
@@ -642,6 +723,9 @@ ldd_status srv_setup(ldd_server* srv) {
   SRV_TRY(hipMemsetAsync(srv->cut_acc, 0, MAX_SLOTS * 8, q));
   SRV_TRY(hipMemsetAsync(srv->lr_part, 0xff, 2 * (size_t)RT * 8, q));
   SRV_TRY(hipMemsetAsync(srv->vslot, 0, V + 1, q));
+  SRV_TRY(hipMemsetAsync(srv->stamp, 0, V * 4, q));  // stamps are step numbers (>= 1)
+  SRV_TRY(hipMemsetAsync(srv->adm_hub, 0, MAX_SLOTS * 8, q));
+  SRV_TRY(hipMemsetAsync(srv->lcnt, 0, MAX_SLOTS * 8, q));
   SRV_TRY(hipMemsetAsync(srv->sst, 0, 2 * MAX_SLOTS * sizeof(SlotState), q));
   SRV_TRY(hipMemsetAsync(srv->s_cnt, 0, 3 * MAX_SLOTS * 8, q));
   SRV_TRY(hipMemsetAsync(srv->s_lr, 0xff, 3 * MAX_SLOTS * 8, q));
@@ -683,14 +767,14 @@ ldd_status srv_setup(ldd_server* srv) {
   c.wake_q = 0;
   c.qcnt = (u64*)srv->qcnt;
   c.lr_part = (u64*)srv->lr_part;
-  c.stamp = nullptr;  // the tail is never entered
+  c.stamp = (unsigned*)srv->stamp;
   c.st = (RoundState*)srv->st;
   c.ctrl = (Ctrl*)srv->ctrl;
   c.dir_policy = srv->cfg.direction;
   c.td_to_bu = 14;
   c.bu_to_td = 24;
-  c.tail_den = 0;
-  c.tail_min_left = 0;
+  c.tail_den = srv->cfg.tail_vertices == 0 ? 64 : (srv->cfg.tail_vertices < 0 ? 0 : srv->cfg.tail_vertices);
+  c.tail_min_left = 16;
   c.host_st = nullptr;
   c.ex_part = (u64*)srv->ex_part;
   c.slots = (const SlotInfo*)srv->slots;
@@ -700,6 +784,7 @@ ldd_status srv_setup(ldd_server* srv) {
   c.sst = (SlotState*)srv->sst;
   c.s_cnt = (u64*)srv->s_cnt;
   c.s_lr = (u64*)srv->s_lr;
+  c.s_end = srv->s_end_dev;
   lb.kbase = 1;
   SRV_TRY(hipMemcpyAsync(srv->lb, &lb, sizeof(LaunchBlock), hipMemcpyHostToDevice, q));
   SRV_TRY(hipStreamSynchronize(q));
@@ -722,6 +807,7 @@ volatile SlotReport& report(ldd_server* srv, int slot) { return ((volatile SlotR
 
 // The slot's report is cleared before its admission is enqueued (the device writes it later).
 void rep_reset(ldd_server* srv, int slot) {
+  ((volatile SlotEnd*)srv->s_end)[slot].step = 0;
   volatile SlotReport& rp = report(srv, slot);
   rp.done = 0;
   rp.R = -1;
@@ -762,7 +848,8 @@ ldd_status srv_admit(ldd_server* srv, const std::vector<Request*>& rs) {
       nblk += t.nblk;
       rep_reset(srv, r->slot);
     }
-    hipLaunchKernelGGL(k_adm_check, dim3(nblk), dim3(ADM_T), 0, s, ab, (u64*)srv->adm_max, (unsigned*)srv->adm_err);
+    hipLaunchKernelGGL(k_adm_check, dim3(nblk), dim3(ADM_T), 0, s, ab, (u64*)srv->adm_max, (unsigned*)srv->adm_err,
+                       (u64*)srv->adm_hub);
     hipLaunchKernelGGL(k_adm_load, dim3(nblk), dim3(ADM_T), 0, s, ab, srv->C, srv->B, srv->max_rounds,
                        (const u64*)srv->adm_max, (unsigned*)srv->adm_err, (int*)srv->rp_g, (int*)srv->col_g,
                        (long long*)srv->shift_g, (u64*)srv->P, (unsigned char*)srv->vslot, (unsigned*)srv->cnt);
@@ -782,26 +869,36 @@ ldd_status srv_admit(ldd_server* srv, const std::vector<Request*>& rs) {
 ldd_status srv_finish(ldd_server* srv, const std::vector<Request*>& rs) {
   const hipStream_t s = srv->stream;
   for (size_t b0 = 0; b0 < rs.size(); b0 += MAX_BATCH) {
-    FinBatch fb{};
-    int nblk = 0;
-    for (size_t i = b0; i < rs.size() && fb.count < MAX_BATCH; ++i) {
+    FinBatch fv{}, fc{};
+    int nv = 0, nc = 0;
+    for (size_t i = b0; i < rs.size() && fv.count < MAX_BATCH; ++i) {
       Request* r = rs[i];
-      FinItem& t = fb.it[fb.count++];
+      FinItem t{};
       t.centre = r->q.centre;
       t.vbeg = r->vbeg;
       t.abeg = r->abeg;
       t.nnz = r->q.nnz;
       t.n = r->q.n;
       t.slot = r->slot;
-      t.blk0 = nblk;
-      t.nblk = (int)std::max<long long>(1, std::min<long long>(2048, (r->q.n + r->q.nnz + 8191) / 8192));
-      nblk += t.nblk;
+      t.blk0 = nv;
+      t.nblk = (int)std::max<long long>(1, std::min<long long>(1024, ((long long)r->q.n + 16383) / 16384));
+      nv += t.nblk;
+      fv.it[fv.count++] = t;
+      t.blk0 = nc;
+      t.nblk = (int)std::max<long long>(1, std::min<long long>(1024, r->q.nnz / 65536));
+      nc += t.nblk;
+      fc.it[fc.count++] = t;
       r->state = RQ_FINISHING;
     }
-    hipLaunchKernelGGL(k_fin, dim3(nblk), dim3(FIN_T), 0, s, fb, srv->B, (const u64*)srv->P, (const int*)srv->rp_g,
-                       (const int*)srv->col_g, (const SlotInfo*)srv->slots, (u64*)srv->cut_acc);
-    hipLaunchKernelGGL(k_fin_out, dim3(1), dim3(64), 0, s, fb, (u64*)srv->cut_acc, (unsigned*)srv->adm_err,
-                       (u64*)srv->adm_max, (const Ctrl*)srv->ctrl, (SlotInfo*)srv->slots, srv->rep_dev);
+    hipLaunchKernelGGL(k_fin_vertices, dim3(nv), dim3(FIN_T), 0, s, fv, srv->B, (const u64*)srv->P,
+                       (const int*)srv->rp_g, (const SlotInfo*)srv->slots, (const u64*)srv->adm_hub,
+                       (u64*)srv->hbits, (long long*)srv->shift_g, (u64*)srv->lcnt);
+    hipLaunchKernelGGL(k_fin_cut, dim3(nc), dim3(FIN_T), 0, s, fc, srv->B, (const u64*)srv->P, (const int*)srv->rp_g,
+                       (const int*)srv->col_g, (const u64*)srv->hbits, (const long long*)srv->shift_g,
+                       (const u64*)srv->lcnt, (u64*)srv->cut_acc);
+    hipLaunchKernelGGL(k_fin_out, dim3(1), dim3(64), 0, s, fv, (u64*)srv->cut_acc, (unsigned*)srv->adm_err,
+                       (u64*)srv->adm_max, (u64*)srv->adm_hub, (u64*)srv->lcnt, (const Ctrl*)srv->ctrl,
+                       (SlotInfo*)srv->slots, srv->rep_dev);
     SRV_TRY(hipGetLastError());
   }
   return LDD_OK;
@@ -848,7 +945,7 @@ ldd_status engine_loop(ldd_server* srv) {
       }
       {
         std::lock_guard<std::mutex> lk(srv->mu);
-        srv->valloc.give(r->vbeg, (long long)r->q.n + 1);
+        srv->valloc.give(r->vbeg, vrange(r->q.n));
         srv->aalloc.give(r->abeg, r->q.nnz);
         srv->slot_req[r->slot] = nullptr;
         r->status = status_of(err);
@@ -904,10 +1001,10 @@ ldd_status engine_loop(ldd_server* srv) {
         for (int i = 0; i < nslots && slot < 0; ++i)
           if (!srv->slot_req[i]) slot = i;
         if (slot < 0) break;
-        const long long vb = srv->valloc.take((long long)r->q.n + 1);
+        const long long vb = srv->valloc.take(vrange(r->q.n));
         const long long ab = vb < 0 ? -1 : srv->aalloc.take(r->q.nnz);
         if (ab < 0) {
-          if (vb >= 0) srv->valloc.give(vb, (long long)r->q.n + 1);
+          if (vb >= 0) srv->valloc.give(vb, vrange(r->q.n));
           break;
         }
         srv->queue.pop_front();
@@ -942,10 +1039,18 @@ ldd_status engine_loop(ldd_server* srv) {
     batch.clear();
     for (int i = 0; i < nslots; ++i) {
       Request* r = srv->slot_req[i];
-      if (r && r->state == RQ_ACTIVE && r->R >= 0 && r->first_step + std::max(r->R, 1) - 1 < srv->steps) {
+      if (!r || r->state != RQ_ACTIVE || r->R < 0) continue;
+      // inert (failed its check), or found done by a step: that step consumed the request's
+      // last frontier, so no later step refers to its vertex ids once they are released
+      const long long end = __atomic_load_n(&((volatile SlotEnd*)srv->s_end)[i].step, __ATOMIC_ACQUIRE);
+      if (r->R == 0 || end > 0) {
         batch.push_back(r);
         finishing.push_back(r);
         --active;
+      } else if (srv->steps > r->first_step + r->R + 4 * srv->cfg.chunk_steps + 8) {
+        snprintf(srv->fatal_msg, sizeof(srv->fatal_msg), "request in slot %d not done %lld steps after its last round",
+                 i, srv->steps - (r->first_step + r->R));
+        return LDD_ERR_INTERNAL;
       }
     }
     if (!batch.empty()) {
@@ -1005,7 +1110,7 @@ extern "C" ldd_status ldd_server_create(const ldd_server_config* cfg, ldd_server
   if (srv->cfg.max_slots <= 0 || srv->cfg.max_slots > MAX_SLOTS) srv->cfg.max_slots = MAX_SLOTS;
   if (srv->cfg.chunk_steps <= 0) srv->cfg.chunk_steps = 8;
   if (srv->cfg.chunk_steps > 64 || srv->cfg.direction < 0 || srv->cfg.direction > 2 || srv->cfg.blocks < 0 ||
-      srv->cfg.max_rounds < 0) {
+      srv->cfg.max_rounds < 0 || srv->cfg.tail_vertices < -1) {
     delete srv;
     ldd_set_error("bad server configuration");
     return LDD_ERR_INVALID_ARG;
@@ -1064,7 +1169,7 @@ extern "C" ldd_status ldd_server_submit(ldd_server* srv, const ldd_request* req,
     ldd_set_error("bad request");
     return LDD_ERR_INVALID_ARG;
   }
-  if ((long long)req->n + 1 > srv->vcap || req->nnz > srv->acap) {
+  if (vrange(req->n) > srv->vcap || req->nnz > srv->acap) {
     ldd_set_error("request of %d vertices and %lld arcs exceeds the arena (%lld, %lld)", req->n,
                   (long long)req->nnz, srv->vcap, srv->acap);
     return LDD_ERR_BUDGET;
@@ -1205,9 +1310,10 @@ extern "C" ldd_status ldd_server_destroy(ldd_server* srv) {
   for (void* p : {srv->P, srv->qv0, srv->qv1, srv->qa0, srv->qa1, srv->wake_ord, srv->rp_g, srv->col_g, srv->shift_g,
                   srv->wake_tab, srv->cnt, srv->cur, srv->slots, srv->st, srv->qcnt, srv->lr_part, srv->lb,
                   srv->ex_part, srv->ctrl, srv->adm_max, srv->adm_err, srv->cut_acc, srv->vslot, srv->sst,
-                  srv->s_cnt, srv->s_lr})
+                  srv->s_cnt, srv->s_lr, srv->stamp, srv->adm_hub, srv->hbits, srv->lcnt})
     if (p) (void)hipFree(p);
   if (srv->rep) (void)hipHostFree(srv->rep);
+  if (srv->s_end) (void)hipHostFree(srv->s_end);
   if (srv->graph) (void)hipGraphExecDestroy(srv->graph);
   for (auto& e : srv->chunk_ev)
     if (e) (void)hipEventDestroy(e);

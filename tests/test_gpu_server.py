@@ -96,6 +96,21 @@ def test_served_mix_equals_oracle_with_arrivals_in_flight(ldd):
         assert info["max_active"] > 1
 
 
+@pytest.mark.parametrize("cfg", [dict(tail_vertices=-1), dict(tail_vertices=1), dict(direction=1),
+                                 dict(direction=2), dict(direction=2, tail_vertices=-1), dict(chunk_steps=1),
+                                 dict(blocks=5)])
+def test_served_schedules_agree_with_oracle(ldd, cfg):
+    """Whatever each request's schedule (rounds only, tail from the first step, forced
+    directions, chunking, grid size), every served result is the oracle's."""
+    reqs = request_mix(seed=21, count=15)
+    with ldd.Server(max_vertices=1 << 17, max_arcs=1 << 21, max_slots=6, **cfg) as srv:
+        devs = [to_dev(rp, ci, s) for rp, ci, s, _ in reqs]
+        tickets = [srv.submit(*d) for d in devs]
+        results = [srv.wait(t) for t in tickets]
+    for (rp, ci, s, name), res in zip(reqs, results):
+        check(ldd, res, rp, ci, s, f"{name} {cfg}")
+
+
 def test_served_equals_single_graph_path(ldd):
     """The same request, served in a mix, and decomposed alone by ldd_decompose."""
     reqs = request_mix(seed=11, count=10)
