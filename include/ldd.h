@@ -154,7 +154,7 @@ ldd_status ldd_decompose_batch(int32_t num_graphs, const int64_t* vtx_off, const
 typedef struct ldd_server ldd_server;
 
 typedef struct {
-  int64_t hbm_budget_bytes; /* arena size in device bytes; split as 45 B per vertex + 4 B per   */
+  int64_t hbm_budget_bytes; /* arena size in device bytes; split as 44 B per vertex + 4 B per   */
                             /* arc for graphs of about 16 arcs per vertex unless max_* are set */
                             /* (arcs at most 2^31 - 1, the rest to vertices, at most 2^30)     */
   int64_t max_vertices;     /* arena vertices (a request takes n + 1 rounded up to 64); 0 = from the budget */

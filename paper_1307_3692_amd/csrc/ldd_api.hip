@@ -399,7 +399,6 @@ static ldd_status decompose_impl(Workspace& w, const ldd_csr* g, const int64_t* 
   c.slots = nullptr;
   c.nslots = 0;
   c.wake_tab = nullptr;
-  c.vslot = nullptr;
   c.sst = nullptr;
   c.s_cnt = nullptr;
   c.s_lr = nullptr;

@@ -91,15 +91,14 @@ struct RoundCtx {
   int tail_min_left;  // ... and more than this many rounds remain
   RoundState* host_st;  // pinned host mirror of the latest state (may be null)
   u64* ex_part;     // [G]: arcs examined by each block over all steps (statistics)
-  // server mode (slots != null): every step is the next global round, no tail, never "done";
-  // round r's wakers are those of every active slot's local round r - r0; each slot takes its
-  // own direction from its own frontier
+  // server mode (k_round_step_srv): every step is the next global round for every slot; round
+  // r's wakers are those of every slot's local round r - r0 in rounds mode; each slot has its
+  // own mode and direction, and its frontier queued in its own vertex range of qv / qa
   const SlotInfo* slots;
   int nslots;
   const int* wake_tab;
-  const unsigned char* vslot;  // slot of every arena vertex
   SlotState* sst;              // [2][MAX_SLOTS]
-  u64* s_cnt;                  // [3][MAX_SLOTS]: (count << 32 | arcs) appended by step k, at k % 3
+  u64* s_cnt;                  // [3][MAX_SLOTS]: (count << 32 | arcs) queued by step k, at k % 3
   u64* s_lr;                   // [3][MAX_SLOTS]: smallest label written by step k, at k % 3
   SlotEnd* s_end;              // [MAX_SLOTS], mapped host memory
 };

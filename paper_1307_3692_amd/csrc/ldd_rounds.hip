@@ -118,48 +118,6 @@ __device__ __forceinline__ void block_append(AppendBuf& ab, bool want, int v, un
   __syncthreads();
 }
 
-// Server mode: per-slot LDS state of a step.
-// what the top-down phase does with a slot's queue entries
-enum { TD_SKIP = 0, TD_ROUND = 1, TD_SWEEP = 2 };
-struct SrvShared {
-  int std_[MAX_SLOTS];   // TD_* of each slot in this step
-  int swake[MAX_SLOTS];  // the slot takes part in this round's wake
-  int sseed[MAX_SLOTS];  // the slot's pull in this step is its tail seed
-  u64 sL[MAX_SLOTS];     // each slot's L_r (its smallest possible offer this round)
-  u64 s_cnt[MAX_SLOTS];  // this block's (count << 32 | arcs) appended per slot
-  u64 s_lr[MAX_SLOTS];   // this block's smallest label written per slot
-  // this round's wake segment of every slot (start in wake_ord, prefix of lengths)
-  long long seg_beg[MAX_SLOTS];
-  int seg_off[MAX_SLOTS + 1];
-  // vertex ranges of the slots that go bottom-up (start, prefix of lengths)
-  long long bseg_beg[MAX_SLOTS];
-  int bseg_off[MAX_SLOTS + 1];
-  unsigned char w_slot[RT + 1];  // slot of each staged top-down entry
-  int skip_to;
-  int any_td;  // some slot with a frontier goes top-down
-};
-
-// Per-slot notes of a tile (server mode): the count and arcs of the vertices appended and the
-// smallest label written, summed per slot over the wave, then one LDS atomic per slot present.
-// Called by every lane of the wave (the loop count is wave-uniform).
-__device__ __forceinline__ void slot_note(SrvShared& ss, bool wrote, bool want, int slot, unsigned deg, u64 label) {
-  const bool any = wrote || want;
-  u64 pending = __ballot(any);
-  while (pending) {
-    const int leader = (int)__builtin_ctzll(pending);
-    const int sl = __shfl(slot, leader, WAVE);
-    const bool mine = any && slot == sl;
-    const u64 m = __ballot(mine);
-    const u64 cnt = wave_sum_u64(mine && want ? (((u64)1 << 32) | deg) : 0);
-    const u64 lab = wave_min_u64(mine && wrote ? label : INF);
-    if ((int)lane_id() == leader) {
-      if (cnt) atomicAdd(&ss.s_cnt[sl], cnt);
-      if (lab != INF) atomicMin(&ss.s_lr[sl], lab);
-    }
-    pending &= ~m;
-  }
-}
-
 __device__ __forceinline__ u64 block_min_u64(u64 v, StepShared& sh) {
   v = wave_min_u64(v);
   const unsigned wid = threadIdx.x / WAVE;
@@ -182,64 +140,6 @@ __device__ __forceinline__ u64 own_offer(const RoundCtx& c, int v) {
 }
 
 // ---- round r: wake bucket r (the delayed source arcs of length in [r, r+1) units) ----------
-// Server mode: the wakers of global round r are, for every active slot with r0 <= r < r0 + R,
-// the vertices of its local round r - r0 (a segment of its part of wake_ord).
-__device__ __forceinline__ void phase_wake_slots(const RoundCtx& c, int r, int k, AppendBuf& ab, SrvShared& sh) {
-  if (threadIdx.x < WAVE) {
-    const int t = threadIdx.x;
-    int len = 0;
-    long long beg = 0;
-    if (t < c.nslots) {
-      const SlotInfo sl = c.slots[t];
-      const long long rho = (long long)r - sl.r0;
-      if (sh.swake[t] && rho >= 0 && rho < sl.R) {
-        const int lo = c.wake_tab[sl.wbase + rho], hi = c.wake_tab[sl.wbase + rho + 1];
-        len = hi - lo;
-        beg = sl.vbeg + lo;
-      }
-    }
-    const unsigned incl = wave_incl_scan((unsigned)len);
-    if (t < MAX_SLOTS) {
-      sh.seg_beg[t] = beg;
-      sh.seg_off[t + 1] = (int)incl;
-    }
-    if (t == 0) sh.seg_off[0] = 0;
-  }
-  __syncthreads();
-  const int ns = c.nslots < MAX_SLOTS ? c.nslots : MAX_SLOTS;
-  const int cnt = sh.seg_off[ns];
-  for (long long base = (long long)blockIdx.x * RT; base < cnt; base += (long long)gridDim.x * RT) {
-    const long long i = base + threadIdx.x;
-    bool want = false, wrote = false;
-    int v = 0, slot = 0;
-    unsigned deg = 0;
-    u64 self = INF;
-    if (i < cnt) {
-      int lo = 0, hi = ns;  // last slot with seg_off <= i
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (sh.seg_off[mid] <= i) lo = mid;
-        else hi = mid;
-      }
-      slot = lo;
-      v = c.wake_ord[sh.seg_beg[lo] + (i - sh.seg_off[lo])];
-      self = own_offer(c, v);
-      if (c.P[v] > self) {
-        const u64 old = atomic_min_u64(&c.P[v], self);
-        if (old > self) {
-          wrote = true;
-          if (old == INF) {
-            want = true;
-            deg = degree(c, v);
-          }
-        }
-      }
-    }
-    slot_note(sh, wrote, want, slot, deg, self);
-    block_append(ab, want, v, deg, c, k);
-  }
-}
-
 // With the q-layout, round r's wakers are the vertices of bucket q = D - r whose shift's
 // fractional part is <= that of Delta, and those of bucket D - r - 1 whose fractional part
 // is larger; the two buckets are adjacent in wake_ord.
@@ -292,11 +192,9 @@ __device__ __forceinline__ void phase_wake(const RoundCtx& c, int r, int k, Appe
 // TAIL = false: round step; an arc appends its far end if it is reached for the first time.
 // TAIL = true: tail sweep `sweep`; an arc appends its far end whenever it lowered the label
 // and the far end is not queued for the next sweep yet.
-// SRV: server mode; the entries of slots that go bottom-up this round are skipped, a whole
-// staged window at a time where they are contiguous.
-template <bool TAIL, bool SRV>
+template <bool TAIL>
 __device__ __forceinline__ void phase_top_down(const RoundCtx& c, int k, const int* qv, const unsigned* qa, unsigned nf, unsigned af,
-                               AppendBuf& ab, StepShared& sh, u64& wmin, unsigned sweep, SrvShared* ss) {
+                               AppendBuf& ab, StepShared& sh, u64& wmin, unsigned sweep) {
   unsigned* w_pre = sh.w_pre;
   int* w_first = sh.w_first;
   u64* w_offer = sh.w_offer;
@@ -316,19 +214,13 @@ __device__ __forceinline__ void phase_top_down(const RoundCtx& c, int k, const i
   }
   __syncthreads();
   unsigned ent = sh.start;
-  unsigned tile = a_begin;
-  while (tile < a_end) {
+  for (unsigned tile = a_begin; tile < a_end; tile += RT) {
     for (int kk = threadIdx.x; kk <= RT; kk += RT) {
       const unsigned e = ent + kk;
       if (e < nf) {
         const int u = qv[e];
         w_pre[kk] = qa[e];
-        bool ok = (unsigned)u < (unsigned)c.n;
-        if (SRV) {
-          const int sl = ok ? c.vslot[u] : 0;
-          ss->w_slot[kk] = (unsigned char)sl;
-          ok = ok && ss->std_[sl] != TD_SKIP;
-        }
+        const bool ok = (unsigned)u < (unsigned)c.n;
         w_first[kk] = ok ? c.row_ptr[u] : 0;
         const u64 pu = ok ? load_u64_relaxed(&c.P[u]) : INF;
         w_offer[kk] = pu == INF ? INF : pu + unit;
@@ -340,10 +232,9 @@ __device__ __forceinline__ void phase_top_down(const RoundCtx& c, int k, const i
     }
     __syncthreads();
     const unsigned a = tile + threadIdx.x;
-    bool want = false, wrote = false;
-    int w = 0, slot = 0;
+    bool want = false;
+    int w = 0;
     unsigned deg = 0;
-    u64 offer = INF;
     if (a < a_end) {
       int lo = 0, hi = RT;  // last kk in [0, RT) with w_pre[kk] <= a
       while (hi - lo > 1) {
@@ -351,8 +242,7 @@ __device__ __forceinline__ void phase_top_down(const RoundCtx& c, int k, const i
         if (w_pre[mid] <= a) lo = mid;
         else hi = mid;
       }
-      offer = w_offer[lo];
-      if (SRV) slot = ss->w_slot[lo];
+      const u64 offer = w_offer[lo];
       const unsigned j = a - w_pre[lo];
       const long long arc = (long long)w_first[lo] + j;
       // j < degree and arc < nnz hold for a symmetric CSR; checked so that malformed input
@@ -363,14 +253,7 @@ __device__ __forceinline__ void phase_top_down(const RoundCtx& c, int k, const i
         if (c.P[w] > offer) {
           const u64 old = atomic_min_u64(&c.P[w], offer);
           if (old > offer) {
-            if (SRV && ss->std_[slot] == TD_SWEEP) {  // the slot's tail: queue on any lowering
-              wrote = true;
-              if (__hip_atomic_fetch_max(&c.stamp[w], (unsigned)k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
-                  (unsigned)k) {
-                want = true;
-                deg = degree(c, w);
-              }
-            } else if (TAIL) {
+            if (TAIL) {
               if (__hip_atomic_fetch_max(&c.stamp[w], sweep + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
                   sweep + 1) {
                 want = true;
@@ -378,7 +261,6 @@ __device__ __forceinline__ void phase_top_down(const RoundCtx& c, int k, const i
               }
             } else {
               wmin = offer < wmin ? offer : wmin;
-              wrote = true;
               if (old == INF) {
                 want = true;
                 deg = degree(c, w);
@@ -390,10 +272,9 @@ __device__ __forceinline__ void phase_top_down(const RoundCtx& c, int k, const i
         atomic_or_u32(&c.ctrl->err, ERR_BAD_COL);
       }
     }
-    if (SRV) slot_note(*ss, wrote, want, slot, deg, offer);
     block_append(ab, want, w, deg, c, k);
     // the entry holding the next tile's first arc is one of ent .. ent+RT (all staged)
-    unsigned next = tile + RT;
+    const unsigned next = tile + RT;
     __syncthreads();
     if (threadIdx.x == 0) {
       int lo = 0, hi = RT + 1;
@@ -402,33 +283,10 @@ __device__ __forceinline__ void phase_top_down(const RoundCtx& c, int k, const i
         if (w_pre[mid] <= next) lo = mid;
         else hi = mid;
       }
-      sh.start = lo;
-      if (SRV) ss->skip_to = RT;
+      sh.start = ent + lo;
     }
     __syncthreads();
-    if (SRV) {
-      // skipped entries from there on: the next tile starts at the first entry that is not
-      // skipped (or at entry RT, the last one staged)
-      const int lo = (int)sh.start;
-      for (int kk = threadIdx.x; kk < RT; kk += RT)
-        if (kk >= lo && w_offer[kk] != INF) atomicMin(&ss->skip_to, kk);
-      __syncthreads();
-      const int to = ss->skip_to;
-      if (to > lo && w_pre[to] > next) next = w_pre[to];
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        int l2 = lo, h2 = RT + 1;  // the entry holding the (possibly moved) tile start
-        while (h2 - l2 > 1) {
-          const int mid = (l2 + h2) >> 1;
-          if (w_pre[mid] <= next) l2 = mid;
-          else h2 = mid;
-        }
-        sh.start = l2;
-      }
-      __syncthreads();
-    }
-    ent += sh.start;
-    tile = next;
+    ent = sh.start;
   }
 }
 
@@ -476,86 +334,6 @@ __device__ __forceinline__ void phase_bottom_up(const RoundCtx& c, int r, int k,
         }
       }
     }
-    block_append(ab, want, v, deg, c, k);
-  }
-}
-
-// Server mode: the same pull over the vertex ranges of the slots that go bottom-up this round,
-// each with its own L_r.
-__device__ __forceinline__ void phase_bottom_up_slots(const RoundCtx& c, int r, int k, AppendBuf& ab, SrvShared& ss) {
-  const int B = c.B;
-  const u64 unit = (u64)1 << (FIX + B);
-  const u64 base_r = (u64)r << (FIX + B);
-  const u64 prev_round = (u64)(r - 1);
-  const int ns = c.nslots < MAX_SLOTS ? c.nslots : MAX_SLOTS;
-  const int cnt = ss.bseg_off[ns];
-  for (long long base = (long long)blockIdx.x * RT; base < cnt; base += (long long)gridDim.x * RT) {
-    const long long i = base + threadIdx.x;
-    bool want = false, wrote = false;
-    int v = 0, slot = 0;
-    unsigned deg = 0;
-    u64 best = INF;
-    if (i < cnt) {
-      int lo = 0, hi = ns;  // last slot with bseg_off <= i
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (ss.bseg_off[mid] <= i) lo = mid;
-        else hi = mid;
-      }
-      slot = lo;
-      v = (int)(ss.bseg_beg[lo] + (i - ss.bseg_off[lo]));
-      const u64 Lr = ss.sL[lo];
-      const bool seed = ss.sseed[lo] != 0;
-      const u64 pv = c.P[v];
-      const int a0 = c.row_ptr[v], a1 = c.row_ptr[v + 1];
-      if (seed && pv >= base_r && a1 > a0) {
-        // tail seed: the vertex's own arc (whatever its wake round) and its neighbours in
-        // F_{r-1}; the sweeps relax the rest, queueing every vertex whose label drops
-        best = own_offer(c, v);
-        for (int a = a0; a < a1 && best > Lr; ++a) {
-          const int u = c.col[a];
-          if ((unsigned)u >= (unsigned)c.n) {
-            atomic_or_u32(&c.ctrl->err, ERR_BAD_COL);
-            break;
-          }
-          const u64 pu = load_u64_relaxed(&c.P[u]);
-          if ((pu >> (FIX + B)) == prev_round && pu != INF && pu + unit < best) best = pu + unit;
-        }
-        if (best < pv) {
-          atomic_min_u64(&c.P[v], best);
-          wrote = true;
-          want = __hip_atomic_fetch_max(&c.stamp[v], (unsigned)k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
-                 (unsigned)k;
-          deg = (unsigned)(a1 - a0);
-        }
-      } else if (!seed && pv >= base_r && pv > Lr) {
-        best = pv;
-        for (int a = a0; a < a1; ++a) {
-          const int u = c.col[a];
-          if ((unsigned)u >= (unsigned)c.n) {
-            atomic_or_u32(&c.ctrl->err, ERR_BAD_COL);
-            break;
-          }
-          const u64 pu = load_u64_relaxed(&c.P[u]);
-          if ((pu >> (FIX + B)) == prev_round && pu != INF) {
-            const u64 offer = pu + unit;
-            if (offer < best) best = offer;
-            if (best <= Lr) break;
-          }
-        }
-        if (best < pv) {
-          const u64 old = atomic_min_u64(&c.P[v], best);
-          if (old > best) {
-            wrote = true;
-            if (old == INF) {
-              want = true;
-              deg = (unsigned)(a1 - a0);
-            }
-          }
-        }
-      }
-    }
-    slot_note(ss, wrote, want, slot, deg, best);
     block_append(ab, want, v, deg, c, k);
   }
 }
@@ -633,7 +411,6 @@ __device__ void store_state(RoundState* p, const RoundState& s) {
 #undef LDD_STORE
 }
 
-template <bool SRV>
 __device__ __forceinline__ RoundState next_state(const RoundCtx& c, int k) {
   const RoundState P = load_state(&c.st[(k - 1) & 1]);
   const u64 out = load_u64_relaxed(qcounter(c, k - 1));
@@ -641,14 +418,6 @@ __device__ __forceinline__ RoundState next_state(const RoundCtx& c, int k) {
   S.seq = k;
   if (P.mode == MODE_DONE) return S;
   const unsigned nf = min((unsigned)(out >> 32), (unsigned)c.n), af = (unsigned)out;
-  if (SRV) {  // server: the next global round, always (directions are per slot)
-    S.settled += nf;
-    S.rounds += 1;
-    S.max_frontier = (long long)nf > S.max_frontier ? (long long)nf : S.max_frontier;
-    S.round = P.round + 1;
-    S.prev = (long long)out;
-    return S;
-  }
   if (P.mode == MODE_ROUNDS) {
     int next_r;
     if (k > 1) {
@@ -701,23 +470,251 @@ __device__ __forceinline__ void add_examined(const RoundCtx& c, u64 examined, St
   }
 }
 
-// Server mode, start of step k (wave 0, one lane per slot), round r: each slot's mode and, in
-// rounds mode, its direction from its own frontier (the notes of step k-1), as next_state and
-// choose_dir decide for one graph; its L_r; the ranges that pull.  Block 0 records the slots'
-// state after step k and reports a slot found done (through mapped host memory).
-__device__ __forceinline__ void slot_setup(const RoundCtx& c, int k, int r, SrvShared& ss) {
+// One step; returns the mode it ran in (MODE_DONE: nothing was left to do).
+__device__ __forceinline__ int round_step(const RoundCtx& c, int k, AppendBuf& ab, StepShared& sh) {
+  if (threadIdx.x == 0) {
+    // Once a step has written "done" into either slot no step writes a slot again, so later
+    // steps only need the two mode words to leave.
+    const bool done = __hip_atomic_load(&c.st[0].mode, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == MODE_DONE ||
+                      __hip_atomic_load(&c.st[1].mode, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == MODE_DONE;
+    if (done) {
+      sh.S.mode = MODE_DONE;
+      sh.S.seq = -1;
+    } else {
+      sh.S = next_state(c, k);
+    }
+    ab.n = 0;
+    ab.arcs = 0;
+  }
+  __syncthreads();
+  const RoundState S = sh.S;
+  if (S.seq < 0) return MODE_DONE;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    store_state<__HIP_MEMORY_SCOPE_AGENT>(&c.st[k & 1], S);
+    __hip_atomic_store(qcounter(c, k + 1), 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // the host stops enqueueing steps once it reads "done"; written once per decomposition,
+    // since a store to host memory delays the completion of the kernel that makes it
+    if (c.host_st && S.mode == MODE_DONE) store_state<__HIP_MEMORY_SCOPE_SYSTEM>(c.host_st, S);
+  }
+  if (S.mode == MODE_DONE) return MODE_DONE;
+  const unsigned nf = min((unsigned)((u64)S.prev >> 32), (unsigned)c.n), af = (unsigned)S.prev;
+  const int* qv = c.qv[(k - 1) & 1];
+  const unsigned* qa = c.qa[(k - 1) & 1];
+  u64 wmin = INF, examined = 0;
+  const bool need_lr = nf && ((S.mode == MODE_ROUNDS && S.dir == DIR_BU) || (S.mode == MODE_TAIL && S.round == 0));
+  if (need_lr) {
+    // L_r: the smallest offer of F_{r-1}, from the per-block minima the previous step left
+    u64 m = INF;
+    for (unsigned b = threadIdx.x; b < gridDim.x; b += RT) {
+      const u64 x = load_u64_relaxed(&c.lr_part[(size_t)((k - 1) & 1) * gridDim.x + b]);
+      m = x < m ? x : m;
+    }
+    m = block_min_u64(m, sh);
+    if (threadIdx.x == 0) sh.lr = m == INF ? INF : m + ((u64)1 << (FIX + c.B));
+    __syncthreads();
+  }
+  if (S.mode == MODE_ROUNDS) {
+    const int r = (int)S.round;
+    phase_wake(c, r, k, ab, wmin);
+    if (nf) {
+      if (S.dir == DIR_BU) {
+        phase_bottom_up(c, r, k, sh.lr, ab, wmin, examined);
+      } else {
+        phase_top_down<false>(c, k, qv, qa, nf, af, ab, sh, wmin, 0);
+        if (blockIdx.x == 0 && threadIdx.x == 0) examined += af;
+      }
+    }
+  } else {
+    const unsigned sweep = (unsigned)S.round;
+    if (sweep == 0) {
+      phase_tail_seed(c, (int)S.tail_round, k, nf ? sh.lr : INF, ab, examined);
+    } else if (nf) {
+      phase_top_down<true>(c, k, qv, qa, nf, af, ab, sh, wmin, sweep);
+      if (blockIdx.x == 0 && threadIdx.x == 0) examined += af;
+    }
+  }
+  block_flush(ab, c, k);
+  const u64 bm = block_min_u64(wmin, sh);
+  if (threadIdx.x == 0) c.lr_part[(size_t)(k & 1) * gridDim.x + blockIdx.x] = bm;
+  add_examined(c, examined, sh);
+  return (int)S.mode;
+}
+
+// (RT, 8): eight waves per SIMD, i.e. two 1024-thread blocks per CU, which caps VGPRs at 64
+__global__ __launch_bounds__(RT, 8) void k_round_step_lb(const LaunchBlock* __restrict__ lb, int j) {
+  __shared__ AppendBuf ab;
+  __shared__ StepShared sh;
+  round_step(lb->c, (int)(lb->kbase + j), ab, sh);
+}
+
+__global__ void k_advance(LaunchBlock* lb, int C) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) lb->kbase += C;
+}
+
+// All steps in one kernel with grid barriers between them (the grid must be co-resident).
+__global__ __launch_bounds__(RT) void k_rounds_persistent(RoundCtx c) {
+  __shared__ AppendBuf ab;
+  __shared__ StepShared sh;
+  u64 gen = 0;
+  const long long kmax = (long long)c.R + c.n + 2;
+  for (int k = 1; k <= kmax; ++k) {
+    if (round_step(c, k, ab, sh) == MODE_DONE) break;
+    grid_sync(&c.ctrl->bar, gridDim.x, gen, &c.ctrl->err);
+    if (__hip_atomic_load(&c.ctrl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & (ERR_BARRIER | ERR_QUEUE)) break;
+  }
+}
+
+// =============================================================================================
+// Server mode
+// =============================================================================================
+// The server's arena is the disjoint union of the admitted requests ("slots").  One step is the
+// next global round for every slot; each slot is in its own mode (rounds, seed, tail sweeps,
+// done) and, in rounds mode, takes its own direction, as next_state and choose_dir decide for
+// one graph.  Each slot's frontier is queued in the slot's own vertex range of the queue arrays
+// (a vertex is queued at most once per step) behind a per-slot reservation counter
+// (count << 32 | arcs), so top-down splits exactly the top-down slots' arcs evenly over the
+// grid, and those counters are each slot's frontier statistics for the next step.
+
+constexpr int SABUF = 2048;  // entries of a block's LDS append buffer in server mode
+enum { TD_SKIP = 0, TD_ROUND = 1, TD_SWEEP = 2 };
+
+struct SrvAppend {
+  int vert[SABUF];
+  u64 loc[SABUF];  // (rank << 32 | arc offset) among the buffered appends of the same slot
+  unsigned char slot[SABUF];
+  u64 tot[MAX_SLOTS];   // (count << 32 | arcs) buffered per slot
+  u64 base[MAX_SLOTS];  // the flush's reservation in each slot's queue
+  unsigned wave_cnt[NW];
+  unsigned n;
+};
+
+struct SrvShared {
+  int td[MAX_SLOTS];    // TD_* of each slot in this step
+  int wake[MAX_SLOTS];  // the slot takes part in this round's wake
+  int seed[MAX_SLOTS];  // the slot's pull in this step is its tail seed
+  int n[MAX_SLOTS];
+  long long vbeg[MAX_SLOTS];
+  u64 L[MAX_SLOTS];      // each slot's L_r: the smallest offer its F_{r-1} makes
+  u64 front[MAX_SLOTS];  // (count << 32 | arcs) of each slot's queue from the previous step
+  u64 lr[MAX_SLOTS];     // this block's smallest label written per slot
+  long long seg_beg[MAX_SLOTS];  // this round's wake segment of every slot
+  int seg_off[MAX_SLOTS + 1];
+  long long pull_beg[MAX_SLOTS];  // vertex ranges that pull (bottom-up or seed)
+  int pull_off[MAX_SLOTS + 1];
+  unsigned td_off[MAX_SLOTS + 1];  // prefix of the top-down slots' frontier arcs
+  unsigned start;
+};
+
+// Reserve the buffered appends in their slots' queues of step k and copy them there.
+__device__ __forceinline__ void srv_flush(SrvAppend& ab, const RoundCtx& c, int k, const SrvShared& ss) {
+  __syncthreads();
+  const unsigned cnt = ab.n;
+  if (cnt == 0) return;
+  if (threadIdx.x < MAX_SLOTS) {
+    const u64 t = ab.tot[threadIdx.x];
+    ab.base[threadIdx.x] = t ? atomic_add_u64(&c.s_cnt[(k % 3) * MAX_SLOTS + threadIdx.x], t) : 0;
+  }
+  __syncthreads();
+  int* qv = c.qv[k & 1];
+  unsigned* qa = c.qa[k & 1];
+  for (unsigned i = threadIdx.x; i < cnt; i += RT) {
+    const int s = ab.slot[i];
+    const u64 b = ab.base[s], x = ab.loc[i];
+    const unsigned idx = (unsigned)(b >> 32) + (unsigned)(x >> 32);
+    if (idx < (unsigned)ss.n[s]) {
+      qv[ss.vbeg[s] + idx] = ab.vert[i];
+      qa[ss.vbeg[s] + idx] = (unsigned)b + (unsigned)x;
+    } else {
+      atomic_or_u32(&c.ctrl->err, ERR_QUEUE);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < MAX_SLOTS) ab.tot[threadIdx.x] = 0;
+  if (threadIdx.x == 0) ab.n = 0;
+  __syncthreads();
+}
+
+// Block-wide append of one tile (every thread calls it): a buffer index per appending thread
+// from ballots, and its rank and arc offset within its slot from a wave-level grouping by slot
+// (one LDS atomic per slot present in the wave).
+__device__ __forceinline__ void srv_append(SrvAppend& ab, bool want, int v, unsigned deg, int slot, const RoundCtx& c,
+                                           int k, const SrvShared& ss) {
+  const unsigned lane = lane_id(), wid = threadIdx.x / WAVE;
+  const u64 mask = __ballot(want);
+  if (lane == 0) ab.wave_cnt[wid] = (unsigned)__popcll(mask);
+  __syncthreads();
+  unsigned wc = 0, tc = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    const unsigned a = ab.wave_cnt[w];
+    if (w < (int)wid) wc += a;
+    tc += a;
+  }
+  if (tc == 0) {
+    __syncthreads();
+    return;
+  }
+  if (ab.n + tc > (unsigned)SABUF) srv_flush(ab, c, k, ss);
+  const unsigned fill = ab.n;
+  u64 myloc = 0;
+  u64 pending = mask;
+  while (pending) {  // wave-uniform
+    const int leader = (int)__builtin_ctzll(pending);
+    const int sl = __shfl(slot, leader, WAVE);
+    const bool mine = want && slot == sl;
+    const u64 m = __ballot(mine);
+    const unsigned d = mine ? deg : 0u;
+    const unsigned incl = wave_incl_scan(d);
+    const unsigned dtot = __shfl(incl, WAVE - 1, WAVE);
+    u64 g = 0;
+    if ((int)lane == leader) g = atomicAdd(&ab.tot[sl], ((u64)__popcll(m) << 32) | (u64)dtot);
+    g = shfl_u64(g, leader);
+    if (mine) myloc = ((u64)((unsigned)(g >> 32) + rank_below(m)) << 32) | (u64)((unsigned)g + incl - d);
+    pending &= ~m;
+  }
+  if (want) {
+    const unsigned idx = fill + wc + rank_below(mask);
+    ab.vert[idx] = v;
+    ab.slot[idx] = (unsigned char)slot;
+    ab.loc[idx] = myloc;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) ab.n = fill + tc;
+  __syncthreads();
+}
+
+// The smallest label each slot had written in this tile (wave-level grouping by slot).
+__device__ __forceinline__ void srv_note_lr(SrvShared& ss, bool wrote, int slot, u64 label) {
+  u64 pending = __ballot(wrote);
+  while (pending) {  // wave-uniform
+    const int leader = (int)__builtin_ctzll(pending);
+    const int sl = __shfl(slot, leader, WAVE);
+    const bool mine = wrote && slot == sl;
+    const u64 m = __ballot(mine);
+    const u64 lab = wave_min_u64(mine ? label : INF);
+    if ((int)lane_id() == leader) atomicMin(&ss.lr[sl], lab);
+    pending &= ~m;
+  }
+}
+
+// Start of step k, round r (wave 0, one lane per slot): each slot's mode for this step and, in
+// rounds mode, its direction from its own frontier; its L_r; the wake, pull and top-down work
+// lists.  Block 0 records the slots' state after step k, clears the counters step k+1 fills,
+// and reports a slot found done (through mapped host memory).
+__device__ __forceinline__ void srv_slot_setup(const RoundCtx& c, int k, int r, SrvShared& ss) {
   if (threadIdx.x >= WAVE) return;
   const int s = threadIdx.x;  // MAX_SLOTS == WAVE
-  int td = TD_SKIP, wake = 0, seed = 0, pull_len = 0;
-  long long pull_beg = 0;
-  u64 L = INF, nf = 0;
+  int td = TD_SKIP, wake = 0, seed = 0, pull_len = 0, n = 0;
+  long long pull_beg = 0, vbeg = 0;
+  u64 L = INF, front = 0;
   if (s < c.nslots) {
     const SlotInfo sl = c.slots[s];
     const SlotState p = c.sst[((k - 1) & 1) * MAX_SLOTS + s];
-    const u64 cnt = c.s_cnt[((k - 1) % 3) * MAX_SLOTS + s];
+    front = c.s_cnt[((k - 1) % 3) * MAX_SLOTS + s];
     const u64 lr = c.s_lr[((k - 1) % 3) * MAX_SLOTS + s];
-    nf = cnt >> 32;
-    const u64 af = cnt & 0xffffffffull;
+    const u64 nf = front >> 32, af = front & 0xffffffffull;
+    n = sl.n;
+    vbeg = sl.vbeg;
     SlotState q = p;
     q.dir = DIR_TD;
     bool report = false;
@@ -727,7 +724,7 @@ __device__ __forceinline__ void slot_setup(const RoundCtx& c, int k, int r, SrvS
       const long long n_act = c.wake_tab[sl.wbase + sl.R];
       const long long left = n_act - q.settled;
       const long long rho = (long long)r - sl.r0;
-      if (left <= 0) {  // every vertex reached: the round that reached the last one ended
+      if (left <= 0) {  // every vertex reached: the round that reached the last one has ended
         q.mode = SM_DONE;
         report = true;
       } else if (c.tail_den > 0 && left * c.tail_den <= n_act && sl.R - rho > c.tail_min_left) {
@@ -742,9 +739,9 @@ __device__ __forceinline__ void slot_setup(const RoundCtx& c, int k, int r, SrvS
           if (c.dir_policy == DIR_TD || c.dir_policy == DIR_BU) {
             dir = c.dir_policy;
           } else {
-            const u64 n = (u64)sl.n;
-            const bool bu_better = af * (u64)c.td_to_bu > (u64)(q.ua > 0 ? q.ua : 0) + n / 4;
-            dir = (p.dir == DIR_BU) ? ((bu_better || nf * (u64)c.bu_to_td >= n) ? DIR_BU : DIR_TD)
+            const u64 nn = (u64)sl.n;
+            const bool bu_better = af * (u64)c.td_to_bu > (u64)(q.ua > 0 ? q.ua : 0) + nn / 4;
+            dir = (p.dir == DIR_BU) ? ((bu_better || nf * (u64)c.bu_to_td >= nn) ? DIR_BU : DIR_TD)
                                     : (bu_better ? DIR_BU : DIR_TD);
           }
         }
@@ -773,147 +770,305 @@ __device__ __forceinline__ void slot_setup(const RoundCtx& c, int k, int r, SrvS
       if (report) __hip_atomic_store(&c.s_end[s].step, (long long)k, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
   }
-  const u64 td_front = __ballot(td != TD_SKIP && nf > 0);
-  const unsigned incl = wave_incl_scan((unsigned)pull_len);
-  ss.std_[s] = td;
-  ss.swake[s] = wake;
-  ss.sseed[s] = seed;
-  ss.sL[s] = L;
-  ss.s_cnt[s] = 0;
-  ss.s_lr[s] = INF;
-  ss.bseg_beg[s] = pull_beg;
-  ss.bseg_off[s + 1] = (int)incl;
+  const unsigned pull_incl = wave_incl_scan((unsigned)pull_len);
+  const unsigned td_incl = wave_incl_scan(td != TD_SKIP ? (unsigned)(front & 0xffffffffull) : 0u);
+  ss.td[s] = td;
+  ss.wake[s] = wake;
+  ss.seed[s] = seed;
+  ss.n[s] = n;
+  ss.vbeg[s] = vbeg;
+  ss.L[s] = L;
+  ss.front[s] = front;
+  ss.lr[s] = INF;
+  ss.pull_beg[s] = pull_beg;
+  ss.pull_off[s + 1] = (int)pull_incl;
+  ss.td_off[s + 1] = td_incl;
   if (s == 0) {
-    ss.bseg_off[0] = 0;
-    ss.any_td = td_front != 0;
+    ss.pull_off[0] = 0;
+    ss.td_off[0] = 0;
   }
 }
 
-// Server mode, end of step k: the block's per-slot notes into the step's counters.
-__device__ __forceinline__ void slot_flush(const RoundCtx& c, int k, SrvShared& ss) {
-  __syncthreads();
-  const int s = threadIdx.x;
-  if (s < MAX_SLOTS && s < c.nslots) {
-    if (ss.s_cnt[s]) atomic_add_u64(&c.s_cnt[(k % 3) * MAX_SLOTS + s], ss.s_cnt[s]);
-    if (ss.s_lr[s] != INF) atomic_min_u64(&c.s_lr[(k % 3) * MAX_SLOTS + s], ss.s_lr[s]);
-  }
-}
-
-// One step; returns the mode it ran in (MODE_DONE: nothing was left to do).
-// SRV: server mode (the next global round over all slots, each in its own direction).
-template <bool SRV>
-__device__ __forceinline__ int round_step(const RoundCtx& c, int k, AppendBuf& ab, StepShared& sh, SrvShared* ss) {
-  if (threadIdx.x == 0) {
-    // Once a step has written "done" into either slot no step writes a slot again, so later
-    // steps only need the two mode words to leave.
-    const bool done = !SRV && (__hip_atomic_load(&c.st[0].mode, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == MODE_DONE ||
-                               __hip_atomic_load(&c.st[1].mode, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == MODE_DONE);
-    if (done) {
-      sh.S.mode = MODE_DONE;
-      sh.S.seq = -1;
-    } else {
-      sh.S = next_state<SRV>(c, k);
-    }
-    ab.n = 0;
-    ab.arcs = 0;
-  }
-  __syncthreads();
-  if (SRV) {
-    slot_setup(c, k, (int)sh.S.round, *ss);
-    __syncthreads();
-  }
-  const RoundState S = sh.S;
-  if (S.seq < 0) return MODE_DONE;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    store_state<__HIP_MEMORY_SCOPE_AGENT>(&c.st[k & 1], S);
-    __hip_atomic_store(qcounter(c, k + 1), 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    // the host stops enqueueing steps once it reads "done"; written once per decomposition,
-    // since a store to host memory delays the completion of the kernel that makes it
-    if (c.host_st && S.mode == MODE_DONE) store_state<__HIP_MEMORY_SCOPE_SYSTEM>(c.host_st, S);
-  }
-  if (S.mode == MODE_DONE) return MODE_DONE;
-  const unsigned nf = min((unsigned)((u64)S.prev >> 32), (unsigned)c.n), af = (unsigned)S.prev;
-  const int* qv = c.qv[(k - 1) & 1];
-  const unsigned* qa = c.qa[(k - 1) & 1];
-  u64 wmin = INF, examined = 0;
-  if (SRV) {
-    const int r = (int)S.round;
-    phase_wake_slots(c, r, k, ab, *ss);
-    if (nf && ss->any_td) phase_top_down<false, true>(c, k, qv, qa, nf, af, ab, sh, wmin, 0, ss);
-    if (ss->bseg_off[MAX_SLOTS]) phase_bottom_up_slots(c, r, k, ab, *ss);
-    block_flush(ab, c, k);
-    slot_flush(c, k, *ss);
-    return MODE_ROUNDS;
-  }
-  const bool need_lr = nf && ((S.mode == MODE_ROUNDS && S.dir == DIR_BU) || (S.mode == MODE_TAIL && S.round == 0));
-  if (need_lr) {
-    // L_r: the smallest offer of F_{r-1}, from the per-block minima the previous step left
-    u64 m = INF;
-    for (unsigned b = threadIdx.x; b < gridDim.x; b += RT) {
-      const u64 x = load_u64_relaxed(&c.lr_part[(size_t)((k - 1) & 1) * gridDim.x + b]);
-      m = x < m ? x : m;
-    }
-    m = block_min_u64(m, sh);
-    if (threadIdx.x == 0) sh.lr = m == INF ? INF : m + ((u64)1 << (FIX + c.B));
-    __syncthreads();
-  }
-  if (S.mode == MODE_ROUNDS) {
-    const int r = (int)S.round;
-    phase_wake(c, r, k, ab, wmin);
-    if (nf) {
-      if (S.dir == DIR_BU) {
-        phase_bottom_up(c, r, k, sh.lr, ab, wmin, examined);
-      } else {
-        phase_top_down<false, false>(c, k, qv, qa, nf, af, ab, sh, wmin, 0, nullptr);
-        if (blockIdx.x == 0 && threadIdx.x == 0) examined += af;
+// Wake: for every slot in rounds mode with r0 <= r < r0 + R, the vertices of its local round
+// r - r0 (a segment of its part of wake_ord) take their own arc.
+__device__ __forceinline__ void srv_wake(const RoundCtx& c, int r, int k, SrvAppend& ab, SrvShared& ss) {
+  if (threadIdx.x < WAVE) {
+    const int t = threadIdx.x;
+    int len = 0;
+    long long beg = 0;
+    if (t < c.nslots && ss.wake[t]) {
+      const SlotInfo sl = c.slots[t];
+      const long long rho = (long long)r - sl.r0;
+      if (rho >= 0 && rho < sl.R) {
+        const int lo = c.wake_tab[sl.wbase + rho], hi = c.wake_tab[sl.wbase + rho + 1];
+        len = hi - lo;
+        beg = sl.vbeg + lo;
       }
     }
-  } else {
-    const unsigned sweep = (unsigned)S.round;
-    if (sweep == 0) {
-      phase_tail_seed(c, (int)S.tail_round, k, nf ? sh.lr : INF, ab, examined);
-    } else if (nf) {
-      phase_top_down<true, false>(c, k, qv, qa, nf, af, ab, sh, wmin, sweep, nullptr);
-      if (blockIdx.x == 0 && threadIdx.x == 0) examined += af;
-    }
+    const unsigned incl = wave_incl_scan((unsigned)len);
+    ss.seg_beg[t] = beg;
+    ss.seg_off[t + 1] = (int)incl;
+    if (t == 0) ss.seg_off[0] = 0;
   }
-  block_flush(ab, c, k);
-  const u64 bm = block_min_u64(wmin, sh);
-  if (threadIdx.x == 0) c.lr_part[(size_t)(k & 1) * gridDim.x + blockIdx.x] = bm;
-  add_examined(c, examined, sh);
-  return (int)S.mode;
+  __syncthreads();
+  const int cnt = ss.seg_off[MAX_SLOTS];
+  for (long long base = (long long)blockIdx.x * RT; base < cnt; base += (long long)gridDim.x * RT) {
+    const long long i = base + threadIdx.x;
+    bool want = false, wrote = false;
+    int v = 0, slot = 0;
+    unsigned deg = 0;
+    u64 self = INF;
+    if (i < cnt) {
+      int lo = 0, hi = MAX_SLOTS;  // the last slot with seg_off <= i
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (ss.seg_off[mid] <= i) lo = mid;
+        else hi = mid;
+      }
+      slot = lo;
+      v = c.wake_ord[ss.seg_beg[lo] + (i - ss.seg_off[lo])];
+      self = own_offer(c, v);
+      if (c.P[v] > self) {
+        const u64 old = atomic_min_u64(&c.P[v], self);
+        if (old > self) {
+          wrote = true;
+          if (old == INF) {
+            want = true;
+            deg = degree(c, v);
+          }
+        }
+      }
+    }
+    srv_note_lr(ss, wrote, slot, self);
+    srv_append(ab, want, v, deg, slot, c, k, ss);
+  }
 }
 
-// (RT, 8): eight waves per SIMD, i.e. two 1024-thread blocks per CU, which caps VGPRs at 64
-__global__ __launch_bounds__(RT, 8) void k_round_step_lb(const LaunchBlock* __restrict__ lb, int j) {
-  __shared__ AppendBuf ab;
-  __shared__ StepShared sh;
-  round_step<false>(lb->c, (int)(lb->kbase + j), ab, sh, nullptr);
+// Top-down over slot s's queue (its frontier from step k-1), slot-local arcs [lo, hi): the
+// windowed search of phase_top_down.  Rounds: a far end reached for the first time is queued;
+// tail sweep: a far end is queued whenever its label drops (once per step, by its stamp).
+__device__ __forceinline__ void srv_td_segment(const RoundCtx& c, int k, SrvAppend& ab, StepShared& sh, SrvShared& ss,
+                                               int s, unsigned lo_a, unsigned hi_a) {
+  unsigned* w_pre = sh.w_pre;
+  int* w_first = sh.w_first;
+  u64* w_offer = sh.w_offer;
+  const u64 unit = (u64)1 << (FIX + c.B);
+  const int* qv = c.qv[(k - 1) & 1] + ss.vbeg[s];
+  const unsigned* qa = c.qa[(k - 1) & 1] + ss.vbeg[s];
+  const unsigned nf = (unsigned)(ss.front[s] >> 32), af = (unsigned)ss.front[s];
+  const bool sweep = ss.td[s] == TD_SWEEP;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned lo = 0, hi = nf;  // the last entry with qa <= lo_a
+    while (hi - lo > 1) {
+      const unsigned mid = (lo + hi) >> 1;
+      if (qa[mid] <= lo_a) lo = mid;
+      else hi = mid;
+    }
+    ss.start = lo;
+  }
+  __syncthreads();
+  unsigned ent = ss.start;
+  for (unsigned tile = lo_a; tile < hi_a; tile += RT) {
+    for (int kk = threadIdx.x; kk <= RT; kk += RT) {
+      const unsigned e = ent + kk;
+      if (e < nf) {
+        const int u = qv[e];
+        w_pre[kk] = qa[e];
+        const bool ok = (unsigned)u < (unsigned)c.n;
+        w_first[kk] = ok ? c.row_ptr[u] : 0;
+        const u64 pu = ok ? load_u64_relaxed(&c.P[u]) : INF;
+        w_offer[kk] = pu == INF ? INF : pu + unit;
+      } else {
+        w_pre[kk] = af;
+        w_first[kk] = 0;
+        w_offer[kk] = INF;
+      }
+    }
+    __syncthreads();
+    const unsigned a = tile + threadIdx.x;
+    bool want = false, wrote = false;
+    int w = 0;
+    unsigned deg = 0;
+    u64 offer = INF;
+    if (a < hi_a) {
+      int lo = 0, hi = RT;  // the last kk in [0, RT) with w_pre[kk] <= a
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (w_pre[mid] <= a) lo = mid;
+        else hi = mid;
+      }
+      offer = w_offer[lo];
+      const unsigned j = a - w_pre[lo];
+      const long long arc = (long long)w_first[lo] + j;
+      const bool in_range = j < w_pre[lo + 1] - w_pre[lo] && arc < c.nnz && offer != INF;
+      w = in_range ? c.col[arc] : -1;
+      if ((unsigned)w < (unsigned)c.n) {
+        if (c.P[w] > offer) {
+          const u64 old = atomic_min_u64(&c.P[w], offer);
+          if (old > offer) {
+            wrote = true;
+            if (sweep) {
+              want = __hip_atomic_fetch_max(&c.stamp[w], (unsigned)k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+                     (unsigned)k;
+            } else {
+              want = old == INF;
+            }
+            if (want) deg = degree(c, w);
+          }
+        }
+      } else if (in_range) {
+        atomic_or_u32(&c.ctrl->err, ERR_BAD_COL);
+      }
+    }
+    srv_note_lr(ss, wrote, s, offer);
+    srv_append(ab, want, w, deg, s, c, k, ss);
+    const unsigned next = tile + RT;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int lo = 0, hi = RT + 1;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (w_pre[mid] <= next) lo = mid;
+        else hi = mid;
+      }
+      ss.start = ent + lo;
+    }
+    __syncthreads();
+    ent = ss.start;
+  }
 }
 
-// The server's step: the next global round over every admitted request.
+// Top-down over the top-down slots' frontier arcs, split evenly over the grid.
+__device__ __forceinline__ void srv_top_down(const RoundCtx& c, int k, SrvAppend& ab, StepShared& sh, SrvShared& ss) {
+  const unsigned T = ss.td_off[MAX_SLOTS];
+  const unsigned G = gridDim.x;
+  const unsigned a_begin = (unsigned)(((u64)T * blockIdx.x) / G);
+  const unsigned a_end = (unsigned)(((u64)T * (blockIdx.x + 1)) / G);
+  if (a_begin >= a_end) return;  // uniform
+  int s = 0, hi = MAX_SLOTS;  // the last slot with td_off <= a_begin
+  while (hi - s > 1) {
+    const int mid = (s + hi) >> 1;
+    if (ss.td_off[mid] <= a_begin) s = mid;
+    else hi = mid;
+  }
+  for (; s < MAX_SLOTS && ss.td_off[s] < a_end; ++s) {
+    const unsigned s0 = ss.td_off[s], s1 = ss.td_off[s + 1];
+    const unsigned lo = a_begin > s0 ? a_begin - s0 : 0u, hi_a = (a_end < s1 ? a_end : s1) - s0;
+    if (s1 > s0 && lo < hi_a) srv_td_segment(c, k, ab, sh, ss, s, lo, hi_a);
+  }
+}
+
+// Pull over the vertex ranges of the slots that go bottom-up (each with its own L_r) or take
+// their tail seed this step (own arc, whatever its wake round, and offers from F_{r-1}).
+__device__ __forceinline__ void srv_pull(const RoundCtx& c, int r, int k, SrvAppend& ab, SrvShared& ss) {
+  const int B = c.B;
+  const u64 unit = (u64)1 << (FIX + B);
+  const u64 base_r = (u64)r << (FIX + B);
+  const u64 prev_round = (u64)(r - 1);
+  const int cnt = ss.pull_off[MAX_SLOTS];
+  for (long long base = (long long)blockIdx.x * RT; base < cnt; base += (long long)gridDim.x * RT) {
+    const long long i = base + threadIdx.x;
+    bool want = false, wrote = false;
+    int v = 0, slot = 0;
+    unsigned deg = 0;
+    u64 best = INF;
+    if (i < cnt) {
+      int lo = 0, hi = MAX_SLOTS;  // the last slot with pull_off <= i
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (ss.pull_off[mid] <= i) lo = mid;
+        else hi = mid;
+      }
+      slot = lo;
+      v = (int)(ss.pull_beg[lo] + (i - ss.pull_off[lo]));
+      const u64 Lr = ss.L[lo];
+      const u64 pv = c.P[v];
+      if (pv >= base_r) {
+        const int a0 = c.row_ptr[v], a1 = c.row_ptr[v + 1];
+        if (ss.seed[lo]) {
+          if (a1 > a0) {
+            best = own_offer(c, v);
+            for (int a = a0; a < a1 && best > Lr; ++a) {
+              const int u = c.col[a];
+              if ((unsigned)u >= (unsigned)c.n) {
+                atomic_or_u32(&c.ctrl->err, ERR_BAD_COL);
+                break;
+              }
+              const u64 pu = load_u64_relaxed(&c.P[u]);
+              if ((pu >> (FIX + B)) == prev_round && pu != INF && pu + unit < best) best = pu + unit;
+            }
+            if (best < pv) {
+              atomic_min_u64(&c.P[v], best);
+              wrote = true;
+              want = __hip_atomic_fetch_max(&c.stamp[v], (unsigned)k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+                     (unsigned)k;
+              deg = (unsigned)(a1 - a0);
+            }
+          }
+        } else if (pv > Lr) {
+          best = pv;
+          for (int a = a0; a < a1; ++a) {
+            const int u = c.col[a];
+            if ((unsigned)u >= (unsigned)c.n) {
+              atomic_or_u32(&c.ctrl->err, ERR_BAD_COL);
+              break;
+            }
+            const u64 pu = load_u64_relaxed(&c.P[u]);
+            if ((pu >> (FIX + B)) == prev_round && pu != INF) {
+              const u64 offer = pu + unit;
+              if (offer < best) best = offer;
+              if (best <= Lr) break;
+            }
+          }
+          if (best < pv) {
+            const u64 old = atomic_min_u64(&c.P[v], best);
+            if (old > best) {
+              wrote = true;
+              if (old == INF) {
+                want = true;
+                deg = (unsigned)(a1 - a0);
+              }
+            }
+          }
+        }
+      }
+    }
+    srv_note_lr(ss, wrote, slot, best);
+    srv_append(ab, want, v, deg, slot, c, k, ss);
+  }
+}
+
+// One server step: the next global round over every admitted request.
+__device__ __forceinline__ void srv_step(const RoundCtx& c, int k, SrvAppend& ab, StepShared& sh, SrvShared& ss) {
+  if (threadIdx.x == 0) {
+    const RoundState P = load_state(&c.st[(k - 1) & 1]);
+    RoundState S = P;
+    S.seq = k;
+    S.round = P.round + 1;
+    S.rounds += 1;
+    sh.S = S;
+    ab.n = 0;
+  }
+  if (threadIdx.x < MAX_SLOTS) ab.tot[threadIdx.x] = 0;
+  __syncthreads();
+  const int r = (int)sh.S.round;
+  srv_slot_setup(c, k, r, ss);
+  __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x == 0) store_state<__HIP_MEMORY_SCOPE_AGENT>(&c.st[k & 1], sh.S);
+  srv_wake(c, r, k, ab, ss);
+  srv_top_down(c, k, ab, sh, ss);
+  if (ss.pull_off[MAX_SLOTS]) srv_pull(c, r, k, ab, ss);
+  srv_flush(ab, c, k, ss);
+  if (threadIdx.x < MAX_SLOTS && threadIdx.x < c.nslots && ss.lr[threadIdx.x] != INF)
+    atomic_min_u64(&c.s_lr[(k % 3) * MAX_SLOTS + threadIdx.x], ss.lr[threadIdx.x]);
+}
+
 __global__ __launch_bounds__(RT, 8) void k_round_step_srv(const LaunchBlock* __restrict__ lb, int j) {
-  __shared__ AppendBuf ab;
+  __shared__ SrvAppend ab;
   __shared__ StepShared sh;
   __shared__ SrvShared ss;
-  round_step<true>(lb->c, (int)(lb->kbase + j), ab, sh, &ss);
-}
-
-__global__ void k_advance(LaunchBlock* lb, int C) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) lb->kbase += C;
-}
-
-// All steps in one kernel with grid barriers between them (the grid must be co-resident).
-__global__ __launch_bounds__(RT) void k_rounds_persistent(RoundCtx c) {
-  __shared__ AppendBuf ab;
-  __shared__ StepShared sh;
-  u64 gen = 0;
-  const long long kmax = (long long)c.R + c.n + 2;
-  for (int k = 1; k <= kmax; ++k) {
-    if (round_step<false>(c, k, ab, sh, nullptr) == MODE_DONE) break;
-    grid_sync(&c.ctrl->bar, gridDim.x, gen, &c.ctrl->err);
-    if (__hip_atomic_load(&c.ctrl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & (ERR_BARRIER | ERR_QUEUE)) break;
-  }
+  srv_step(lb->c, (int)(lb->kbase + j), ab, sh, ss);
 }
 
 }  // namespace ldd

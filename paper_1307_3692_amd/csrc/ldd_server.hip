@@ -150,7 +150,7 @@ __global__ __launch_bounds__(ADM_T) void k_adm_load(AdmBatch b, u64 C, int B, in
                                                     const u64* __restrict__ adm_max, unsigned* __restrict__ adm_err,
                                                     int* __restrict__ rp_g, int* __restrict__ col_g,
                                                     long long* __restrict__ shift_g, u64* __restrict__ P,
-                                                    unsigned char* __restrict__ vslot, unsigned* __restrict__ cnt) {
+                                                    unsigned* __restrict__ cnt) {
   __shared__ unsigned h[QCAP];
   __shared__ int any_bad;
   const AdmItem& t = b.it[item_of(b, blockIdx.x)];
@@ -163,7 +163,6 @@ __global__ __launch_bounds__(ADM_T) void k_adm_load(AdmBatch b, u64 C, int B, in
   const long long lo = chunk(t.n, j, t.nblk), hi = chunk(t.n, j + 1, t.nblk);
   for (long long v = lo + threadIdx.x; v < hi; v += ADM_T) {
     const long long g = t.vbeg + v;
-    vslot[g] = (unsigned char)t.slot;
     if (R) {
       const int a = t.rp[v], e = t.rp[v + 1];
       const u64 sv = (u64)t.shift[v];
@@ -179,7 +178,6 @@ __global__ __launch_bounds__(ADM_T) void k_adm_load(AdmBatch b, u64 C, int B, in
     }
   }
   if (j == t.nblk - 1 && threadIdx.x == 0) {
-    vslot[t.vbeg + t.n] = (unsigned char)t.slot;
     rp_g[t.vbeg + t.n] = (int)(t.abeg + (R ? t.nnz : 0));
     shift_g[t.vbeg + t.n] = (long long)C;
     P[t.vbeg + t.n] = 0;
@@ -601,7 +599,7 @@ struct ldd_server {
   void *rp_g = nullptr, *col_g = nullptr, *shift_g = nullptr, *wake_tab = nullptr, *cnt = nullptr, *cur = nullptr;
   void *slots = nullptr, *st = nullptr, *qcnt = nullptr, *lr_part = nullptr, *lb = nullptr, *ex_part = nullptr;
   void *ctrl = nullptr, *adm_max = nullptr, *adm_err = nullptr, *cut_acc = nullptr;
-  void *vslot = nullptr, *sst = nullptr, *s_cnt = nullptr, *s_lr = nullptr, *stamp = nullptr;
+  void *sst = nullptr, *s_cnt = nullptr, *s_lr = nullptr, *stamp = nullptr;
   void *adm_hub = nullptr, *hbits = nullptr, *lcnt = nullptr;
   SlotEnd* s_end = nullptr;      // mapped host memory: the step each slot was found done
   SlotEnd* s_end_dev = nullptr;  // its device address
@@ -674,8 +672,8 @@ ldd_status srv_alloc(ldd_server* srv, void** p, size_t bytes) {
 }
 
 // Device bytes per arena vertex (label, two queues with arc prefixes, wake order, row offset,
-// shift, slot, tail stamp) and per arena arc (column id).
-constexpr long long BYTES_PER_VERTEX = 8 + 8 + 8 + 4 + 4 + 8 + 1 + 4;
+// shift, tail stamp) and per arena arc (column id).
+constexpr long long BYTES_PER_VERTEX = 8 + 8 + 8 + 4 + 4 + 8 + 4;
 constexpr long long BYTES_PER_ARC = 4;
 
 ldd_status srv_setup(ldd_server* srv) {
@@ -697,7 +695,7 @@ ldd_status srv_setup(ldd_server* srv) {
       (s = srv_alloc(srv, &srv->lb, sizeof(LaunchBlock))) || (s = srv_alloc(srv, &srv->ex_part, (size_t)RT * 8)) ||
       (s = srv_alloc(srv, &srv->ctrl, sizeof(Ctrl))) || (s = srv_alloc(srv, &srv->adm_max, MAX_SLOTS * 8)) ||
       (s = srv_alloc(srv, &srv->adm_err, MAX_SLOTS * 4)) || (s = srv_alloc(srv, &srv->cut_acc, MAX_SLOTS * 8)) ||
-      (s = srv_alloc(srv, &srv->vslot, V + 1)) || (s = srv_alloc(srv, &srv->sst, 2 * MAX_SLOTS * sizeof(SlotState))) ||
+      (s = srv_alloc(srv, &srv->sst, 2 * MAX_SLOTS * sizeof(SlotState))) ||
       (s = srv_alloc(srv, &srv->s_cnt, 3 * MAX_SLOTS * 8)) || (s = srv_alloc(srv, &srv->s_lr, 3 * MAX_SLOTS * 8)) ||
       (s = srv_alloc(srv, &srv->stamp, V * 4)) || (s = srv_alloc(srv, &srv->adm_hub, MAX_SLOTS * 8)) ||
       (s = srv_alloc(srv, &srv->hbits, (V / 64 + 2) * 8)) || (s = srv_alloc(srv, &srv->lcnt, MAX_SLOTS * 8)))
@@ -722,7 +720,6 @@ ldd_status srv_setup(ldd_server* srv) {
   SRV_TRY(hipMemsetAsync(srv->adm_err, 0, MAX_SLOTS * 4, q));
   SRV_TRY(hipMemsetAsync(srv->cut_acc, 0, MAX_SLOTS * 8, q));
   SRV_TRY(hipMemsetAsync(srv->lr_part, 0xff, 2 * (size_t)RT * 8, q));
-  SRV_TRY(hipMemsetAsync(srv->vslot, 0, V + 1, q));
   SRV_TRY(hipMemsetAsync(srv->stamp, 0, V * 4, q));  // stamps are step numbers (>= 1)
   SRV_TRY(hipMemsetAsync(srv->adm_hub, 0, MAX_SLOTS * 8, q));
   SRV_TRY(hipMemsetAsync(srv->lcnt, 0, MAX_SLOTS * 8, q));
@@ -780,7 +777,6 @@ ldd_status srv_setup(ldd_server* srv) {
   c.slots = (const SlotInfo*)srv->slots;
   c.nslots = srv->cfg.max_slots;
   c.wake_tab = (const int*)srv->wake_tab;
-  c.vslot = (const unsigned char*)srv->vslot;
   c.sst = (SlotState*)srv->sst;
   c.s_cnt = (u64*)srv->s_cnt;
   c.s_lr = (u64*)srv->s_lr;
@@ -852,7 +848,7 @@ ldd_status srv_admit(ldd_server* srv, const std::vector<Request*>& rs) {
                        (u64*)srv->adm_hub);
     hipLaunchKernelGGL(k_adm_load, dim3(nblk), dim3(ADM_T), 0, s, ab, srv->C, srv->B, srv->max_rounds,
                        (const u64*)srv->adm_max, (unsigned*)srv->adm_err, (int*)srv->rp_g, (int*)srv->col_g,
-                       (long long*)srv->shift_g, (u64*)srv->P, (unsigned char*)srv->vslot, (unsigned*)srv->cnt);
+                       (long long*)srv->shift_g, (u64*)srv->P, (unsigned*)srv->cnt);
     hipLaunchKernelGGL(k_adm_commit, dim3(ab.count), dim3(ADM_T), 0, s, ab, srv->max_rounds,
                        (const u64*)srv->adm_max, (unsigned*)srv->adm_err, (unsigned*)srv->cnt,
                        (unsigned*)srv->cur, (int*)srv->wake_tab, (SlotInfo*)srv->slots, (RoundState*)srv->st,
@@ -1309,7 +1305,7 @@ extern "C" ldd_status ldd_server_destroy(ldd_server* srv) {
   if (srv->stream) (void)hipStreamSynchronize(srv->stream);
   for (void* p : {srv->P, srv->qv0, srv->qv1, srv->qa0, srv->qa1, srv->wake_ord, srv->rp_g, srv->col_g, srv->shift_g,
                   srv->wake_tab, srv->cnt, srv->cur, srv->slots, srv->st, srv->qcnt, srv->lr_part, srv->lb,
-                  srv->ex_part, srv->ctrl, srv->adm_max, srv->adm_err, srv->cut_acc, srv->vslot, srv->sst,
+                  srv->ex_part, srv->ctrl, srv->adm_max, srv->adm_err, srv->cut_acc, srv->sst,
                   srv->s_cnt, srv->s_lr, srv->stamp, srv->adm_hub, srv->hbits, srv->lcnt})
     if (p) (void)hipFree(p);
   if (srv->rep) (void)hipHostFree(srv->rep);
