@@ -141,12 +141,12 @@ ldd_status ldd_decompose_batch(int32_t num_graphs, const int64_t* vtx_off, const
 /*
  * Serving: a long-lived engine that decomposes a stream of independent requests (the same
  * operation as ldd_decompose per request, bit for bit) with continuous batching.  Admitted
- * requests share one device-resident arena and advance together, one launch per round over
- * all of them; a request joins at the next round boundary and leaves as soon as its own last
- * round has run, while others keep going.  The arena is sized once, from the memory budget;
- * requests wait in a first-come-first-served queue until their vertices, arcs and a slot fit.
- * A request whose round 0 runs at global round r0 is the search of Sec. 5 with every source
- * arc lengthened by r0 units, which changes no comparison inside its component.
+ * requests share one device-resident arena of per-vertex state and advance together, one
+ * launch per round over all of them; a request joins at the next round boundary and leaves as
+ * soon as its own labels are final, while others keep going.  The arena is sized once, from
+ * the memory budget; requests wait in a first-come-first-served queue until their vertices and
+ * a slot fit.  A request whose round 0 runs at global round r0 is the search of Sec. 5 with
+ * every source arc lengthened by r0 units, which changes no comparison inside its component.
  *
  * Threads: one engine thread per server owns its device stream.  submit / poll / wait / cancel
  * / query may be called from any thread.  All calls return an ldd_status.
@@ -154,19 +154,20 @@ ldd_status ldd_decompose_batch(int32_t num_graphs, const int64_t* vtx_off, const
 typedef struct ldd_server ldd_server;
 
 typedef struct {
-  int64_t hbm_budget_bytes; /* arena size in device bytes; split as 44 B per vertex + 4 B per   */
-                            /* arc for graphs of about 16 arcs per vertex unless max_* are set */
-                            /* (arcs at most 2^31 - 1, the rest to vertices, at most 2^30)     */
-  int64_t max_vertices;     /* arena vertices (a request takes n + 1 rounded up to 64); 0 = from the budget */
-  int64_t max_arcs;         /* arena arcs (a request takes nnz); 0 = from the budget            */
-  int32_t max_slots;        /* requests on the device at once, 1..64 (0 = 64)                   */
-  int32_t chunk_steps;      /* rounds per replayed launch graph, 1..64 (0 = 8)                  */
-  int32_t blocks;           /* workgroups of the round kernel (0 = 2 per CU)                    */
-  int32_t direction;        /* LDD_DIR_* policy of every round                                   */
-  int32_t max_rounds;       /* testing: key range in rounds before keys are rebased (0 = the    */
-                            /* largest the label width allows); requests may need at most half */
-  int32_t tail_vertices;    /* a request finishes by label correction once its unreached       */
-                            /* vertices * this <= its vertices with arcs (0 = 64, -1 = never)   */
+  int64_t hbm_budget_bytes; /* arena size in device bytes, 33 B per arena vertex (labels, queues, */
+                            /* wake order, stamps); requests' CSR and shifts stay in the callers' */
+                            /* buffers and take no arena space                                    */
+  int64_t max_vertices;     /* arena vertices (a request takes n + 1 rounded up to 64);           */
+                            /* 0 = from the budget (at most 2^30)                                 */
+  int64_t max_arcs;         /* unused (0)                                                         */
+  int32_t max_slots;        /* requests on the device at once, 1..64 (0 = 64)                     */
+  int32_t chunk_steps;      /* rounds per replayed launch graph, 1..64 (0 = 8)                    */
+  int32_t blocks;           /* workgroups of the round kernel (0 = 2 per CU)                      */
+  int32_t direction;        /* LDD_DIR_* policy of every round                                     */
+  int32_t max_rounds;       /* testing: key range in rounds before keys are rebased (0 = the      */
+                            /* largest the label width allows); requests may need at most half   */
+  int32_t tail_vertices;    /* a request finishes by label correction once its unreached         */
+                            /* vertices * this <= its vertices with arcs (0 = 64, -1 = never)     */
   int32_t reserved[6];
 } ldd_server_config;
 
@@ -196,7 +197,7 @@ typedef struct {
 
 typedef struct {
   int64_t arena_vertices;
-  int64_t arena_arcs;
+  int64_t arena_arcs;       /* 0: arcs are read from the callers' buffers                          */
   int32_t max_rounds;       /* largest floor(Delta / 2^20) + 1 a request may have              */
   int32_t max_slots;
   int64_t admitted;
@@ -212,7 +213,7 @@ typedef struct {
 ldd_status ldd_server_create(const ldd_server_config* cfg, ldd_server** out);
 
 /* Queue a request.  Only O(1) checks happen here: LDD_ERR_INVALID_ARG for bad sizes or NULL
- * pointers, LDD_ERR_BUDGET if it can never fit the arena.  On LDD_OK *ticket names the request
+ * pointers, LDD_ERR_BUDGET if its vertices can never fit the arena.  On LDD_OK *ticket names the request
  * until its result is collected.  An event recorded on req->hip_stream orders the request's
  * admission after the work that stream has queued so far.  The content is checked on the
  * device at admission: row offsets not non-decreasing from 0 to nnz, a shift outside

@@ -403,6 +403,7 @@ static ldd_status decompose_impl(Workspace& w, const ldd_csr* g, const int64_t* 
   c.s_cnt = nullptr;
   c.s_lr = nullptr;
   c.s_end = nullptr;
+  c.slot_err = nullptr;
   HIP_TRY(hipMemsetAsync(w.ex_part.p, 0, (size_t)RT * sizeof(u64), st));
 
   const int engine = o.engine == LDD_ENGINE_AUTO ? LDD_ENGINE_LAUNCH : o.engine;

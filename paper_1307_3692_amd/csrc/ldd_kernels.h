@@ -37,9 +37,16 @@ struct RoundState {
 
 // Server mode: one admitted request per slot, in its own vertex range of the arena.
 constexpr int MAX_SLOTS = 64;
+// The request's CSR and shifts stay in the caller's device buffers (local ids); arena vertex
+// vbeg + v is the request's vertex v.
 struct SlotInfo {
+  const int* rp;
+  const int* col;
+  const long long* shift;
+  u64 delta;        // the request's max shift
   long long vbeg;   // first arena vertex of the slot
   long long r0;     // global round of the request's round 0
+  long long nnz;
   int R;            // the request's rounds (its wake rounds are r0 .. r0 + R - 1)
   int wbase;        // its round offsets start at wake_tab[wbase] (R + 1 entries)
   int active;
@@ -101,6 +108,7 @@ struct RoundCtx {
   u64* s_cnt;                  // [3][MAX_SLOTS]: (count << 32 | arcs) queued by step k, at k % 3
   u64* s_lr;                   // [3][MAX_SLOTS]: smallest label written by step k, at k % 3
   SlotEnd* s_end;              // [MAX_SLOTS], mapped host memory
+  unsigned* slot_err;          // [MAX_SLOTS]: error bits of each request (a column id out of range)
 };
 
 // Arguments of graph-launched steps: step k = kbase + j of a chunk; k_advance moves kbase.

@@ -589,6 +589,11 @@ struct SrvAppend {
 };
 
 struct SrvShared {
+  const int* rp[MAX_SLOTS];  // each slot's request: CSR and shifts (local ids)
+  const int* col[MAX_SLOTS];
+  const long long* shift[MAX_SLOTS];
+  u64 off0[MAX_SLOTS];       // delta + r0 * 2^20: a vertex's own arc is off0 - shift
+  long long nnz[MAX_SLOTS];
   int td[MAX_SLOTS];    // TD_* of each slot in this step
   int wake[MAX_SLOTS];  // the slot takes part in this round's wake
   int seed[MAX_SLOTS];  // the slot's pull in this step is its tail seed
@@ -697,6 +702,16 @@ __device__ __forceinline__ void srv_note_lr(SrvShared& ss, bool wrote, int slot,
   }
 }
 
+__device__ __forceinline__ unsigned srv_degree(const SrvShared& ss, int s, int v) {
+  const int lv = v - (int)ss.vbeg[s];
+  return (unsigned)(ss.rp[s][lv + 1] - ss.rp[s][lv]);
+}
+
+// The request's own arc of arena vertex v: its source-arc length raised by r0 units.
+__device__ __forceinline__ u64 srv_own_offer(const RoundCtx& c, const SrvShared& ss, int s, int v) {
+  return ((ss.off0[s] - (u64)ss.shift[s][v - ss.vbeg[s]]) << c.B) | (u64)v;
+}
+
 // Start of step k, round r (wave 0, one lane per slot): each slot's mode for this step and, in
 // rounds mode, its direction from its own frontier; its L_r; the wake, pull and top-down work
 // lists.  Block 0 records the slots' state after step k, clears the counters step k+1 fills,
@@ -709,6 +724,11 @@ __device__ __forceinline__ void srv_slot_setup(const RoundCtx& c, int k, int r, 
   u64 L = INF, front = 0;
   if (s < c.nslots) {
     const SlotInfo sl = c.slots[s];
+    ss.rp[s] = sl.rp;
+    ss.col[s] = sl.col;
+    ss.shift[s] = sl.shift;
+    ss.off0[s] = sl.delta + (u64)sl.r0 * ((u64)1 << FIX);
+    ss.nnz[s] = sl.nnz;
     const SlotState p = c.sst[((k - 1) & 1) * MAX_SLOTS + s];
     front = c.s_cnt[((k - 1) % 3) * MAX_SLOTS + s];
     const u64 lr = c.s_lr[((k - 1) % 3) * MAX_SLOTS + s];
@@ -827,14 +847,14 @@ __device__ __forceinline__ void srv_wake(const RoundCtx& c, int r, int k, SrvApp
       }
       slot = lo;
       v = c.wake_ord[ss.seg_beg[lo] + (i - ss.seg_off[lo])];
-      self = own_offer(c, v);
+      self = srv_own_offer(c, ss, lo, v);
       if (c.P[v] > self) {
         const u64 old = atomic_min_u64(&c.P[v], self);
         if (old > self) {
           wrote = true;
           if (old == INF) {
             want = true;
-            deg = degree(c, v);
+            deg = srv_degree(ss, lo, v);
           }
         }
       }
@@ -857,6 +877,10 @@ __device__ __forceinline__ void srv_td_segment(const RoundCtx& c, int k, SrvAppe
   const unsigned* qa = c.qa[(k - 1) & 1] + ss.vbeg[s];
   const unsigned nf = (unsigned)(ss.front[s] >> 32), af = (unsigned)ss.front[s];
   const bool sweep = ss.td[s] == TD_SWEEP;
+  const int* rp = ss.rp[s];
+  const int* col = ss.col[s];
+  const long long vbeg = ss.vbeg[s], nnz = ss.nnz[s];
+  const int n = ss.n[s];
   __syncthreads();
   if (threadIdx.x == 0) {
     unsigned lo = 0, hi = nf;  // the last entry with qa <= lo_a
@@ -875,8 +899,9 @@ __device__ __forceinline__ void srv_td_segment(const RoundCtx& c, int k, SrvAppe
       if (e < nf) {
         const int u = qv[e];
         w_pre[kk] = qa[e];
-        const bool ok = (unsigned)u < (unsigned)c.n;
-        w_first[kk] = ok ? c.row_ptr[u] : 0;
+        const long long lu = (long long)u - vbeg;
+        const bool ok = lu >= 0 && lu < n;
+        w_first[kk] = ok ? rp[lu] : 0;
         const u64 pu = ok ? load_u64_relaxed(&c.P[u]) : INF;
         w_offer[kk] = pu == INF ? INF : pu + unit;
       } else {
@@ -901,9 +926,10 @@ __device__ __forceinline__ void srv_td_segment(const RoundCtx& c, int k, SrvAppe
       offer = w_offer[lo];
       const unsigned j = a - w_pre[lo];
       const long long arc = (long long)w_first[lo] + j;
-      const bool in_range = j < w_pre[lo + 1] - w_pre[lo] && arc < c.nnz && offer != INF;
-      w = in_range ? c.col[arc] : -1;
-      if ((unsigned)w < (unsigned)c.n) {
+      const bool in_range = j < w_pre[lo + 1] - w_pre[lo] && arc < nnz && offer != INF;
+      const int wl = in_range ? col[arc] : -1;
+      w = (int)(vbeg + wl);
+      if ((unsigned)wl < (unsigned)n) {
         if (c.P[w] > offer) {
           const u64 old = atomic_min_u64(&c.P[w], offer);
           if (old > offer) {
@@ -914,11 +940,11 @@ __device__ __forceinline__ void srv_td_segment(const RoundCtx& c, int k, SrvAppe
             } else {
               want = old == INF;
             }
-            if (want) deg = degree(c, w);
+            if (want) deg = (unsigned)(rp[wl + 1] - rp[wl]);
           }
         }
       } else if (in_range) {
-        atomic_or_u32(&c.ctrl->err, ERR_BAD_COL);
+        atomic_or_u32(&c.slot_err[s], ERR_BAD_COL);
       }
     }
     srv_note_lr(ss, wrote, s, offer);
@@ -981,21 +1007,26 @@ __device__ __forceinline__ void srv_pull(const RoundCtx& c, int r, int k, SrvApp
         else hi = mid;
       }
       slot = lo;
-      v = (int)(ss.pull_beg[lo] + (i - ss.pull_off[lo]));
+      const long long lv = ss.pull_beg[lo] - ss.vbeg[lo] + (i - ss.pull_off[lo]);
+      v = (int)(ss.vbeg[lo] + lv);
       const u64 Lr = ss.L[lo];
       const u64 pv = c.P[v];
+      const int* rp = ss.rp[lo];
+      const int* col = ss.col[lo];
+      const long long vbeg = ss.vbeg[lo];
+      const unsigned n = (unsigned)ss.n[lo];
       if (pv >= base_r) {
-        const int a0 = c.row_ptr[v], a1 = c.row_ptr[v + 1];
+        const int a0 = rp[lv], a1 = rp[lv + 1];
         if (ss.seed[lo]) {
           if (a1 > a0) {
-            best = own_offer(c, v);
+            best = srv_own_offer(c, ss, lo, v);
             for (int a = a0; a < a1 && best > Lr; ++a) {
-              const int u = c.col[a];
-              if ((unsigned)u >= (unsigned)c.n) {
-                atomic_or_u32(&c.ctrl->err, ERR_BAD_COL);
+              const int ul = col[a];
+              if ((unsigned)ul >= n) {
+                atomic_or_u32(&c.slot_err[lo], ERR_BAD_COL);
                 break;
               }
-              const u64 pu = load_u64_relaxed(&c.P[u]);
+              const u64 pu = load_u64_relaxed(&c.P[vbeg + ul]);
               if ((pu >> (FIX + B)) == prev_round && pu != INF && pu + unit < best) best = pu + unit;
             }
             if (best < pv) {
@@ -1009,12 +1040,12 @@ __device__ __forceinline__ void srv_pull(const RoundCtx& c, int r, int k, SrvApp
         } else if (pv > Lr) {
           best = pv;
           for (int a = a0; a < a1; ++a) {
-            const int u = c.col[a];
-            if ((unsigned)u >= (unsigned)c.n) {
-              atomic_or_u32(&c.ctrl->err, ERR_BAD_COL);
+            const int ul = col[a];
+            if ((unsigned)ul >= n) {
+              atomic_or_u32(&c.slot_err[lo], ERR_BAD_COL);
               break;
             }
-            const u64 pu = load_u64_relaxed(&c.P[u]);
+            const u64 pu = load_u64_relaxed(&c.P[vbeg + ul]);
             if ((pu >> (FIX + B)) == prev_round && pu != INF) {
               const u64 offer = pu + unit;
               if (offer < best) best = offer;

@@ -1,21 +1,22 @@
 // Serving: decomposition requests admitted continuously into one device-resident arena.
 //
-// Every admitted request owns a slot: a vertex range and an arc range of the arena holding its
-// CSR rewritten to arena ids.  The round engine runs one global round per step over the whole
-// arena, i.e. over the disjoint union of all admitted requests.  A request whose round 0 is the
-// global round r0 gets the source-arc lengths Delta_g - shift + r0 * 2^20: every key of the
-// request grows by the same constant, so its argmin and its tie order -- its result -- are those
-// of the request alone (Sec. 5: the super-source search only compares keys within a component),
-// and its round rho runs at global round r0 + rho.  It is complete once global round r0 + R - 1,
-// its last wake round, has run.
+// Every admitted request owns a slot: a range of arena vertices (labels, queues, wake order),
+// while its CSR and shifts stay in the caller's device buffers.  The round engine runs one
+// global round per step over the whole arena, i.e. over the disjoint union of all admitted
+// requests.  A request whose round 0 is the global round r0 gets the source-arc lengths
+// Delta_g - shift + r0 * 2^20: every key of the request grows by the same constant, so its
+// argmin and its tie order -- its result -- are those of the request alone (Sec. 5: the
+// super-source search only compares keys within a component), and its round rho runs at global
+// round r0 + rho.  Each request has its own mode (rounds, then a label-correcting tail once few
+// of its vertices remain) and is done as soon as its labels are final.
 //
-// Requests join and leave between step chunks.  Admission (validation, copy into the arena,
-// wake-round sort) and finishing (centres, cut, report) each run as a few kernels for a whole
-// batch of requests, their descriptors passed as kernel arguments, enqueued on the engine stream
-// between graph replays; results reach the host through mapped memory.  So the host cost per
-// engine iteration does not grow with the number of requests that join or leave.  Keys grow
-// with the global round; when they approach the label's key range, all live keys are lowered
-// by the same number of rounds (a rebase), again between chunks.
+// Requests join and leave between step chunks.  Admission (validation, labels, wake-round
+// sort) and finishing (centres, cut, report) each run as a few kernels for a whole batch of
+// requests, their descriptors passed as kernel arguments, enqueued on the engine stream between
+// graph replays; results reach the host through mapped memory.  So the host cost per engine
+// iteration does not grow with the number of requests that join or leave.  Keys grow with the
+// global round; when they approach the label's key range, all live keys are lowered by the same
+// number of rounds (a rebase), again between chunks.
 //
 // One engine thread owns the engine stream; submit, poll, wait and cancel touch host queues
 // (submit also records an event on the caller's stream, which admission waits for).
@@ -51,7 +52,7 @@ struct AdmItem {
   const int* rp;
   const int* col;
   const long long* shift;
-  long long vbeg, abeg, nnz, r0;
+  long long vbeg, nnz, r0;
   int n, slot, blk0, nblk;
 };
 struct AdmBatch {
@@ -61,7 +62,9 @@ struct AdmBatch {
 
 struct FinItem {
   int* centre;
-  long long vbeg, abeg, nnz;
+  const int* rp;
+  const int* col;
+  long long vbeg, nnz;
   int n, slot, blk0, nblk;
 };
 struct FinBatch {
@@ -139,65 +142,39 @@ __global__ __launch_bounds__(ADM_T) void k_adm_check(AdmBatch b, u64* __restrict
   }
 }
 
-// The request's CSR into the arena: global row offsets and column ids, shifts stored as
-// C - (Delta_g - shift + r0 2^20), so that the engine's C - shift is the request's source-arc
-// length; labels INF for vertices with arcs, their own offer for isolated ones.  Vertex n of
-// the slot is a separator closing the last row: settled (label 0) and never woken.  A column id
-// outside [0, n) is redirected to the separator (every access stays inside the slot) and flags
-// the request.  A request whose rows or shifts failed the check gets empty rows and settled
-// labels: it stays inert.  Also counts the request's vertices per wake round.
-__global__ __launch_bounds__(ADM_T) void k_adm_load(AdmBatch b, u64 C, int B, int max_rounds,
-                                                    const u64* __restrict__ adm_max, unsigned* __restrict__ adm_err,
-                                                    int* __restrict__ rp_g, int* __restrict__ col_g,
-                                                    long long* __restrict__ shift_g, u64* __restrict__ P,
+// The request's labels in the arena: INF for vertices with arcs, their own offer for isolated
+// ones (the own arc of local vertex v is Delta_g - shift[v] + r0 2^20: the request's source-arc
+// length raised by r0 units); the request's CSR and shifts stay in the caller's buffers.  Vertex
+// n of the slot is settled (label 0).  A request whose rows or shifts failed the check gets
+// settled labels only: it stays inert.  Also counts the request's vertices per wake round.
+__global__ __launch_bounds__(ADM_T) void k_adm_load(AdmBatch b, int B, int max_rounds, const u64* __restrict__ adm_max,
+                                                    const unsigned* __restrict__ adm_err, u64* __restrict__ P,
                                                     unsigned* __restrict__ cnt) {
   __shared__ unsigned h[QCAP];
-  __shared__ int any_bad;
   const AdmItem& t = b.it[item_of(b, blockIdx.x)];
   const int j = blockIdx.x - t.blk0;
   const u64 delta = adm_max[t.slot];
   const int R = request_rounds(delta, adm_err[t.slot], max_rounds);
   for (int r = threadIdx.x; r < R; r += ADM_T) h[r] = 0;
-  if (threadIdx.x == 0) any_bad = 0;
   __syncthreads();
   const long long lo = chunk(t.n, j, t.nblk), hi = chunk(t.n, j + 1, t.nblk);
   for (long long v = lo + threadIdx.x; v < hi; v += ADM_T) {
     const long long g = t.vbeg + v;
     if (R) {
-      const int a = t.rp[v], e = t.rp[v + 1];
+      const bool arcs = t.rp[v + 1] > t.rp[v];
       const u64 sv = (u64)t.shift[v];
       const u64 off = delta - sv + (u64)t.r0 * S_ONE;
-      rp_g[g] = (int)(t.abeg + a);
-      shift_g[g] = (long long)(C - off);
-      P[g] = e > a ? INF : ((off << B) | (u64)g);
-      if (e > a) atomicAdd(&h[(delta - sv) >> FIX], 1u);
+      P[g] = arcs ? INF : ((off << B) | (u64)g);
+      if (arcs) atomicAdd(&h[(delta - sv) >> FIX], 1u);
     } else {
-      rp_g[g] = (int)t.abeg;
-      shift_g[g] = (long long)C;
       P[g] = 0;
     }
   }
-  if (j == t.nblk - 1 && threadIdx.x == 0) {
-    rp_g[t.vbeg + t.n] = (int)(t.abeg + (R ? t.nnz : 0));
-    shift_g[t.vbeg + t.n] = (long long)C;
-    P[t.vbeg + t.n] = 0;
-  }
-  if (R) {
-    const long long alo = chunk(t.nnz, j, t.nblk), ahi = chunk(t.nnz, j + 1, t.nblk);
-    for (long long a = alo + threadIdx.x; a < ahi; a += ADM_T) {
-      int c = t.col[a];
-      if ((unsigned)c >= (unsigned)t.n) {
-        c = t.n;
-        any_bad = 1;
-      }
-      col_g[t.abeg + a] = (int)(t.vbeg + c);
-    }
-  }
+  if (j == t.nblk - 1 && threadIdx.x == 0) P[t.vbeg + t.n] = 0;
   __syncthreads();
   unsigned* row = cnt + (size_t)t.slot * max_rounds;
   for (int r = threadIdx.x; r < R; r += ADM_T)
     if (h[r]) atomicAdd(&row[r], h[r]);
-  if (threadIdx.x == 0 && any_bad) atomic_or_u32(&adm_err[t.slot], ERR_BAD_COL);
 }
 
 // One block per request: round offsets (wake_tab row of the slot, R + 1 entries) and the place
@@ -243,6 +220,11 @@ __global__ __launch_bounds__(ADM_T) void k_adm_commit(AdmBatch b, int max_rounds
   }
   if (threadIdx.x == 0) {
     SlotInfo e;
+    e.rp = t.rp;
+    e.col = t.col;
+    e.shift = t.shift;
+    e.delta = delta;
+    e.nnz = t.nnz;
     e.vbeg = t.vbeg;
     e.r0 = t.r0;
     e.R = R;
@@ -311,12 +293,13 @@ __device__ __forceinline__ long long chunk64(long long n, int j, int nb) {
 }
 
 // Centres (request-local ids) into the caller's buffer, the bit of H of every vertex, and the
-// rows outside H with arcs, listed as (arc prefix << 32 | local id) in the slot's shift area
-// (shifts are not read once a request is done).
+// rows outside H with arcs, listed (local id, arc prefix) in the slot's range of one queue pair
+// (a request found done has nothing queued and is never expanded again).
 __global__ __launch_bounds__(FIN_T) void k_fin_vertices(FinBatch b, int B, const u64* __restrict__ P,
-                                                        const int* __restrict__ rp_g, const SlotInfo* __restrict__ slots,
+                                                        const SlotInfo* __restrict__ slots,
                                                         const u64* __restrict__ adm_hub, u64* __restrict__ hbits,
-                                                        long long* __restrict__ list, u64* __restrict__ lcnt) {
+                                                        int* __restrict__ list_v, unsigned* __restrict__ list_a,
+                                                        u64* __restrict__ lcnt) {
   constexpr int NWF = FIN_T / WAVE;
   __shared__ unsigned w_cnt[NWF], w_arcs[NWF];
   __shared__ u64 base;
@@ -335,7 +318,7 @@ __global__ __launch_bounds__(FIN_T) void k_fin_vertices(FinBatch b, int B, const
     if (v < hi) {
       const u64 c = P[t.vbeg + v] & mask;
       t.centre[v] = ran ? (int)(c - (u64)t.vbeg) : -1;
-      deg = (unsigned)(rp_g[t.vbeg + v + 1] - rp_g[t.vbeg + v]);
+      deg = (unsigned)(t.rp[v + 1] - t.rp[v]);
       inH = c == hubc;
       out = ran && !inH && deg > 0;
     }
@@ -363,7 +346,8 @@ __global__ __launch_bounds__(FIN_T) void k_fin_vertices(FinBatch b, int B, const
       if (out) {
         const unsigned idx = (unsigned)(base >> 32) + bc + rank_below(om);
         const unsigned pre = (unsigned)base + ba + incl - deg;
-        list[t.vbeg + idx] = (long long)(((u64)pre << 32) | (u64)v);
+        list_v[t.vbeg + idx] = (int)v;
+        list_a[t.vbeg + idx] = pre;
       }
     }
     __syncthreads();
@@ -373,9 +357,9 @@ __global__ __launch_bounds__(FIN_T) void k_fin_vertices(FinBatch b, int B, const
 // The listed rows' arcs, split evenly over the item's blocks, walked in tiles of FIN_T arcs with
 // a window of list entries in LDS.
 __global__ __launch_bounds__(FIN_T) void k_fin_cut(FinBatch b, int B, const u64* __restrict__ P,
-                                                   const int* __restrict__ rp_g, const int* __restrict__ col_g,
-                                                   const u64* __restrict__ hbits, const long long* __restrict__ list,
-                                                   const u64* __restrict__ lcnt, u64* __restrict__ cut_acc) {
+                                                   const u64* __restrict__ hbits, const int* __restrict__ list_v,
+                                                   const unsigned* __restrict__ list_a, const u64* __restrict__ lcnt,
+                                                   u64* __restrict__ cut_acc) {
   constexpr int T = FIN_T;
   __shared__ unsigned w_pre[T + 1];
   __shared__ int w_first[T + 1];
@@ -388,7 +372,8 @@ __global__ __launch_bounds__(FIN_T) void k_fin_cut(FinBatch b, int B, const u64*
   const u64 lc = lcnt[t.slot];
   const unsigned ne = (unsigned)(lc >> 32), na = (unsigned)lc;
   const unsigned a_begin = (unsigned)(((u64)na * j) / t.nblk), a_end = (unsigned)(((u64)na * (j + 1)) / t.nblk);
-  const long long* L = list + t.vbeg;
+  const int* LV = list_v + t.vbeg;
+  const unsigned* LA = list_a + t.vbeg;
   const u64* Ps = P + t.vbeg;
   u64 cut = 0;
   if (a_begin < a_end) {  // uniform
@@ -396,7 +381,7 @@ __global__ __launch_bounds__(FIN_T) void k_fin_cut(FinBatch b, int B, const u64*
       unsigned lo = 0, hi = ne;  // the last entry whose arcs start at or before a_begin
       while (hi - lo > 1) {
         const unsigned mid = (lo + hi) >> 1;
-        if ((unsigned)((u64)L[mid] >> 32) <= a_begin) lo = mid;
+        if (LA[mid] <= a_begin) lo = mid;
         else hi = mid;
       }
       s_ent = lo;
@@ -407,10 +392,9 @@ __global__ __launch_bounds__(FIN_T) void k_fin_cut(FinBatch b, int B, const u64*
       for (int kk = threadIdx.x; kk <= T; kk += T) {
         const unsigned e = ent + kk;
         if (e < ne) {
-          const u64 x = (u64)L[e];
-          const int v = (int)(x & 0xffffffffull);
-          w_pre[kk] = (unsigned)(x >> 32);
-          w_first[kk] = rp_g[t.vbeg + v];
+          const int v = LV[e];
+          w_pre[kk] = LA[e];
+          w_first[kk] = t.rp[v];
           w_c[kk] = Ps[v] & mask;
         } else {
           w_pre[kk] = na;
@@ -427,9 +411,12 @@ __global__ __launch_bounds__(FIN_T) void k_fin_cut(FinBatch b, int B, const u64*
           if (w_pre[mid] <= a) lo = mid;
           else hi = mid;
         }
-        const long long w = (long long)col_g[(long long)w_first[lo] + (a - w_pre[lo])];  // arena id
-        if ((hbits[w >> 6] >> (w & 63)) & 1) cut += 2;
-        else cut += (P[w] & mask) != w_c[lo];
+        const int wl = t.col[(long long)w_first[lo] + (a - w_pre[lo])];
+        if ((unsigned)wl < (unsigned)t.n) {  // (a request with a bad column id fails anyway)
+          const long long w = t.vbeg + wl;  // arena id
+          if ((hbits[w >> 6] >> (w & 63)) & 1) cut += 2;
+          else cut += (P[w] & mask) != w_c[lo];
+        }
       }
       const unsigned next = tile + T;
       __syncthreads();
@@ -479,8 +466,8 @@ __global__ void k_fin_out(FinBatch b, u64* __restrict__ cut_acc, unsigned* __res
 // Rebase: every live key drops by X rounds.  Keys below X rounds belong to vertices outside the
 // active slots (free ranges, separators, finished requests): they become 0, i.e. settled.
 // The slots' r0 and the host's round numbering move by the same X.
-__global__ __launch_bounds__(256) void k_rebase(long long V, int B, u64 C, long long X, u64* __restrict__ P,
-                                                long long* __restrict__ shift_g, u64* __restrict__ lr_part, int n_lr,
+__global__ __launch_bounds__(256) void k_rebase(long long V, int B, long long X, u64* __restrict__ P,
+                                                u64* __restrict__ lr_part, int n_lr,
                                                 u64* __restrict__ s_lr, SlotInfo* __restrict__ slots, int nslots,
                                                 RoundState* st, long long k_last) {
   const u64 xf = (u64)X * S_ONE;
@@ -491,8 +478,6 @@ __global__ __launch_bounds__(256) void k_rebase(long long V, int B, u64 C, long 
     if (i < V) {
       const u64 p = P[i];
       if (p != INF) P[i] = (p >> B) >= xf ? p - (xf << B) : 0;
-      const u64 off = C - (u64)shift_g[i];
-      shift_g[i] = (long long)(off >= xf ? C - (off - xf) : C);
     }
     if (i < n_lr) {
       const u64 l = lr_part[i];
@@ -572,7 +557,7 @@ struct Request {
   int state = RQ_QUEUED;
   ldd_status status = LDD_ERR_PENDING;
   int slot = -1;
-  long long vbeg = 0, abeg = 0;
+  long long vbeg = 0;
   long long r0 = 0;          // global round of its round 0 (numbering at admission)
   long long first_step = 0;  // the step that runs its round 0
   int R = -1;                // rounds, once the admission has reported them
@@ -585,9 +570,8 @@ struct Request {
 struct ldd_server {
   ldd_server_config cfg{};
   int dev = 0;
-  long long vcap = 0, acap = 0;
+  long long vcap = 0;
   int B = 1;
-  u64 C = 0;                  // engine Delta: a vertex's source-arc length is C - shift_g
   long long round_limit = 0;  // keys stay below round_limit * 2^20
   int max_rounds = 0;         // largest R a request may have
   hipStream_t stream = nullptr;
@@ -596,7 +580,7 @@ struct ldd_server {
   int blocks = 0;
   // arena and engine buffers (device)
   void *P = nullptr, *qv0 = nullptr, *qv1 = nullptr, *qa0 = nullptr, *qa1 = nullptr, *wake_ord = nullptr;
-  void *rp_g = nullptr, *col_g = nullptr, *shift_g = nullptr, *wake_tab = nullptr, *cnt = nullptr, *cur = nullptr;
+  void *wake_tab = nullptr, *cnt = nullptr, *cur = nullptr;
   void *slots = nullptr, *st = nullptr, *qcnt = nullptr, *lr_part = nullptr, *lb = nullptr, *ex_part = nullptr;
   void *ctrl = nullptr, *adm_max = nullptr, *adm_err = nullptr, *cut_acc = nullptr;
   void *sst = nullptr, *s_cnt = nullptr, *s_lr = nullptr, *stamp = nullptr;
@@ -605,7 +589,7 @@ struct ldd_server {
   SlotEnd* s_end_dev = nullptr;  // its device address
   SlotReport* rep = nullptr;      // mapped host memory
   SlotReport* rep_dev = nullptr;  // its device address
-  RangeAlloc valloc, aalloc;
+  RangeAlloc valloc;
   Request* slot_req[MAX_SLOTS] = {};
   long long steps = 0;       // steps enqueued so far
   long long round_base = 0;  // global round of step 1 in the current numbering
@@ -671,23 +655,22 @@ ldd_status srv_alloc(ldd_server* srv, void** p, size_t bytes) {
   return LDD_OK;
 }
 
-// Device bytes per arena vertex (label, two queues with arc prefixes, wake order, row offset,
-// shift, tail stamp) and per arena arc (column id).
-constexpr long long BYTES_PER_VERTEX = 8 + 8 + 8 + 4 + 4 + 8 + 4;
-constexpr long long BYTES_PER_ARC = 4;
+// Device bytes per arena vertex: label, two queues with arc prefixes, wake order, tail stamp
+// and a bit of the finishing bitmap (rounded up).  The requests' CSR and shifts stay in the
+// callers' buffers.
+constexpr long long BYTES_PER_VERTEX = 8 + 8 + 8 + 4 + 4 + 1;
 
 ldd_status srv_setup(ldd_server* srv) {
   SRV_TRY(hipSetDevice(srv->dev));
   SRV_TRY(hipStreamCreateWithFlags(&srv->stream, hipStreamNonBlocking));
   for (auto& e : srv->chunk_ev) SRV_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-  const long long V = srv->vcap, A = srv->acap;
+  const long long V = srv->vcap;
   const size_t per_slot = (size_t)MAX_SLOTS * (srv->max_rounds + 1);
   ldd_status s;
   if ((s = srv_alloc(srv, &srv->P, V * 8)) || (s = srv_alloc(srv, &srv->qv0, V * 4)) ||
       (s = srv_alloc(srv, &srv->qv1, V * 4)) || (s = srv_alloc(srv, &srv->qa0, V * 4)) ||
       (s = srv_alloc(srv, &srv->qa1, V * 4)) || (s = srv_alloc(srv, &srv->wake_ord, V * 4)) ||
-      (s = srv_alloc(srv, &srv->rp_g, (V + 1) * 4)) || (s = srv_alloc(srv, &srv->col_g, A * 4)) ||
-      (s = srv_alloc(srv, &srv->shift_g, V * 8)) || (s = srv_alloc(srv, &srv->wake_tab, per_slot * 4)) ||
+      (s = srv_alloc(srv, &srv->wake_tab, per_slot * 4)) ||
       (s = srv_alloc(srv, &srv->cnt, per_slot * 4)) || (s = srv_alloc(srv, &srv->cur, per_slot * 4)) ||
       (s = srv_alloc(srv, &srv->slots, sizeof(SlotInfo) * MAX_SLOTS)) ||
       (s = srv_alloc(srv, &srv->st, 2 * sizeof(RoundState))) || (s = srv_alloc(srv, &srv->qcnt, 3 * 16 * 8)) ||
@@ -710,7 +693,6 @@ ldd_status srv_setup(ldd_server* srv) {
   const hipStream_t q = srv->stream;
   // every vertex is settled (label 0) until a request claims it
   SRV_TRY(hipMemsetAsync(srv->P, 0, V * 8, q));
-  SRV_TRY(hipMemsetAsync(srv->shift_g, 0, V * 8, q));
   SRV_TRY(hipMemsetAsync(srv->cnt, 0, per_slot * 4, q));
   SRV_TRY(hipMemsetAsync(srv->slots, 0, sizeof(SlotInfo) * MAX_SLOTS, q));
   SRV_TRY(hipMemsetAsync(srv->qcnt, 0, 3 * 16 * 8, q));
@@ -736,7 +718,6 @@ ldd_status srv_setup(ldd_server* srv) {
   pair[1].seq = -1;
   SRV_TRY(hipMemcpyAsync(srv->st, pair, sizeof(pair), hipMemcpyHostToDevice, q));
   srv->valloc.init(V);
-  srv->aalloc.init(A);
 
   int ncu = 0;
   SRV_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, srv->dev));
@@ -747,12 +728,12 @@ ldd_status srv_setup(ldd_server* srv) {
   c.n = (int)V;
   c.B = srv->B;
   c.R = INT32_MAX;
-  c.nnz = A;
-  c.delta = srv->C;
+  c.nnz = 0;  // the requests' CSR and shifts are read through their slots
+  c.delta = 0;
   c.n_active = 0;
-  c.row_ptr = (const int*)srv->rp_g;
-  c.col = (const int*)srv->col_g;
-  c.shift = (const long long*)srv->shift_g;
+  c.row_ptr = nullptr;
+  c.col = nullptr;
+  c.shift = nullptr;
   c.P = (u64*)srv->P;
   c.qv[0] = (int*)srv->qv0;
   c.qv[1] = (int*)srv->qv1;
@@ -781,6 +762,7 @@ ldd_status srv_setup(ldd_server* srv) {
   c.s_cnt = (u64*)srv->s_cnt;
   c.s_lr = (u64*)srv->s_lr;
   c.s_end = srv->s_end_dev;
+  c.slot_err = (unsigned*)srv->adm_err;
   lb.kbase = 1;
   SRV_TRY(hipMemcpyAsync(srv->lb, &lb, sizeof(LaunchBlock), hipMemcpyHostToDevice, q));
   SRV_TRY(hipStreamSynchronize(q));
@@ -834,7 +816,6 @@ ldd_status srv_admit(ldd_server* srv, const std::vector<Request*>& rs) {
       t.col = r->q.col_idx;
       t.shift = (const long long*)r->q.shift_fix;
       t.vbeg = r->vbeg;
-      t.abeg = r->abeg;
       t.nnz = r->q.nnz;
       t.r0 = r->r0;
       t.n = r->q.n;
@@ -846,9 +827,8 @@ ldd_status srv_admit(ldd_server* srv, const std::vector<Request*>& rs) {
     }
     hipLaunchKernelGGL(k_adm_check, dim3(nblk), dim3(ADM_T), 0, s, ab, (u64*)srv->adm_max, (unsigned*)srv->adm_err,
                        (u64*)srv->adm_hub);
-    hipLaunchKernelGGL(k_adm_load, dim3(nblk), dim3(ADM_T), 0, s, ab, srv->C, srv->B, srv->max_rounds,
-                       (const u64*)srv->adm_max, (unsigned*)srv->adm_err, (int*)srv->rp_g, (int*)srv->col_g,
-                       (long long*)srv->shift_g, (u64*)srv->P, (unsigned*)srv->cnt);
+    hipLaunchKernelGGL(k_adm_load, dim3(nblk), dim3(ADM_T), 0, s, ab, srv->B, srv->max_rounds,
+                       (const u64*)srv->adm_max, (const unsigned*)srv->adm_err, (u64*)srv->P, (unsigned*)srv->cnt);
     hipLaunchKernelGGL(k_adm_commit, dim3(ab.count), dim3(ADM_T), 0, s, ab, srv->max_rounds,
                        (const u64*)srv->adm_max, (unsigned*)srv->adm_err, (unsigned*)srv->cnt,
                        (unsigned*)srv->cur, (int*)srv->wake_tab, (SlotInfo*)srv->slots, (RoundState*)srv->st,
@@ -871,8 +851,9 @@ ldd_status srv_finish(ldd_server* srv, const std::vector<Request*>& rs) {
       Request* r = rs[i];
       FinItem t{};
       t.centre = r->q.centre;
+      t.rp = r->q.row_ptr;
+      t.col = r->q.col_idx;
       t.vbeg = r->vbeg;
-      t.abeg = r->abeg;
       t.nnz = r->q.nnz;
       t.n = r->q.n;
       t.slot = r->slot;
@@ -887,11 +868,11 @@ ldd_status srv_finish(ldd_server* srv, const std::vector<Request*>& rs) {
       r->state = RQ_FINISHING;
     }
     hipLaunchKernelGGL(k_fin_vertices, dim3(nv), dim3(FIN_T), 0, s, fv, srv->B, (const u64*)srv->P,
-                       (const int*)srv->rp_g, (const SlotInfo*)srv->slots, (const u64*)srv->adm_hub,
-                       (u64*)srv->hbits, (long long*)srv->shift_g, (u64*)srv->lcnt);
-    hipLaunchKernelGGL(k_fin_cut, dim3(nc), dim3(FIN_T), 0, s, fc, srv->B, (const u64*)srv->P, (const int*)srv->rp_g,
-                       (const int*)srv->col_g, (const u64*)srv->hbits, (const long long*)srv->shift_g,
-                       (const u64*)srv->lcnt, (u64*)srv->cut_acc);
+                       (const SlotInfo*)srv->slots, (const u64*)srv->adm_hub, (u64*)srv->hbits, (int*)srv->qv0,
+                       (unsigned*)srv->qa0, (u64*)srv->lcnt);
+    hipLaunchKernelGGL(k_fin_cut, dim3(nc), dim3(FIN_T), 0, s, fc, srv->B, (const u64*)srv->P, (const u64*)srv->hbits,
+                       (const int*)srv->qv0, (const unsigned*)srv->qa0, (const u64*)srv->lcnt,
+                       (u64*)srv->cut_acc);
     hipLaunchKernelGGL(k_fin_out, dim3(1), dim3(64), 0, s, fv, (u64*)srv->cut_acc, (unsigned*)srv->adm_err,
                        (u64*)srv->adm_max, (u64*)srv->adm_hub, (u64*)srv->lcnt, (const Ctrl*)srv->ctrl,
                        (SlotInfo*)srv->slots, srv->rep_dev);
@@ -903,8 +884,7 @@ ldd_status srv_finish(ldd_server* srv, const std::vector<Request*>& rs) {
 // Lower the global round numbering by X rounds (X <= every active slot's r0).
 ldd_status srv_rebase(ldd_server* srv, long long X) {
   hipLaunchKernelGGL(k_rebase, dim3((unsigned)std::min<long long>(8192, (std::max<long long>(srv->vcap, 2 * RT) + 255) / 256)), dim3(256), 0,
-                     srv->stream, srv->vcap, srv->B, srv->C, X, (u64*)srv->P, (long long*)srv->shift_g,
-                     (u64*)srv->lr_part, 2 * RT, (u64*)srv->s_lr, (SlotInfo*)srv->slots, MAX_SLOTS,
+                     srv->stream, srv->vcap, srv->B, X, (u64*)srv->P, (u64*)srv->lr_part, 2 * RT, (u64*)srv->s_lr, (SlotInfo*)srv->slots, MAX_SLOTS,
                      (RoundState*)srv->st, srv->steps);
   SRV_TRY(hipGetLastError());
   srv->round_base -= X;
@@ -942,7 +922,6 @@ ldd_status engine_loop(ldd_server* srv) {
       {
         std::lock_guard<std::mutex> lk(srv->mu);
         srv->valloc.give(r->vbeg, vrange(r->q.n));
-        srv->aalloc.give(r->abeg, r->q.nnz);
         srv->slot_req[r->slot] = nullptr;
         r->status = status_of(err);
         r->cut = r->status == LDD_OK ? (int64_t)rp.cut : 0;
@@ -998,14 +977,9 @@ ldd_status engine_loop(ldd_server* srv) {
           if (!srv->slot_req[i]) slot = i;
         if (slot < 0) break;
         const long long vb = srv->valloc.take(vrange(r->q.n));
-        const long long ab = vb < 0 ? -1 : srv->aalloc.take(r->q.nnz);
-        if (ab < 0) {
-          if (vb >= 0) srv->valloc.give(vb, vrange(r->q.n));
-          break;
-        }
+        if (vb < 0) break;
         srv->queue.pop_front();
         r->vbeg = vb;
-        r->abeg = ab;
         r->slot = slot;
         r->r0 = r0;
         r->first_step = srv->steps + 1;
@@ -1116,28 +1090,19 @@ extern "C" ldd_status ldd_server_create(const ldd_server_config* cfg, ldd_server
     ldd_set_error("no HIP device");
     return LDD_ERR_HIP;
   }
-  long long V = srv->cfg.max_vertices, A = srv->cfg.max_arcs;
-  if (V <= 0 || A <= 0) {  // split the budget for graphs of about 16 arcs per vertex
-    V = srv->cfg.hbm_budget_bytes / (BYTES_PER_VERTEX + 16 * BYTES_PER_ARC);
-    A = 16 * V;
-    if (A >= (1ll << 31)) {  // arc ids are int32: the rest of the budget goes to vertices
-      A = (1ll << 31) - 1;
-      V = std::min<long long>(1ll << 30, (srv->cfg.hbm_budget_bytes - A * BYTES_PER_ARC) / BYTES_PER_VERTEX);
-    }
-  }
-  const long long used = V * BYTES_PER_VERTEX + A * BYTES_PER_ARC;
-  if (V < 2 || V > (1ll << 30) || A < 1 || A >= (1ll << 31) ||
-      (srv->cfg.hbm_budget_bytes > 0 && used > srv->cfg.hbm_budget_bytes)) {
+  long long V = srv->cfg.max_vertices;
+  if (V <= 0) V = std::min<long long>(1ll << 30, srv->cfg.hbm_budget_bytes / BYTES_PER_VERTEX);
+  const long long used = V * BYTES_PER_VERTEX;
+  if (V < 64 || V > (1ll << 30) || (srv->cfg.hbm_budget_bytes > 0 && used > srv->cfg.hbm_budget_bytes)) {
     delete srv;
-    ldd_set_error("budget gives an unusable arena (%lld vertices, %lld arcs, %lld bytes)", V, A, used);
+    ldd_set_error("budget gives an unusable arena (%lld vertices, %lld bytes)", V, used);
     return LDD_ERR_BUDGET;
   }
   srv->vcap = V;
-  srv->acap = A;
   srv->B = log2_ceil(V);
   srv->round_limit = std::min<long long>(1ll << 30, 1ll << (64 - srv->B - FIX - 1));
   if (srv->cfg.max_rounds > 0) srv->round_limit = std::min<long long>(srv->round_limit, srv->cfg.max_rounds);
-  srv->C = (u64)srv->round_limit << FIX;  // keys stay below C, and (C + 2^20) << B < 2^64
+  // keys stay below round_limit * 2^20, so (key + 2^20) << B < 2^64
   srv->max_rounds = (int)std::min<long long>(QCAP, srv->round_limit / 2 - 1);
   if (srv->max_rounds < 1) {
     delete srv;
@@ -1165,9 +1130,8 @@ extern "C" ldd_status ldd_server_submit(ldd_server* srv, const ldd_request* req,
     ldd_set_error("bad request");
     return LDD_ERR_INVALID_ARG;
   }
-  if (vrange(req->n) > srv->vcap || req->nnz > srv->acap) {
-    ldd_set_error("request of %d vertices and %lld arcs exceeds the arena (%lld, %lld)", req->n,
-                  (long long)req->nnz, srv->vcap, srv->acap);
+  if (vrange(req->n) > srv->vcap) {
+    ldd_set_error("request of %d vertices exceeds the arena (%lld vertices)", req->n, srv->vcap);
     return LDD_ERR_BUDGET;
   }
   Request* r = new Request();
@@ -1278,7 +1242,7 @@ extern "C" ldd_status ldd_server_query(ldd_server* srv, ldd_server_info* out) {
   }
   std::lock_guard<std::mutex> lk(srv->mu);
   out->arena_vertices = srv->vcap;
-  out->arena_arcs = srv->acap;
+  out->arena_arcs = 0;  // arcs stay in the callers' buffers
   out->max_rounds = srv->max_rounds;
   out->max_slots = srv->cfg.max_slots;
   out->admitted = srv->admitted;
@@ -1303,7 +1267,7 @@ extern "C" ldd_status ldd_server_destroy(ldd_server* srv) {
   if (srv->engine.joinable()) srv->engine.join();
   const ldd_status fatal = srv->fatal;
   if (srv->stream) (void)hipStreamSynchronize(srv->stream);
-  for (void* p : {srv->P, srv->qv0, srv->qv1, srv->qa0, srv->qa1, srv->wake_ord, srv->rp_g, srv->col_g, srv->shift_g,
+  for (void* p : {srv->P, srv->qv0, srv->qv1, srv->qa0, srv->qa1, srv->wake_ord,
                   srv->wake_tab, srv->cnt, srv->cur, srv->slots, srv->st, srv->qcnt, srv->lr_part, srv->lb,
                   srv->ex_part, srv->ctrl, srv->adm_max, srv->adm_err, srv->cut_acc, srv->sst,
                   srv->s_cnt, srv->s_lr, srv->stamp, srv->adm_hub, srv->hbits, srv->lcnt})
