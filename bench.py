@@ -6,12 +6,16 @@ symmetrised, relabelled; 16.7M vertices, 260M edges) with beta = 0.05 and seeded
 shifts, inputs resident in HBM.  Prints one JSON line.
 
   value        GTEPS = undirected edges / seconds per step (whole graph)
-  roofline     the round kernel: algorithmic bytes / its average duration (HIP events on the
-               launch stream), against 8 TB/s HBM3E
-  cpu_baseline the CPU oracle (single-threaded Dijkstra) on a bounded sample of the same
-               workload family (RMAT scale 22), on this host
+  roofline     the round kernel: algorithmic bytes per launch over its average launch
+               duration (HIP events on the launch stream), against 8 TB/s HBM3E; traffic from
+               the committed rocprofv3 counter runs when they match the current kernel sources
+  batched      512 uneven graphs in one call (one launch per round for all) vs one call each
+  served       a Poisson stream of RMAT 12-22 requests through the serving engine vs the same
+               stream one decomposition at a time (FIFO), latency p50 / p99 and capacity
+  cpu_baseline the CPU oracle (single-threaded Dijkstra) on the same graph and shifts
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rmat-24] [--no-cpu-baseline]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rmat-24]
+                       [--no-batch] [--no-serve] [--no-cpu-baseline] [--copy-probe]
 """
 import argparse
 import hashlib
@@ -33,11 +37,15 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(st):
-    """Bytes the round kernel must move: per arc read, its column id (4 B) and the far end's
-    label (8 B); per non-isolated vertex, its two row offsets (8 B), shift (8 B), label
-    written (8 B) and queue entry written and read back (16 B)."""
-    return 12 * st["arcs_examined"] + 40 * st["n_active"]
+def algorithmic_bytes(st, n):
+    """Bytes the round kernel must move over one decomposition:
+    per arc examined, its column id (4 B) and the far end's label (8 B);
+    per vertex with arcs, its wake-order entry (4 B) and shift (8 B) when woken, its two row
+    offsets (8 B), its label written (8 B), and its queue entry (vertex and arc prefix, 8 B)
+    written and read back (16 B): 44 B;
+    per pull pass (every bottom-up round and the tail seed), every label read once (8 B)."""
+    pulls = st["bu_rounds"] + (1 if st["tail_round"] >= 0 else 0)
+    return 12 * st["arcs_examined"] + 44 * st["n_active"] + 8 * n * pulls
 
 
 def kernel_sources_sha():
@@ -61,17 +69,16 @@ def measured_traffic(workload):
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline(sample="rmat-22"):
+def cpu_baseline(rp, ci, s, name):
+    """The CPU oracle (single-threaded Dijkstra over the same integer keys) on the same graph
+    and shifts as the GPU run: one run, timed on this host."""
     import oracle  # the CPU leg only
-
-    import inputs
-    rp, ci, s, beta = inputs.workload(sample)
     t = time.perf_counter()
     oracle.decompose(rp, ci, s)
     dt = time.perf_counter() - t
     return {"value": round(ci.size / 2 / dt / 1e9, 6), "unit": "GTEPS", "cores": 1, "kind": "oracle",
-            "sample": f"{sample}: RMAT scale 22, same generator and beta, n={rp.size - 1}, m={ci.size // 2}, "
-                      f"1 run of {dt:.1f} s single-threaded"}
+            "sample": f"{name}: the whole benchmark graph and shifts (n={rp.size - 1}, m={ci.size // 2}), "
+                      f"1 run of {dt:.1f} s on one core of this host"}
 
 
 def pack(graphs):
@@ -217,7 +224,7 @@ def serve_run(ldd, srv, tm, req, outs, arrivals=None):
     return lat, float(done_py.max() - start), results
 
 
-def run_serving(n_requests: int = 2000, budget_gib: float = 16.0, small_budget_gib: float = 1.0):
+def run_serving(n_requests: int = 2000, budget_gib: float = 16.0, small_budget_gib: float = 0.25):
     """Serving: a stream of RMAT 12-22 requests through ldd_server_* (continuous batching into
     one device-resident arena) against the plain path (one ldd_decompose per request, FIFO).
     Capacity comes from a saturating closed loop; latency from Poisson arrivals at 80% of it."""
@@ -317,6 +324,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after the steps, copy 1 GiB three times (a plain copy kernel of known size, to "
+                         "calibrate HBM byte counters taken in the same run)")
     ap.add_argument("--engine", type=int, default=0)
     ap.add_argument("--direction", type=int, default=0)
     ap.add_argument("--blocks", type=int, default=0)
@@ -365,9 +375,19 @@ def main():
             bit_exact = bool(hashlib.sha256(got.view(np.uint8)).hexdigest() == gold["sha_centre"]
                              and cut == gold["cut"])
 
+    if args.copy_probe:
+        a = torch.ones(1 << 28, dtype=torch.int32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    # the round kernel: algorithmic bytes per launch over its average launch duration (HIP
+    # events around the launches on their stream)
     t_rounds = float(np.mean(rounds_ms)) * 1e-3
-    alg = algorithmic_bytes(stats)
-    achieved = alg / t_rounds / 1e9 if t_rounds > 0 else 0.0
+    launches = max(1, stats["steps"])
+    alg = algorithmic_bytes(stats, n)
+    achieved = (alg / launches) / (t_rounds / launches) / 1e9 if t_rounds > 0 else 0.0
     traffic = measured_traffic(args.workload)
     out = {
         "metric": METRIC,
@@ -390,10 +410,10 @@ def main():
         "bit_exact": bit_exact,
         "rounds": stats["rounds"], "td_rounds": stats["td_rounds"], "bu_rounds": stats["bu_rounds"],
         "tail_sweeps": stats["tail_iters"], "stage_ms": {k: round(stats[k], 4) for k in ("ms_prep", "ms_rounds", "ms_finalize", "ms_cut")},
-        "roofline": {"bound": "hbm", "kernel": "k_round_step", "achieved": round(achieved, 1),
+        "roofline": {"bound": "hbm", "kernel": "k_round_step_lb", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "algorithmic_bytes": int(alg),
-                     "kernel_ms": round(t_rounds * 1e3, 4)},
+                     "traffic": traffic, "algorithmic_bytes_per_launch": int(alg / launches),
+                     "launches": launches, "avg_launch_us": round(t_rounds / launches * 1e6, 3)},
     }
     if not args.no_batch:
         del d_rp, d_ci, d_s, centre
@@ -403,8 +423,8 @@ def main():
         torch.cuda.empty_cache()
         out["served"] = run_serving(args.serve_requests)
     if not args.no_cpu_baseline:
-        log("cpu baseline: oracle on rmat-22 ...")
-        out["cpu_baseline"] = cpu_baseline()
+        log(f"cpu baseline: oracle on {args.workload} ...")
+        out["cpu_baseline"] = cpu_baseline(rp, ci, s, args.workload)
     print(json.dumps(out), flush=True)
 
 

@@ -103,6 +103,7 @@ typedef struct {
   float ms_rounds;         /* device time: all rounds                                     */
   float ms_finalize;       /* device time: centre extraction                              */
   float ms_cut;            /* device time: cut count                                      */
+  int32_t steps;           /* round-kernel launches (steps) enqueued, done ones included  */
 } ldd_stats;
 
 /*

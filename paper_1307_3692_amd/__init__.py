@@ -56,7 +56,7 @@ class Stats(ctypes.Structure):
                 ("delta", ctypes.c_int64), ("pieces", ctypes.c_int64), ("max_frontier", ctypes.c_int64),
                 ("arcs_examined", ctypes.c_int64), ("n_active", ctypes.c_int64),
                 ("ms_prep", ctypes.c_float), ("ms_rounds", ctypes.c_float), ("ms_finalize", ctypes.c_float),
-                ("ms_cut", ctypes.c_float)]
+                ("ms_cut", ctypes.c_float), ("steps", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

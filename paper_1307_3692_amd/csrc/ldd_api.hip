@@ -420,6 +420,7 @@ static ldd_status decompose_impl(Workspace& w, const ldd_csr* g, const int64_t* 
                                          args, 0, st));
       HIP_TRY(hipMemcpyAsync(w.host->st, w.st.p, 2 * sizeof(RoundState), hipMemcpyDeviceToHost, st));
       HIP_TRY(hipStreamSynchronize(st));
+      steps = 1;
     } else {
       // Steps run as replays of a captured chunk graph.  Two chunks are kept in flight: the
       // host waits for the older one, reads the state the steps publish to mapped host memory,
@@ -462,7 +463,6 @@ static ldd_status decompose_impl(Workspace& w, const ldd_csr* g, const int64_t* 
       HIP_TRY(hipMemcpyAsync(w.host->st, w.st.p, 2 * sizeof(RoundState), hipMemcpyDeviceToHost, st));
     }
   }
-  (void)steps;
   HIP_TRY(hipEventRecord(w.ev[2], st));
   const int g_f = grid_for((n + 63) / 64, 256, 1024);  // whole bitmap words per block
   hipLaunchKernelGGL(k_finalize, dim3(g_f), dim3(1024), 0, st, n, B, g->row_ptr, (const u64*)P, centre,
@@ -496,6 +496,7 @@ static ldd_status decompose_impl(Workspace& w, const ldd_csr* g, const int64_t* 
     stats->tail_iters = n_active ? (int32_t)fs.tail_iters : 0;
     stats->tail_round = n_active ? (int32_t)fs.tail_round : -1;
     stats->blocks = blocks;
+    stats->steps = (int32_t)steps;
     stats->delta = (int64_t)delta;
     stats->pieces = (int64_t)h.pieces;
     stats->max_frontier = n_active ? (int64_t)fs.max_frontier : 0;
