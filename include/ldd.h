@@ -140,6 +140,28 @@ ldd_status ldd_decompose_batch(int32_t num_graphs, const int64_t* vtx_off, const
                                int32_t* centre, int64_t* cut_edges, const ldd_options* opt, void* hip_stream);
 
 /*
+ * Tune the round engine's mapping for a workload: grid size (blocks), the top-down / bottom-up
+ * switching thresholds (td_to_bu, bu_to_td) and the tail threshold (tail_vertices), searched one
+ * knob at a time by timing whole decompositions of the given inputs (median of three, HIP
+ * events on hip_stream).  The inputs are those of ldd_decompose_batch (num_graphs = 1: one graph,
+ * run through ldd_decompose); centre is scratch output of the right size.  Every candidate gives
+ * the same result, so only time is traded.  The winner is cached per workload signature (device,
+ * CU count, number of graphs, vertices, arcs) in the process and, if cache_path is not NULL, in
+ * that text file (appended; a later line for a signature wins).  base (may be NULL) supplies the
+ * other options.  *best receives base with the tuned knobs; *report (may be NULL) the timings.
+ */
+typedef struct {
+  float default_ms;   /* the starting point (the base options' knobs, or the defaults)       */
+  float best_ms;      /* the winner (from the cache if from_cache)                            */
+  int32_t runs;       /* decompositions timed                                                 */
+  int32_t from_cache; /* 1: no run, the cached winner was returned                            */
+} ldd_tune_report;
+
+ldd_status ldd_tune(int32_t num_graphs, const int64_t* vtx_off, const int64_t* arc_off, const int32_t* row_ptr,
+                    const int32_t* col_idx, const int64_t* shift_fix, int32_t* centre, const ldd_options* base,
+                    const char* cache_path, ldd_options* best, ldd_tune_report* report, void* hip_stream);
+
+/*
  * Serving: a long-lived engine that decomposes a stream of independent requests (the same
  * operation as ldd_decompose per request, bit for bit) with continuous batching.  Admitted
  * requests share one device-resident arena of per-vertex state and advance together, one

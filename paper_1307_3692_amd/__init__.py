@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _ROOT = os.path.dirname(_HERE)
 SO_PATH = os.path.join(_HERE, "libldd.so")
 SOURCES = [os.path.join(_HERE, "csrc", f) for f in ("ldd_kernels.hip", "ldd_rounds.hip", "ldd_api.hip",
-                                                   "ldd_batch.hip", "ldd_server.hip")]
+                                                   "ldd_batch.hip", "ldd_server.hip", "ldd_tune.hip")]
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
@@ -28,7 +28,7 @@ ENGINE_AUTO, ENGINE_PERSISTENT, ENGINE_LAUNCH = 0, 1, 2
 
 EXPORTED = ("ldd_decompose", "ldd_workspace_bytes", "ldd_decompose_batch", "ldd_status_string", "ldd_last_error",
             "ldd_release_workspace", "ldd_server_create", "ldd_server_submit", "ldd_server_poll", "ldd_server_wait",
-            "ldd_server_cancel", "ldd_server_query", "ldd_server_destroy")
+            "ldd_server_cancel", "ldd_server_query", "ldd_server_destroy", "ldd_tune")
 
 
 class LddError(RuntimeError):
@@ -57,6 +57,14 @@ class Stats(ctypes.Structure):
                 ("arcs_examined", ctypes.c_int64), ("n_active", ctypes.c_int64),
                 ("ms_prep", ctypes.c_float), ("ms_rounds", ctypes.c_float), ("ms_finalize", ctypes.c_float),
                 ("ms_cut", ctypes.c_float), ("steps", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class TuneReport(ctypes.Structure):
+    _fields_ = [("default_ms", ctypes.c_float), ("best_ms", ctypes.c_float), ("runs", ctypes.c_int32),
+                ("from_cache", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -136,6 +144,9 @@ def lib():
     L.ldd_server_destroy.argtypes = [vp]
     for f in ("create", "submit", "poll", "wait", "cancel", "query", "destroy"):
         getattr(L, "ldd_server_" + f).restype = i32
+    L.ldd_tune.argtypes = [i32, vp, vp, vp, vp, vp, vp, ctypes.POINTER(Options), ctypes.c_char_p,
+                           ctypes.POINTER(Options), ctypes.POINTER(TuneReport), vp]
+    L.ldd_tune.restype = i32
     _lib = L
     return L
 
@@ -231,6 +242,39 @@ def decompose_batch(vtx_off, arc_off, row_ptr, col_idx, shift_fix, *, centre=Non
                                      col_idx.data_ptr() if col_idx.numel() else None, shift_fix.data_ptr(),
                                      centre.data_ptr(), cuts.ctypes.data, ctypes.byref(o), _stream_handle(stream)))
     return centre, [int(x) for x in cuts[:G]]
+
+
+def tune(row_ptr, col_idx, shift_fix, *, vtx_off=None, arc_off=None, centre=None, cache_path=None, stream=None,
+         **opts):
+    """Tune the round engine's knobs (``ldd_tune``) for one graph (no offsets) or a packed batch.
+
+    Returns ``(options dict for decompose / decompose_batch, report dict)``.
+    """
+    import numpy as np
+    import torch
+    _device_tensor(row_ptr, torch.int32, "row_ptr")
+    _device_tensor(col_idx, torch.int32, "col_idx")
+    _device_tensor(shift_fix, torch.int64, "shift_fix")
+    if vtx_off is None:
+        n = row_ptr.numel() - 1
+        vo = np.array([0, n], dtype=np.int64)
+        ao = np.array([0, col_idx.numel()], dtype=np.int64)
+    else:
+        vo = np.ascontiguousarray(vtx_off, dtype=np.int64)
+        ao = np.ascontiguousarray(arc_off, dtype=np.int64)
+    G = vo.size - 1
+    if centre is None:
+        centre = torch.empty(int(vo[-1]), dtype=torch.int32, device=row_ptr.device)
+    base = make_options(**opts)
+    best = Options()
+    rep = TuneReport()
+    _check(lib().ldd_tune(G, vo.ctypes.data, ao.ctypes.data, row_ptr.data_ptr(),
+                          col_idx.data_ptr() if col_idx.numel() else None, shift_fix.data_ptr(), centre.data_ptr(),
+                          ctypes.byref(base), cache_path.encode() if cache_path else None, ctypes.byref(best),
+                          ctypes.byref(rep), _stream_handle(stream)))
+    tuned = dict(opts, blocks=best.blocks, td_to_bu=best.td_to_bu, bu_to_td=best.bu_to_td,
+                 tail_vertices=best.tail_vertices)
+    return tuned, rep.as_dict()
 
 
 def workspace_bytes(n: int, nnz: int) -> int:

@@ -51,6 +51,7 @@ def test_argument_errors_answer_before_device_work():
     assert L.ldd_server_cancel(None, 1) == ldd.ERR_INVALID_ARG
     assert L.ldd_server_query(None, None) == ldd.ERR_INVALID_ARG
     assert L.ldd_server_destroy(None) == ldd.ERR_INVALID_ARG
+    assert L.ldd_tune(0, None, None, None, None, None, None, None, None, None, None, None) == ldd.ERR_INVALID_ARG
     # a graph descriptor with bad sizes is rejected from the descriptor alone
     g = ldd.Csr(-1, 0, None, None)
     assert L.ldd_decompose(ctypes.byref(g), None, 1.0, None, None, None, None, None) == ldd.ERR_INVALID_ARG
@@ -64,7 +65,7 @@ def test_workspace_bytes_grows_with_n():
 
 STRUCTS = {"ldd_csr": ldd.Csr, "ldd_options": ldd.Options, "ldd_stats": ldd.Stats,
            "ldd_server_config": ldd.ServerConfig, "ldd_request": ldd.Request, "ldd_result": ldd.Result,
-           "ldd_server_info": ldd.ServerInfo}
+           "ldd_server_info": ldd.ServerInfo, "ldd_tune_report": ldd.TuneReport}
 
 
 def test_ctypes_layouts_match_the_header(tmp_path):

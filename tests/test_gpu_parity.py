@@ -329,3 +329,41 @@ def test_batch_512_workload_digest(ldd):
     centre, cuts = ldd.decompose_batch(vo, ao, d_rp, d_ci, d_s)
     assert sha(centre.cpu().numpy()) == gold["sha_centre"]
     assert sha(np.array(cuts, np.int64)) == gold["sha_cuts"]
+
+
+def test_tuner_changes_time_only(ldd, tmp_path):
+    """ldd_tune searches the engine's knobs by timing; the tuned options give the same bits,
+    and a second call is answered from the cache (in the process and in the file)."""
+    rp, ci, s, beta = inputs.workload("rmat-16")
+    d = to_dev(rp, ci, s)
+    cache = str(tmp_path / "tune.txt")
+    opts, rep = ldd.tune(*d, cache_path=cache)
+    log(f"tuned {opts} {rep}")
+    assert rep["runs"] > 0 and rep["from_cache"] == 0 and rep["best_ms"] <= rep["default_ms"]
+    c_ref, _, cut_ref = oracle.decompose(rp, ci, s)
+    c1, cut1 = ldd.decompose(*d, beta, **opts)
+    assert np.array_equal(c1.cpu().numpy(), c_ref) and cut1 == cut_ref
+    opts2, rep2 = ldd.tune(*d, cache_path=cache)
+    assert rep2["from_cache"] == 1 and opts2 == opts
+    with open(cache) as f:
+        assert len(f.read().splitlines()) == 1
+
+
+def test_tuner_on_a_batch(ldd):
+    graphs = inputs.batch_graphs(24, seed=5, n_lo=200, n_hi=3000)
+    vo, ao = [0], [0]
+    for rp, ci, s, _ in graphs:
+        vo.append(vo[-1] + rp.size - 1)
+        ao.append(ao[-1] + ci.size)
+    rp = np.concatenate([g[0] for g in graphs])
+    ci = np.concatenate([g[1] for g in graphs])
+    s = np.concatenate([g[2] for g in graphs])
+    d_rp, d_ci, d_s = to_dev(rp, ci, s)
+    opts, rep = ldd.tune(d_rp, d_ci, d_s, vtx_off=vo, arc_off=ao)
+    assert rep["runs"] > 0
+    centre, cuts = ldd.decompose_batch(vo, ao, d_rp, d_ci, d_s, **opts)
+    got = centre.cpu().numpy()
+    for g, (grp, gci, gs, _) in enumerate(graphs):
+        c_ref, _, cut_ref = oracle.decompose(grp, gci, gs)
+        assert np.array_equal(got[vo[g]:vo[g + 1]], c_ref), g
+        assert cuts[g] == cut_ref, g
