@@ -97,6 +97,7 @@ struct Workspace {
   std::mutex mu;
   Buf P, qv0, qv1, qa0, qa1, wake_ord, stamp, hub_bits;  // per vertex
   Buf hist, cursor, wake_off, next_ne, mat, qmax;        // per round / q-bucket (mat: per bucket and prep block)
+  Buf cand, cand_cnt;                                    // per prep block: first-window candidates
   Buf ctrl, st, qcnt, lr_part, lb, ex_part;
   // batch: union CSR with global ids, adjusted shifts, graph of each vertex, per-graph data
   Buf b_rp, b_col, b_shift, b_gid, b_off, b_dg, b_cut;
@@ -183,10 +184,12 @@ int grid_for(long long items, int threads, int cap) {
 extern "C" size_t ldd_workspace_bytes(int32_t n, int64_t nnz) {
   (void)nnz;
   const size_t nv = n > 0 ? (size_t)n : 1;
-  // labels 8 + two queues (4 + 4 each) + wake order 4 + tail stamp 4 = 32 bytes per vertex, plus rounds
-  // arrays sized by the shift range (bounded here by 2^16 rounds) and the control block
-  return nv * 32 + (size_t)(65536 + 2) * (4 * 4) + sizeof(Ctrl) + 2 * sizeof(RoundState) + 3 * 16 * 8 +
-         2 * (size_t)RT * 8;
+  // labels 8 + two queues (4 + 4 each) + wake order 4 + tail stamp 4 = 32 bytes per vertex, the
+  // piece bitmap, the preparation's per-block bucket counts and window lists, rounds arrays
+  // sized by the shift range (bounded here by 2^16 rounds) and the control block
+  const size_t gp = std::min<size_t>(1024, std::max<size_t>(1, nv / 16384));
+  return nv * 32 + (nv + 63) / 64 * 8 + gp * ((size_t)QCAP * 4 + (size_t)CAND * 8 + 8) +
+         (size_t)(65536 + 2) * (4 * 4) + sizeof(Ctrl) + 2 * sizeof(RoundState) + 3 * 16 * 8 + 2 * (size_t)RT * 8;
 }
 
 extern "C" void ldd_release_workspace(void) {
@@ -197,7 +200,7 @@ extern "C" void ldd_release_workspace(void) {
   for (auto& g : w->graphs) (void)hipGraphExecDestroy(g.exec);  // they hold workspace pointers
   w->graphs.clear();
   for (Buf* b : {&w->P, &w->qv0, &w->qv1, &w->qa0, &w->qa1, &w->wake_ord, &w->stamp, &w->hub_bits, &w->hist,
-                 &w->cursor, &w->wake_off, &w->next_ne, &w->mat, &w->qmax, &w->ctrl, &w->st, &w->qcnt, &w->lr_part,
+                 &w->cursor, &w->wake_off, &w->next_ne, &w->mat, &w->qmax, &w->cand, &w->cand_cnt, &w->ctrl, &w->st, &w->qcnt, &w->lr_part,
                  &w->lb, &w->ex_part, &w->b_rp, &w->b_col, &w->b_shift, &w->b_gid, &w->b_off, &w->b_dg,
                  &w->b_cut}) {
     if (b->p) (void)hipFree(b->p);
@@ -293,10 +296,12 @@ static ldd_status decompose_impl(Workspace& w, const ldd_csr* g, const int64_t* 
   const int g_n = grid_for(n, 256 * 4, 2048);
   // preparation pass A: labels, Delta, checks and the q-bucket histogram (per block)
   const int gp = (int)std::min<long long>(1024, std::max<long long>(1, n / 16384));
-  if ((s = grow(w.mat, (size_t)QCAP * gp * 4)) || (s = grow(w.qmax, (size_t)gp * 4))) return s;
+  if ((s = grow(w.mat, (size_t)QCAP * gp * 4)) || (s = grow(w.qmax, (size_t)gp * 4)) ||
+      (s = grow(w.cand, (size_t)CAND * gp * 8)) || (s = grow(w.cand_cnt, (size_t)gp * 4)))
+    return s;
   HIP_TRY(hipMemsetAsync(ctrl, 0, sizeof(Ctrl), st));
   hipLaunchKernelGGL(k_init, dim3(gp), dim3(1024), 0, st, n, nnz, g->row_ptr, (const long long*)shift_fix, P, ctrl,
-                     (unsigned*)w.mat.p, (int*)w.qmax.p);
+                     (unsigned*)w.mat.p, (int*)w.qmax.p, (u64*)w.cand.p, (unsigned*)w.cand_cnt.p);
   if (o.validate && nnz > 0)
     hipLaunchKernelGGL(k_check_cols, dim3(grid_for(nnz, 256, 4096)), dim3(256), 0, st, n, nnz, g->col_idx, ctrl);
   HIP_TRY(hipGetLastError());
@@ -326,16 +331,20 @@ static ldd_status decompose_impl(Workspace& w, const ldd_csr* g, const int64_t* 
 
   const long long D = (long long)(delta >> FIX);
   int wake_q = 0;
+  long long place_lo = 0;
   if (!w.host->ctrl.wide && D < QCAP) {
-    // pass B: vertices sorted by the integer part of their shift, no global atomics
+    // pass B: vertices sorted by the integer part of their shift, no global atomics; only the
+    // first window of buckets is placed now (the round steps place the rest when needed)
     wake_q = 1;
+    place_lo = std::min<long long>(w.host->ctrl.place_lo, D + 1);
     hipLaunchKernelGGL(k_qbucket_scan, dim3((unsigned)(((D + 1) * WAVE + 255) / 256)), dim3(256), 0, st, (int)(D + 1),
                        gp, (unsigned*)w.mat.p, (const int*)w.qmax.p, (unsigned*)w.hist.p);
     hipLaunchKernelGGL(k_qscan, dim3(1), dim3(1024), 0, st, (int)D, (const unsigned*)w.hist.p, (int*)w.wake_off.p,
                        (int*)w.next_ne.p);
-    hipLaunchKernelGGL(k_place, dim3(gp), dim3(1024), 0, st, n, B, g->row_ptr, (const long long*)shift_fix,
-                       (const Ctrl*)ctrl, (const unsigned*)w.mat.p, (const int*)w.qmax.p, (const int*)w.wake_off.p,
-                       (int*)w.wake_ord.p, P);
+    if (place_lo <= D)
+      hipLaunchKernelGGL(k_place_window, dim3(gp), dim3(256), 0, st, (int)place_lo, (int)D, (const unsigned*)w.mat.p,
+                         (const int*)w.qmax.p, (const int*)w.wake_off.p, (const u64*)w.cand.p,
+                         (const unsigned*)w.cand_cnt.p, (int*)w.wake_ord.p);
   } else {
     // shifts spanning more than QCAP units: exact wake rounds via global atomics
     HIP_TRY(hipMemsetAsync(w.hist.p, 0, nr * 4, st));
@@ -358,6 +367,8 @@ static ldd_status decompose_impl(Workspace& w, const ldd_csr* g, const int64_t* 
   s0.dir = DIR_TD;
   s0.unsettled_arcs = (u64)nnz;
   s0.tail_round = -1;
+  s0.placed_lo = place_lo;
+  s0.flip = 0;
   // both slots: a step leaves as soon as either slot says "done", and slot 1 still holds the
   // previous call's last state
   w.host->st[0] = s0;
@@ -380,10 +391,13 @@ static ldd_status decompose_impl(Workspace& w, const ldd_csr* g, const int64_t* 
   c.qv[1] = (int*)w.qv1.p;
   c.qa[0] = (unsigned*)w.qa0.p;
   c.qa[1] = (unsigned*)w.qa1.p;
-  c.wake_ord = (const int*)w.wake_ord.p;
+  c.wake_ord = (int*)w.wake_ord.p;
   c.wake_off = (const int*)w.wake_off.p;
   c.next_ne = (const int*)w.next_ne.p;
   c.wake_q = wake_q;
+  c.prep_blocks = gp;
+  c.mat = (const unsigned*)w.mat.p;
+  c.qmax = (const int*)w.qmax.p;
   c.qcnt = (u64*)w.qcnt.p;
   c.lr_part = (u64*)w.lr_part.p;
   c.stamp = (unsigned*)w.stamp.p;

@@ -26,6 +26,9 @@ constexpr int FIX = 20;
 constexpr u64 INF = ~0ull;
 constexpr int WAVE = 64;
 constexpr int QCAP = 8192;  // integer parts of shifts bucketed in LDS by the preparation
+// per preparation block, at most this many vertices of its highest q-buckets are listed for the
+// first wake window (the buckets every block lists in full are placed before the rounds)
+constexpr int CAND = 256;
 
 // error bits raised by kernels (ctrl->err)
 enum : unsigned {
@@ -45,6 +48,7 @@ struct Ctrl {
   alignas(128) u64 hub;     // (degree << 32 | id) of the highest-degree vertex
   alignas(128) unsigned err;  // ERR_* bits
   unsigned wide;              // some shift has an integer part >= QCAP
+  alignas(128) unsigned place_lo;  // lowest q-bucket every preparation block listed in full
   alignas(128) u64 bar;     // grid barrier arrival counter (persistent engine)
   alignas(128) u64 cut_arcs;  // 2 per arc to H plus 1 per two-sided cut arc outside H
   alignas(128) u64 pieces;  // vertices that are their own centre

@@ -6,7 +6,9 @@
 namespace ldd {
 
 enum { DIR_TD = 1, DIR_BU = 2 };  // matches LDD_DIR_TOP_DOWN / LDD_DIR_BOTTOM_UP; 0 = auto
-enum { MODE_ROUNDS = 0, MODE_TAIL = 1, MODE_DONE = 2 };
+// MODE_PLACE: the step places the wake buckets [max(0, placed_lo - ABUF), placed_lo) that the
+// next round needs (the preparation placed only the first window), then the rounds go on
+enum { MODE_ROUNDS = 0, MODE_TAIL = 1, MODE_DONE = 2, MODE_PLACE = 3 };
 
 constexpr int RT = 1024;    // threads per block of the round kernels (16 waves)
 constexpr int ABUF = 4096;  // entries of a block's LDS append buffer
@@ -27,7 +29,9 @@ constexpr int ABUF = 4096;  // entries of a block's LDS append buffer
   X(td_rounds)                                                                              \
   X(bu_rounds)                                                                              \
   X(tail_iters)                                                                             \
-  X(tail_round)     /* first round the tail replaced (-1: none) */
+  X(tail_round)     /* first round the tail replaced (-1: none) */                        \
+  X(placed_lo)      /* wake buckets >= placed_lo are placed (q-layout) */                   \
+  X(flip)           /* step k reads queue (k - 1 + flip) & 1 and writes (k + flip) & 1 */
 
 struct RoundState {
 #define LDD_DECL(f) long long f;
@@ -82,10 +86,13 @@ struct RoundCtx {
   u64* P;           // labels
   int* qv[2];       // queues (double-buffered by step parity)
   unsigned* qa[2];  // arc prefix of each queue entry
-  const int* wake_ord;
+  int* wake_ord;
   const int* wake_off;  // wake_q: q-bucket offsets [D + 2]; else round offsets [R + 1]
   const int* next_ne;
   int wake_q;           // 1: wake_ord is sorted by integer part of the shift (see k_init)
+  int prep_blocks;      // wake_q: blocks of the preparation, whose per-bucket counts are
+  const unsigned* mat;  //   mat[q * prep_blocks + b] (exclusive over blocks) for q <= qmax[b]
+  const int* qmax;
   u64* qcnt;        // 3 counters, 16 u64 apart: step k appends to counter k % 3
   u64* lr_part;     // [2][G]: per-block minimum label written by a step (parity of k)
   unsigned* stamp;  // per vertex: last tail sweep that queued it
@@ -118,11 +125,11 @@ struct LaunchBlock {
 };
 
 __global__ void k_init(int n, long long nnz, const int* row_ptr, const long long* shift, u64* P, Ctrl* ctrl,
-                       unsigned* mat, int* qmax);
+                       unsigned* mat, int* qmax, u64* cand, unsigned* cand_cnt);
 __global__ void k_qbucket_scan(int Qn, int G, unsigned* mat, const int* qmax, unsigned* tot);
 __global__ void k_qscan(int D, const unsigned* tot, int* qoff, int* next_ne);
-__global__ void k_place(int n, int B, const int* row_ptr, const long long* shift, const Ctrl* ctrl, const unsigned* mat,
-                        const int* qmax, const int* qoff, int* wake_ord, u64* P);
+__global__ void k_place_window(int q_lo, int D, const unsigned* mat, const int* qmax, const int* qoff, const u64* cand,
+                               const unsigned* cand_cnt, int* wake_ord);
 __global__ void k_check_cols(int n, long long nnz, const int* col, Ctrl* ctrl);
 __global__ void k_wake_count(int n, int B, const int* row_ptr, const long long* shift, const Ctrl* ctrl, u64* P,
                              unsigned* hist, int R, int use_lds);

@@ -2,14 +2,17 @@
 //
 // Pipeline for one graph (Sec. 5 of the paper: shortest paths from a super source whose
 // arcs of length Delta - delta_u are added lazily, processed one integer distance at a time):
-//   k_init          labels := INF, Delta := max shift (Algorithm 1 step 2), CSR bounds checks
-//   k_wake_count    isolated vertices settle at once; others counted per wake round
-//                   w(u) = (Delta - shift_fix[u]) >> 20 (the round the delayed arc s->u fires)
-//   k_wake_scan     bucket offsets and "next non-empty bucket" links
-//   k_wake_scatter  counting sort of vertices by wake round
-//   k_rounds        all rounds in one persistent kernel with grid barriers (or the same
-//                   phases launched one kernel each): wake bucket r, expand F_{r-1} top-down
-//                   (push) or bottom-up (pull), append first-reached vertices to F_r
+//   k_init          labels := INF, Delta := max shift (Algorithm 1 step 2), CSR bounds checks,
+//                   per-block histogram of q = shift >> 20 and lists of the highest buckets
+//   k_qbucket_scan  per bucket, offsets of the blocks' counts
+//   k_qscan         bucket offsets and "next round that wakes anyone" links
+//   k_place_window  the first window of buckets into the wake order (the round steps place
+//                   lower buckets if the rounds reach them)
+//   (shifts spanning QCAP units or more: k_wake_count / k_wake_scan / k_wake_scatter, a
+//   counting sort by exact wake round w(u) = (Delta - shift_fix[u]) >> 20)
+//   rounds          one step per round (ldd_rounds.hip): wake the round's vertices, expand
+//                   F_{r-1} top-down (push) or bottom-up (pull), append first-reached vertices
+//                   to F_r; a label-correcting tail once few vertices are left
 //   k_finalize      centre = low B bits of the label (Algorithm 1 step 4)
 //   k_cut           edges whose endpoints have different centres (Def. 1.1)
 #include "ldd_device.h"
@@ -51,12 +54,29 @@ __device__ __forceinline__ u64 block_sum(u64 v, u64* red) {
 // Block b owns vertices [b n / G, (b+1) n / G); each wave takes 256 consecutive ones per
 // pass (four per lane at stride 64, coalesced).  mat[q * G + b] = count of block b in bucket
 // q for q <= qmax[b]; a q >= QCAP sets ctrl->wide and the sorted layout is not used.
+//
+// The first wake window.  Shifts are exponential, so the high buckets (the early rounds)
+// hold few vertices and the low ones nearly all.  Each block lists the vertices of its
+// highest buckets, as many whole buckets as fit in CAND entries, with their bucket:
+// cand[b * CAND + i] = (q << 32) | v, bucket floor t_b.  Every block has listed all of its
+// vertices in buckets >= place_lo = max_b t_b, so the preparation places exactly those
+// buckets from the lists, without another pass over the shifts; the rest are placed by a
+// round step only if the rounds get that far (isolated vertices are never placed: their label
+// stays INF and the output maps it to the vertex itself).
+constexpr int QL = 16384;  // vertices per block whose bucket is kept in LDS between the passes
+constexpr unsigned short Q_NONE = 0xFFFF;
+
 __global__ __launch_bounds__(1024) void k_init(int n, long long nnz, const int* __restrict__ row_ptr,
                                               const long long* __restrict__ shift, u64* __restrict__ P,
-                                              Ctrl* ctrl, unsigned* __restrict__ mat, int* __restrict__ qmax) {
+                                              Ctrl* ctrl, unsigned* __restrict__ mat, int* __restrict__ qmax,
+                                              u64* __restrict__ cand, unsigned* __restrict__ cand_cnt) {
   __shared__ unsigned h[QCAP];
+  __shared__ unsigned short ql[QL];
   __shared__ u64 red[4][16];
+  __shared__ int t_sh;
+  __shared__ unsigned c_n;
   for (int i = threadIdx.x; i < QCAP; i += blockDim.x) h[i] = 0;
+  if (threadIdx.x == 0) c_n = 0;
   __syncthreads();
   u64 mx = 0, active = 0, hub = 0, qm = 0;
   unsigned bad = 0, wide = 0;
@@ -79,15 +99,18 @@ __global__ __launch_bounds__(1024) void k_init(int n, long long nnz, const int* 
         const u64 key = ((u64)(unsigned)(b - a) << 32) | (u64)v;  // degree, then id
         hub = key > hub ? key : hub;
         P[v] = INF;
+        unsigned short qs = Q_NONE;
         if (b > a && s_ok) {
           const u64 q = (u64)s >> FIX;
           if (q < (u64)QCAP) {
             atomicAdd(&h[q], 1u);
             qm = (q + 1) > qm ? (q + 1) : qm;  // q + 1 so that 0 means "no vertex"
+            qs = (unsigned short)q;
           } else {
             wide = 1;
           }
         }
+        if (v - lo < QL) ql[v - lo] = qs;
       }
     }
   }
@@ -95,11 +118,54 @@ __global__ __launch_bounds__(1024) void k_init(int n, long long nnz, const int* 
   active = block_sum(active, red[1]);
   hub = block_max(hub, red[2]);
   qm = block_max(qm, red[3]);
+  // bucket floor t_b: the lowest bucket such that buckets t_b .. qm - 1 hold at most CAND
+  // vertices (wave 0 walks the histogram down from the top, 64 buckets at a time)
+  if (wid == 0) {
+    int t = 0;
+    unsigned acc = 0;
+    for (int top = (int)qm - 1; top >= 0; top -= WAVE) {
+      const int q = top - (int)lane;
+      const unsigned incl = acc + wave_incl_scan(q >= 0 ? h[q] : 0u);
+      const u64 over = __ballot(incl > (unsigned)CAND);
+      if (over) {  // wave-uniform
+        t = top - (int)__builtin_ctzll(over) + 1;
+        break;
+      }
+      acc = __shfl(incl, WAVE - 1, WAVE);
+    }
+    if (lane == 0) t_sh = t;
+  }
+  __syncthreads();
+  const int tb = t_sh;
+  u64* my_cand = cand + (size_t)blockIdx.x * CAND;
+  for (long long base = lo + 256ll * wid; base < hi; base += 256ll * nw) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const long long v = base + 64 * j + lane;
+      if (v < hi) {
+        unsigned q = Q_NONE;
+        if (v - lo < QL) {
+          q = ql[v - lo];
+        } else {  // blocks of more than QL vertices read the rest again
+          const long long s = shift[v];
+          if (row_ptr[v + 1] > row_ptr[v] && s >= 0 && (u64)s < ((u64)QCAP << FIX)) q = (unsigned)((u64)s >> FIX);
+        }
+        if (q != Q_NONE && (int)q >= tb) {
+          const unsigned idx = atomicAdd(&c_n, 1u);
+          if (idx < (unsigned)CAND) my_cand[idx] = ((u64)q << 32) | (u64)v;
+          else bad |= ERR_QUEUE;  // cannot happen: the buckets >= t_b hold at most CAND
+        }
+      }
+    }
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
     if (mx) atomic_max_u64(&ctrl->delta, mx);
     if (active) atomic_add_u64(&ctrl->n_active, active);
     atomic_max_u64(&ctrl->hub, hub);
     qmax[blockIdx.x] = (int)qm - 1;
+    cand_cnt[blockIdx.x] = c_n < (unsigned)CAND ? c_n : (unsigned)CAND;
+    if (qm) __hip_atomic_fetch_max(&ctrl->place_lo, (unsigned)tb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   if (bad) atomic_or_u32(&ctrl->err, bad);
   if (wide) atomic_or_u32(&ctrl->wide, 1u);
@@ -127,89 +193,80 @@ __global__ __launch_bounds__(256) void k_qbucket_scan(int Qn, int G, unsigned* _
 }
 
 // One block: bucket offsets qoff[0..D+1] and, per round r (R = D + 1 rounds), the next round
-// at or after r whose two q-buckets (D - r and D - r - 1) are not both empty.
+// at or after r whose two q-buckets (D - r and D - r - 1) are not both empty.  Thread t takes
+// a run of consecutive buckets (rounds); the runs' sums are combined by an exclusive prefix
+// scan, their first non-empty rounds by a suffix minimum (wave shuffles, then across waves).
 __global__ __launch_bounds__(1024) void k_qscan(int D, const unsigned* __restrict__ tot, int* __restrict__ qoff,
                                                 int* __restrict__ next_ne) {
-  __shared__ unsigned part[1024];
-  __shared__ int nxt[1024];
+  __shared__ unsigned w_sum[16];
+  __shared__ int w_first[16];
   const int Qn = D + 1, R = D + 1;
   const int t = threadIdx.x;
+  const unsigned lane = lane_id(), wid = t / WAVE;
   const int per = (Qn + 1023) / 1024;
-  const int lo = t * per, hi = min(Qn, lo + per);
+  const int lo = min(Qn, t * per), hi = min(Qn, lo + per);
   unsigned s = 0;
-  int first = R;  // smallest round in this thread's range (rounds r = lo..hi-1) that may wake someone
+  int first = R;  // smallest round of this run that may wake someone
   for (int i = lo; i < hi; ++i) s += tot[i];
-  for (int r = lo; r < hi; ++r) {
-    const bool ne = tot[D - r] > 0 || (r < D && tot[D - r - 1] > 0);
-    if (ne && first == R) first = r;
+  for (int r = hi - 1; r >= lo; --r)
+    if (tot[D - r] > 0 || (r < D && tot[D - r - 1] > 0)) first = r;
+  const unsigned incl = wave_incl_scan(s);
+  int suf = first;  // inclusive suffix minimum over the wave
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const int y = __shfl_down(suf, o, WAVE);
+    if (lane + (unsigned)o < (unsigned)WAVE) suf = y < suf ? y : suf;
   }
-  part[t] = s;
-  nxt[t] = first;
+  if (lane == WAVE - 1) w_sum[wid] = incl;
+  if (lane == 0) w_first[wid] = suf;
   __syncthreads();
-  if (t == 0) {
-    unsigned acc = 0;
-    for (int i = 0; i < 1024; ++i) {
-      const unsigned x = part[i];
-      part[i] = acc;
-      acc += x;
-    }
-    int nx = R;
-    for (int i = 1023; i >= 0; --i) {
-      if (nxt[i] != R) nx = nxt[i];
-      nxt[i] = nx;
-    }
+  unsigned before = 0, total = 0;
+  int after = R;
+  for (int w = 0; w < 16; ++w) {
+    if (w < (int)wid) before += w_sum[w];
+    if (w > (int)wid) after = w_first[w] < after ? w_first[w] : after;
+    total += w_sum[w];
   }
-  __syncthreads();
-  unsigned acc = part[t];
+  const int next_in_wave = __shfl_down(suf, 1, WAVE);
+  if (lane + 1 < (unsigned)WAVE) after = next_in_wave < after ? next_in_wave : after;
+  unsigned acc = before + incl - s;
   for (int i = lo; i < hi; ++i) {
     qoff[i] = (int)acc;
     acc += tot[i];
   }
-  int nx_after = (t + 1 < 1024) ? nxt[t + 1] : R;
+  int nx = after;
   for (int r = hi - 1; r >= lo; --r) {
-    const bool ne = tot[D - r] > 0 || (r < D && tot[D - r - 1] > 0);
-    if (ne) nx_after = r;
-    next_ne[r] = nx_after;
+    if (tot[D - r] > 0 || (r < D && tot[D - r - 1] > 0)) nx = r;
+    next_ne[r] = nx;
   }
-  if (t == 1023) {
-    qoff[Qn] = (int)acc;
+  if (t == 0) {
+    qoff[Qn] = (int)total;
     next_ne[R] = R;
   }
 }
 
-// Pass B: each vertex with arcs goes to qoff[q] + mat[q * G + b] + its rank in block b's
-// bucket; isolated vertices settle (their only offer is their own arc).  Same chunks as k_init.
-__global__ __launch_bounds__(1024) void k_place(int n, int B, const int* __restrict__ row_ptr,
-                                               const long long* __restrict__ shift, const Ctrl* __restrict__ ctrl,
-                                               const unsigned* __restrict__ mat, const int* __restrict__ qmax,
-                                               const int* __restrict__ qoff, int* __restrict__ wake_ord,
-                                               u64* __restrict__ P) {
+// Places the first wake window, buckets [q_lo, D], from the blocks' candidate lists.  A
+// vertex's slot is its bucket's offset, plus the counts of the same bucket in earlier
+// preparation blocks, plus its rank inside its own block (an LDS cursor per bucket).
+__global__ __launch_bounds__(256) void k_place_window(int q_lo, int D, const unsigned* __restrict__ mat,
+                                                      const int* __restrict__ qmax, const int* __restrict__ qoff,
+                                                      const u64* __restrict__ cand,
+                                                      const unsigned* __restrict__ cand_cnt,
+                                                      int* __restrict__ wake_ord) {
   __shared__ unsigned cur[QCAP];
   const unsigned G = gridDim.x;
-  const int qm = qmax[blockIdx.x];
-  for (int q = threadIdx.x; q <= qm; q += blockDim.x) cur[q] = (unsigned)qoff[q] + mat[(size_t)q * G + blockIdx.x];
+  const int qm = min(qmax[blockIdx.x], D);
+  for (int q = q_lo + (int)threadIdx.x; q <= qm; q += blockDim.x)
+    cur[q - q_lo] = (unsigned)qoff[q] + mat[(size_t)q * G + blockIdx.x];
   __syncthreads();
-  const u64 delta = ctrl->delta;
-  const unsigned lane = lane_id(), wid = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
-  const long long lo = (long long)n * blockIdx.x / gridDim.x, hi = (long long)n * (blockIdx.x + 1) / gridDim.x;
-  for (long long base = lo + 256ll * wid; base < hi; base += 256ll * nw) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const long long v = base + 64 * j + lane;
-      if (v < hi) {
-        const u64 s = (u64)shift[v];
-        if (row_ptr[v + 1] == row_ptr[v]) {
-          P[v] = ((delta - s) << B) | (u64)v;
-        } else {
-          wake_ord[atomicAdd(&cur[s >> FIX], 1u)] = (int)v;
-        }
-      }
-    }
+  const unsigned cnt = cand_cnt[blockIdx.x];
+  for (unsigned i = threadIdx.x; i < cnt; i += blockDim.x) {
+    const u64 e = cand[(size_t)blockIdx.x * CAND + i];
+    const int q = (int)(e >> 32);
+    if (q >= q_lo && q <= qm) wake_ord[atomicAdd(&cur[q - q_lo], 1u)] = (int)(unsigned)e;
   }
 }
 
-// Optional O(nnz) check that every column id is in range (the round kernels also guard
-// each access, so this only moves the error report before any traversal).
 __global__ __launch_bounds__(256) void k_check_cols(int n, long long nnz, const int* __restrict__ col, Ctrl* ctrl) {
   unsigned bad = 0;
   const long long stride = (long long)gridDim.x * blockDim.x;
@@ -347,7 +404,9 @@ __global__ __launch_bounds__(FT) void k_finalize(int n, int B, const int* __rest
   __shared__ u64 red[2][FT / WAVE];
   const u64 mask = ((u64)1 << B) - 1;
   const int hub = (int)(unsigned)ctrl->hub;
-  const int hub_c = (hub >= 0 && hub < n) ? (int)(P[hub] & mask) : -1;
+  // a label still INF belongs to an isolated vertex (never placed, never reached): its own centre
+  const u64 p_hub = (hub >= 0 && hub < n) ? P[hub] : INF;
+  const int hub_c = (hub >= 0 && hub < n) ? (p_hub == INF ? hub : (int)(p_hub & mask)) : -1;
   if (threadIdx.x == 0) {
     b_n = 0;
     b_arcs = 0;
@@ -369,12 +428,12 @@ __global__ __launch_bounds__(FT) void k_finalize(int n, int B, const int* __rest
       deg[j] = 0;
       if (v < hi) {
         const u64 p = P[v];
-        const int cv = (int)(p & mask);
+        const int cv = p == INF ? (int)v : (int)(p & mask);
         centre[v] = cv;
         pieces += (cv == (int)v);
-        unreached += (p == INF);
-        in_hub = cv == hub_c;
         deg[j] = (unsigned)(row_ptr[v + 1] - row_ptr[v]);
+        unreached += (p == INF && deg[j] > 0);
+        in_hub = cv == hub_c;
         want[j] = !in_hub && deg[j] > 0;
       }
       const u64 bits = __ballot(in_hub);

@@ -34,6 +34,7 @@ struct AppendBuf {
   unsigned n;
   unsigned arcs;
   u64 base;
+  int wpar;  // queue buffer the step writes
 };
 
 struct StepShared {
@@ -58,8 +59,8 @@ __device__ __forceinline__ void block_flush(AppendBuf& ab, const RoundCtx& c, in
   __syncthreads();
   const u64 base = ab.base;
   const unsigned b_cnt = (unsigned)(base >> 32), b_arcs = (unsigned)base;
-  int* qv = c.qv[k & 1];
-  unsigned* qa = c.qa[k & 1];
+  int* qv = c.qv[ab.wpar];
+  unsigned* qa = c.qa[ab.wpar];
   for (unsigned i = threadIdx.x; i < cnt; i += RT) {
     const unsigned idx = b_cnt + i;
     if (idx < (unsigned)c.n) {
@@ -411,12 +412,57 @@ __device__ void store_state(RoundState* p, const RoundState& s) {
 #undef LDD_STORE
 }
 
+// Round r wakes buckets D - r and D - r - 1 (bucket 0 alone when r = D).
+__device__ __forceinline__ bool needs_place(const RoundCtx& c, int r, long long placed_lo) {
+  const long long D = (long long)(c.delta >> FIX);
+  const long long need = D - r - 1 > 0 ? D - r - 1 : 0;
+  return c.wake_q && need < placed_lo;
+}
+
+// ---- placement: wake buckets [max(0, placed_lo - ABUF), placed_lo) ------------------------
+// Same slots as the preparation would have given them: per preparation block pb, a cursor per
+// bucket starts at the bucket's offset plus the counts of earlier blocks (mat); the block's
+// vertices of those buckets are scattered through the cursors (kept in the append buffer's LDS).
+__device__ __forceinline__ void phase_place(const RoundCtx& c, long long placed_lo, AppendBuf& ab) {
+  const int hi_q = (int)placed_lo, lo_q = hi_q > ABUF ? hi_q - ABUF : 0;
+  const int G = c.prep_blocks;
+  int* cur = ab.vert;
+  const unsigned lane = lane_id(), wid = threadIdx.x / WAVE;
+  for (int pb = blockIdx.x; pb < G; pb += gridDim.x) {
+    __syncthreads();
+    const int qm = min(c.qmax[pb], hi_q - 1);
+    for (int q = lo_q + (int)threadIdx.x; q <= qm; q += RT)
+      cur[q - lo_q] = c.wake_off[q] + (int)c.mat[(size_t)q * G + pb];
+    __syncthreads();
+    const long long lo = (long long)c.n * pb / G, hi = (long long)c.n * (pb + 1) / G;
+    for (long long base = lo + 256ll * wid; base < hi; base += 256ll * NW) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const long long v = base + 64 * j + lane;
+        if (v < hi) {
+          const long long q = (long long)((u64)c.shift[v] >> FIX);
+          if (q >= lo_q && q <= qm && c.row_ptr[v + 1] > c.row_ptr[v])
+            c.wake_ord[atomicAdd(&cur[q - lo_q], 1)] = (int)v;
+        }
+      }
+    }
+  }
+}
+
 __device__ __forceinline__ RoundState next_state(const RoundCtx& c, int k) {
   const RoundState P = load_state(&c.st[(k - 1) & 1]);
   const u64 out = load_u64_relaxed(qcounter(c, k - 1));
   RoundState S = P;
   S.seq = k;
   if (P.mode == MODE_DONE) return S;
+  if (P.mode == MODE_PLACE) {
+    // step k-1 placed buckets [lo, placed_lo) and queued nothing: round P.round runs now, on
+    // the queue step k-2 wrote (hence the parity flip), unless it needs still lower buckets
+    S.placed_lo = P.placed_lo > ABUF ? P.placed_lo - ABUF : 0;
+    S.flip = P.flip ^ 1;
+    S.mode = needs_place(c, (int)S.round, S.placed_lo) ? MODE_PLACE : MODE_ROUNDS;
+    return S;
+  }
   const unsigned nf = min((unsigned)(out >> 32), (unsigned)c.n), af = (unsigned)out;
   if (P.mode == MODE_ROUNDS) {
     int next_r;
@@ -447,6 +493,7 @@ __device__ __forceinline__ RoundState next_state(const RoundCtx& c, int k) {
     } else {
       S.round = next_r;
       S.dir = nf ? choose_dir(c, (int)P.dir, nf, af, (u64)S.unsettled_arcs) : P.dir;
+      if (needs_place(c, next_r, S.placed_lo)) S.mode = MODE_PLACE;
     }
   } else {  // MODE_TAIL: step k-1 ran sweep P.round and queued `out`
     S.tail_iters += 1;
@@ -487,37 +534,48 @@ __device__ __forceinline__ int round_step(const RoundCtx& c, int k, AppendBuf& a
     ab.arcs = 0;
   }
   __syncthreads();
-  const RoundState S = sh.S;
-  if (S.seq < 0) return MODE_DONE;
+  // the fields the step uses, as wave-uniform scalars (the rest of the state stays in LDS)
+  const int mode = __builtin_amdgcn_readfirstlane((int)sh.S.mode);
+  if (__builtin_amdgcn_readfirstlane((int)(sh.S.seq < 0))) return MODE_DONE;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    store_state<__HIP_MEMORY_SCOPE_AGENT>(&c.st[k & 1], S);
+    store_state<__HIP_MEMORY_SCOPE_AGENT>(&c.st[k & 1], sh.S);
     __hip_atomic_store(qcounter(c, k + 1), 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     // the host stops enqueueing steps once it reads "done"; written once per decomposition,
     // since a store to host memory delays the completion of the kernel that makes it
-    if (c.host_st && S.mode == MODE_DONE) store_state<__HIP_MEMORY_SCOPE_SYSTEM>(c.host_st, S);
+    if (c.host_st && mode == MODE_DONE) store_state<__HIP_MEMORY_SCOPE_SYSTEM>(c.host_st, sh.S);
   }
-  if (S.mode == MODE_DONE) return MODE_DONE;
-  const unsigned nf = min((unsigned)((u64)S.prev >> 32), (unsigned)c.n), af = (unsigned)S.prev;
-  const int* qv = c.qv[(k - 1) & 1];
-  const unsigned* qa = c.qa[(k - 1) & 1];
+  if (mode == MODE_DONE) return MODE_DONE;
+  if (mode == MODE_PLACE) {
+    phase_place(c, sh.S.placed_lo, ab);
+    return MODE_PLACE;
+  }
+  const int round = __builtin_amdgcn_readfirstlane((int)sh.S.round);
+  const int dir = __builtin_amdgcn_readfirstlane((int)sh.S.dir);
+  const int rpar = (int)((k - 1 + __builtin_amdgcn_readfirstlane((int)sh.S.flip)) & 1), wpar = rpar ^ 1;
+  const u64 prev = (u64)sh.S.prev;
+  if (threadIdx.x == 0) ab.wpar = wpar;
+  const unsigned nf = __builtin_amdgcn_readfirstlane(min((unsigned)(prev >> 32), (unsigned)c.n));
+  const unsigned af = __builtin_amdgcn_readfirstlane((unsigned)prev);
+  const int* qv = c.qv[rpar];
+  const unsigned* qa = c.qa[rpar];
   u64 wmin = INF, examined = 0;
-  const bool need_lr = nf && ((S.mode == MODE_ROUNDS && S.dir == DIR_BU) || (S.mode == MODE_TAIL && S.round == 0));
+  const bool need_lr = nf && ((mode == MODE_ROUNDS && dir == DIR_BU) || (mode == MODE_TAIL && round == 0));
   if (need_lr) {
     // L_r: the smallest offer of F_{r-1}, from the per-block minima the previous step left
     u64 m = INF;
     for (unsigned b = threadIdx.x; b < gridDim.x; b += RT) {
-      const u64 x = load_u64_relaxed(&c.lr_part[(size_t)((k - 1) & 1) * gridDim.x + b]);
+      const u64 x = load_u64_relaxed(&c.lr_part[(size_t)rpar * gridDim.x + b]);
       m = x < m ? x : m;
     }
     m = block_min_u64(m, sh);
     if (threadIdx.x == 0) sh.lr = m == INF ? INF : m + ((u64)1 << (FIX + c.B));
     __syncthreads();
   }
-  if (S.mode == MODE_ROUNDS) {
-    const int r = (int)S.round;
+  if (mode == MODE_ROUNDS) {
+    const int r = round;
     phase_wake(c, r, k, ab, wmin);
     if (nf) {
-      if (S.dir == DIR_BU) {
+      if (dir == DIR_BU) {
         phase_bottom_up(c, r, k, sh.lr, ab, wmin, examined);
       } else {
         phase_top_down<false>(c, k, qv, qa, nf, af, ab, sh, wmin, 0);
@@ -525,9 +583,9 @@ __device__ __forceinline__ int round_step(const RoundCtx& c, int k, AppendBuf& a
       }
     }
   } else {
-    const unsigned sweep = (unsigned)S.round;
+    const unsigned sweep = (unsigned)round;
     if (sweep == 0) {
-      phase_tail_seed(c, (int)S.tail_round, k, nf ? sh.lr : INF, ab, examined);
+      phase_tail_seed(c, __builtin_amdgcn_readfirstlane((int)sh.S.tail_round), k, nf ? sh.lr : INF, ab, examined);
     } else if (nf) {
       phase_top_down<true>(c, k, qv, qa, nf, af, ab, sh, wmin, sweep);
       if (blockIdx.x == 0 && threadIdx.x == 0) examined += af;
@@ -535,9 +593,9 @@ __device__ __forceinline__ int round_step(const RoundCtx& c, int k, AppendBuf& a
   }
   block_flush(ab, c, k);
   const u64 bm = block_min_u64(wmin, sh);
-  if (threadIdx.x == 0) c.lr_part[(size_t)(k & 1) * gridDim.x + blockIdx.x] = bm;
+  if (threadIdx.x == 0) c.lr_part[(size_t)wpar * gridDim.x + blockIdx.x] = bm;
   add_examined(c, examined, sh);
-  return (int)S.mode;
+  return mode;
 }
 
 // (RT, 8): eight waves per SIMD, i.e. two 1024-thread blocks per CU, which caps VGPRs at 64

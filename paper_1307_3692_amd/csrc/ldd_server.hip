@@ -739,7 +739,7 @@ ldd_status srv_setup(ldd_server* srv) {
   c.qv[1] = (int*)srv->qv1;
   c.qa[0] = (unsigned*)srv->qa0;
   c.qa[1] = (unsigned*)srv->qa1;
-  c.wake_ord = (const int*)srv->wake_ord;
+  c.wake_ord = (int*)srv->wake_ord;
   c.wake_off = nullptr;
   c.next_ne = nullptr;
   c.wake_q = 0;
