@@ -277,9 +277,15 @@ extern "C" ldd_status ldd_decompose(const ldd_csr* g, const int64_t* shift_fix, 
   return decompose_impl(w, g, shift_fix, centre, cut_edges, o, stats, st, nullptr);
 }
 
-static ldd_status decompose_impl(Workspace& w, const ldd_csr* g, const int64_t* shift_fix, int32_t* centre,
-                                 int64_t* cut_edges, const ldd_options& o, ldd_stats* stats, hipStream_t st,
-                                 const BatchView* bv) {
+static const ldd_status REDO_WIDE = static_cast<ldd_status>(100);  // internal: run again on the wide layout
+
+// One decomposition.  wide = false: the sorted (q-bucket) layout, enqueued in full without the
+// host waiting (k_setup decides on the device whether the rounds run); if the shifts turn out to
+// span QCAP units or more, the run reports REDO_WIDE and is redone with wide = true, whose
+// preparation reads Delta on the host to size its per-round arrays.
+static ldd_status decompose_run(Workspace& w, const ldd_csr* g, const int64_t* shift_fix, int32_t* centre,
+                                int64_t* cut_edges, const ldd_options& o, ldd_stats* stats, hipStream_t st,
+                                const BatchView* bv, bool wide) {
   const int n = g->n;
   const long long nnz = g->nnz;
   ldd_status s = ws_setup(w);
@@ -291,6 +297,7 @@ static ldd_status decompose_impl(Workspace& w, const ldd_csr* g, const int64_t* 
     return s;
   Ctrl* ctrl = (Ctrl*)w.ctrl.p;
   u64* P = (u64*)w.P.p;
+  const int B = ceil_log2(n) < 1 ? 1 : ceil_log2(n);
 
   HIP_TRY(hipEventRecord(w.ev[0], st));
   const int g_n = grid_for(n, 256 * 4, 2048);
@@ -305,48 +312,45 @@ static ldd_status decompose_impl(Workspace& w, const ldd_csr* g, const int64_t* 
   if (o.validate && nnz > 0)
     hipLaunchKernelGGL(k_check_cols, dim3(grid_for(nnz, 256, 4096)), dim3(256), 0, st, n, nnz, g->col_idx, ctrl);
   HIP_TRY(hipGetLastError());
-  HIP_TRY(hipMemcpyAsync(&w.host->ctrl, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  {
-    ldd_status e = finish_error(w.host->ctrl.err);
-    if (e != LDD_OK) return e;
-  }
-  const u64 delta = w.host->ctrl.delta;
-  const u64 n_active = w.host->ctrl.n_active;
-  const int B = ceil_log2(n) < 1 ? 1 : ceil_log2(n);
-  // largest label: ((delta + 2^20) << B) | (n - 1) must stay below INF
-  if ((delta + (1ull << FIX)) >= (1ull << (64 - B))) {
-    ldd_set_error("labels need (Delta + 2^20) << %d < 2^64 (Delta = %llu)", B, (unsigned long long)delta);
-    return LDD_ERR_OVERFLOW;
-  }
-  const long long R = (long long)(delta >> FIX) + 1;
-  if (R > (1ll << 28)) {
-    ldd_set_error("shift range needs %lld rounds", R);
-    return LDD_ERR_OVERFLOW;
-  }
-  const size_t nr = (size_t)R + 2;
-  if ((s = grow(w.hist, nr * 4)) || (s = grow(w.cursor, nr * 4)) || (s = grow(w.wake_off, nr * 4)) ||
-      (s = grow(w.next_ne, nr * 4)))
-    return s;
 
-  const long long D = (long long)(delta >> FIX);
-  int wake_q = 0;
-  long long place_lo = 0;
-  if (!w.host->ctrl.wide && D < QCAP) {
+  long long R_bound;  // rounds bound for the host's step limit
+  if (!wide) {
     // pass B: vertices sorted by the integer part of their shift, no global atomics; only the
     // first window of buckets is placed now (the round steps place the rest when needed)
-    wake_q = 1;
-    place_lo = std::min<long long>(w.host->ctrl.place_lo, D + 1);
-    hipLaunchKernelGGL(k_qbucket_scan, dim3((unsigned)(((D + 1) * WAVE + 255) / 256)), dim3(256), 0, st, (int)(D + 1),
-                       gp, (unsigned*)w.mat.p, (const int*)w.qmax.p, (unsigned*)w.hist.p);
-    hipLaunchKernelGGL(k_qscan, dim3(1), dim3(1024), 0, st, (int)D, (const unsigned*)w.hist.p, (int*)w.wake_off.p,
-                       (int*)w.next_ne.p);
-    if (place_lo <= D)
-      hipLaunchKernelGGL(k_place_window, dim3(gp), dim3(256), 0, st, (int)place_lo, (int)D, (const unsigned*)w.mat.p,
-                         (const int*)w.qmax.p, (const int*)w.wake_off.p, (const u64*)w.cand.p,
-                         (const unsigned*)w.cand_cnt.p, (int*)w.wake_ord.p);
+    const size_t nq = (size_t)QCAP + 2;
+    if ((s = grow(w.hist, nq * 4)) || (s = grow(w.wake_off, nq * 4)) || (s = grow(w.next_ne, nq * 4))) return s;
+    R_bound = QCAP;
+    hipLaunchKernelGGL(k_qbucket_scan, dim3(std::min(QCAP, 1024)), dim3(256), 0, st, gp, (unsigned*)w.mat.p,
+                       (const int*)w.qmax.p, (unsigned*)w.hist.p, (const Ctrl*)ctrl);
+    hipLaunchKernelGGL(k_qscan, dim3(1), dim3(1024), 0, st, (const Ctrl*)ctrl, (const unsigned*)w.hist.p,
+                       (int*)w.wake_off.p, (int*)w.next_ne.p);
+    hipLaunchKernelGGL(k_place_window, dim3(gp), dim3(256), 0, st, (const Ctrl*)ctrl, (const unsigned*)w.mat.p,
+                       (const int*)w.qmax.p, (const int*)w.wake_off.p, (const u64*)w.cand.p,
+                       (const unsigned*)w.cand_cnt.p, (int*)w.wake_ord.p);
   } else {
-    // shifts spanning more than QCAP units: exact wake rounds via global atomics
+    // shifts spanning QCAP units or more: exact wake rounds via global atomics, arrays sized
+    // by the rounds bound the host reads first
+    HIP_TRY(hipMemcpyAsync(&w.host->ctrl, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    {
+      ldd_status e = finish_error(w.host->ctrl.err);
+      if (e != LDD_OK) return e;
+    }
+    const u64 delta = w.host->ctrl.delta;
+    if ((delta + (1ull << FIX)) >= (1ull << (64 - B))) {
+      ldd_set_error("labels need (Delta + 2^20) << %d < 2^64 (Delta = %llu)", B, (unsigned long long)delta);
+      return LDD_ERR_OVERFLOW;
+    }
+    const long long R = (long long)(delta >> FIX) + 1;
+    if (R > (1ll << 28)) {
+      ldd_set_error("shift range needs %lld rounds", R);
+      return LDD_ERR_OVERFLOW;
+    }
+    R_bound = R;
+    const size_t nr = (size_t)R + 2;
+    if ((s = grow(w.hist, nr * 4)) || (s = grow(w.cursor, nr * 4)) || (s = grow(w.wake_off, nr * 4)) ||
+        (s = grow(w.next_ne, nr * 4)))
+      return s;
     HIP_TRY(hipMemsetAsync(w.hist.p, 0, nr * 4, st));
     hipLaunchKernelGGL(k_wake_count, dim3(g_n), dim3(256), 0, st, n, B, g->row_ptr, (const long long*)shift_fix,
                        (const Ctrl*)ctrl, P, (unsigned*)w.hist.p, (int)R, 0);
@@ -360,29 +364,13 @@ static ldd_status decompose_impl(Workspace& w, const ldd_csr* g, const int64_t* 
   const int tail_den = o.tail_vertices < 0 ? 0 : (o.tail_vertices > 0 ? o.tail_vertices : 64);
   if (tail_den) HIP_TRY(hipMemsetAsync(w.stamp.p, 0, nv * 4, st));
   HIP_TRY(hipMemsetAsync(w.qcnt.p, 0, 3 * 16 * sizeof(u64), st));
-  RoundState s0{};
-  s0.seq = 0;
-  s0.mode = MODE_ROUNDS;
-  s0.round = -1;
-  s0.dir = DIR_TD;
-  s0.unsettled_arcs = (u64)nnz;
-  s0.tail_round = -1;
-  s0.placed_lo = place_lo;
-  s0.flip = 0;
-  // both slots: a step leaves as soon as either slot says "done", and slot 1 still holds the
-  // previous call's last state
-  w.host->st[0] = s0;
-  w.host->st[1] = s0;
-  w.host->st[1].seq = -1;
-  HIP_TRY(hipMemcpyAsync(w.st.p, &w.host->st[0], 2 * sizeof(RoundState), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemsetAsync(w.ex_part.p, 0, (size_t)RT * sizeof(u64), st));
 
+  // round arguments; Delta, the rounds bound and the vertices with arcs are filled in by k_setup
   RoundCtx c{};
   c.n = n;
   c.B = B;
-  c.R = (int)R;
   c.nnz = nnz;
-  c.delta = delta;
-  c.n_active = n_active;
   c.row_ptr = g->row_ptr;
   c.col = g->col_idx;
   c.shift = (const long long*)shift_fix;
@@ -394,7 +382,7 @@ static ldd_status decompose_impl(Workspace& w, const ldd_csr* g, const int64_t* 
   c.wake_ord = (int*)w.wake_ord.p;
   c.wake_off = (const int*)w.wake_off.p;
   c.next_ne = (const int*)w.next_ne.p;
-  c.wake_q = wake_q;
+  c.wake_q = wide ? 0 : 1;
   c.prep_blocks = gp;
   c.mat = (const unsigned*)w.mat.p;
   c.qmax = (const int*)w.qmax.p;
@@ -410,73 +398,64 @@ static ldd_status decompose_impl(Workspace& w, const ldd_csr* g, const int64_t* 
   c.tail_min_left = 16;
   c.host_st = nullptr;
   c.ex_part = (u64*)w.ex_part.p;
-  c.slots = nullptr;
-  c.nslots = 0;
-  c.wake_tab = nullptr;
-  c.sst = nullptr;
-  c.s_cnt = nullptr;
-  c.s_lr = nullptr;
-  c.s_end = nullptr;
-  c.slot_err = nullptr;
-  HIP_TRY(hipMemsetAsync(w.ex_part.p, 0, (size_t)RT * sizeof(u64), st));
 
   const int engine = o.engine == LDD_ENGINE_AUTO ? LDD_ENGINE_LAUNCH : o.engine;
   int blocks = o.blocks > 0 ? o.blocks : 2 * w.num_cu;
   if (blocks > RT) blocks = RT;  // the per-block minima of a step are reduced by one block
   if (engine == LDD_ENGINE_PERSISTENT && blocks > w.max_coresident) blocks = w.max_coresident;
-  const long long kmax = R + (long long)n + 2;
+  // rounds, placement steps, tail sweeps (each settles or lowers at least one label) and slack
+  const long long kmax = R_bound + R_bound / ABUF + 1 + (long long)n + 2;
   long long steps = 0;
-  HIP_TRY(hipEventRecord(w.ev[1], st));
-  if (n_active > 0) {
-    if (engine == LDD_ENGINE_PERSISTENT) {
-      void* args[] = {&c};
-      HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_rounds_persistent), dim3(blocks), dim3(RT),
-                                         args, 0, st));
-      HIP_TRY(hipMemcpyAsync(w.host->st, w.st.p, 2 * sizeof(RoundState), hipMemcpyDeviceToHost, st));
-      HIP_TRY(hipStreamSynchronize(st));
-      steps = 1;
-    } else {
-      // Steps run as replays of a captured chunk graph.  Two chunks are kept in flight: the
-      // host waits for the older one, reads the state the steps publish to mapped host memory,
-      // and enqueues another chunk only if the decomposition is not done yet.
-      hipGraphExec_t exec = nullptr;
-      if ((s = step_graph(w, blocks, &exec))) return s;
-      void* host_st_dev = nullptr;
-      HIP_TRY(hipHostGetDevicePointer(&host_st_dev, &w.host->live, 0));
-      c.host_st = (RoundState*)host_st_dev;
-      w.host->lb.c = c;
-      w.host->lb.kbase = 1;
-      volatile RoundState* live = &w.host->live;
-      live->mode = MODE_ROUNDS;
-      live->seq = 0;
-      HIP_TRY(hipMemcpyAsync(w.lb.p, &w.host->lb, sizeof(LaunchBlock), hipMemcpyHostToDevice, st));
-      long long submitted = 0;
-      int inflight = 0, oldest = 0;
-      for (int i = 0; i < 2; ++i) {
-        HIP_TRY(hipGraphLaunch(exec, st));
-        HIP_TRY(hipEventRecord(w.chunk_ev[i], st));
-        submitted += CHUNK;
-        ++inflight;
-      }
-      for (;;) {
-        HIP_TRY(hipEventSynchronize(w.chunk_ev[oldest]));
-        --inflight;
-        if (live->mode == MODE_DONE) break;
-        if (submitted > kmax) {
-          HIP_TRY(hipStreamSynchronize(st));
-          ldd_set_error("round steps exceeded their bound (%lld)", kmax);
-          return LDD_ERR_INTERNAL;
-        }
-        HIP_TRY(hipGraphLaunch(exec, st));
-        HIP_TRY(hipEventRecord(w.chunk_ev[oldest], st));
-        submitted += CHUNK;
-        ++inflight;
-        oldest ^= 1;
-      }
-      steps = submitted;
-      HIP_TRY(hipMemcpyAsync(w.host->st, w.st.p, 2 * sizeof(RoundState), hipMemcpyDeviceToHost, st));
-    }
+  volatile RoundState* live = &w.host->live;
+  void* host_st_dev = nullptr;
+  hipGraphExec_t exec = nullptr;
+  if (engine != LDD_ENGINE_PERSISTENT) {
+    if ((s = step_graph(w, blocks, &exec))) return s;
+    HIP_TRY(hipHostGetDevicePointer(&host_st_dev, &w.host->live, 0));
+    c.host_st = (RoundState*)host_st_dev;
+    live->mode = MODE_ROUNDS;
+    live->seq = 0;
   }
+  w.host->lb.c = c;
+  w.host->lb.kbase = 1;
+  HIP_TRY(hipMemcpyAsync(w.lb.p, &w.host->lb, sizeof(LaunchBlock), hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_setup, dim3(1), dim3(64), 0, st, ctrl, (RoundState*)w.st.p, (LaunchBlock*)w.lb.p,
+                     (RoundState*)host_st_dev, nnz, B, wide ? 0 : 1);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipEventRecord(w.ev[1], st));
+  if (engine == LDD_ENGINE_PERSISTENT) {
+    const LaunchBlock* lbp = (const LaunchBlock*)w.lb.p;
+    void* args[] = {&lbp};
+    HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_rounds_persistent), dim3(blocks), dim3(RT), args,
+                                       0, st));
+    steps = 1;
+  } else {
+    // Steps run as replays of a captured chunk graph.  Two chunks are kept in flight: the host
+    // waits for the older one, reads the state the steps publish to mapped host memory, and
+    // enqueues another chunk only if the decomposition is not done yet.
+    long long submitted = 0;
+    int oldest = 0;
+    for (int i = 0; i < 2; ++i) {
+      HIP_TRY(hipGraphLaunch(exec, st));
+      HIP_TRY(hipEventRecord(w.chunk_ev[i], st));
+      submitted += CHUNK;
+    }
+    for (;;) {
+      HIP_TRY(hipEventSynchronize(w.chunk_ev[oldest]));
+      if (live->mode == MODE_DONE) break;
+      if (submitted > kmax) {
+        HIP_TRY(hipStreamSynchronize(st));
+        ldd_set_error("round steps exceeded their bound (%lld)", kmax);
+        return LDD_ERR_INTERNAL;
+      }
+      HIP_TRY(hipGraphLaunch(exec, st));
+      HIP_TRY(hipEventRecord(w.chunk_ev[oldest], st));
+      submitted += CHUNK;
+      oldest ^= 1;
+    }
+    steps = submitted;
+  }
+  HIP_TRY(hipMemcpyAsync(w.host->st, w.st.p, 2 * sizeof(RoundState), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipEventRecord(w.ev[2], st));
   const int g_f = grid_for((n + 63) / 64, 256, 1024);  // whole bitmap words per block
   hipLaunchKernelGGL(k_finalize, dim3(g_f), dim3(1024), 0, st, n, B, g->row_ptr, (const u64*)P, centre,
@@ -492,10 +471,27 @@ static ldd_status decompose_impl(Workspace& w, const ldd_csr* g, const int64_t* 
   if (stats) HIP_TRY(hipMemcpyAsync(w.host->ex_part, w.ex_part.p, (size_t)blocks * sizeof(u64), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   const Ctrl& h = w.host->ctrl;
+  switch (h.setup) {
+    case SETUP_OK:
+    case SETUP_EMPTY:
+      break;
+    case SETUP_WIDE:
+      return REDO_WIDE;
+    case SETUP_OVERFLOW:
+      ldd_set_error("labels need (Delta + 2^20) << %d < 2^64 and at most 2^28 rounds (Delta = %llu)", B,
+                    (unsigned long long)h.delta);
+      return LDD_ERR_OVERFLOW;
+    default: {
+      ldd_status e = finish_error(h.err);
+      return e != LDD_OK ? e : LDD_ERR_INTERNAL;
+    }
+  }
   {
     ldd_status e = finish_error(h.err);
     if (e != LDD_OK) return e;
   }
+  const u64 delta = h.delta, n_active = h.n_active;
+  const long long R = (long long)(delta >> FIX) + 1;
   const RoundState& fs = w.host->st[0].seq > w.host->st[1].seq ? w.host->st[0] : w.host->st[1];
   if (h.unreached != 0 || (n_active > 0 && fs.mode != MODE_DONE)) {
     ldd_set_error("rounds ended with %llu labels unset (mode %lld)", (unsigned long long)h.unreached, fs.mode);
@@ -529,6 +525,14 @@ static ldd_status decompose_impl(Workspace& w, const ldd_csr* g, const int64_t* 
     stats->ms_cut = ms;
   }
   return LDD_OK;
+}
+
+static ldd_status decompose_impl(Workspace& w, const ldd_csr* g, const int64_t* shift_fix, int32_t* centre,
+                                 int64_t* cut_edges, const ldd_options& o, ldd_stats* stats, hipStream_t st,
+                                 const BatchView* bv) {
+  ldd_status s = decompose_run(w, g, shift_fix, centre, cut_edges, o, stats, st, bv, false);
+  if (s == REDO_WIDE) s = decompose_run(w, g, shift_fix, centre, cut_edges, o, stats, st, bv, true);
+  return s;
 }
 
 // ------------------------------------------------------------------------------------------

@@ -40,6 +40,16 @@ enum : unsigned {
   ERR_QUEUE = 32u         // queue overflow (more appends than vertices)
 };
 
+// Outcome of the preparation, decided on the device so that the host enqueues the whole
+// decomposition without waiting for it.
+enum : unsigned {
+  SETUP_OK = 0,        // rounds run
+  SETUP_EMPTY = 1,     // no vertex has an arc: every vertex is its own centre
+  SETUP_INVALID = 2,   // bad row_ptr, shift or column id (ctrl->err says which)
+  SETUP_OVERFLOW = 3,  // labels would not fit 64 bits, or too many rounds
+  SETUP_WIDE = 4       // shifts span QCAP units or more: the host redoes the call on the wide path
+};
+
 // Control block in device memory, one per decomposition in flight.  Counters that many
 // blocks update get a 128-byte line each: atomics to one line serialise (~12 ns apiece).
 struct Ctrl {
@@ -49,6 +59,7 @@ struct Ctrl {
   alignas(128) unsigned err;  // ERR_* bits
   unsigned wide;              // some shift has an integer part >= QCAP
   alignas(128) unsigned place_lo;  // lowest q-bucket every preparation block listed in full
+  unsigned setup;                  // SETUP_*: what k_setup found (the rounds run only on SETUP_OK)
   alignas(128) u64 bar;     // grid barrier arrival counter (persistent engine)
   alignas(128) u64 cut_arcs;  // 2 per arc to H plus 1 per two-sided cut arc outside H
   alignas(128) u64 pieces;  // vertices that are their own centre

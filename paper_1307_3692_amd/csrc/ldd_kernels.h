@@ -126,9 +126,9 @@ struct LaunchBlock {
 
 __global__ void k_init(int n, long long nnz, const int* row_ptr, const long long* shift, u64* P, Ctrl* ctrl,
                        unsigned* mat, int* qmax, u64* cand, unsigned* cand_cnt);
-__global__ void k_qbucket_scan(int Qn, int G, unsigned* mat, const int* qmax, unsigned* tot);
-__global__ void k_qscan(int D, const unsigned* tot, int* qoff, int* next_ne);
-__global__ void k_place_window(int q_lo, int D, const unsigned* mat, const int* qmax, const int* qoff, const u64* cand,
+__global__ void k_qbucket_scan(int G, unsigned* mat, const int* qmax, unsigned* tot, const Ctrl* ctrl);
+__global__ void k_qscan(const Ctrl* ctrl, const unsigned* tot, int* qoff, int* next_ne);
+__global__ void k_place_window(const Ctrl* ctrl, const unsigned* mat, const int* qmax, const int* qoff, const u64* cand,
                                const unsigned* cand_cnt, int* wake_ord);
 __global__ void k_check_cols(int n, long long nnz, const int* col, Ctrl* ctrl);
 __global__ void k_wake_count(int n, int B, const int* row_ptr, const long long* shift, const Ctrl* ctrl, u64* P,
@@ -140,7 +140,8 @@ __global__ void k_fill_u64(u64* p, long long count, u64 value);
 __global__ void k_round_step_lb(const LaunchBlock* lb, int j);
 __global__ void k_round_step_srv(const LaunchBlock* lb, int j);
 __global__ void k_advance(LaunchBlock* lb, int C);
-__global__ void k_rounds_persistent(RoundCtx c);
+__global__ void k_rounds_persistent(const LaunchBlock* lb);
+__global__ void k_setup(Ctrl* ctrl, RoundState* st, LaunchBlock* lb, RoundState* live, long long nnz, int B, int qpath);
 __global__ void k_finalize(int n, int B, const int* row_ptr, const u64* P, int* centre, u64* hub_bits, int* lv,
                            unsigned* la, Ctrl* ctrl);
 __global__ void k_cut(int n, const int* row_ptr, const int* col, const int* centre, const u64* hub_bits, const int* lv,

@@ -66,7 +66,7 @@ __device__ __forceinline__ u64 block_sum(u64 v, u64* red) {
 constexpr int QL = 16384;  // vertices per block whose bucket is kept in LDS between the passes
 constexpr unsigned short Q_NONE = 0xFFFF;
 
-__global__ __launch_bounds__(1024) void k_init(int n, long long nnz, const int* __restrict__ row_ptr,
+__global__ __launch_bounds__(1024, 8) void k_init(int n, long long nnz, const int* __restrict__ row_ptr,
                                               const long long* __restrict__ shift, u64* __restrict__ P,
                                               Ctrl* ctrl, unsigned* __restrict__ mat, int* __restrict__ qmax,
                                               u64* __restrict__ cand, unsigned* __restrict__ cand_cnt) {
@@ -78,20 +78,30 @@ __global__ __launch_bounds__(1024) void k_init(int n, long long nnz, const int* 
   for (int i = threadIdx.x; i < QCAP; i += blockDim.x) h[i] = 0;
   if (threadIdx.x == 0) c_n = 0;
   __syncthreads();
-  u64 mx = 0, active = 0, hub = 0, qm = 0;
-  unsigned bad = 0, wide = 0;
+  u64 mx = 0, hub = 0;
+  unsigned active = 0, qm = 0, bad = 0, wide = 0;
   const unsigned lane = lane_id(), wid = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
   const long long lo = (long long)n * blockIdx.x / gridDim.x, hi = (long long)n * (blockIdx.x + 1) / gridDim.x;
   for (long long base = lo + 256ll * wid; base < hi; base += 256ll * nw) {
+    // all loads of the four vertices first (indices clamped into the block, so unconditional)
+    long long sv[4];
+    int av[4], bv[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const long long v = min(base + 64 * j + lane, hi - 1);
+      sv[j] = shift[v];
+      av[j] = row_ptr[v];
+      bv[j] = row_ptr[v + 1];
+    }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const long long v = base + 64 * j + lane;
       if (v < hi) {
-        const long long s = shift[v];
+        const long long s = sv[j];
         const bool s_ok = s >= 0 && s <= (1ll << 52);
         if (!s_ok) bad |= ERR_BAD_SHIFT;
         else mx = (u64)s > mx ? (u64)s : mx;
-        const int a = row_ptr[v], b = row_ptr[v + 1];
+        const int a = av[j], b = bv[j];
         if (a < 0 || b < a || (long long)b > nnz) bad |= ERR_BAD_ROWPTR;
         if (v == 0 && a != 0) bad |= ERR_BAD_ROWPTR;
         if (v == n - 1 && (long long)b != nnz) bad |= ERR_BAD_ROWPTR;
@@ -104,7 +114,7 @@ __global__ __launch_bounds__(1024) void k_init(int n, long long nnz, const int* 
           const u64 q = (u64)s >> FIX;
           if (q < (u64)QCAP) {
             atomicAdd(&h[q], 1u);
-            qm = (q + 1) > qm ? (q + 1) : qm;  // q + 1 so that 0 means "no vertex"
+            qm = (unsigned)q + 1 > qm ? (unsigned)q + 1 : qm;  // q + 1 so that 0 means "no vertex"
             qs = (unsigned short)q;
           } else {
             wide = 1;
@@ -115,9 +125,9 @@ __global__ __launch_bounds__(1024) void k_init(int n, long long nnz, const int* 
     }
   }
   mx = block_max(mx, red[0]);
-  active = block_sum(active, red[1]);
+  const u64 act = block_sum(active, red[1]);
   hub = block_max(hub, red[2]);
-  qm = block_max(qm, red[3]);
+  qm = (unsigned)block_max(qm, red[3]);
   // bucket floor t_b: the lowest bucket such that buckets t_b .. qm - 1 hold at most CAND
   // vertices (wave 0 walks the histogram down from the top, 64 buckets at a time)
   if (wid == 0) {
@@ -138,30 +148,24 @@ __global__ __launch_bounds__(1024) void k_init(int n, long long nnz, const int* 
   __syncthreads();
   const int tb = t_sh;
   u64* my_cand = cand + (size_t)blockIdx.x * CAND;
-  for (long long base = lo + 256ll * wid; base < hi; base += 256ll * nw) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const long long v = base + 64 * j + lane;
-      if (v < hi) {
-        unsigned q = Q_NONE;
-        if (v - lo < QL) {
-          q = ql[v - lo];
-        } else {  // blocks of more than QL vertices read the rest again
-          const long long s = shift[v];
-          if (row_ptr[v + 1] > row_ptr[v] && s >= 0 && (u64)s < ((u64)QCAP << FIX)) q = (unsigned)((u64)s >> FIX);
-        }
-        if (q != Q_NONE && (int)q >= tb) {
-          const unsigned idx = atomicAdd(&c_n, 1u);
-          if (idx < (unsigned)CAND) my_cand[idx] = ((u64)q << 32) | (u64)v;
-          else bad |= ERR_QUEUE;  // cannot happen: the buckets >= t_b hold at most CAND
-        }
-      }
+  auto list = [&](long long v, unsigned q) {
+    if (q != Q_NONE && (int)q >= tb) {
+      const unsigned idx = atomicAdd(&c_n, 1u);
+      if (idx < (unsigned)CAND) my_cand[idx] = ((u64)q << 32) | (u64)v;
+      else bad |= ERR_QUEUE;  // cannot happen: the buckets >= t_b hold at most CAND
     }
+  };
+  const long long hi_l = min(hi, lo + QL);
+  for (long long v = lo + threadIdx.x; v < hi_l; v += blockDim.x) list(v, ql[v - lo]);
+  for (long long v = hi_l + threadIdx.x; v < hi; v += blockDim.x) {  // blocks of more than QL vertices
+    const long long s = shift[v];
+    const bool keep = row_ptr[v + 1] > row_ptr[v] && s >= 0 && (u64)s < ((u64)QCAP << FIX);
+    list(v, keep ? (unsigned)((u64)s >> FIX) : Q_NONE);
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     if (mx) atomic_max_u64(&ctrl->delta, mx);
-    if (active) atomic_add_u64(&ctrl->n_active, active);
+    if (act) atomic_add_u64(&ctrl->n_active, act);
     atomic_max_u64(&ctrl->hub, hub);
     qmax[blockIdx.x] = (int)qm - 1;
     cand_cnt[blockIdx.x] = c_n < (unsigned)CAND ? c_n : (unsigned)CAND;
@@ -173,33 +177,64 @@ __global__ __launch_bounds__(1024) void k_init(int n, long long nnz, const int* 
   for (int q = threadIdx.x; q < (int)qm; q += blockDim.x) mat[(size_t)q * G + blockIdx.x] = h[q];
 }
 
-// One wave per q-bucket: exclusive scan of the per-block counts (in place) and the total.
-__global__ __launch_bounds__(256) void k_qbucket_scan(int Qn, int G, unsigned* __restrict__ mat,
-                                                      const int* __restrict__ qmax, unsigned* __restrict__ tot) {
-  const int q = (int)((blockIdx.x * blockDim.x + threadIdx.x) / WAVE);
-  if (q >= Qn) return;  // whole waves leave together
-  const unsigned lane = lane_id();
-  unsigned* row = mat + (size_t)q * G;
-  unsigned run = 0;
-  for (int b0 = 0; b0 < G; b0 += WAVE) {
-    const int b = b0 + (int)lane;
-    const bool has = b < G && q <= qmax[b];
-    const unsigned x = has ? row[b] : 0u;
-    const unsigned incl = wave_incl_scan(x);
-    if (has) row[b] = run + incl - x;
-    run += __shfl(incl, WAVE - 1, WAVE);
+// The sorted (q-bucket) layout applies: valid input, every shift's integer part below QCAP.
+// The kernels of that layout are enqueued before the host knows, and leave at once otherwise.
+__device__ __forceinline__ bool qpath_ok(const Ctrl* ctrl) {
+  return !(ctrl->err & (ERR_BAD_SHIFT | ERR_BAD_ROWPTR | ERR_BAD_COL)) && !ctrl->wide &&
+         (ctrl->delta >> FIX) < (u64)QCAP;
+}
+
+// One block per q-bucket (striding): exclusive scan of the per-block counts (in place) and
+// the bucket's total.  G <= 1024 preparation blocks, at most four per thread.
+__global__ __launch_bounds__(256) void k_qbucket_scan(int G, unsigned* __restrict__ mat, const int* __restrict__ qmax,
+                                                      unsigned* __restrict__ tot, const Ctrl* __restrict__ ctrl) {
+  __shared__ unsigned wsum[4];
+  if (!qpath_ok(ctrl)) return;
+  const int Qn = (int)(ctrl->delta >> FIX) + 1;
+  const unsigned lane = lane_id(), wid = threadIdx.x / WAVE;
+  const int per = (G + 255) / 256;
+  const int b0 = (int)threadIdx.x * per;
+  int qm[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) qm[i] = (i < per && b0 + i < G) ? qmax[b0 + i] : -1;
+  for (int q = blockIdx.x; q < Qn; q += gridDim.x) {
+    unsigned* row = mat + (size_t)q * G;
+    unsigned x[4], sum = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      x[i] = q <= qm[i] ? row[b0 + i] : 0u;
+      sum += x[i];
+    }
+    const unsigned incl = wave_incl_scan(sum);
+    __syncthreads();  // the previous bucket's reads of wsum are done
+    if (lane == WAVE - 1) wsum[wid] = incl;
+    __syncthreads();
+    unsigned acc = incl - sum, total = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      if (w < (int)wid) acc += wsum[w];
+      total += wsum[w];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (q <= qm[i]) {
+        row[b0 + i] = acc;
+        acc += x[i];
+      }
+    if (threadIdx.x == 0) tot[q] = total;
   }
-  if (lane == 0) tot[q] = run;
 }
 
 // One block: bucket offsets qoff[0..D+1] and, per round r (R = D + 1 rounds), the next round
 // at or after r whose two q-buckets (D - r and D - r - 1) are not both empty.  Thread t takes
 // a run of consecutive buckets (rounds); the runs' sums are combined by an exclusive prefix
 // scan, their first non-empty rounds by a suffix minimum (wave shuffles, then across waves).
-__global__ __launch_bounds__(1024) void k_qscan(int D, const unsigned* __restrict__ tot, int* __restrict__ qoff,
-                                                int* __restrict__ next_ne) {
+__global__ __launch_bounds__(1024) void k_qscan(const Ctrl* __restrict__ ctrl, const unsigned* __restrict__ tot,
+                                                int* __restrict__ qoff, int* __restrict__ next_ne) {
   __shared__ unsigned w_sum[16];
   __shared__ int w_first[16];
+  if (!qpath_ok(ctrl)) return;
+  const int D = (int)(ctrl->delta >> FIX);
   const int Qn = D + 1, R = D + 1;
   const int t = threadIdx.x;
   const unsigned lane = lane_id(), wid = t / WAVE;
@@ -245,15 +280,19 @@ __global__ __launch_bounds__(1024) void k_qscan(int D, const unsigned* __restric
   }
 }
 
-// Places the first wake window, buckets [q_lo, D], from the blocks' candidate lists.  A
-// vertex's slot is its bucket's offset, plus the counts of the same bucket in earlier
-// preparation blocks, plus its rank inside its own block (an LDS cursor per bucket).
-__global__ __launch_bounds__(256) void k_place_window(int q_lo, int D, const unsigned* __restrict__ mat,
+// Places the first wake window, buckets [q_lo, D] (q_lo = place_lo), from the blocks'
+// candidate lists.  A vertex's slot is its bucket's offset, plus the counts of the same bucket
+// in earlier preparation blocks, plus its rank inside its own block (an LDS cursor per bucket).
+__global__ __launch_bounds__(256) void k_place_window(const Ctrl* __restrict__ ctrl, const unsigned* __restrict__ mat,
                                                       const int* __restrict__ qmax, const int* __restrict__ qoff,
                                                       const u64* __restrict__ cand,
                                                       const unsigned* __restrict__ cand_cnt,
                                                       int* __restrict__ wake_ord) {
   __shared__ unsigned cur[QCAP];
+  if (!qpath_ok(ctrl)) return;
+  const int D = (int)(ctrl->delta >> FIX);
+  const int q_lo = (int)ctrl->place_lo;
+  if (q_lo > D) return;
   const unsigned G = gridDim.x;
   const int qm = min(qmax[blockIdx.x], D);
   for (int q = q_lo + (int)threadIdx.x; q <= qm; q += blockDim.x)
@@ -265,6 +304,39 @@ __global__ __launch_bounds__(256) void k_place_window(int q_lo, int D, const uns
     const int q = (int)(e >> 32);
     if (q >= q_lo && q <= qm) wake_ord[atomicAdd(&cur[q - q_lo], 1u)] = (int)(unsigned)e;
   }
+}
+
+// Single thread, after the preparation: decides whether the rounds run (ctrl->setup), writes
+// the initial round state into both slots and completes the round kernels' arguments with what
+// only the device knows (Delta, the rounds bound, the vertices with arcs).  When the rounds are
+// not to run, both slots and the host's mirror say "done", so enqueued steps return at once.
+__global__ void k_setup(Ctrl* ctrl, RoundState* st, LaunchBlock* lb, RoundState* live, long long nnz, int B,
+                        int qpath) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const u64 delta = ctrl->delta, n_active = ctrl->n_active;
+  const u64 D = delta >> FIX;
+  unsigned code = SETUP_OK;
+  if (ctrl->err & (ERR_BAD_SHIFT | ERR_BAD_ROWPTR | ERR_BAD_COL)) code = SETUP_INVALID;
+  else if (delta + ((u64)1 << FIX) >= ((u64)1 << (64 - B)) || D + 1 > ((u64)1 << 28)) code = SETUP_OVERFLOW;
+  else if (qpath && (ctrl->wide || D >= (u64)QCAP)) code = SETUP_WIDE;
+  else if (n_active == 0) code = SETUP_EMPTY;
+  ctrl->setup = code;
+  RoundState s0{};
+  s0.seq = 0;
+  s0.mode = code == SETUP_OK ? MODE_ROUNDS : MODE_DONE;
+  s0.round = -1;
+  s0.dir = DIR_TD;
+  s0.unsettled_arcs = nnz;
+  s0.tail_round = -1;
+  s0.placed_lo = qpath ? (long long)(ctrl->place_lo < D + 1 ? ctrl->place_lo : D + 1) : 0;
+  s0.flip = 0;
+  st[0] = s0;
+  s0.seq = -1;  // slot 1 stands for "step -1"
+  st[1] = s0;
+  lb->c.delta = delta;
+  lb->c.R = code == SETUP_OK ? (int)(D + 1) : 0;
+  lb->c.n_active = n_active;
+  if (code != SETUP_OK && live) __hip_atomic_store(&live->mode, (long long)MODE_DONE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 __global__ __launch_bounds__(256) void k_check_cols(int n, long long nnz, const int* __restrict__ col, Ctrl* ctrl) {
@@ -402,6 +474,9 @@ __global__ __launch_bounds__(FT) void k_finalize(int n, int B, const int* __rest
   __shared__ unsigned b_n, b_arcs;
   __shared__ u64 b_base;
   __shared__ u64 red[2][FT / WAVE];
+  // labels and rows are not to be trusted when the preparation refused the input; the list
+  // stays empty and the cut kernel finds nothing to do
+  if (ctrl->setup >= SETUP_INVALID) return;
   const u64 mask = ((u64)1 << B) - 1;
   const int hub = (int)(unsigned)ctrl->hub;
   // a label still INF belongs to an isolated vertex (never placed, never reached): its own centre
@@ -420,6 +495,15 @@ __global__ __launch_bounds__(FT) void k_finalize(int n, int B, const int* __rest
   for (long long base = lo; base < hi; base += 4 * FT) {
     bool want[4];
     unsigned deg[4];
+    u64 pl[4];
+    int a0[4], a1[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {  // all loads first (indices clamped, so unconditional)
+      const long long v = min(base + 256 * wid + 64 * j + lane, hi - 1);
+      pl[j] = P[v];
+      a0[j] = row_ptr[v];
+      a1[j] = row_ptr[v + 1];
+    }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const long long v = base + 256 * wid + 64 * j + lane;
@@ -427,11 +511,11 @@ __global__ __launch_bounds__(FT) void k_finalize(int n, int B, const int* __rest
       want[j] = false;
       deg[j] = 0;
       if (v < hi) {
-        const u64 p = P[v];
+        const u64 p = pl[j];
         const int cv = p == INF ? (int)v : (int)(p & mask);
         centre[v] = cv;
         pieces += (cv == (int)v);
-        deg[j] = (unsigned)(row_ptr[v + 1] - row_ptr[v]);
+        deg[j] = (unsigned)(a1[j] - a0[j]);
         unreached += (p == INF && deg[j] > 0);
         in_hub = cv == hub_c;
         want[j] = !in_hub && deg[j] > 0;

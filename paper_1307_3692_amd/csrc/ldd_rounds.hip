@@ -610,9 +610,10 @@ __global__ void k_advance(LaunchBlock* lb, int C) {
 }
 
 // All steps in one kernel with grid barriers between them (the grid must be co-resident).
-__global__ __launch_bounds__(RT) void k_rounds_persistent(RoundCtx c) {
+__global__ __launch_bounds__(RT) void k_rounds_persistent(const LaunchBlock* __restrict__ lb) {
   __shared__ AppendBuf ab;
   __shared__ StepShared sh;
+  const RoundCtx& c = lb->c;
   u64 gen = 0;
   const long long kmax = (long long)c.R + c.n + 2;
   for (int k = 1; k <= kmax; ++k) {
