@@ -134,6 +134,26 @@ __device__ __forceinline__ void atomic_or_u32(unsigned* p, unsigned v) {
 __device__ __forceinline__ unsigned load_u32_acquire(const unsigned* p) {
   return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
+// Last index i in [0, cnt) with a[i] <= x, for a non-decreasing array with a[0] <= x.  One
+// wave splits the range 64 ways per pass (ceil(log64 cnt) + 1 dependent loads instead of
+// log2 cnt); called by all lanes of the wave, every lane gets the answer.
+__device__ __forceinline__ unsigned wave_search_le(const unsigned* a, unsigned cnt, unsigned x) {
+  const unsigned lane = lane_id();
+  unsigned lo = 0, hi = cnt;
+  while (hi - lo > (unsigned)WAVE) {
+    const u64 span = hi - lo;
+    const unsigned idx = lo + (unsigned)(span * lane / WAVE);
+    const u64 m = __ballot(a[idx] <= x);  // a prefix of the lanes; lane 0 holds a[lo] <= x
+    const unsigned L = 63u - (unsigned)__builtin_clzll(m);
+    const unsigned nlo = lo + (unsigned)(span * L / WAVE);
+    if (L < (unsigned)WAVE - 1) hi = lo + (unsigned)(span * (L + 1) / WAVE);
+    lo = nlo;
+  }
+  const unsigned idx = lo + lane;
+  const u64 m = __ballot(idx < hi && a[idx] <= x);
+  return lo + (63u - (unsigned)__builtin_clzll(m));
+}
+
 __device__ __forceinline__ u64 load_u64_relaxed(const u64* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

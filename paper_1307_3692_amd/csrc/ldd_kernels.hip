@@ -637,14 +637,9 @@ __global__ __launch_bounds__(256) void k_cut(int n, const int* __restrict__ row_
   const unsigned a_end = (unsigned)(((u64)al * (blockIdx.x + 1)) / G);
   u64 one_side = 0, both = 0;
   if (a_begin < a_end) {
-    if (threadIdx.x == 0) {
-      unsigned lo = 0, hi = nl;
-      while (hi - lo > 1) {
-        const unsigned mid = (lo + hi) >> 1;
-        if (la[mid] <= a_begin) lo = mid;
-        else hi = mid;
-      }
-      s_start = lo;
+    if (threadIdx.x < WAVE) {
+      const unsigned e = wave_search_le(la, nl, a_begin);
+      if (threadIdx.x == 0) s_start = e;
     }
     __syncthreads();
     unsigned ent = s_start;

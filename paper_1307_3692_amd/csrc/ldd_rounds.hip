@@ -204,14 +204,9 @@ __device__ __forceinline__ void phase_top_down(const RoundCtx& c, int k, const i
   const unsigned a_begin = (unsigned)(((u64)af * blockIdx.x) / G);
   const unsigned a_end = (unsigned)(((u64)af * (blockIdx.x + 1)) / G);
   if (a_begin >= a_end) return;
-  if (threadIdx.x == 0) {
-    unsigned lo = 0, hi = nf;  // last entry with qa <= a_begin
-    while (hi - lo > 1) {
-      const unsigned mid = (lo + hi) >> 1;
-      if (qa[mid] <= a_begin) lo = mid;
-      else hi = mid;
-    }
-    sh.start = lo;
+  if (threadIdx.x < WAVE) {  // last entry with qa <= a_begin
+    const unsigned e = wave_search_le(qa, nf, a_begin);
+    if (threadIdx.x == 0) sh.start = e;
   }
   __syncthreads();
   unsigned ent = sh.start;
@@ -941,14 +936,9 @@ __device__ __forceinline__ void srv_td_segment(const RoundCtx& c, int k, SrvAppe
   const long long vbeg = ss.vbeg[s], nnz = ss.nnz[s];
   const int n = ss.n[s];
   __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned lo = 0, hi = nf;  // the last entry with qa <= lo_a
-    while (hi - lo > 1) {
-      const unsigned mid = (lo + hi) >> 1;
-      if (qa[mid] <= lo_a) lo = mid;
-      else hi = mid;
-    }
-    ss.start = lo;
+  if (threadIdx.x < WAVE) {  // the last entry with qa <= lo_a
+    const unsigned e = wave_search_le(qa, nf, lo_a);
+    if (threadIdx.x == 0) ss.start = e;
   }
   __syncthreads();
   unsigned ent = ss.start;

@@ -377,14 +377,9 @@ __global__ __launch_bounds__(FIN_T) void k_fin_cut(FinBatch b, int B, const u64*
   const u64* Ps = P + t.vbeg;
   u64 cut = 0;
   if (a_begin < a_end) {  // uniform
-    if (threadIdx.x == 0) {
-      unsigned lo = 0, hi = ne;  // the last entry whose arcs start at or before a_begin
-      while (hi - lo > 1) {
-        const unsigned mid = (lo + hi) >> 1;
-        if (LA[mid] <= a_begin) lo = mid;
-        else hi = mid;
-      }
-      s_ent = lo;
+    if (threadIdx.x < WAVE) {  // the last entry whose arcs start at or before a_begin
+      const unsigned e = wave_search_le(LA, ne, a_begin);
+      if (threadIdx.x == 0) s_ent = e;
     }
     __syncthreads();
     unsigned ent = s_ent;
