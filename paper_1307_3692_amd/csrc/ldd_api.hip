@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -78,15 +79,15 @@ ldd_status grow(Buf& b, size_t bytes) {
   return LDD_OK;
 }
 
-struct HostMirror {  // pinned copies of the device control block and round states
+struct HostMirror {  // pinned, mapped host memory
   Ctrl ctrl;
   u64 ex_part[RT];
-  RoundState st[2];
-  RoundState live;  // written by the step kernels as they run
-  LaunchBlock lb;   // staging for the device copy
+  Report report;   // written by the device as a decomposition ends
+  LaunchBlock lb;  // staging for the device copy
 };
 
-constexpr int CHUNK = 8;  // steps per graph replay
+constexpr int CHUNK = 8;     // steps per graph replay
+constexpr int INFLIGHT = 2;  // replays enqueued ahead of the one running
 
 struct StepGraph {
   int blocks = 0;
@@ -103,8 +104,10 @@ struct Workspace {
   Buf b_rp, b_col, b_shift, b_gid, b_off, b_dg, b_cut;
   HostMirror* host = nullptr;
   hipEvent_t ev[6] = {};
-  hipEvent_t chunk_ev[2] = {};
+  hipEvent_t chunk_ev[INFLIGHT] = {};
+  hipEvent_t out_ev = nullptr;
   hipStream_t capture = nullptr;
+  hipStream_t out = nullptr;  // the output pass, concurrent with the replays still queued
   std::vector<StepGraph> graphs;
   int num_cu = 0;
   int max_coresident = 0;  // co-resident blocks of the persistent round kernel
@@ -126,6 +129,8 @@ ldd_status ws_setup(Workspace& w) {
     for (auto& e : w.ev) HIP_TRY(hipEventCreate(&e));
     for (auto& e : w.chunk_ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     HIP_TRY(hipStreamCreateWithFlags(&w.capture, hipStreamNonBlocking));
+    HIP_TRY(hipStreamCreateWithFlags(&w.out, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&w.out_ev, hipEventDisableTiming));
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&w.num_cu, hipDeviceAttributeMultiprocessorCount, dev));
@@ -197,6 +202,7 @@ extern "C" void ldd_release_workspace(void) {
   if (hipGetDevice(&dev) != hipSuccess) return;
   Workspace* w = workspace_for(dev);
   std::lock_guard<std::mutex> lk(w->mu);
+  (void)hipDeviceSynchronize();  // round steps a call left queued (they return at once) may still read it
   for (auto& g : w->graphs) (void)hipGraphExecDestroy(g.exec);  // they hold workspace pointers
   w->graphs.clear();
   for (Buf* b : {&w->P, &w->qv0, &w->qv1, &w->qa0, &w->qa1, &w->wake_ord, &w->stamp, &w->hub_bits, &w->hist,
@@ -396,8 +402,13 @@ static ldd_status decompose_run(Workspace& w, const ldd_csr* g, const int64_t* s
   c.bu_to_td = o.bu_to_td > 0 ? o.bu_to_td : 24;
   c.tail_den = tail_den;
   c.tail_min_left = 16;
-  c.host_st = nullptr;
   c.ex_part = (u64*)w.ex_part.p;
+  void* report_dev = nullptr;
+  HIP_TRY(hipHostGetDevicePointer(&report_dev, &w.host->report, 0));
+  c.report = (Report*)report_dev;
+  volatile Report* rep = &w.host->report;
+  rep->ready = 0;
+  rep->out_ready = 0;
 
   const int engine = o.engine == LDD_ENGINE_AUTO ? LDD_ENGINE_LAUNCH : o.engine;
   int blocks = o.blocks > 0 ? o.blocks : 2 * w.num_cu;
@@ -406,98 +417,135 @@ static ldd_status decompose_run(Workspace& w, const ldd_csr* g, const int64_t* s
   // rounds, placement steps, tail sweeps (each settles or lowers at least one label) and slack
   const long long kmax = R_bound + R_bound / ABUF + 1 + (long long)n + 2;
   long long steps = 0;
-  volatile RoundState* live = &w.host->live;
-  void* host_st_dev = nullptr;
   hipGraphExec_t exec = nullptr;
-  if (engine != LDD_ENGINE_PERSISTENT) {
-    if ((s = step_graph(w, blocks, &exec))) return s;
-    HIP_TRY(hipHostGetDevicePointer(&host_st_dev, &w.host->live, 0));
-    c.host_st = (RoundState*)host_st_dev;
-    live->mode = MODE_ROUNDS;
-    live->seq = 0;
-  }
+  if (engine != LDD_ENGINE_PERSISTENT && (s = step_graph(w, blocks, &exec))) return s;
   w.host->lb.c = c;
   w.host->lb.kbase = 1;
   HIP_TRY(hipMemcpyAsync(w.lb.p, &w.host->lb, sizeof(LaunchBlock), hipMemcpyHostToDevice, st));
-  hipLaunchKernelGGL(k_setup, dim3(1), dim3(64), 0, st, ctrl, (RoundState*)w.st.p, (LaunchBlock*)w.lb.p,
-                     (RoundState*)host_st_dev, nnz, B, wide ? 0 : 1);
+  hipLaunchKernelGGL(k_setup, dim3(1), dim3(64), 0, st, ctrl, (RoundState*)w.st.p, (LaunchBlock*)w.lb.p, c.report, nnz,
+                     B, wide ? 0 : 1);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipEventRecord(w.ev[1], st));
+  // The host spins on the report (written by the step that finds the rounds done) and on the
+  // oldest replay's completion, which makes room for another.  Replays still queued after the
+  // report return at once; the output pass runs on its own stream beside them.
   if (engine == LDD_ENGINE_PERSISTENT) {
     const LaunchBlock* lbp = (const LaunchBlock*)w.lb.p;
     void* args[] = {&lbp};
     HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_rounds_persistent), dim3(blocks), dim3(RT), args,
                                        0, st));
+    HIP_TRY(hipEventRecord(w.chunk_ev[0], st));
+    while (!rep->ready) {
+      const hipError_t q = hipEventQuery(w.chunk_ev[0]);
+      if (q == hipErrorNotReady) {
+        __builtin_ia32_pause();
+        continue;
+      }
+      HIP_TRY(q);
+      break;  // ended: the report is there, or missing (checked below)
+    }
     steps = 1;
   } else {
-    // Steps run as replays of a captured chunk graph.  Two chunks are kept in flight: the host
-    // waits for the older one, reads the state the steps publish to mapped host memory, and
-    // enqueues another chunk only if the decomposition is not done yet.
     long long submitted = 0;
-    int oldest = 0;
-    for (int i = 0; i < 2; ++i) {
+    int head = 0;
+    for (int i = 0; i < INFLIGHT; ++i) {
       HIP_TRY(hipGraphLaunch(exec, st));
       HIP_TRY(hipEventRecord(w.chunk_ev[i], st));
       submitted += CHUNK;
     }
-    for (;;) {
-      HIP_TRY(hipEventSynchronize(w.chunk_ev[oldest]));
-      if (live->mode == MODE_DONE) break;
+    while (!rep->ready) {
+      const hipError_t q = hipEventQuery(w.chunk_ev[head]);
+      if (q == hipErrorNotReady) {
+        __builtin_ia32_pause();
+        continue;
+      }
+      HIP_TRY(q);
+      if (rep->ready) break;
       if (submitted > kmax) {
         HIP_TRY(hipStreamSynchronize(st));
         ldd_set_error("round steps exceeded their bound (%lld)", kmax);
         return LDD_ERR_INTERNAL;
       }
       HIP_TRY(hipGraphLaunch(exec, st));
-      HIP_TRY(hipEventRecord(w.chunk_ev[oldest], st));
+      HIP_TRY(hipEventRecord(w.chunk_ev[head], st));
       submitted += CHUNK;
-      oldest ^= 1;
+      head = (head + 1) % INFLIGHT;
     }
     steps = submitted;
   }
-  HIP_TRY(hipMemcpyAsync(w.host->st, w.st.p, 2 * sizeof(RoundState), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipEventRecord(w.ev[2], st));
-  const int g_f = grid_for((n + 63) / 64, 256, 1024);  // whole bitmap words per block
-  hipLaunchKernelGGL(k_finalize, dim3(g_f), dim3(1024), 0, st, n, B, g->row_ptr, (const u64*)P, centre,
-                     (u64*)w.hub_bits.p, (int*)w.qv0.p, (unsigned*)w.qa0.p, ctrl);
-  HIP_TRY(hipEventRecord(w.ev[3], st));
-  if (nnz > 0)
-    hipLaunchKernelGGL(k_cut, dim3(grid_for(nnz, 256 * 8, 2048)), dim3(256), 0, st, n, g->row_ptr, g->col_idx,
-                       (const int*)centre, (const u64*)w.hub_bits.p, (const int*)w.qv0.p, (const unsigned*)w.qa0.p,
-                       ctrl, bv ? bv->gid : nullptr, bv ? bv->cut_g : nullptr);
-  HIP_TRY(hipGetLastError());
-  HIP_TRY(hipEventRecord(w.ev[4], st));
-  HIP_TRY(hipMemcpyAsync(&w.host->ctrl, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
-  if (stats) HIP_TRY(hipMemcpyAsync(w.host->ex_part, w.ex_part.p, (size_t)blocks * sizeof(u64), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  const Ctrl& h = w.host->ctrl;
-  switch (h.setup) {
+  if (!rep->ready) {
+    HIP_TRY(hipStreamSynchronize(st));
+    ldd_set_error("the rounds ended without a report");
+    return LDD_ERR_INTERNAL;
+  }
+  std::atomic_thread_fence(std::memory_order_acquire);
+  switch (rep->setup) {
     case SETUP_OK:
     case SETUP_EMPTY:
       break;
     case SETUP_WIDE:
+      HIP_TRY(hipStreamSynchronize(st));
       return REDO_WIDE;
     case SETUP_OVERFLOW:
       ldd_set_error("labels need (Delta + 2^20) << %d < 2^64 and at most 2^28 rounds (Delta = %llu)", B,
-                    (unsigned long long)h.delta);
+                    (unsigned long long)rep->delta);
       return LDD_ERR_OVERFLOW;
     default: {
-      ldd_status e = finish_error(h.err);
+      ldd_status e = finish_error(rep->err);
       return e != LDD_OK ? e : LDD_ERR_INTERNAL;
     }
   }
   {
-    ldd_status e = finish_error(h.err);
+    ldd_status e = finish_error(rep->err);
     if (e != LDD_OK) return e;
   }
-  const u64 delta = h.delta, n_active = h.n_active;
-  const long long R = (long long)(delta >> FIX) + 1;
-  const RoundState& fs = w.host->st[0].seq > w.host->st[1].seq ? w.host->st[0] : w.host->st[1];
-  if (h.unreached != 0 || (n_active > 0 && fs.mode != MODE_DONE)) {
-    ldd_set_error("rounds ended with %llu labels unset (mode %lld)", (unsigned long long)h.unreached, fs.mode);
+  // output pass: every label is final once the report is there
+  const hipStream_t so = w.out;
+  HIP_TRY(hipEventRecord(w.ev[2], so));
+  const int g_f = grid_for((n + 63) / 64, 256, 1024);  // whole bitmap words per block
+  hipLaunchKernelGGL(k_finalize, dim3(g_f), dim3(1024), 0, so, n, B, g->row_ptr, (const u64*)P, centre,
+                     (u64*)w.hub_bits.p, (int*)w.qv0.p, (unsigned*)w.qa0.p, ctrl);
+  HIP_TRY(hipEventRecord(w.ev[3], so));
+  if (nnz > 0)
+    hipLaunchKernelGGL(k_cut, dim3(grid_for(nnz, 256 * 8, 2048)), dim3(256), 0, so, n, g->row_ptr, g->col_idx,
+                       (const int*)centre, (const u64*)w.hub_bits.p, (const int*)w.qv0.p, (const unsigned*)w.qa0.p,
+                       ctrl, bv ? bv->gid : nullptr, bv ? bv->cut_g : nullptr);
+  HIP_TRY(hipEventRecord(w.ev[4], so));
+  hipLaunchKernelGGL(k_out_report, dim3(1), dim3(64), 0, so, (const Ctrl*)ctrl, c.report);
+  HIP_TRY(hipGetLastError());
+  if (stats) HIP_TRY(hipMemcpyAsync(w.host->ex_part, w.ex_part.p, (size_t)blocks * sizeof(u64), hipMemcpyDeviceToHost, so));
+  HIP_TRY(hipEventRecord(w.out_ev, so));
+  HIP_TRY(hipStreamWaitEvent(st, w.out_ev, 0));  // later work on the caller's stream sees the output
+  if (stats) {
+    HIP_TRY(hipEventSynchronize(w.out_ev));
+  } else {
+    while (!rep->out_ready) {
+      const hipError_t q = hipEventQuery(w.out_ev);
+      if (q == hipErrorNotReady) {
+        __builtin_ia32_pause();
+        continue;
+      }
+      HIP_TRY(q);
+      break;
+    }
+  }
+  if (!rep->out_ready) {
+    ldd_set_error("the output pass ended without a report");
     return LDD_ERR_INTERNAL;
   }
-  if (cut_edges) *cut_edges = (int64_t)(h.cut_arcs / 2);
+  std::atomic_thread_fence(std::memory_order_acquire);
+  {
+    ldd_status e = finish_error(rep->out_err);
+    if (e != LDD_OK) return e;
+  }
+  const u64 delta = rep->delta, n_active = rep->n_active;
+  const long long R = (long long)(delta >> FIX) + 1;
+  const RoundState fs = *(const RoundState*)&rep->st;
+  if (rep->unreached != 0 || (n_active > 0 && fs.mode != MODE_DONE)) {
+    ldd_set_error("rounds ended with %llu labels unset (mode %lld)", (unsigned long long)rep->unreached, fs.mode);
+    return LDD_ERR_INTERNAL;
+  }
+  if (cut_edges) *cut_edges = (int64_t)(rep->cut_arcs / 2);
   if (stats) {
     stats->rounds = n_active ? (int32_t)fs.rounds : 0;
     stats->rounds_bound = (int32_t)R;
@@ -508,7 +556,7 @@ static ldd_status decompose_run(Workspace& w, const ldd_csr* g, const int64_t* s
     stats->blocks = blocks;
     stats->steps = (int32_t)steps;
     stats->delta = (int64_t)delta;
-    stats->pieces = (int64_t)h.pieces;
+    stats->pieces = (int64_t)rep->pieces;
     stats->max_frontier = n_active ? (int64_t)fs.max_frontier : 0;
     u64 ex = 0;
     for (int b = 0; b < blocks; ++b) ex += w.host->ex_part[b];

@@ -39,6 +39,19 @@ struct RoundState {
 #undef LDD_DECL
 };
 
+// What the host reads at the end, in mapped host memory.  The step that finds the rounds done
+// (or k_setup, when the rounds are not to run) writes the first part and then `ready`; the
+// output pass writes the totals and then `out_ready`.
+struct Report {
+  RoundState st;
+  u64 delta, n_active;
+  unsigned err, setup;
+  long long ready;
+  u64 cut_arcs, pieces, unreached;
+  unsigned out_err;
+  long long out_ready;
+};
+
 // Server mode: one admitted request per slot, in its own vertex range of the arena.
 constexpr int MAX_SLOTS = 64;
 // The request's CSR and shifts stay in the caller's device buffers (local ids); arena vertex
@@ -103,7 +116,7 @@ struct RoundCtx {
   int bu_to_td;
   int tail_den;     // enter the tail once unsettled * tail_den <= n_active (0: never)
   int tail_min_left;  // ... and more than this many rounds remain
-  RoundState* host_st;  // pinned host mirror of the latest state (may be null)
+  Report* report;   // mapped host memory (may be null)
   u64* ex_part;     // [G]: arcs examined by each block over all steps (statistics)
   // server mode (k_round_step_srv): every step is the next global round for every slot; round
   // r's wakers are those of every slot's local round r - r0 in rounds mode; each slot has its
@@ -141,7 +154,8 @@ __global__ void k_round_step_lb(const LaunchBlock* lb, int j);
 __global__ void k_round_step_srv(const LaunchBlock* lb, int j);
 __global__ void k_advance(LaunchBlock* lb, int C);
 __global__ void k_rounds_persistent(const LaunchBlock* lb);
-__global__ void k_setup(Ctrl* ctrl, RoundState* st, LaunchBlock* lb, RoundState* live, long long nnz, int B, int qpath);
+__global__ void k_setup(Ctrl* ctrl, RoundState* st, LaunchBlock* lb, Report* report, long long nnz, int B, int qpath);
+__global__ void k_out_report(const Ctrl* ctrl, Report* report);
 __global__ void k_finalize(int n, int B, const int* row_ptr, const u64* P, int* centre, u64* hub_bits, int* lv,
                            unsigned* la, Ctrl* ctrl);
 __global__ void k_cut(int n, const int* row_ptr, const int* col, const int* centre, const u64* hub_bits, const int* lv,

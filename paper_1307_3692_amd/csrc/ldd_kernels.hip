@@ -309,8 +309,9 @@ __global__ __launch_bounds__(256) void k_place_window(const Ctrl* __restrict__ c
 // Single thread, after the preparation: decides whether the rounds run (ctrl->setup), writes
 // the initial round state into both slots and completes the round kernels' arguments with what
 // only the device knows (Delta, the rounds bound, the vertices with arcs).  When the rounds are
-// not to run, both slots and the host's mirror say "done", so enqueued steps return at once.
-__global__ void k_setup(Ctrl* ctrl, RoundState* st, LaunchBlock* lb, RoundState* live, long long nnz, int B,
+// not to run, both slots say "done" (enqueued steps return at once) and the report is written
+// here.
+__global__ void k_setup(Ctrl* ctrl, RoundState* st, LaunchBlock* lb, Report* report, long long nnz, int B,
                         int qpath) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const u64 delta = ctrl->delta, n_active = ctrl->n_active;
@@ -336,7 +337,26 @@ __global__ void k_setup(Ctrl* ctrl, RoundState* st, LaunchBlock* lb, RoundState*
   lb->c.delta = delta;
   lb->c.R = code == SETUP_OK ? (int)(D + 1) : 0;
   lb->c.n_active = n_active;
-  if (code != SETUP_OK && live) __hip_atomic_store(&live->mode, (long long)MODE_DONE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  if (code != SETUP_OK && report) {
+    report->st = s0;
+    report->delta = delta;
+    report->n_active = n_active;
+    report->err = ctrl->err;
+    report->setup = code;
+    __threadfence_system();  // the fields before the flag
+    __hip_atomic_store(&report->ready, 1ll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
+// Single thread, after the cut: the output totals for the host.
+__global__ void k_out_report(const Ctrl* ctrl, Report* report) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  report->cut_arcs = ctrl->cut_arcs;
+  report->pieces = ctrl->pieces;
+  report->unreached = ctrl->unreached;
+  report->out_err = ctrl->err;
+  __threadfence_system();
+  __hip_atomic_store(&report->out_ready, 1ll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 __global__ __launch_bounds__(256) void k_check_cols(int n, long long nnz, const int* __restrict__ col, Ctrl* ctrl) {

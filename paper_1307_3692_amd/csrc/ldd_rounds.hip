@@ -535,9 +535,19 @@ __device__ __forceinline__ int round_step(const RoundCtx& c, int k, AppendBuf& a
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     store_state<__HIP_MEMORY_SCOPE_AGENT>(&c.st[k & 1], sh.S);
     __hip_atomic_store(qcounter(c, k + 1), 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    // the host stops enqueueing steps once it reads "done"; written once per decomposition,
-    // since a store to host memory delays the completion of the kernel that makes it
-    if (c.host_st && mode == MODE_DONE) store_state<__HIP_MEMORY_SCOPE_SYSTEM>(c.host_st, sh.S);
+    // the host stops enqueueing steps once it reads the report; written once per
+    // decomposition, since a store to host memory delays the completion of the kernel that
+    // makes it
+    if (c.report && mode == MODE_DONE) {
+      Report* r = c.report;
+      r->st = sh.S;
+      r->delta = c.delta;
+      r->n_active = c.n_active;
+      r->err = __hip_atomic_load(&c.ctrl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      r->setup = SETUP_OK;
+      __threadfence_system();  // the fields before the flag
+      __hip_atomic_store(&r->ready, 1ll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
   }
   if (mode == MODE_DONE) return MODE_DONE;
   if (mode == MODE_PLACE) {

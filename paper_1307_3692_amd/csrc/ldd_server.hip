@@ -748,7 +748,7 @@ ldd_status srv_setup(ldd_server* srv) {
   c.bu_to_td = 24;
   c.tail_den = srv->cfg.tail_vertices == 0 ? 64 : (srv->cfg.tail_vertices < 0 ? 0 : srv->cfg.tail_vertices);
   c.tail_min_left = 16;
-  c.host_st = nullptr;
+  c.report = nullptr;
   c.ex_part = (u64*)srv->ex_part;
   c.slots = (const SlotInfo*)srv->slots;
   c.nslots = srv->cfg.max_slots;
