@@ -100,7 +100,7 @@ typedef struct {
                            /* arcs scanned before the early exit bottom-up)               */
   int64_t n_active;        /* vertices with at least one arc                              */
   float ms_prep;           /* device time: init, Delta, wake-round sort (HIP events)      */
-  float ms_rounds;         /* device time: all rounds                                     */
+  float ms_rounds;         /* device time: all round steps enqueued, idle ones included   */
   float ms_finalize;       /* device time: centre extraction                              */
   float ms_cut;            /* device time: cut count                                      */
   int32_t steps;           /* round-kernel launches (steps) enqueued, done ones included  */

@@ -473,6 +473,7 @@ static ldd_status decompose_run(Workspace& w, const ldd_csr* g, const int64_t* s
     }
     steps = submitted;
   }
+  HIP_TRY(hipEventRecord(w.ev[2], st));  // after every step enqueued, idle ones included
   if (!rep->ready) {
     HIP_TRY(hipStreamSynchronize(st));
     ldd_set_error("the rounds ended without a report");
@@ -501,16 +502,16 @@ static ldd_status decompose_run(Workspace& w, const ldd_csr* g, const int64_t* s
   }
   // output pass: every label is final once the report is there
   const hipStream_t so = w.out;
-  HIP_TRY(hipEventRecord(w.ev[2], so));
+  HIP_TRY(hipEventRecord(w.ev[3], so));
   const int g_f = grid_for((n + 63) / 64, 256, 1024);  // whole bitmap words per block
   hipLaunchKernelGGL(k_finalize, dim3(g_f), dim3(1024), 0, so, n, B, g->row_ptr, (const u64*)P, centre,
                      (u64*)w.hub_bits.p, (int*)w.qv0.p, (unsigned*)w.qa0.p, ctrl);
-  HIP_TRY(hipEventRecord(w.ev[3], so));
+  HIP_TRY(hipEventRecord(w.ev[4], so));
   if (nnz > 0)
     hipLaunchKernelGGL(k_cut, dim3(grid_for(nnz, 256 * 8, 2048)), dim3(256), 0, so, n, g->row_ptr, g->col_idx,
                        (const int*)centre, (const u64*)w.hub_bits.p, (const int*)w.qv0.p, (const unsigned*)w.qa0.p,
                        ctrl, bv ? bv->gid : nullptr, bv ? bv->cut_g : nullptr);
-  HIP_TRY(hipEventRecord(w.ev[4], so));
+  HIP_TRY(hipEventRecord(w.ev[5], so));
   hipLaunchKernelGGL(k_out_report, dim3(1), dim3(64), 0, so, (const Ctrl*)ctrl, c.report);
   HIP_TRY(hipGetLastError());
   if (stats) HIP_TRY(hipMemcpyAsync(w.host->ex_part, w.ex_part.p, (size_t)blocks * sizeof(u64), hipMemcpyDeviceToHost, so));
@@ -518,6 +519,7 @@ static ldd_status decompose_run(Workspace& w, const ldd_csr* g, const int64_t* s
   HIP_TRY(hipStreamWaitEvent(st, w.out_ev, 0));  // later work on the caller's stream sees the output
   if (stats) {
     HIP_TRY(hipEventSynchronize(w.out_ev));
+    HIP_TRY(hipEventSynchronize(w.ev[2]));
   } else {
     while (!rep->out_ready) {
       const hipError_t q = hipEventQuery(w.out_ev);
@@ -567,9 +569,9 @@ static ldd_status decompose_run(Workspace& w, const ldd_csr* g, const int64_t* s
     stats->ms_prep = ms;
     (void)hipEventElapsedTime(&ms, w.ev[1], w.ev[2]);
     stats->ms_rounds = ms;
-    (void)hipEventElapsedTime(&ms, w.ev[2], w.ev[3]);
-    stats->ms_finalize = ms;
     (void)hipEventElapsedTime(&ms, w.ev[3], w.ev[4]);
+    stats->ms_finalize = ms;
+    (void)hipEventElapsedTime(&ms, w.ev[4], w.ev[5]);
     stats->ms_cut = ms;
   }
   return LDD_OK;
