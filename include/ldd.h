@@ -31,7 +31,9 @@
  *     reported as LDD_ERR_INVALID_ARG by bounds checks inside the kernels (no out-of-range
  *     access is made).  ldd_last_error() gives a thread-local detail string.
  *   - hip_stream is a hipStream_t (NULL = default stream).  Work is ordered on that stream;
- *     the single-graph and batch calls return after the stream has completed the call.
+ *     the single-graph and batch calls return once their outputs are complete.  Round steps
+ *     enqueued ahead of the end may still be queued on the stream then; they return at once,
+ *     and later work on the stream is ordered after them and after the outputs.
  */
 #ifndef LDD_H
 #define LDD_H
@@ -115,7 +117,7 @@ typedef struct {
  *   cut_edges  host int64*, OUT (may be NULL): edges whose endpoints have different centres.
  *   opt        NULL for defaults.
  *   stats      host, OUT (may be NULL).
- * Returns after the work on hip_stream has completed.
+ * Returns once centre and the cut are complete (see the stream convention above).
  */
 ldd_status ldd_decompose(const ldd_csr* g, const int64_t* shift_fix, double beta, int32_t* centre,
                          int64_t* cut_edges, const ldd_options* opt, ldd_stats* stats, void* hip_stream);
