@@ -179,7 +179,11 @@ __global__ __launch_bounds__(ADM_T) void k_adm_load(AdmBatch b, int B, int max_r
 
 // One block per request: round offsets (wake_tab row of the slot, R + 1 entries) and the place
 // cursors from the counts (which are cleared for the next occupant), the slot's table entry,
-// the engine state's unsettled arcs, and the report (adm_err, then R).
+// the engine state's unsettled arcs, and the report (adm_err, then R).  The request's rounds
+// before its first non-empty one, fr, wake nobody: its origin moves fr rounds back (r0 - fr),
+// so that its first wakers wake in the first step after admission.  Its keys stay >= the round
+// of admission (every vertex with arcs has Delta - shift >= fr units), so nothing it writes is
+// settled before that step.
 __global__ __launch_bounds__(ADM_T) void k_adm_commit(AdmBatch b, int max_rounds, const u64* __restrict__ adm_max,
                                                       unsigned* __restrict__ adm_err, unsigned* __restrict__ cnt,
                                                       unsigned* __restrict__ cur, int* __restrict__ wake_tab,
@@ -187,6 +191,7 @@ __global__ __launch_bounds__(ADM_T) void k_adm_commit(AdmBatch b, int max_rounds
                                                       SlotState* __restrict__ sst, u64* __restrict__ s_cnt,
                                                       u64* __restrict__ s_lr, SlotReport* rep) {
   __shared__ unsigned part[ADM_T];
+  __shared__ int first_ne;
   const AdmItem& t = b.it[blockIdx.x];
   const u64 delta = adm_max[t.slot];
   const unsigned err = adm_err[t.slot];
@@ -197,9 +202,15 @@ __global__ __launch_bounds__(ADM_T) void k_adm_commit(AdmBatch b, int max_rounds
   const int per = (R + ADM_T - 1) / ADM_T;
   const int lo = threadIdx.x * per, hi = min(R, lo + per);
   unsigned s = 0;
-  for (int r = lo; r < hi; ++r) s += crow[r];
+  int fr = R;
+  for (int r = lo; r < hi; ++r) {
+    s += crow[r];
+    if (crow[r] && fr == R) fr = r;
+  }
+  if (threadIdx.x == 0) first_ne = R;
   part[threadIdx.x] = s;
   __syncthreads();
+  if (fr < R) atomicMin(&first_ne, fr);
   if (threadIdx.x == 0) {
     unsigned acc = 0;
     for (int i = 0; i < ADM_T; ++i) {
@@ -226,7 +237,7 @@ __global__ __launch_bounds__(ADM_T) void k_adm_commit(AdmBatch b, int max_rounds
     e.delta = delta;
     e.nnz = t.nnz;
     e.vbeg = t.vbeg;
-    e.r0 = t.r0;
+    e.r0 = t.r0 - (first_ne < R ? first_ne : 0);
     e.R = R;
     e.wbase = t.slot * (max_rounds + 1);
     e.active = R > 0;
