@@ -286,95 +286,137 @@ __device__ __forceinline__ void phase_top_down(const RoundCtx& c, int k, const i
   }
 }
 
-// ---- bottom-up: vertices not settled before round r pull from their neighbours in F_{r-1} ---
-// A neighbour u is in F_{r-1} iff its label lies in [base(r-1), base(r)).  L_r (the smallest
-// offer F_{r-1} makes) ends the scan as soon as it is attained.
-__device__ __forceinline__ void phase_bottom_up(const RoundCtx& c, int r, int k, u64 Lr, AppendBuf& ab, u64& wmin, u64& examined) {
-  const int B = c.B;
-  const u64 unit = (u64)1 << (FIX + B);
-  const u64 base_r = (u64)r << (FIX + B);
-  const u64 prev_round = (u64)(r - 1);
-  for (long long base = (long long)blockIdx.x * RT; base < c.n; base += (long long)gridDim.x * RT) {
-    const long long vi = base + threadIdx.x;
-    bool want = false;
-    unsigned deg = 0;
-    const int v = (int)vi;
-    if (vi < c.n) {
-      const u64 pv = c.P[v];
-      if (pv >= base_r && pv > Lr) {
-        const int a0 = c.row_ptr[v], a1 = c.row_ptr[v + 1];
-        u64 best = pv;
-        for (int a = a0; a < a1; ++a) {
-          ++examined;
-          const int u = c.col[a];
-          if ((unsigned)u >= (unsigned)c.n) {
-            atomic_or_u32(&c.ctrl->err, ERR_BAD_COL);
-            break;
-          }
-          const u64 pu = load_u64_relaxed(&c.P[u]);
-          if ((pu >> (FIX + B)) == prev_round && pu != INF) {
-            const u64 offer = pu + unit;
-            if (offer < best) best = offer;
-            if (best <= Lr) break;
-          }
-        }
-        if (best < pv) {
-          const u64 old = atomic_min_u64(&c.P[v], best);
-          if (old > best) {
-            wmin = best < wmin ? best : wmin;
-            if (old == INF) {
-              want = true;
-              deg = (unsigned)(a1 - a0);
-            }
-          }
-        }
+// ---- pull: bottom-up rounds and the tail seed -------------------------------------------
+// Bottom-up round r: every vertex not settled before r pulls the best offer of its neighbours
+// in F_{r-1} (a neighbour u is in F_{r-1} iff its label lies in [base(r-1), base(r))), stopping
+// as soon as the offer reaches L_r, the smallest offer F_{r-1} makes.
+// Tail seed (SEED): every vertex not settled before round r takes the best of its own arc and
+// the offers of its neighbours in F_{r-1} (the only settled vertices whose offers have not been
+// propagated yet); the sweeps then relax to the fixpoint.
+// A thread scans its vertex's row for up to PULL_CAP arcs.  Rows still undecided after that
+// are finished by their whole wave, one at a time, 64 arcs per pass with a wave minimum and the
+// same stop at L_r: a high-degree vertex no longer holds its wave for a serial scan of its row.
+constexpr int PULL_CAP = 16;
+
+// A pulled vertex v whose best offer is below its label: the label drops (atomic minimum);
+// bottom-up queues v if it was not reached before, the seed if it is not queued yet.
+template <bool SEED>
+__device__ __forceinline__ void pull_update(const RoundCtx& c, int v, u64 best, int degree, u64& wmin, bool& want,
+                                            unsigned& deg) {
+  if (SEED) {
+    atomic_min_u64(&c.P[v], best);
+    want = __hip_atomic_fetch_max(&c.stamp[v], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < 1u;
+    deg = (unsigned)degree;
+  } else {
+    const u64 old = atomic_min_u64(&c.P[v], best);
+    if (old > best) {
+      wmin = best < wmin ? best : wmin;
+      if (old == INF) {
+        want = true;
+        deg = (unsigned)degree;
       }
     }
-    block_append(ab, want, v, deg, c, k);
   }
 }
 
-// ---- tail seed: every vertex not settled before round r takes the best of its own arc and
-// the offers of its neighbours in F_{r-1} (the only settled vertices whose offers have not
-// been propagated yet); the sweeps then relax to the fixpoint.  Pulling touches only the
-// rows of unsettled vertices, which are few when the tail starts.
-__device__ __forceinline__ void phase_tail_seed(const RoundCtx& c, int r, int k, u64 Lr, AppendBuf& ab,
-                                                u64& examined) {
+// The rows the lanes in `rows` left undecided, each finished by the whole wave in turn: 64 arcs
+// per pass, a wave minimum, the stop at L_r.  A listed lane's next arc, row end and best offer
+// so far are in the step's LDS windows at its thread index (free during a pull); its best offer
+// comes back there.  Out of line: it is the rare path, and inlined it costs the common path
+// registers.  Returns the arcs read (in lane 0).
+__device__ __attribute__((noinline)) unsigned pull_rows_wave(const RoundCtx& c, u64 rows, unsigned* w_a, int* w_a1,
+                                                             u64* w_best, u64 Lr, int r) {
+  unsigned examined = 0;
+  const int B = c.B;
+  const u64 unit = (u64)1 << (FIX + B);
+  const u64 prev_round = (u64)(r - 1);
+  const unsigned lane = lane_id(), wave0 = threadIdx.x - lane;
+  for (; rows; rows &= rows - 1) {
+    const int src = __ffsll((long long)rows) - 1;
+    int ra = (int)w_a[wave0 + src];
+    const int ra1 = w_a1[wave0 + src];
+    u64 rb = w_best[wave0 + src];
+    while (ra < ra1 && rb > Lr) {  // uniform over the wave
+      const int ai = ra + (int)lane;
+      u64 mine = INF;
+      bool bad = false;
+      if (ai < ra1) {
+        const int u = c.col[ai];
+        bad = (unsigned)u >= (unsigned)c.n;
+        if (!bad) {
+          const u64 pu = load_u64_relaxed(&c.P[u]);
+          if ((pu >> (FIX + B)) == prev_round && pu != INF) mine = pu + unit;
+        }
+      }
+      if (lane == 0) examined += (unsigned)min(ra1 - ra, WAVE);
+      if (__ballot(bad)) {
+        if (lane == 0) atomic_or_u32(&c.ctrl->err, ERR_BAD_COL);
+        break;
+      }
+      const u64 wm = wave_min_u64(mine);
+      rb = wm < rb ? wm : rb;
+      ra += WAVE;
+    }
+    if ((int)lane == src) w_best[wave0 + src] = rb;
+  }
+  return examined;
+}
+
+template <bool SEED>
+__device__ __forceinline__ void phase_pull(const RoundCtx& c, int r, int k, u64 Lr, AppendBuf& ab, StepShared& sh,
+                                           u64& wmin, u64& examined_total) {
+  unsigned examined = 0;
   const int B = c.B;
   const u64 unit = (u64)1 << (FIX + B);
   const u64 base_r = (u64)r << (FIX + B);
   const u64 prev_round = (u64)(r - 1);
   for (long long base = (long long)blockIdx.x * RT; base < c.n; base += (long long)gridDim.x * RT) {
     const long long vi = base + threadIdx.x;
-    bool want = false;
-    unsigned deg = 0;
     const int v = (int)vi;
+    bool want = false, defer = false;
+    unsigned deg = 0;
     if (vi < c.n) {
       const u64 pv = c.P[v];
-      if (pv >= base_r) {
+      if (pv >= base_r && (SEED || pv > Lr)) {
         const int a0 = c.row_ptr[v], a1 = c.row_ptr[v + 1];
-        deg = (unsigned)(a1 - a0);
-        if (deg > 0) {
-          u64 best = own_offer(c, v);
-          for (int a = a0; a < a1 && best > Lr; ++a) {
+        if (!SEED || a1 > a0) {
+          u64 best = SEED ? own_offer(c, v) : pv;
+          int a = a0;
+          bool bad = false;
+          const int a_cap = a1 - a0 > PULL_CAP ? a0 + PULL_CAP : a1;
+          for (; a < a_cap && best > Lr; ++a) {
             ++examined;
             const int u = c.col[a];
             if ((unsigned)u >= (unsigned)c.n) {
               atomic_or_u32(&c.ctrl->err, ERR_BAD_COL);
+              bad = true;
               break;
             }
             const u64 pu = load_u64_relaxed(&c.P[u]);
             if ((pu >> (FIX + B)) == prev_round && pu != INF && pu + unit < best) best = pu + unit;
           }
-          if (best < pv) {
-            atomic_min_u64(&c.P[v], best);
-            want = __hip_atomic_fetch_max(&c.stamp[v], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < 1u;
+          if (!bad && a < a1 && best > Lr) {  // long row, undecided: the wave finishes it below
+            defer = true;
+            sh.w_pre[threadIdx.x] = (unsigned)a;
+            sh.w_first[threadIdx.x] = a1;
+            sh.w_offer[threadIdx.x] = best;
+          } else if (best < pv) {
+            pull_update<SEED>(c, v, best, a1 - a0, wmin, want, deg);
           }
         }
       }
     }
+    const u64 m = __ballot(defer);
+    if (m) {
+      examined += pull_rows_wave(c, m, sh.w_pre, sh.w_first, sh.w_offer, Lr, r);
+      if (defer) {
+        const u64 best = sh.w_offer[threadIdx.x];
+        if (best < c.P[v]) pull_update<SEED>(c, v, best, c.row_ptr[v + 1] - c.row_ptr[v], wmin, want, deg);
+      }
+    }
     block_append(ab, want, v, deg, c, k);
   }
+  examined_total += examined;
 }
 
 // Direction of the next round.  Top-down touches every arc of the frontier (random accesses);
@@ -581,7 +623,7 @@ __device__ __forceinline__ int round_step(const RoundCtx& c, int k, AppendBuf& a
     phase_wake(c, r, k, ab, wmin);
     if (nf) {
       if (dir == DIR_BU) {
-        phase_bottom_up(c, r, k, sh.lr, ab, wmin, examined);
+        phase_pull<false>(c, r, k, sh.lr, ab, sh, wmin, examined);
       } else {
         phase_top_down<false>(c, k, qv, qa, nf, af, ab, sh, wmin, 0);
         if (blockIdx.x == 0 && threadIdx.x == 0) examined += af;
@@ -590,7 +632,8 @@ __device__ __forceinline__ int round_step(const RoundCtx& c, int k, AppendBuf& a
   } else {
     const unsigned sweep = (unsigned)round;
     if (sweep == 0) {
-      phase_tail_seed(c, __builtin_amdgcn_readfirstlane((int)sh.S.tail_round), k, nf ? sh.lr : INF, ab, examined);
+      phase_pull<true>(c, __builtin_amdgcn_readfirstlane((int)sh.S.tail_round), k, nf ? sh.lr : INF, ab, sh, wmin,
+                       examined);
     } else if (nf) {
       phase_top_down<true>(c, k, qv, qa, nf, af, ab, sh, wmin, sweep);
       if (blockIdx.x == 0 && threadIdx.x == 0) examined += af;
@@ -672,6 +715,7 @@ struct SrvShared {
   int pull_off[MAX_SLOTS + 1];
   unsigned td_off[MAX_SLOTS + 1];  // prefix of the top-down slots' frontier arcs
   unsigned start;
+  int pslot[RT];  // pull: slot of a thread's row left to its wave
 };
 
 // Reserve the buffered appends in their slots' queues of step k and copy them there.
@@ -1046,7 +1090,72 @@ __device__ __forceinline__ void srv_top_down(const RoundCtx& c, int k, SrvAppend
 
 // Pull over the vertex ranges of the slots that go bottom-up (each with its own L_r) or take
 // their tail seed this step (own arc, whatever its wake round, and offers from F_{r-1}).
-__device__ __forceinline__ void srv_pull(const RoundCtx& c, int r, int k, SrvAppend& ab, SrvShared& ss) {
+// The rows the lanes in `rows` left undecided (as in the single-graph pull, the row state in
+// the step's LDS windows at the thread index, the slot beside it), each finished by the whole
+// wave in turn with its slot's CSR, id range and L_r.
+__device__ __attribute__((noinline)) void srv_pull_rows_wave(const RoundCtx& c, u64 rows, unsigned* w_a, int* w_a1,
+                                                             u64* w_best, const int* w_slot, const SrvShared& ss,
+                                                             int r) {
+  const int B = c.B;
+  const u64 unit = (u64)1 << (FIX + B);
+  const u64 prev_round = (u64)(r - 1);
+  const unsigned lane = lane_id(), wave0 = threadIdx.x - lane;
+  for (; rows; rows &= rows - 1) {
+    const int src = __ffsll((long long)rows) - 1;
+    const int s = w_slot[wave0 + src];
+    const int* col = ss.col[s];
+    const long long vbeg = ss.vbeg[s];
+    const unsigned n = (unsigned)ss.n[s];
+    const u64 Lr = ss.L[s];
+    int ra = (int)w_a[wave0 + src];
+    const int ra1 = w_a1[wave0 + src];
+    u64 rb = w_best[wave0 + src];
+    while (ra < ra1 && rb > Lr) {  // uniform over the wave
+      const int ai = ra + (int)lane;
+      u64 mine = INF;
+      bool bad = false;
+      if (ai < ra1) {
+        const int ul = col[ai];
+        bad = (unsigned)ul >= n;
+        if (!bad) {
+          const u64 pu = load_u64_relaxed(&c.P[vbeg + ul]);
+          if ((pu >> (FIX + B)) == prev_round && pu != INF) mine = pu + unit;
+        }
+      }
+      if (__ballot(bad)) {
+        if (lane == 0) atomic_or_u32(&c.slot_err[s], ERR_BAD_COL);
+        break;
+      }
+      const u64 wm = wave_min_u64(mine);
+      rb = wm < rb ? wm : rb;
+      ra += WAVE;
+    }
+    if ((int)lane == src) w_best[wave0 + src] = rb;
+  }
+}
+
+// A pulled vertex whose best offer is below its label: the label drops; a bottom-up vertex is
+// queued if it was not reached before, a seeded one if it is not queued in this step yet.
+__device__ __forceinline__ void srv_pull_update(const RoundCtx& c, int k, int v, bool seed, u64 best, unsigned degree,
+                                                bool& wrote, bool& want, unsigned& deg) {
+  if (seed) {
+    atomic_min_u64(&c.P[v], best);
+    wrote = true;
+    want = __hip_atomic_fetch_max(&c.stamp[v], (unsigned)k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (unsigned)k;
+    deg = degree;
+  } else {
+    const u64 old = atomic_min_u64(&c.P[v], best);
+    if (old > best) {
+      wrote = true;
+      if (old == INF) {
+        want = true;
+        deg = degree;
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void srv_pull(const RoundCtx& c, int r, int k, SrvAppend& ab, StepShared& sh, SrvShared& ss) {
   const int B = c.B;
   const u64 unit = (u64)1 << (FIX + B);
   const u64 base_r = (u64)r << (FIX + B);
@@ -1054,7 +1163,7 @@ __device__ __forceinline__ void srv_pull(const RoundCtx& c, int r, int k, SrvApp
   const int cnt = ss.pull_off[MAX_SLOTS];
   for (long long base = (long long)blockIdx.x * RT; base < cnt; base += (long long)gridDim.x * RT) {
     const long long i = base + threadIdx.x;
-    bool want = false, wrote = false;
+    bool want = false, wrote = false, defer = false;
     int v = 0, slot = 0;
     unsigned deg = 0;
     u64 best = INF;
@@ -1074,54 +1183,45 @@ __device__ __forceinline__ void srv_pull(const RoundCtx& c, int r, int k, SrvApp
       const int* col = ss.col[lo];
       const long long vbeg = ss.vbeg[lo];
       const unsigned n = (unsigned)ss.n[lo];
-      if (pv >= base_r) {
+      const bool seed = ss.seed[lo];
+      if (pv >= base_r && (seed || pv > Lr)) {
         const int a0 = rp[lv], a1 = rp[lv + 1];
-        if (ss.seed[lo]) {
-          if (a1 > a0) {
-            best = srv_own_offer(c, ss, lo, v);
-            for (int a = a0; a < a1 && best > Lr; ++a) {
-              const int ul = col[a];
-              if ((unsigned)ul >= n) {
-                atomic_or_u32(&c.slot_err[lo], ERR_BAD_COL);
-                break;
-              }
-              const u64 pu = load_u64_relaxed(&c.P[vbeg + ul]);
-              if ((pu >> (FIX + B)) == prev_round && pu != INF && pu + unit < best) best = pu + unit;
-            }
-            if (best < pv) {
-              atomic_min_u64(&c.P[v], best);
-              wrote = true;
-              want = __hip_atomic_fetch_max(&c.stamp[v], (unsigned)k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
-                     (unsigned)k;
-              deg = (unsigned)(a1 - a0);
-            }
-          }
-        } else if (pv > Lr) {
-          best = pv;
-          for (int a = a0; a < a1; ++a) {
+        if (!seed || a1 > a0) {
+          best = seed ? srv_own_offer(c, ss, lo, v) : pv;
+          int a = a0;
+          bool bad = false;
+          const int a_cap = a1 - a0 > PULL_CAP ? a0 + PULL_CAP : a1;
+          for (; a < a_cap && best > Lr; ++a) {
             const int ul = col[a];
             if ((unsigned)ul >= n) {
               atomic_or_u32(&c.slot_err[lo], ERR_BAD_COL);
+              bad = true;
               break;
             }
             const u64 pu = load_u64_relaxed(&c.P[vbeg + ul]);
-            if ((pu >> (FIX + B)) == prev_round && pu != INF) {
-              const u64 offer = pu + unit;
-              if (offer < best) best = offer;
-              if (best <= Lr) break;
-            }
+            if ((pu >> (FIX + B)) == prev_round && pu != INF && pu + unit < best) best = pu + unit;
           }
-          if (best < pv) {
-            const u64 old = atomic_min_u64(&c.P[v], best);
-            if (old > best) {
-              wrote = true;
-              if (old == INF) {
-                want = true;
-                deg = (unsigned)(a1 - a0);
-              }
-            }
+          if (!bad && a < a1 && best > Lr) {  // long row, undecided: the wave finishes it below
+            defer = true;
+            sh.w_pre[threadIdx.x] = (unsigned)a;
+            sh.w_first[threadIdx.x] = a1;
+            sh.w_offer[threadIdx.x] = best;
+            ss.pslot[threadIdx.x] = lo;
+          } else if (best < pv) {
+            srv_pull_update(c, k, v, seed, best, (unsigned)(a1 - a0), wrote, want, deg);
           }
         }
+      }
+    }
+    const u64 m = __ballot(defer);
+    if (m) {
+      srv_pull_rows_wave(c, m, sh.w_pre, sh.w_first, sh.w_offer, ss.pslot, ss, r);
+      if (defer) {
+        best = sh.w_offer[threadIdx.x];
+        const long long lv = v - ss.vbeg[slot];
+        if (best < c.P[v])
+          srv_pull_update(c, k, v, ss.seed[slot], best, (unsigned)(ss.rp[slot][lv + 1] - ss.rp[slot][lv]), wrote, want,
+                          deg);
       }
     }
     srv_note_lr(ss, wrote, slot, best);
@@ -1148,7 +1248,7 @@ __device__ __forceinline__ void srv_step(const RoundCtx& c, int k, SrvAppend& ab
   if (blockIdx.x == 0 && threadIdx.x == 0) store_state<__HIP_MEMORY_SCOPE_AGENT>(&c.st[k & 1], sh.S);
   srv_wake(c, r, k, ab, ss);
   srv_top_down(c, k, ab, sh, ss);
-  if (ss.pull_off[MAX_SLOTS]) srv_pull(c, r, k, ab, ss);
+  if (ss.pull_off[MAX_SLOTS]) srv_pull(c, r, k, ab, sh, ss);
   srv_flush(ab, c, k, ss);
   if (threadIdx.x < MAX_SLOTS && threadIdx.x < c.nslots && ss.lr[threadIdx.x] != INF)
     atomic_min_u64(&c.s_lr[(k % 3) * MAX_SLOTS + threadIdx.x], ss.lr[threadIdx.x]);
