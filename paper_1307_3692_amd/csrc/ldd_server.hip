@@ -326,10 +326,13 @@ __global__ __launch_bounds__(FIN_T) void k_fin_vertices(FinBatch b, int B, const
     bool out = false;
     unsigned deg = 0;
     bool inH = false;
+    // loads first, at an index clamped into the chunk, so that they need no branch
+    const long long vc = v < hi ? v : hi - 1;
+    const u64 c = P[t.vbeg + vc] & mask;
+    const int r0 = t.rp[vc], r1 = t.rp[vc + 1];
     if (v < hi) {
-      const u64 c = P[t.vbeg + v] & mask;
       t.centre[v] = ran ? (int)(c - (u64)t.vbeg) : -1;
-      deg = (unsigned)(t.rp[v + 1] - t.rp[v]);
+      deg = (unsigned)(r1 - r0);
       inH = c == hubc;
       out = ran && !inH && deg > 0;
     }
@@ -864,11 +867,11 @@ ldd_status srv_finish(ldd_server* srv, const std::vector<Request*>& rs) {
       t.n = r->q.n;
       t.slot = r->slot;
       t.blk0 = nv;
-      t.nblk = (int)std::max<long long>(1, std::min<long long>(1024, ((long long)r->q.n + 16383) / 16384));
+      t.nblk = (int)std::max<long long>(1, std::min<long long>(4096, ((long long)r->q.n + 2047) / 2048));
       nv += t.nblk;
       fv.it[fv.count++] = t;
       t.blk0 = nc;
-      t.nblk = (int)std::max<long long>(1, std::min<long long>(1024, r->q.nnz / 65536));
+      t.nblk = (int)std::max<long long>(1, std::min<long long>(4096, r->q.nnz / 8192));
       nc += t.nblk;
       fc.it[fc.count++] = t;
       r->state = RQ_FINISHING;
