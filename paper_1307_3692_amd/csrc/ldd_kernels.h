@@ -65,7 +65,7 @@ struct SlotInfo {
   long long r0;     // global round of the request's round 0
   long long nnz;
   int R;            // the request's rounds (its wake rounds are r0 .. r0 + R - 1)
-  int wbase;        // its round offsets start at wake_tab[wbase] (R + 1 entries)
+  int wbase;        // its rows of wake_tab (bucket offsets, R + 1) and wake_cur (splits, R)
   int active;
   int n;            // the request's vertices
 };
@@ -123,7 +123,8 @@ struct RoundCtx {
   // own mode and direction, and its frontier queued in its own vertex range of qv / qa
   const SlotInfo* slots;
   int nslots;
-  const int* wake_tab;
+  const int* wake_tab;          // per slot: first wake_ord entry of each shift bucket q, then the total
+  const u64* wake_cur;          // per slot: low half = end of bucket q's wakers of round D - q
   SlotState* sst;              // [2][MAX_SLOTS]
   u64* s_cnt;                  // [3][MAX_SLOTS]: (count << 32 | arcs) queued by step k, at k % 3
   u64* s_lr;                   // [3][MAX_SLOTS]: smallest label written by step k, at k % 3

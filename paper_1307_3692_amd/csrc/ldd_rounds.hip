@@ -918,7 +918,8 @@ __device__ __forceinline__ void srv_slot_setup(const RoundCtx& c, int k, int r, 
 }
 
 // Wake: for every slot in rounds mode with r0 <= r < r0 + R, the vertices of its local round
-// r - r0 (a segment of its part of wake_ord) take their own arc.
+// rho = r - r0 take their own arc: the back of shift bucket D - rho - 1 and the front of bucket
+// D - rho (D = R - 1), one range of its part of wake_ord.
 __device__ __forceinline__ void srv_wake(const RoundCtx& c, int r, int k, SrvAppend& ab, SrvShared& ss) {
   if (threadIdx.x < WAVE) {
     const int t = threadIdx.x;
@@ -928,8 +929,10 @@ __device__ __forceinline__ void srv_wake(const RoundCtx& c, int r, int k, SrvApp
       const SlotInfo sl = c.slots[t];
       const long long rho = (long long)r - sl.r0;
       if (rho >= 0 && rho < sl.R) {
-        const int lo = c.wake_tab[sl.wbase + rho], hi = c.wake_tab[sl.wbase + rho + 1];
-        len = hi - lo;
+        const long long q = sl.R - 1 - rho;
+        const unsigned hi = (unsigned)c.wake_cur[sl.wbase + q];
+        const unsigned lo = q > 0 ? (unsigned)c.wake_cur[sl.wbase + q - 1] : 0u;
+        len = (int)(hi - lo);
         beg = sl.vbeg + lo;
       }
     }

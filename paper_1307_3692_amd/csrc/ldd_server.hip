@@ -97,6 +97,7 @@ __device__ __forceinline__ int request_rounds(u64 delta, unsigned err, int max_r
   return ((err & ROW_ERRS) == 0 && R <= (u64)max_rounds) ? (int)R : 0;
 }
 
+// the block's maximum (or error bits), in thread 0 only
 __device__ __forceinline__ u64 block_max_or(u64 v, u64* red, bool is_or) {
   if (is_or) {
     v = wave_max_u64(v & ERR_BAD_SHIFT) | wave_max_u64(v & ERR_BAD_ROWPTR);
@@ -113,25 +114,43 @@ __device__ __forceinline__ u64 block_max_or(u64 v, u64* red, bool is_or) {
 }
 
 // ------------------------------------------------------------------------------------------
-// admission: check -> load (+ round histogram) -> commit (round offsets, slot entry) -> place
+// admission: scan (checks, labels, bucket histogram) -> commit (bucket offsets, slot entry)
+// -> place
 // ------------------------------------------------------------------------------------------
-// Rows non-decreasing from 0 to nnz, shifts in [0, 2^52]; the request's max shift.
-// Also the request's hub, (degree << 32 | id) of a vertex of largest degree, for the cut.
-__global__ __launch_bounds__(ADM_T) void k_adm_check(AdmBatch b, u64* __restrict__ adm_max,
-                                                     unsigned* __restrict__ adm_err, u64* __restrict__ adm_hub) {
+// One pass over a request's rows and shifts: rows non-decreasing from 0 to nnz, shifts in
+// [0, 2^52], the request's max shift and hub ((degree << 32 | id) of a vertex of largest degree,
+// for the cut); labels INF (an isolated vertex keeps INF, which the finishing maps to the vertex
+// itself); and the vertices with arcs counted by the integer part q of their shift.  The wake
+// round of a vertex is D - q or D - q - 1 (D = Delta >> 20), depending on whether its shift's
+// fractional part exceeds Delta's, so the q-buckets need no Delta and give every round's
+// wakers in two adjacent segments.  Vertex n of the slot is settled (label 0).
+__global__ __launch_bounds__(ADM_T) void k_adm_scan(AdmBatch b, int max_rounds, u64* __restrict__ adm_max,
+                                                    unsigned* __restrict__ adm_err, u64* __restrict__ adm_hub,
+                                                    u64* __restrict__ P, unsigned* __restrict__ cnt) {
+  __shared__ unsigned h[QCAP];
   __shared__ u64 red[ADM_T / WAVE];
   const AdmItem& t = b.it[item_of(b, blockIdx.x)];
   const int j = blockIdx.x - t.blk0;
+  const int Q = max_rounds < QCAP ? max_rounds : QCAP;  // buckets a runnable request can have
+  for (int q = threadIdx.x; q < Q; q += ADM_T) h[q] = 0;
+  __syncthreads();
   const long long lo = chunk(t.n, j, t.nblk), hi = chunk(t.n, j + 1, t.nblk);
   u64 mx = 0, bad = 0, hub = 0;
   for (long long v = lo + threadIdx.x; v < hi; v += ADM_T) {
     const int a = t.rp[v], e = t.rp[v + 1];
+    const long long s = t.shift[v];
+    P[t.vbeg + v] = INF;
     if (e < a || (v == 0 && a != 0) || (v == t.n - 1 && (long long)e != t.nnz)) bad |= ERR_BAD_ROWPTR;
     else if (e > a && (((u64)(unsigned)(e - a) << 32) | (u64)v) > hub) hub = ((u64)(unsigned)(e - a) << 32) | (u64)v;
-    const long long s = t.shift[v];
-    if (s < 0 || s > (1ll << 52)) bad |= ERR_BAD_SHIFT;
-    else mx = (u64)s > mx ? (u64)s : mx;
+    if (s < 0 || s > (1ll << 52)) {
+      bad |= ERR_BAD_SHIFT;
+    } else {
+      mx = (u64)s > mx ? (u64)s : mx;
+      const u64 q = (u64)s >> FIX;
+      if (e > a && q < (u64)Q) atomicAdd(&h[q], 1u);  // a larger q: too many rounds to run anyway
+    }
   }
+  if (j == t.nblk - 1 && threadIdx.x == 0) P[t.vbeg + t.n] = 0;
   mx = block_max_or(mx, red, false);
   hub = block_max_or(hub, red, false);
   bad = block_max_or(bad, red, true);
@@ -140,95 +159,70 @@ __global__ __launch_bounds__(ADM_T) void k_adm_check(AdmBatch b, u64* __restrict
     if (hub) atomic_max_u64(&adm_hub[t.slot], hub);
     if (bad) atomic_or_u32(&adm_err[t.slot], (unsigned)bad);
   }
-}
-
-// The request's labels in the arena: INF for vertices with arcs, their own offer for isolated
-// ones (the own arc of local vertex v is Delta_g - shift[v] + r0 2^20: the request's source-arc
-// length raised by r0 units); the request's CSR and shifts stay in the caller's buffers.  Vertex
-// n of the slot is settled (label 0).  A request whose rows or shifts failed the check gets
-// settled labels only: it stays inert.  Also counts the request's vertices per wake round.
-__global__ __launch_bounds__(ADM_T) void k_adm_load(AdmBatch b, int B, int max_rounds, const u64* __restrict__ adm_max,
-                                                    const unsigned* __restrict__ adm_err, u64* __restrict__ P,
-                                                    unsigned* __restrict__ cnt) {
-  __shared__ unsigned h[QCAP];
-  const AdmItem& t = b.it[item_of(b, blockIdx.x)];
-  const int j = blockIdx.x - t.blk0;
-  const u64 delta = adm_max[t.slot];
-  const int R = request_rounds(delta, adm_err[t.slot], max_rounds);
-  for (int r = threadIdx.x; r < R; r += ADM_T) h[r] = 0;
-  __syncthreads();
-  const long long lo = chunk(t.n, j, t.nblk), hi = chunk(t.n, j + 1, t.nblk);
-  for (long long v = lo + threadIdx.x; v < hi; v += ADM_T) {
-    const long long g = t.vbeg + v;
-    if (R) {
-      const bool arcs = t.rp[v + 1] > t.rp[v];
-      const u64 sv = (u64)t.shift[v];
-      const u64 off = delta - sv + (u64)t.r0 * S_ONE;
-      P[g] = arcs ? INF : ((off << B) | (u64)g);
-      if (arcs) atomicAdd(&h[(delta - sv) >> FIX], 1u);
-    } else {
-      P[g] = 0;
-    }
-  }
-  if (j == t.nblk - 1 && threadIdx.x == 0) P[t.vbeg + t.n] = 0;
-  __syncthreads();
   unsigned* row = cnt + (size_t)t.slot * max_rounds;
-  for (int r = threadIdx.x; r < R; r += ADM_T)
-    if (h[r]) atomicAdd(&row[r], h[r]);
+  for (int q = threadIdx.x; q < Q; q += ADM_T)
+    if (h[q]) atomicAdd(&row[q], h[q]);
 }
 
-// One block per request: round offsets (wake_tab row of the slot, R + 1 entries) and the place
-// cursors from the counts (which are cleared for the next occupant), the slot's table entry,
-// the engine state's unsettled arcs, and the report (adm_err, then R).  The request's rounds
-// before its first non-empty one, fr, wake nobody: its origin moves fr rounds back (r0 - fr),
+// One block per request: bucket offsets (wake_tab row of the slot, indexed by q, R + 1 entries)
+// and the place cursors from the counts (the whole row of counts is cleared for the next
+// occupant; a cursor holds the bucket's next front position in its low half and the entries
+// placed from its end in its high half), the slot's table entry, the engine state's unsettled arcs, and the report
+// (adm_err, then R).  The request's rounds before its first possible waker, fr = D - q_max - 1
+// (q_max its highest non-empty bucket), wake nobody: its origin moves fr rounds back (r0 - fr),
 // so that its first wakers wake in the first step after admission.  Its keys stay >= the round
 // of admission (every vertex with arcs has Delta - shift >= fr units), so nothing it writes is
 // settled before that step.
 __global__ __launch_bounds__(ADM_T) void k_adm_commit(AdmBatch b, int max_rounds, const u64* __restrict__ adm_max,
                                                       unsigned* __restrict__ adm_err, unsigned* __restrict__ cnt,
-                                                      unsigned* __restrict__ cur, int* __restrict__ wake_tab,
+                                                      u64* __restrict__ cur, int* __restrict__ wake_tab,
                                                       SlotInfo* __restrict__ slots, RoundState* st, long long k_last,
                                                       SlotState* __restrict__ sst, u64* __restrict__ s_cnt,
                                                       u64* __restrict__ s_lr, SlotReport* rep) {
-  __shared__ unsigned part[ADM_T];
-  __shared__ int first_ne;
+  __shared__ unsigned w_sum[ADM_T / WAVE];
+  __shared__ int q_top;
   const AdmItem& t = b.it[blockIdx.x];
   const u64 delta = adm_max[t.slot];
   const unsigned err = adm_err[t.slot];
   const int R = request_rounds(delta, err, max_rounds);
   unsigned* crow = cnt + (size_t)t.slot * max_rounds;
-  unsigned* urow = cur + (size_t)t.slot * max_rounds;
+  u64* urow = cur + (size_t)t.slot * (max_rounds + 1);
   int* wrow = wake_tab + (size_t)t.slot * (max_rounds + 1);
-  const int per = (R + ADM_T - 1) / ADM_T;
-  const int lo = threadIdx.x * per, hi = min(R, lo + per);
+  // thread i takes buckets [i per, (i + 1) per) of the whole row (cleared), the first R counted
+  const int per = (max_rounds + ADM_T - 1) / ADM_T;
+  const int lo = threadIdx.x * per, hi = min(max_rounds, lo + per);
   unsigned s = 0;
-  int fr = R;
-  for (int r = lo; r < hi; ++r) {
-    s += crow[r];
-    if (crow[r] && fr == R) fr = r;
+  int top = -1;
+  for (int q = lo; q < hi; ++q) {
+    if (q < R) {
+      s += crow[q];
+      if (crow[q]) top = q;
+    }
   }
-  if (threadIdx.x == 0) first_ne = R;
-  part[threadIdx.x] = s;
+  if (threadIdx.x == 0) q_top = -1;
+  const unsigned lane = lane_id(), wid = threadIdx.x / WAVE;
+  const unsigned incl = wave_incl_scan(s);
+  if (lane == WAVE - 1) w_sum[wid] = incl;
   __syncthreads();
-  if (fr < R) atomicMin(&first_ne, fr);
-  if (threadIdx.x == 0) {
-    unsigned acc = 0;
-    for (int i = 0; i < ADM_T; ++i) {
-      const unsigned x = part[i];
-      part[i] = acc;
+  if (top >= 0) atomicMax(&q_top, top);
+  unsigned acc = incl - s, total = 0;
+  for (int w = 0; w < ADM_T / WAVE; ++w) {
+    if (w < (int)wid) acc += w_sum[w];
+    total += w_sum[w];
+  }
+  for (int q = lo; q < hi; ++q) {
+    if (q < R) {
+      const unsigned x = crow[q];
+      wrow[q] = (int)acc;
+      urow[q] = acc;
       acc += x;
     }
-    wrow[R] = (int)acc;
+    crow[q] = 0;
   }
+  if (threadIdx.x == 0 && R) wrow[R] = (int)total;
   __syncthreads();
-  unsigned acc = part[threadIdx.x];
-  for (int r = lo; r < hi; ++r) {
-    const unsigned x = crow[r];
-    wrow[r] = (int)acc;
-    urow[r] = acc;
-    crow[r] = 0;
-    acc += x;
-  }
+  const int D = R - 1;
+  const int first_ne = q_top >= 0 && D - q_top - 1 > 0 ? D - q_top - 1 : 0;
   if (threadIdx.x == 0) {
     SlotInfo e;
     e.rp = t.rp;
@@ -237,7 +231,7 @@ __global__ __launch_bounds__(ADM_T) void k_adm_commit(AdmBatch b, int max_rounds
     e.delta = delta;
     e.nnz = t.nnz;
     e.vbeg = t.vbeg;
-    e.r0 = t.r0 - (first_ne < R ? first_ne : 0);
+    e.r0 = t.r0 - first_ne;
     e.R = R;
     e.wbase = t.slot * (max_rounds + 1);
     e.active = R > 0;
@@ -261,29 +255,43 @@ __global__ __launch_bounds__(ADM_T) void k_adm_commit(AdmBatch b, int max_rounds
   }
 }
 
-// Each vertex with arcs to its wake round's segment of the slot's part of wake_ord.
+// Each vertex with arcs to its q-bucket's segment of the slot's part of wake_ord: to the front
+// of the segment if its shift's fractional part is at most Delta's (it wakes in round D - q),
+// to the back otherwise (round D - q - 1).  Buckets ascend, so the wakers of round rho are one
+// range, from the split of bucket D - rho - 1 to the split of bucket D - rho, and the split of
+// bucket q is the low half of its cursor once every block has placed its vertices.
 __global__ __launch_bounds__(ADM_T) void k_adm_place(AdmBatch b, int max_rounds, const u64* __restrict__ adm_max,
-                                                     const unsigned* __restrict__ adm_err, unsigned* __restrict__ cur,
-                                                     int* __restrict__ wake_ord) {
-  __shared__ unsigned h[QCAP];
+                                                     const unsigned* __restrict__ adm_err, u64* __restrict__ cur,
+                                                     const int* __restrict__ wake_tab, int* __restrict__ wake_ord) {
+  __shared__ unsigned hf[QCAP], hb[QCAP];
   const AdmItem& t = b.it[item_of(b, blockIdx.x)];
   const int j = blockIdx.x - t.blk0;
   const u64 delta = adm_max[t.slot];
   const int R = request_rounds(delta, adm_err[t.slot], max_rounds);
   if (R == 0) return;  // whole block leaves together
-  for (int r = threadIdx.x; r < R; r += ADM_T) h[r] = 0;
+  const u64 dfrac = delta & (S_ONE - 1);
+  for (int q = threadIdx.x; q < R; q += ADM_T) hf[q] = hb[q] = 0;
   __syncthreads();
   const long long lo = chunk(t.n, j, t.nblk), hi = chunk(t.n, j + 1, t.nblk);
   for (long long v = lo + threadIdx.x; v < hi; v += ADM_T)
-    if (t.rp[v + 1] > t.rp[v]) atomicAdd(&h[(delta - (u64)t.shift[v]) >> FIX], 1u);
+    if (t.rp[v + 1] > t.rp[v]) {
+      const u64 s = (u64)t.shift[v];
+      atomicAdd((s & (S_ONE - 1)) > dfrac ? &hb[s >> FIX] : &hf[s >> FIX], 1u);
+    }
   __syncthreads();
-  unsigned* urow = cur + (size_t)t.slot * max_rounds;
-  for (int r = threadIdx.x; r < R; r += ADM_T)
-    if (h[r]) h[r] = atomicAdd(&urow[r], h[r]);
+  u64* urow = cur + (size_t)t.slot * (max_rounds + 1);
+  const int* wrow = wake_tab + (size_t)t.slot * (max_rounds + 1);
+  for (int q = threadIdx.x; q < R; q += ADM_T)
+    if (hf[q] | hb[q]) {
+      const u64 old = atomicAdd((unsigned long long*)&urow[q], ((u64)hb[q] << 32) | hf[q]);
+      hf[q] = (unsigned)old;
+      hb[q] = (unsigned)wrow[q + 1] - (unsigned)(old >> 32) - hb[q];
+    }
   __syncthreads();
   for (long long v = lo + threadIdx.x; v < hi; v += ADM_T)
     if (t.rp[v + 1] > t.rp[v]) {
-      const unsigned pos = atomicAdd(&h[(delta - (u64)t.shift[v]) >> FIX], 1u);
+      const u64 s = (u64)t.shift[v];
+      const unsigned pos = atomicAdd((s & (S_ONE - 1)) > dfrac ? &hb[s >> FIX] : &hf[s >> FIX], 1u);
       wake_ord[t.vbeg + pos] = (int)(t.vbeg + v);
     }
 }
@@ -319,7 +327,8 @@ __global__ __launch_bounds__(FIN_T) void k_fin_vertices(FinBatch b, int B, const
   const u64 mask = ((u64)1 << B) - 1;
   const bool ran = slots[t.slot].active != 0;
   const long long lo = chunk64(t.n, j, t.nblk), hi = chunk64(t.n, j + 1, t.nblk);
-  const u64 hubc = P[t.vbeg + (long long)(adm_hub[t.slot] & 0xffffffffull)] & mask;
+  const long long hv = t.vbeg + (long long)(adm_hub[t.slot] & 0xffffffffull);
+  const u64 hubc = P[hv] == INF ? (u64)hv : (P[hv] & mask);
   const unsigned lane = lane_id(), wid = threadIdx.x / WAVE;
   for (long long v0 = lo; v0 < hi; v0 += FIN_T) {  // uniform trip count over the block
     const long long v = v0 + threadIdx.x;
@@ -328,7 +337,8 @@ __global__ __launch_bounds__(FIN_T) void k_fin_vertices(FinBatch b, int B, const
     bool inH = false;
     // loads first, at an index clamped into the chunk, so that they need no branch
     const long long vc = v < hi ? v : hi - 1;
-    const u64 c = P[t.vbeg + vc] & mask;
+    const u64 p = P[t.vbeg + vc];
+    const u64 c = p == INF ? (u64)(t.vbeg + vc) : (p & mask);  // INF: isolated, its own centre
     const int r0 = t.rp[vc], r1 = t.rp[vc + 1];
     if (v < hi) {
       t.centre[v] = ran ? (int)(c - (u64)t.vbeg) : -1;
@@ -680,7 +690,7 @@ ldd_status srv_setup(ldd_server* srv) {
       (s = srv_alloc(srv, &srv->qv1, V * 4)) || (s = srv_alloc(srv, &srv->qa0, V * 4)) ||
       (s = srv_alloc(srv, &srv->qa1, V * 4)) || (s = srv_alloc(srv, &srv->wake_ord, V * 4)) ||
       (s = srv_alloc(srv, &srv->wake_tab, per_slot * 4)) ||
-      (s = srv_alloc(srv, &srv->cnt, per_slot * 4)) || (s = srv_alloc(srv, &srv->cur, per_slot * 4)) ||
+      (s = srv_alloc(srv, &srv->cnt, per_slot * 4)) || (s = srv_alloc(srv, &srv->cur, per_slot * 8)) ||
       (s = srv_alloc(srv, &srv->slots, sizeof(SlotInfo) * MAX_SLOTS)) ||
       (s = srv_alloc(srv, &srv->st, 2 * sizeof(RoundState))) || (s = srv_alloc(srv, &srv->qcnt, 3 * 16 * 8)) ||
       (s = srv_alloc(srv, &srv->lr_part, 2 * (size_t)RT * 8)) ||
@@ -767,6 +777,7 @@ ldd_status srv_setup(ldd_server* srv) {
   c.slots = (const SlotInfo*)srv->slots;
   c.nslots = srv->cfg.max_slots;
   c.wake_tab = (const int*)srv->wake_tab;
+  c.wake_cur = (const u64*)srv->cur;
   c.sst = (SlotState*)srv->sst;
   c.s_cnt = (u64*)srv->s_cnt;
   c.s_lr = (u64*)srv->s_lr;
@@ -834,16 +845,15 @@ ldd_status srv_admit(ldd_server* srv, const std::vector<Request*>& rs) {
       nblk += t.nblk;
       rep_reset(srv, r->slot);
     }
-    hipLaunchKernelGGL(k_adm_check, dim3(nblk), dim3(ADM_T), 0, s, ab, (u64*)srv->adm_max, (unsigned*)srv->adm_err,
-                       (u64*)srv->adm_hub);
-    hipLaunchKernelGGL(k_adm_load, dim3(nblk), dim3(ADM_T), 0, s, ab, srv->B, srv->max_rounds,
-                       (const u64*)srv->adm_max, (const unsigned*)srv->adm_err, (u64*)srv->P, (unsigned*)srv->cnt);
+    hipLaunchKernelGGL(k_adm_scan, dim3(nblk), dim3(ADM_T), 0, s, ab, srv->max_rounds, (u64*)srv->adm_max,
+                       (unsigned*)srv->adm_err, (u64*)srv->adm_hub, (u64*)srv->P, (unsigned*)srv->cnt);
     hipLaunchKernelGGL(k_adm_commit, dim3(ab.count), dim3(ADM_T), 0, s, ab, srv->max_rounds,
                        (const u64*)srv->adm_max, (unsigned*)srv->adm_err, (unsigned*)srv->cnt,
-                       (unsigned*)srv->cur, (int*)srv->wake_tab, (SlotInfo*)srv->slots, (RoundState*)srv->st,
+                       (u64*)srv->cur, (int*)srv->wake_tab, (SlotInfo*)srv->slots, (RoundState*)srv->st,
                        srv->steps, (SlotState*)srv->sst, (u64*)srv->s_cnt, (u64*)srv->s_lr, srv->rep_dev);
     hipLaunchKernelGGL(k_adm_place, dim3(nblk), dim3(ADM_T), 0, s, ab, srv->max_rounds, (const u64*)srv->adm_max,
-                       (const unsigned*)srv->adm_err, (unsigned*)srv->cur, (int*)srv->wake_ord);
+                       (const unsigned*)srv->adm_err, (u64*)srv->cur, (const int*)srv->wake_tab,
+                       (int*)srv->wake_ord);
     SRV_TRY(hipGetLastError());
   }
   return LDD_OK;

@@ -115,6 +115,23 @@ def test_medium_workloads_vs_oracle(ldd, name):
         assert cut == want_cut
 
 
+def test_pull_rows_finished_by_waves(ldd):
+    """An RMAT graph and shifts on which the bottom-up early exit rarely fires (several centres'
+    waves meet): most pulled rows run past the per-thread cap and are finished by their wave.
+    Every schedule still gives the oracle's bits."""
+    rp, ci = inputs.rmat(19, 16, seed=1019)
+    s = inputs.make_shifts(rp.size - 1, 0.1, 1044)
+    t = time.time()
+    want_c, _, want_cut = oracle.decompose(rp, ci, s)
+    log(f"rmat-19 beta 0.1: n={rp.size - 1} nnz={ci.size} oracle {time.time() - t:.2f}s")
+    for mode in (dict(), dict(direction=2), dict(tail_vertices=1), dict(engine=1)):
+        got, cut, st = run(ldd, rp, ci, s, 0.1, **mode)
+        log(f"  {mode}: arcs examined / arcs {st['arcs_examined'] / ci.size:.3f}")
+        assert np.array_equal(got, want_c), (mode, np.count_nonzero(got != want_c))
+        assert cut == want_cut
+    assert st["arcs_examined"] > ci.size // 4  # the long-row path was exercised
+
+
 @pytest.mark.parametrize("kind,n", [("er", 3000), ("rgg", 5000), ("er", 150_000), ("rgg", 200_000)])
 def test_batch_graph_kinds_vs_oracle(ldd, kind, n):
     rp, ci = inputs.er(n, 8.0, 77) if kind == "er" else inputs.rgg(n, 6.0, 77)
