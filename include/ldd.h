@@ -78,7 +78,7 @@ typedef struct {
   int32_t td_to_bu;       /* switch to bottom-up when frontier arcs * td_to_bu > unsettled arcs (0 = default 14) */
   int32_t bu_to_td;       /* switch back when frontier vertices * bu_to_td < n (0 = default 24)                 */
   int32_t tail_vertices;  /* finish by label correction once unsettled vertices * this <= active vertices
-                             (0 = default 64, -1 = never)                                                      */
+                             (0 = default 32, -1 = never)                                                      */
   int32_t batch_mode;     /* ldd_decompose_batch: LDD_BATCH_UNION (one launch per round for all graphs)  */
                           /* or LDD_BATCH_SEQUENTIAL (one ldd_decompose per graph, for comparison)      */
   int32_t reserved[8];
@@ -192,7 +192,7 @@ typedef struct {
   int32_t max_rounds;       /* testing: key range in rounds before keys are rebased (0 = the      */
                             /* largest the label width allows); requests may need at most half   */
   int32_t tail_vertices;    /* a request finishes by label correction once its unreached         */
-                            /* vertices * this <= its vertices with arcs (0 = 64, -1 = never)     */
+                            /* vertices * this <= its vertices with arcs (0 = 32, -1 = never)     */
   int32_t reserved[6];
 } ldd_server_config;
 

@@ -83,7 +83,6 @@ struct HostMirror {  // pinned, mapped host memory
   Ctrl ctrl;
   u64 ex_part[RT];
   Report report;   // written by the device as a decomposition ends
-  LaunchBlock lb;  // staging for the device copy
 };
 
 constexpr int CHUNK = 8;     // steps per graph replay
@@ -97,6 +96,8 @@ struct StepGraph {
 struct Workspace {
   std::mutex mu;
   Buf P, qv0, qv1, qa0, qa1, wake_ord, stamp, hub_bits;  // per vertex
+  unsigned stamp_base = 0;     // every tail stamp in `stamp` is <= stamp_base ...
+  void* stamp_clean = nullptr;  // ... while this equals stamp.p
   Buf hist, cursor, wake_off, next_ne, mat, qmax;        // per round / q-bucket (mat: per bucket and prep block)
   Buf cand, cand_cnt;                                    // per prep block: first-window candidates
   Buf ctrl, st, qcnt, lr_part, lb, ex_part;
@@ -367,10 +368,15 @@ static ldd_status decompose_run(Workspace& w, const ldd_csr* g, const int64_t* s
   }
   HIP_TRY(hipGetLastError());
 
-  const int tail_den = o.tail_vertices < 0 ? 0 : (o.tail_vertices > 0 ? o.tail_vertices : 64);
-  if (tail_den) HIP_TRY(hipMemsetAsync(w.stamp.p, 0, nv * 4, st));
-  HIP_TRY(hipMemsetAsync(w.qcnt.p, 0, 3 * 16 * sizeof(u64), st));
-  HIP_TRY(hipMemsetAsync(w.ex_part.p, 0, (size_t)RT * sizeof(u64), st));
+  const int tail_den = o.tail_vertices < 0 ? 0 : (o.tail_vertices > 0 ? o.tail_vertices : 32);
+  // tail stamps: cleared only when the buffer is new, was left in an unknown state, or the
+  // base has come within 2^30 of wrapping; otherwise this call's tags lie above every old one
+  if (tail_den && (w.stamp_clean != w.stamp.p || w.stamp_base >= (1u << 30))) {
+    HIP_TRY(hipMemsetAsync(w.stamp.p, 0, w.stamp.bytes, st));
+    w.stamp_base = 0;
+  }
+  const unsigned stamp_base = w.stamp_base;
+  w.stamp_clean = nullptr;  // unknown until this call's steps are counted
 
   // round arguments; Delta, the rounds bound and the vertices with arcs are filled in by k_setup
   RoundCtx c{};
@@ -395,6 +401,7 @@ static ldd_status decompose_run(Workspace& w, const ldd_csr* g, const int64_t* s
   c.qcnt = (u64*)w.qcnt.p;
   c.lr_part = (u64*)w.lr_part.p;
   c.stamp = (unsigned*)w.stamp.p;
+  c.stamp_base = stamp_base;
   c.st = (RoundState*)w.st.p;
   c.ctrl = ctrl;
   c.dir_policy = o.direction;
@@ -419,11 +426,7 @@ static ldd_status decompose_run(Workspace& w, const ldd_csr* g, const int64_t* s
   long long steps = 0;
   hipGraphExec_t exec = nullptr;
   if (engine != LDD_ENGINE_PERSISTENT && (s = step_graph(w, blocks, &exec))) return s;
-  w.host->lb.c = c;
-  w.host->lb.kbase = 1;
-  HIP_TRY(hipMemcpyAsync(w.lb.p, &w.host->lb, sizeof(LaunchBlock), hipMemcpyHostToDevice, st));
-  hipLaunchKernelGGL(k_setup, dim3(1), dim3(64), 0, st, ctrl, (RoundState*)w.st.p, (LaunchBlock*)w.lb.p, c.report, nnz,
-                     B, wide ? 0 : 1);
+  hipLaunchKernelGGL(k_setup, dim3(1), dim3(256), 0, st, c, (LaunchBlock*)w.lb.p, wide ? 0 : 1);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipEventRecord(w.ev[1], st));
   // The host spins on the report (written by the step that finds the rounds done) and on the
@@ -472,6 +475,9 @@ static ldd_status decompose_run(Workspace& w, const ldd_csr* g, const int64_t* s
       head = (head + 1) % INFLIGHT;
     }
     steps = submitted;
+    // step k tags at most stamp_base + k + 1 (k <= submitted): the next call starts above that
+    w.stamp_base = stamp_base + (unsigned)submitted + 2;
+    w.stamp_clean = w.stamp.p;
   }
   HIP_TRY(hipEventRecord(w.ev[2], st));  // after every step enqueued, idle ones included
   if (!rep->ready) {
@@ -503,8 +509,8 @@ static ldd_status decompose_run(Workspace& w, const ldd_csr* g, const int64_t* s
   // output pass: every label is final once the report is there
   const hipStream_t so = w.out;
   HIP_TRY(hipEventRecord(w.ev[3], so));
-  const int g_f = grid_for((n + 63) / 64, 256, 1024);  // whole bitmap words per block
-  hipLaunchKernelGGL(k_finalize, dim3(g_f), dim3(1024), 0, so, n, B, g->row_ptr, (const u64*)P, centre,
+  const int g_f = grid_for((n + 63) / 64, 128, 2048);  // whole bitmap words per block
+  hipLaunchKernelGGL(k_finalize, dim3(g_f), dim3(512), 0, so, n, B, g->row_ptr, (const u64*)P, centre,
                      (u64*)w.hub_bits.p, (int*)w.qv0.p, (unsigned*)w.qa0.p, ctrl);
   HIP_TRY(hipEventRecord(w.ev[4], so));
   if (nnz > 0)

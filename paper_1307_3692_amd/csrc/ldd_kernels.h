@@ -108,7 +108,8 @@ struct RoundCtx {
   const int* qmax;
   u64* qcnt;        // 3 counters, 16 u64 apart: step k appends to counter k % 3
   u64* lr_part;     // [2][G]: per-block minimum label written by a step (parity of k)
-  unsigned* stamp;  // per vertex: last tail sweep that queued it
+  unsigned* stamp;  // per vertex: last tail sweep that queued it, as stamp_base + sweep + 1
+  unsigned stamp_base;  // every stamp left by earlier calls is <= stamp_base (no clearing per call)
   RoundState* st;   // [2]: state after step k lives in st[k & 1]
   Ctrl* ctrl;
   int dir_policy;   // 0 auto, DIR_TD, DIR_BU
@@ -155,7 +156,7 @@ __global__ void k_round_step_lb(const LaunchBlock* lb, int j);
 __global__ void k_round_step_srv(const LaunchBlock* lb, int j);
 __global__ void k_advance(LaunchBlock* lb, int C);
 __global__ void k_rounds_persistent(const LaunchBlock* lb);
-__global__ void k_setup(Ctrl* ctrl, RoundState* st, LaunchBlock* lb, Report* report, long long nnz, int B, int qpath);
+__global__ void k_setup(RoundCtx c, LaunchBlock* lb, int qpath);
 __global__ void k_out_report(const Ctrl* ctrl, Report* report);
 __global__ void k_finalize(int n, int B, const int* row_ptr, const u64* P, int* centre, u64* hub_bits, int* lv,
                            unsigned* la, Ctrl* ctrl);

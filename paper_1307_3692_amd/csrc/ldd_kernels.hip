@@ -306,19 +306,23 @@ __global__ __launch_bounds__(256) void k_place_window(const Ctrl* __restrict__ c
   }
 }
 
-// Single thread, after the preparation: decides whether the rounds run (ctrl->setup), writes
-// the initial round state into both slots and completes the round kernels' arguments with what
-// only the device knows (Delta, the rounds bound, the vertices with arcs).  When the rounds are
-// not to run, both slots say "done" (enqueued steps return at once) and the report is written
+// One block, after the preparation: decides whether the rounds run (ctrl->setup), writes the
+// initial round state into both slots, clears the steps' queue counters and statistics, and
+// writes the round kernels' argument block: the host's arguments completed with what only the
+// device knows (Delta, the rounds bound, the vertices with arcs), first step 1.  When the rounds
+// are not to run, both slots say "done" (enqueued steps return at once) and the report is written
 // here.
-__global__ void k_setup(Ctrl* ctrl, RoundState* st, LaunchBlock* lb, Report* report, long long nnz, int B,
-                        int qpath) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ void k_setup(RoundCtx c, LaunchBlock* lb, int qpath) {
+  if (blockIdx.x != 0) return;
+  for (int i = threadIdx.x; i < 3 * 16; i += blockDim.x) c.qcnt[i] = 0;
+  for (int i = threadIdx.x; i < RT; i += blockDim.x) c.ex_part[i] = 0;
+  if (threadIdx.x != 0) return;
+  Ctrl* ctrl = c.ctrl;
   const u64 delta = ctrl->delta, n_active = ctrl->n_active;
   const u64 D = delta >> FIX;
   unsigned code = SETUP_OK;
   if (ctrl->err & (ERR_BAD_SHIFT | ERR_BAD_ROWPTR | ERR_BAD_COL)) code = SETUP_INVALID;
-  else if (delta + ((u64)1 << FIX) >= ((u64)1 << (64 - B)) || D + 1 > ((u64)1 << 28)) code = SETUP_OVERFLOW;
+  else if (delta + ((u64)1 << FIX) >= ((u64)1 << (64 - c.B)) || D + 1 > ((u64)1 << 28)) code = SETUP_OVERFLOW;
   else if (qpath && (ctrl->wide || D >= (u64)QCAP)) code = SETUP_WIDE;
   else if (n_active == 0) code = SETUP_EMPTY;
   ctrl->setup = code;
@@ -327,17 +331,20 @@ __global__ void k_setup(Ctrl* ctrl, RoundState* st, LaunchBlock* lb, Report* rep
   s0.mode = code == SETUP_OK ? MODE_ROUNDS : MODE_DONE;
   s0.round = -1;
   s0.dir = DIR_TD;
-  s0.unsettled_arcs = nnz;
+  s0.unsettled_arcs = c.nnz;
   s0.tail_round = -1;
   s0.placed_lo = qpath ? (long long)(ctrl->place_lo < D + 1 ? ctrl->place_lo : D + 1) : 0;
   s0.flip = 0;
-  st[0] = s0;
+  c.st[0] = s0;
   s0.seq = -1;  // slot 1 stands for "step -1"
-  st[1] = s0;
-  lb->c.delta = delta;
-  lb->c.R = code == SETUP_OK ? (int)(D + 1) : 0;
-  lb->c.n_active = n_active;
-  if (code != SETUP_OK && report) {
+  c.st[1] = s0;
+  c.delta = delta;
+  c.R = code == SETUP_OK ? (int)(D + 1) : 0;
+  c.n_active = n_active;
+  lb->c = c;
+  lb->kbase = 1;
+  if (code != SETUP_OK && c.report) {
+    Report* report = c.report;
     report->st = s0;
     report->delta = delta;
     report->n_active = n_active;
@@ -481,10 +488,11 @@ __global__ void k_fill_u64(u64* p, long long count, u64 value) {
 //   cut = #{arcs v->w : v not in H, w in H} + #{arcs v->w : v, w not in H, c(v) != c(w)} / 2
 // (an edge with one endpoint in H is seen once; one with both outside is seen twice).  On
 // graphs with one dominant piece that skips nearly every arc.
-constexpr int FT = 1024;     // threads per finalize block
+constexpr int FT = 512;      // threads per finalize block
 constexpr int FBUF = 4096;   // LDS list buffer entries
 
-__global__ __launch_bounds__(FT) void k_finalize(int n, int B, const int* __restrict__ row_ptr,
+// (FT, 6): at most 80 VGPRs, three 512-thread blocks per CU
+__global__ __launch_bounds__(FT, 6) void k_finalize(int n, int B, const int* __restrict__ row_ptr,
                                                  const u64* __restrict__ P, int* __restrict__ centre,
                                                  u64* __restrict__ hub_bits, int* __restrict__ lv,
                                                  unsigned* __restrict__ la, Ctrl* ctrl) {

@@ -250,8 +250,8 @@ __device__ __forceinline__ void phase_top_down(const RoundCtx& c, int k, const i
           const u64 old = atomic_min_u64(&c.P[w], offer);
           if (old > offer) {
             if (TAIL) {
-              if (__hip_atomic_fetch_max(&c.stamp[w], sweep + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
-                  sweep + 1) {
+              const unsigned tag = c.stamp_base + sweep + 1;
+              if (__hip_atomic_fetch_max(&c.stamp[w], tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < tag) {
                 want = true;
                 deg = degree(c, w);
               }
@@ -305,7 +305,8 @@ __device__ __forceinline__ void pull_update(const RoundCtx& c, int v, u64 best, 
                                             unsigned& deg) {
   if (SEED) {
     atomic_min_u64(&c.P[v], best);
-    want = __hip_atomic_fetch_max(&c.stamp[v], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < 1u;
+    const unsigned tag = c.stamp_base + 1;  // the seed is sweep 0
+    want = __hip_atomic_fetch_max(&c.stamp[v], tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < tag;
     deg = (unsigned)degree;
   } else {
     const u64 old = atomic_min_u64(&c.P[v], best);

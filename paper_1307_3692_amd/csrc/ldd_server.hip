@@ -770,7 +770,7 @@ ldd_status srv_setup(ldd_server* srv) {
   c.dir_policy = srv->cfg.direction;
   c.td_to_bu = 14;
   c.bu_to_td = 24;
-  c.tail_den = srv->cfg.tail_vertices == 0 ? 64 : (srv->cfg.tail_vertices < 0 ? 0 : srv->cfg.tail_vertices);
+  c.tail_den = srv->cfg.tail_vertices == 0 ? 32 : (srv->cfg.tail_vertices < 0 ? 0 : srv->cfg.tail_vertices);
   c.tail_min_left = 16;
   c.report = nullptr;
   c.ex_part = (u64*)srv->ex_part;

@@ -149,7 +149,7 @@ extern "C" ldd_status ldd_tune(int32_t num_graphs, const int64_t* vtx_off, const
     return t[1];
   };
   Knobs cur{base && base->blocks ? base->blocks : 2 * ncu, base && base->td_to_bu ? base->td_to_bu : 14,
-            base && base->bu_to_td ? base->bu_to_td : 24, base && base->tail_vertices ? base->tail_vertices : 64};
+            base && base->bu_to_td ? base->bu_to_td : 24, base && base->tail_vertices ? base->tail_vertices : 32};
   (void)measure(cur);  // warm-up (workspace growth, code loading)
   if (failure != LDD_OK) {
     (void)hipEventDestroy(e0);
