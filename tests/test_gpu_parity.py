@@ -100,6 +100,26 @@ def test_deterministic_repeats(ldd):
         assert np.array_equal(got, first[0]) and cut == first[1]
 
 
+def test_tail_stamps_across_calls(ldd):
+    """The tail's per-vertex stamps are not cleared between calls (each call tags above every
+    earlier tag).  Calls that alternate between graphs of different sizes, with the tail taking
+    over from the first step and the engines mixed, keep giving the oracle's bits; the
+    persistent engine leaves the stamps in a state the next call must clear."""
+    cases = []
+    for name in ("rmat-16", "grid2d-64x64", "rmat-18"):
+        rp, ci, s, beta = inputs.workload(name)
+        want_c, _, want_cut = oracle.decompose(rp, ci, s)
+        cases.append((name, to_dev(rp, ci, s), beta, want_c, want_cut))
+    for i in range(12):
+        name, d, beta, want_c, want_cut = cases[i % 3]
+        mode = dict(tail_vertices=1, engine=1) if i % 4 == 3 else dict(tail_vertices=1 if i % 2 else 8)
+        centre, cut, st = ldd.decompose(*d, beta, stats=True, **mode)
+        got = centre.cpu().numpy()
+        log(f"call {i} {name} {mode}: tail sweeps {st['tail_iters']}")
+        assert np.array_equal(got, want_c), (i, name, mode, np.count_nonzero(got != want_c))
+        assert cut == want_cut
+
+
 @pytest.mark.parametrize("name", ["rmat-16", "rmat-18", "grid3d-64", "grid2d-1000"])
 def test_medium_workloads_vs_oracle(ldd, name):
     rp, ci, s, beta = inputs.workload(name)
