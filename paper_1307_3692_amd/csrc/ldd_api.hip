@@ -87,9 +87,13 @@ struct HostMirror {  // pinned, mapped host memory
 
 constexpr int CHUNK = 8;     // steps per graph replay
 constexpr int INFLIGHT = 2;  // replays enqueued ahead of the one running
+// Replays enqueued after the last step that has work return at once, but the output pass
+// queues behind them: so the second replay is a short one, and once the tail has started (a
+// few sweeps are left) the next replays are short again, growing back to CHUNK.
+constexpr int CHUNK_SIZES[] = {2, 4, CHUNK};
 
 struct StepGraph {
-  int blocks = 0;
+  int blocks = 0, steps = 0;
   hipGraphExec_t exec = nullptr;
 };
 
@@ -150,24 +154,24 @@ ldd_status ws_setup(Workspace& w) {
   return LDD_OK;
 }
 
-// A graph of CHUNK step launches (reading their arguments from the workspace's LaunchBlock)
-// followed by one k_advance; instantiated once per grid size and replayed for every call.
-ldd_status step_graph(Workspace& w, int blocks, hipGraphExec_t* out) {
+// A graph of `steps` step launches (reading their arguments from the workspace's LaunchBlock)
+// followed by one k_advance; instantiated once per grid size and length, replayed for every call.
+ldd_status step_graph(Workspace& w, int blocks, int steps, hipGraphExec_t* out) {
   for (auto& g : w.graphs)
-    if (g.blocks == blocks) {
+    if (g.blocks == blocks && g.steps == steps) {
       *out = g.exec;
       return LDD_OK;
     }
   const LaunchBlock* lbp = (const LaunchBlock*)w.lb.p;
   hipGraph_t graph = nullptr;
   HIP_TRY(hipStreamBeginCapture(w.capture, hipStreamCaptureModeThreadLocal));
-  for (int j = 0; j < CHUNK; ++j) hipLaunchKernelGGL(k_round_step_lb, dim3(blocks), dim3(RT), 0, w.capture, lbp, j);
-  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, w.capture, (LaunchBlock*)w.lb.p, CHUNK);
+  for (int j = 0; j < steps; ++j) hipLaunchKernelGGL(k_round_step_lb, dim3(blocks), dim3(RT), 0, w.capture, lbp, j);
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, w.capture, (LaunchBlock*)w.lb.p, steps);
   HIP_TRY(hipStreamEndCapture(w.capture, &graph));
   hipGraphExec_t exec = nullptr;
   HIP_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
   HIP_TRY(hipGraphDestroy(graph));
-  w.graphs.push_back({blocks, exec});
+  w.graphs.push_back({blocks, steps, exec});
   *out = exec;
   return LDD_OK;
 }
@@ -416,6 +420,7 @@ static ldd_status decompose_run(Workspace& w, const ldd_csr* g, const int64_t* s
   volatile Report* rep = &w.host->report;
   rep->ready = 0;
   rep->out_ready = 0;
+  rep->tail_hint = 0;
 
   const int engine = o.engine == LDD_ENGINE_AUTO ? LDD_ENGINE_LAUNCH : o.engine;
   int blocks = o.blocks > 0 ? o.blocks : 2 * w.num_cu;
@@ -424,8 +429,10 @@ static ldd_status decompose_run(Workspace& w, const ldd_csr* g, const int64_t* s
   // rounds, placement steps, tail sweeps (each settles or lowers at least one label) and slack
   const long long kmax = R_bound + R_bound / ABUF + 1 + (long long)n + 2;
   long long steps = 0;
-  hipGraphExec_t exec = nullptr;
-  if (engine != LDD_ENGINE_PERSISTENT && (s = step_graph(w, blocks, &exec))) return s;
+  hipGraphExec_t exec[3] = {};
+  if (engine != LDD_ENGINE_PERSISTENT)
+    for (int i = 0; i < 3; ++i)
+      if ((s = step_graph(w, blocks, CHUNK_SIZES[i], &exec[i]))) return s;
   hipLaunchKernelGGL(k_setup, dim3(1), dim3(256), 0, st, c, (LaunchBlock*)w.lb.p, wide ? 0 : 1);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipEventRecord(w.ev[1], st));
@@ -451,11 +458,16 @@ static ldd_status decompose_run(Workspace& w, const ldd_csr* g, const int64_t* s
   } else {
     long long submitted = 0;
     int head = 0;
-    for (int i = 0; i < INFLIGHT; ++i) {
-      HIP_TRY(hipGraphLaunch(exec, st));
-      HIP_TRY(hipEventRecord(w.chunk_ev[i], st));
-      submitted += CHUNK;
-    }
+    // replay lengths: CHUNK, then short; after the tail hint short again, then growing
+    int size_i = 2, hint_seen = 0;
+    auto launch = [&](int slot, int i) -> hipError_t {
+      hipError_t e = hipGraphLaunch(exec[i], st);
+      if (e == hipSuccess) e = hipEventRecord(w.chunk_ev[slot], st);
+      submitted += CHUNK_SIZES[i];
+      return e;
+    };
+    HIP_TRY(launch(0, 2));
+    HIP_TRY(launch(1, 0));
     while (!rep->ready) {
       const hipError_t q = hipEventQuery(w.chunk_ev[head]);
       if (q == hipErrorNotReady) {
@@ -469,9 +481,12 @@ static ldd_status decompose_run(Workspace& w, const ldd_csr* g, const int64_t* s
         ldd_set_error("round steps exceeded their bound (%lld)", kmax);
         return LDD_ERR_INTERNAL;
       }
-      HIP_TRY(hipGraphLaunch(exec, st));
-      HIP_TRY(hipEventRecord(w.chunk_ev[head], st));
-      submitted += CHUNK;
+      if (!hint_seen && rep->tail_hint) {
+        hint_seen = 1;
+        size_i = 0;
+      }
+      HIP_TRY(launch(head, size_i));
+      if (size_i < 2) ++size_i;
       head = (head + 1) % INFLIGHT;
     }
     steps = submitted;

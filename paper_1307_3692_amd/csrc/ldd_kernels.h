@@ -50,6 +50,7 @@ struct Report {
   u64 cut_arcs, pieces, unreached;
   unsigned out_err;
   long long out_ready;
+  long long tail_hint;  // set by the step that starts the label-correcting tail
 };
 
 // Server mode: one admitted request per slot, in its own vertex range of the arena.

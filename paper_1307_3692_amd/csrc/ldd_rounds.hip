@@ -371,13 +371,18 @@ __device__ __forceinline__ void phase_pull(const RoundCtx& c, int r, int k, u64 
   const u64 unit = (u64)1 << (FIX + B);
   const u64 base_r = (u64)r << (FIX + B);
   const u64 prev_round = (u64)(r - 1);
-  for (long long base = (long long)blockIdx.x * RT; base < c.n; base += (long long)gridDim.x * RT) {
+  const long long stride = (long long)gridDim.x * RT;
+  // each tile's labels are loaded during the tile before, so that the load is in flight across
+  // the append's barriers (a label read early can only be higher than the current one: labels
+  // only drop, so the worst case is a pull that finds nothing to lower)
+  u64 pv_next = (long long)blockIdx.x * RT + threadIdx.x < c.n ? c.P[blockIdx.x * RT + threadIdx.x] : 0;
+  for (long long base = (long long)blockIdx.x * RT; base < c.n; base += stride) {
     const long long vi = base + threadIdx.x;
     const int v = (int)vi;
     bool want = false, defer = false;
     unsigned deg = 0;
+    const u64 pv = pv_next;
     if (vi < c.n) {
-      const u64 pv = c.P[v];
       if (pv >= base_r && (SEED || pv > Lr)) {
         const int a0 = c.row_ptr[v], a1 = c.row_ptr[v + 1];
         if (!SEED || a1 > a0) {
@@ -415,6 +420,7 @@ __device__ __forceinline__ void phase_pull(const RoundCtx& c, int r, int k, u64 
         if (best < c.P[v]) pull_update<SEED>(c, v, best, c.row_ptr[v + 1] - c.row_ptr[v], wmin, want, deg);
       }
     }
+    pv_next = vi + stride < c.n ? c.P[vi + stride] : 0;
     block_append(ab, want, v, deg, c, k);
   }
   examined_total += examined;
@@ -580,7 +586,9 @@ __device__ __forceinline__ int round_step(const RoundCtx& c, int k, AppendBuf& a
     __hip_atomic_store(qcounter(c, k + 1), 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     // the host stops enqueueing steps once it reads the report; written once per
     // decomposition, since a store to host memory delays the completion of the kernel that
-    // makes it
+    // makes it.  Likewise the hint that the tail has started (few steps are left), once.
+    if (c.report && mode == MODE_TAIL && sh.S.round == 0)
+      __hip_atomic_store(&c.report->tail_hint, 1ll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     if (c.report && mode == MODE_DONE) {
       Report* r = c.report;
       r->st = sh.S;
