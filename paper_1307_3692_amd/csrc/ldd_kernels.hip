@@ -646,8 +646,28 @@ __global__ __launch_bounds__(FT, 6) void k_finalize(int n, int B, const int* __r
 
 __device__ __forceinline__ bool hub_bit(const u64* bits, int v) { return (bits[v >> 6] >> (v & 63)) & 1; }
 
-// Cut count over the list of rows outside H (see k_finalize): its arcs are split evenly over
-// the grid and walked in tiles of 256 with the list entries staged in LDS.
+// Per-graph cut totals (batch): lane contributions to graph g (g < 0: none), one atomic per
+// wave when all of its contributions go to one graph.  Called by a converged wave.
+__device__ __forceinline__ void cut_per_graph(u64* cut_g, int g, unsigned contrib) {
+  const u64 any = __ballot(g >= 0);
+  if (!any) return;
+  const int leader = __ffsll((long long)any) - 1;
+  const int g0 = __shfl(g, leader, WAVE);
+  if (__all(g < 0 || g == g0)) {
+    const u64 t = wave_sum_u64(g >= 0 ? contrib : 0);
+    if ((int)lane_id() == leader) atomic_add_u64(&cut_g[g0], t);
+  } else if (g >= 0) {
+    atomic_add_u64(&cut_g[g], contrib);
+  }
+}
+
+// Largest degree up to which the cut walks whole rows, one per thread, instead of splitting
+// the listed rows' arcs evenly over the grid.
+constexpr unsigned CUT_ROW_DEG = 64;
+
+// Cut count over the rows outside H (see k_finalize).  When no degree exceeds CUT_ROW_DEG each
+// thread walks whole rows (independent loads, no staging); otherwise the listed rows' arcs are
+// split evenly over the grid and walked in tiles of 256 with the list entries staged in LDS.
 __global__ __launch_bounds__(256) void k_cut(int n, const int* __restrict__ row_ptr, const int* __restrict__ col,
                                              const int* __restrict__ centre, const u64* __restrict__ hub_bits,
                                              const int* __restrict__ lv, const unsigned* __restrict__ la,
@@ -664,7 +684,28 @@ __global__ __launch_bounds__(256) void k_cut(int n, const int* __restrict__ row_
   const unsigned a_begin = (unsigned)(((u64)al * blockIdx.x) / G);
   const unsigned a_end = (unsigned)(((u64)al * (blockIdx.x + 1)) / G);
   u64 one_side = 0, both = 0;
-  if (a_begin < a_end) {
+  if ((unsigned)(ctrl->hub >> 32) <= CUT_ROW_DEG) {
+    // every degree is small: rows one per thread, every row outside H (the listed rows)
+    for (long long base = (long long)blockIdx.x * T; base < n; base += (long long)G * T) {
+      const long long v = base + threadIdx.x;
+      unsigned c1 = 0, c2 = 0;  // arcs to another piece outside H, arcs into H
+      int g = -1;
+      if (v < n && !hub_bit(hub_bits, (int)v)) {
+        const int a0 = row_ptr[v], a1 = row_ptr[v + 1], cv = centre[v];
+        for (int a = a0; a < a1; ++a) {
+          const int w = col[a];
+          if ((unsigned)w < (unsigned)n) {
+            if (hub_bit(hub_bits, w)) ++c2;
+            else c1 += centre[w] != cv ? 1u : 0u;
+          }
+        }
+        if (cut_g && (c1 | c2)) g = gid[v];
+      }
+      one_side += c2;
+      both += c1;
+      if (cut_g) cut_per_graph(cut_g, g, 2 * c2 + c1);
+    }
+  } else if (a_begin < a_end) {
     if (threadIdx.x < WAVE) {
       const unsigned e = wave_search_le(la, nl, a_begin);
       if (threadIdx.x == 0) s_start = e;
@@ -709,20 +750,7 @@ __global__ __launch_bounds__(256) void k_cut(int n, const int* __restrict__ row_
       }
       if (contrib == 2) one_side += 1;
       else both += contrib;
-      if (cut_g) {  // per-graph totals (batch): one atomic per wave when all its arcs share a graph
-        const int g = (contrib && row >= 0) ? gid[row] : -1;
-        const u64 any = __ballot(g >= 0);
-        if (any) {
-          const int leader = __ffsll((long long)any) - 1;
-          const int g0 = __shfl(g, leader, WAVE);
-          if (__all(g < 0 || g == g0)) {
-            const u64 t = wave_sum_u64(g >= 0 ? contrib : 0);
-            if ((int)lane_id() == leader) atomic_add_u64(&cut_g[g0], t);
-          } else if (g >= 0) {
-            atomic_add_u64(&cut_g[g], contrib);
-          }
-        }
-      }
+      if (cut_g) cut_per_graph(cut_g, (contrib && row >= 0) ? gid[row] : -1, contrib);
       const unsigned next = tile + T;
       __syncthreads();
       if (threadIdx.x == 0) {
