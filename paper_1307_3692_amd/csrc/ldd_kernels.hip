@@ -785,6 +785,21 @@ __device__ __forceinline__ int graph_of(const long long* __restrict__ off, int G
   return lo;
 }
 
+// The graph of positions that a thread visits in increasing order: one search for the first,
+// then a walk over the offsets (amortised one comparison per position).
+struct GraphCursor {
+  int g = -1;
+  long long next = 0;  // off[g + 1]
+  __device__ __forceinline__ int at(const long long* __restrict__ off, int G, long long x) {
+    if (g < 0) {
+      g = graph_of(off, G, x);
+      next = off[g + 1];
+    }
+    while (next <= x) next = off[++g + 1];
+    return g;
+  }
+};
+
 // Global row offsets and the graph of every vertex; per-graph max shift (one 128-byte line per
 // graph, one atomic per wave when the wave lies in one graph); bounds checks of each graph.
 __global__ __launch_bounds__(256) void k_batch_rows(int G, long long N, const long long* __restrict__ vo,
@@ -792,13 +807,14 @@ __global__ __launch_bounds__(256) void k_batch_rows(int G, long long N, const lo
                                                     const long long* __restrict__ shift, int* __restrict__ rp_out,
                                                     int* __restrict__ gid, u64* __restrict__ dg, Ctrl* ctrl) {
   unsigned bad = 0;
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long base = (long long)blockIdx.x * blockDim.x; base < N; base += stride) {
+  const long long lo = N * blockIdx.x / gridDim.x, hi = N * (blockIdx.x + 1) / gridDim.x;
+  GraphCursor cur;
+  for (long long base = lo; base < hi; base += blockDim.x) {
     const long long v = base + threadIdx.x;
     int g = -1;
     u64 sv = 0;
-    if (v < N) {
-      g = graph_of(vo, G, v);
+    if (v < hi) {
+      g = cur.at(vo, G, v);
       const long long lv = v - vo[g], ng = vo[g + 1] - vo[g], mg = ao[g + 1] - ao[g];
       const long long at = vo[g] + g + lv;
       const int a = row_ptr[at], b = row_ptr[at + 1];
@@ -831,9 +847,10 @@ __global__ __launch_bounds__(256) void k_batch_cols(int G, long long M, const lo
                                                     const long long* __restrict__ ao, const int* __restrict__ col,
                                                     int* __restrict__ col_out, Ctrl* ctrl) {
   unsigned bad = 0;
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long a = (long long)blockIdx.x * blockDim.x + threadIdx.x; a < M; a += stride) {
-    const int g = graph_of(ao, G, a);
+  const long long lo = M * blockIdx.x / gridDim.x, hi = M * (blockIdx.x + 1) / gridDim.x;
+  GraphCursor cur;
+  for (long long a = lo + threadIdx.x; a < hi; a += blockDim.x) {
+    const int g = cur.at(ao, G, a);
     const int c = col[a];
     const long long ng = vo[g + 1] - vo[g];
     if (c < 0 || c >= ng) {
