@@ -692,11 +692,19 @@ __global__ __launch_bounds__(256) void k_cut(int n, const int* __restrict__ row_
       int g = -1;
       if (v < n && !hub_bit(hub_bits, (int)v)) {
         const int a0 = row_ptr[v], a1 = row_ptr[v + 1], cv = centre[v];
-        for (int a = a0; a < a1; ++a) {
-          const int w = col[a];
-          if ((unsigned)w < (unsigned)n) {
-            if (hub_bit(hub_bits, w)) ++c2;
-            else c1 += centre[w] != cv ? 1u : 0u;
+        // four arcs at a time: their column ids, then their hub bits and centres, so that
+        // each group costs two dependent loads rather than each arc
+        for (int a = a0; a < a1; a += 4) {
+          int w[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) w[j] = a + j < a1 ? col[a + j] : -1;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const bool ok = (unsigned)w[j] < (unsigned)n;
+            const u64 hb = ok ? hub_bits[w[j] >> 6] : 0;
+            const int cw = ok ? centre[w[j]] : cv;
+            if ((hb >> (w[j] & 63)) & 1) ++c2;
+            else c1 += cw != cv ? 1u : 0u;
           }
         }
         if (cut_g && (c1 | c2)) g = gid[v];
