@@ -339,7 +339,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the decomposition of one graph "
-              "is sized for one MI355X; see DESIGN.md for how it would shard)", file=sys.stderr)
+              "is sized for one MI355X and the library has no multi-GPU path)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -228,7 +228,7 @@ def test_order_statistic_gap_fact():
 
 
 # ------------------------------------------------------------------------------------------
-# certificate checker
+# the linear-time certificate
 # ------------------------------------------------------------------------------------------
 def test_certificate_accepts_exact_and_rejects_everything_else():
     rng = np.random.default_rng(21)
