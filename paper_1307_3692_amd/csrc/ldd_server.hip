@@ -594,6 +594,11 @@ struct ldd_server {
   long long round_limit = 0;  // keys stay below round_limit * 2^20
   int max_rounds = 0;         // largest R a request may have
   hipStream_t stream = nullptr;
+  // finishing runs on its own stream, beside the steps that follow: it reads only the finished
+  // requests' vertex ranges and slots, which no step and no admission touches until the reports
+  // arrive; fin_dep orders it after the steps enqueued before it
+  hipStream_t fin_stream = nullptr;
+  hipEvent_t fin_dep = nullptr, fin_done = nullptr;
   hipEvent_t chunk_ev[2] = {};
   hipGraphExec_t graph = nullptr;
   int blocks = 0;
@@ -682,6 +687,9 @@ constexpr long long BYTES_PER_VERTEX = 8 + 8 + 8 + 4 + 4 + 1;
 ldd_status srv_setup(ldd_server* srv) {
   SRV_TRY(hipSetDevice(srv->dev));
   SRV_TRY(hipStreamCreateWithFlags(&srv->stream, hipStreamNonBlocking));
+  SRV_TRY(hipStreamCreateWithFlags(&srv->fin_stream, hipStreamNonBlocking));
+  SRV_TRY(hipEventCreateWithFlags(&srv->fin_dep, hipEventDisableTiming));
+  SRV_TRY(hipEventCreateWithFlags(&srv->fin_done, hipEventDisableTiming));
   for (auto& e : srv->chunk_ev) SRV_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   const long long V = srv->vcap;
   const size_t per_slot = (size_t)MAX_SLOTS * (srv->max_rounds + 1);
@@ -862,7 +870,9 @@ ldd_status srv_admit(ldd_server* srv, const std::vector<Request*>& rs) {
 // Enqueue the finishing of a batch of requests whose last round and the step after it are
 // enqueued: centres into the callers' buffers, cuts, reports.
 ldd_status srv_finish(ldd_server* srv, const std::vector<Request*>& rs) {
-  const hipStream_t s = srv->stream;
+  const hipStream_t s = srv->fin_stream;
+  SRV_TRY(hipEventRecord(srv->fin_dep, srv->stream));
+  SRV_TRY(hipStreamWaitEvent(s, srv->fin_dep, 0));
   for (size_t b0 = 0; b0 < rs.size(); b0 += MAX_BATCH) {
     FinBatch fv{}, fc{};
     int nv = 0, nc = 0;
@@ -897,11 +907,13 @@ ldd_status srv_finish(ldd_server* srv, const std::vector<Request*>& rs) {
                        (SlotInfo*)srv->slots, srv->rep_dev);
     SRV_TRY(hipGetLastError());
   }
+  SRV_TRY(hipEventRecord(srv->fin_done, s));
   return LDD_OK;
 }
 
 // Lower the global round numbering by X rounds (X <= every active slot's r0).
 ldd_status srv_rebase(ldd_server* srv, long long X) {
+  SRV_TRY(hipStreamWaitEvent(srv->stream, srv->fin_done, 0));  // finishing reads labels the rebase rewrites
   hipLaunchKernelGGL(k_rebase, dim3((unsigned)std::min<long long>(8192, (std::max<long long>(srv->vcap, 2 * RT) + 255) / 256)), dim3(256), 0,
                      srv->stream, srv->vcap, srv->B, X, (u64*)srv->P, (u64*)srv->lr_part, 2 * RT, (u64*)srv->s_lr, (SlotInfo*)srv->slots, MAX_SLOTS,
                      (RoundState*)srv->st, srv->steps);
@@ -1052,7 +1064,7 @@ ldd_status engine_loop(ldd_server* srv) {
       oldest ^= 1;
       --inflight;
     } else if (inflight == 0 && active == 0 && !finishing.empty()) {
-      SRV_TRY(hipStreamSynchronize(srv->stream));
+      SRV_TRY(hipStreamSynchronize(srv->fin_stream));
     }
   }
 }
@@ -1286,6 +1298,7 @@ extern "C" ldd_status ldd_server_destroy(ldd_server* srv) {
   if (srv->engine.joinable()) srv->engine.join();
   const ldd_status fatal = srv->fatal;
   if (srv->stream) (void)hipStreamSynchronize(srv->stream);
+  if (srv->fin_stream) (void)hipStreamSynchronize(srv->fin_stream);
   for (void* p : {srv->P, srv->qv0, srv->qv1, srv->qa0, srv->qa1, srv->wake_ord,
                   srv->wake_tab, srv->cnt, srv->cur, srv->slots, srv->st, srv->qcnt, srv->lr_part, srv->lb,
                   srv->ex_part, srv->ctrl, srv->adm_max, srv->adm_err, srv->cut_acc, srv->sst,
@@ -1298,6 +1311,9 @@ extern "C" ldd_status ldd_server_destroy(ldd_server* srv) {
     if (e) (void)hipEventDestroy(e);
   for (hipEvent_t e : srv->ev_pool) (void)hipEventDestroy(e);
   if (srv->stream) (void)hipStreamDestroy(srv->stream);
+  if (srv->fin_stream) (void)hipStreamDestroy(srv->fin_stream);
+  if (srv->fin_dep) (void)hipEventDestroy(srv->fin_dep);
+  if (srv->fin_done) (void)hipEventDestroy(srv->fin_done);
   for (auto& kv : srv->all) {
     if (kv.second->ready) (void)hipEventDestroy(kv.second->ready);
     delete kv.second;
