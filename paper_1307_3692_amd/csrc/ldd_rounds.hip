@@ -1203,15 +1203,28 @@ __device__ __forceinline__ void srv_pull(const RoundCtx& c, int r, int k, SrvApp
           int a = a0;
           bool bad = false;
           const int a_cap = a1 - a0 > PULL_CAP ? a0 + PULL_CAP : a1;
-          for (; a < a_cap && best > Lr; ++a) {
-            const int ul = col[a];
-            if ((unsigned)ul >= n) {
+          // the first arc alone (most rows stop there), then four per group: their column ids,
+          // then their labels, so that a group costs two dependent loads
+          while (a < a_cap && best > Lr) {
+            const int lim = min(a_cap, a + (a == a0 ? 1 : 4));
+            int ul[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) ul[j] = a + j < lim ? col[a + j] : 0;
+            bool bad_g = false;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bad_g |= a + j < lim && (unsigned)ul[j] >= n;
+            if (bad_g) {
               atomic_or_u32(&c.slot_err[lo], ERR_BAD_COL);
               bad = true;
               break;
             }
-            const u64 pu = load_u64_relaxed(&c.P[vbeg + ul]);
-            if ((pu >> (FIX + B)) == prev_round && pu != INF && pu + unit < best) best = pu + unit;
+            u64 pu[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) pu[j] = a + j < lim ? load_u64_relaxed(&c.P[vbeg + ul[j]]) : INF;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              if ((pu[j] >> (FIX + B)) == prev_round && pu[j] != INF && pu[j] + unit < best) best = pu[j] + unit;
+            a = lim;
           }
           if (!bad && a < a1 && best > Lr) {  // long row, undecided: the wave finishes it below
             defer = true;
