@@ -552,6 +552,8 @@ __global__ __launch_bounds__(FT, 6) void k_finalize(int n, int B, const int* __r
       const long long w0 = base + 256 * wid + 64 * j;
       if (lane == 0 && w0 < hi) hub_bits[w0 >> 6] = bits;
     }
+    // a pass that lists nothing (most passes when one piece holds most rows) ends here
+    if (!__syncthreads_or((int)(want[0] | want[1] | want[2] | want[3]))) continue;
     // list entries of this pass: per-wave counts over the four sub-tiles, then the block
     unsigned my_cnt[4], my_arcs[4], wc_tot = 0, wa_tot = 0;
     u64 m[4];
