@@ -310,6 +310,9 @@ static ldd_status decompose_run(Workspace& w, const ldd_csr* g, const int64_t* s
   u64* P = (u64*)w.P.p;
   const int B = ceil_log2(n) < 1 ? 1 : ceil_log2(n);
 
+  // the previous call on this workspace may have left idle steps queued on its stream, which
+  // read the argument block and the state this call is about to rewrite: start after them
+  HIP_TRY(hipStreamWaitEvent(st, w.ev[2], 0));
   HIP_TRY(hipEventRecord(w.ev[0], st));
   const int g_n = grid_for(n, 256 * 4, 2048);
   // preparation pass A: labels, Delta, checks and the q-bucket histogram (per block)

@@ -120,6 +120,29 @@ def test_tail_stamps_across_calls(ldd):
         assert cut == want_cut
 
 
+def test_calls_on_alternating_streams(ldd):
+    """A call may leave idle round steps queued on its stream when it returns; a next call on
+    another stream reuses the same workspace.  Calls alternating between two streams, back to
+    back and without synchronising, keep giving the oracle's bits."""
+    import torch
+    cases = []
+    for name in ("rmat-16", "grid2d-64x64", "rmat-18"):
+        rp, ci, s, beta = inputs.workload(name)
+        want_c, _, want_cut = oracle.decompose(rp, ci, s)
+        cases.append((name, to_dev(rp, ci, s), beta, want_c, want_cut))
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for i in range(12):
+        name, d, beta, want_c, want_cut = cases[i % 3]
+        st = streams[i % 2]
+        st.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(st):
+            centre, cut = ldd.decompose(*d, beta, stream=st)
+            got = centre.cpu().numpy()
+        log(f"call {i} {name} on stream {i % 2}")
+        assert np.array_equal(got, want_c), (i, name, np.count_nonzero(got != want_c))
+        assert cut == want_cut
+
+
 @pytest.mark.parametrize("name", ["rmat-16", "rmat-18", "grid3d-64", "grid2d-1000"])
 def test_medium_workloads_vs_oracle(ldd, name):
     rp, ci, s, beta = inputs.workload(name)
