@@ -33,7 +33,8 @@
  *   - hip_stream is a hipStream_t (NULL = default stream).  Work is ordered on that stream;
  *     the single-graph and batch calls return once their outputs are complete.  Round steps
  *     enqueued ahead of the end may still be queued on the stream then; they return at once,
- *     and later work on the stream is ordered after them and after the outputs.
+ *     and later work on the stream is ordered after them and after the outputs; a later call
+ *     on another stream of the same device starts after them too (the workspace is shared).
  */
 #ifndef LDD_H
 #define LDD_H
