@@ -1048,7 +1048,7 @@ ldd_status engine_loop(ldd_server* srv) {
         batch.push_back(r);
         finishing.push_back(r);
         --active;
-      } else if (srv->steps > r->first_step + r->R + 4 * srv->cfg.chunk_steps + 8) {
+      } else if (srv->steps > r->first_step + r->R + 4 * std::max(srv->cfg.chunk_steps, 8) + 8) {
         snprintf(srv->fatal_msg, sizeof(srv->fatal_msg), "request in slot %d not done %lld steps after its last round",
                  i, srv->steps - (r->first_step + r->R));
         return LDD_ERR_INTERNAL;
@@ -1109,7 +1109,7 @@ extern "C" ldd_status ldd_server_create(const ldd_server_config* cfg, ldd_server
   srv->cfg = *cfg;
   srv->t0 = now_s();
   if (srv->cfg.max_slots <= 0 || srv->cfg.max_slots > MAX_SLOTS) srv->cfg.max_slots = MAX_SLOTS;
-  if (srv->cfg.chunk_steps <= 0) srv->cfg.chunk_steps = 8;
+  if (srv->cfg.chunk_steps <= 0) srv->cfg.chunk_steps = 4;
   if (srv->cfg.chunk_steps > 64 || srv->cfg.direction < 0 || srv->cfg.direction > 2 || srv->cfg.blocks < 0 ||
       srv->cfg.max_rounds < 0 || srv->cfg.tail_vertices < -1) {
     delete srv;
