@@ -829,13 +829,28 @@ __device__ __forceinline__ u64 srv_own_offer(const RoundCtx& c, const SrvShared&
   return ((ss.off0[s] - (u64)ss.shift[s][v - ss.vbeg[s]]) << c.B) | (u64)v;
 }
 
-// Start of step k, round r (wave 0, one lane per slot): each slot's mode for this step and, in
+// The per-slot prefix sums are taken one wave per WAVE slots; each later wave adds the total of
+// the waves before it (one barrier per wave after the first; nothing when one wave holds them all).
+template <typename A, typename B>
+__device__ __forceinline__ void slot_carry(A* a, B* b) {
+  for (int w = 1; w < MAX_SLOTS / WAVE; ++w) {
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t >= w * WAVE && t < (w + 1) * WAVE) {
+      a[t + 1] += a[w * WAVE];
+      if (b) b[t + 1] += b[w * WAVE];
+    }
+  }
+}
+
+// Start of step k, round r (one lane per slot): each slot's mode for this step and, in
 // rounds mode, its direction from its own frontier; its L_r; the wake, pull and top-down work
 // lists.  Block 0 records the slots' state after step k, clears the counters step k+1 fills,
 // and reports a slot found done (through mapped host memory).
 __device__ __forceinline__ void srv_slot_setup(const RoundCtx& c, int k, int r, SrvShared& ss) {
-  if (threadIdx.x >= WAVE) return;
-  const int s = threadIdx.x;  // MAX_SLOTS == WAVE
+  static_assert(MAX_SLOTS % WAVE == 0, "slots fill whole waves");
+  if (threadIdx.x >= MAX_SLOTS) return;
+  const int s = threadIdx.x;
   int td = TD_SKIP, wake = 0, seed = 0, pull_len = 0, n = 0;
   long long pull_beg = 0, vbeg = 0;
   u64 L = INF, front = 0;
@@ -930,7 +945,7 @@ __device__ __forceinline__ void srv_slot_setup(const RoundCtx& c, int k, int r, 
 // rho = r - r0 take their own arc: the back of shift bucket D - rho - 1 and the front of bucket
 // D - rho (D = R - 1), one range of its part of wake_ord.
 __device__ __forceinline__ void srv_wake(const RoundCtx& c, int r, int k, SrvAppend& ab, SrvShared& ss) {
-  if (threadIdx.x < WAVE) {
+  if (threadIdx.x < MAX_SLOTS) {
     const int t = threadIdx.x;
     int len = 0;
     long long beg = 0;
@@ -950,6 +965,7 @@ __device__ __forceinline__ void srv_wake(const RoundCtx& c, int r, int k, SrvApp
     ss.seg_off[t + 1] = (int)incl;
     if (t == 0) ss.seg_off[0] = 0;
   }
+  slot_carry(ss.seg_off, (int*)nullptr);
   __syncthreads();
   const int cnt = ss.seg_off[MAX_SLOTS];
   for (long long base = (long long)blockIdx.x * RT; base < cnt; base += (long long)gridDim.x * RT) {
@@ -1269,6 +1285,7 @@ __device__ __forceinline__ void srv_step(const RoundCtx& c, int k, SrvAppend& ab
   __syncthreads();
   const int r = (int)sh.S.round;
   srv_slot_setup(c, k, r, ss);
+  slot_carry(ss.pull_off, ss.td_off);
   __syncthreads();
   if (blockIdx.x == 0 && threadIdx.x == 0) store_state<__HIP_MEMORY_SCOPE_AGENT>(&c.st[k & 1], sh.S);
   srv_wake(c, r, k, ab, ss);
