@@ -186,7 +186,7 @@ typedef struct {
   int64_t max_vertices;     /* arena vertices (a request takes n + 1 rounded up to 64);           */
                             /* 0 = from the budget (at most 2^30)                                 */
   int64_t max_arcs;         /* unused (0)                                                         */
-  int32_t max_slots;        /* requests on the device at once, 1..192 (0 = 192)                   */
+  int32_t max_slots;        /* requests on the device at once, 1..256 (0 = 256)                   */
   int32_t chunk_steps;      /* rounds per replayed launch graph, 1..64 (0 = 4)                    */
   int32_t blocks;           /* workgroups of the round kernel (0 = 2 per CU)                      */
   int32_t direction;        /* LDD_DIR_* policy of every round                                     */

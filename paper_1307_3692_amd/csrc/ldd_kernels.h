@@ -54,7 +54,7 @@ struct Report {
 };
 
 // Server mode: one admitted request per slot, in its own vertex range of the arena.
-constexpr int MAX_SLOTS = 192;
+constexpr int MAX_SLOTS = 256;
 // The request's CSR and shifts stay in the caller's device buffers (local ids); arena vertex
 // vbeg + v is the request's vertex v.
 struct SlotInfo {

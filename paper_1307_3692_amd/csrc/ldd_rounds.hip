@@ -691,7 +691,9 @@ __global__ __launch_bounds__(RT) void k_rounds_persistent(const LaunchBlock* __r
 // (count << 32 | arcs), so top-down splits exactly the top-down slots' arcs evenly over the
 // grid, and those counters are each slot's frontier statistics for the next step.
 
-constexpr int SABUF = 2048;  // entries of a block's LDS append buffer in server mode
+constexpr int SABUF = 1792;  // entries of a block's LDS append buffer in server mode
+static_assert(SABUF >= RT, "a whole tile's appends fit the buffer");
+static_assert(MAX_SLOTS <= 256, "buffered appends keep their slot in one byte");
 enum { TD_SKIP = 0, TD_ROUND = 1, TD_SWEEP = 2 };
 
 struct SrvAppend {
