@@ -238,3 +238,19 @@ def test_poll_until_done(ldd):
         assert got is not None
         check(ldd, got, rp, ci, s, "rmat-12 polled")
         assert got[2]["t_admit"] >= got[2]["t_submit"] and got[2]["t_done"] >= got[2]["t_admit"]
+
+
+def test_more_requests_than_one_wave_of_slots(ldd):
+    """Several hundred requests submitted at once, so that more than one wave's worth of slots
+    (64) is on the device together: the per-slot prefix sums of a step are carried from wave to
+    wave, and every request still gets exactly its own result."""
+    reqs = request_mix(seed=11, count=300)
+    with ldd.Server(max_vertices=1 << 22, max_arcs=1 << 24) as srv:
+        tensors = [to_dev(rp, ci, s) for rp, ci, s, _ in reqs]
+        tickets = [srv.submit(*d) for d in tensors]
+        results = [srv.wait(t) for t in tickets]
+        info = srv.info()
+    log(f"server info {info}")
+    for got, (rp, ci, s, name) in zip(results, reqs):
+        check(ldd, got, rp, ci, s, name)
+    assert info["max_slots"] == 256 and info["max_active"] > 64
