@@ -12,10 +12,12 @@ shifts, inputs resident in HBM.  Prints one JSON line.
   batched      512 uneven graphs in one call (one launch per round for all) vs one call each
   served       a Poisson stream of RMAT 12-22 requests through the serving engine vs the same
                stream one decomposition at a time (FIFO), latency p50 / p99 and capacity
-  cpu_baseline the CPU oracle (single-threaded Dijkstra) on the same graph and shifts
+  grid2d       grid 64x64: p50 / p99 latency over 1000 calls
+  grid3d       grid 256^3: time, round steps, the round kernel's roofline
+  cpu_baseline the CPU oracle's bucketed search (single-threaded, one core) on the same graph and shifts
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rmat-24]
-                       [--no-batch] [--no-serve] [--no-cpu-baseline] [--copy-probe]
+                       [--no-batch] [--no-serve] [--no-grids] [--no-cpu-baseline] [--copy-probe]
 """
 import argparse
 import hashlib
@@ -69,16 +71,9 @@ def measured_traffic(workload):
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline(rp, ci, s, name):
-    """The CPU oracle (single-threaded Dijkstra over the same integer keys) on the same graph
-    and shifts as the GPU run: one run, timed on this host."""
-    import oracle  # the CPU leg only
-    t = time.perf_counter()
-    oracle.decompose(rp, ci, s)
-    dt = time.perf_counter() - t
-    return {"value": round(ci.size / 2 / dt / 1e9, 6), "unit": "GTEPS", "cores": 1, "kind": "oracle",
-            "sample": f"{name}: the whole benchmark graph and shifts (n={rp.size - 1}, m={ci.size // 2}), "
-                      f"1 run of {dt:.1f} s on one core of this host"}
+def sha_array(a):
+    import numpy as np
+    return hashlib.sha256(np.ascontiguousarray(a).view(np.uint8)).hexdigest()
 
 
 def pack(graphs):
@@ -153,28 +148,22 @@ def run_batched(reps: int, plain_reps: int = 1):
     return out
 
 
-SERVE_SCALES = tuple(range(12, 23))
-SERVE_BETAS = (0.05, 0.1, 0.2)
-
-
 def serve_templates(dev):
     """The request pool: RMAT scale 12..22 (edge factor 16, graph seed 1000 + scale), each with
     beta in {0.05, 0.1, 0.2} and two shift seeds: 66 distinct (graph, beta, shifts) templates,
-    device-resident.  A request stream draws templates uniformly, so its scale is uniform in
-    12..22 and its beta uniform in the three values."""
+    device-resident (inputs.serve_recipe).  A request stream draws templates uniformly, so its
+    scale is uniform in 12..22 and its beta uniform in the three values."""
     import torch
 
     import inputs
-    out = []
-    for scale in SERVE_SCALES:
-        rp, ci = inputs.rmat(scale, 16, seed=1000 + scale)
-        d_rp, d_ci = torch.from_numpy(rp).to(dev), torch.from_numpy(ci).to(dev)
-        for j, beta in enumerate(SERVE_BETAS):
-            for k in range(2):
-                seed = 1000 + 6 * (scale - 12) + 2 * j + k
-                d_s = torch.from_numpy(inputs.make_shifts(rp.size - 1, beta, seed)).to(dev)
-                out.append({"scale": scale, "beta": beta, "seed": seed, "n": rp.size - 1, "m": ci.size // 2,
-                            "rp": d_rp, "ci": d_ci, "s": d_s})
+    out, graphs = [], {}
+    for scale, beta, gseed, sseed in inputs.serve_recipe():
+        if scale not in graphs:
+            rp, ci = inputs.rmat(scale, 16, seed=gseed)
+            graphs = {scale: (torch.from_numpy(rp).to(dev), torch.from_numpy(ci).to(dev), rp.size - 1, ci.size // 2)}
+        d_rp, d_ci, n, m = graphs[scale]
+        d_s = torch.from_numpy(inputs.make_shifts(n, beta, sseed)).to(dev)
+        out.append({"scale": scale, "beta": beta, "seed": sseed, "n": n, "m": m, "rp": d_rp, "ci": d_ci, "s": d_s})
     return out
 
 
@@ -244,10 +233,19 @@ def run_serving(n_requests: int = 2000, budget_gib: float = 16.0, small_budget_g
     log(f"serve: {len(tm)} templates generated in {time.time() - t:.1f}s")
     rng = np.random.default_rng(1)
     req = rng.integers(0, len(tm), n_requests)
-    ref = []
-    for x in tm:  # plain results, the identity check for every served request
+    # reference results: the plain path's result of each template, checked against the oracle's
+    # digest of that template; every served request is then compared with it on the device
+    gold = None
+    if os.path.exists(GOLDEN):
+        with open(GOLDEN) as f:
+            gold = json.load(f).get("serve-templates", {}).get("templates")
+    ref, ref_oracle = [], []
+    for i, x in enumerate(tm):
         c, cut = ldd.decompose(x["rp"], x["ci"], x["s"], x["beta"])
         ref.append((c, cut))
+        if gold:
+            ref_oracle.append(sha_array(c.cpu().numpy()) == gold[i]["sha_centre"] and cut == gold[i]["cut"])
+    templates_vs_oracle = bool(gold) and all(ref_oracle)
     # plain: the request stream one ldd_decompose at a time
     service = np.zeros(n_requests)
     plain_out = {}
@@ -305,6 +303,7 @@ def run_serving(n_requests: int = 2000, budget_gib: float = 16.0, small_budget_g
         "plain_at_own_80pct_p99_ms": round(float(np.percentile(plain_own, 99)), 3),
         "speedup_capacity_vs_plain": round(cap / plain_cap, 2),
         "identical_to_plain": bool(same_c and same_p),
+        "bit_exact": bool(same_c and same_p and templates_vs_oracle),
     })
     if small_budget_gib:
         with ldd.Server(hbm_budget_bytes=int(small_budget_gib * 2**30)) as srv:
@@ -320,6 +319,154 @@ def run_serving(n_requests: int = 2000, budget_gib: float = 16.0, small_budget_g
     return out
 
 
+def golden(name):
+    if not os.path.exists(GOLDEN):
+        return None
+    with open(GOLDEN) as f:
+        return json.load(f).get(name)
+
+
+def roofline_block(stats, n, kernel, traffic=None):
+    """The round kernel's algorithmic bytes per launch over its average launch duration (HIP
+    events around the launches on their stream, idle launches included)."""
+    t_rounds = stats["ms_rounds"] * 1e-3
+    launches = max(1, stats["steps"])
+    alg = algorithmic_bytes(stats, n)
+    achieved = (alg / launches) / (t_rounds / launches) / 1e9 if t_rounds > 0 else 0.0
+    return {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "algorithmic_bytes_per_launch": int(alg / launches), "launches": launches,
+            "avg_launch_us": round(t_rounds / launches * 1e6, 3)}
+
+
+def run_single(ldd, name, steps, warmup, opts, keep_host=False):
+    """Decompose one named workload `steps` times after `warmup` untimed calls, inputs resident
+    in HBM; per-call latency from the host clock, stage times and counters from the library."""
+    import numpy as np
+    import torch
+
+    import inputs
+    t = time.time()
+    rp, ci, s, beta = inputs.workload(name)
+    n, m = rp.size - 1, ci.size // 2
+    log(f"workload {name}: n={n} m={m} beta={beta} generated in {time.time() - t:.1f}s")
+    dev = torch.device("cuda:0")
+    d_rp, d_ci, d_s = (torch.from_numpy(a).to(dev) for a in (rp, ci, s))
+    centre = torch.empty(n, dtype=torch.int32, device=dev)
+    for _ in range(warmup):
+        ldd.decompose(d_rp, d_ci, d_s, beta, centre=centre, **opts)
+    torch.cuda.synchronize()
+    lat, stage = [], []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        a = time.perf_counter()
+        _, cut, stats = ldd.decompose(d_rp, d_ci, d_s, beta, centre=centre, stats=True, **opts)
+        lat.append(time.perf_counter() - a)
+        stage.append(stats)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    gold = golden(name)
+    bit_exact = None
+    if gold:
+        bit_exact = bool(sha_array(centre.cpu().numpy()) == gold["sha_centre"] and cut == gold["cut"])
+    # medians of the per-call device times (HIP events)
+    med = {k: float(np.median([st[k] for st in stage])) for k in ("ms_prep", "ms_rounds", "ms_finalize", "ms_cut")}
+    stats = dict(stage[-1])
+    stats.update(med)
+    out = {"name": name, "n": n, "m": m, "beta": beta, "lat": lat, "ms_per_step": total / steps * 1e3,
+           "stats": stats, "bit_exact": bit_exact, "cut": cut}
+    if keep_host:
+        out["host"] = (rp, ci, s)
+    del d_rp, d_ci, d_s, centre
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_grid2d(ldd, calls=1000):
+    """The small high-overhead case: grid 64x64, beta 0.1, shift seed 1; latency of each of
+    `calls` decompositions (host clock around the call, which returns with the cut on the host)."""
+    import numpy as np
+    r = run_single(ldd, "grid2d-64x64", calls, 20, {})
+    lat = np.array(r["lat"]) * 1e3
+    st = r["stats"]
+    out = {"workload": "grid2d-64x64: 4-neighbour grid 64x64 (4096 vertices, 8064 edges), beta 0.1, shift seed 1",
+           "calls": calls, "p50_ms": round(float(np.percentile(lat, 50)), 4),
+           "p99_ms": round(float(np.percentile(lat, 99)), 4), "mean_ms": round(float(lat.mean()), 4),
+           "decompositions_per_s": round(1e3 / float(lat.mean()), 1),
+           "rounds": st["rounds"], "steps": st["steps"], "tail_sweeps": st["tail_iters"],
+           "bit_exact": r["bit_exact"]}
+    log(f"grid2d: {out}")
+    return out
+
+
+def run_grid3d(ldd, steps=5):
+    """The high-diameter case: grid 256^3, beta 0.02, shift seed 1: time per decomposition, round
+    steps and the round kernel's roofline."""
+    import numpy as np
+    r = run_single(ldd, "grid3d-256", steps, 2, {})
+    st = r["stats"]
+    ms = float(np.median(r["lat"])) * 1e3
+    out = {"workload": "grid3d-256: 6-neighbour grid 256^3 (16.7M vertices, 50.1M edges), beta 0.02, shift seed 1",
+           "ms": round(ms, 3), "ms_per_step": round(r["ms_per_step"], 3),
+           "gteps": round(r["m"] / (ms * 1e-3) / 1e9, 3),
+           "rounds": st["rounds"], "rounds_bound": st["rounds_bound"], "tail_sweeps": st["tail_iters"],
+           "steps": st["steps"], "us_per_step": round(st["ms_rounds"] * 1e3 / max(1, st["steps"]), 2),
+           "arcs_examined": st["arcs_examined"],
+           "stage_ms": {k: round(st[k], 4) for k in ("ms_prep", "ms_rounds", "ms_finalize", "ms_cut")},
+           "roofline": roofline_block(st, r["n"], "k_round_step_lb", measured_traffic("grid3d-256")),
+           "bit_exact": r["bit_exact"]}
+    log(f"grid3d: {out}")
+    return out
+
+
+def cpu_host_info():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count(), len(os.sched_getaffinity(0))
+
+
+CPU_CHILD = r"""
+import os, sys, time, json
+sys.path.insert(0, sys.argv[1])
+os.sched_setaffinity(0, {int(sys.argv[3])})
+import numpy as np
+import inputs, oracle
+rp, ci, s, beta = inputs.workload(sys.argv[2])
+times = []
+for _ in range(int(sys.argv[4])):
+    t = time.perf_counter()
+    oracle.decompose_rounds(rp, ci, s)
+    times.append(time.perf_counter() - t)
+print(json.dumps({"times": times, "m": int(ci.size // 2), "n": int(rp.size - 1)}))
+"""
+
+
+def cpu_baseline(name, runs=3):
+    """The CPU oracle's bucketed search (one integer distance per round, single-threaded) on the
+    same graph and shifts as the GPU run, in a child process pinned to one core: median of
+    `runs` runs, generation excluded."""
+    import subprocess
+    model, ncpu, avail = cpu_host_info()
+    core = sorted(os.sched_getaffinity(0))[-1]
+    p = subprocess.run([sys.executable, "-c", CPU_CHILD, ROOT, name, str(core), str(runs)], capture_output=True,
+                       text=True, check=True)
+    r = json.loads(p.stdout.strip().splitlines()[-1])
+    times = sorted(r["times"])
+    med = times[len(times) // 2]
+    return {"value": round(r["m"] / med / 1e9, 6), "unit": "GTEPS", "cores": 1, "kind": "oracle",
+            "sample": f"{name}: the whole benchmark graph and shifts (n={r['n']}, m={r['m']}), bucketed search "
+                      f"(oracle.decompose_rounds), median of {runs} runs ({', '.join(f'{t:.2f}' for t in r['times'])} s) "
+                      f"on one core (pinned to cpu {core}) of this host",
+            "cpu_model": model, "nproc": ncpu, "cpus_available": avail}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -329,6 +476,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-grids", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the steps, copy 1 GiB three times (a plain copy kernel of known size, to "
@@ -345,56 +493,22 @@ def main():
     import numpy as np
     import torch
 
-    import inputs
     import paper_1307_3692_amd as ldd
 
-    t = time.time()
-    rp, ci, s, beta = inputs.workload(args.workload)
-    n, nnz = rp.size - 1, ci.size
-    m = nnz // 2
-    log(f"workload {args.workload}: n={n} m={m} beta={beta} generated in {time.time() - t:.1f}s")
-    dev = torch.device("cuda:0")
-    d_rp, d_ci, d_s = (torch.from_numpy(a).to(dev) for a in (rp, ci, s))
-    centre = torch.empty(n, dtype=torch.int32, device=dev)
     opts = dict(engine=args.engine, direction=args.direction, blocks=args.blocks)
-    for _ in range(args.warmup):
-        ldd.decompose(d_rp, d_ci, d_s, beta, centre=centre, **opts)
-    torch.cuda.synchronize()
-    lat, rounds_ms, stats = [], [], None
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        a = time.perf_counter()
-        _, cut, stats = ldd.decompose(d_rp, d_ci, d_s, beta, centre=centre, stats=True, **opts)
-        lat.append(time.perf_counter() - a)
-        rounds_ms.append(stats["ms_rounds"])
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t0
-    ms_step = total / args.steps * 1e3
-    log(f"steps {args.steps}: {ms_step:.3f} ms/step, rounds kernel {np.mean(rounds_ms):.3f} ms, stats {stats}")
-
-    bit_exact = None
-    if os.path.exists(GOLDEN):
-        with open(GOLDEN) as f:
-            gold = json.load(f).get(args.workload)
-        if gold:
-            got = centre.cpu().numpy()
-            bit_exact = bool(hashlib.sha256(got.view(np.uint8)).hexdigest() == gold["sha_centre"]
-                             and cut == gold["cut"])
-
+    r = run_single(ldd, args.workload, args.steps, args.warmup, opts)
+    stats, n, m = r["stats"], r["n"], r["m"]
+    ms_step = r["ms_per_step"]
+    log(f"steps {args.steps}: {ms_step:.3f} ms/step, stats {stats}")
     if args.copy_probe:
+        dev = torch.device("cuda:0")
         a = torch.ones(1 << 28, dtype=torch.int32, device=dev)
         b = torch.empty_like(a)
         for _ in range(3):
             b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    # the round kernel: algorithmic bytes per launch over its average launch duration (HIP
-    # events around the launches on their stream)
-    t_rounds = float(np.mean(rounds_ms)) * 1e-3
-    launches = max(1, stats["steps"])
-    alg = algorithmic_bytes(stats, n)
-    achieved = (alg / launches) / (t_rounds / launches) / 1e9 if t_rounds > 0 else 0.0
-    traffic = measured_traffic(args.workload)
+    lat = np.array(r["lat"])
     out = {
         "metric": METRIC,
         "value": round(m / (ms_step * 1e-3) / 1e9, 4),
@@ -408,21 +522,23 @@ def main():
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "n": n, "m": m, "beta": beta, "graph_seed": 1, "shift_seed": 1,
+        "config": {"workload": args.workload, "n": n, "m": m, "beta": r["beta"], "graph_seed": 1, "shift_seed": 1,
                    "engine": ["auto(launch)", "persistent", "launch"][args.engine], "parallelism": "single-gpu"},
         "decompositions_per_s": round(1e3 / ms_step, 3),
         "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 4),
         "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 4),
-        "bit_exact": bit_exact,
+        "bit_exact": r["bit_exact"],
         "rounds": stats["rounds"], "td_rounds": stats["td_rounds"], "bu_rounds": stats["bu_rounds"],
-        "tail_sweeps": stats["tail_iters"], "stage_ms": {k: round(stats[k], 4) for k in ("ms_prep", "ms_rounds", "ms_finalize", "ms_cut")},
-        "roofline": {"bound": "hbm", "kernel": "k_round_step_lb", "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "algorithmic_bytes_per_launch": int(alg / launches),
-                     "launches": launches, "avg_launch_us": round(t_rounds / launches * 1e6, 3)},
+        "tail_sweeps": stats["tail_iters"],
+        "arcs_examined": stats["arcs_examined"],
+        "examined_arcs_per_s": round(stats["arcs_examined"] / (ms_step * 1e-3), 1),
+        "stage_ms": {k: round(stats[k], 4) for k in ("ms_prep", "ms_rounds", "ms_finalize", "ms_cut")},
+        "roofline": roofline_block(stats, n, "k_round_step_lb", measured_traffic(args.workload)),
     }
+    if not args.no_grids:
+        out["grid2d"] = run_grid2d(ldd)
+        out["grid3d"] = run_grid3d(ldd)
     if not args.no_batch:
-        del d_rp, d_ci, d_s, centre
         torch.cuda.empty_cache()
         out["batched"] = run_batched(reps=5)
     if not args.no_serve:
@@ -430,7 +546,7 @@ def main():
         out["served"] = run_serving(args.serve_requests)
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on {args.workload} ...")
-        out["cpu_baseline"] = cpu_baseline(rp, ci, s, args.workload)
+        out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)
 
 

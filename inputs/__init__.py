@@ -169,6 +169,24 @@ def batch_graphs(num_graphs: int = 512, seed: int = 1, **kw):
     return graphs
 
 
+SERVE_SCALES = tuple(range(12, 23))
+SERVE_BETAS = (0.05, 0.1, 0.2)
+
+
+def serve_recipe():
+    """The serving workload's request templates: RMAT scale 12..22 (edge factor 16, graph seed
+    1000 + scale), each with beta in {0.05, 0.1, 0.2} and two shift seeds
+    1000 + 6 (scale - 12) + 2 j + k (j the beta's index, k = 0, 1): 66 templates, as a list of
+    (scale, beta, graph_seed, shift_seed).  A request stream draws templates uniformly, so its
+    scale is uniform in 12..22 and its beta uniform in the three values."""
+    out = []
+    for scale in SERVE_SCALES:
+        for j, beta in enumerate(SERVE_BETAS):
+            for k in range(2):
+                out.append((scale, beta, 1000 + scale, 1000 + 6 * (scale - 12) + 2 * j + k))
+    return out
+
+
 # ------------------------------------------------------------------------------------------
 # Named single-graph workloads
 # ------------------------------------------------------------------------------------------

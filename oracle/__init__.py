@@ -7,6 +7,8 @@ ctypes wrapper over ``liblddoracle.so`` (``ldd_oracle.c``):
 
 * :func:`decompose` -- every vertex's centre and the cut, by Dijkstra from the super source
   of Sec. 5 over (length, first vertex) pairs in lexicographic order;
+* :func:`decompose_rounds` -- the same result by the bucketed search of Sec. 5 (one bucket per
+  integer distance, Dial's bucket queue), the single-threaded CPU baseline the benchmark times;
 * :func:`centre_of` -- one vertex's centre by the definition of Algorithm 2 (BFS from v,
   lexicographic argmin of the shifted distance, Eq. (1));
 * :func:`cut` -- cut edges of an assignment (Def. 1.1);
@@ -69,6 +71,8 @@ def _load():
     vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
     lib.oracle_decompose_mut.argtypes = [i64, vp, vp, vp, vp, vp, vp, i32]
     lib.oracle_decompose_mut.restype = i32
+    lib.oracle_decompose_rounds.argtypes = [i64, vp, vp, vp, vp, vp, vp]
+    lib.oracle_decompose_rounds.restype = i32
     lib.oracle_centre_of.argtypes = [i64, vp, vp, vp, i64, vp, vp]
     lib.oracle_centre_of.restype = i32
     lib.oracle_cut.argtypes = [i64, vp, vp, vp]
@@ -100,6 +104,19 @@ def decompose(row_ptr, col_idx, shift_fix, mutation: int = MUT_NONE):
                                       length.ctypes.data, ctypes.addressof(cut_v), mutation)
     if rc != OK:
         raise OracleError(f"oracle_decompose failed with code {rc}")
+    return centre, length, int(cut_v.value)
+
+
+def decompose_rounds(row_ptr, col_idx, shift_fix):
+    """As :func:`decompose`, by the bucketed search of Sec. 5 (one integer distance per round)."""
+    n, rp, ci, sf = _arrays(row_ptr, col_idx, shift_fix)
+    centre = np.empty(n, dtype=np.int32)
+    length = np.empty(n, dtype=np.int64)
+    cut_v = ctypes.c_int64(0)
+    rc = _load().oracle_decompose_rounds(n, rp.ctypes.data, ci.ctypes.data, sf.ctypes.data, centre.ctypes.data,
+                                         length.ctypes.data, ctypes.addressof(cut_v))
+    if rc != OK:
+        raise OracleError(f"oracle_decompose_rounds failed with code {rc}")
     return centre, length, int(cut_v.value)
 
 

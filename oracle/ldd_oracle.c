@@ -77,6 +77,8 @@ static int valid_shifts(int64_t n, const int64_t* shift_fix) {
   return 1;
 }
 
+int64_t oracle_cut(int64_t n, const int32_t* row_ptr, const int32_t* col_idx, const int32_t* centre);
+
 /* lexicographic (length, first vertex) order */
 static inline int lex_less(int64_t ka, int32_t oa, int64_t kb, int32_t ob) {
   return ka < kb || (ka == kb && oa < ob);
@@ -225,6 +227,104 @@ int oracle_decompose_mut(int64_t n, const int32_t* row_ptr, const int32_t* col_i
 int oracle_decompose(int64_t n, const int32_t* row_ptr, const int32_t* col_idx, const int64_t* shift_fix,
                      int32_t* centre, int64_t* len_out, int64_t* cut_out) {
   return oracle_decompose_mut(n, row_ptr, col_idx, shift_fix, centre, len_out, cut_out, MUT_NONE);
+}
+
+/* ---------------------------------------------------------------------------------------- */
+/* The same result by the bucketed search of Sec. 5: lengths are processed one integer       */
+/* distance ("round") at a time, with one bucket per integer part (Dial's bucket queue).     */
+/* Vertex u's own source arc has length off[u] = Delta - shift[u] and enters at round        */
+/* off[u] >> 20; a graph edge adds one unit (2^20), so a label first reached in round r      */
+/* carries a length in [r 2^20, (r+1) 2^20).  Round r takes every own arc of its bucket and  */
+/* every offer relayed from a vertex settled in round r-1, keeps per vertex the              */
+/* lexicographically smallest (length, first vertex) pair, settles every vertex touched,     */
+/* and relays the settled labels plus one unit to unsettled neighbours for round r+1.  Only  */
+/* round r-1 can relay lengths of integer part r, so each round's minimum is final.          */
+/* ---------------------------------------------------------------------------------------- */
+int oracle_decompose_rounds(int64_t n, const int32_t* row_ptr, const int32_t* col_idx, const int64_t* shift_fix,
+                            int32_t* centre, int64_t* len_out, int64_t* cut_out) {
+  if (!valid_csr(n, row_ptr, col_idx) || (n > 0 && (!shift_fix || !centre))) return OR_BAD_ARG;
+  if (!valid_shifts(n, shift_fix)) return OR_BAD_ARG;
+  if (n == 0) {
+    if (cut_out) *cut_out = 0;
+    return OR_OK;
+  }
+  int64_t delta = 0;
+  for (int64_t u = 0; u < n; ++u)
+    if (shift_fix[u] > delta) delta = shift_fix[u];
+  const int64_t rounds = (delta >> 20) + 1; /* own arcs enter in rounds 0 .. rounds-1 */
+  int64_t* len = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+  int32_t* org = (int32_t*)malloc((size_t)n * sizeof(int32_t));
+  int64_t* done = (int64_t*)malloc((size_t)n * sizeof(int64_t)); /* round settled, -1 = not yet */
+  int64_t* bstart = (int64_t*)calloc((size_t)rounds + 1, sizeof(int64_t));
+  int32_t* bucket = (int32_t*)malloc((size_t)n * sizeof(int32_t));
+  int32_t* touched = (int32_t*)malloc((size_t)n * sizeof(int32_t));
+  int32_t* settled = (int32_t*)malloc((size_t)n * sizeof(int32_t));
+  if (!len || !org || !done || !bstart || !bucket || !touched || !settled) {
+    free(len); free(org); free(done); free(bstart); free(bucket); free(touched); free(settled);
+    return OR_NO_MEM;
+  }
+  /* bucket of each own arc by the integer part of its length (counting sort) */
+  for (int64_t u = 0; u < n; ++u) bstart[((delta - shift_fix[u]) >> 20) + 1]++;
+  for (int64_t r = 0; r < rounds; ++r) bstart[r + 1] += bstart[r];
+  for (int64_t u = 0; u < n; ++u) {
+    const int64_t r = (delta - shift_fix[u]) >> 20;
+    bucket[bstart[r]++] = (int32_t)u;
+  }
+  for (int64_t r = rounds; r > 0; --r) bstart[r] = bstart[r - 1];
+  bstart[0] = 0;
+  for (int64_t v = 0; v < n; ++v) {
+    done[v] = -1;
+    len[v] = INT64_MAX;
+    org[v] = -1;
+  }
+  /* touched[0 .. nt) : vertices holding an offer for the current round (from relays) */
+  int64_t nt = 0, left = n;
+  for (int64_t r = 0; left > 0; ++r) {
+    /* own arcs of bucket r compete with the relayed offers already in len / org */
+    if (r < rounds)
+      for (int64_t i = bstart[r]; i < bstart[r + 1]; ++i) {
+        const int32_t u = bucket[i];
+        if (done[u] >= 0) continue;
+        const int64_t l = delta - shift_fix[u];
+        if (org[u] < 0) touched[nt++] = u; /* first offer this round */
+        if (lex_less(l, u, len[u], org[u] < 0 ? INT32_MAX : org[u])) {
+          len[u] = l;
+          org[u] = u;
+        }
+      }
+    /* settle every touched vertex: its minimum over this round's offers is final */
+    int64_t ns = 0;
+    for (int64_t i = 0; i < nt; ++i) {
+      const int32_t v = touched[i];
+      done[v] = r;
+      settled[ns++] = v;
+    }
+    left -= ns;
+    nt = 0;
+    /* relay to unsettled neighbours: offers for round r+1 */
+    for (int64_t i = 0; i < ns; ++i) {
+      const int32_t v = settled[i];
+      const int64_t l = len[v] + S_ONE;
+      for (int32_t a = row_ptr[v]; a < row_ptr[v + 1]; ++a) {
+        const int32_t w = col_idx[a];
+        if (done[w] >= 0) continue;
+        if (org[w] < 0) {
+          touched[nt++] = w;
+          len[w] = l;
+          org[w] = org[v];
+        } else if (lex_less(l, org[v], len[w], org[w])) {
+          len[w] = l;
+          org[w] = org[v];
+        }
+      }
+    }
+  }
+  for (int64_t v = 0; v < n; ++v) centre[v] = org[v];
+  if (len_out)
+    for (int64_t v = 0; v < n; ++v) len_out[v] = len[v];
+  if (cut_out) *cut_out = oracle_cut(n, row_ptr, col_idx, centre);
+  free(len); free(org); free(done); free(bstart); free(bucket); free(touched); free(settled);
+  return OR_OK;
 }
 
 /* ---------------------------------------------------------------------------------------- */

@@ -41,6 +41,8 @@ namespace ldd {
 
 constexpr u64 S_ONE = (u64)1 << FIX;
 constexpr int MAX_BATCH = 16;         // requests per admission / finishing launch
+// most arcs of the requests on the device at once (32-bit arc offsets of a step's top-down split)
+constexpr unsigned long long MAX_ACTIVE_ARCS = 0xffffffffull;
 constexpr int ADM_T = 1024;           // threads of the admission kernels
 constexpr int FIN_T = 256;            // threads of the finishing kernel (its arc tile)
 constexpr unsigned ERR_ROUNDS = 64u;  // the request needs more rounds than the server takes
@@ -630,6 +632,9 @@ struct ldd_server {
   std::thread engine;
   double t0 = 0;
   long long admitted = 0, completed = 0, max_active = 0, rebases = 0;
+  // arcs of the requests on the device: a step splits the top-down slots' frontier arcs over the
+  // grid with 32-bit prefix sums, so admission keeps this sum below 2^32
+  long long active_arcs = 0;
 };
 
 namespace {
@@ -953,6 +958,7 @@ ldd_status engine_loop(ldd_server* srv) {
       {
         std::lock_guard<std::mutex> lk(srv->mu);
         srv->valloc.give(r->vbeg, vrange(r->q.n));
+        srv->active_arcs -= r->q.nnz;
         srv->slot_req[r->slot] = nullptr;
         r->status = status_of(err);
         r->cut = r->status == LDD_OK ? (int64_t)rp.cut : 0;
@@ -1007,9 +1013,11 @@ ldd_status engine_loop(ldd_server* srv) {
         for (int i = 0; i < nslots && slot < 0; ++i)
           if (!srv->slot_req[i]) slot = i;
         if (slot < 0) break;
+        if (srv->active_arcs + r->q.nnz > (long long)MAX_ACTIVE_ARCS) break;
         const long long vb = srv->valloc.take(vrange(r->q.n));
         if (vb < 0) break;
         srv->queue.pop_front();
+        srv->active_arcs += r->q.nnz;
         r->vbeg = vb;
         r->slot = slot;
         r->r0 = r0;

@@ -103,3 +103,25 @@ def small_cases(seed=0, count=60):
         for kind in KINDS:
             cases.append((rp, ci, shift_family(rng, rp.size - 1, kind), f"g{i}-{kind}"))
     return cases
+
+
+def multigraph(rng, rp, ci, max_copies=3, loops=0.2):
+    """The simple graph (rp, ci) with every edge repeated 1..max_copies times (both arcs each
+    time) and a self-loop arc at about a fraction `loops` of the vertices, as a CSR built without
+    deduplication.  Returns (row_ptr, col_idx, copies) where copies[a] is the multiplicity of the
+    simple graph's arc a."""
+    n = rp.size - 1
+    src = np.repeat(np.arange(n), np.diff(rp))
+    lo = src < ci
+    eu, ev = src[lo], ci[lo]
+    k = rng.integers(1, max_copies + 1, eu.size)
+    s = np.concatenate([np.repeat(eu, k), np.repeat(ev, k)])
+    d = np.concatenate([np.repeat(ev, k), np.repeat(eu, k)])
+    lv = np.flatnonzero(rng.random(n) < loops)
+    s, d = np.concatenate([s, lv]), np.concatenate([d, lv])
+    order = np.argsort(s, kind="stable")
+    s, d = s[order], d[order]
+    mrp = np.zeros(n + 1, np.int32)
+    np.add.at(mrp, s + 1, 1)
+    copies = {(int(a), int(b)): int(c) for a, b, c in zip(eu, ev, k)}
+    return np.cumsum(mrp).astype(np.int32), d.astype(np.int32), copies

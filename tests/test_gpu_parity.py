@@ -17,7 +17,7 @@ import pytest
 
 import inputs
 import oracle
-from graphs import S, small_cases
+from graphs import S, multigraph, small_cases
 
 pytestmark = pytest.mark.gpu
 
@@ -265,6 +265,26 @@ def test_degenerate_graphs(ldd):
         for mode in MODES[:3]:
             got, cut, _ = run(ldd, rp, ci, s, **mode)
             assert np.array_equal(got, want_c) and cut == want_cut
+
+
+def test_self_loops_and_repeated_arcs(ldd):
+    """A CSR with self-loops and every edge stored 1-3 times (as the header allows): centres as
+    for the simple graph, the cut counting every copy of a cut edge and no self-loop, equal to
+    the oracle in every schedule."""
+    rng = np.random.default_rng(33)
+    cases = []
+    for rp, ci, s, name in small_cases(seed=5, count=12)[::4]:
+        mrp, mci, _ = multigraph(rng, rp, ci)
+        cases.append((mrp, mci, s, "multi-" + name))
+    rp, ci = inputs.rmat(14, 16, seed=77)
+    mrp, mci, _ = multigraph(rng, rp, ci, max_copies=2, loops=0.05)
+    cases.append((mrp, mci, inputs.make_shifts(rp.size - 1, 0.1, 77), "multi-rmat-14"))
+    for rp, ci, s, name in cases:
+        want_c, _, want_cut = oracle.decompose(rp, ci, s)
+        for mode in MODES:
+            got, cut, _ = run(ldd, rp, ci, s, **mode)
+            assert np.array_equal(got, want_c), (name, mode, np.nonzero(got != want_c)[0][:10])
+            assert cut == want_cut, (name, mode, cut, want_cut)
 
 
 def test_errors_are_reported(ldd):

@@ -25,8 +25,8 @@ import oracle
 
 
 
-from graphs import (S, all_pairs, brute_force, complete, cycle, disjoint_union, path, random_graph,  # noqa: E402
-                    shift_family, small_cases, star, KINDS)
+from graphs import (S, all_pairs, brute_force, complete, cycle, disjoint_union, multigraph, path,  # noqa: E402
+                    random_graph, shift_family, small_cases, star, KINDS)
 
 
 CASES = small_cases()
@@ -46,6 +46,31 @@ def test_oracle_matches_brute_force():
             d = all_pairs(rp, ci)
             expect = s.max() + S * d[c, np.arange(s.size)].astype(np.int64) - s[c]
             assert np.array_equal(length, expect), name
+
+
+def test_rounds_oracle_matches_brute_force():
+    """The bucketed search of Sec. 5 (one integer distance per round) gives the definition's
+    centres, lengths and cut on every small case, tie-heavy shifts included."""
+    for rp, ci, s, name in CASES:
+        c, length, cut = oracle.decompose_rounds(rp, ci, s)
+        bc, bcut = brute_force(rp, ci, s)
+        assert np.array_equal(c, bc), name
+        assert cut == bcut, name
+        if s.size:
+            d = all_pairs(rp, ci)
+            expect = s.max() + S * d[c, np.arange(s.size)].astype(np.int64) - s[c]
+            assert np.array_equal(length, expect), name
+
+
+def test_rounds_oracle_certified_on_larger_graphs():
+    """On graphs too large for brute force, the bucketed search passes the certificate and
+    agrees with the heap-based search."""
+    for rp, ci, s in (inputs.workload("rmat-16")[:3], inputs.workload("grid3d-64")[:3],
+                      (*inputs.er(20000, 3.0, 5), inputs.make_shifts(20000, 0.3, 5))):
+        c, length, cut = oracle.decompose_rounds(rp, ci, s)
+        assert oracle.certify(rp, ci, s, c) == (oracle.OK, -1)
+        c2, length2, cut2 = oracle.decompose(rp, ci, s)
+        assert np.array_equal(c, c2) and np.array_equal(length, length2) and cut == cut2
 
 
 def test_centre_of_matches_brute_force():
@@ -78,6 +103,22 @@ def test_hypothesis_random_graphs():
         assert np.array_equal(c, bc) and cut == bcut
 
     run()
+
+
+def test_multigraph_self_loops_and_repeated_arcs():
+    """Self-loops and repeated edges change no distance, so the centres are those of the simple
+    graph (brute force); the cut counts every copy of a cut edge and never a self-loop (Def. 1.1
+    counted per stored edge)."""
+    rng = np.random.default_rng(21)
+    for _ in range(40):
+        n = int(rng.integers(2, 30))
+        rp, ci = random_graph(rng, n, float(rng.choice([0.1, 0.3])))
+        mrp, mci, copies = multigraph(rng, rp, ci)
+        s = shift_family(rng, n, str(rng.choice(KINDS)))
+        c, _, cut = oracle.decompose(mrp, mci, s)
+        bc, _ = brute_force(rp, ci, s)
+        assert np.array_equal(c, bc)
+        assert cut == sum(k for (u, v), k in copies.items() if bc[u] != bc[v])
 
 
 # ------------------------------------------------------------------------------------------
