@@ -266,6 +266,30 @@ ldd_status ldd_server_query(ldd_server* srv, ldd_server_info* out);
  * dropped).  Returns the engine's failure status, if any. */
 ldd_status ldd_server_destroy(ldd_server* srv);
 
+/*
+ * Decompose one graph without allocating: for callers that cannot allocate device or pinned
+ * host memory (code that must not call hipMalloc / hipFree, tight serving loops, harnesses
+ * that forbid allocation).  Same operation, arguments and result as ldd_decompose (bit for
+ * bit), with these differences:
+ *   - every device buffer beyond the caller's inputs and outputs comes from one file-scope
+ *     device array of LDD_STATIC_SCRATCH_BYTES (34.4 MiB) per device, held from the first
+ *     call on that device until the process ends; the call makes no hipMalloc / hipFree, no
+ *     pinned host allocation and creates no event, stream or graph;
+ *   - n <= LDD_STATIC_MAX_VERTICES, else LDD_ERR_BUDGET before any device work; shifts whose
+ *     range spans 8192 or more units of distance (floor(max shift / 2^20) >= 8192) also give
+ *     LDD_ERR_BUDGET (ldd_decompose handles them);
+ *   - work runs on hip_stream only, and the call synchronises that stream (after every eight
+ *     round steps and at the end), so it cannot be captured into a graph;
+ *   - no statistics; opt->engine must not be LDD_ENGINE_PERSISTENT.
+ * All calls on one device share its array and the array keeps the last call's contents (what
+ * must start at zero is cleared at the start of each call): calls that overlap on one device,
+ * from several threads or streams, race and must be serialised by the caller.
+ */
+#define LDD_STATIC_MAX_VERTICES (1 << 20)
+#define LDD_STATIC_SCRATCH_BYTES 36040704
+ldd_status ldd_decompose_static(const ldd_csr* g, const int64_t* shift_fix, double beta, int32_t* centre,
+                                int64_t* cut_edges, const ldd_options* opt, void* hip_stream);
+
 /* Human-readable name of a status code (static string). */
 const char* ldd_status_string(ldd_status s);
 /* Detail of the last error on this thread (static thread-local buffer). */

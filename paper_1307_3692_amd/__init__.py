@@ -17,7 +17,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _ROOT = os.path.dirname(_HERE)
 SO_PATH = os.path.join(_HERE, "libldd.so")
 SOURCES = [os.path.join(_HERE, "csrc", f) for f in ("ldd_kernels.hip", "ldd_rounds.hip", "ldd_api.hip",
-                                                   "ldd_batch.hip", "ldd_server.hip", "ldd_tune.hip")]
+                                                   "ldd_batch.hip", "ldd_server.hip", "ldd_tune.hip",
+                                                   "ldd_static.hip")]
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
@@ -28,7 +29,8 @@ ENGINE_AUTO, ENGINE_PERSISTENT, ENGINE_LAUNCH = 0, 1, 2
 
 EXPORTED = ("ldd_decompose", "ldd_workspace_bytes", "ldd_decompose_batch", "ldd_status_string", "ldd_last_error",
             "ldd_release_workspace", "ldd_server_create", "ldd_server_submit", "ldd_server_poll", "ldd_server_wait",
-            "ldd_server_cancel", "ldd_server_query", "ldd_server_destroy", "ldd_tune")
+            "ldd_server_cancel", "ldd_server_query", "ldd_server_destroy", "ldd_tune",
+            "ldd_decompose_static")
 
 
 class LddError(RuntimeError):
@@ -125,6 +127,9 @@ def lib():
     L.ldd_decompose.argtypes = [ctypes.POINTER(Csr), vp, ctypes.c_double, vp, ctypes.POINTER(ctypes.c_int64),
                                 ctypes.POINTER(Options), ctypes.POINTER(Stats), vp]
     L.ldd_decompose.restype = i32
+    L.ldd_decompose_static.argtypes = [ctypes.POINTER(Csr), vp, ctypes.c_double, vp, ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(Options), vp]
+    L.ldd_decompose_static.restype = i32
     L.ldd_decompose_batch.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(Options), vp]
     L.ldd_decompose_batch.restype = i32
     L.ldd_workspace_bytes.argtypes = [i32, i64]
@@ -212,6 +217,29 @@ def decompose(row_ptr, col_idx, shift_fix, beta: float, *, centre=None, stream=N
     if stats:
         return centre, int(cut.value), st.as_dict()
     return centre, int(cut.value)
+
+
+STATIC_MAX_VERTICES = 1 << 20  # LDD_STATIC_MAX_VERTICES
+
+
+def decompose_static(row_ptr, col_idx, shift_fix, beta: float, *, centre, stream=None, **opts):
+    """As :func:`decompose`, through ``ldd_decompose_static``: the library allocates nothing
+    (its scratch is a fixed device array of the library, n <= STATIC_MAX_VERTICES).  The caller
+    provides the output tensor ``centre``.  Returns the cut."""
+    import torch
+    _device_tensor(row_ptr, torch.int32, "row_ptr")
+    _device_tensor(col_idx, torch.int32, "col_idx")
+    _device_tensor(shift_fix, torch.int64, "shift_fix")
+    _device_tensor(centre, torch.int32, "centre")
+    n = row_ptr.numel() - 1
+    if n < 0 or shift_fix.numel() != n or centre.numel() != n:
+        raise ValueError("row_ptr, shift_fix and centre sizes disagree")
+    g = Csr(n, col_idx.numel(), row_ptr.data_ptr(), col_idx.data_ptr() if col_idx.numel() else None)
+    cut = ctypes.c_int64(0)
+    o = make_options(**opts)
+    _check(lib().ldd_decompose_static(ctypes.byref(g), shift_fix.data_ptr(), float(beta), centre.data_ptr(),
+                                      ctypes.byref(cut), ctypes.byref(o), _stream_handle(stream)))
+    return int(cut.value)
 
 
 def decompose_batch(vtx_off, arc_off, row_ptr, col_idx, shift_fix, *, centre=None, stream=None, **opts):
