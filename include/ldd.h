@@ -55,7 +55,8 @@ typedef enum {
   LDD_ERR_BUDGET = 5,      /* server: request larger than the whole memory budget          */
   LDD_ERR_CANCELLED = 6,   /* server: request cancelled before it ran                      */
   LDD_ERR_INTERNAL = 7,    /* round watchdog or barrier time-out fired (a library bug)     */
-  LDD_ERR_PENDING = 8      /* server: request not finished yet                             */
+  LDD_ERR_PENDING = 8,     /* server: request not finished yet                             */
+  LDD_ERR_RETRIES = 9      /* verified decomposition: no draw met the bounds               */
 } ldd_status;
 
 /* One CSR graph in device memory (see conventions above). */
@@ -68,8 +69,10 @@ typedef struct {
 
 /* Traversal direction policy of a round (the result never depends on it). */
 enum { LDD_DIR_AUTO = 0, LDD_DIR_TOP_DOWN = 1, LDD_DIR_BOTTOM_UP = 2 };
-/* Round engine: one persistent kernel with grid barriers, or one launch per phase. */
-enum { LDD_ENGINE_AUTO = 0, LDD_ENGINE_PERSISTENT = 1, LDD_ENGINE_LAUNCH = 2 };
+/* Round engine: one persistent kernel with grid barriers, one launch per round step over the
+ * whole GPU, or one workgroup running every round of the graph (workgroup barriers only).  AUTO
+ * takes the workgroup engine for graphs of at most 2^15 arcs and the launch engine otherwise. */
+enum { LDD_ENGINE_AUTO = 0, LDD_ENGINE_PERSISTENT = 1, LDD_ENGINE_LAUNCH = 2, LDD_ENGINE_WORKGROUP = 3 };
 
 typedef struct {
   int32_t direction;      /* LDD_DIR_*                                                    */
@@ -80,12 +83,16 @@ typedef struct {
   int32_t bu_to_td;       /* switch back when frontier vertices * bu_to_td < n (0 = default 24)                 */
   int32_t tail_vertices;  /* finish by label correction once unsettled vertices * this <= active vertices
                              (0 = default 32, -1 = never)                                                      */
-  int32_t batch_mode;     /* ldd_decompose_batch: LDD_BATCH_UNION (one launch per round for all graphs)  */
-                          /* or LDD_BATCH_SEQUENTIAL (one ldd_decompose per graph, for comparison)      */
+  int32_t batch_mode;     /* ldd_decompose_batch: LDD_BATCH_* (below)                                    */
   int32_t reserved[8];
 } ldd_options;
 
-enum { LDD_BATCH_UNION = 0, LDD_BATCH_SEQUENTIAL = 1 };
+/* Batch engines: AUTO = WORKGROUP (one workgroup per graph, the largest graphs first, every
+ * graph's rounds with workgroup barriers only; a graph whose shifts span 4096 or more units of
+ * distance runs alone on the launch engine); SEQUENTIAL = one ldd_decompose per graph (the plain
+ * path, for comparison); UNION = the disjoint union of all graphs on the launch engine, one
+ * launch per round for all graphs. */
+enum { LDD_BATCH_AUTO = 0, LDD_BATCH_SEQUENTIAL = 1, LDD_BATCH_UNION = 2, LDD_BATCH_WORKGROUP = 3 };
 
 /* Counters of the last call (filled when a non-NULL pointer is passed). */
 typedef struct {
@@ -289,6 +296,64 @@ ldd_status ldd_server_destroy(ldd_server* srv);
 #define LDD_STATIC_SCRATCH_BYTES 36040704
 ldd_status ldd_decompose_static(const ldd_csr* g, const int64_t* shift_fix, double beta, int32_t* centre,
                                 int64_t* cut_edges, const ldd_options* opt, void* hip_stream);
+
+/*
+ * Shifts delta_u ~ Exp(beta) for u < n in fixed point (Algorithm 1 step 1, Sec. 2; the
+ * exponential density beta exp(-beta x) of Sec. 3), shift_fix[u] = floor(2^20 delta_u), drawn by
+ * inverting the CDF at a uniform U_u from a counter-based generator: draw u of seed s depends
+ * only on (s, u) (O(n) work, O(1) depth, as the proof of Theorem 1.1 in Sec. 5 uses).  The recipe
+ * (SplitMix64 draws, U = (x >> 11) 2^-53, -ln(1 - U) by an integer-only base-2 logarithm to 47
+ * bits, then floor((T * ln2 * 2^-27) / beta) in correctly rounded double arithmetic) gives the same
+ * bits on the host and on the device.
+ *   ldd_make_shifts         host:   out_host int64[n] (caller's host memory).
+ *   ldd_make_shifts_device  device: out_device int64[n] (caller's device memory), enqueued on
+ *                           hip_stream; returns once enqueued.
+ * LDD_ERR_INVALID_ARG for n < 0, a NULL buffer with n > 0, or beta not finite and > 0.
+ */
+ldd_status ldd_make_shifts(int32_t n, double beta, uint64_t seed, int64_t* out_host);
+ldd_status ldd_make_shifts_device(int32_t n, double beta, uint64_t seed, int64_t* out_device, void* hip_stream);
+
+/*
+ * Las Vegas decomposition (the proof of Theorem 1.1, Sec. 5): draw the shifts on the device
+ * (ldd_make_shifts_device with seed, seed + 1, ...), decompose, verify the partition, and draw
+ * again until it meets both bounds of a (beta, O(log n / beta)) decomposition:
+ *   cut_edges  <= cut_factor * beta * m                  (m = nnz / 2; Cor. 4.5 bounds the
+ *                                                          expected cut by (1 - e^-beta) m)
+ *   max_v dist(c(v), v) <= radius_factor * ln(n) / beta  (Lemma 4.2: every shift is below
+ *                                                          (d+1) ln n / beta w.h.p., and a
+ *                                                          vertex's distance to its centre is
+ *                                                          at most the centre's shift)
+ * Verification is O(m) work on the device: the cut of the output pass and the largest distance
+ * to a centre, read off the exact labels.  Defaults: cut_factor 2 (by Markov's inequality a
+ * draw fails the cut bound with probability below 1/2), radius_factor 3 (d = 2), 16 attempts.
+ *   g          graph in device memory (as ldd_decompose).
+ *   shift_fix  device int64[n], OUT: the shifts of the last draw (caller's memory).
+ *   centre     device int32[n], OUT: the decomposition of the last draw.
+ *   vopt, opt  NULL for defaults.
+ *   report     host, OUT (may be NULL): attempts, acceptance, the last draw's seed, cut and radius.
+ * Returns LDD_OK when the last draw was accepted, LDD_ERR_RETRIES when max_attempts draws all
+ * failed (the outputs then hold the last draw), or the decomposition's own errors.
+ */
+typedef struct {
+  double cut_factor;     /* accept when cut_edges <= cut_factor * beta * m (0 = 2)            */
+  double radius_factor;  /* accept when every distance to a centre <= radius_factor ln n / beta (0 = 3) */
+  int32_t max_attempts;  /* draws before giving up (0 = 16)                                    */
+  int32_t reserved[7];
+} ldd_verify_options;
+
+typedef struct {
+  int32_t attempts;      /* draws made; the outputs hold the last one                         */
+  int32_t accepted;      /* 1: the last draw met both bounds                                  */
+  uint64_t seed;         /* seed of the last draw                                             */
+  int64_t cut_edges;     /* cut of the last draw                                              */
+  int64_t max_radius;    /* largest dist(c(v), v) of the last draw                            */
+  double cut_bound;      /* cut_factor * beta * m                                             */
+  double radius_bound;   /* radius_factor * ln(n) / beta                                      */
+} ldd_verify_report;
+
+ldd_status ldd_decompose_verified(const ldd_csr* g, double beta, uint64_t seed, int64_t* shift_fix, int32_t* centre,
+                                  const ldd_verify_options* vopt, const ldd_options* opt, ldd_verify_report* report,
+                                  void* hip_stream);
 
 /* Human-readable name of a status code (static string). */
 const char* ldd_status_string(ldd_status s);

@@ -25,7 +25,9 @@ _SRC = os.path.join(_HERE, "gen.c")
 FIX_SHIFT = 20
 FIX_ONE = 1 << FIX_SHIFT
 
-# purpose tags for ldd_in_u01 draws made from Python (graph/shift tags 1..5 live in gen.c)
+# purpose tags: gen.c's own streams (shifts 1, RMAT 2, relabel 3, ER 4, RGG 5) and the draws
+# made from Python
+TAG_SHIFT = 1
 TAG_BATCH = 16
 TAG_SERVE = 17
 

@@ -52,17 +52,47 @@ double ldd_in_u01(uint64_t seed, uint64_t tag, uint64_t i) { return u01(ldd_in_s
 
 /* ------------------------------------------------------------------------------------------ */
 /* Shifts: delta_u ~ Exp(beta) (rate beta, mean 1/beta; Sec. 3 density beta*exp(-beta x)),  */
-/* sampled by inversion of the CDF 1 - exp(-beta x): delta = -log1p(-U)/beta, U in [0,1).     */
-/* Quantised by truncation: shift_fix = floor(delta * 2^20).                                   */
+/* sampled by inversion of the CDF 1 - exp(-beta x): delta = -ln(1 - U)/beta, U in [0,1),     */
+/* quantised by truncation: shift_fix = floor(delta * 2^20).                                   */
+/*                                                                                            */
+/* The logarithm is evaluated with integers only, so that any implementation of this recipe  */
+/* (CPU or GPU) gives the same bits: with U = (x >> 11) 2^-53 and M = 2^53 - (x >> 11), in    */
+/* [1, 2^53], -ln(1-U) = ln 2 * (53 - log2 M).  log2 M = e + log2(m), e = floor(log2 M) and   */
+/* m in [1, 2) held as a 64-bit fraction; the bits of log2(m) come from repeated squaring    */
+/* (square m: if m^2 >= 2 the next bit is 1 and m becomes m^2 / 2, else it is 0 and m becomes */
+/* m^2), 47 of them, truncated.  T = 2^47 (53 - e) - bits is an integer below 2^53, so it    */
+/* converts to double exactly; then                                                            */
+/*     shift_fix = floor( (T * (ln 2 * 2^-27)) / beta )                                        */
+/* with one IEEE double multiplication and one division, each correctly rounded (the factor  */
+/* ln 2 * 2^-27 folds 2^-47 of T and 2^20 of the fixed point into the constant ln 2).         */
 /* ------------------------------------------------------------------------------------------ */
+static inline uint64_t neglog2_q47(uint64_t x) {
+  const uint64_t M = (1ULL << 53) - (x >> 11);
+  const int e = 63 - __builtin_clzll(M);
+  uint64_t m = M << (63 - e); /* m / 2^63 in [1, 2) */
+  uint64_t bits = 0;
+  for (int k = 0; k < 47; ++k) {
+    const unsigned __int128 sq = (unsigned __int128)m * m; /* sq / 2^126 in [1, 4) */
+    bits <<= 1;
+    if (sq >> 127) {
+      bits |= 1;
+      m = (uint64_t)(sq >> 64);
+    } else {
+      m = (uint64_t)(sq >> 63);
+    }
+  }
+  return ((uint64_t)(53 - e) << 47) - bits;
+}
+
+#define LN2_2M27 0x1.62e42fefa39efp-28 /* ln 2 * 2^-27 (the double nearest ln 2, scaled) */
+
 int ldd_in_make_shifts(int64_t n, double beta, uint64_t seed, int64_t* out) {
   if (n < 0 || (out == NULL && n > 0) || !(beta > 0.0) || !isfinite(beta)) return 1;
   const uint64_t st = ldd_in_stream(seed, TAG_SHIFT);
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
-    const double u = u01(st, (uint64_t)i);
-    const double d = -log1p(-u) / beta;
-    out[i] = (int64_t)floor(d * FIX_ONE);
+    const double t = (double)neglog2_q47(draw(st, (uint64_t)i));
+    out[i] = (int64_t)floor((t * LN2_2M27) / beta);
   }
   return 0;
 }

@@ -18,19 +18,20 @@ _ROOT = os.path.dirname(_HERE)
 SO_PATH = os.path.join(_HERE, "libldd.so")
 SOURCES = [os.path.join(_HERE, "csrc", f) for f in ("ldd_kernels.hip", "ldd_rounds.hip", "ldd_api.hip",
                                                    "ldd_batch.hip", "ldd_server.hip", "ldd_tune.hip",
-                                                   "ldd_static.hip")]
+                                                   "ldd_static.hip", "ldd_shifts.hip", "ldd_block.hip")]
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 # status codes (ldd_status)
-OK, ERR_INVALID_ARG, ERR_OOM, ERR_OVERFLOW, ERR_HIP, ERR_BUDGET, ERR_CANCELLED, ERR_INTERNAL, ERR_PENDING = range(9)
+(OK, ERR_INVALID_ARG, ERR_OOM, ERR_OVERFLOW, ERR_HIP, ERR_BUDGET, ERR_CANCELLED, ERR_INTERNAL, ERR_PENDING,
+ ERR_RETRIES) = range(10)
 DIR_AUTO, DIR_TOP_DOWN, DIR_BOTTOM_UP = 0, 1, 2
-ENGINE_AUTO, ENGINE_PERSISTENT, ENGINE_LAUNCH = 0, 1, 2
+ENGINE_AUTO, ENGINE_PERSISTENT, ENGINE_LAUNCH, ENGINE_WORKGROUP = 0, 1, 2, 3
 
 EXPORTED = ("ldd_decompose", "ldd_workspace_bytes", "ldd_decompose_batch", "ldd_status_string", "ldd_last_error",
             "ldd_release_workspace", "ldd_server_create", "ldd_server_submit", "ldd_server_poll", "ldd_server_wait",
             "ldd_server_cancel", "ldd_server_query", "ldd_server_destroy", "ldd_tune",
-            "ldd_decompose_static")
+            "ldd_decompose_static", "ldd_make_shifts", "ldd_make_shifts_device", "ldd_decompose_verified")
 
 
 class LddError(RuntimeError):
@@ -59,6 +60,20 @@ class Stats(ctypes.Structure):
                 ("arcs_examined", ctypes.c_int64), ("n_active", ctypes.c_int64),
                 ("ms_prep", ctypes.c_float), ("ms_rounds", ctypes.c_float), ("ms_finalize", ctypes.c_float),
                 ("ms_cut", ctypes.c_float), ("steps", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class VerifyOptions(ctypes.Structure):
+    _fields_ = [("cut_factor", ctypes.c_double), ("radius_factor", ctypes.c_double), ("max_attempts", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 7)]
+
+
+class VerifyReport(ctypes.Structure):
+    _fields_ = [("attempts", ctypes.c_int32), ("accepted", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("cut_edges", ctypes.c_int64), ("max_radius", ctypes.c_int64), ("cut_bound", ctypes.c_double),
+                ("radius_bound", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -130,6 +145,14 @@ def lib():
     L.ldd_decompose_static.argtypes = [ctypes.POINTER(Csr), vp, ctypes.c_double, vp, ctypes.POINTER(ctypes.c_int64),
                                        ctypes.POINTER(Options), vp]
     L.ldd_decompose_static.restype = i32
+    L.ldd_make_shifts.argtypes = [i32, ctypes.c_double, ctypes.c_uint64, vp]
+    L.ldd_make_shifts.restype = i32
+    L.ldd_make_shifts_device.argtypes = [i32, ctypes.c_double, ctypes.c_uint64, vp, vp]
+    L.ldd_make_shifts_device.restype = i32
+    L.ldd_decompose_verified.argtypes = [ctypes.POINTER(Csr), ctypes.c_double, ctypes.c_uint64, vp, vp,
+                                         ctypes.POINTER(VerifyOptions), ctypes.POINTER(Options),
+                                         ctypes.POINTER(VerifyReport), vp]
+    L.ldd_decompose_verified.restype = i32
     L.ldd_decompose_batch.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(Options), vp]
     L.ldd_decompose_batch.restype = i32
     L.ldd_workspace_bytes.argtypes = [i32, i64]
@@ -177,11 +200,11 @@ def _device_tensor(t, dtype, name):
     return t
 
 
-BATCH_UNION, BATCH_SEQUENTIAL = 0, 1
+BATCH_AUTO, BATCH_SEQUENTIAL, BATCH_UNION, BATCH_WORKGROUP = 0, 1, 2, 3
 
 
 def make_options(direction=DIR_AUTO, engine=ENGINE_AUTO, validate=False, blocks=0, td_to_bu=0, bu_to_td=0,
-                 tail_vertices=0, batch_mode=BATCH_UNION) -> Options:
+                 tail_vertices=0, batch_mode=BATCH_AUTO) -> Options:
     o = Options()
     o.direction, o.engine, o.validate, o.blocks = direction, engine, int(validate), blocks
     o.td_to_bu, o.bu_to_td, o.tail_vertices, o.batch_mode = td_to_bu, bu_to_td, tail_vertices, batch_mode
@@ -217,6 +240,56 @@ def decompose(row_ptr, col_idx, shift_fix, beta: float, *, centre=None, stream=N
     if stats:
         return centre, int(cut.value), st.as_dict()
     return centre, int(cut.value)
+
+
+def make_shifts(n: int, beta: float, seed: int):
+    """Host shifts of the library's sampler (``ldd_make_shifts``): numpy int64[n]."""
+    import numpy as np
+    out = np.empty(n, dtype=np.int64)
+    _check(lib().ldd_make_shifts(int(n), float(beta), seed & (2**64 - 1), out.ctypes.data if n else None))
+    return out
+
+
+def make_shifts_device(n: int, beta: float, seed: int, *, out=None, stream=None):
+    """Device shifts of the library's sampler (``ldd_make_shifts_device``): torch int64[n] on
+    the current GPU, enqueued on the stream (default: torch's current stream)."""
+    import torch
+    if out is None:
+        out = torch.empty(n, dtype=torch.int64, device="cuda")
+    else:
+        _device_tensor(out, torch.int64, "out")
+        if out.numel() != n:
+            raise ValueError("out has the wrong size")
+    _check(lib().ldd_make_shifts_device(int(n), float(beta), seed & (2**64 - 1), out.data_ptr() if n else None,
+                                        _stream_handle(stream)))
+    return out
+
+
+def decompose_verified(row_ptr, col_idx, beta: float, seed: int, *, cut_factor: float = 0.0,
+                       radius_factor: float = 0.0, max_attempts: int = 0, stream=None, **opts):
+    """Las Vegas decomposition (``ldd_decompose_verified``): shifts drawn on the device from
+    seed, seed + 1, ... until the cut and every distance to a centre meet their bounds.
+    Returns ``(centre, shift_fix, report dict)``; ``report["accepted"]`` is 0 when every draw
+    failed (status LDD_ERR_RETRIES), in which case the outputs hold the last draw."""
+    import torch
+    _device_tensor(row_ptr, torch.int32, "row_ptr")
+    _device_tensor(col_idx, torch.int32, "col_idx")
+    n = row_ptr.numel() - 1
+    if n < 0:
+        raise ValueError("row_ptr is empty")
+    centre = torch.empty(n, dtype=torch.int32, device=row_ptr.device)
+    shifts = torch.empty(n, dtype=torch.int64, device=row_ptr.device)
+    g = Csr(n, col_idx.numel(), row_ptr.data_ptr(), col_idx.data_ptr() if col_idx.numel() else None)
+    v = VerifyOptions()
+    v.cut_factor, v.radius_factor, v.max_attempts = cut_factor, radius_factor, max_attempts
+    o = make_options(**opts)
+    rep = VerifyReport()
+    status = lib().ldd_decompose_verified(ctypes.byref(g), float(beta), seed & (2**64 - 1), shifts.data_ptr(),
+                                          centre.data_ptr(), ctypes.byref(v), ctypes.byref(o), ctypes.byref(rep),
+                                          _stream_handle(stream))
+    if status != ERR_RETRIES:
+        _check(status)
+    return centre, shifts, rep.as_dict()
 
 
 STATIC_MAX_VERTICES = 1 << 20  # LDD_STATIC_MAX_VERTICES

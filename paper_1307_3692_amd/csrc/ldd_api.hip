@@ -5,11 +5,13 @@
 #include <cstdio>
 #include <algorithm>
 #include <atomic>
+#include <cmath>
 #include <cstring>
 #include <mutex>
 #include <vector>
 
 #include "../../include/ldd.h"
+#include "ldd_block.h"
 #include "ldd_internal.h"
 #include "ldd_kernels.h"
 
@@ -40,6 +42,7 @@ extern "C" const char* ldd_status_string(ldd_status s) {
     case LDD_ERR_CANCELLED: return "cancelled";
     case LDD_ERR_INTERNAL: return "internal error";
     case LDD_ERR_PENDING: return "pending";
+    case LDD_ERR_RETRIES: return "no draw met the bounds";
   }
   return "unknown status";
 }
@@ -83,6 +86,7 @@ struct HostMirror {  // pinned, mapped host memory
   Ctrl ctrl;
   u64 ex_part[RT];
   Report report;   // written by the device as a decomposition ends
+  BlockOut bout;   // the workgroup engine's result for one graph
 };
 
 constexpr int CHUNK = 8;     // steps per graph replay
@@ -104,7 +108,9 @@ struct Workspace {
   void* stamp_clean = nullptr;  // ... while this equals stamp.p
   Buf hist, cursor, wake_off, next_ne, mat, qmax;        // per round / q-bucket (mat: per bucket and prep block)
   Buf cand, cand_cnt;                                    // per prep block: first-window candidates
-  Buf ctrl, st, qcnt, lr_part, lb, ex_part;
+  Buf ctrl, st, qcnt, lr_part, lb, ex_part, vr;
+  // workgroup engine: queues and wake order (3 ints per vertex), jobs, order, results, job counter
+  Buf bk_wq, bk_jobs, bk_order, bk_out, bk_cnt;
   // batch: union CSR with global ids, adjusted shifts, graph of each vertex, per-graph data
   Buf b_rp, b_col, b_shift, b_gid, b_off, b_dg, b_cut;
   HostMirror* host = nullptr;
@@ -212,7 +218,7 @@ extern "C" void ldd_release_workspace(void) {
   w->graphs.clear();
   for (Buf* b : {&w->P, &w->qv0, &w->qv1, &w->qa0, &w->qa1, &w->wake_ord, &w->stamp, &w->hub_bits, &w->hist,
                  &w->cursor, &w->wake_off, &w->next_ne, &w->mat, &w->qmax, &w->cand, &w->cand_cnt, &w->ctrl, &w->st, &w->qcnt, &w->lr_part,
-                 &w->lb, &w->ex_part, &w->b_rp, &w->b_col, &w->b_shift, &w->b_gid, &w->b_off, &w->b_dg,
+                 &w->lb, &w->ex_part, &w->vr, &w->bk_wq, &w->bk_jobs, &w->bk_order, &w->bk_out, &w->bk_cnt, &w->b_rp, &w->b_col, &w->b_shift, &w->b_gid, &w->b_off, &w->b_dg,
                  &w->b_cut}) {
     if (b->p) (void)hipFree(b->p);
     b->p = nullptr;
@@ -271,7 +277,7 @@ extern "C" ldd_status ldd_decompose(const ldd_csr* g, const int64_t* shift_fix, 
   }
   ldd_options o{};
   if (opt) o = *opt;
-  if (o.direction < 0 || o.direction > 2 || o.engine < 0 || o.engine > 2 || o.blocks < 0) {
+  if (o.direction < 0 || o.direction > 2 || o.engine < 0 || o.engine > 3 || o.blocks < 0) {
     ldd_set_error("bad options");
     return LDD_ERR_INVALID_ARG;
   }
@@ -425,7 +431,7 @@ static ldd_status decompose_run(Workspace& w, const ldd_csr* g, const int64_t* s
   rep->out_ready = 0;
   rep->tail_hint = 0;
 
-  const int engine = o.engine == LDD_ENGINE_AUTO ? LDD_ENGINE_LAUNCH : o.engine;
+  const int engine = o.engine == LDD_ENGINE_PERSISTENT ? LDD_ENGINE_PERSISTENT : LDD_ENGINE_LAUNCH;
   int blocks = o.blocks > 0 ? o.blocks : 2 * w.num_cu;
   if (blocks > RT) blocks = RT;  // the per-block minima of a step are reduced by one block
   if (engine == LDD_ENGINE_PERSISTENT && blocks > w.max_coresident) blocks = w.max_coresident;
@@ -601,12 +607,200 @@ static ldd_status decompose_run(Workspace& w, const ldd_csr* g, const int64_t* s
   return LDD_OK;
 }
 
+// ------------------------------------------------------------------------------------------
+// the workgroup engine for one graph: one workgroup runs all rounds (small graphs)
+// ------------------------------------------------------------------------------------------
+// graphs the automatic engine choice gives to one workgroup: few enough arcs that one workgroup
+// reads them faster than round steps over the whole GPU synchronise
+constexpr long long BLOCK_AUTO_ARCS = 1ll << 15;
+
+static const ldd_status REDO_MULTI = static_cast<ldd_status>(101);  // internal: shifts too wide for a workgroup
+
+static ldd_status block_status(unsigned err, u64 delta, int n) {
+  if (err & (ERR_BAD_SHIFT | ERR_BAD_ROWPTR | ERR_BAD_COL)) return finish_error(err);
+  if (err & BLK_OVERFLOW) {
+    ldd_set_error("labels need (Delta + 2^20) << %d < 2^64 (Delta = %llu)", ceil_log2(n) < 1 ? 1 : ceil_log2(n),
+                  (unsigned long long)delta);
+    return LDD_ERR_OVERFLOW;
+  }
+  if (err & BLK_WIDE) return REDO_MULTI;
+  if (err) {
+    ldd_set_error("workgroup engine error flags 0x%x", err);
+    return LDD_ERR_INTERNAL;
+  }
+  return LDD_OK;
+}
+
+__global__ void k_block_job_single(int n, long long nnz, const int* row_ptr, const int* col, const long long* shift,
+                                   int* centre, u64* P, int* wq, int tail_den, BlockJob* job) {
+  if (threadIdx.x || blockIdx.x) return;
+  BlockJob j;
+  j.n = n;
+  j.nnz = nnz;
+  j.row_ptr = row_ptr;
+  j.col = col;
+  j.shift = shift;
+  j.centre = centre;
+  j.P = P;
+  j.wake = wq;
+  j.q0 = wq + n;
+  j.q1 = wq + 2 * (long long)n;
+  j.tail_den = tail_den;
+  *job = j;
+}
+
+static int tail_den_of(const ldd_options& o) {
+  return o.tail_vertices < 0 ? 0 : (o.tail_vertices > 0 ? o.tail_vertices : 32);
+}
+
+static ldd_status decompose_block(Workspace& w, const ldd_csr* g, const int64_t* shift_fix, int32_t* centre,
+                                  int64_t* cut_edges, const ldd_options& opt, ldd_stats* stats, hipStream_t st) {
+  const int n = g->n;
+  const size_t nv = (size_t)n;
+  ldd_status s = ws_setup(w);
+  if (s != LDD_OK) return s;
+  if ((s = grow(w.P, nv * 8)) || (s = grow(w.bk_wq, nv * 12)) || (s = grow(w.bk_jobs, sizeof(BlockJob))) ||
+      (s = grow(w.bk_out, sizeof(BlockOut))) || (s = grow(w.bk_cnt, 8)))
+    return s;
+  HIP_TRY(hipStreamWaitEvent(st, w.ev[2], 0));  // after any step a previous call left queued
+  HIP_TRY(hipEventRecord(w.ev[0], st));
+  hipLaunchKernelGGL(k_block_job_single, dim3(1), dim3(64), 0, st, n, (long long)g->nnz, g->row_ptr, g->col_idx,
+                     (const long long*)shift_fix, centre, (u64*)w.P.p, (int*)w.bk_wq.p, tail_den_of(opt),
+                     (BlockJob*)w.bk_jobs.p);
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, (u64*)w.bk_cnt.p, 1ll, 0ull);
+  HIP_TRY(hipEventRecord(w.ev[1], st));
+  hipLaunchKernelGGL(k_block_decompose, dim3(1), dim3(1024), 0, st, (const BlockJob*)w.bk_jobs.p, (const int*)nullptr,
+                     1, (unsigned*)w.bk_cnt.p, (BlockOut*)w.bk_out.p);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipEventRecord(w.ev[2], st));
+  HIP_TRY(hipMemcpyAsync(&w.host->bout, w.bk_out.p, sizeof(BlockOut), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  const BlockOut o = w.host->bout;
+  w.host->report.delta = o.delta;  // read by the verification pass
+  s = block_status(o.err, o.delta, n);
+  if (s != LDD_OK) return s;
+  if (cut_edges) *cut_edges = (int64_t)(o.cut_arcs / 2);
+  if (stats) {
+    stats->rounds = (int32_t)o.rounds;
+    stats->rounds_bound = (int32_t)((o.delta >> FIX) + 1);
+    stats->td_rounds = (int32_t)o.rounds;
+    stats->bu_rounds = 0;
+    stats->tail_iters = (int32_t)o.sweeps;
+    stats->tail_round = o.sweeps ? (int32_t)o.rounds : -1;
+    stats->blocks = 1;
+    stats->steps = 1;
+    stats->delta = (int64_t)o.delta;
+    stats->pieces = (int64_t)o.pieces;
+    stats->max_frontier = 0;
+    stats->arcs_examined = (int64_t)o.examined;
+    stats->n_active = (int64_t)o.n_active;
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, w.ev[0], w.ev[1]);
+    stats->ms_prep = ms;
+    (void)hipEventElapsedTime(&ms, w.ev[1], w.ev[2]);
+    stats->ms_rounds = ms;
+    stats->ms_finalize = 0;
+    stats->ms_cut = 0;
+  }
+  return LDD_OK;
+}
+
 static ldd_status decompose_impl(Workspace& w, const ldd_csr* g, const int64_t* shift_fix, int32_t* centre,
                                  int64_t* cut_edges, const ldd_options& o, ldd_stats* stats, hipStream_t st,
                                  const BatchView* bv) {
+  const bool block = !bv && (o.engine == LDD_ENGINE_WORKGROUP ||
+                             (o.engine == LDD_ENGINE_AUTO && g->nnz <= BLOCK_AUTO_ARCS));
+  if (block) {
+    ldd_status s = decompose_block(w, g, shift_fix, centre, cut_edges, o, stats, st);
+    if (s != REDO_MULTI) return s;
+  }
   ldd_status s = decompose_run(w, g, shift_fix, centre, cut_edges, o, stats, st, bv, false);
   if (s == REDO_WIDE) s = decompose_run(w, g, shift_fix, centre, cut_edges, o, stats, st, bv, true);
   return s;
+}
+
+// ------------------------------------------------------------------------------------------
+// Las Vegas: draw, decompose, verify, draw again (proof of Theorem 1.1, Sec. 5)
+// ------------------------------------------------------------------------------------------
+extern "C" ldd_status ldd_decompose_verified(const ldd_csr* g, double beta, uint64_t seed, int64_t* shift_fix,
+                                             int32_t* centre, const ldd_verify_options* vopt, const ldd_options* opt,
+                                             ldd_verify_report* report, void* hip_stream) {
+  g_err[0] = 0;
+  if (!g || g->n < 0 || g->nnz < 0 || g->nnz >= (1ll << 31)) {
+    ldd_set_error("bad graph");
+    return LDD_ERR_INVALID_ARG;
+  }
+  const int n = g->n;
+  if (!(beta > 0.0) || !std::isfinite(beta)) {
+    ldd_set_error("beta must be finite and positive");
+    return LDD_ERR_INVALID_ARG;
+  }
+  if (n > 0 && (!g->row_ptr || !shift_fix || !centre || (g->nnz > 0 && !g->col_idx))) {
+    ldd_set_error("NULL device pointer");
+    return LDD_ERR_INVALID_ARG;
+  }
+  ldd_verify_options v{};
+  if (vopt) v = *vopt;
+  if (v.cut_factor < 0 || v.radius_factor < 0 || v.max_attempts < 0 || !std::isfinite(v.cut_factor) ||
+      !std::isfinite(v.radius_factor)) {
+    ldd_set_error("bad verification options");
+    return LDD_ERR_INVALID_ARG;
+  }
+  const double cut_factor = v.cut_factor > 0 ? v.cut_factor : 2.0;
+  const double radius_factor = v.radius_factor > 0 ? v.radius_factor : 3.0;
+  const int max_attempts = v.max_attempts > 0 ? v.max_attempts : 16;
+  ldd_options o{};
+  if (opt) o = *opt;
+  if (o.direction < 0 || o.direction > 2 || o.engine < 0 || o.engine > 3 || o.blocks < 0) {
+    ldd_set_error("bad options");
+    return LDD_ERR_INVALID_ARG;
+  }
+  ldd_verify_report r{};
+  r.cut_bound = cut_factor * beta * ((double)g->nnz / 2.0);
+  r.radius_bound = n > 1 ? radius_factor * std::log((double)n) / beta : 0.0;
+  if (n == 0) {
+    r.attempts = 1;
+    r.accepted = 1;
+    r.seed = seed;
+    if (report) *report = r;
+    return LDD_OK;
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  Workspace& w = *workspace_for(dev);
+  std::lock_guard<std::mutex> lk(w.mu);
+  ldd_status s = grow(w.vr, 256);
+  if (s != LDD_OK) return s;
+  const int B = ceil_log2(n) < 1 ? 1 : ceil_log2(n);
+  for (int a = 0; a < max_attempts; ++a) {
+    const uint64_t sd = seed + (uint64_t)a;
+    if ((s = ldd_shifts_on_device(n, beta, sd, shift_fix, st))) return s;
+    int64_t cut = 0;
+    if ((s = decompose_impl(w, g, shift_fix, centre, &cut, o, nullptr, st, nullptr))) return s;
+    // the labels of this draw are still in the workspace: the largest distance to a centre
+    const u64 delta = w.host->report.delta;
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, (u64*)w.vr.p, 1ll, 0ull);
+    hipLaunchKernelGGL(k_max_radius, dim3(grid_for(n, 256 * 8, 2048)), dim3(256), 0, st, n, B, (const u64*)w.P.p,
+                       (const long long*)shift_fix, delta, (u64*)w.vr.p);
+    HIP_TRY(hipGetLastError());
+    u64 radius = 0;
+    HIP_TRY(hipMemcpyAsync(&radius, w.vr.p, sizeof(u64), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    r.attempts = a + 1;
+    r.seed = sd;
+    r.cut_edges = cut;
+    r.max_radius = (int64_t)radius;
+    r.accepted = (double)cut <= r.cut_bound && (double)radius <= r.radius_bound;
+    if (r.accepted) break;
+  }
+  if (report) *report = r;
+  if (!r.accepted) {
+    ldd_set_error("no draw of %d met cut <= %.6g and radius <= %.6g (last: cut %lld, radius %lld)", max_attempts,
+                  r.cut_bound, r.radius_bound, (long long)r.cut_edges, (long long)r.max_radius);
+    return LDD_ERR_RETRIES;
+  }
+  return LDD_OK;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -623,6 +817,96 @@ ldd_status ldd_batch_sequential(int32_t num_graphs, const int64_t* vtx_off, cons
                                  hip_stream);
     if (s != LDD_OK) return s;
     if (cut_edges) cut_edges[gi] = cut;
+  }
+  return LDD_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// many graphs at once on the workgroup engine: one workgroup per graph, largest first
+// ------------------------------------------------------------------------------------------
+ldd_status ldd_batch_workgroup(int32_t G, const int64_t* vtx_off, const int64_t* arc_off, const int32_t* row_ptr,
+                               const int32_t* col_idx, const int64_t* shift_fix, int32_t* centre, int64_t* cut_edges,
+                               const ldd_options* opt, void* hip_stream) {
+  const long long N = vtx_off[G];
+  if (N > INT32_MAX) {
+    ldd_set_error("batch too large (%lld vertices)", N);
+    return LDD_ERR_INVALID_ARG;
+  }
+  if (N == 0 || G == 0) {
+    if (cut_edges)
+      for (int g = 0; g < G; ++g) cut_edges[g] = 0;
+    return LDD_OK;
+  }
+  ldd_options o{};
+  if (opt) o = *opt;
+  hipStream_t st = (hipStream_t)hip_stream;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  Workspace& w = *workspace_for(dev);
+  std::vector<int> redo;  // graphs whose shifts span too many rounds for a workgroup
+  {
+    std::lock_guard<std::mutex> lk(w.mu);
+    ldd_status s = ws_setup(w);
+    if (s != LDD_OK) return s;
+    if ((s = grow(w.P, (size_t)N * 8)) || (s = grow(w.bk_wq, (size_t)N * 12)) ||
+        (s = grow(w.bk_jobs, (size_t)G * sizeof(BlockJob))) || (s = grow(w.bk_order, (size_t)G * 4)) ||
+        (s = grow(w.bk_out, (size_t)G * sizeof(BlockOut))) || (s = grow(w.bk_cnt, 8)) ||
+        (s = grow(w.b_off, (size_t)(G + 1) * 16)))
+      return s;
+    // largest graphs (by arcs, then vertices) first, so that the last graphs to start are short
+    std::vector<int> order((size_t)G);
+    for (int g = 0; g < G; ++g) order[g] = g;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+      const long long ea = arc_off[a + 1] - arc_off[a], eb = arc_off[b + 1] - arc_off[b];
+      if (ea != eb) return ea > eb;
+      return vtx_off[a + 1] - vtx_off[a] > vtx_off[b + 1] - vtx_off[b];
+    });
+    long long* d_vo = (long long*)w.b_off.p;
+    long long* d_ao = d_vo + (G + 1);
+    HIP_TRY(hipStreamWaitEvent(st, w.ev[2], 0));  // after any step a previous call left queued
+    HIP_TRY(hipMemcpyAsync(d_vo, vtx_off, (size_t)(G + 1) * 8, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(d_ao, arc_off, (size_t)(G + 1) * 8, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(w.bk_order.p, order.data(), (size_t)G * 4, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_block_jobs, dim3(grid_for(G, 256, 1024)), dim3(256), 0, st, G, N, (const long long*)d_vo,
+                       (const long long*)d_ao, row_ptr, col_idx, (const long long*)shift_fix, centre, (u64*)w.P.p,
+                       (int*)w.bk_wq.p, tail_den_of(o), (BlockJob*)w.bk_jobs.p);
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, (u64*)w.bk_cnt.p, 1ll, 0ull);
+    const int per_cu = o.blocks > 0 ? 0 : 2;
+    int grid = o.blocks > 0 ? o.blocks : per_cu * w.num_cu;
+    if (grid > G) grid = G;
+    hipLaunchKernelGGL(k_block_decompose, dim3(grid), dim3(1024), 0, st, (const BlockJob*)w.bk_jobs.p,
+                       (const int*)w.bk_order.p, G, (unsigned*)w.bk_cnt.p, (BlockOut*)w.bk_out.p);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventRecord(w.ev[2], st));
+    std::vector<BlockOut> outs((size_t)G);
+    HIP_TRY(hipMemcpyAsync(outs.data(), w.bk_out.p, (size_t)G * sizeof(BlockOut), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int g = 0; g < G; ++g) {
+      s = block_status(outs[g].err, outs[g].delta, (int)(vtx_off[g + 1] - vtx_off[g]));
+      if (s == REDO_MULTI) {
+        redo.push_back(g);
+        continue;
+      }
+      if (s != LDD_OK) {
+        char msg[512];
+        snprintf(msg, sizeof(msg), "graph %d: %s", g, ldd_last_error());
+        ldd_set_error("%s", msg);
+        return s;
+      }
+      if (cut_edges) cut_edges[g] = (int64_t)(outs[g].cut_arcs / 2);
+    }
+  }
+  // a graph whose shifts span too many rounds for a workgroup's wake sort: the multi-block engine
+  for (int g : redo) {
+    ldd_csr gg{(int32_t)(vtx_off[g + 1] - vtx_off[g]), arc_off[g + 1] - arc_off[g], row_ptr + vtx_off[g] + g,
+               col_idx + arc_off[g]};
+    ldd_options og = o;
+    og.engine = LDD_ENGINE_LAUNCH;
+    int64_t cut = 0;
+    const ldd_status s = ldd_decompose(&gg, shift_fix + vtx_off[g], 1.0, centre + vtx_off[g], &cut, &og, nullptr,
+                                       hip_stream);
+    if (s != LDD_OK) return s;
+    if (cut_edges) cut_edges[g] = cut;
   }
   return LDD_OK;
 }

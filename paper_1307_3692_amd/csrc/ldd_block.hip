@@ -1,0 +1,500 @@
+// Workgroup-owned decomposition: one workgroup runs every round of one graph, with workgroup
+// barriers between rounds and no grid-wide step.  This is the search of Sec. 5 (Algorithm 2 via
+// the delayed-start breadth-first search), round by round, as the multi-block engine runs it:
+//
+//   preparation  Delta = max shift; labels INF; the vertices with arcs sorted by wake round
+//                w(v) = (Delta - shift[v]) >> 20 (counting sort in LDS)
+//   round r      wake: every vertex of bucket r offers its own label ((Delta - shift[v]) << B) | v;
+//                top-down: every vertex u of F_{r-1} offers P(u) + (2^20 << B) along its arcs;
+//                offers are applied with an atomic minimum on the 64-bit label (exact), and the
+//                first offer a vertex receives appends it to F_r
+//   empty F_r    the next round is the next non-empty wake bucket
+//   output       centre = low B bits of the label (INF: an isolated vertex, its own centre) and
+//                the cut (Def. 1.1)
+//
+// A round costs a few workgroup barriers and a handful of dependent cache accesses instead of a
+// kernel launch and a grid-wide state exchange, so graphs with many rounds and small frontiers
+// (small graphs, high-diameter graphs) run far faster here; a batch runs one graph per workgroup,
+// the largest first, each workgroup taking the next graph when it finishes one.
+//
+// Top-down is arc-balanced inside the workgroup: a chunk of RT frontier entries is staged in LDS
+// (first arc, degree prefix, offer) and every thread takes arcs of the chunk by index, finding its
+// entry by binary search, so a high-degree vertex is shared by all threads.
+#include "ldd_block.h"
+
+namespace ldd {
+
+namespace {
+
+constexpr int BT = 1024;         // threads per workgroup
+constexpr int BNW = BT / WAVE;   // waves per workgroup
+constexpr int WPT = BLOCK_WCAP / BT;  // wake buckets per thread in the scans
+
+struct BlockShared {
+  int woff[BLOCK_WCAP + 1];  // wake bucket offsets (exclusive prefix), then the scatter cursors
+  unsigned pre[BT + 1];      // top-down chunk: exclusive degree prefix
+  int first[BT];             // first arc of each staged entry
+  u64 offer[BT];             // offer of each staged entry
+  u64 red64[BNW];
+  unsigned red32[BNW];
+  int job;
+  int nxt;                   // next non-empty wake bucket (block minimum)
+  unsigned cnt;              // appends to the next frontier in this round
+  unsigned err;
+  u64 delta, n_active;       // preparation results
+  u64 settled, examined;     // round results
+  long long rounds, sweeps;
+};
+
+__device__ __forceinline__ u64 block_max64(u64 v, BlockShared& sh) {
+  v = wave_max_u64(v);
+  __syncthreads();
+  if (lane_id() == 0) sh.red64[threadIdx.x / WAVE] = v;
+  __syncthreads();
+  u64 m = 0;
+#pragma unroll
+  for (int w = 0; w < BNW; ++w) m = sh.red64[w] > m ? sh.red64[w] : m;
+  return m;
+}
+
+__device__ __forceinline__ u64 block_sum64(u64 v, BlockShared& sh) {
+  v = wave_sum_u64(v);
+  __syncthreads();
+  if (lane_id() == 0) sh.red64[threadIdx.x / WAVE] = v;
+  __syncthreads();
+  u64 s = 0;
+#pragma unroll
+  for (int w = 0; w < BNW; ++w) s += sh.red64[w];
+  return s;
+}
+
+// exclusive prefix sum of x over the workgroup; *total receives the sum (all threads call)
+__device__ __forceinline__ unsigned block_excl_scan(unsigned x, BlockShared& sh, unsigned* total) {
+  const unsigned incl = wave_incl_scan(x);
+  const unsigned wid = threadIdx.x / WAVE;
+  __syncthreads();
+  if (lane_id() == WAVE - 1) sh.red32[wid] = incl;
+  __syncthreads();
+  unsigned before = 0, all = 0;
+#pragma unroll
+  for (int w = 0; w < BNW; ++w) {
+    const unsigned t = sh.red32[w];
+    before += w < (int)wid ? t : 0u;
+    all += t;
+  }
+  *total = all;
+  return before + incl - x;
+}
+
+// The first non-empty wake bucket at or after r (D + n + 1 when none is left: past the end);
+// all threads call.  Found by a block-wide minimum over the bucket offsets.
+__device__ __forceinline__ int next_nonempty(BlockShared& sh, int r, int D) {
+  __syncthreads();
+  if (threadIdx.x == 0) sh.nxt = 0x7fffffff;
+  __syncthreads();
+  for (int q = r + (int)threadIdx.x; q <= D; q += BT)
+    if (sh.woff[q + 1] > sh.woff[q]) atomicMin(&sh.nxt, q);
+  __syncthreads();
+  const int q = sh.nxt;
+  __syncthreads();
+  return q <= D ? q : 0x3fffffff;
+}
+
+// A graph's labels are touched by its own workgroup only while it runs, so their loads and atomics
+// need workgroup scope alone (all waves of a workgroup share one CU and its vector L1).
+__device__ __forceinline__ u64 wg_load(const u64* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ u64 wg_min(u64* p, u64 v) {
+  return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ void append(BlockShared& sh, int* next, int v) {
+  const unsigned idx = atomicAdd(&sh.cnt, 1u);
+  next[idx] = v;
+}
+
+// Preparation of one graph: checks, Delta, the vertices with arcs, labels INF, and the wake
+// buckets (counting sort of the vertices with arcs by w(v) = (Delta - shift) >> 20 in LDS, with
+// bucket offsets).  Results in sh (delta, n_active, err, woff).
+__device__ __attribute__((noinline)) void block_prepare(const BlockJob& j, BlockShared& sh) {
+  const int n = j.n;
+  const long long nnz = j.nnz;
+  const int* __restrict__ rp = j.row_ptr;
+  const long long* __restrict__ shift = j.shift;
+  u64* P = j.P;
+  const int tid = threadIdx.x;
+  unsigned err = 0;
+  u64 dmax = 0, active = 0;
+  if (n > 0 && (rp[0] != 0 || (long long)rp[n] != nnz) && tid == 0) err |= ERR_BAD_ROWPTR;
+  for (int v = tid; v < n; v += BT) {
+    const long long s = shift[v];
+    if (s < 0 || s > (1ll << 52)) err |= ERR_BAD_SHIFT;
+    const int a0 = rp[v], a1 = rp[v + 1];
+    if (a1 < a0) err |= ERR_BAD_ROWPTR;
+    active += a1 > a0;
+    dmax = (u64)s > dmax ? (u64)s : dmax;
+    P[v] = INF;
+  }
+  if (tid == 0) sh.err = 0;
+  for (int q = tid; q <= BLOCK_WCAP; q += BT) sh.woff[q] = 0;
+  __syncthreads();
+  if (err) atomicOr(&sh.err, err);
+  const u64 delta = block_max64(dmax, sh);
+  const u64 n_active = block_sum64(active, sh);
+  const int B = n > 1 ? 32 - __builtin_clz((unsigned)(n - 1)) : 1;
+  const u64 D = delta >> FIX;
+  if (tid == 0) {
+    unsigned e = sh.err;
+    if (!e && (delta + ((u64)1 << FIX)) >= ((u64)1 << (64 - B))) e |= BLK_OVERFLOW;
+    else if (!e && D >= (u64)BLOCK_WCAP) e |= BLK_WIDE;
+    sh.err = e;
+    sh.delta = delta;
+    sh.n_active = n_active;
+  }
+  __syncthreads();
+  if (sh.err) return;
+  for (int v = tid; v < n; v += BT)
+    if (rp[v + 1] > rp[v]) atomicAdd(&sh.woff[(int)((delta - (u64)shift[v]) >> FIX)], 1);
+  __syncthreads();
+  {
+    unsigned loc[WPT], sum = 0;
+#pragma unroll
+    for (int i = 0; i < WPT; ++i) {
+      loc[i] = (unsigned)sh.woff[tid * WPT + i];
+      sum += loc[i];
+    }
+    unsigned total;
+    unsigned run = block_excl_scan(sum, sh, &total);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < WPT; ++i) {
+      const unsigned c = loc[i];
+      sh.woff[tid * WPT + i] = (int)run;
+      run += c;
+    }
+    if (tid == 0) sh.woff[BLOCK_WCAP] = (int)total;
+  }
+  __syncthreads();
+  // scatter: woff[q] serves as bucket q's cursor (it ends at the start of bucket q + 1) and is
+  // shifted back by one bucket afterwards
+  for (int v = tid; v < n; v += BT) {
+    if (rp[v + 1] > rp[v]) {
+      const int q = (int)((delta - (u64)shift[v]) >> FIX);
+      j.wake[atomicAdd(&sh.woff[q], 1)] = v;
+    }
+  }
+  __syncthreads();
+  {
+    int vals[WPT];
+#pragma unroll
+    for (int i = 0; i < WPT; ++i) {
+      const int q = tid * WPT + i;
+      vals[i] = q == 0 ? 0 : sh.woff[q - 1];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < WPT; ++i) sh.woff[tid * WPT + i] = vals[i];
+    __syncthreads();
+  }
+}
+
+// Relax the arcs of a staged chunk (ne entries: first arc, degree prefix, offer in LDS; total
+// arcs): every arc offers its entry's label plus one unit to its far end (atomic minimum).  A
+// round appends a far end reached for the first time (old label INF); a tail sweep appends a far
+// end whose label dropped, once per sweep (its stamp takes the sweep's tag).  U arcs per thread
+// are issued together (entries by binary search in LDS, column ids, far labels, minima); one at a
+// time measured fastest (more in flight cost registers and did not pay on batches or small graphs).
+template <bool SWEEP>
+__device__ __forceinline__ void relax_chunk(const BlockJob& j, BlockShared& sh, int* next, unsigned ne,
+                                            unsigned total, int tag) {
+  constexpr int U = 1;
+  const int n = j.n;
+  const long long nnz = j.nnz;
+  const int* __restrict__ col = j.col;
+  u64* P = j.P;
+  const int top = ne > 1 ? 1 << (31 - __builtin_clz(ne - 1)) : 0;
+  for (unsigned base = threadIdx.x; base < total; base += U * BT) {
+    int w[U];
+    u64 off[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const unsigned a = base + (unsigned)k * BT;
+      int lo = 0;  // last entry with pre <= a (steps from the largest power of two below ne)
+      for (int step = top; step >= 1; step >>= 1)
+        if (lo + step < (int)ne && sh.pre[lo + step] <= a) lo += step;
+      const long long arc = (long long)sh.first[lo] + (a - sh.pre[lo]);
+      w[k] = a < total ? (arc < nnz ? col[arc] : -1) : -2;
+      off[k] = sh.offer[lo];
+    }
+    u64 pw[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const bool ok = (unsigned)w[k] < (unsigned)n;
+      if (!ok && w[k] != -2) atomicOr(&sh.err, ERR_BAD_COL);
+      pw[k] = ok ? wg_load(&P[w[k]]) : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      if (pw[k] > off[k]) {
+        const u64 old = wg_min(&P[w[k]], off[k]);
+        if (SWEEP) {
+          if (old > off[k] &&
+              __hip_atomic_exchange(&j.wake[w[k]], tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != tag)
+            append(sh, next, w[k]);
+        } else if (old == INF) {
+          append(sh, next, w[k]);
+        }
+      }
+    }
+  }
+}
+
+// Stage a chunk of frontier entries [c0, c0 + BT) in LDS and relax its arcs (all threads call).
+template <bool SWEEP>
+__device__ __forceinline__ u64 expand_frontier(const BlockJob& j, BlockShared& sh, const int* cur, unsigned nf,
+                                               int* next, u64 unit, int tag) {
+  const int* __restrict__ rp = j.row_ptr;
+  u64 examined = 0;
+  for (unsigned c0 = 0; c0 < nf; c0 += BT) {
+    const unsigned e = c0 + threadIdx.x;
+    unsigned deg = 0;
+    if (e < nf) {
+      const int u = cur[e];
+      const int a0 = rp[u], a1 = rp[u + 1];
+      deg = (unsigned)(a1 - a0);
+      sh.first[threadIdx.x] = a0;
+      sh.offer[threadIdx.x] = wg_load(&j.P[u]) + unit;
+    }
+    unsigned total;
+    const unsigned ex = block_excl_scan(deg, sh, &total);
+    sh.pre[threadIdx.x] = ex;
+    __syncthreads();
+    examined += threadIdx.x == 0 ? total : 0;
+    relax_chunk<SWEEP>(j, sh, next, nf - c0 < (unsigned)BT ? nf - c0 : (unsigned)BT, total, tag);
+    __syncthreads();
+  }
+  return examined;
+}
+
+// The rounds of one prepared graph (results in sh: settled, examined, rounds, sweeps, err).
+// Once few vertices are left (unreached vertices * tail_den <= vertices with arcs) and more than
+// TAIL_MIN_LEFT rounds remain, the tail finishes by label correction: every unreached vertex
+// takes the best of its own label and its neighbours' in F_{r-1} (the only settled vertices
+// whose offers are still pending), then sweeps relax the changed labels until none drops.  The
+// labels are the unique fixpoint of P(v) = min(own label, min_w P(w) + unit), so the result is
+// the same exact one.
+constexpr int TAIL_MIN_LEFT = 16;
+
+__device__ __attribute__((noinline)) void block_rounds(const BlockJob& j, BlockShared& sh) {
+  const int n = j.n;
+  const int* __restrict__ rp = j.row_ptr;
+  const int* __restrict__ col = j.col;
+  const long long* __restrict__ shift = j.shift;
+  u64* P = j.P;
+  const int tid = threadIdx.x;
+  const u64 delta = sh.delta, n_active = sh.n_active;
+  const int B = n > 1 ? 32 - __builtin_clz((unsigned)(n - 1)) : 1;
+  const int D = (int)(delta >> FIX);
+  const u64 unit = (u64)1 << (FIX + B);
+  int* cur = j.q0;
+  int* next = j.q1;
+  unsigned nf = 0;
+  u64 settled = 0, examined = 0;
+  long long rounds = 0, sweeps = 0;
+  int r = next_nonempty(sh, 0, D);
+  bool tail = false;
+  while (settled < n_active && r <= D + n && rounds <= (long long)D + n + 2) {  // r past the end: stop
+    __syncthreads();  // every thread has read the previous round's count and error bits
+    if (tid == 0) sh.cnt = 0;
+    __syncthreads();
+    // wake bucket r
+    if (r <= D) {
+      const int w0 = sh.woff[r], w1 = sh.woff[r + 1];
+      for (int i = w0 + tid; i < w1; i += BT) {
+        const int v = j.wake[i];
+        const u64 self = ((delta - (u64)shift[v]) << B) | (u64)v;
+        if (wg_load(&P[v]) > self) {
+          const u64 old = wg_min(&P[v], self);
+          if (old == INF) append(sh, next, v);
+        }
+      }
+    }
+    examined += expand_frontier<false>(j, sh, cur, nf, next, unit, 0);
+    __syncthreads();
+    nf = sh.cnt;
+    if (sh.err) break;
+    settled += nf;
+    ++rounds;
+    int* t = cur;
+    cur = next;
+    next = t;
+    if (nf) ++r;
+    else r = next_nonempty(sh, r + 1, D);
+    const u64 left = n_active - settled;
+    if (j.tail_den > 0 && left > 0 && left * (u64)j.tail_den <= n_active && D - r > TAIL_MIN_LEFT) {
+      tail = true;
+      break;
+    }
+  }
+  if (tail && !sh.err) {
+    // seed: F_{r-1} is cur (nf entries, final labels); every unreached vertex with arcs takes the
+    // best of its own label and its neighbours' in F_{r-1}, and is queued for the first sweep
+    __syncthreads();
+    if (tid == 0) sh.cnt = 0;
+    __syncthreads();
+    const u64 prev_round = (u64)(r - 1);
+    for (int v = tid; v < n; v += BT) {
+      const int a0 = rp[v], a1 = rp[v + 1];
+      if (a1 == a0 || wg_load(&P[v]) != INF) continue;
+      u64 best = ((delta - (u64)shift[v]) << B) | (u64)v;
+      for (int a = a0; a < a1; ++a) {
+        const int u = col[a];
+        if ((unsigned)u >= (unsigned)n) {
+          atomicOr(&sh.err, ERR_BAD_COL);
+          break;
+        }
+        const u64 pu = wg_load(&P[u]);
+        if (pu != INF && (pu >> (FIX + B)) == prev_round && pu + unit < best) best = pu + unit;
+      }
+      examined += (u64)(a1 - a0);
+      __hip_atomic_store(&P[v], best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      j.wake[v] = -1;  // the stamp of the first sweep
+      append(sh, next, v);
+    }
+    __syncthreads();
+    nf = sh.cnt;
+    int* t = cur;
+    cur = next;
+    next = t;
+    // sweeps: sweep k relaxes the labels queued by the step before and queues those that drop
+    for (int k = 1; nf && !sh.err && sweeps <= n; ++k) {
+      __syncthreads();
+      if (tid == 0) sh.cnt = 0;
+      __syncthreads();
+      examined += expand_frontier<true>(j, sh, cur, nf, next, unit, -(k + 1));
+      __syncthreads();
+      nf = sh.cnt;
+      ++sweeps;
+      t = cur;
+      cur = next;
+      next = t;
+    }
+    settled = n_active;
+  }
+  __syncthreads();
+  examined = block_sum64(examined, sh);
+  if (tid == 0) {
+    sh.settled = settled;
+    sh.examined = examined;
+    sh.rounds = rounds;
+    sh.sweeps = sweeps;
+  }
+  __syncthreads();
+}
+
+// Centres (INF: an isolated vertex, its own centre) and the cut, from the final labels.
+__device__ __attribute__((noinline)) void block_output(const BlockJob& j, BlockShared& sh, BlockOut* out) {
+  const int n = j.n;
+  const int* __restrict__ rp = j.row_ptr;
+  const int* __restrict__ col = j.col;
+  u64* P = j.P;
+  const int tid = threadIdx.x;
+  const int B = n > 1 ? 32 - __builtin_clz((unsigned)(n - 1)) : 1;
+  const u64 mask = ((u64)1 << B) - 1;
+  const unsigned e0 = sh.err | (sh.settled < sh.n_active ? ERR_WATCHDOG : 0u);
+  u64 cut2 = 0, pieces = 0;
+  if (!e0) {
+    for (int v = tid; v < n; v += BT) {
+      const u64 p = wg_load(&P[v]);
+      const int c = p == INF ? v : (int)(p & mask);
+      j.centre[v] = c;
+      pieces += c == v;
+      for (int a = rp[v]; a < rp[v + 1]; ++a) {
+        const int w = col[a];
+        if ((unsigned)w >= (unsigned)n) {  // arcs of the last frontier were not read by a round
+          atomicOr(&sh.err, ERR_BAD_COL);
+          break;
+        }
+        const u64 pw = wg_load(&P[w]);
+        const int cw = pw == INF ? w : (int)(pw & mask);
+        cut2 += cw != c;
+      }
+    }
+  }
+  cut2 = block_sum64(cut2, sh);
+  pieces = block_sum64(pieces, sh);
+  if (tid == 0) {
+    out->err = e0 | sh.err;
+    out->cut_arcs = cut2;
+    out->pieces = pieces;
+    out->delta = sh.delta;
+    out->n_active = sh.n_active;
+    out->rounds = sh.rounds;
+    out->sweeps = sh.sweeps;
+    out->examined = sh.examined;
+  }
+}
+
+// One graph, the whole workgroup.
+__device__ void block_graph(const BlockJob& j, BlockShared& sh, BlockOut* out) {
+  block_prepare(j, sh);
+  if (sh.err) {
+    if (threadIdx.x == 0) {
+      out->err = sh.err;
+      out->delta = sh.delta;
+    }
+    return;
+  }
+  block_rounds(j, sh);
+  block_output(j, sh, out);
+}
+
+}  // namespace
+
+// (BT, 8): eight waves per SIMD, two workgroups per CU (at most 64 VGPRs).
+// One workgroup per graph at a time: the workgroup takes the next graph of `order` from the
+// shared counter until none is left.
+__global__ __launch_bounds__(BT, 8) void k_block_decompose(const BlockJob* __restrict__ jobs, const int* __restrict__ order,
+                                                           int njobs, unsigned* next_job, BlockOut* outs) {
+  __shared__ BlockShared sh;
+  for (;;) {
+    if (threadIdx.x == 0) sh.job = (int)atomicAdd(next_job, 1u);
+    __syncthreads();
+    const int k = sh.job;
+    __syncthreads();
+    if (k >= njobs) return;
+    const int g = order ? order[k] : k;
+    const u64 t0 = wall_clock64();
+    block_graph(jobs[g], sh, &outs[g]);
+    if (threadIdx.x == 0) {
+      outs[g].t_begin = t0;
+      outs[g].t_end = wall_clock64();
+    }
+    __syncthreads();
+  }
+}
+
+// Per-graph job descriptors of a batch in one offset CSR (graph g's rows at row_ptr[vo[g] + g]).
+__global__ void k_block_jobs(int G, long long N, const long long* vo, const long long* ao, const int* row_ptr,
+                             const int* col, const long long* shift, int* centre, u64* P, int* wq, int tail_den,
+                             BlockJob* jobs) {
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < G; g += gridDim.x * blockDim.x) {
+    BlockJob j;
+    const long long v0 = vo[g];
+    j.n = (int)(vo[g + 1] - v0);
+    j.nnz = ao[g + 1] - ao[g];
+    j.row_ptr = row_ptr + v0 + g;
+    j.col = col + ao[g];
+    j.shift = shift + v0;
+    j.centre = centre + v0;
+    j.P = P + v0;
+    j.wake = wq + v0;
+    j.q0 = wq + N + v0;
+    j.q1 = wq + 2 * N + v0;
+    j.tail_den = tail_den;
+    jobs[g] = j;
+  }
+}
+
+}  // namespace ldd

@@ -159,6 +159,7 @@ __global__ void k_advance(LaunchBlock* lb, int C);
 __global__ void k_rounds_persistent(const LaunchBlock* lb);
 __global__ void k_setup(RoundCtx c, LaunchBlock* lb, int qpath);
 __global__ void k_out_report(const Ctrl* ctrl, Report* report);
+__global__ void k_max_radius(int n, int B, const u64* P, const long long* shift, u64 delta, u64* out);
 __global__ void k_finalize(int n, int B, const int* row_ptr, const u64* P, int* centre, u64* hub_bits, int* lv,
                            unsigned* la, Ctrl* ctrl);
 __global__ void k_cut(int n, const int* row_ptr, const int* col, const int* centre, const u64* hub_bits, const int* lv,

@@ -355,6 +355,35 @@ __global__ void k_setup(RoundCtx c, LaunchBlock* lb, int qpath) {
   }
 }
 
+// Verification (proof of Theorem 1.1, Sec. 5): the largest distance from a vertex to its centre.
+// A final label holds key(v) = Delta - shift[c] + 2^20 dist(c, v) and c = low B bits, so the
+// distance is (key(v) - (Delta - shift[c])) >> 20 exactly; a label still INF (an isolated vertex,
+// its own centre) has distance 0.  Block maxima are combined with one atomic per block into *out
+// (cleared by the caller).
+__global__ __launch_bounds__(256) void k_max_radius(int n, int B, const u64* __restrict__ P,
+                                                    const long long* __restrict__ shift, u64 delta, u64* out) {
+  __shared__ u64 red[256 / WAVE];
+  u64 best = 0;
+  const u64 mask = ((u64)1 << B) - 1;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+    const u64 p = P[v];
+    if (p == INF) continue;
+    const u64 c = p & mask, key = p >> B;
+    const u64 off = delta - (u64)shift[c];
+    const u64 d = (key - off) >> FIX;
+    best = d > best ? d : best;
+  }
+  best = wave_max_u64(best);
+  if (lane_id() == 0) red[threadIdx.x / WAVE] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    u64 m = 0;
+    for (int w = 0; w < 256 / WAVE; ++w) m = red[w] > m ? red[w] : m;
+    if (m) atomic_max_u64(out, m);
+  }
+}
+
 // Single thread, after the cut: the output totals for the host.
 __global__ void k_out_report(const Ctrl* ctrl, Report* report) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;

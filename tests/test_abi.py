@@ -34,9 +34,9 @@ def test_library_exports_every_declared_symbol():
 
 def test_status_strings():
     L = ldd.lib()
-    names = [L.ldd_status_string(i).decode() for i in range(10)]
-    assert names[0] == "ok" and names[ldd.ERR_PENDING] == "pending" and names[9] == "unknown status"
-    assert len(set(names)) == 10
+    names = [L.ldd_status_string(i).decode() for i in range(11)]
+    assert names[0] == "ok" and names[ldd.ERR_PENDING] == "pending" and names[10] == "unknown status"
+    assert len(set(names)) == 11
 
 
 def test_argument_errors_answer_before_device_work():
@@ -63,9 +63,28 @@ def test_workspace_bytes_grows_with_n():
     assert 0 < a < b and b - a >= 1000 * 32
 
 
+def test_host_shift_sampler_equals_the_input_generator():
+    """ldd_make_shifts (the library's host sampler, a host function) gives byte for byte the
+    shifts of the seeded input generator that every test and benchmark input comes from."""
+    import numpy as np
+
+    import inputs
+    for n, beta, seed in ((0, 0.1, 1), (1, 0.05, 2), (4096, 0.1, 1), (100_003, 0.02, 77), (20_000, 2.5, 2**63 + 5)):
+        assert np.array_equal(ldd.make_shifts(n, beta, seed), inputs.make_shifts(n, beta, seed)), (n, beta, seed)
+    L = ldd.lib()
+    out = np.empty(4, np.int64)
+    assert L.ldd_make_shifts(4, 0.0, 1, out.ctypes.data) == ldd.ERR_INVALID_ARG
+    assert L.ldd_make_shifts(4, float("inf"), 1, out.ctypes.data) == ldd.ERR_INVALID_ARG
+    assert L.ldd_make_shifts(-1, 0.1, 1, out.ctypes.data) == ldd.ERR_INVALID_ARG
+    assert L.ldd_make_shifts(4, 0.1, 1, None) == ldd.ERR_INVALID_ARG
+    assert L.ldd_make_shifts_device(4, -1.0, 1, None, None) == ldd.ERR_INVALID_ARG
+    assert L.ldd_decompose_verified(None, 0.1, 1, None, None, None, None, None, None) == ldd.ERR_INVALID_ARG
+
+
 STRUCTS = {"ldd_csr": ldd.Csr, "ldd_options": ldd.Options, "ldd_stats": ldd.Stats,
            "ldd_server_config": ldd.ServerConfig, "ldd_request": ldd.Request, "ldd_result": ldd.Result,
-           "ldd_server_info": ldd.ServerInfo, "ldd_tune_report": ldd.TuneReport}
+           "ldd_server_info": ldd.ServerInfo, "ldd_tune_report": ldd.TuneReport,
+           "ldd_verify_options": ldd.VerifyOptions, "ldd_verify_report": ldd.VerifyReport}
 
 
 def test_ctypes_layouts_match_the_header(tmp_path):

@@ -23,18 +23,20 @@ pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_digests.json")
 
-# schedules that must all give the same bits: direction policy, engine, grid size, and the
-# label-correcting tail (off, default, or from the very first step)
+# schedules that must all give the same bits: engine (automatic, workgroup, launch, persistent),
+# direction policy, grid size, and the label-correcting tail (off, default, or from the first step)
 MODES = [
     dict(),
-    dict(direction=1),
-    dict(direction=2),
+    dict(engine=3),  # one workgroup runs every round
+    dict(engine=2),  # one launch per round step over the GPU
+    dict(engine=2, direction=1),
+    dict(engine=2, direction=2),
     dict(engine=1),
     dict(engine=1, direction=2),
-    dict(blocks=3),
-    dict(blocks=7, direction=2),
-    dict(tail_vertices=-1),
-    dict(tail_vertices=1),
+    dict(engine=2, blocks=3),
+    dict(engine=2, blocks=7, direction=2),
+    dict(engine=2, tail_vertices=-1),
+    dict(engine=2, tail_vertices=1),
 ]
 
 
@@ -112,7 +114,7 @@ def test_tail_stamps_across_calls(ldd):
         cases.append((name, to_dev(rp, ci, s), beta, want_c, want_cut))
     for i in range(12):
         name, d, beta, want_c, want_cut = cases[i % 3]
-        mode = dict(tail_vertices=1, engine=1) if i % 4 == 3 else dict(tail_vertices=1 if i % 2 else 8)
+        mode = dict(tail_vertices=1, engine=1) if i % 4 == 3 else dict(tail_vertices=1 if i % 2 else 8, engine=2)
         centre, cut, st = ldd.decompose(*d, beta, stats=True, **mode)
         got = centre.cpu().numpy()
         log(f"call {i} {name} {mode}: tail sweeps {st['tail_iters']}")
@@ -150,7 +152,7 @@ def test_medium_workloads_vs_oracle(ldd, name):
     want_c, _, want_cut = oracle.decompose(rp, ci, s)
     log(f"{name}: n={rp.size - 1} nnz={ci.size} oracle {time.time() - t:.2f}s")
     for mode in (dict(), dict(direction=1), dict(direction=2), dict(engine=1), dict(tail_vertices=-1),
-                 dict(tail_vertices=1)):
+                 dict(tail_vertices=1), dict(engine=3)):
         got, cut, st = run(ldd, rp, ci, s, beta, **mode)
         log(f"  {mode}: rounds {st['rounds']} td {st['td_rounds']} bu {st['bu_rounds']} tail {st['tail_iters']} "
             f"from {st['tail_round']} rounds_ms {st['ms_rounds']:.3f}")
@@ -181,8 +183,9 @@ def test_batch_graph_kinds_vs_oracle(ldd, kind, n):
     for beta in (0.02, 0.3):
         s = inputs.make_shifts(n, beta, 78)
         want_c, _, want_cut = oracle.decompose(rp, ci, s)
-        got, cut, _ = run(ldd, rp, ci, s, beta)
-        assert np.array_equal(got, want_c) and cut == want_cut
+        for mode in (dict(), dict(engine=3)):
+            got, cut, _ = run(ldd, rp, ci, s, beta, **mode)
+            assert np.array_equal(got, want_c) and cut == want_cut, mode
 
 
 def test_tie_heavy_shifts(ldd):
@@ -379,7 +382,8 @@ def test_batch_union_equals_alone_and_oracle(ldd):
     vo, ao, rp_all, ci_all, s_all = pack(graphs)
     d_rp, d_ci, d_s = to_dev(rp_all, ci_all, s_all)
     want = [oracle.decompose(rp, ci, s) for rp, ci, s in graphs]
-    for mode in (dict(), dict(batch_mode=1), dict(direction=2), dict(tail_vertices=-1), dict(engine=1)):
+    for mode in (dict(), dict(batch_mode=1), dict(batch_mode=3, blocks=5), dict(batch_mode=2),
+                 dict(batch_mode=2, direction=2), dict(batch_mode=2, tail_vertices=-1), dict(batch_mode=2, engine=1)):
         centre, cuts = ldd.decompose_batch(vo, ao, d_rp, d_ci, d_s, **mode)
         centre = centre.cpu().numpy()
         for g, (wc, _, wcut) in enumerate(want):
@@ -406,9 +410,10 @@ def test_batch_512_workload_digest(ldd):
     vo, ao, rp_all, ci_all, s_all = pack(graphs)
     log(f"batch-512: {vo[-1]} vertices, {ao[-1]} arcs")
     d_rp, d_ci, d_s = to_dev(rp_all, ci_all, s_all)
-    centre, cuts = ldd.decompose_batch(vo, ao, d_rp, d_ci, d_s)
-    assert sha(centre.cpu().numpy()) == gold["sha_centre"]
-    assert sha(np.array(cuts, np.int64)) == gold["sha_cuts"]
+    for mode in (dict(), dict(batch_mode=2)):  # workgroup engine, disjoint union
+        centre, cuts = ldd.decompose_batch(vo, ao, d_rp, d_ci, d_s, **mode)
+        assert sha(centre.cpu().numpy()) == gold["sha_centre"], mode
+        assert sha(np.array(cuts, np.int64)) == gold["sha_cuts"], mode
 
 
 def test_tuner_changes_time_only(ldd, tmp_path):

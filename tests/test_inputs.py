@@ -101,6 +101,21 @@ def test_shifts_exponential_distribution():
     assert stat.pvalue > 1e-4
 
 
+def test_shifts_integer_log_equals_inversion_formula():
+    """The integer-only logarithm gives floor(2^20 * (-ln(1 - U)) / beta) for the stream's
+    uniforms U: against libm's log1p in double, every value is within one fixed-point unit
+    and nearly all are equal (they differ only where the real value lies within rounding of an
+    integer)."""
+    for beta, seed in ((0.05, 1), (0.3, 77), (1.7, 5)):
+        n = 20000
+        s = inputs.make_shifts(n, beta, seed)
+        u = np.array([inputs.u01(seed, inputs.TAG_SHIFT, i) for i in range(n)])
+        ref = np.floor(-np.log1p(-u) / beta * inputs.FIX_ONE).astype(np.int64)
+        diff = s - ref
+        assert np.abs(diff).max() <= 1
+        assert np.count_nonzero(diff) <= 5
+
+
 def test_shifts_deterministic_and_prefix_stable():
     a = inputs.make_shifts(1000, 0.05, seed=9)
     b = inputs.make_shifts(2000, 0.05, seed=9)

@@ -343,3 +343,30 @@ def test_bad_arguments_rejected():
         oracle.decompose(rp, ci, np.array([0, -1, 0], np.int64))
     with pytest.raises(oracle.OracleError):
         oracle.decompose(np.array([0, 1, 1, 5], np.int32), np.array([1, 0, 9, 9, 9], np.int32), np.zeros(3, np.int64))
+
+
+# ------------------------------------------------------------------------------------------
+# the verification bounds of the Las Vegas loop (proof of Theorem 1.1, Sec. 5)
+# ------------------------------------------------------------------------------------------
+def radius_of(rp, ci, s):
+    """Largest distance from a vertex to its centre, from the oracle's lengths."""
+    c, length, cut = oracle.decompose(rp, ci, s)
+    d = (length - (int(s.max()) - s[c])) >> 20
+    return c, int(d.max()), cut
+
+
+def test_las_vegas_bounds_hold_with_constant_probability():
+    """With cut_factor 2 and radius_factor 3, a draw passes both checks with probability at
+    least 1/2 (Markov's inequality on E[cut] <= (1 - e^-beta) m, Cor. 4.5; every distance to a
+    centre is at most the largest shift, below 3 ln n / beta with probability >= 1 - n^-2,
+    Lemma 4.2).  Over 120 seeded draws per graph, far more than half pass."""
+    for (rp, ci), beta in ((inputs.grid2d(64, 64), 0.1), (inputs.rmat(12, 16, seed=3), 0.2)):
+        n, m = rp.size - 1, ci.size // 2
+        ok = 0
+        for seed in range(120):
+            s = inputs.make_shifts(n, beta, 1000 + seed)
+            c, radius, cut = radius_of(rp, ci, s)
+            # the radius never exceeds the largest shift (proof of Theorem 1.1)
+            assert radius * S <= int(s.max())
+            ok += cut <= 2 * beta * m and radius <= 3 * math.log(n) / beta
+        assert ok >= 60, ok
