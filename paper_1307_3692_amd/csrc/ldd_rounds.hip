@@ -37,10 +37,17 @@ struct AppendBuf {
   int wpar;  // queue buffer the step writes
 };
 
+// the tail seed scans SEED_SCAN vertices per thread per window and lists the unsettled ones (as
+// 16-bit offsets in the window)
+constexpr int SEED_SCAN = 8;
+constexpr int SLIST = SEED_SCAN * RT;
+static_assert(SLIST <= 65536, "window offsets fit 16 bits");
+
 struct StepShared {
   RoundState S;
   u64 lr;
   unsigned start;
+  unsigned nlist;   // tail seed: vertices listed in the current window
   u64 red[NW];
   // top-down window: RT+1 queue entries (arc prefix, first arc in col_idx, offer)
   unsigned w_pre[RT + 1];
@@ -426,6 +433,83 @@ __device__ __forceinline__ void phase_pull(const RoundCtx& c, int r, int k, u64 
   examined_total += examined;
 }
 
+// ---- tail seed, listed -------------------------------------------------------------------
+// Every vertex with arcs not settled before round r takes the best of its own label (whatever its
+// wake round) and the offers of its neighbours in F_{r-1}.  The seed step writes nothing else, so
+// a vertex's label is INF until its own thread writes it.  Each block takes a contiguous vertex
+// range and walks it in windows of SLIST vertices: a coalesced scan of labels and row offsets
+// lists the window's unsettled vertices with arcs in LDS, then the listed vertices pull, RT at a
+// time (rows undecided after PULL_CAP arcs finished by their wave, as in the bottom-up pull).
+// Settled and isolated vertices cost one coalesced label read (and, unsettled, the row offsets).
+__device__ __forceinline__ void phase_seed(const RoundCtx& c, int r, int k, u64 Lr, AppendBuf& ab, StepShared& sh,
+                                           unsigned short* list, u64& wmin, u64& examined_total) {
+  unsigned examined = 0;
+  const int B = c.B;
+  const u64 unit = (u64)1 << (FIX + B);
+  const u64 base_r = (u64)r << (FIX + B);
+  const u64 prev_round = (u64)(r - 1);
+  const long long v0 = (long long)c.n * blockIdx.x / gridDim.x, v1 = (long long)c.n * (blockIdx.x + 1) / gridDim.x;
+  for (long long w0 = v0; w0 < v1; w0 += SLIST) {
+    __syncthreads();  // every thread has read the previous window's list count
+    if (threadIdx.x == 0) sh.nlist = 0;
+    __syncthreads();
+    u64 pv[SEED_SCAN];
+#pragma unroll
+    for (int j = 0; j < SEED_SCAN; ++j) {
+      const long long v = w0 + (long long)j * RT + threadIdx.x;
+      pv[j] = v < v1 ? c.P[v] : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < SEED_SCAN; ++j) {
+      const long long v = w0 + (long long)j * RT + threadIdx.x;
+      if (v < v1 && pv[j] >= base_r && c.row_ptr[v + 1] > c.row_ptr[v])
+        list[atomicAdd(&sh.nlist, 1u)] = (unsigned short)(v - w0);
+    }
+    __syncthreads();
+    const unsigned cnt = sh.nlist;
+    for (unsigned c0 = 0; c0 < cnt; c0 += RT) {
+      const unsigned i = c0 + threadIdx.x;
+      bool want = false, defer = false;
+      int v = 0;
+      unsigned deg = 0;
+      if (i < cnt) {
+        v = (int)(w0 + list[i]);
+        const int a0 = c.row_ptr[v], a1 = c.row_ptr[v + 1];
+        u64 best = own_offer(c, v);
+        int a = a0;
+        bool bad = false;
+        const int a_cap = a1 - a0 > PULL_CAP ? a0 + PULL_CAP : a1;
+        for (; a < a_cap && best > Lr; ++a) {
+          ++examined;
+          const int u = c.col[a];
+          if ((unsigned)u >= (unsigned)c.n) {
+            atomic_or_u32(&c.ctrl->err, ERR_BAD_COL);
+            bad = true;
+            break;
+          }
+          const u64 pu = load_u64_relaxed(&c.P[u]);
+          if ((pu >> (FIX + B)) == prev_round && pu != INF && pu + unit < best) best = pu + unit;
+        }
+        if (!bad && a < a1 && best > Lr) {  // long row, undecided: the wave finishes it below
+          defer = true;
+          sh.w_pre[threadIdx.x] = (unsigned)a;
+          sh.w_first[threadIdx.x] = a1;
+          sh.w_offer[threadIdx.x] = best;
+        } else {
+          pull_update<true>(c, v, best, a1 - a0, wmin, want, deg);
+        }
+      }
+      const u64 m = __ballot(defer);
+      if (m) {
+        examined += pull_rows_wave(c, m, sh.w_pre, sh.w_first, sh.w_offer, Lr, r);
+        if (defer) pull_update<true>(c, v, sh.w_offer[threadIdx.x], c.row_ptr[v + 1] - c.row_ptr[v], wmin, want, deg);
+      }
+      block_append(ab, want, v, deg, c, k);
+    }
+  }
+  examined_total += examined;
+}
+
 // Direction of the next round.  Top-down touches every arc of the frontier (random accesses);
 // bottom-up reads every label once (sequential) plus at most the arcs of unsettled vertices,
 // usually far fewer thanks to the early exit.  Bottom-up is taken once the frontier's arcs
@@ -562,7 +646,8 @@ __device__ __forceinline__ void add_examined(const RoundCtx& c, u64 examined, St
 }
 
 // One step; returns the mode it ran in (MODE_DONE: nothing was left to do).
-__device__ __forceinline__ int round_step(const RoundCtx& c, int k, AppendBuf& ab, StepShared& sh) {
+__device__ __forceinline__ int round_step(const RoundCtx& c, int k, AppendBuf& ab, StepShared& sh,
+                                          unsigned short* slist) {
   if (threadIdx.x == 0) {
     // Once a step has written "done" into either slot no step writes a slot again, so later
     // steps only need the two mode words to leave.
@@ -641,8 +726,8 @@ __device__ __forceinline__ int round_step(const RoundCtx& c, int k, AppendBuf& a
   } else {
     const unsigned sweep = (unsigned)round;
     if (sweep == 0) {
-      phase_pull<true>(c, __builtin_amdgcn_readfirstlane((int)sh.S.tail_round), k, nf ? sh.lr : INF, ab, sh, wmin,
-                       examined);
+      phase_seed(c, __builtin_amdgcn_readfirstlane((int)sh.S.tail_round), k, nf ? sh.lr : INF, ab, sh, slist, wmin,
+                 examined);
     } else if (nf) {
       phase_top_down<true>(c, k, qv, qa, nf, af, ab, sh, wmin, sweep);
       if (blockIdx.x == 0 && threadIdx.x == 0) examined += af;
@@ -659,7 +744,8 @@ __device__ __forceinline__ int round_step(const RoundCtx& c, int k, AppendBuf& a
 __global__ __launch_bounds__(RT, 8) void k_round_step_lb(const LaunchBlock* __restrict__ lb, int j) {
   __shared__ AppendBuf ab;
   __shared__ StepShared sh;
-  round_step(lb->c, (int)(lb->kbase + j), ab, sh);
+  __shared__ unsigned short slist[SLIST];
+  round_step(lb->c, (int)(lb->kbase + j), ab, sh, slist);
 }
 
 __global__ void k_advance(LaunchBlock* lb, int C) {
@@ -670,11 +756,12 @@ __global__ void k_advance(LaunchBlock* lb, int C) {
 __global__ __launch_bounds__(RT) void k_rounds_persistent(const LaunchBlock* __restrict__ lb) {
   __shared__ AppendBuf ab;
   __shared__ StepShared sh;
+  __shared__ unsigned short slist[SLIST];
   const RoundCtx& c = lb->c;
   u64 gen = 0;
   const long long kmax = (long long)c.R + c.n + 2;
   for (int k = 1; k <= kmax; ++k) {
-    if (round_step(c, k, ab, sh) == MODE_DONE) break;
+    if (round_step(c, k, ab, sh, slist) == MODE_DONE) break;
     grid_sync(&c.ctrl->bar, gridDim.x, gen, &c.ctrl->err);
     if (__hip_atomic_load(&c.ctrl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & (ERR_BARRIER | ERR_QUEUE)) break;
   }
