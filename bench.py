@@ -14,6 +14,7 @@ shifts, inputs resident in HBM.  Prints one JSON line.
                stream one decomposition at a time (FIFO), latency p50 / p99 and capacity
   grid2d       grid 64x64: p50 / p99 latency over 1000 calls
   grid3d       grid 256^3: time, round steps, the round kernel's roofline
+  shift_variants  Sec. 5's permutation variants of the shifts vs Exp shifts: cut and radius
   cpu_baseline the CPU oracle's bucketed search (single-threaded, one core) on the same graph and shifts
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rmat-24]
@@ -430,6 +431,39 @@ def run_grid3d(ldd, steps=5):
     return out
 
 
+def run_shift_variants(ldd, seeds=10):
+    """Sec. 5's closing remarks: integer shifts with a random-ranking tie-break, and shifts taken
+    from positions in a random ranking, against the Exp(beta) shifts -- the cut fraction and the
+    largest distance to a centre over seeded draws, each decomposition by the library."""
+    import numpy as np
+    import torch
+
+    import inputs
+    dev = torch.device("cuda:0")
+    names = {ldd.SHIFTS_EXP: "exp", ldd.SHIFTS_INT_PERM: "integer+ranking", ldd.SHIFTS_PERM_ORDER: "ranking positions"}
+    out = []
+    for gname, (rp, ci), beta in (("grid2d-1000", inputs.grid2d(1000, 1000), 0.01),
+                                  ("grid2d-1000", inputs.grid2d(1000, 1000), 0.05),
+                                  ("rmat-20", inputs.rmat(20, 16, seed=1), 0.2)):
+        n, m = rp.size - 1, ci.size // 2
+        d_rp, d_ci = torch.from_numpy(rp).to(dev), torch.from_numpy(ci).to(dev)
+        centre = torch.empty(n, dtype=torch.int32, device=dev)
+        for kind, kname in names.items():
+            cuts, radii, pieces = [], [], []
+            for sd in range(seeds):
+                s = torch.from_numpy(ldd.make_shifts_variant(n, beta, 100 + sd, kind)).to(dev)
+                _, cut, st = ldd.decompose(d_rp, d_ci, s, beta, centre=centre, stats=True)
+                cuts.append(cut / m)
+                radii.append(st["max_radius"])
+                pieces.append(st["pieces"])
+            out.append({"graph": gname, "beta": beta, "shifts": kname, "draws": seeds,
+                        "cut_fraction_mean": round(float(np.mean(cuts)), 6), "cut_fraction_sd": round(float(np.std(cuts)), 6),
+                        "max_radius_mean": round(float(np.mean(radii)), 2), "max_radius_sd": round(float(np.std(radii)), 2),
+                        "pieces_mean": round(float(np.mean(pieces)), 1)})
+            log(f"shift variants: {out[-1]}")
+    return out
+
+
 def cpu_host_info():
     model = "unknown"
     try:
@@ -549,6 +583,7 @@ def main():
     if not args.no_grids:
         out["grid2d"] = run_grid2d(ldd)
         out["grid3d"] = run_grid3d(ldd)
+        out["shift_variants"] = run_shift_variants(ldd)
     if not args.no_batch:
         torch.cuda.empty_cache()
         out["batched"] = run_batched(reps=5)

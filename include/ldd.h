@@ -114,6 +114,7 @@ typedef struct {
   float ms_finalize;       /* device time: centre extraction                              */
   float ms_cut;            /* device time: cut count                                      */
   int32_t steps;           /* round-kernel launches (steps) enqueued, done ones included  */
+  int64_t max_radius;      /* largest distance from a vertex to its centre                */
 } ldd_stats;
 
 /*
@@ -311,6 +312,26 @@ ldd_status ldd_decompose_static(const ldd_csr* g, const int64_t* shift_fix, doub
  * LDD_ERR_INVALID_ARG for n < 0, a NULL buffer with n > 0, or beta not finite and > 0.
  */
 ldd_status ldd_make_shifts(int32_t n, double beta, uint64_t seed, int64_t* out_host);
+
+/*
+ * Shift variants of the closing remarks of Sec. 5, which note that the fractional parts of the
+ * shifts act only as a random ordering for ties, and that shifts may be assigned from positions
+ * in a random permutation instead of being sampled.  A seeded random ranking orders the vertices
+ * (by a 64-bit counter-based draw of the seed's permutation stream, ties by id).
+ *   LDD_SHIFTS_EXP         ldd_make_shifts.
+ *   LDD_SHIFTS_INT_PERM    the integer parts of the Exp(beta) shifts of the same seed, plus the
+ *                          fraction floor((n - 1 - rank) 2^20 / n): rank 0 wins every tie.  The
+ *                          fractions are distinct while n <= 2^20 (beyond, nearby ranks share one
+ *                          and the smaller id wins).
+ *   LDD_SHIFTS_PERM_ORDER  the vertex of rank i takes the expected i-th largest of n Exp(beta)
+ *                          draws, (H_n - H_i) / beta (H_i = sum_{j<=i} 1/j, the order statistics'
+ *                          expectations), as floor(2^20 (S_i / beta)) with S_i accumulated from
+ *                          S_n = 0 down to S_i = S_{i+1} + 1/(i+1) in double.
+ * Host only (the ranking is a sort); out_host int64[n].  LDD_ERR_INVALID_ARG as ldd_make_shifts,
+ * or for an unknown kind.
+ */
+enum { LDD_SHIFTS_EXP = 0, LDD_SHIFTS_INT_PERM = 1, LDD_SHIFTS_PERM_ORDER = 2 };
+ldd_status ldd_make_shifts_variant(int32_t n, double beta, uint64_t seed, int32_t kind, int64_t* out_host);
 ldd_status ldd_make_shifts_device(int32_t n, double beta, uint64_t seed, int64_t* out_device, void* hip_stream);
 
 /*

@@ -28,6 +28,7 @@ FIX_ONE = 1 << FIX_SHIFT
 # purpose tags: gen.c's own streams (shifts 1, RMAT 2, relabel 3, ER 4, RGG 5) and the draws
 # made from Python
 TAG_SHIFT = 1
+TAG_PERM = 6
 TAG_BATCH = 16
 TAG_SERVE = 17
 
@@ -53,6 +54,8 @@ def _load():
     vp, i64, u64, f64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double, ctypes.c_int
     lib.ldd_in_make_shifts.argtypes = [i64, f64, u64, vp]
     lib.ldd_in_make_shifts.restype = i32
+    lib.ldd_in_make_shifts_variant.argtypes = [i64, f64, u64, i32, vp]
+    lib.ldd_in_make_shifts_variant.restype = i32
     lib.ldd_in_u01.argtypes = [u64, u64, u64]
     lib.ldd_in_u01.restype = f64
     lib.ldd_in_draw.argtypes = [u64, u64, u64]
@@ -101,6 +104,30 @@ def make_shifts(n: int, beta: float, seed: int) -> np.ndarray:
     if _load().ldd_in_make_shifts(n, float(beta), seed & (2**64 - 1), out.ctypes.data) != 0:
         raise ValueError(f"bad shift arguments n={n} beta={beta}")
     return out
+
+
+SHIFTS_EXP, SHIFTS_INT_PERM, SHIFTS_PERM_ORDER = 0, 1, 2
+
+
+def make_shifts_variant(n: int, beta: float, seed: int, kind: int) -> np.ndarray:
+    """Shift variants of Sec. 5's closing remarks: SHIFTS_EXP (the Exp(beta) shifts),
+    SHIFTS_INT_PERM (their integer parts plus a random-ranking tie-break as fractional part),
+    SHIFTS_PERM_ORDER (the expected exponential order statistics assigned by a random ranking)."""
+    out = np.empty(n, dtype=np.int64)
+    rc = _load().ldd_in_make_shifts_variant(n, float(beta), seed & (2**64 - 1), int(kind), out.ctypes.data)
+    if rc != 0:
+        raise ValueError(f"bad shift variant arguments n={n} beta={beta} kind={kind}")
+    return out
+
+
+def perm_rank(n: int, seed: int) -> np.ndarray:
+    """The seeded random ranking of the shift variants (vertices by draw of stream (seed, TAG_PERM),
+    ties by id): rank[v]."""
+    keys = np.array([_load().ldd_in_draw(seed & (2**64 - 1), TAG_PERM, v) for v in range(n)], dtype=np.uint64)
+    order = np.lexsort((np.arange(n), keys))
+    rank = np.empty(n, np.int64)
+    rank[order] = np.arange(n)
+    return rank
 
 
 def u01(seed: int, tag: int, i: int) -> float:

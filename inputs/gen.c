@@ -28,7 +28,7 @@
 #define FIX_ONE 1048576.0 /* 2^20: fixed-point scale of the shifts */
 
 /* Purpose tags: each kind of draw gets its own stream so that inputs never share draws. */
-enum { TAG_SHIFT = 1, TAG_RMAT = 2, TAG_RELABEL = 3, TAG_ER = 4, TAG_RGG = 5 };
+enum { TAG_SHIFT = 1, TAG_RMAT = 2, TAG_RELABEL = 3, TAG_ER = 4, TAG_RGG = 5, TAG_PERM = 6 };
 
 static inline uint64_t mix64(uint64_t z) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
@@ -94,6 +94,78 @@ int ldd_in_make_shifts(int64_t n, double beta, uint64_t seed, int64_t* out) {
     const double t = (double)neglog2_q47(draw(st, (uint64_t)i));
     out[i] = (int64_t)floor((t * LN2_2M27) / beta);
   }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Shift variants of the closing remarks of Sec. 5.                                           */
+/*   kind 1 (integer shifts, permutation tie-break): the integer part of the Exp(beta) shift   */
+/*     above (same draws), plus a fractional part that encodes a uniformly random ranking of  */
+/*     the vertices -- rank 0 wins every tie: frac = floor((n - 1 - rank) 2^20 / n), distinct  */
+/*     while n <= 2^20 (beyond, ranks 2^-20 apart share a fraction and the smaller id wins).  */
+/*   kind 2 (shifts from permutation positions): the vertex of rank i takes the expected i-th */
+/*     largest of n Exp(beta) draws, (H_n - H_i) / beta with H_i = sum_{j<=i} 1/j (Renyi's     */
+/*     representation of exponential order statistics), so no exponential is sampled.         */
+/*     The suffix sums S_i = sum_{j=i+1..n} 1/j are accumulated from S_n = 0 downwards in     */
+/*     double; shift_fix = floor((S_i / beta) * 2^20).                                        */
+/* The ranking sorts the vertices by a 64-bit draw of stream (seed, TAG_PERM), ties by id.     */
+/* ------------------------------------------------------------------------------------------ */
+typedef struct {
+  uint64_t key;
+  int64_t v;
+} perm_item;
+
+static int cmp_perm(const void* a, const void* b) {
+  const perm_item *x = (const perm_item*)a, *y = (const perm_item*)b;
+  if (x->key != y->key) return x->key < y->key ? -1 : 1;
+  return (x->v > y->v) - (x->v < y->v);
+}
+
+/* rank[v] in [0, n): position of v in the seeded random order */
+static int perm_ranks(int64_t n, uint64_t seed, int64_t* rank) {
+  perm_item* it = (perm_item*)malloc((size_t)(n > 0 ? n : 1) * sizeof(perm_item));
+  if (!it) return 1;
+  const uint64_t st = ldd_in_stream(seed, TAG_PERM);
+  for (int64_t v = 0; v < n; ++v) {
+    it[v].key = draw(st, (uint64_t)v);
+    it[v].v = v;
+  }
+  qsort(it, (size_t)n, sizeof(perm_item), cmp_perm);
+  for (int64_t i = 0; i < n; ++i) rank[it[i].v] = i;
+  free(it);
+  return 0;
+}
+
+int ldd_in_make_shifts_variant(int64_t n, double beta, uint64_t seed, int kind, int64_t* out) {
+  if (kind == 0) return ldd_in_make_shifts(n, beta, seed, out);
+  if (n < 0 || (out == NULL && n > 0) || !(beta > 0.0) || !isfinite(beta) || (kind != 1 && kind != 2)) return 1;
+  if (n == 0) return 0;
+  int64_t* rank = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+  if (!rank || perm_ranks(n, seed, rank)) {
+    free(rank);
+    return 2;
+  }
+  if (kind == 1) {
+    if (ldd_in_make_shifts(n, beta, seed, out)) {
+      free(rank);
+      return 1;
+    }
+    for (int64_t v = 0; v < n; ++v) {
+      const int64_t frac = (int64_t)(((unsigned __int128)(n - 1 - rank[v]) << 20) / (unsigned __int128)n);
+      out[v] = (out[v] >> 20 << 20) | frac;
+    }
+  } else {
+    double* sfx = (double*)malloc((size_t)(n + 1) * sizeof(double));
+    if (!sfx) {
+      free(rank);
+      return 2;
+    }
+    sfx[n] = 0.0;
+    for (int64_t i = n - 1; i >= 0; --i) sfx[i] = sfx[i + 1] + 1.0 / (double)(i + 1);
+    for (int64_t v = 0; v < n; ++v) out[v] = (int64_t)floor((sfx[rank[v]] / beta) * FIX_ONE);
+    free(sfx);
+  }
+  free(rank);
   return 0;
 }
 

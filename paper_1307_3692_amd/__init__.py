@@ -31,7 +31,8 @@ ENGINE_AUTO, ENGINE_PERSISTENT, ENGINE_LAUNCH, ENGINE_WORKGROUP = 0, 1, 2, 3
 EXPORTED = ("ldd_decompose", "ldd_workspace_bytes", "ldd_decompose_batch", "ldd_status_string", "ldd_last_error",
             "ldd_release_workspace", "ldd_server_create", "ldd_server_submit", "ldd_server_poll", "ldd_server_wait",
             "ldd_server_cancel", "ldd_server_query", "ldd_server_destroy", "ldd_tune",
-            "ldd_decompose_static", "ldd_make_shifts", "ldd_make_shifts_device", "ldd_decompose_verified")
+            "ldd_decompose_static", "ldd_make_shifts", "ldd_make_shifts_device", "ldd_decompose_verified",
+            "ldd_make_shifts_variant")
 
 
 class LddError(RuntimeError):
@@ -59,7 +60,7 @@ class Stats(ctypes.Structure):
                 ("delta", ctypes.c_int64), ("pieces", ctypes.c_int64), ("max_frontier", ctypes.c_int64),
                 ("arcs_examined", ctypes.c_int64), ("n_active", ctypes.c_int64),
                 ("ms_prep", ctypes.c_float), ("ms_rounds", ctypes.c_float), ("ms_finalize", ctypes.c_float),
-                ("ms_cut", ctypes.c_float), ("steps", ctypes.c_int32)]
+                ("ms_cut", ctypes.c_float), ("steps", ctypes.c_int32), ("max_radius", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -147,6 +148,8 @@ def lib():
     L.ldd_decompose_static.restype = i32
     L.ldd_make_shifts.argtypes = [i32, ctypes.c_double, ctypes.c_uint64, vp]
     L.ldd_make_shifts.restype = i32
+    L.ldd_make_shifts_variant.argtypes = [i32, ctypes.c_double, ctypes.c_uint64, i32, vp]
+    L.ldd_make_shifts_variant.restype = i32
     L.ldd_make_shifts_device.argtypes = [i32, ctypes.c_double, ctypes.c_uint64, vp, vp]
     L.ldd_make_shifts_device.restype = i32
     L.ldd_decompose_verified.argtypes = [ctypes.POINTER(Csr), ctypes.c_double, ctypes.c_uint64, vp, vp,
@@ -247,6 +250,18 @@ def make_shifts(n: int, beta: float, seed: int):
     import numpy as np
     out = np.empty(n, dtype=np.int64)
     _check(lib().ldd_make_shifts(int(n), float(beta), seed & (2**64 - 1), out.ctypes.data if n else None))
+    return out
+
+
+SHIFTS_EXP, SHIFTS_INT_PERM, SHIFTS_PERM_ORDER = 0, 1, 2
+
+
+def make_shifts_variant(n: int, beta: float, seed: int, kind: int):
+    """Host shifts of a variant of Sec. 5's closing remarks (``ldd_make_shifts_variant``)."""
+    import numpy as np
+    out = np.empty(n, dtype=np.int64)
+    _check(lib().ldd_make_shifts_variant(int(n), float(beta), seed & (2**64 - 1), int(kind),
+                                         out.ctypes.data if n else None))
     return out
 
 

@@ -296,6 +296,22 @@ extern "C" ldd_status ldd_decompose(const ldd_csr* g, const int64_t* shift_fix, 
 
 static const ldd_status REDO_WIDE = static_cast<ldd_status>(100);  // internal: run again on the wide layout
 
+// The largest distance from a vertex to its centre, from the final labels still in the workspace.
+static ldd_status max_radius(Workspace& w, int n, const int64_t* shift_fix, u64 delta, hipStream_t st, int64_t* out) {
+  ldd_status s = grow(w.vr, 256);
+  if (s != LDD_OK) return s;
+  const int B = ceil_log2(n) < 1 ? 1 : ceil_log2(n);
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, (u64*)w.vr.p, 1ll, 0ull);
+  hipLaunchKernelGGL(k_max_radius, dim3(grid_for(n, 256 * 8, 2048)), dim3(256), 0, st, n, B, (const u64*)w.P.p,
+                     (const long long*)shift_fix, delta, (u64*)w.vr.p);
+  HIP_TRY(hipGetLastError());
+  u64 radius = 0;
+  HIP_TRY(hipMemcpyAsync(&radius, w.vr.p, sizeof(u64), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  *out = (int64_t)radius;
+  return LDD_OK;
+}
+
 // One decomposition.  wide = false: the sorted (q-bucket) layout, enqueued in full without the
 // host waiting (k_setup decides on the device whether the rounds run); if the shifts turn out to
 // span QCAP units or more, the run reports REDO_WIDE and is redone with wide = true, whose
@@ -603,6 +619,10 @@ static ldd_status decompose_run(Workspace& w, const ldd_csr* g, const int64_t* s
     stats->ms_finalize = ms;
     (void)hipEventElapsedTime(&ms, w.ev[4], w.ev[5]);
     stats->ms_cut = ms;
+    if (!bv) {
+      ldd_status sr = max_radius(w, n, shift_fix, delta, st, &stats->max_radius);
+      if (sr != LDD_OK) return sr;
+    }
   }
   return LDD_OK;
 }
@@ -701,6 +721,8 @@ static ldd_status decompose_block(Workspace& w, const ldd_csr* g, const int64_t*
     stats->ms_rounds = ms;
     stats->ms_finalize = 0;
     stats->ms_cut = 0;
+    s = max_radius(w, n, shift_fix, o.delta, st, &stats->max_radius);
+    if (s != LDD_OK) return s;
   }
   return LDD_OK;
 }
@@ -770,27 +792,19 @@ extern "C" ldd_status ldd_decompose_verified(const ldd_csr* g, double beta, uint
   HIP_TRY(hipGetDevice(&dev));
   Workspace& w = *workspace_for(dev);
   std::lock_guard<std::mutex> lk(w.mu);
-  ldd_status s = grow(w.vr, 256);
-  if (s != LDD_OK) return s;
-  const int B = ceil_log2(n) < 1 ? 1 : ceil_log2(n);
+  ldd_status s = LDD_OK;
   for (int a = 0; a < max_attempts; ++a) {
     const uint64_t sd = seed + (uint64_t)a;
     if ((s = ldd_shifts_on_device(n, beta, sd, shift_fix, st))) return s;
     int64_t cut = 0;
     if ((s = decompose_impl(w, g, shift_fix, centre, &cut, o, nullptr, st, nullptr))) return s;
     // the labels of this draw are still in the workspace: the largest distance to a centre
-    const u64 delta = w.host->report.delta;
-    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, (u64*)w.vr.p, 1ll, 0ull);
-    hipLaunchKernelGGL(k_max_radius, dim3(grid_for(n, 256 * 8, 2048)), dim3(256), 0, st, n, B, (const u64*)w.P.p,
-                       (const long long*)shift_fix, delta, (u64*)w.vr.p);
-    HIP_TRY(hipGetLastError());
-    u64 radius = 0;
-    HIP_TRY(hipMemcpyAsync(&radius, w.vr.p, sizeof(u64), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
+    int64_t radius = 0;
+    if ((s = max_radius(w, n, shift_fix, w.host->report.delta, st, &radius))) return s;
     r.attempts = a + 1;
     r.seed = sd;
     r.cut_edges = cut;
-    r.max_radius = (int64_t)radius;
+    r.max_radius = radius;
     r.accepted = (double)cut <= r.cut_bound && (double)radius <= r.radius_bound;
     if (r.accepted) break;
   }

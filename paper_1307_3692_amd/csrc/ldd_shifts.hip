@@ -21,6 +21,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <utility>
+#include <vector>
 
 #include "../../include/ldd.h"
 #include "ldd_internal.h"
@@ -29,7 +31,9 @@ namespace {
 
 constexpr uint64_t GOLDEN = 0x9E3779B97F4A7C15ull;
 constexpr uint64_t TAG_SHIFT = 1;
+constexpr uint64_t TAG_PERM = 6;
 constexpr double LN2_2M27 = 0x1.62e42fefa39efp-28;  // ln 2 * 2^-27
+constexpr int FIX_BITS = 20;
 
 __host__ __device__ inline uint64_t mix64(uint64_t z) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -37,9 +41,11 @@ __host__ __device__ inline uint64_t mix64(uint64_t z) {
   return z ^ (z >> 31);
 }
 
-__host__ __device__ inline uint64_t shift_stream(uint64_t seed) {
-  return mix64(mix64(seed + GOLDEN) ^ (TAG_SHIFT * 0xD1B54A32D192ED03ull));
+__host__ __device__ inline uint64_t stream_of(uint64_t seed, uint64_t tag) {
+  return mix64(mix64(seed + GOLDEN) ^ (tag * 0xD1B54A32D192ED03ull));
 }
+
+__host__ __device__ inline uint64_t shift_stream(uint64_t seed) { return stream_of(seed, TAG_SHIFT); }
 
 __host__ __device__ inline int top_bit(uint64_t v) {  // v > 0
   int e = 0;
@@ -102,6 +108,37 @@ extern "C" ldd_status ldd_make_shifts(int32_t n, double beta, uint64_t seed, int
   }
   const uint64_t stream = shift_stream(seed);
   for (int32_t i = 0; i < n; ++i) out_host[i] = shift_of(stream, (uint64_t)i, beta);
+  return LDD_OK;
+}
+
+// The shift variants of the closing remarks of Sec. 5 (see ldd.h).  The random ranking orders
+// the vertices by a 64-bit draw of stream (seed, 6), ties by id.
+extern "C" ldd_status ldd_make_shifts_variant(int32_t n, double beta, uint64_t seed, int32_t kind, int64_t* out_host) {
+  if (kind == LDD_SHIFTS_EXP) return ldd_make_shifts(n, beta, seed, out_host);
+  if (n < 0 || (n > 0 && !out_host) || !beta_ok(beta) || (kind != LDD_SHIFTS_INT_PERM && kind != LDD_SHIFTS_PERM_ORDER)) {
+    ldd_set_error("ldd_make_shifts_variant: need n >= 0, an output buffer, a finite beta > 0 and a known kind");
+    return LDD_ERR_INVALID_ARG;
+  }
+  if (n == 0) return LDD_OK;
+  std::vector<std::pair<uint64_t, int32_t>> order((size_t)n);
+  const uint64_t ps = stream_of(seed, TAG_PERM);
+  for (int32_t v = 0; v < n; ++v) order[v] = {mix64(ps + ((uint64_t)v + 1) * GOLDEN), v};
+  std::sort(order.begin(), order.end());
+  if (kind == LDD_SHIFTS_INT_PERM) {
+    const uint64_t st = shift_stream(seed);
+    for (int32_t i = 0; i < n; ++i) {
+      const int32_t v = order[i].second;
+      const int64_t whole = shift_of(st, (uint64_t)v, beta) >> FIX_BITS;
+      const int64_t frac = (int64_t)(((unsigned __int128)(uint64_t)(n - 1 - i) << FIX_BITS) / (uint64_t)n);
+      out_host[v] = (whole << FIX_BITS) | frac;
+    }
+  } else {
+    // rank i takes (H_n - H_i) / beta: suffix sums of 1/j from the top, in this order
+    std::vector<double> sfx((size_t)n + 1);
+    sfx[n] = 0.0;
+    for (int32_t i = n - 1; i >= 0; --i) sfx[i] = sfx[i + 1] + 1.0 / (double)(i + 1);
+    for (int32_t i = 0; i < n; ++i) out_host[order[i].second] = (int64_t)floor((sfx[i] / beta) * 1048576.0);
+  }
   return LDD_OK;
 }
 

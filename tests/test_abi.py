@@ -81,6 +81,22 @@ def test_host_shift_sampler_equals_the_input_generator():
     assert L.ldd_decompose_verified(None, 0.1, 1, None, None, None, None, None, None) == ldd.ERR_INVALID_ARG
 
 
+def test_host_shift_variants_equal_the_input_generator():
+    """ldd_make_shifts_variant (host) gives byte for byte the input generator's shift variants of
+    Sec. 5's closing remarks (integer shifts with a permutation tie-break; shifts from
+    permutation positions)."""
+    import numpy as np
+
+    import inputs
+    for kind in (ldd.SHIFTS_EXP, ldd.SHIFTS_INT_PERM, ldd.SHIFTS_PERM_ORDER):
+        for n, beta, seed in ((0, 0.1, 1), (1, 0.3, 2), (5000, 0.1, 3), (70_001, 0.02, 2**64 - 3)):
+            a = ldd.make_shifts_variant(n, beta, seed, kind)
+            b = inputs.make_shifts_variant(n, beta, seed, kind)
+            assert np.array_equal(a, b), (kind, n, beta, seed)
+    out = np.empty(4, np.int64)
+    assert ldd.lib().ldd_make_shifts_variant(4, 0.1, 1, 3, out.ctypes.data) == ldd.ERR_INVALID_ARG
+
+
 STRUCTS = {"ldd_csr": ldd.Csr, "ldd_options": ldd.Options, "ldd_stats": ldd.Stats,
            "ldd_server_config": ldd.ServerConfig, "ldd_request": ldd.Request, "ldd_result": ldd.Result,
            "ldd_server_info": ldd.ServerInfo, "ldd_tune_report": ldd.TuneReport,

@@ -138,3 +138,50 @@ def test_batch_recipe_ranges():
     # log-uniform: the median of log n sits near the middle of the range
     mid = 0.5 * (math.log(1000) + math.log(200_000))
     assert abs(np.median(np.log(ns)) - mid) < 0.5
+
+
+# ------------------------------------------------------------------------------------------
+# shift variants of Sec. 5's closing remarks
+# ------------------------------------------------------------------------------------------
+def test_integer_shifts_with_permutation_tie_break():
+    """Integer parts are those of the Exp(beta) shifts (same draws); the fractional parts encode
+    the seeded ranking (rank 0 wins every tie: the largest fraction), distinct while n <= 2^20."""
+    for n, beta, seed in ((1, 0.1, 1), (997, 0.1, 3), (20000, 0.05, 8)):
+        s = inputs.make_shifts_variant(n, beta, seed, inputs.SHIFTS_INT_PERM)
+        e = inputs.make_shifts(n, beta, seed)
+        assert np.array_equal(s >> 20, e >> 20)
+        rank = inputs.perm_rank(n, seed)
+        assert np.array_equal(np.sort(rank), np.arange(n))
+        frac = s & ((1 << 20) - 1)
+        assert np.array_equal(frac, ((n - 1 - rank) << 20) // n)
+        assert np.unique(frac).size == n
+
+
+def test_shifts_from_permutation_positions():
+    """The vertex of rank i takes floor(2^20 (H_n - H_i) / beta): checked against exact rational
+    harmonic numbers (within one fixed-point unit, nearly always equal); the values decrease with
+    the rank, and their mean is 1/beta (the mean of the exponential order statistics)."""
+    from fractions import Fraction
+    n, beta, seed = 600, 0.25, 4
+    s = inputs.make_shifts_variant(n, beta, seed, inputs.SHIFTS_PERM_ORDER)
+    rank = inputs.perm_rank(n, seed)
+    by_rank = np.empty(n, np.int64)
+    by_rank[rank] = s
+    h = [Fraction(0)]
+    for j in range(1, n + 1):
+        h.append(h[-1] + Fraction(1, j))
+    exact = np.array([math.floor((h[n] - h[i]) / Fraction(beta) * (1 << 20)) for i in range(n)], np.int64)
+    assert np.abs(by_rank - exact).max() <= 1 and np.count_nonzero(by_rank != exact) <= 3
+    assert np.all(np.diff(by_rank) < 0)
+    big = inputs.make_shifts_variant(200_000, 0.1, 5, inputs.SHIFTS_PERM_ORDER)
+    assert abs(big.mean() / inputs.FIX_ONE - 10.0) < 1e-3
+
+
+def test_permutation_ranking_is_uniform():
+    """Over seeds, the rank of a fixed vertex is uniform over the n positions (chi-square)."""
+    n, seeds = 8, 4000
+    counts = np.zeros(n)
+    for seed in range(seeds):
+        counts[inputs.perm_rank(n, 100 + seed)[3]] += 1
+    stat = scipy.stats.chisquare(counts)
+    assert stat.pvalue > 1e-4
