@@ -376,6 +376,27 @@ ldd_status ldd_decompose_verified(const ldd_csr* g, double beta, uint64_t seed, 
                                   const ldd_verify_options* vopt, const ldd_options* opt, ldd_verify_report* report,
                                   void* hip_stream);
 
+/*
+ * Block decomposition (the Linial-Saks decomposition of Sec. 2, obtained by iterating the
+ * decomposition): level 0 decomposes the whole graph with shifts drawn as ldd_make_shifts_device
+ * (beta, seed); the edges inside a piece take level 0 and the cut edges form the graph of level
+ * 1, decomposed with seed + 1, and so on.  Each level cuts an edge with probability below beta
+ * (Cor. 4.5), so the edges left shrink geometrically; the edges of one level join only vertices
+ * of one piece of that level, within O(log n / beta) of its centre (Lemma 4.2).
+ *   g            graph in device memory (as ldd_decompose).
+ *   beta         the decomposition's parameter per level, in (0, 1); 0 = 1/2.
+ *   max_levels   levels at most (>= 1).
+ *   arc_level    device int32[nnz], OUT: the level of every arc (both arcs of an edge share it);
+ *                -1 for arcs left after max_levels levels.
+ *   levels       host, OUT: levels run.
+ *   level_edges  host int64[max_levels] (may be NULL), OUT: edges placed in each level run.
+ *   opt          options of the per-level decompositions (NULL = defaults).
+ * Returns LDD_ERR_RETRIES when arcs are left after max_levels levels (outputs as described),
+ * else as ldd_decompose.  Allocates its own device buffers (a few arrays of n and nnz ints).
+ */
+ldd_status ldd_block_decompose(const ldd_csr* g, double beta, uint64_t seed, int32_t max_levels, int32_t* arc_level,
+                               int32_t* levels, int64_t* level_edges, const ldd_options* opt, void* hip_stream);
+
 /* Human-readable name of a status code (static string). */
 const char* ldd_status_string(ldd_status s);
 /* Detail of the last error on this thread (static thread-local buffer). */

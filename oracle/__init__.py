@@ -12,7 +12,9 @@ ctypes wrapper over ``liblddoracle.so`` (``ldd_oracle.c``):
 * :func:`centre_of` -- one vertex's centre by the definition of Algorithm 2 (BFS from v,
   lexicographic argmin of the shifted distance, Eq. (1));
 * :func:`cut` -- cut edges of an assignment (Def. 1.1);
-* :func:`certify` -- linear-time certificate that an assignment is the exact argmin.
+* :func:`certify` -- linear-time certificate that an assignment is the exact argmin;
+* :func:`block_decomposition` -- the Linial-Saks block decomposition of Sec. 2 by iterating
+  :func:`decompose` on the edges not placed yet.
 """
 from __future__ import annotations
 
@@ -150,3 +152,28 @@ def certify(row_ptr, col_idx, shift_fix, centre):
     rc = _load().oracle_certify(n, rp.ctypes.data, ci.ctypes.data, sf.ctypes.data, ce.ctypes.data,
                                 ctypes.addressof(bad))
     return int(rc), int(bad.value)
+
+
+def block_decomposition(row_ptr, col_idx, level_shifts):
+    """Block decomposition by iterated decomposition (Sec. 2, Linial-Saks): level L decomposes
+    the graph of the arcs not placed yet with ``level_shifts[L]``; arcs whose ends share a centre
+    take level L, the others go on.  Returns (arc_level int32[nnz] with -1 for arcs not placed,
+    the number of levels run, edges placed per level)."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    n = rp.size - 1
+    level = np.full(ci.size, -1, np.int32)
+    src = np.repeat(np.arange(n, dtype=np.int32), np.diff(rp))
+    ids = np.arange(ci.size)
+    placed, run = [], 0
+    for L, s in enumerate(level_shifts):
+        if ids.size == 0:
+            break
+        rp_l = np.concatenate([[0], np.cumsum(np.bincount(src, minlength=n))]).astype(np.int32)
+        c, _, _ = decompose(rp_l, ci[ids], s)
+        inside = c[src] == c[ci[ids]]
+        level[ids[inside]] = L
+        placed.append(int(np.count_nonzero(inside)) // 2)
+        ids, src = ids[~inside], src[~inside]
+        run = L + 1
+    return level, run, placed

@@ -18,7 +18,8 @@ _ROOT = os.path.dirname(_HERE)
 SO_PATH = os.path.join(_HERE, "libldd.so")
 SOURCES = [os.path.join(_HERE, "csrc", f) for f in ("ldd_kernels.hip", "ldd_rounds.hip", "ldd_api.hip",
                                                    "ldd_batch.hip", "ldd_server.hip", "ldd_tune.hip",
-                                                   "ldd_static.hip", "ldd_shifts.hip", "ldd_block.hip")]
+                                                   "ldd_static.hip", "ldd_shifts.hip", "ldd_block.hip",
+                                                   "ldd_blockdec.hip")]
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
@@ -32,7 +33,7 @@ EXPORTED = ("ldd_decompose", "ldd_workspace_bytes", "ldd_decompose_batch", "ldd_
             "ldd_release_workspace", "ldd_server_create", "ldd_server_submit", "ldd_server_poll", "ldd_server_wait",
             "ldd_server_cancel", "ldd_server_query", "ldd_server_destroy", "ldd_tune",
             "ldd_decompose_static", "ldd_make_shifts", "ldd_make_shifts_device", "ldd_decompose_verified",
-            "ldd_make_shifts_variant")
+            "ldd_make_shifts_variant", "ldd_block_decompose")
 
 
 class LddError(RuntimeError):
@@ -148,6 +149,9 @@ def lib():
     L.ldd_decompose_static.restype = i32
     L.ldd_make_shifts.argtypes = [i32, ctypes.c_double, ctypes.c_uint64, vp]
     L.ldd_make_shifts.restype = i32
+    L.ldd_block_decompose.argtypes = [ctypes.POINTER(Csr), ctypes.c_double, ctypes.c_uint64, i32, vp,
+                                      ctypes.POINTER(ctypes.c_int32), vp, ctypes.POINTER(Options), vp]
+    L.ldd_block_decompose.restype = i32
     L.ldd_make_shifts_variant.argtypes = [i32, ctypes.c_double, ctypes.c_uint64, i32, vp]
     L.ldd_make_shifts_variant.restype = i32
     L.ldd_make_shifts_device.argtypes = [i32, ctypes.c_double, ctypes.c_uint64, vp, vp]
@@ -305,6 +309,29 @@ def decompose_verified(row_ptr, col_idx, beta: float, seed: int, *, cut_factor: 
     if status != ERR_RETRIES:
         _check(status)
     return centre, shifts, rep.as_dict()
+
+
+def block_decompose(row_ptr, col_idx, *, beta: float = 0.5, seed: int = 1, max_levels: int = 64, stream=None,
+                    **opts):
+    """Linial-Saks block decomposition by iterated decomposition (``ldd_block_decompose``).
+    Returns ``(arc_level int32[nnz] tensor, level_edges list)``; arcs left after max_levels
+    levels keep level -1 (status LDD_ERR_RETRIES is returned as that, not raised)."""
+    import numpy as np
+    import torch
+    _device_tensor(row_ptr, torch.int32, "row_ptr")
+    _device_tensor(col_idx, torch.int32, "col_idx")
+    n = row_ptr.numel() - 1
+    arc_level = torch.empty(col_idx.numel(), dtype=torch.int32, device=row_ptr.device)
+    g = Csr(n, col_idx.numel(), row_ptr.data_ptr(), col_idx.data_ptr() if col_idx.numel() else None)
+    levels = ctypes.c_int32(0)
+    edges = np.zeros(max_levels, np.int64)
+    o = make_options(**opts)
+    status = lib().ldd_block_decompose(ctypes.byref(g), float(beta), seed & (2**64 - 1), int(max_levels),
+                                       arc_level.data_ptr() if col_idx.numel() else None, ctypes.byref(levels),
+                                       edges.ctypes.data, ctypes.byref(o), _stream_handle(stream))
+    if status != ERR_RETRIES:
+        _check(status)
+    return arc_level, [int(x) for x in edges[:levels.value]]
 
 
 STATIC_MAX_VERTICES = 1 << 20  # LDD_STATIC_MAX_VERTICES

@@ -370,3 +370,59 @@ def test_las_vegas_bounds_hold_with_constant_probability():
             assert radius * S <= int(s.max())
             ok += cut <= 2 * beta * m and radius <= 3 * math.log(n) / beta
         assert ok >= 60, ok
+
+
+# ------------------------------------------------------------------------------------------
+# block decomposition by iterated decomposition (Sec. 2, Linial-Saks)
+# ------------------------------------------------------------------------------------------
+def brute_block_levels(rp, ci, level_shifts):
+    """The iteration written with the brute-force decomposition (scipy distances + argmin)."""
+    n = rp.size - 1
+    src = np.repeat(np.arange(n), np.diff(rp))
+    level = np.full(ci.size, -1)
+    alive = np.ones(ci.size, bool)
+    for L, s in enumerate(level_shifts):
+        if not alive.any():
+            break
+        rp_l, ci_l = inputs.from_edges(n, src[alive], ci[alive])
+        c, _ = brute_force(rp_l, ci_l, s)
+        inside = alive & (c[src] == c[ci])
+        level[inside] = L
+        alive &= ~inside
+    return level
+
+
+def test_block_decomposition_matches_brute_force():
+    rng = np.random.default_rng(31)
+    for _ in range(25):
+        n = int(rng.integers(2, 30))
+        rp, ci = random_graph(rng, n, float(rng.choice([0.1, 0.3, 0.6])))
+        shifts = [shift_family(rng, n, str(rng.choice(KINDS))) for _ in range(12)]
+        lv, run, placed = oracle.block_decomposition(rp, ci, shifts)
+        assert np.array_equal(lv, brute_block_levels(rp, ci, shifts))
+        assert sum(placed) == np.count_nonzero(lv >= 0) // 2
+
+
+def test_block_decomposition_invariants():
+    """Both arcs of an edge share a level; a dominant shift places a connected graph in level 0;
+    singleton decompositions (all shifts below one unit) place nothing; with beta = 1/2 the edges
+    left shrink geometrically (each level cuts an edge with probability below 1 - e^-1/2 < 0.4,
+    Cor. 4.5), so a few dozen levels place all of them."""
+    rp, ci = inputs.grid2d(12, 12)
+    n = rp.size - 1
+    s0 = np.zeros(n, np.int64)
+    s0[30] = 100 * S
+    lv, run, _ = oracle.block_decomposition(rp, ci, [s0])
+    assert run == 1 and np.all(lv == 0)
+    lv, run, placed = oracle.block_decomposition(rp, ci, [np.zeros(n, np.int64), s0])
+    assert placed[0] == 0 and np.all(lv == 1)
+    for (rp, ci) in (inputs.grid2d(40, 40), inputs.rmat(12, 16, seed=6), inputs.er(3000, 6.0, 2)):
+        n, m = rp.size - 1, ci.size // 2
+        shifts = [inputs.make_shifts(n, 0.5, 500 + L) for L in range(60)]
+        lv, run, placed = oracle.block_decomposition(rp, ci, shifts)
+        assert np.all(lv >= 0) and run < 60
+        src = np.repeat(np.arange(n), np.diff(rp))
+        lookup = dict(zip(zip(src.tolist(), ci.tolist()), lv.tolist()))
+        assert all(lookup[(v, u)] == l for (u, v), l in lookup.items())
+        left = m - np.cumsum(placed)
+        assert left[0] <= 0.6 * m and (run < 4 or left[3] <= 0.3 * m)
