@@ -84,12 +84,16 @@ typedef struct {
   int32_t tail_vertices;  /* finish by label correction once unsettled vertices * this <= active vertices
                              (0 = default 32, -1 = never)                                                      */
   int32_t batch_mode;     /* ldd_decompose_batch: LDD_BATCH_* (below)                                    */
-  int32_t reserved[8];
+  int32_t team_arcs;      /* workgroup batch engine: arcs per workgroup of a team (0 = default: all arcs over
+                             the grid, at least 2^14; -1 = no teams: one workgroup per graph)                 */
+  int32_t reserved[7];
 } ldd_options;
 
 /* Batch engines: AUTO = WORKGROUP (one workgroup per graph, the largest graphs first, every
- * graph's rounds with workgroup barriers only; a graph whose shifts span 4096 or more units of
- * distance runs alone on the launch engine); SEQUENTIAL = one ldd_decompose per graph (the plain
+ * graph's rounds with workgroup barriers only; a graph with many more arcs than a workgroup's
+ * share of the batch runs on a team of up to 16 workgroups that meet at a barrier in device
+ * memory once per round; a graph whose shifts span 4096 or more units of distance runs alone on
+ * the launch engine); SEQUENTIAL = one ldd_decompose per graph (the plain
  * path, for comparison); UNION = the disjoint union of all graphs on the launch engine, one
  * launch per round for all graphs. */
 enum { LDD_BATCH_AUTO = 0, LDD_BATCH_SEQUENTIAL = 1, LDD_BATCH_UNION = 2, LDD_BATCH_WORKGROUP = 3 };

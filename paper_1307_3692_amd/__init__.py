@@ -50,8 +50,8 @@ class Csr(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("direction", ctypes.c_int32), ("engine", ctypes.c_int32), ("validate", ctypes.c_int32),
                 ("blocks", ctypes.c_int32), ("td_to_bu", ctypes.c_int32), ("bu_to_td", ctypes.c_int32),
-                ("tail_vertices", ctypes.c_int32), ("batch_mode", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 8)]
+                ("tail_vertices", ctypes.c_int32), ("batch_mode", ctypes.c_int32), ("team_arcs", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 7)]
 
 
 class Stats(ctypes.Structure):
@@ -211,10 +211,11 @@ BATCH_AUTO, BATCH_SEQUENTIAL, BATCH_UNION, BATCH_WORKGROUP = 0, 1, 2, 3
 
 
 def make_options(direction=DIR_AUTO, engine=ENGINE_AUTO, validate=False, blocks=0, td_to_bu=0, bu_to_td=0,
-                 tail_vertices=0, batch_mode=BATCH_AUTO) -> Options:
+                 tail_vertices=0, batch_mode=BATCH_AUTO, team_arcs=0) -> Options:
     o = Options()
     o.direction, o.engine, o.validate, o.blocks = direction, engine, int(validate), blocks
     o.td_to_bu, o.bu_to_td, o.tail_vertices, o.batch_mode = td_to_bu, bu_to_td, tail_vertices, batch_mode
+    o.team_arcs = team_arcs
     return o
 
 

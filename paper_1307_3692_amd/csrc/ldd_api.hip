@@ -110,7 +110,7 @@ struct Workspace {
   Buf cand, cand_cnt;                                    // per prep block: first-window candidates
   Buf ctrl, st, qcnt, lr_part, lb, ex_part, vr;
   // workgroup engine: queues and wake order (3 ints per vertex), jobs, order, results, job counter
-  Buf bk_wq, bk_jobs, bk_order, bk_out, bk_cnt;
+  Buf bk_wq, bk_jobs, bk_order, bk_out, bk_cnt, bk_team, bk_sync, bk_tq;
   // batch: union CSR with global ids, adjusted shifts, graph of each vertex, per-graph data
   Buf b_rp, b_col, b_shift, b_gid, b_off, b_dg, b_cut;
   HostMirror* host = nullptr;
@@ -218,7 +218,7 @@ extern "C" void ldd_release_workspace(void) {
   w->graphs.clear();
   for (Buf* b : {&w->P, &w->qv0, &w->qv1, &w->qa0, &w->qa1, &w->wake_ord, &w->stamp, &w->hub_bits, &w->hist,
                  &w->cursor, &w->wake_off, &w->next_ne, &w->mat, &w->qmax, &w->cand, &w->cand_cnt, &w->ctrl, &w->st, &w->qcnt, &w->lr_part,
-                 &w->lb, &w->ex_part, &w->vr, &w->bk_wq, &w->bk_jobs, &w->bk_order, &w->bk_out, &w->bk_cnt, &w->b_rp, &w->b_col, &w->b_shift, &w->b_gid, &w->b_off, &w->b_dg,
+                 &w->lb, &w->ex_part, &w->vr, &w->bk_wq, &w->bk_jobs, &w->bk_order, &w->bk_out, &w->bk_cnt, &w->bk_team, &w->bk_sync, &w->bk_tq, &w->b_rp, &w->b_col, &w->b_shift, &w->b_gid, &w->b_off, &w->b_dg,
                  &w->b_cut}) {
     if (b->p) (void)hipFree(b->p);
     b->p = nullptr;
@@ -666,6 +666,9 @@ __global__ void k_block_job_single(int n, long long nnz, const int* row_ptr, con
   j.q0 = wq + n;
   j.q1 = wq + 2 * (long long)n;
   j.tail_den = tail_den;
+  j.team = 1;
+  j.sync = nullptr;
+  j.tq = nullptr;
   *job = j;
 }
 
@@ -689,8 +692,8 @@ static ldd_status decompose_block(Workspace& w, const ldd_csr* g, const int64_t*
                      (BlockJob*)w.bk_jobs.p);
   hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, (u64*)w.bk_cnt.p, 1ll, 0ull);
   HIP_TRY(hipEventRecord(w.ev[1], st));
-  hipLaunchKernelGGL(k_block_decompose, dim3(1), dim3(1024), 0, st, (const BlockJob*)w.bk_jobs.p, (const int*)nullptr,
-                     1, (unsigned*)w.bk_cnt.p, (BlockOut*)w.bk_out.p);
+  hipLaunchKernelGGL(k_block_decompose, dim3(1), dim3(1024), 0, st, (const BlockJob*)w.bk_jobs.p,
+                     (const TeamJob*)nullptr, 1, (unsigned*)w.bk_cnt.p, (BlockOut*)w.bk_out.p);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipEventRecord(w.ev[2], st));
   HIP_TRY(hipMemcpyAsync(&w.host->bout, w.bk_out.p, sizeof(BlockOut), hipMemcpyDeviceToHost, st));
@@ -862,34 +865,75 @@ ldd_status ldd_batch_workgroup(int32_t G, const int64_t* vtx_off, const int64_t*
     std::lock_guard<std::mutex> lk(w.mu);
     ldd_status s = ws_setup(w);
     if (s != LDD_OK) return s;
-    if ((s = grow(w.P, (size_t)N * 8)) || (s = grow(w.bk_wq, (size_t)N * 12)) ||
-        (s = grow(w.bk_jobs, (size_t)G * sizeof(BlockJob))) || (s = grow(w.bk_order, (size_t)G * 4)) ||
-        (s = grow(w.bk_out, (size_t)G * sizeof(BlockOut))) || (s = grow(w.bk_cnt, 8)) ||
-        (s = grow(w.b_off, (size_t)(G + 1) * 16)))
-      return s;
-    // largest graphs (by arcs, then vertices) first, so that the last graphs to start are short
+    int grid = o.blocks > 0 ? o.blocks : 2 * w.num_cu;
+    // Teams: a graph with more arcs than a workgroup's share of the batch (all arcs over the grid,
+    // at least 2^14; or team_arcs when given) runs on K = ceil(arcs / share) workgroups (at most
+    // TEAM_MAX, at most a quarter of the grid, at least 64 vertices per member), so that no graph
+    // holds one workgroup long after the others are done.
+    const long long M = arc_off[G];
+    std::vector<int> team((size_t)G, 1);
+    const long long share = o.team_arcs > 0 ? o.team_arcs : std::max(M / grid, 1ll << 14);
+    const int kcap = o.team_arcs < 0 ? 1 : std::min(TEAM_MAX, grid / 4);
+    for (int g = 0; g < G; ++g) {
+      const long long e = arc_off[g + 1] - arc_off[g], nv = vtx_off[g + 1] - vtx_off[g];
+      long long k = (e + share - 1) / share;
+      k = std::min<long long>(k, kcap);
+      k = std::min<long long>(k, nv / 64);
+      team[g] = k > 1 ? (int)k : 1;
+    }
+    // jobs, the heaviest per workgroup (arcs / team size, then vertices) first; a team's members
+    // are consecutive
     std::vector<int> order((size_t)G);
     for (int g = 0; g < G; ++g) order[g] = g;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-      const long long ea = arc_off[a + 1] - arc_off[a], eb = arc_off[b + 1] - arc_off[b];
+      const long long ea = (arc_off[a + 1] - arc_off[a]) / team[a], eb = (arc_off[b + 1] - arc_off[b]) / team[b];
       if (ea != eb) return ea > eb;
       return vtx_off[a + 1] - vtx_off[a] > vtx_off[b + 1] - vtx_off[b];
     });
+    std::vector<TeamJob> jobs;
+    jobs.reserve((size_t)G);
+    std::vector<int> tinfo((size_t)G * 2, 0);
+    std::vector<long long> tq_off((size_t)G, 0);
+    int nteams = 0;
+    long long tq_len = 0;
+    for (int g : order) {
+      tinfo[2 * (size_t)g] = team[g];
+      if (team[g] > 1) {
+        tinfo[2 * (size_t)g + 1] = nteams++;
+        tq_off[g] = tq_len;
+        tq_len += 2ll * team[g] * (vtx_off[g + 1] - vtx_off[g]);
+      }
+      for (int m = 0; m < team[g]; ++m) jobs.push_back(TeamJob{g, m});
+    }
+    const int njobs = (int)jobs.size();
+    if ((s = grow(w.P, (size_t)N * 8)) || (s = grow(w.bk_wq, (size_t)N * 12)) ||
+        (s = grow(w.bk_jobs, (size_t)G * sizeof(BlockJob))) || (s = grow(w.bk_order, (size_t)njobs * sizeof(TeamJob))) ||
+        (s = grow(w.bk_out, (size_t)G * sizeof(BlockOut))) || (s = grow(w.bk_cnt, 8)) ||
+        (s = grow(w.b_off, (size_t)(G + 1) * 16)) || (s = grow(w.bk_team, (size_t)G * 16)) ||
+        (s = grow(w.bk_sync, (size_t)(nteams > 0 ? nteams : 1) * sizeof(TeamSync))) ||
+        (s = grow(w.bk_tq, (size_t)(tq_len > 0 ? tq_len : 1) * 4)))
+      return s;
     long long* d_vo = (long long*)w.b_off.p;
     long long* d_ao = d_vo + (G + 1);
+    int* d_team = (int*)w.bk_team.p;
+    long long* d_tqoff = (long long*)((char*)w.bk_team.p + (size_t)G * 8);
     HIP_TRY(hipStreamWaitEvent(st, w.ev[2], 0));  // after any step a previous call left queued
     HIP_TRY(hipMemcpyAsync(d_vo, vtx_off, (size_t)(G + 1) * 8, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(d_ao, arc_off, (size_t)(G + 1) * 8, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(w.bk_order.p, order.data(), (size_t)G * 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(w.bk_order.p, jobs.data(), (size_t)njobs * sizeof(TeamJob), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(d_team, tinfo.data(), (size_t)G * 8, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(d_tqoff, tq_off.data(), (size_t)G * 8, hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(k_block_jobs, dim3(grid_for(G, 256, 1024)), dim3(256), 0, st, G, N, (const long long*)d_vo,
                        (const long long*)d_ao, row_ptr, col_idx, (const long long*)shift_fix, centre, (u64*)w.P.p,
-                       (int*)w.bk_wq.p, tail_den_of(o), (BlockJob*)w.bk_jobs.p);
+                       (int*)w.bk_wq.p, tail_den_of(o), (const int*)d_team, (TeamSync*)w.bk_sync.p, (int*)w.bk_tq.p,
+                       (const long long*)d_tqoff, (BlockJob*)w.bk_jobs.p);
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, (u64*)w.bk_cnt.p, 1ll, 0ull);
-    const int per_cu = o.blocks > 0 ? 0 : 2;
-    int grid = o.blocks > 0 ? o.blocks : per_cu * w.num_cu;
-    if (grid > G) grid = G;
+    if (nteams > 0)
+      hipLaunchKernelGGL(k_fill_u64, dim3(grid_for((long long)nteams * sizeof(TeamSync) / 8, 256, 1024)), dim3(256), 0,
+                         st, (u64*)w.bk_sync.p, (long long)nteams * (long long)(sizeof(TeamSync) / 8), 0ull);
+    if (grid > njobs) grid = njobs;
     hipLaunchKernelGGL(k_block_decompose, dim3(grid), dim3(1024), 0, st, (const BlockJob*)w.bk_jobs.p,
-                       (const int*)w.bk_order.p, G, (unsigned*)w.bk_cnt.p, (BlockOut*)w.bk_out.p);
+                       (const TeamJob*)w.bk_order.p, njobs, (unsigned*)w.bk_cnt.p, (BlockOut*)w.bk_out.p);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(w.ev[2], st));
     std::vector<BlockOut> outs((size_t)G);

@@ -1,5 +1,5 @@
-// The workgroup-owned engine (one workgroup runs every round of one graph): job and result
-// records and the kernels.
+// The workgroup-owned engine (one workgroup, or a team of a few workgroups, runs every round of
+// one graph): job and result records and the kernels.
 #pragma once
 #include "ldd_device.h"
 
@@ -13,6 +13,18 @@ constexpr int BLOCK_WCAP = 4096;
 // needs more wake buckets than the workgroup sorts
 enum : unsigned { BLK_OVERFLOW = 64u, BLK_WIDE = 128u };
 
+// A large graph of a batch runs on a team of K <= TEAM_MAX workgroups that meet at a barrier
+// once per round.  Per team, in device memory, zeroed before the launch: the barrier's arrival
+// counter, each member's values for the round's exchange (double-buffered), and each member's
+// non-empty wake buckets.
+constexpr int TEAM_MAX = 16;
+
+struct TeamSync {
+  alignas(128) unsigned arrive;
+  alignas(128) u64 red[2][TEAM_MAX][4];
+  u64 nz[TEAM_MAX][BLOCK_WCAP / 64];
+};
+
 struct BlockJob {
   int n;
   long long nnz;
@@ -25,6 +37,9 @@ struct BlockJob {
   int* q0;               // workspace [n]: frontier queues
   int* q1;
   int tail_den;          // label-correcting tail once unreached * tail_den <= vertices with arcs (0: never)
+  int team;              // workgroups on this graph (1: alone)
+  TeamSync* sync;        // team > 1: the team's barrier and exchange area
+  int* tq;               // team > 1: workspace [2 * team * n]: two sets of per-member frontier segments
 };
 
 struct BlockOut {
@@ -40,9 +55,14 @@ struct BlockOut {
   u64 t_end;      // ... and when it finished it
 };
 
-__global__ void k_block_decompose(const BlockJob* jobs, const int* order, int njobs, unsigned* next_job, BlockOut* outs);
+// One job of the kernel's list: graph g, member m of its team.
+struct TeamJob {
+  int g, m;
+};
+
+__global__ void k_block_decompose(const BlockJob* jobs, const TeamJob* order, int njobs, unsigned* next_job, BlockOut* outs);
 __global__ void k_block_jobs(int G, long long N, const long long* vo, const long long* ao, const int* row_ptr,
                              const int* col, const long long* shift, int* centre, u64* P, int* wq, int tail_den,
-                             BlockJob* jobs);
+                             const int* team, TeamSync* sync, int* tq, const long long* tq_off, BlockJob* jobs);
 
 }  // namespace ldd

@@ -20,6 +20,14 @@
 // Top-down is arc-balanced inside the workgroup: a chunk of RT frontier entries is staged in LDS
 // (first arc, degree prefix, offer) and every thread takes arcs of the chunk by index, finding its
 // entry by binary search, so a high-degree vertex is shared by all threads.
+//
+// A graph too large for one workgroup to finish in step with the rest of a batch runs on a team
+// of K workgroups (K <= TEAM_MAX, all resident at once): member m owns a slice of the vertices
+// (its preparation, wake buckets, tail seed and output) and one K-th of every frontier; each
+// member appends what it reaches to a segment of its own, and the members meet once per round
+// at a barrier in device memory where they exchange their segment lengths and error bits, so
+// the next frontier is the concatenation of the K segments.  The labels are then shared by
+// several CUs, so their loads and atomics take device scope.
 #include "ldd_block.h"
 
 namespace ldd {
@@ -44,6 +52,14 @@ struct BlockShared {
   u64 delta, n_active;       // preparation results
   u64 settled, examined;     // round results
   long long rounds, sweeps;
+  // team of several workgroups on one graph
+  TeamSync* ts;
+  int tK, tm, tlo, thi;      // team size, this member, this member's vertex slice
+  unsigned epoch;            // barriers passed
+  int par;                   // exchange buffer in use
+  unsigned tpre[TEAM_MAX + 1];  // current frontier: exclusive prefix of the members' segment lengths
+  u64 tv[TEAM_MAX][4];       // the members' values of the last exchange
+  u64 nz[BLOCK_WCAP / 64];   // non-empty wake buckets of the whole graph
 };
 
 __device__ __forceinline__ u64 block_max64(u64 v, BlockShared& sh) {
@@ -101,60 +117,40 @@ __device__ __forceinline__ int next_nonempty(BlockShared& sh, int r, int D) {
 }
 
 // A graph's labels are touched by its own workgroup only while it runs, so their loads and atomics
-// need workgroup scope alone (all waves of a workgroup share one CU and its vector L1).
-__device__ __forceinline__ u64 wg_load(const u64* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+// need workgroup scope alone (all waves of a workgroup share one CU and its vector L1); a team's
+// labels are shared by its members' CUs and take device scope.
+constexpr int WG = __HIP_MEMORY_SCOPE_WORKGROUP;
+constexpr int AG = __HIP_MEMORY_SCOPE_AGENT;
+
+template <int SC>
+__device__ __forceinline__ u64 lab_load(const u64* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, SC);
 }
-__device__ __forceinline__ u64 wg_min(u64* p, u64 v) {
-  return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+template <int SC>
+__device__ __forceinline__ u64 lab_min(u64* p, u64 v) {
+  return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, SC);
 }
+template <int SC>
+__device__ __forceinline__ void lab_store(u64* p, u64 v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, SC);
+}
+__device__ __forceinline__ u64 wg_load(const u64* p) { return lab_load<WG>(p); }
 
 __device__ __forceinline__ void append(BlockShared& sh, int* next, int v) {
   const unsigned idx = atomicAdd(&sh.cnt, 1u);
   next[idx] = v;
 }
 
-// Preparation of one graph: checks, Delta, the vertices with arcs, labels INF, and the wake
-// buckets (counting sort of the vertices with arcs by w(v) = (Delta - shift) >> 20 in LDS, with
-// bucket offsets).  Results in sh (delta, n_active, err, woff).
-__device__ __attribute__((noinline)) void block_prepare(const BlockJob& j, BlockShared& sh) {
-  const int n = j.n;
-  const long long nnz = j.nnz;
+// Wake buckets of the vertices with arcs in [lo, hi): counting sort by w(v) = (Delta - shift) >> 20
+// in LDS; the sorted ids go to wake[lo ...] and sh.woff[q] is bucket q's offset from lo (all
+// threads call).
+__device__ __forceinline__ void wake_sort(const BlockJob& j, BlockShared& sh, int lo, int hi, u64 delta) {
   const int* __restrict__ rp = j.row_ptr;
   const long long* __restrict__ shift = j.shift;
-  u64* P = j.P;
   const int tid = threadIdx.x;
-  unsigned err = 0;
-  u64 dmax = 0, active = 0;
-  if (n > 0 && (rp[0] != 0 || (long long)rp[n] != nnz) && tid == 0) err |= ERR_BAD_ROWPTR;
-  for (int v = tid; v < n; v += BT) {
-    const long long s = shift[v];
-    if (s < 0 || s > (1ll << 52)) err |= ERR_BAD_SHIFT;
-    const int a0 = rp[v], a1 = rp[v + 1];
-    if (a1 < a0) err |= ERR_BAD_ROWPTR;
-    active += a1 > a0;
-    dmax = (u64)s > dmax ? (u64)s : dmax;
-    P[v] = INF;
-  }
-  if (tid == 0) sh.err = 0;
   for (int q = tid; q <= BLOCK_WCAP; q += BT) sh.woff[q] = 0;
   __syncthreads();
-  if (err) atomicOr(&sh.err, err);
-  const u64 delta = block_max64(dmax, sh);
-  const u64 n_active = block_sum64(active, sh);
-  const int B = n > 1 ? 32 - __builtin_clz((unsigned)(n - 1)) : 1;
-  const u64 D = delta >> FIX;
-  if (tid == 0) {
-    unsigned e = sh.err;
-    if (!e && (delta + ((u64)1 << FIX)) >= ((u64)1 << (64 - B))) e |= BLK_OVERFLOW;
-    else if (!e && D >= (u64)BLOCK_WCAP) e |= BLK_WIDE;
-    sh.err = e;
-    sh.delta = delta;
-    sh.n_active = n_active;
-  }
-  __syncthreads();
-  if (sh.err) return;
-  for (int v = tid; v < n; v += BT)
+  for (int v = lo + tid; v < hi; v += BT)
     if (rp[v + 1] > rp[v]) atomicAdd(&sh.woff[(int)((delta - (u64)shift[v]) >> FIX)], 1);
   __syncthreads();
   {
@@ -178,10 +174,10 @@ __device__ __attribute__((noinline)) void block_prepare(const BlockJob& j, Block
   __syncthreads();
   // scatter: woff[q] serves as bucket q's cursor (it ends at the start of bucket q + 1) and is
   // shifted back by one bucket afterwards
-  for (int v = tid; v < n; v += BT) {
+  for (int v = lo + tid; v < hi; v += BT) {
     if (rp[v + 1] > rp[v]) {
       const int q = (int)((delta - (u64)shift[v]) >> FIX);
-      j.wake[atomicAdd(&sh.woff[q], 1)] = v;
+      j.wake[lo + atomicAdd(&sh.woff[q], 1)] = v;
     }
   }
   __syncthreads();
@@ -199,13 +195,69 @@ __device__ __attribute__((noinline)) void block_prepare(const BlockJob& j, Block
   }
 }
 
+// Checks, Delta and the count of vertices with arcs over [lo, hi), which also get label INF
+// (all threads call; results are the workgroup's: *dmax and *active reduced, errors in sh.err,
+// which the caller cleared).
+__device__ __forceinline__ void prepare_scan(const BlockJob& j, BlockShared& sh, int lo, int hi, bool ends,
+                                             u64* dmax_out, u64* active_out) {
+  const int n = j.n;
+  const long long nnz = j.nnz;
+  const int* __restrict__ rp = j.row_ptr;
+  const long long* __restrict__ shift = j.shift;
+  u64* P = j.P;
+  const int tid = threadIdx.x;
+  unsigned err = 0;
+  u64 dmax = 0, active = 0;
+  if (ends && n > 0 && (rp[0] != 0 || (long long)rp[n] != nnz) && tid == 0) err |= ERR_BAD_ROWPTR;
+  for (int v = lo + tid; v < hi; v += BT) {
+    const long long s = shift[v];
+    if (s < 0 || s > (1ll << 52)) err |= ERR_BAD_SHIFT;
+    const int a0 = rp[v], a1 = rp[v + 1];
+    if (a1 < a0) err |= ERR_BAD_ROWPTR;
+    active += a1 > a0;
+    dmax = (u64)s > dmax ? (u64)s : dmax;
+    P[v] = INF;
+  }
+  if (err) atomicOr(&sh.err, err);
+  *dmax_out = block_max64(dmax, sh);
+  *active_out = block_sum64(active, sh);
+  __syncthreads();
+}
+
+// The checks that need Delta: labels fit 64 bits, and the shifts span fewer than BLOCK_WCAP units.
+__device__ __forceinline__ unsigned range_err(int n, u64 delta) {
+  const int B = n > 1 ? 32 - __builtin_clz((unsigned)(n - 1)) : 1;
+  if ((delta + ((u64)1 << FIX)) >= ((u64)1 << (64 - B))) return BLK_OVERFLOW;
+  if ((delta >> FIX) >= (u64)BLOCK_WCAP) return BLK_WIDE;
+  return 0;
+}
+
+// Preparation of one graph: checks, Delta, the vertices with arcs, labels INF, and the wake
+// buckets.  Results in sh (delta, n_active, err, woff).
+__device__ __attribute__((noinline)) void block_prepare(const BlockJob& j, BlockShared& sh) {
+  if (threadIdx.x == 0) sh.err = 0;
+  __syncthreads();
+  u64 delta, n_active;
+  prepare_scan(j, sh, 0, j.n, true, &delta, &n_active);
+  if (threadIdx.x == 0) {
+    unsigned e = sh.err;
+    if (!e) e = range_err(j.n, delta);
+    sh.err = e;
+    sh.delta = delta;
+    sh.n_active = n_active;
+  }
+  __syncthreads();
+  if (sh.err) return;
+  wake_sort(j, sh, 0, j.n, delta);
+}
+
 // Relax the arcs of a staged chunk (ne entries: first arc, degree prefix, offer in LDS; total
 // arcs): every arc offers its entry's label plus one unit to its far end (atomic minimum).  A
 // round appends a far end reached for the first time (old label INF); a tail sweep appends a far
 // end whose label dropped, once per sweep (its stamp takes the sweep's tag).  U arcs per thread
 // are issued together (entries by binary search in LDS, column ids, far labels, minima); one at a
 // time measured fastest (more in flight cost registers and did not pay on batches or small graphs).
-template <bool SWEEP>
+template <int SC, bool SWEEP>
 __device__ __forceinline__ void relax_chunk(const BlockJob& j, BlockShared& sh, int* next, unsigned ne,
                                             unsigned total, int tag) {
   constexpr int U = 1;
@@ -232,15 +284,14 @@ __device__ __forceinline__ void relax_chunk(const BlockJob& j, BlockShared& sh, 
     for (int k = 0; k < U; ++k) {
       const bool ok = (unsigned)w[k] < (unsigned)n;
       if (!ok && w[k] != -2) atomicOr(&sh.err, ERR_BAD_COL);
-      pw[k] = ok ? wg_load(&P[w[k]]) : 0;
+      pw[k] = ok ? lab_load<SC>(&P[w[k]]) : 0;
     }
 #pragma unroll
     for (int k = 0; k < U; ++k) {
       if (pw[k] > off[k]) {
-        const u64 old = wg_min(&P[w[k]], off[k]);
+        const u64 old = lab_min<SC>(&P[w[k]], off[k]);
         if (SWEEP) {
-          if (old > off[k] &&
-              __hip_atomic_exchange(&j.wake[w[k]], tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != tag)
+          if (old > off[k] && __hip_atomic_exchange(&j.wake[w[k]], tag, __ATOMIC_RELAXED, SC) != tag)
             append(sh, next, w[k]);
         } else if (old == INF) {
           append(sh, next, w[k]);
@@ -250,28 +301,37 @@ __device__ __forceinline__ void relax_chunk(const BlockJob& j, BlockShared& sh, 
   }
 }
 
-// Stage a chunk of frontier entries [c0, c0 + BT) in LDS and relax its arcs (all threads call).
-template <bool SWEEP>
-__device__ __forceinline__ u64 expand_frontier(const BlockJob& j, BlockShared& sh, const int* cur, unsigned nf,
-                                               int* next, u64 unit, int tag) {
+// Relax the arcs of frontier entries [e0, e1), staged in LDS a chunk of BT entries at a time (all
+// threads call).  Alone (TEAM false) the frontier is cur[0 ...]; in a team it is the concatenation
+// of the members' segments, member s's at cur + s n with length tpre[s + 1] - tpre[s].
+template <int SC, bool SWEEP, bool TEAM>
+__device__ __forceinline__ u64 expand_frontier(const BlockJob& j, BlockShared& sh, const int* cur, unsigned e0,
+                                               unsigned e1, int* next, u64 unit, int tag) {
   const int* __restrict__ rp = j.row_ptr;
   u64 examined = 0;
-  for (unsigned c0 = 0; c0 < nf; c0 += BT) {
+  for (unsigned c0 = e0; c0 < e1; c0 += BT) {
     const unsigned e = c0 + threadIdx.x;
     unsigned deg = 0;
-    if (e < nf) {
-      const int u = cur[e];
+    if (e < e1) {
+      int u;
+      if (TEAM) {
+        int s = 0;
+        while (s + 1 < sh.tK && sh.tpre[s + 1] <= e) ++s;
+        u = cur[(long long)s * j.n + (e - sh.tpre[s])];
+      } else {
+        u = cur[e];
+      }
       const int a0 = rp[u], a1 = rp[u + 1];
       deg = (unsigned)(a1 - a0);
       sh.first[threadIdx.x] = a0;
-      sh.offer[threadIdx.x] = wg_load(&j.P[u]) + unit;
+      sh.offer[threadIdx.x] = lab_load<SC>(&j.P[u]) + unit;
     }
     unsigned total;
     const unsigned ex = block_excl_scan(deg, sh, &total);
     sh.pre[threadIdx.x] = ex;
     __syncthreads();
     examined += threadIdx.x == 0 ? total : 0;
-    relax_chunk<SWEEP>(j, sh, next, nf - c0 < (unsigned)BT ? nf - c0 : (unsigned)BT, total, tag);
+    relax_chunk<SC, SWEEP>(j, sh, next, e1 - c0 < (unsigned)BT ? e1 - c0 : (unsigned)BT, total, tag);
     __syncthreads();
   }
   return examined;
@@ -315,12 +375,12 @@ __device__ __attribute__((noinline)) void block_rounds(const BlockJob& j, BlockS
         const int v = j.wake[i];
         const u64 self = ((delta - (u64)shift[v]) << B) | (u64)v;
         if (wg_load(&P[v]) > self) {
-          const u64 old = wg_min(&P[v], self);
+          const u64 old = lab_min<WG>(&P[v], self);
           if (old == INF) append(sh, next, v);
         }
       }
     }
-    examined += expand_frontier<false>(j, sh, cur, nf, next, unit, 0);
+    examined += expand_frontier<WG, false, false>(j, sh, cur, 0, nf, next, unit, 0);
     __syncthreads();
     nf = sh.cnt;
     if (sh.err) break;
@@ -358,7 +418,7 @@ __device__ __attribute__((noinline)) void block_rounds(const BlockJob& j, BlockS
         if (pu != INF && (pu >> (FIX + B)) == prev_round && pu + unit < best) best = pu + unit;
       }
       examined += (u64)(a1 - a0);
-      __hip_atomic_store(&P[v], best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      lab_store<WG>(&P[v], best);
       j.wake[v] = -1;  // the stamp of the first sweep
       append(sh, next, v);
     }
@@ -372,7 +432,7 @@ __device__ __attribute__((noinline)) void block_rounds(const BlockJob& j, BlockS
       __syncthreads();
       if (tid == 0) sh.cnt = 0;
       __syncthreads();
-      examined += expand_frontier<true>(j, sh, cur, nf, next, unit, -(k + 1));
+      examined += expand_frontier<WG, true, false>(j, sh, cur, 0, nf, next, unit, -(k + 1));
       __syncthreads();
       nf = sh.cnt;
       ++sweeps;
@@ -450,13 +510,336 @@ __device__ void block_graph(const BlockJob& j, BlockShared& sh, BlockOut* out) {
   block_output(j, sh, out);
 }
 
+// ---- a team of workgroups on one graph ----------------------------------------------------
+
+// The team's barrier, with an exchange: every member publishes four values (workgroup-uniform:
+// thread 0's are taken), and after the barrier every member holds all members' values in sh.tv
+// (all threads call).  The arrival counter only grows; the values are double-buffered, so a
+// member that leaves one exchange cannot overwrite values another member has yet to read (that
+// member must arrive at the next barrier first).  The release on arrival and the acquire after
+// the wait make every write of the members before the barrier (labels, segments, stamps) visible
+// after it.  A bounded wait raises ERR_BARRIER instead of hanging.
+__device__ void team_exchange(BlockShared& sh, u64 a, u64 b, u64 c, u64 d) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    TeamSync* ts = sh.ts;
+    u64* r = &ts->red[sh.par][sh.tm][0];
+    __hip_atomic_store(r + 0, a, __ATOMIC_RELAXED, AG);
+    __hip_atomic_store(r + 1, b, __ATOMIC_RELAXED, AG);
+    __hip_atomic_store(r + 2, c, __ATOMIC_RELAXED, AG);
+    __hip_atomic_store(r + 3, d, __ATOMIC_RELAXED, AG);
+    const unsigned target = (sh.epoch + 1) * (unsigned)sh.tK;
+    __hip_atomic_fetch_add(&ts->arrive, 1u, __ATOMIC_RELEASE, AG);
+    unsigned spins = 0;
+    while (__hip_atomic_load(&ts->arrive, __ATOMIC_RELAXED, AG) < target) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > (1u << 26)) {
+        sh.err |= ERR_BARRIER;
+        break;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < 4 * sh.tK)
+    sh.tv[threadIdx.x >> 2][threadIdx.x & 3] =
+        __hip_atomic_load(&sh.ts->red[sh.par][0][0] + threadIdx.x, __ATOMIC_RELAXED, AG);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    sh.epoch += 1;
+    sh.par ^= 1;
+  }
+  __syncthreads();
+}
+
+// After an exchange of (segment length, -, error bits, -): the exclusive prefix of the segment
+// lengths in sh.tpre, their total (returned) and the OR of the error bits (all threads call;
+// uniform results).
+__device__ __forceinline__ unsigned team_counts(BlockShared& sh, unsigned* err) {
+  unsigned tot = 0, e = 0;
+  for (int k = 0; k < sh.tK; ++k) {
+    if (threadIdx.x == 0) sh.tpre[k] = tot;
+    tot += (unsigned)sh.tv[k][0];
+    e |= (unsigned)sh.tv[k][2];
+  }
+  if (threadIdx.x == 0) sh.tpre[sh.tK] = tot;
+  *err = e;
+  __syncthreads();
+  return tot;
+}
+
+// The first non-empty wake bucket of the whole graph at or after r, from the bitmap sh.nz (D + n +
+// 1 past the end, as next_nonempty; all threads call).
+__device__ __forceinline__ int team_next_nonempty(BlockShared& sh, int r, int D) {
+  __syncthreads();
+  if (threadIdx.x == 0) sh.nxt = 0x7fffffff;
+  __syncthreads();
+  const int w = (int)threadIdx.x;
+  if (w < BLOCK_WCAP / 64 && r < BLOCK_WCAP) {
+    const int b0 = w * 64;
+    u64 bits = sh.nz[w];
+    if (b0 + 63 < r) bits = 0;
+    else if (b0 < r) bits &= ~0ull << (r - b0);
+    if (bits) atomicMin(&sh.nxt, b0 + __builtin_ctzll(bits));
+  }
+  __syncthreads();
+  const int q = sh.nxt;
+  __syncthreads();
+  return q <= D ? q : 0x3fffffff;
+}
+
+// Team preparation: every member scans its slice (checks, labels INF, Delta and the vertices
+// with arcs, combined by an exchange) and sorts its slice's wake buckets; the members' non-empty
+// buckets are combined into sh.nz by a second barrier.
+__device__ __attribute__((noinline)) void team_prepare(const BlockJob& j, BlockShared& sh) {
+  const int tid = threadIdx.x;
+  if (tid == 0) sh.err = 0;
+  __syncthreads();
+  u64 dmax, active;
+  prepare_scan(j, sh, sh.tlo, sh.thi, sh.tm == 0, &dmax, &active);
+  team_exchange(sh, active, dmax, sh.err, 0);
+  u64 n_active = 0, delta = 0;
+  unsigned e = 0;
+  for (int k = 0; k < sh.tK; ++k) {
+    n_active += sh.tv[k][0];
+    delta = sh.tv[k][1] > delta ? sh.tv[k][1] : delta;
+    e |= (unsigned)sh.tv[k][2];
+  }
+  if (!e) e = range_err(j.n, delta);
+  __syncthreads();
+  if (tid == 0) {
+    sh.err |= e;
+    sh.delta = delta;
+    sh.n_active = n_active;
+  }
+  __syncthreads();
+  if (sh.err) return;
+  wake_sort(j, sh, sh.tlo, sh.thi, delta);
+  if (tid < BLOCK_WCAP / 64) {
+    u64 bits = 0;
+    for (int b = 0; b < 64; ++b) {
+      const int q = tid * 64 + b;
+      bits |= (u64)(sh.woff[q + 1] > sh.woff[q]) << b;
+    }
+    __hip_atomic_store(&sh.ts->nz[sh.tm][tid], bits, __ATOMIC_RELAXED, AG);
+  }
+  team_exchange(sh, 0, 0, 0, 0);
+  if (tid < BLOCK_WCAP / 64) {
+    u64 bits = 0;
+    for (int k = 0; k < sh.tK; ++k) bits |= __hip_atomic_load(&sh.ts->nz[k][tid], __ATOMIC_RELAXED, AG);
+    sh.nz[tid] = bits;
+  }
+  __syncthreads();
+}
+
+// The rounds of a team: the same rounds and tail as block_rounds, with labels at device scope,
+// wakes from the member's slice, expansion of the member's K-th of the frontier, appends to the
+// member's segment, and one exchange per round (or seed, or sweep) for the segment lengths.
+__device__ __attribute__((noinline)) void team_rounds(const BlockJob& j, BlockShared& sh) {
+  const int n = j.n;
+  const int* __restrict__ rp = j.row_ptr;
+  const int* __restrict__ col = j.col;
+  const long long* __restrict__ shift = j.shift;
+  u64* P = j.P;
+  const int tid = threadIdx.x;
+  const int K = sh.tK, m = sh.tm, lo = sh.tlo, hi = sh.thi;
+  const u64 delta = sh.delta, n_active = sh.n_active;
+  const int B = n > 1 ? 32 - __builtin_clz((unsigned)(n - 1)) : 1;
+  const int D = (int)(delta >> FIX);
+  const u64 unit = (u64)1 << (FIX + B);
+  int* cur = j.tq;
+  int* nxt = j.tq + (long long)K * n;
+  unsigned nf = 0, e = 0;
+  u64 settled = 0, examined = 0;
+  long long rounds = 0, sweeps = 0;
+  int r = team_next_nonempty(sh, 0, D);
+  bool tail = false;
+  while (settled < n_active && r <= D + n && rounds <= (long long)D + n + 2) {
+    __syncthreads();
+    if (tid == 0) sh.cnt = 0;
+    __syncthreads();
+    int* mine = nxt + (long long)m * n;
+    if (r <= D) {
+      const int w0 = sh.woff[r], w1 = sh.woff[r + 1];
+      for (int i = w0 + tid; i < w1; i += BT) {
+        const int v = j.wake[lo + i];
+        const u64 self = ((delta - (u64)shift[v]) << B) | (u64)v;
+        if (lab_load<AG>(&P[v]) > self) {
+          const u64 old = lab_min<AG>(&P[v], self);
+          if (old == INF) append(sh, mine, v);
+        }
+      }
+    }
+    const unsigned e0 = (unsigned)((u64)nf * m / K), e1 = (unsigned)((u64)nf * (m + 1) / K);
+    examined += expand_frontier<AG, false, true>(j, sh, cur, e0, e1, mine, unit, 0);
+    __syncthreads();
+    team_exchange(sh, sh.cnt, 0, sh.err, 0);
+    nf = team_counts(sh, &e);
+    if (e) break;
+    settled += nf;
+    ++rounds;
+    int* t = cur;
+    cur = nxt;
+    nxt = t;
+    if (nf) ++r;
+    else r = team_next_nonempty(sh, r + 1, D);
+    const u64 left = n_active - settled;
+    if (j.tail_den > 0 && left > 0 && left * (u64)j.tail_den <= n_active && D - r > TAIL_MIN_LEFT) {
+      tail = true;
+      break;
+    }
+  }
+  if (tail && !e) {
+    // seed over the member's slice (see block_rounds), then sweeps over the team's segments
+    __syncthreads();
+    if (tid == 0) sh.cnt = 0;
+    __syncthreads();
+    int* mine = nxt + (long long)m * n;
+    const u64 prev_round = (u64)(r - 1);
+    for (int v = lo + tid; v < hi; v += BT) {
+      const int a0 = rp[v], a1 = rp[v + 1];
+      if (a1 == a0 || lab_load<AG>(&P[v]) != INF) continue;
+      u64 best = ((delta - (u64)shift[v]) << B) | (u64)v;
+      for (int a = a0; a < a1; ++a) {
+        const int u = col[a];
+        if ((unsigned)u >= (unsigned)n) {
+          atomicOr(&sh.err, ERR_BAD_COL);
+          break;
+        }
+        const u64 pu = lab_load<AG>(&P[u]);
+        if (pu != INF && (pu >> (FIX + B)) == prev_round && pu + unit < best) best = pu + unit;
+      }
+      examined += (u64)(a1 - a0);
+      lab_store<AG>(&P[v], best);
+      j.wake[v] = -1;  // the stamp of the first sweep
+      append(sh, mine, v);
+    }
+    __syncthreads();
+    team_exchange(sh, sh.cnt, 0, sh.err, 0);
+    nf = team_counts(sh, &e);
+    int* t = cur;
+    cur = nxt;
+    nxt = t;
+    for (int k = 1; nf && !e && sweeps <= n; ++k) {
+      __syncthreads();
+      if (tid == 0) sh.cnt = 0;
+      __syncthreads();
+      mine = nxt + (long long)m * n;
+      const unsigned e0 = (unsigned)((u64)nf * m / K), e1 = (unsigned)((u64)nf * (m + 1) / K);
+      examined += expand_frontier<AG, true, true>(j, sh, cur, e0, e1, mine, unit, -(k + 1));
+      __syncthreads();
+      team_exchange(sh, sh.cnt, 0, sh.err, 0);
+      nf = team_counts(sh, &e);
+      ++sweeps;
+      t = cur;
+      cur = nxt;
+      nxt = t;
+    }
+    settled = n_active;
+  }
+  __syncthreads();
+  examined = block_sum64(examined, sh);
+  if (tid == 0) {
+    sh.err |= e;
+    sh.settled = settled;
+    sh.examined = examined;
+    sh.rounds = rounds;
+    sh.sweeps = sweeps;
+  }
+  __syncthreads();
+}
+
+// Centres and cut of the member's slice, summed over the team by a last exchange; member 0
+// writes the graph's result.
+__device__ __attribute__((noinline)) void team_output(const BlockJob& j, BlockShared& sh, BlockOut* out) {
+  const int n = j.n;
+  const int* __restrict__ rp = j.row_ptr;
+  const int* __restrict__ col = j.col;
+  u64* P = j.P;
+  const int tid = threadIdx.x;
+  const int B = n > 1 ? 32 - __builtin_clz((unsigned)(n - 1)) : 1;
+  const u64 mask = ((u64)1 << B) - 1;
+  const unsigned e0 = sh.err | (sh.settled < sh.n_active ? ERR_WATCHDOG : 0u);
+  u64 cut2 = 0, pieces = 0;
+  if (!e0) {
+    for (int v = sh.tlo + tid; v < sh.thi; v += BT) {
+      const u64 p = lab_load<AG>(&P[v]);
+      const int c = p == INF ? v : (int)(p & mask);
+      j.centre[v] = c;
+      pieces += c == v;
+      for (int a = rp[v]; a < rp[v + 1]; ++a) {
+        const int w = col[a];
+        if ((unsigned)w >= (unsigned)n) {
+          atomicOr(&sh.err, ERR_BAD_COL);
+          break;
+        }
+        const u64 pw = lab_load<AG>(&P[w]);
+        const int cw = pw == INF ? w : (int)(pw & mask);
+        cut2 += cw != c;
+      }
+    }
+  }
+  cut2 = block_sum64(cut2, sh);
+  pieces = block_sum64(pieces, sh);
+  __syncthreads();
+  team_exchange(sh, cut2, pieces, e0 | sh.err, sh.examined);
+  if (tid == 0 && sh.tm == 0) {
+    u64 c = 0, p = 0, x = 0;
+    unsigned e = 0;
+    for (int k = 0; k < sh.tK; ++k) {
+      c += sh.tv[k][0];
+      p += sh.tv[k][1];
+      e |= (unsigned)sh.tv[k][2];
+      x += sh.tv[k][3];
+    }
+    out->err = e | sh.err;
+    out->cut_arcs = c;
+    out->pieces = p;
+    out->delta = sh.delta;
+    out->n_active = sh.n_active;
+    out->rounds = sh.rounds;
+    out->sweeps = sh.sweeps;
+    out->examined = x;
+  }
+}
+
+// Member m of the graph's team: the slice of 64-aligned vertices it owns, then the three phases.
+__device__ void team_graph(const BlockJob& j, BlockShared& sh, BlockOut* out, int m) {
+  const int n = j.n, K = j.team;
+  const int chunk = (int)((((long long)n + K - 1) / K + 63) & ~63ll);
+  if (threadIdx.x == 0) {
+    sh.ts = j.sync;
+    sh.tK = K;
+    sh.tm = m;
+    sh.tlo = (int)min((long long)n, (long long)m * chunk);
+    sh.thi = (int)min((long long)n, (long long)sh.tlo + chunk);
+    sh.epoch = 0;
+    sh.par = 0;
+  }
+  __syncthreads();
+  team_prepare(j, sh);
+  if (sh.err) {
+    if (threadIdx.x == 0 && m == 0) {
+      out->err = sh.err;
+      out->delta = sh.delta;
+    }
+    return;
+  }
+  team_rounds(j, sh);
+  team_output(j, sh, out);
+}
+
 }  // namespace
 
 // (BT, 8): eight waves per SIMD, two workgroups per CU (at most 64 VGPRs).
-// One workgroup per graph at a time: the workgroup takes the next graph of `order` from the
-// shared counter until none is left.
-__global__ __launch_bounds__(BT, 8) void k_block_decompose(const BlockJob* __restrict__ jobs, const int* __restrict__ order,
-                                                           int njobs, unsigned* next_job, BlockOut* outs) {
+// Each workgroup takes the next job of `order` (a graph, or one member of a graph's team) from
+// the shared counter until none is left.
+// A team's members are consecutive jobs: a member that starts early waits at the team's first
+// barrier for workgroups that finish their current job, which every resident workgroup does, so
+// the team size must not exceed the resident workgroups (the host keeps it within the grid).
+__global__ __launch_bounds__(BT, 8) void k_block_decompose(const BlockJob* __restrict__ jobs,
+                                                           const TeamJob* __restrict__ order, int njobs,
+                                                           unsigned* next_job, BlockOut* outs) {
   __shared__ BlockShared sh;
   for (;;) {
     if (threadIdx.x == 0) sh.job = (int)atomicAdd(next_job, 1u);
@@ -464,10 +847,12 @@ __global__ __launch_bounds__(BT, 8) void k_block_decompose(const BlockJob* __res
     const int k = sh.job;
     __syncthreads();
     if (k >= njobs) return;
-    const int g = order ? order[k] : k;
+    const int g = order ? order[k].g : k;
+    const int m = order ? order[k].m : 0;
     const u64 t0 = wall_clock64();
-    block_graph(jobs[g], sh, &outs[g]);
-    if (threadIdx.x == 0) {
+    if (jobs[g].team > 1) team_graph(jobs[g], sh, &outs[g], m);
+    else block_graph(jobs[g], sh, &outs[g]);
+    if (threadIdx.x == 0 && m == 0) {
       outs[g].t_begin = t0;
       outs[g].t_end = wall_clock64();
     }
@@ -475,10 +860,11 @@ __global__ __launch_bounds__(BT, 8) void k_block_decompose(const BlockJob* __res
   }
 }
 
-// Per-graph job descriptors of a batch in one offset CSR (graph g's rows at row_ptr[vo[g] + g]).
+// Per-graph job descriptors of a batch in one offset CSR (graph g's rows at row_ptr[vo[g] + g]);
+// team[2 g] = graph g's team size, team[2 g + 1] its TeamSync, tq_off[g] its segments in tq.
 __global__ void k_block_jobs(int G, long long N, const long long* vo, const long long* ao, const int* row_ptr,
                              const int* col, const long long* shift, int* centre, u64* P, int* wq, int tail_den,
-                             BlockJob* jobs) {
+                             const int* team, TeamSync* sync, int* tq, const long long* tq_off, BlockJob* jobs) {
   for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < G; g += gridDim.x * blockDim.x) {
     BlockJob j;
     const long long v0 = vo[g];
@@ -493,6 +879,9 @@ __global__ void k_block_jobs(int G, long long N, const long long* vo, const long
     j.q0 = wq + N + v0;
     j.q1 = wq + 2 * N + v0;
     j.tail_den = tail_den;
+    j.team = team ? team[2 * g] : 1;
+    j.sync = j.team > 1 ? sync + team[2 * g + 1] : nullptr;
+    j.tq = j.team > 1 ? tq + tq_off[g] : nullptr;
     jobs[g] = j;
   }
 }

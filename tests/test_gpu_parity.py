@@ -382,13 +382,74 @@ def test_batch_union_equals_alone_and_oracle(ldd):
     vo, ao, rp_all, ci_all, s_all = pack(graphs)
     d_rp, d_ci, d_s = to_dev(rp_all, ci_all, s_all)
     want = [oracle.decompose(rp, ci, s) for rp, ci, s in graphs]
-    for mode in (dict(), dict(batch_mode=1), dict(batch_mode=3, blocks=5), dict(batch_mode=2),
+    for mode in (dict(), dict(batch_mode=1), dict(batch_mode=3, blocks=5), dict(batch_mode=3, team_arcs=-1),
+                 dict(batch_mode=3, team_arcs=64), dict(batch_mode=2),
                  dict(batch_mode=2, direction=2), dict(batch_mode=2, tail_vertices=-1), dict(batch_mode=2, engine=1)):
         centre, cuts = ldd.decompose_batch(vo, ao, d_rp, d_ci, d_s, **mode)
         centre = centre.cpu().numpy()
         for g, (wc, _, wcut) in enumerate(want):
             assert np.array_equal(centre[vo[g]:vo[g + 1]], wc), (mode, g)
             assert cuts[g] == wcut, (mode, g)
+
+
+def test_batch_teams_equal_oracle(ldd):
+    """Graphs split over teams of workgroups (forced by a small team_arcs): many rounds and the
+    tail (grid, geometric), few rounds (Erdos-Renyi, RMAT), tie-heavy shifts, teams beside lone
+    graphs, teams on a grid of 24 workgroups, and a batch of small graphs where a member's vertex
+    slice is empty (200 vertices over 3 members of 128); every graph equals the oracle, with the
+    tail on, off, and from the first chance."""
+    rng = np.random.default_rng(45)
+    big = []
+    rp, ci = inputs.grid2d(90, 90)
+    big.append((rp, ci, inputs.make_shifts(8100, 0.05, 11)))
+    rp, ci = inputs.rgg(20_000, 8.0, 3)
+    big.append((rp, ci, inputs.make_shifts(20_000, 0.02, 12)))
+    rp, ci = inputs.er(15_000, 10.0, 4)
+    big.append((rp, ci, inputs.make_shifts(15_000, 0.1, 13)))
+    rp, ci = inputs.rmat(12)
+    big.append((rp, ci, inputs.make_shifts(rp.size - 1, 0.2, 14)))
+    rp, ci = inputs.grid2d(40, 40)
+    big.append((rp, ci, (rng.integers(0, 3, 1600) * S).astype(np.int64)))
+    for k in range(6):
+        rp, ci = inputs.er(300 + 50 * k, 3.0, 20 + k)
+        big.append((rp, ci, inputs.make_shifts(rp.size - 1, 0.1, 30 + k)))
+    small = []
+    rp, ci = inputs.er(200, 6.0, 5)
+    small.append((rp, ci, inputs.make_shifts(200, 0.1, 15)))
+    rp, ci = inputs.grid2d(12, 30)
+    small.append((rp, ci, inputs.make_shifts(360, 0.1, 16)))
+    rp, ci = inputs.from_edges(130, [], [])
+    small.append((rp, ci, inputs.make_shifts(130, 0.1, 17)))
+    for graphs, modes in ((big, (dict(team_arcs=32), dict(team_arcs=32, tail_vertices=-1),
+                                 dict(team_arcs=32, tail_vertices=1), dict(team_arcs=8000),
+                                 dict(team_arcs=32, blocks=24))),
+                          (small, (dict(team_arcs=32), dict(team_arcs=32, tail_vertices=1)))):
+        vo, ao, rp_all, ci_all, s_all = pack(graphs)
+        d_rp, d_ci, d_s = to_dev(rp_all, ci_all, s_all)
+        want = [oracle.decompose(rp, ci, s) for rp, ci, s in graphs]
+        for mode in modes:
+            log(f"teams {len(graphs)} graphs {mode}")
+            centre, cuts = ldd.decompose_batch(vo, ao, d_rp, d_ci, d_s, batch_mode=3, **mode)
+            centre = centre.cpu().numpy()
+            for g, (wc, _, wcut) in enumerate(want):
+                assert np.array_equal(centre[vo[g]:vo[g + 1]], wc), (mode, g)
+                assert cuts[g] == wcut, (mode, g)
+
+
+def test_batch_team_rejects_bad_column(ldd):
+    rp, ci = inputs.rgg(6000, 8.0, 9)
+    ci2 = ci.copy()
+    ci2[ci.size // 2] = 6000  # out of range, in the middle of the graph (another member's slice)
+    graphs = [(rp, ci, inputs.make_shifts(6000, 0.05, 1)), (rp, ci2, inputs.make_shifts(6000, 0.05, 2))]
+    vo, ao, rp_all, ci_all, s_all = pack(graphs)
+    d_rp, d_ci, d_s = to_dev(rp_all, ci_all, s_all)
+    with pytest.raises(ldd.LddError) as e:
+        ldd.decompose_batch(vo, ao, d_rp, d_ci, d_s, batch_mode=3, team_arcs=256)
+    assert e.value.status == ldd.ERR_INVALID_ARG
+    vo, ao, rp_all, ci_all, s_all = pack(graphs[:1])
+    centre, cuts = ldd.decompose_batch(vo, ao, *to_dev(rp_all, ci_all, s_all), batch_mode=3, team_arcs=256)
+    wc, _, wcut = oracle.decompose(rp, ci, graphs[0][2])
+    assert np.array_equal(centre.cpu().numpy()[:6000], wc) and cuts[0] == wcut
 
 
 def test_batch_rejects_bad_local_ids(ldd):
