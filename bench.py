@@ -9,7 +9,8 @@ shifts, inputs resident in HBM.  Prints one JSON line.
   roofline     the round kernel: algorithmic bytes per launch over its average launch
                duration (HIP events on the launch stream), against 8 TB/s HBM3E; traffic from
                the committed rocprofv3 counter runs when they match the current kernel sources
-  batched      512 uneven graphs in one call (one workgroup per graph) vs one call each
+  batched      512 uneven graphs in one call (workgroup engine: one workgroup, or a team of
+               workgroups for the largest graphs, per graph) vs one call each
   served       a Poisson stream of RMAT 12-22 requests through the serving engine vs the same
                stream one decomposition at a time (FIFO), latency p50 / p99 and capacity
   grid2d       grid 64x64: p50 / p99 latency over 1000 calls

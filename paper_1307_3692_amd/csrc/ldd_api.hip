@@ -662,9 +662,10 @@ __global__ void k_block_job_single(int n, long long nnz, const int* row_ptr, con
   j.shift = shift;
   j.centre = centre;
   j.P = P;
+  j.wk = (u64*)wq;
   j.wake = wq;
-  j.q0 = wq + n;
-  j.q1 = wq + 2 * (long long)n;
+  j.q0 = wq + 2 * (long long)n;
+  j.q1 = wq + 3 * (long long)n;
   j.tail_den = tail_den;
   j.team = 1;
   j.sync = nullptr;
@@ -682,7 +683,7 @@ static ldd_status decompose_block(Workspace& w, const ldd_csr* g, const int64_t*
   const size_t nv = (size_t)n;
   ldd_status s = ws_setup(w);
   if (s != LDD_OK) return s;
-  if ((s = grow(w.P, nv * 8)) || (s = grow(w.bk_wq, nv * 12)) || (s = grow(w.bk_jobs, sizeof(BlockJob))) ||
+  if ((s = grow(w.P, nv * 8)) || (s = grow(w.bk_wq, nv * 16)) || (s = grow(w.bk_jobs, sizeof(BlockJob))) ||
       (s = grow(w.bk_out, sizeof(BlockOut))) || (s = grow(w.bk_cnt, 8)))
     return s;
   HIP_TRY(hipStreamWaitEvent(st, w.ev[2], 0));  // after any step a previous call left queued
@@ -906,7 +907,7 @@ ldd_status ldd_batch_workgroup(int32_t G, const int64_t* vtx_off, const int64_t*
       for (int m = 0; m < team[g]; ++m) jobs.push_back(TeamJob{g, m});
     }
     const int njobs = (int)jobs.size();
-    if ((s = grow(w.P, (size_t)N * 8)) || (s = grow(w.bk_wq, (size_t)N * 12)) ||
+    if ((s = grow(w.P, (size_t)N * 8)) || (s = grow(w.bk_wq, (size_t)N * 16)) ||
         (s = grow(w.bk_jobs, (size_t)G * sizeof(BlockJob))) || (s = grow(w.bk_order, (size_t)njobs * sizeof(TeamJob))) ||
         (s = grow(w.bk_out, (size_t)G * sizeof(BlockOut))) || (s = grow(w.bk_cnt, 8)) ||
         (s = grow(w.b_off, (size_t)(G + 1) * 16)) || (s = grow(w.bk_team, (size_t)G * 16)) ||

@@ -33,7 +33,8 @@ struct BlockJob {
   const long long* shift;
   int* centre;           // OUT [n]
   u64* P;                // workspace [n]: labels
-  int* wake;             // workspace [n]: vertices with arcs by wake round
+  u64* wk;               // workspace [n]: own labels of the vertices with arcs, by wake round
+  int* wake;             // the first 4n bytes of wk: the tail's sweep stamps (once no wake is left)
   int* q0;               // workspace [n]: frontier queues
   int* q1;
   int tail_den;          // label-correcting tail once unreached * tail_den <= vertices with arcs (0: never)

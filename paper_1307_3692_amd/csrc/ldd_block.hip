@@ -47,7 +47,8 @@ struct BlockShared {
   unsigned red32[BNW];
   int job;
   int nxt;                   // next non-empty wake bucket (block minimum)
-  unsigned cnt;              // appends to the next frontier in this round
+  unsigned cnt;              // appends to the next frontier in this round (team, tail)
+  unsigned cnt3[3];          // the same, alone: round k counts in cnt3[k % 3], so one barrier per round
   unsigned err;
   u64 delta, n_active;       // preparation results
   u64 settled, examined;     // round results
@@ -136,18 +137,19 @@ __device__ __forceinline__ void lab_store(u64* p, u64 v) {
 }
 __device__ __forceinline__ u64 wg_load(const u64* p) { return lab_load<WG>(p); }
 
-__device__ __forceinline__ void append(BlockShared& sh, int* next, int v) {
-  const unsigned idx = atomicAdd(&sh.cnt, 1u);
+__device__ __forceinline__ void append(unsigned* cnt, int* next, int v) {
+  const unsigned idx = atomicAdd(cnt, 1u);
   next[idx] = v;
 }
 
 // Wake buckets of the vertices with arcs in [lo, hi): counting sort by w(v) = (Delta - shift) >> 20
-// in LDS; the sorted ids go to wake[lo ...] and sh.woff[q] is bucket q's offset from lo (all
-// threads call).
+// in LDS; the vertices' own labels ((Delta - shift[v]) << B) | v go to wk[lo ...] in bucket order
+// (a wake then needs no shift load) and sh.woff[q] is bucket q's offset from lo (all threads call).
 __device__ __forceinline__ void wake_sort(const BlockJob& j, BlockShared& sh, int lo, int hi, u64 delta) {
   const int* __restrict__ rp = j.row_ptr;
   const long long* __restrict__ shift = j.shift;
   const int tid = threadIdx.x;
+  const int B = j.n > 1 ? 32 - __builtin_clz((unsigned)(j.n - 1)) : 1;
   for (int q = tid; q <= BLOCK_WCAP; q += BT) sh.woff[q] = 0;
   __syncthreads();
   for (int v = lo + tid; v < hi; v += BT)
@@ -177,7 +179,7 @@ __device__ __forceinline__ void wake_sort(const BlockJob& j, BlockShared& sh, in
   for (int v = lo + tid; v < hi; v += BT) {
     if (rp[v + 1] > rp[v]) {
       const int q = (int)((delta - (u64)shift[v]) >> FIX);
-      j.wake[lo + atomicAdd(&sh.woff[q], 1)] = v;
+      j.wk[lo + atomicAdd(&sh.woff[q], 1)] = ((delta - (u64)shift[v]) << B) | (u64)v;
     }
   }
   __syncthreads();
@@ -259,7 +261,7 @@ __device__ __attribute__((noinline)) void block_prepare(const BlockJob& j, Block
 // time measured fastest (more in flight cost registers and did not pay on batches or small graphs).
 template <int SC, bool SWEEP>
 __device__ __forceinline__ void relax_chunk(const BlockJob& j, BlockShared& sh, int* next, unsigned ne,
-                                            unsigned total, int tag) {
+                                            unsigned total, int tag, unsigned* cnt) {
   constexpr int U = 1;
   const int n = j.n;
   const long long nnz = j.nnz;
@@ -292,9 +294,9 @@ __device__ __forceinline__ void relax_chunk(const BlockJob& j, BlockShared& sh, 
         const u64 old = lab_min<SC>(&P[w[k]], off[k]);
         if (SWEEP) {
           if (old > off[k] && __hip_atomic_exchange(&j.wake[w[k]], tag, __ATOMIC_RELAXED, SC) != tag)
-            append(sh, next, w[k]);
+            append(cnt, next, w[k]);
         } else if (old == INF) {
-          append(sh, next, w[k]);
+          append(cnt, next, w[k]);
         }
       }
     }
@@ -306,7 +308,7 @@ __device__ __forceinline__ void relax_chunk(const BlockJob& j, BlockShared& sh, 
 // of the members' segments, member s's at cur + s n with length tpre[s + 1] - tpre[s].
 template <int SC, bool SWEEP, bool TEAM>
 __device__ __forceinline__ u64 expand_frontier(const BlockJob& j, BlockShared& sh, const int* cur, unsigned e0,
-                                               unsigned e1, int* next, u64 unit, int tag) {
+                                               unsigned e1, int* next, u64 unit, int tag, unsigned* cnt) {
   const int* __restrict__ rp = j.row_ptr;
   u64 examined = 0;
   for (unsigned c0 = e0; c0 < e1; c0 += BT) {
@@ -331,7 +333,7 @@ __device__ __forceinline__ u64 expand_frontier(const BlockJob& j, BlockShared& s
     sh.pre[threadIdx.x] = ex;
     __syncthreads();
     examined += threadIdx.x == 0 ? total : 0;
-    relax_chunk<SC, SWEEP>(j, sh, next, e1 - c0 < (unsigned)BT ? e1 - c0 : (unsigned)BT, total, tag);
+    relax_chunk<SC, SWEEP>(j, sh, next, e1 - c0 < (unsigned)BT ? e1 - c0 : (unsigned)BT, total, tag, cnt);
     __syncthreads();
   }
   return examined;
@@ -362,27 +364,26 @@ __device__ __attribute__((noinline)) void block_rounds(const BlockJob& j, BlockS
   unsigned nf = 0;
   u64 settled = 0, examined = 0;
   long long rounds = 0, sweeps = 0;
+  const u64 mask = ((u64)1 << B) - 1;
+  if (tid < 3) sh.cnt3[tid] = 0;
+  int ci = 0;  // this round's append counter: cnt3[ci]; cnt3[(ci + 2) % 3] is cleared for two rounds on
   int r = next_nonempty(sh, 0, D);
   bool tail = false;
   while (settled < n_active && r <= D + n && rounds <= (long long)D + n + 2) {  // r past the end: stop
-    __syncthreads();  // every thread has read the previous round's count and error bits
-    if (tid == 0) sh.cnt = 0;
-    __syncthreads();
-    // wake bucket r
-    if (r <= D) {
-      const int w0 = sh.woff[r], w1 = sh.woff[r + 1];
-      for (int i = w0 + tid; i < w1; i += BT) {
-        const int v = j.wake[i];
-        const u64 self = ((delta - (u64)shift[v]) << B) | (u64)v;
-        if (wg_load(&P[v]) > self) {
-          const u64 old = lab_min<WG>(&P[v], self);
-          if (old == INF) append(sh, next, v);
-        }
-      }
+    unsigned* cnt = &sh.cnt3[ci];
+    const int w0 = r <= D ? sh.woff[r] : 0, w1 = r <= D ? sh.woff[r + 1] : 0;
+    // wake bucket r: each vertex offers its own label (a load first: a vertex reached earlier with
+    // a smaller label needs no atomic)
+    for (int i = w0 + tid; i < w1; i += BT) {
+      const u64 self = j.wk[i];
+      const int v = (int)(self & mask);
+      if (wg_load(&P[v]) > self && lab_min<WG>(&P[v], self) == INF) append(cnt, next, v);
     }
-    examined += expand_frontier<WG, false, false>(j, sh, cur, 0, nf, next, unit, 0);
-    __syncthreads();
-    nf = sh.cnt;
+    examined += expand_frontier<WG, false, false>(j, sh, cur, 0, nf, next, unit, 0, cnt);
+    __syncthreads();  // this round's appends are done; every thread has read the count of round k - 1
+    nf = *cnt;
+    if (tid == 0) sh.cnt3[ci == 0 ? 2 : ci - 1] = 0;  // round k - 1's counter, next used by round k + 2
+    ci = ci == 2 ? 0 : ci + 1;
     if (sh.err) break;
     settled += nf;
     ++rounds;
@@ -400,9 +401,7 @@ __device__ __attribute__((noinline)) void block_rounds(const BlockJob& j, BlockS
   if (tail && !sh.err) {
     // seed: F_{r-1} is cur (nf entries, final labels); every unreached vertex with arcs takes the
     // best of its own label and its neighbours' in F_{r-1}, and is queued for the first sweep
-    __syncthreads();
-    if (tid == 0) sh.cnt = 0;
-    __syncthreads();
+    unsigned* cnt = &sh.cnt3[ci];
     const u64 prev_round = (u64)(r - 1);
     for (int v = tid; v < n; v += BT) {
       const int a0 = rp[v], a1 = rp[v + 1];
@@ -420,21 +419,23 @@ __device__ __attribute__((noinline)) void block_rounds(const BlockJob& j, BlockS
       examined += (u64)(a1 - a0);
       lab_store<WG>(&P[v], best);
       j.wake[v] = -1;  // the stamp of the first sweep
-      append(sh, next, v);
+      append(cnt, next, v);
     }
     __syncthreads();
-    nf = sh.cnt;
+    nf = *cnt;
+    if (tid == 0) sh.cnt3[ci == 0 ? 2 : ci - 1] = 0;
+    ci = ci == 2 ? 0 : ci + 1;
     int* t = cur;
     cur = next;
     next = t;
     // sweeps: sweep k relaxes the labels queued by the step before and queues those that drop
     for (int k = 1; nf && !sh.err && sweeps <= n; ++k) {
+      unsigned* cnt = &sh.cnt3[ci];
+      examined += expand_frontier<WG, true, false>(j, sh, cur, 0, nf, next, unit, -(k + 1), cnt);
       __syncthreads();
-      if (tid == 0) sh.cnt = 0;
-      __syncthreads();
-      examined += expand_frontier<WG, true, false>(j, sh, cur, 0, nf, next, unit, -(k + 1));
-      __syncthreads();
-      nf = sh.cnt;
+      nf = *cnt;
+      if (tid == 0) sh.cnt3[ci == 0 ? 2 : ci - 1] = 0;
+      ci = ci == 2 ? 0 : ci + 1;
       ++sweeps;
       t = cur;
       cur = next;
@@ -647,6 +648,7 @@ __device__ __attribute__((noinline)) void team_rounds(const BlockJob& j, BlockSh
   const int B = n > 1 ? 32 - __builtin_clz((unsigned)(n - 1)) : 1;
   const int D = (int)(delta >> FIX);
   const u64 unit = (u64)1 << (FIX + B);
+  const u64 mask = ((u64)1 << B) - 1;
   int* cur = j.tq;
   int* nxt = j.tq + (long long)K * n;
   unsigned nf = 0, e = 0;
@@ -662,16 +664,13 @@ __device__ __attribute__((noinline)) void team_rounds(const BlockJob& j, BlockSh
     if (r <= D) {
       const int w0 = sh.woff[r], w1 = sh.woff[r + 1];
       for (int i = w0 + tid; i < w1; i += BT) {
-        const int v = j.wake[lo + i];
-        const u64 self = ((delta - (u64)shift[v]) << B) | (u64)v;
-        if (lab_load<AG>(&P[v]) > self) {
-          const u64 old = lab_min<AG>(&P[v], self);
-          if (old == INF) append(sh, mine, v);
-        }
+        const u64 self = j.wk[lo + i];
+        const int v = (int)(self & mask);
+        if (lab_load<AG>(&P[v]) > self && lab_min<AG>(&P[v], self) == INF) append(&sh.cnt, mine, v);
       }
     }
     const unsigned e0 = (unsigned)((u64)nf * m / K), e1 = (unsigned)((u64)nf * (m + 1) / K);
-    examined += expand_frontier<AG, false, true>(j, sh, cur, e0, e1, mine, unit, 0);
+    examined += expand_frontier<AG, false, true>(j, sh, cur, e0, e1, mine, unit, 0, &sh.cnt);
     __syncthreads();
     team_exchange(sh, sh.cnt, 0, sh.err, 0);
     nf = team_counts(sh, &e);
@@ -712,7 +711,7 @@ __device__ __attribute__((noinline)) void team_rounds(const BlockJob& j, BlockSh
       examined += (u64)(a1 - a0);
       lab_store<AG>(&P[v], best);
       j.wake[v] = -1;  // the stamp of the first sweep
-      append(sh, mine, v);
+      append(&sh.cnt, mine, v);
     }
     __syncthreads();
     team_exchange(sh, sh.cnt, 0, sh.err, 0);
@@ -726,7 +725,7 @@ __device__ __attribute__((noinline)) void team_rounds(const BlockJob& j, BlockSh
       __syncthreads();
       mine = nxt + (long long)m * n;
       const unsigned e0 = (unsigned)((u64)nf * m / K), e1 = (unsigned)((u64)nf * (m + 1) / K);
-      examined += expand_frontier<AG, true, true>(j, sh, cur, e0, e1, mine, unit, -(k + 1));
+      examined += expand_frontier<AG, true, true>(j, sh, cur, e0, e1, mine, unit, -(k + 1), &sh.cnt);
       __syncthreads();
       team_exchange(sh, sh.cnt, 0, sh.err, 0);
       nf = team_counts(sh, &e);
@@ -875,9 +874,10 @@ __global__ void k_block_jobs(int G, long long N, const long long* vo, const long
     j.shift = shift + v0;
     j.centre = centre + v0;
     j.P = P + v0;
-    j.wake = wq + v0;
-    j.q0 = wq + N + v0;
-    j.q1 = wq + 2 * N + v0;
+    j.wk = (u64*)wq + v0;
+    j.wake = (int*)(j.wk);
+    j.q0 = wq + 2 * N + v0;
+    j.q1 = wq + 3 * N + v0;
     j.tail_den = tail_den;
     j.team = team ? team[2 * g] : 1;
     j.sync = j.team > 1 ? sync + team[2 * g + 1] : nullptr;
