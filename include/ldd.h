@@ -78,7 +78,8 @@ typedef struct {
   int32_t direction;      /* LDD_DIR_*                                                    */
   int32_t engine;         /* LDD_ENGINE_*                                                 */
   int32_t validate;       /* 1: check CSR monotonicity on the device before running       */
-  int32_t blocks;         /* workgroups of the round kernel (0 = 2 per CU; at most 1024) */
+  int32_t blocks;         /* workgroups of the round kernel (0 = 2 per CU; the workgroup batch engine:
+                             1 per CU; at most 1024)                                                          */
   int32_t td_to_bu;       /* switch to bottom-up when frontier arcs * td_to_bu > unsettled arcs (0 = default 14) */
   int32_t bu_to_td;       /* switch back when frontier vertices * bu_to_td < n (0 = default 24)                 */
   int32_t tail_vertices;  /* finish by label correction once unsettled vertices * this <= active vertices
@@ -155,10 +156,12 @@ ldd_status ldd_decompose_batch(int32_t num_graphs, const int64_t* vtx_off, const
                                int32_t* centre, int64_t* cut_edges, const ldd_options* opt, void* hip_stream);
 
 /*
- * Tune the round engine's mapping for a workload: grid size (blocks), the top-down / bottom-up
- * switching thresholds (td_to_bu, bu_to_td) and the tail threshold (tail_vertices), searched one
- * knob at a time by timing whole decompositions of the given inputs (median of three, HIP
- * events on hip_stream).  The inputs are those of ldd_decompose_batch (num_graphs = 1: one graph,
+ * Tune the engine and its mapping for a workload: the engine (one graph: engine = LAUNCH,
+ * PERSISTENT, or WORKGROUP when nnz <= 2^22; a batch: batch_mode = WORKGROUP or UNION), grid size
+ * (blocks), the top-down / bottom-up switching thresholds (td_to_bu, bu_to_td; not for the
+ * workgroup engine, which runs top-down only), the tail threshold (tail_vertices) and, for the
+ * workgroup batch engine, the arcs per team member (team_arcs), searched one knob at a time by
+ * timing whole decompositions of the given inputs (median of three, HIP events on hip_stream).  The inputs are those of ldd_decompose_batch (num_graphs = 1: one graph,
  * run through ldd_decompose); centre is scratch output of the right size.  Every candidate gives
  * the same result, so only time is traded.  The winner is cached per workload signature (device,
  * CU count, number of graphs, vertices, arcs) in the process and, if cache_path is not NULL, in

@@ -390,7 +390,7 @@ def decompose_batch(vtx_off, arc_off, row_ptr, col_idx, shift_fix, *, centre=Non
 
 def tune(row_ptr, col_idx, shift_fix, *, vtx_off=None, arc_off=None, centre=None, cache_path=None, stream=None,
          **opts):
-    """Tune the round engine's knobs (``ldd_tune``) for one graph (no offsets) or a packed batch.
+    """Tune the engine and its knobs (``ldd_tune``) for one graph (no offsets) or a packed batch.
 
     Returns ``(options dict for decompose / decompose_batch, report dict)``.
     """
@@ -417,7 +417,11 @@ def tune(row_ptr, col_idx, shift_fix, *, vtx_off=None, arc_off=None, centre=None
                           ctypes.byref(base), cache_path.encode() if cache_path else None, ctypes.byref(best),
                           ctypes.byref(rep), _stream_handle(stream)))
     tuned = dict(opts, blocks=best.blocks, td_to_bu=best.td_to_bu, bu_to_td=best.bu_to_td,
-                 tail_vertices=best.tail_vertices)
+                 tail_vertices=best.tail_vertices, team_arcs=best.team_arcs)
+    if G == 1:
+        tuned["engine"] = best.engine
+    else:
+        tuned["batch_mode"] = best.batch_mode
     return tuned, rep.as_dict()
 
 

@@ -1,6 +1,8 @@
-// Autotuning of the round engine's mapping: grid size, the top-down / bottom-up switching
-// thresholds and the tail threshold, searched one knob at a time (coordinate descent) by timing
-// whole decompositions of the caller's inputs with HIP events.  Every candidate computes the
+// Autotuning of the engine and its mapping: the engine (one graph: launch, persistent or
+// workgroup; a batch: workgroup engine or disjoint union), the grid size, the top-down /
+// bottom-up switching thresholds, the tail threshold and, for the workgroup batch engine, the
+// arcs per team member, searched one knob at a time (coordinate descent) by timing whole
+// decompositions of the caller's inputs with HIP events.  Every candidate computes the
 // same result (the labels are the unique lexicographic minimum whatever the schedule), so
 // tuning trades nothing but time.  Results are cached per workload signature, in the process and
 // optionally in a text file (one line per signature).
@@ -20,8 +22,14 @@
 namespace {
 
 struct Knobs {
-  int blocks, td_to_bu, bu_to_td, tail;
+  int mode;  // one graph: LDD_ENGINE_*; a batch: LDD_BATCH_*
+  int blocks, td_to_bu, bu_to_td, tail, team_arcs;
 };
+
+// the workgroup engine takes no direction thresholds (it runs top-down only)
+bool workgroup_mode(int G, const Knobs& k) {
+  return G == 1 ? k.mode == LDD_ENGINE_WORKGROUP : (k.mode == LDD_BATCH_AUTO || k.mode == LDD_BATCH_WORKGROUP);
+}
 
 std::mutex g_mu;
 std::map<std::string, std::pair<Knobs, float>> g_cache;
@@ -44,7 +52,8 @@ bool file_lookup(const char* path, const std::string& key, Knobs* k, float* ms) 
     char name[300];
     Knobs x{};
     float t = 0;
-    if (sscanf(line, "%299s %d %d %d %d %f", name, &x.blocks, &x.td_to_bu, &x.bu_to_td, &x.tail, &t) == 6 &&
+    if (sscanf(line, "%299s %d %d %d %d %d %d %f", name, &x.mode, &x.blocks, &x.td_to_bu, &x.bu_to_td, &x.tail,
+               &x.team_arcs, &t) == 8 &&
         key == name) {
       *k = x;  // the last line for a signature wins
       *ms = t;
@@ -59,13 +68,17 @@ void file_store(const char* path, const std::string& key, const Knobs& k, float 
   if (!path) return;
   FILE* f = fopen(path, "a");
   if (!f) return;
-  fprintf(f, "%s %d %d %d %d %.4f\n", key.c_str(), k.blocks, k.td_to_bu, k.bu_to_td, k.tail, ms);
+  fprintf(f, "%s %d %d %d %d %d %d %.4f\n", key.c_str(), k.mode, k.blocks, k.td_to_bu, k.bu_to_td, k.tail,
+          k.team_arcs, ms);
   fclose(f);
 }
 
-ldd_options to_options(const ldd_options* base, const Knobs& k) {
+ldd_options to_options(const ldd_options* base, int G, const Knobs& k) {
   ldd_options o{};
   if (base) o = *base;
+  if (G == 1) o.engine = k.mode;
+  else o.batch_mode = k.mode;
+  o.team_arcs = k.team_arcs;
   o.blocks = k.blocks;
   o.td_to_bu = k.td_to_bu;
   o.bu_to_td = k.bu_to_td;
@@ -108,7 +121,7 @@ extern "C" ldd_status ldd_tune(int32_t num_graphs, const int64_t* vtx_off, const
       hit = true;
     }
     if (hit) {
-      *best = to_options(base, k);
+      *best = to_options(base, num_graphs, k);
       rep.best_ms = ms;
       rep.from_cache = 1;
       if (report) *report = rep;
@@ -124,7 +137,7 @@ extern "C" ldd_status ldd_tune(int32_t num_graphs, const int64_t* vtx_off, const
   ldd_status failure = LDD_OK;
   // one timed decomposition (median of three) with the given knobs
   auto measure = [&](const Knobs& k) -> float {
-    const ldd_options o = to_options(base, k);
+    const ldd_options o = to_options(base, num_graphs, k);
     float t[3];
     for (int i = 0; i < 3; ++i) {
       ldd_status s;
@@ -148,8 +161,14 @@ extern "C" ldd_status ldd_tune(int32_t num_graphs, const int64_t* vtx_off, const
     std::sort(t, t + 3);
     return t[1];
   };
-  Knobs cur{base && base->blocks ? base->blocks : 2 * ncu, base && base->td_to_bu ? base->td_to_bu : 14,
-            base && base->bu_to_td ? base->bu_to_td : 24, base && base->tail_vertices ? base->tail_vertices : 32};
+  const int mode0 = num_graphs == 1 ? (base ? base->engine : 0) : (base ? base->batch_mode : 0);
+  const int blocks0 = num_graphs > 1 && (mode0 == LDD_BATCH_AUTO || mode0 == LDD_BATCH_WORKGROUP) ? ncu : 2 * ncu;
+  Knobs cur{mode0,
+            base && base->blocks ? base->blocks : blocks0,
+            base && base->td_to_bu ? base->td_to_bu : 14,
+            base && base->bu_to_td ? base->bu_to_td : 24,
+            base && base->tail_vertices ? base->tail_vertices : 32,
+            base ? base->team_arcs : 0};
   (void)measure(cur);  // warm-up (workspace growth, code loading)
   if (failure != LDD_OK) {
     (void)hipEventDestroy(e0);
@@ -158,18 +177,34 @@ extern "C" ldd_status ldd_tune(int32_t num_graphs, const int64_t* vtx_off, const
   }
   float cur_ms = measure(cur);
   rep.default_ms = cur_ms;
+  // engines: one graph tries the workgroup engine only when it is small enough that one
+  // workgroup could compete (at most 2^22 arcs); a batch tries both batch engines
+  std::vector<int> modes;
+  if (num_graphs == 1) {
+    modes = {LDD_ENGINE_LAUNCH, LDD_ENGINE_PERSISTENT};
+    if (nnz <= (1ll << 22)) modes.push_back(LDD_ENGINE_WORKGROUP);
+  } else {
+    modes = {LDD_BATCH_WORKGROUP, LDD_BATCH_UNION};
+  }
   const std::vector<int> blocks = {ncu, 2 * ncu, 3 * ncu, 4 * ncu};
   const std::vector<int> td_to_bu = {6, 10, 14, 20, 30};
   const std::vector<int> bu_to_td = {12, 24, 48};
   const std::vector<int> tail = {16, 32, 64, 128, 256, -1};
+  const std::vector<int> team = {-1, 1 << 16, 1 << 17, 1 << 18, 1 << 19, 0};
+  constexpr int KNOBS = 6;
   for (int round = 0; round < 2 && failure == LDD_OK; ++round) {
     bool moved = false;
-    for (int knob = 0; knob < 4 && failure == LDD_OK; ++knob) {
-      const std::vector<int>& cand = knob == 0 ? blocks : knob == 1 ? td_to_bu : knob == 2 ? bu_to_td : tail;
+    for (int knob = 0; knob < KNOBS && failure == LDD_OK; ++knob) {
+      const bool wg = workgroup_mode(num_graphs, cur);
+      if ((knob == 2 || knob == 3) && wg) continue;        // no direction switching to tune
+      if (knob == 5 && (!wg || num_graphs == 1)) continue;  // teams: the workgroup batch engine only
+      const std::vector<int>& cand = knob == 0 ? modes : knob == 1 ? blocks : knob == 2 ? td_to_bu
+                                   : knob == 3 ? bu_to_td : knob == 4 ? tail : team;
       for (int v : cand) {
         Knobs k = cur;
-        int* field = knob == 0 ? &k.blocks : knob == 1 ? &k.td_to_bu : knob == 2 ? &k.bu_to_td : &k.tail;
-        if (*field == v || (knob == 0 && v > 1024)) continue;
+        int* field = knob == 0 ? &k.mode : knob == 1 ? &k.blocks : knob == 2 ? &k.td_to_bu : knob == 3 ? &k.bu_to_td
+                   : knob == 4 ? &k.tail : &k.team_arcs;
+        if (*field == v || (knob == 1 && v > 1024)) continue;
         *field = v;
         const float t = measure(k);
         if (t < cur_ms * 0.98f) {  // a clear win only
@@ -189,7 +224,7 @@ extern "C" ldd_status ldd_tune(int32_t num_graphs, const int64_t* vtx_off, const
     g_cache[key] = {cur, cur_ms};
     file_store(cache_path, key, cur, cur_ms);
   }
-  *best = to_options(base, cur);
+  *best = to_options(base, num_graphs, cur);
   rep.best_ms = cur_ms;
   if (report) *report = rep;
   return LDD_OK;
