@@ -193,6 +193,27 @@ def fifo_latencies(arrivals, service):
     return done - arrivals
 
 
+def plain_run(ldd, tm, req, arrivals, bufs):
+    """The plain path under the same kind of load: one ldd_decompose per request in arrival order,
+    each started no earlier than its arrival (offsets in seconds); latency (ms) from the arrival
+    to the call's return (the call returns with its cut on the host)."""
+    import numpy as np
+    lat = np.zeros(len(req))
+    t0 = time.perf_counter()
+    for i, ti in enumerate(req):
+        due = t0 + arrivals[i]
+        while True:
+            now = time.perf_counter()
+            if now >= due:
+                break
+            if due - now > 2e-3:
+                time.sleep(due - now - 1e-3)
+        x = tm[ti]
+        ldd.decompose(x["rp"], x["ci"], x["s"], x["beta"], centre=bufs[ti])
+        lat[i] = time.perf_counter() - due
+    return lat * 1e3
+
+
 def serve_run(ldd, srv, tm, req, outs, arrivals=None):
     """Submit requests (all at once, or at the given arrival offsets in seconds), collect them
     on a second thread; returns per-request latency (ms) and the run's wall span (s)."""
@@ -237,7 +258,10 @@ def serve_run(ldd, srv, tm, req, outs, arrivals=None):
 def run_serving(n_requests: int = 2000, budget_gib: float = 16.0, small_budget_gib: float = 0.25):
     """Serving: a stream of RMAT 12-22 requests through ldd_server_* (continuous batching into
     one device-resident arena) against the plain path (one ldd_decompose per request, FIFO).
-    Capacity comes from a saturating closed loop; latency from Poisson arrivals at 80% of it."""
+    Capacity comes from a saturating closed loop; latency from Poisson arrivals at 80% of it.
+    The plain path's latency at its own 80% load is a real run of the same arrival pattern
+    (scaled to its capacity); the FIFO model over its measured service times is kept beside it,
+    and also gives the plain latency at the server's arrival rate, which plain cannot sustain."""
     import numpy as np
     import torch
 
@@ -300,6 +324,7 @@ def run_serving(n_requests: int = 2000, budget_gib: float = 16.0, small_budget_g
     plain_same = fifo_latencies(arr, service) * 1e3
     arr_own = arr * (lam / (0.8 * plain_cap))
     plain_own = fifo_latencies(arr_own, service) * 1e3
+    plain_own_run = plain_run(ldd, tm, req, arr_own, plain_out)
     out.update({
         "hbm_budget_gib": budget_gib, "arena_vertices": info["arena_vertices"], "arena_arcs": info["arena_arcs"],
         "capacity_req_per_s": round(cap, 1),
@@ -314,8 +339,10 @@ def run_serving(n_requests: int = 2000, budget_gib: float = 16.0, small_budget_g
         "plain_mean_service_ms": round(float(service.mean()) * 1e3, 4),
         "plain_at_same_lambda_p50_ms": round(float(np.percentile(plain_same, 50)), 3),
         "plain_at_same_lambda_p99_ms": round(float(np.percentile(plain_same, 99)), 3),
-        "plain_at_own_80pct_p50_ms": round(float(np.percentile(plain_own, 50)), 3),
-        "plain_at_own_80pct_p99_ms": round(float(np.percentile(plain_own, 99)), 3),
+        "plain_at_own_80pct_p50_ms": round(float(np.percentile(plain_own_run, 50)), 3),
+        "plain_at_own_80pct_p99_ms": round(float(np.percentile(plain_own_run, 99)), 3),
+        "plain_at_own_80pct_model_p50_ms": round(float(np.percentile(plain_own, 50)), 3),
+        "plain_at_own_80pct_model_p99_ms": round(float(np.percentile(plain_own, 99)), 3),
         "speedup_capacity_vs_plain": round(cap / plain_cap, 2),
         "identical_to_plain": bool(same_c and same_p),
         "bit_exact": bool(same_c and same_p and templates_vs_oracle),
