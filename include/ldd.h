@@ -70,9 +70,18 @@ typedef struct {
 /* Traversal direction policy of a round (the result never depends on it). */
 enum { LDD_DIR_AUTO = 0, LDD_DIR_TOP_DOWN = 1, LDD_DIR_BOTTOM_UP = 2 };
 /* Round engine: one persistent kernel with grid barriers, one launch per round step over the
- * whole GPU, or one workgroup running every round of the graph (workgroup barriers only).  AUTO
- * takes the workgroup engine for graphs of at most 2^15 arcs and the launch engine otherwise. */
-enum { LDD_ENGINE_AUTO = 0, LDD_ENGINE_PERSISTENT = 1, LDD_ENGINE_LAUNCH = 2, LDD_ENGINE_WORKGROUP = 3 };
+ * whole GPU, one workgroup running every round of the graph (workgroup barriers only), or a team
+ * of workgroups (blocks of them, default one per CU, at most two per CU) running every round with
+ * one barrier in device memory per round (top-down only: for large graphs of low degree and many
+ * rounds, such as grids).  AUTO takes the workgroup engine for graphs of at most 2^15 arcs and
+ * the launch engine otherwise; ldd_tune may pick any of them. */
+enum {
+  LDD_ENGINE_AUTO = 0,
+  LDD_ENGINE_PERSISTENT = 1,
+  LDD_ENGINE_LAUNCH = 2,
+  LDD_ENGINE_WORKGROUP = 3,
+  LDD_ENGINE_TEAM = 4
+};
 
 typedef struct {
   int32_t direction;      /* LDD_DIR_*                                                    */
@@ -157,9 +166,9 @@ ldd_status ldd_decompose_batch(int32_t num_graphs, const int64_t* vtx_off, const
 
 /*
  * Tune the engine and its mapping for a workload: the engine (one graph: engine = LAUNCH,
- * PERSISTENT, or WORKGROUP when nnz <= 2^22; a batch: batch_mode = WORKGROUP or UNION), grid size
- * (blocks), the top-down / bottom-up switching thresholds (td_to_bu, bu_to_td; not for the
- * workgroup engine, which runs top-down only), the tail threshold (tail_vertices) and, for the
+ * PERSISTENT, TEAM, or WORKGROUP when nnz <= 2^22; a batch: batch_mode = WORKGROUP or UNION), grid
+ * size (blocks), the top-down / bottom-up switching thresholds (td_to_bu, bu_to_td; not for the
+ * workgroup engine and its teams, which run top-down only), the tail threshold (tail_vertices) and, for the
  * workgroup batch engine, the arcs per team member (team_arcs), searched one knob at a time by
  * timing whole decompositions of the given inputs (median of three, HIP events on hip_stream).  The inputs are those of ldd_decompose_batch (num_graphs = 1: one graph,
  * run through ldd_decompose); centre is scratch output of the right size.  Every candidate gives

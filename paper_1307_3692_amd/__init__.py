@@ -27,7 +27,7 @@ HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
 (OK, ERR_INVALID_ARG, ERR_OOM, ERR_OVERFLOW, ERR_HIP, ERR_BUDGET, ERR_CANCELLED, ERR_INTERNAL, ERR_PENDING,
  ERR_RETRIES) = range(10)
 DIR_AUTO, DIR_TOP_DOWN, DIR_BOTTOM_UP = 0, 1, 2
-ENGINE_AUTO, ENGINE_PERSISTENT, ENGINE_LAUNCH, ENGINE_WORKGROUP = 0, 1, 2, 3
+ENGINE_AUTO, ENGINE_PERSISTENT, ENGINE_LAUNCH, ENGINE_WORKGROUP, ENGINE_TEAM = 0, 1, 2, 3, 4
 
 EXPORTED = ("ldd_decompose", "ldd_workspace_bytes", "ldd_decompose_batch", "ldd_status_string", "ldd_last_error",
             "ldd_release_workspace", "ldd_server_create", "ldd_server_submit", "ldd_server_poll", "ldd_server_wait",

@@ -110,7 +110,7 @@ struct Workspace {
   Buf cand, cand_cnt;                                    // per prep block: first-window candidates
   Buf ctrl, st, qcnt, lr_part, lb, ex_part, vr;
   // workgroup engine: queues and wake order (3 ints per vertex), jobs, order, results, job counter
-  Buf bk_wq, bk_jobs, bk_order, bk_out, bk_cnt, bk_team, bk_sync, bk_tq;
+  Buf bk_wq, bk_jobs, bk_order, bk_out, bk_cnt, bk_team, bk_sync;
   // batch: union CSR with global ids, adjusted shifts, graph of each vertex, per-graph data
   Buf b_rp, b_col, b_shift, b_gid, b_off, b_dg, b_cut;
   HostMirror* host = nullptr;
@@ -218,7 +218,7 @@ extern "C" void ldd_release_workspace(void) {
   w->graphs.clear();
   for (Buf* b : {&w->P, &w->qv0, &w->qv1, &w->qa0, &w->qa1, &w->wake_ord, &w->stamp, &w->hub_bits, &w->hist,
                  &w->cursor, &w->wake_off, &w->next_ne, &w->mat, &w->qmax, &w->cand, &w->cand_cnt, &w->ctrl, &w->st, &w->qcnt, &w->lr_part,
-                 &w->lb, &w->ex_part, &w->vr, &w->bk_wq, &w->bk_jobs, &w->bk_order, &w->bk_out, &w->bk_cnt, &w->bk_team, &w->bk_sync, &w->bk_tq, &w->b_rp, &w->b_col, &w->b_shift, &w->b_gid, &w->b_off, &w->b_dg,
+                 &w->lb, &w->ex_part, &w->vr, &w->bk_wq, &w->bk_jobs, &w->bk_order, &w->bk_out, &w->bk_cnt, &w->bk_team, &w->bk_sync, &w->b_rp, &w->b_col, &w->b_shift, &w->b_gid, &w->b_off, &w->b_dg,
                  &w->b_cut}) {
     if (b->p) (void)hipFree(b->p);
     b->p = nullptr;
@@ -277,7 +277,7 @@ extern "C" ldd_status ldd_decompose(const ldd_csr* g, const int64_t* shift_fix, 
   }
   ldd_options o{};
   if (opt) o = *opt;
-  if (o.direction < 0 || o.direction > 2 || o.engine < 0 || o.engine > 3 || o.blocks < 0) {
+  if (o.direction < 0 || o.direction > 2 || o.engine < 0 || o.engine > 4 || o.blocks < 0) {
     ldd_set_error("bad options");
     return LDD_ERR_INVALID_ARG;
   }
@@ -652,7 +652,8 @@ static ldd_status block_status(unsigned err, u64 delta, int n) {
 }
 
 __global__ void k_block_job_single(int n, long long nnz, const int* row_ptr, const int* col, const long long* shift,
-                                   int* centre, u64* P, int* wq, int tail_den, BlockJob* job) {
+                                   int* centre, u64* P, int* wq, int tail_den, int team, TeamSync* sync,
+                                   BlockJob* job) {
   if (threadIdx.x || blockIdx.x) return;
   BlockJob j;
   j.n = n;
@@ -667,9 +668,8 @@ __global__ void k_block_job_single(int n, long long nnz, const int* row_ptr, con
   j.q0 = wq + 2 * (long long)n;
   j.q1 = wq + 3 * (long long)n;
   j.tail_den = tail_den;
-  j.team = 1;
-  j.sync = nullptr;
-  j.tq = nullptr;
+  j.team = team;
+  j.sync = team > 1 ? sync : nullptr;
   *job = j;
 }
 
@@ -677,24 +677,38 @@ static int tail_den_of(const ldd_options& o) {
   return o.tail_vertices < 0 ? 0 : (o.tail_vertices > 0 ? o.tail_vertices : 32);
 }
 
+// One graph on the workgroup engine: one workgroup (WORKGROUP), or a team of K workgroups
+// (TEAM: blocks of them, default one per CU, at most the two per CU that can be resident, at least
+// 64 vertices per member) meeting at a device-memory barrier once per round.
 static ldd_status decompose_block(Workspace& w, const ldd_csr* g, const int64_t* shift_fix, int32_t* centre,
                                   int64_t* cut_edges, const ldd_options& opt, ldd_stats* stats, hipStream_t st) {
   const int n = g->n;
   const size_t nv = (size_t)n;
+  int K = 1;
+  if (opt.engine == LDD_ENGINE_TEAM) {
+    K = opt.blocks > 0 ? opt.blocks : w.num_cu;
+    K = std::min(K, std::min(2 * w.num_cu, TEAM_GROUP * TEAM_GROUPS));
+    K = std::min(K, n / 64);
+    K = std::max(K, 1);
+  }
   ldd_status s = ws_setup(w);
   if (s != LDD_OK) return s;
   if ((s = grow(w.P, nv * 8)) || (s = grow(w.bk_wq, nv * 16)) || (s = grow(w.bk_jobs, sizeof(BlockJob))) ||
-      (s = grow(w.bk_out, sizeof(BlockOut))) || (s = grow(w.bk_cnt, 8)))
+      (s = grow(w.bk_out, sizeof(BlockOut))) || (s = grow(w.bk_cnt, 8)) || (s = grow(w.bk_sync, sizeof(TeamSync))))
     return s;
   HIP_TRY(hipStreamWaitEvent(st, w.ev[2], 0));  // after any step a previous call left queued
   HIP_TRY(hipEventRecord(w.ev[0], st));
   hipLaunchKernelGGL(k_block_job_single, dim3(1), dim3(64), 0, st, n, (long long)g->nnz, g->row_ptr, g->col_idx,
-                     (const long long*)shift_fix, centre, (u64*)w.P.p, (int*)w.bk_wq.p, tail_den_of(opt),
-                     (BlockJob*)w.bk_jobs.p);
+                     (const long long*)shift_fix, centre, (u64*)w.P.p, (int*)w.bk_wq.p, tail_den_of(opt), K,
+                     (TeamSync*)w.bk_sync.p, (BlockJob*)w.bk_jobs.p);
   hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, (u64*)w.bk_cnt.p, 1ll, 0ull);
+  if (K > 1)
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(256), 0, st, (u64*)w.bk_sync.p, (long long)(sizeof(TeamSync) / 8),
+                       0ull);
   HIP_TRY(hipEventRecord(w.ev[1], st));
-  hipLaunchKernelGGL(k_block_decompose, dim3(1), dim3(1024), 0, st, (const BlockJob*)w.bk_jobs.p,
-                     (const TeamJob*)nullptr, 1, (unsigned*)w.bk_cnt.p, (BlockOut*)w.bk_out.p);
+  // no job list: job k is member k of graph 0
+  hipLaunchKernelGGL(k_block_decompose, dim3(K), dim3(1024), 0, st, (const BlockJob*)w.bk_jobs.p,
+                     (const TeamJob*)nullptr, K, (unsigned*)w.bk_cnt.p, (BlockOut*)w.bk_out.p);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipEventRecord(w.ev[2], st));
   HIP_TRY(hipMemcpyAsync(&w.host->bout, w.bk_out.p, sizeof(BlockOut), hipMemcpyDeviceToHost, st));
@@ -711,7 +725,7 @@ static ldd_status decompose_block(Workspace& w, const ldd_csr* g, const int64_t*
     stats->bu_rounds = 0;
     stats->tail_iters = (int32_t)o.sweeps;
     stats->tail_round = o.sweeps ? (int32_t)o.rounds : -1;
-    stats->blocks = 1;
+    stats->blocks = K;
     stats->steps = 1;
     stats->delta = (int64_t)o.delta;
     stats->pieces = (int64_t)o.pieces;
@@ -734,7 +748,7 @@ static ldd_status decompose_block(Workspace& w, const ldd_csr* g, const int64_t*
 static ldd_status decompose_impl(Workspace& w, const ldd_csr* g, const int64_t* shift_fix, int32_t* centre,
                                  int64_t* cut_edges, const ldd_options& o, ldd_stats* stats, hipStream_t st,
                                  const BatchView* bv) {
-  const bool block = !bv && (o.engine == LDD_ENGINE_WORKGROUP ||
+  const bool block = !bv && (o.engine == LDD_ENGINE_WORKGROUP || o.engine == LDD_ENGINE_TEAM ||
                              (o.engine == LDD_ENGINE_AUTO && g->nnz <= BLOCK_AUTO_ARCS));
   if (block) {
     ldd_status s = decompose_block(w, g, shift_fix, centre, cut_edges, o, stats, st);
@@ -777,7 +791,7 @@ extern "C" ldd_status ldd_decompose_verified(const ldd_csr* g, double beta, uint
   const int max_attempts = v.max_attempts > 0 ? v.max_attempts : 16;
   ldd_options o{};
   if (opt) o = *opt;
-  if (o.direction < 0 || o.direction > 2 || o.engine < 0 || o.engine > 3 || o.blocks < 0) {
+  if (o.direction < 0 || o.direction > 2 || o.engine < 0 || o.engine > 4 || o.blocks < 0) {
     ldd_set_error("bad options");
     return LDD_ERR_INVALID_ARG;
   }
@@ -896,40 +910,31 @@ ldd_status ldd_batch_workgroup(int32_t G, const int64_t* vtx_off, const int64_t*
     std::vector<TeamJob> jobs;
     jobs.reserve((size_t)G);
     std::vector<int> tinfo((size_t)G * 2, 0);
-    std::vector<long long> tq_off((size_t)G, 0);
     int nteams = 0;
-    long long tq_len = 0;
     for (int g : order) {
       tinfo[2 * (size_t)g] = team[g];
-      if (team[g] > 1) {
-        tinfo[2 * (size_t)g + 1] = nteams++;
-        tq_off[g] = tq_len;
-        tq_len += 2ll * team[g] * (vtx_off[g + 1] - vtx_off[g]);
-      }
+      if (team[g] > 1) tinfo[2 * (size_t)g + 1] = nteams++;
       for (int m = 0; m < team[g]; ++m) jobs.push_back(TeamJob{g, m});
     }
     const int njobs = (int)jobs.size();
     if ((s = grow(w.P, (size_t)N * 8)) || (s = grow(w.bk_wq, (size_t)N * 16)) ||
         (s = grow(w.bk_jobs, (size_t)G * sizeof(BlockJob))) || (s = grow(w.bk_order, (size_t)njobs * sizeof(TeamJob))) ||
         (s = grow(w.bk_out, (size_t)G * sizeof(BlockOut))) || (s = grow(w.bk_cnt, 8)) ||
-        (s = grow(w.b_off, (size_t)(G + 1) * 16)) || (s = grow(w.bk_team, (size_t)G * 16)) ||
-        (s = grow(w.bk_sync, (size_t)(nteams > 0 ? nteams : 1) * sizeof(TeamSync))) ||
-        (s = grow(w.bk_tq, (size_t)(tq_len > 0 ? tq_len : 1) * 4)))
+        (s = grow(w.b_off, (size_t)(G + 1) * 16)) || (s = grow(w.bk_team, (size_t)G * 8)) ||
+        (s = grow(w.bk_sync, (size_t)(nteams > 0 ? nteams : 1) * sizeof(TeamSync))))
       return s;
     long long* d_vo = (long long*)w.b_off.p;
     long long* d_ao = d_vo + (G + 1);
     int* d_team = (int*)w.bk_team.p;
-    long long* d_tqoff = (long long*)((char*)w.bk_team.p + (size_t)G * 8);
     HIP_TRY(hipStreamWaitEvent(st, w.ev[2], 0));  // after any step a previous call left queued
     HIP_TRY(hipMemcpyAsync(d_vo, vtx_off, (size_t)(G + 1) * 8, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(d_ao, arc_off, (size_t)(G + 1) * 8, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(w.bk_order.p, jobs.data(), (size_t)njobs * sizeof(TeamJob), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(d_team, tinfo.data(), (size_t)G * 8, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(d_tqoff, tq_off.data(), (size_t)G * 8, hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(k_block_jobs, dim3(grid_for(G, 256, 1024)), dim3(256), 0, st, G, N, (const long long*)d_vo,
                        (const long long*)d_ao, row_ptr, col_idx, (const long long*)shift_fix, centre, (u64*)w.P.p,
-                       (int*)w.bk_wq.p, tail_den_of(o), (const int*)d_team, (TeamSync*)w.bk_sync.p, (int*)w.bk_tq.p,
-                       (const long long*)d_tqoff, (BlockJob*)w.bk_jobs.p);
+                       (int*)w.bk_wq.p, tail_den_of(o), (const int*)d_team, (TeamSync*)w.bk_sync.p,
+                       (BlockJob*)w.bk_jobs.p);
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, (u64*)w.bk_cnt.p, 1ll, 0ull);
     if (nteams > 0)
       hipLaunchKernelGGL(k_fill_u64, dim3(grid_for((long long)nteams * sizeof(TeamSync) / 8, 256, 1024)), dim3(256), 0,

@@ -13,16 +13,35 @@ constexpr int BLOCK_WCAP = 4096;
 // needs more wake buckets than the workgroup sorts
 enum : unsigned { BLK_OVERFLOW = 64u, BLK_WIDE = 128u };
 
-// A large graph of a batch runs on a team of K <= TEAM_MAX workgroups that meet at a barrier
-// once per round.  Per team, in device memory, zeroed before the launch: the barrier's arrival
-// counter, each member's values for the round's exchange (double-buffered), and each member's
-// non-empty wake buckets.
+// A graph too large for one workgroup runs on a team of K workgroups (all resident at once) that
+// meet at a barrier in device memory once per round.  Per team, in device memory, zeroed before
+// the launch: the barrier's words (below), the OR of the members' error bits, the append counters
+// of the shared frontier queue, the preparation's and the output's sums, and the OR of the
+// members' non-empty wake buckets.  Its size does not depend on K.  A batch gives a team at most
+// TEAM_MAX workgroups; one graph alone may take every resident workgroup.
 constexpr int TEAM_MAX = 16;
 
+constexpr int TEAM_GROUP = 16;   // barrier arrivals are counted per group of 16 members, then per group
+constexpr int TEAM_GROUPS = 32;  // a team has at most TEAM_GROUP * TEAM_GROUPS = 512 members
+
+struct TeamLine {
+  alignas(128) u64 v;
+};
+
+// Barrier k of a team uses the words of slot k % 3; member 0 clears slot (k + 1) % 3 before it
+// arrives at barrier k.  An arrival adds (1 << 42) | (error ? 1 << 32 : 0) | (its appends) to its
+// group's word, the group's last arrival adds the group's sums (one arrival) to the team's word,
+// and the team's last arrival publishes the step's queue length with the barrier's number in gen.
 struct TeamSync {
-  alignas(128) unsigned arrive;
-  alignas(128) u64 red[2][TEAM_MAX][4];
-  u64 nz[TEAM_MAX][BLOCK_WCAP / 64];
+  TeamLine gw[3][TEAM_GROUPS];  // per step slot: the groups' arrivals, errors and appends
+  TeamLine tw[3];               // per step slot: the team's (arrivals are groups)
+  alignas(128) u64 gen;         // (queue length, or 0xffffffff after an error) << 32 | barriers passed
+  alignas(128) unsigned err;    // OR of every member's error bits
+  alignas(128) u64 qcnt[3];     // per step slot: the shared queue's reservations
+  alignas(128) u64 delta;
+  alignas(128) u64 active;
+  alignas(128) u64 cut, pieces, examined;
+  alignas(128) u64 nz[BLOCK_WCAP / 64];
 };
 
 struct BlockJob {
@@ -39,8 +58,7 @@ struct BlockJob {
   int* q1;
   int tail_den;          // label-correcting tail once unreached * tail_den <= vertices with arcs (0: never)
   int team;              // workgroups on this graph (1: alone)
-  TeamSync* sync;        // team > 1: the team's barrier and exchange area
-  int* tq;               // team > 1: workspace [2 * team * n]: two sets of per-member frontier segments
+  TeamSync* sync;        // team > 1: the team's barrier and counters
 };
 
 struct BlockOut {
@@ -64,6 +82,6 @@ struct TeamJob {
 __global__ void k_block_decompose(const BlockJob* jobs, const TeamJob* order, int njobs, unsigned* next_job, BlockOut* outs);
 __global__ void k_block_jobs(int G, long long N, const long long* vo, const long long* ao, const int* row_ptr,
                              const int* col, const long long* shift, int* centre, u64* P, int* wq, int tail_den,
-                             const int* team, TeamSync* sync, int* tq, const long long* tq_off, BlockJob* jobs);
+                             const int* team, TeamSync* sync, BlockJob* jobs);
 
 }  // namespace ldd

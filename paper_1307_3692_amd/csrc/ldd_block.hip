@@ -21,13 +21,13 @@
 // (first arc, degree prefix, offer) and every thread takes arcs of the chunk by index, finding its
 // entry by binary search, so a high-degree vertex is shared by all threads.
 //
-// A graph too large for one workgroup to finish in step with the rest of a batch runs on a team
-// of K workgroups (K <= TEAM_MAX, all resident at once): member m owns a slice of the vertices
-// (its preparation, wake buckets, tail seed and output) and one K-th of every frontier; each
-// member appends what it reaches to a segment of its own, and the members meet once per round
-// at a barrier in device memory where they exchange their segment lengths and error bits, so
-// the next frontier is the concatenation of the K segments.  The labels are then shared by
-// several CUs, so their loads and atomics take device scope.
+// A graph too large for one workgroup (a batch's largest graphs, or one large high-diameter graph)
+// runs on a team of K workgroups, all resident at once: member m owns a slice of the vertices
+// (its preparation, wake buckets, tail seed and output) and the m-th K-th of every frontier; the
+// next frontier is one shared queue, to which each member appends through a staging buffer in LDS
+// and one reservation per round; the members meet once per round at a barrier in device memory,
+// where the queue's length and the error bits are read.  The labels are then shared by several
+// CUs, so their loads and atomics take device scope.
 #include "ldd_block.h"
 
 namespace ldd {
@@ -37,6 +37,7 @@ namespace {
 constexpr int BT = 1024;         // threads per workgroup
 constexpr int BNW = BT / WAVE;   // waves per workgroup
 constexpr int WPT = BLOCK_WCAP / BT;  // wake buckets per thread in the scans
+constexpr unsigned TB_CAP = 2048;     // a team member's staged appends per round (more go straight out)
 
 struct BlockShared {
   int woff[BLOCK_WCAP + 1];  // wake bucket offsets (exclusive prefix), then the scatter cursors
@@ -57,10 +58,12 @@ struct BlockShared {
   TeamSync* ts;
   int tK, tm, tlo, thi;      // team size, this member, this member's vertex slice
   unsigned epoch;            // barriers passed
-  int par;                   // exchange buffer in use
-  unsigned tpre[TEAM_MAX + 1];  // current frontier: exclusive prefix of the members' segment lengths
-  u64 tv[TEAM_MAX][4];       // the members' values of the last exchange
+  unsigned bn;               // appends staged in tbuf this round
+  unsigned tnf;              // the queue length the last team barrier published
+  unsigned tcount;           // this member's appends to the shared queue in this step
+  unsigned tbase;            // the staged appends' place in the shared queue
   u64 nz[BLOCK_WCAP / 64];   // non-empty wake buckets of the whole graph
+  int tbuf[TB_CAP];          // staged appends of this member
 };
 
 __device__ __forceinline__ u64 block_max64(u64 v, BlockShared& sh) {
@@ -118,8 +121,13 @@ __device__ __forceinline__ int next_nonempty(BlockShared& sh, int r, int D) {
 }
 
 // A graph's labels are touched by its own workgroup only while it runs, so their loads and atomics
-// need workgroup scope alone (all waves of a workgroup share one CU and its vector L1); a team's
-// labels are shared by its members' CUs and take device scope.
+// need workgroup scope alone (all waves of a workgroup share one CU and its vector L1).  A team's
+// labels are shared by its members' CUs: their atomics (the claims) take device scope, while
+// their loads stay at workgroup scope and may hit the CU's caches.  A load that decides something
+// (an offer, a frontier test in the seed, a centre) reads a label that was final at the last team
+// barrier, whose acquire invalidated the caches; a load that only filters atomics (is the label
+// still larger than the offer?) may see an older value, which is never smaller (labels only
+// decrease), so at worst it lets through an atomic that finds nothing to do.
 constexpr int WG = __HIP_MEMORY_SCOPE_WORKGROUP;
 constexpr int AG = __HIP_MEMORY_SCOPE_AGENT;
 
@@ -141,6 +149,53 @@ __device__ __forceinline__ void append(unsigned* cnt, int* next, int v) {
   const unsigned idx = atomicAdd(cnt, 1u);
   next[idx] = v;
 }
+
+// Appends to the next frontier.  Alone: counted in LDS, written at once.  step() is called by
+// every thread after each pass of at most BT appends (nothing to do here).
+struct LocalAppend {
+  unsigned* cnt;
+  int* next;
+  __device__ __forceinline__ void operator()(int v) const { append(cnt, next, v); }
+  __device__ __forceinline__ void step() const {}
+};
+
+// The staged appends of a team member go to the team's shared queue behind one reservation
+// (all threads call; `c` entries staged, c <= TB_CAP).
+__device__ __forceinline__ void team_flush(BlockShared& sh, int* next, u64* gcnt, unsigned c) {
+  if (threadIdx.x == 0) {
+    sh.tbase = (unsigned)__hip_atomic_fetch_add(gcnt, (u64)c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    sh.tcount += c;
+  }
+  __syncthreads();
+  for (unsigned i = threadIdx.x; i < c; i += BT) next[sh.tbase + i] = sh.tbuf[i];
+  __syncthreads();
+  if (threadIdx.x == 0) sh.bn = 0;
+  __syncthreads();
+}
+
+// A team member: staged in LDS; after a pass that may leave fewer than BT free entries, the
+// staged entries are placed in the shared queue (step(), uniform: one reservation per 1024 or
+// more appends), and the rest at the end of the round.  An append past the staging capacity
+// (which the passes never reach) would reserve its own slot.
+struct TeamAppend {
+  BlockShared* sh;
+  int* next;
+  u64* gcnt;
+  __device__ __forceinline__ void operator()(int v) const {
+    const unsigned i = atomicAdd(&sh->bn, 1u);
+    if (i < TB_CAP) {
+      sh->tbuf[i] = v;
+    } else {
+      next[__hip_atomic_fetch_add(gcnt, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)] = v;
+      atomicAdd(&sh->tcount, 1u);
+    }
+  }
+  __device__ __forceinline__ void step() const {
+    __syncthreads();
+    const unsigned c = sh->bn;
+    if (c > TB_CAP - BT) team_flush(*sh, next, gcnt, c < TB_CAP ? c : TB_CAP);
+  }
+};
 
 // Wake buckets of the vertices with arcs in [lo, hi): counting sort by w(v) = (Delta - shift) >> 20
 // in LDS; the vertices' own labels ((Delta - shift[v]) << B) | v go to wk[lo ...] in bucket order
@@ -259,16 +314,17 @@ __device__ __attribute__((noinline)) void block_prepare(const BlockJob& j, Block
 // end whose label dropped, once per sweep (its stamp takes the sweep's tag).  U arcs per thread
 // are issued together (entries by binary search in LDS, column ids, far labels, minima); one at a
 // time measured fastest (more in flight cost registers and did not pay on batches or small graphs).
-template <int SC, bool SWEEP>
-__device__ __forceinline__ void relax_chunk(const BlockJob& j, BlockShared& sh, int* next, unsigned ne,
-                                            unsigned total, int tag, unsigned* cnt) {
+template <int SC, bool SWEEP, class App>
+__device__ __forceinline__ void relax_chunk(const BlockJob& j, BlockShared& sh, unsigned ne, unsigned total, int tag,
+                                            const App& app) {
   constexpr int U = 1;
   const int n = j.n;
   const long long nnz = j.nnz;
   const int* __restrict__ col = j.col;
   u64* P = j.P;
   const int top = ne > 1 ? 1 << (31 - __builtin_clz(ne - 1)) : 0;
-  for (unsigned base = threadIdx.x; base < total; base += U * BT) {
+  for (unsigned b0 = 0; b0 < total; b0 += U * BT) {  // the same passes in every thread (app.step)
+    const unsigned base = b0 + threadIdx.x;
     int w[U];
     u64 off[U];
 #pragma unroll
@@ -286,54 +342,46 @@ __device__ __forceinline__ void relax_chunk(const BlockJob& j, BlockShared& sh, 
     for (int k = 0; k < U; ++k) {
       const bool ok = (unsigned)w[k] < (unsigned)n;
       if (!ok && w[k] != -2) atomicOr(&sh.err, ERR_BAD_COL);
-      pw[k] = ok ? lab_load<SC>(&P[w[k]]) : 0;
+      pw[k] = ok ? wg_load(&P[w[k]]) : 0;
     }
 #pragma unroll
     for (int k = 0; k < U; ++k) {
       if (pw[k] > off[k]) {
         const u64 old = lab_min<SC>(&P[w[k]], off[k]);
         if (SWEEP) {
-          if (old > off[k] && __hip_atomic_exchange(&j.wake[w[k]], tag, __ATOMIC_RELAXED, SC) != tag)
-            append(cnt, next, w[k]);
+          if (old > off[k] && __hip_atomic_exchange(&j.wake[w[k]], tag, __ATOMIC_RELAXED, SC) != tag) app(w[k]);
         } else if (old == INF) {
-          append(cnt, next, w[k]);
+          app(w[k]);
         }
       }
     }
+    app.step();
   }
 }
 
-// Relax the arcs of frontier entries [e0, e1), staged in LDS a chunk of BT entries at a time (all
-// threads call).  Alone (TEAM false) the frontier is cur[0 ...]; in a team it is the concatenation
-// of the members' segments, member s's at cur + s n with length tpre[s + 1] - tpre[s].
-template <int SC, bool SWEEP, bool TEAM>
+// Relax the arcs of frontier entries cur[e0 .. e1), staged in LDS a chunk of BT entries at a time
+// (all threads call).
+template <int SC, bool SWEEP, class App>
 __device__ __forceinline__ u64 expand_frontier(const BlockJob& j, BlockShared& sh, const int* cur, unsigned e0,
-                                               unsigned e1, int* next, u64 unit, int tag, unsigned* cnt) {
+                                               unsigned e1, u64 unit, int tag, const App& app) {
   const int* __restrict__ rp = j.row_ptr;
   u64 examined = 0;
   for (unsigned c0 = e0; c0 < e1; c0 += BT) {
     const unsigned e = c0 + threadIdx.x;
     unsigned deg = 0;
     if (e < e1) {
-      int u;
-      if (TEAM) {
-        int s = 0;
-        while (s + 1 < sh.tK && sh.tpre[s + 1] <= e) ++s;
-        u = cur[(long long)s * j.n + (e - sh.tpre[s])];
-      } else {
-        u = cur[e];
-      }
+      const int u = cur[e];
       const int a0 = rp[u], a1 = rp[u + 1];
       deg = (unsigned)(a1 - a0);
       sh.first[threadIdx.x] = a0;
-      sh.offer[threadIdx.x] = lab_load<SC>(&j.P[u]) + unit;
+      sh.offer[threadIdx.x] = wg_load(&j.P[u]) + unit;
     }
     unsigned total;
     const unsigned ex = block_excl_scan(deg, sh, &total);
     sh.pre[threadIdx.x] = ex;
     __syncthreads();
     examined += threadIdx.x == 0 ? total : 0;
-    relax_chunk<SC, SWEEP>(j, sh, next, e1 - c0 < (unsigned)BT ? e1 - c0 : (unsigned)BT, total, tag, cnt);
+    relax_chunk<SC, SWEEP>(j, sh, e1 - c0 < (unsigned)BT ? e1 - c0 : (unsigned)BT, total, tag, app);
     __syncthreads();
   }
   return examined;
@@ -379,7 +427,7 @@ __device__ __attribute__((noinline)) void block_rounds(const BlockJob& j, BlockS
       const int v = (int)(self & mask);
       if (wg_load(&P[v]) > self && lab_min<WG>(&P[v], self) == INF) append(cnt, next, v);
     }
-    examined += expand_frontier<WG, false, false>(j, sh, cur, 0, nf, next, unit, 0, cnt);
+    examined += expand_frontier<WG, false>(j, sh, cur, 0, nf, unit, 0, LocalAppend{cnt, next});
     __syncthreads();  // this round's appends are done; every thread has read the count of round k - 1
     nf = *cnt;
     if (tid == 0) sh.cnt3[ci == 0 ? 2 : ci - 1] = 0;  // round k - 1's counter, next used by round k + 2
@@ -431,7 +479,7 @@ __device__ __attribute__((noinline)) void block_rounds(const BlockJob& j, BlockS
     // sweeps: sweep k relaxes the labels queued by the step before and queues those that drop
     for (int k = 1; nf && !sh.err && sweeps <= n; ++k) {
       unsigned* cnt = &sh.cnt3[ci];
-      examined += expand_frontier<WG, true, false>(j, sh, cur, 0, nf, next, unit, -(k + 1), cnt);
+      examined += expand_frontier<WG, true>(j, sh, cur, 0, nf, unit, -(k + 1), LocalAppend{cnt, next});
       __syncthreads();
       nf = *cnt;
       if (tid == 0) sh.cnt3[ci == 0 ? 2 : ci - 1] = 0;
@@ -513,60 +561,98 @@ __device__ void block_graph(const BlockJob& j, BlockShared& sh, BlockOut* out) {
 
 // ---- a team of workgroups on one graph ----------------------------------------------------
 
-// The team's barrier, with an exchange: every member publishes four values (workgroup-uniform:
-// thread 0's are taken), and after the barrier every member holds all members' values in sh.tv
-// (all threads call).  The arrival counter only grows; the values are double-buffered, so a
-// member that leaves one exchange cannot overwrite values another member has yet to read (that
-// member must arrive at the next barrier first).  The release on arrival and the acquire after
-// the wait make every write of the members before the barrier (labels, segments, stamps) visible
-// after it.  A bounded wait raises ERR_BARRIER instead of hanging.
-__device__ void team_exchange(BlockShared& sh, u64 a, u64 b, u64 c, u64 d) {
+// Member 0 clears the words of the next step's slot before it arrives at this step's barrier:
+// every member read them (as the slot of the step before last) before arriving at the last
+// barrier, and the next step uses them only after this step's barrier (all threads call).
+__device__ __forceinline__ void team_clear_next(BlockShared& sh) {
+  if (sh.tm != 0) return;
+  const int nx = (int)((sh.epoch + 1) % 3);
+  const int ng = (sh.tK + TEAM_GROUP - 1) / TEAM_GROUP;
+  if ((int)threadIdx.x < ng) __hip_atomic_store(&sh.ts->gw[nx][threadIdx.x].v, 0ull, __ATOMIC_RELAXED, AG);
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(&sh.ts->tw[nx].v, 0ull, __ATOMIC_RELAXED, AG);
+    __hip_atomic_store(&sh.ts->qcnt[nx], 0ull, __ATOMIC_RELAXED, AG);
+  }
+}
+
+// The team's barrier k (all threads call; k = sh.epoch, slot k % 3).  Every wave first waits for
+// its own stores and atomics to complete (a workgroup barrier does not wait for other waves'
+// stores to leave the CU).  Then thread 0 arrives, adding (1 << 42) | (error ? 1 << 32 : 0) | (its
+// appends this step) to its group's word; the group's last arrival adds the group's sums to the
+// team's word, and the team's last arrival publishes the step's queue length (the sum of the
+// appends; 0xffffffff if any member had an error) with the barrier's number in gen, which the
+// others wait for.  In a team of at most TEAM_GROUP members the arrivals go to the team's word
+// directly.  Arrivals are acquire-release read-modify-writes and gen a release store, so every
+// write of the members before the barrier (labels, queue entries, stamps, counters) is visible
+// after the acquire that follows the wait.  A bounded wait raises ERR_BARRIER instead of hanging.
+// Returns the queue length; after an error every member ORs the team's error bits into sh.err.
+__device__ unsigned team_barrier(BlockShared& sh) {
+  team_clear_next(sh);
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
     TeamSync* ts = sh.ts;
-    u64* r = &ts->red[sh.par][sh.tm][0];
-    __hip_atomic_store(r + 0, a, __ATOMIC_RELAXED, AG);
-    __hip_atomic_store(r + 1, b, __ATOMIC_RELAXED, AG);
-    __hip_atomic_store(r + 2, c, __ATOMIC_RELAXED, AG);
-    __hip_atomic_store(r + 3, d, __ATOMIC_RELAXED, AG);
-    const unsigned target = (sh.epoch + 1) * (unsigned)sh.tK;
-    __hip_atomic_fetch_add(&ts->arrive, 1u, __ATOMIC_RELEASE, AG);
-    unsigned spins = 0;
-    while (__hip_atomic_load(&ts->arrive, __ATOMIC_RELAXED, AG) < target) {
-      __builtin_amdgcn_s_sleep(1);
-      if (++spins > (1u << 26)) {
-        sh.err |= ERR_BARRIER;
-        break;
+    const unsigned K = (unsigned)sh.tK, g = (unsigned)sh.tm / TEAM_GROUP;
+    const unsigned ng = (K + TEAM_GROUP - 1) / TEAM_GROUP;
+    const unsigned in_g = K - g * TEAM_GROUP < (unsigned)TEAM_GROUP ? K - g * TEAM_GROUP : (unsigned)TEAM_GROUP;
+    const unsigned e1 = sh.epoch + 1;
+    const int slot = (int)(sh.epoch % 3);
+    if (sh.err) __hip_atomic_fetch_or(&ts->err, sh.err, __ATOMIC_RELAXED, AG);
+    constexpr u64 ONE = 1ull << 42, SUMS = ONE - 1;
+    const u64 mine = ONE | (sh.err ? 1ull << 32 : 0ull) | (u64)sh.tcount;
+    bool last = false;
+    u64 sum = 0;
+    if (ng == 1) {
+      const u64 old = __hip_atomic_fetch_add(&ts->tw[slot].v, mine, __ATOMIC_ACQ_REL, AG);
+      last = (old >> 42) + 1 == K;
+      sum = (old & SUMS) + (mine & SUMS);
+    } else {
+      const u64 old = __hip_atomic_fetch_add(&ts->gw[slot][g].v, mine, __ATOMIC_ACQ_REL, AG);
+      if ((old >> 42) + 1 == in_g) {
+        const u64 grp = ONE | ((old & SUMS) + (mine & SUMS));
+        const u64 top = __hip_atomic_fetch_add(&ts->tw[slot].v, grp, __ATOMIC_ACQ_REL, AG);
+        last = (top >> 42) + 1 == ng;
+        sum = (top & SUMS) + (grp & SUMS);
+      }
+    }
+    u64 word;
+    if (last) {
+      const unsigned nf = (sum >> 32) ? 0xffffffffu : (unsigned)sum;
+      word = ((u64)nf << 32) | e1;
+      __hip_atomic_store(&ts->gen, word, __ATOMIC_RELEASE, AG);
+    } else {
+      unsigned spins = 0;
+      while ((unsigned)(word = __hip_atomic_load(&ts->gen, __ATOMIC_RELAXED, AG)) < e1) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > (1u << 22)) {  // seconds: far beyond any round, or a member's late start
+          __hip_atomic_fetch_or(&ts->err, (unsigned)ERR_BARRIER, __ATOMIC_RELAXED, AG);
+          word = (u64)0xffffffffu << 32;
+          break;
+        }
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    unsigned nf = (unsigned)(word >> 32);
+    if (nf == 0xffffffffu) {
+      const unsigned e = __hip_atomic_load(&ts->err, __ATOMIC_RELAXED, AG);
+      sh.err |= e ? e : (unsigned)ERR_BARRIER;
+      nf = 0;
+    }
+    sh.tnf = nf;
+    sh.tcount = 0;
+    sh.epoch = e1;
   }
   __syncthreads();
-  if ((int)threadIdx.x < 4 * sh.tK)
-    sh.tv[threadIdx.x >> 2][threadIdx.x & 3] =
-        __hip_atomic_load(&sh.ts->red[sh.par][0][0] + threadIdx.x, __ATOMIC_RELAXED, AG);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    sh.epoch += 1;
-    sh.par ^= 1;
-  }
-  __syncthreads();
+  return sh.tnf;
 }
 
-// After an exchange of (segment length, -, error bits, -): the exclusive prefix of the segment
-// lengths in sh.tpre, their total (returned) and the OR of the error bits (all threads call;
-// uniform results).
-__device__ __forceinline__ unsigned team_counts(BlockShared& sh, unsigned* err) {
-  unsigned tot = 0, e = 0;
-  for (int k = 0; k < sh.tK; ++k) {
-    if (threadIdx.x == 0) sh.tpre[k] = tot;
-    tot += (unsigned)sh.tv[k][0];
-    e |= (unsigned)sh.tv[k][2];
-  }
-  if (threadIdx.x == 0) sh.tpre[sh.tK] = tot;
-  *err = e;
+// End of a member's step: its staged appends go to the shared queue `next`, then the barrier,
+// which returns the queue's length, the same in every member (all threads call).
+__device__ unsigned team_round_end(BlockShared& sh, int* next, u64* gcnt) {
   __syncthreads();
-  return tot;
+  const unsigned c = sh.bn < TB_CAP ? sh.bn : TB_CAP;
+  if (c) team_flush(sh, next, gcnt, c);
+  return team_barrier(sh);
 }
 
 // The first non-empty wake bucket of the whole graph at or after r, from the bitmap sh.nz (D + n +
@@ -589,23 +675,28 @@ __device__ __forceinline__ int team_next_nonempty(BlockShared& sh, int r, int D)
   return q <= D ? q : 0x3fffffff;
 }
 
-// Team preparation: every member scans its slice (checks, labels INF, Delta and the vertices
-// with arcs, combined by an exchange) and sorts its slice's wake buckets; the members' non-empty
-// buckets are combined into sh.nz by a second barrier.
+// Team preparation: every member scans its slice (checks, labels INF, Delta and the vertices with
+// arcs, combined by atomics in the team's record) and sorts its slice's wake buckets; the members'
+// non-empty buckets are ORed into the record and read back after a second barrier.
 __device__ __attribute__((noinline)) void team_prepare(const BlockJob& j, BlockShared& sh) {
   const int tid = threadIdx.x;
-  if (tid == 0) sh.err = 0;
+  TeamSync* ts = sh.ts;
+  if (tid == 0) {
+    sh.err = 0;
+    sh.bn = 0;
+  }
   __syncthreads();
   u64 dmax, active;
   prepare_scan(j, sh, sh.tlo, sh.thi, sh.tm == 0, &dmax, &active);
-  team_exchange(sh, active, dmax, sh.err, 0);
-  u64 n_active = 0, delta = 0;
-  unsigned e = 0;
-  for (int k = 0; k < sh.tK; ++k) {
-    n_active += sh.tv[k][0];
-    delta = sh.tv[k][1] > delta ? sh.tv[k][1] : delta;
-    e |= (unsigned)sh.tv[k][2];
+  if (tid == 0) {
+    if (dmax) __hip_atomic_fetch_max(&ts->delta, dmax, __ATOMIC_RELAXED, AG);
+    if (active) __hip_atomic_fetch_add(&ts->active, active, __ATOMIC_RELAXED, AG);
+    if (sh.err) __hip_atomic_fetch_or(&ts->err, sh.err, __ATOMIC_RELAXED, AG);
   }
+  team_barrier(sh);
+  const u64 delta = __hip_atomic_load(&ts->delta, __ATOMIC_RELAXED, AG);
+  const u64 n_active = __hip_atomic_load(&ts->active, __ATOMIC_RELAXED, AG);
+  unsigned e = __hip_atomic_load(&ts->err, __ATOMIC_RELAXED, AG);
   if (!e) e = range_err(j.n, delta);
   __syncthreads();
   if (tid == 0) {
@@ -622,26 +713,24 @@ __device__ __attribute__((noinline)) void team_prepare(const BlockJob& j, BlockS
       const int q = tid * 64 + b;
       bits |= (u64)(sh.woff[q + 1] > sh.woff[q]) << b;
     }
-    __hip_atomic_store(&sh.ts->nz[sh.tm][tid], bits, __ATOMIC_RELAXED, AG);
+    if (bits) __hip_atomic_fetch_or(&ts->nz[tid], bits, __ATOMIC_RELAXED, AG);
   }
-  team_exchange(sh, 0, 0, 0, 0);
-  if (tid < BLOCK_WCAP / 64) {
-    u64 bits = 0;
-    for (int k = 0; k < sh.tK; ++k) bits |= __hip_atomic_load(&sh.ts->nz[k][tid], __ATOMIC_RELAXED, AG);
-    sh.nz[tid] = bits;
-  }
+  team_barrier(sh);
+  if (tid < BLOCK_WCAP / 64) sh.nz[tid] = __hip_atomic_load(&ts->nz[tid], __ATOMIC_RELAXED, AG);
   __syncthreads();
 }
 
 // The rounds of a team: the same rounds and tail as block_rounds, with labels at device scope,
 // wakes from the member's slice, expansion of the member's K-th of the frontier, appends to the
-// member's segment, and one exchange per round (or seed, or sweep) for the segment lengths.
+// shared queue, and one barrier per round (or seed, or sweep), which returns the next frontier's
+// length.
 __device__ __attribute__((noinline)) void team_rounds(const BlockJob& j, BlockShared& sh) {
   const int n = j.n;
   const int* __restrict__ rp = j.row_ptr;
   const int* __restrict__ col = j.col;
   const long long* __restrict__ shift = j.shift;
   u64* P = j.P;
+  TeamSync* ts = sh.ts;
   const int tid = threadIdx.x;
   const int K = sh.tK, m = sh.tm, lo = sh.tlo, hi = sh.thi;
   const u64 delta = sh.delta, n_active = sh.n_active;
@@ -649,32 +738,32 @@ __device__ __attribute__((noinline)) void team_rounds(const BlockJob& j, BlockSh
   const int D = (int)(delta >> FIX);
   const u64 unit = (u64)1 << (FIX + B);
   const u64 mask = ((u64)1 << B) - 1;
-  int* cur = j.tq;
-  int* nxt = j.tq + (long long)K * n;
-  unsigned nf = 0, e = 0;
+  int* cur = j.q0;
+  int* nxt = j.q1;
+  unsigned nf = 0;
   u64 settled = 0, examined = 0;
   long long rounds = 0, sweeps = 0;
   int r = team_next_nonempty(sh, 0, D);
   bool tail = false;
   while (settled < n_active && r <= D + n && rounds <= (long long)D + n + 2) {
-    __syncthreads();
-    if (tid == 0) sh.cnt = 0;
-    __syncthreads();
-    int* mine = nxt + (long long)m * n;
+    u64* gcnt = &ts->qcnt[sh.epoch % 3];
+    const TeamAppend app{&sh, nxt, gcnt};
     if (r <= D) {
       const int w0 = sh.woff[r], w1 = sh.woff[r + 1];
-      for (int i = w0 + tid; i < w1; i += BT) {
-        const u64 self = j.wk[lo + i];
-        const int v = (int)(self & mask);
-        if (lab_load<AG>(&P[v]) > self && lab_min<AG>(&P[v], self) == INF) append(&sh.cnt, mine, v);
+      for (int i0 = w0; i0 < w1; i0 += BT) {  // the same passes in every thread (app.step)
+        const int i = i0 + tid;
+        if (i < w1) {
+          const u64 self = j.wk[lo + i];
+          const int v = (int)(self & mask);
+          if (wg_load(&P[v]) > self && lab_min<AG>(&P[v], self) == INF) app(v);
+        }
+        app.step();
       }
     }
     const unsigned e0 = (unsigned)((u64)nf * m / K), e1 = (unsigned)((u64)nf * (m + 1) / K);
-    examined += expand_frontier<AG, false, true>(j, sh, cur, e0, e1, mine, unit, 0, &sh.cnt);
-    __syncthreads();
-    team_exchange(sh, sh.cnt, 0, sh.err, 0);
-    nf = team_counts(sh, &e);
-    if (e) break;
+    examined += expand_frontier<AG, false>(j, sh, cur, e0, e1, unit, 0, app);
+    nf = team_round_end(sh, nxt, gcnt);
+    if (sh.err) break;
     settled += nf;
     ++rounds;
     int* t = cur;
@@ -688,47 +777,41 @@ __device__ __attribute__((noinline)) void team_rounds(const BlockJob& j, BlockSh
       break;
     }
   }
-  if (tail && !e) {
-    // seed over the member's slice (see block_rounds), then sweeps over the team's segments
-    __syncthreads();
-    if (tid == 0) sh.cnt = 0;
-    __syncthreads();
-    int* mine = nxt + (long long)m * n;
+  if (tail && !sh.err) {
+    // seed over the member's slice (see block_rounds), then sweeps over the shared queue
+    u64* gcnt = &ts->qcnt[sh.epoch % 3];
+    const TeamAppend app{&sh, nxt, gcnt};
     const u64 prev_round = (u64)(r - 1);
-    for (int v = lo + tid; v < hi; v += BT) {
-      const int a0 = rp[v], a1 = rp[v + 1];
-      if (a1 == a0 || lab_load<AG>(&P[v]) != INF) continue;
-      u64 best = ((delta - (u64)shift[v]) << B) | (u64)v;
-      for (int a = a0; a < a1; ++a) {
-        const int u = col[a];
-        if ((unsigned)u >= (unsigned)n) {
-          atomicOr(&sh.err, ERR_BAD_COL);
-          break;
+    for (int v0 = lo; v0 < hi; v0 += BT) {  // the same passes in every thread (app.step)
+      const int v = v0 + tid;
+      const int a0 = v < hi ? rp[v] : 0, a1 = v < hi ? rp[v + 1] : 0;
+      if (a1 > a0 && wg_load(&P[v]) == INF) {
+        u64 best = ((delta - (u64)shift[v]) << B) | (u64)v;
+        for (int a = a0; a < a1; ++a) {
+          const int u = col[a];
+          if ((unsigned)u >= (unsigned)n) {
+            atomicOr(&sh.err, ERR_BAD_COL);
+            break;
+          }
+          const u64 pu = wg_load(&P[u]);
+          if (pu != INF && (pu >> (FIX + B)) == prev_round && pu + unit < best) best = pu + unit;
         }
-        const u64 pu = lab_load<AG>(&P[u]);
-        if (pu != INF && (pu >> (FIX + B)) == prev_round && pu + unit < best) best = pu + unit;
+        examined += (u64)(a1 - a0);
+        lab_store<AG>(&P[v], best);
+        j.wake[v] = -1;  // the stamp of the first sweep
+        app(v);
       }
-      examined += (u64)(a1 - a0);
-      lab_store<AG>(&P[v], best);
-      j.wake[v] = -1;  // the stamp of the first sweep
-      append(&sh.cnt, mine, v);
+      app.step();
     }
-    __syncthreads();
-    team_exchange(sh, sh.cnt, 0, sh.err, 0);
-    nf = team_counts(sh, &e);
+    nf = team_round_end(sh, nxt, gcnt);
     int* t = cur;
     cur = nxt;
     nxt = t;
-    for (int k = 1; nf && !e && sweeps <= n; ++k) {
-      __syncthreads();
-      if (tid == 0) sh.cnt = 0;
-      __syncthreads();
-      mine = nxt + (long long)m * n;
+    for (int k = 1; nf && !sh.err && sweeps <= n; ++k) {
+      gcnt = &ts->qcnt[sh.epoch % 3];
       const unsigned e0 = (unsigned)((u64)nf * m / K), e1 = (unsigned)((u64)nf * (m + 1) / K);
-      examined += expand_frontier<AG, true, true>(j, sh, cur, e0, e1, mine, unit, -(k + 1), &sh.cnt);
-      __syncthreads();
-      team_exchange(sh, sh.cnt, 0, sh.err, 0);
-      nf = team_counts(sh, &e);
+      examined += expand_frontier<AG, true>(j, sh, cur, e0, e1, unit, -(k + 1), TeamAppend{&sh, nxt, gcnt});
+      nf = team_round_end(sh, nxt, gcnt);
       ++sweeps;
       t = cur;
       cur = nxt;
@@ -739,7 +822,6 @@ __device__ __attribute__((noinline)) void team_rounds(const BlockJob& j, BlockSh
   __syncthreads();
   examined = block_sum64(examined, sh);
   if (tid == 0) {
-    sh.err |= e;
     sh.settled = settled;
     sh.examined = examined;
     sh.rounds = rounds;
@@ -748,13 +830,14 @@ __device__ __attribute__((noinline)) void team_rounds(const BlockJob& j, BlockSh
   __syncthreads();
 }
 
-// Centres and cut of the member's slice, summed over the team by a last exchange; member 0
-// writes the graph's result.
+// Centres and cut of the member's slice, summed in the team's record; after a last barrier,
+// member 0 writes the graph's result.
 __device__ __attribute__((noinline)) void team_output(const BlockJob& j, BlockShared& sh, BlockOut* out) {
   const int n = j.n;
   const int* __restrict__ rp = j.row_ptr;
   const int* __restrict__ col = j.col;
   u64* P = j.P;
+  TeamSync* ts = sh.ts;
   const int tid = threadIdx.x;
   const int B = n > 1 ? 32 - __builtin_clz((unsigned)(n - 1)) : 1;
   const u64 mask = ((u64)1 << B) - 1;
@@ -762,7 +845,7 @@ __device__ __attribute__((noinline)) void team_output(const BlockJob& j, BlockSh
   u64 cut2 = 0, pieces = 0;
   if (!e0) {
     for (int v = sh.tlo + tid; v < sh.thi; v += BT) {
-      const u64 p = lab_load<AG>(&P[v]);
+      const u64 p = wg_load(&P[v]);
       const int c = p == INF ? v : (int)(p & mask);
       j.centre[v] = c;
       pieces += c == v;
@@ -772,7 +855,7 @@ __device__ __attribute__((noinline)) void team_output(const BlockJob& j, BlockSh
           atomicOr(&sh.err, ERR_BAD_COL);
           break;
         }
-        const u64 pw = lab_load<AG>(&P[w]);
+        const u64 pw = wg_load(&P[w]);
         const int cw = pw == INF ? w : (int)(pw & mask);
         cut2 += cw != c;
       }
@@ -781,24 +864,22 @@ __device__ __attribute__((noinline)) void team_output(const BlockJob& j, BlockSh
   cut2 = block_sum64(cut2, sh);
   pieces = block_sum64(pieces, sh);
   __syncthreads();
-  team_exchange(sh, cut2, pieces, e0 | sh.err, sh.examined);
+  if (tid == 0) {
+    if (cut2) __hip_atomic_fetch_add(&ts->cut, cut2, __ATOMIC_RELAXED, AG);
+    if (pieces) __hip_atomic_fetch_add(&ts->pieces, pieces, __ATOMIC_RELAXED, AG);
+    if (sh.examined) __hip_atomic_fetch_add(&ts->examined, sh.examined, __ATOMIC_RELAXED, AG);
+    if (e0 | sh.err) __hip_atomic_fetch_or(&ts->err, e0 | sh.err, __ATOMIC_RELAXED, AG);
+  }
+  team_barrier(sh);
   if (tid == 0 && sh.tm == 0) {
-    u64 c = 0, p = 0, x = 0;
-    unsigned e = 0;
-    for (int k = 0; k < sh.tK; ++k) {
-      c += sh.tv[k][0];
-      p += sh.tv[k][1];
-      e |= (unsigned)sh.tv[k][2];
-      x += sh.tv[k][3];
-    }
-    out->err = e | sh.err;
-    out->cut_arcs = c;
-    out->pieces = p;
+    out->err = __hip_atomic_load(&ts->err, __ATOMIC_RELAXED, AG) | sh.err;
+    out->cut_arcs = __hip_atomic_load(&ts->cut, __ATOMIC_RELAXED, AG);
+    out->pieces = __hip_atomic_load(&ts->pieces, __ATOMIC_RELAXED, AG);
+    out->examined = __hip_atomic_load(&ts->examined, __ATOMIC_RELAXED, AG);
     out->delta = sh.delta;
     out->n_active = sh.n_active;
     out->rounds = sh.rounds;
     out->sweeps = sh.sweeps;
-    out->examined = x;
   }
 }
 
@@ -813,7 +894,7 @@ __device__ void team_graph(const BlockJob& j, BlockShared& sh, BlockOut* out, in
     sh.tlo = (int)min((long long)n, (long long)m * chunk);
     sh.thi = (int)min((long long)n, (long long)sh.tlo + chunk);
     sh.epoch = 0;
-    sh.par = 0;
+    sh.tcount = 0;
   }
   __syncthreads();
   team_prepare(j, sh);
@@ -846,8 +927,8 @@ __global__ __launch_bounds__(BT, 8) void k_block_decompose(const BlockJob* __res
     const int k = sh.job;
     __syncthreads();
     if (k >= njobs) return;
-    const int g = order ? order[k].g : k;
-    const int m = order ? order[k].m : 0;
+    const int g = order ? order[k].g : 0;  // no list: job k is member k of graph 0
+    const int m = order ? order[k].m : k;
     const u64 t0 = wall_clock64();
     if (jobs[g].team > 1) team_graph(jobs[g], sh, &outs[g], m);
     else block_graph(jobs[g], sh, &outs[g]);
@@ -860,10 +941,10 @@ __global__ __launch_bounds__(BT, 8) void k_block_decompose(const BlockJob* __res
 }
 
 // Per-graph job descriptors of a batch in one offset CSR (graph g's rows at row_ptr[vo[g] + g]);
-// team[2 g] = graph g's team size, team[2 g + 1] its TeamSync, tq_off[g] its segments in tq.
+// team[2 g] = graph g's team size, team[2 g + 1] its TeamSync.
 __global__ void k_block_jobs(int G, long long N, const long long* vo, const long long* ao, const int* row_ptr,
                              const int* col, const long long* shift, int* centre, u64* P, int* wq, int tail_den,
-                             const int* team, TeamSync* sync, int* tq, const long long* tq_off, BlockJob* jobs) {
+                             const int* team, TeamSync* sync, BlockJob* jobs) {
   for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < G; g += gridDim.x * blockDim.x) {
     BlockJob j;
     const long long v0 = vo[g];
@@ -881,7 +962,6 @@ __global__ void k_block_jobs(int G, long long N, const long long* vo, const long
     j.tail_den = tail_den;
     j.team = team ? team[2 * g] : 1;
     j.sync = j.team > 1 ? sync + team[2 * g + 1] : nullptr;
-    j.tq = j.team > 1 ? tq + tq_off[g] : nullptr;
     jobs[g] = j;
   }
 }

@@ -192,11 +192,14 @@ __device__ __forceinline__ void wave_append(bool want, int v, unsigned deg, Queu
 }
 
 // Grid-wide barrier for a co-resident (cooperatively launched) grid.  Arrival counter is
-// monotone; generation `gen` is kept per block.  The release fence before arriving and the
-// acquire fence after leaving make every write of the previous phase (plain stores and
-// atomics) visible to every block at agent scope.  A bounded spin turns a hang into
+// monotone; generation `gen` is kept per block.  Every wave first waits for its own stores and
+// atomics to complete (a workgroup barrier does not wait for other waves' stores to leave the
+// CU); thread 0's release on arrival then writes them back at agent scope, and the acquire fence
+// after leaving makes every write of the previous phase (plain stores and atomics) visible to
+// every block at agent scope.  A bounded spin turns a hang into
 // ERR_BARRIER; the caller then leaves its loop.
 __device__ __forceinline__ void grid_sync(u64* bar, unsigned nblocks, u64& gen, unsigned* err) {
+  __builtin_amdgcn_s_waitcnt(0);  // this wave's stores (and atomics) have completed
   __syncthreads();
   if (threadIdx.x == 0) {
     gen += 1;

@@ -1,5 +1,5 @@
-// Autotuning of the engine and its mapping: the engine (one graph: launch, persistent or
-// workgroup; a batch: workgroup engine or disjoint union), the grid size, the top-down /
+// Autotuning of the engine and its mapping: the engine (one graph: launch, persistent, a team of
+// workgroups, or one workgroup; a batch: workgroup engine or disjoint union), the grid size, the top-down /
 // bottom-up switching thresholds, the tail threshold and, for the workgroup batch engine, the
 // arcs per team member, searched one knob at a time (coordinate descent) by timing whole
 // decompositions of the caller's inputs with HIP events.  Every candidate computes the
@@ -26,9 +26,10 @@ struct Knobs {
   int blocks, td_to_bu, bu_to_td, tail, team_arcs;
 };
 
-// the workgroup engine takes no direction thresholds (it runs top-down only)
+// the workgroup engine and its teams take no direction thresholds (they run top-down only)
 bool workgroup_mode(int G, const Knobs& k) {
-  return G == 1 ? k.mode == LDD_ENGINE_WORKGROUP : (k.mode == LDD_BATCH_AUTO || k.mode == LDD_BATCH_WORKGROUP);
+  return G == 1 ? (k.mode == LDD_ENGINE_WORKGROUP || k.mode == LDD_ENGINE_TEAM)
+                : (k.mode == LDD_BATCH_AUTO || k.mode == LDD_BATCH_WORKGROUP);
 }
 
 std::mutex g_mu;
@@ -181,7 +182,7 @@ extern "C" ldd_status ldd_tune(int32_t num_graphs, const int64_t* vtx_off, const
   // workgroup could compete (at most 2^22 arcs); a batch tries both batch engines
   std::vector<int> modes;
   if (num_graphs == 1) {
-    modes = {LDD_ENGINE_LAUNCH, LDD_ENGINE_PERSISTENT};
+    modes = {LDD_ENGINE_LAUNCH, LDD_ENGINE_PERSISTENT, LDD_ENGINE_TEAM};
     if (nnz <= (1ll << 22)) modes.push_back(LDD_ENGINE_WORKGROUP);
   } else {
     modes = {LDD_BATCH_WORKGROUP, LDD_BATCH_UNION};

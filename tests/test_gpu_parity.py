@@ -37,6 +37,9 @@ MODES = [
     dict(engine=2, blocks=7, direction=2),
     dict(engine=2, tail_vertices=-1),
     dict(engine=2, tail_vertices=1),
+    dict(engine=4),  # a team of workgroups (one per CU) with a device-memory barrier per round
+    dict(engine=4, blocks=7, tail_vertices=1),
+    dict(engine=4, blocks=3, tail_vertices=-1),
 ]
 
 
@@ -183,7 +186,7 @@ def test_batch_graph_kinds_vs_oracle(ldd, kind, n):
     for beta in (0.02, 0.3):
         s = inputs.make_shifts(n, beta, 78)
         want_c, _, want_cut = oracle.decompose(rp, ci, s)
-        for mode in (dict(), dict(engine=3)):
+        for mode in (dict(), dict(engine=3), dict(engine=4)):
             got, cut, _ = run(ldd, rp, ci, s, beta, **mode)
             assert np.array_equal(got, want_c) and cut == want_cut, mode
 
@@ -235,7 +238,7 @@ def test_full_size_rmat24(ldd):
 
 
 def test_full_size_grid3d_256(ldd):
-    full_size(ldd, "grid3d-256", (dict(), dict(engine=1), dict(tail_vertices=-1)))
+    full_size(ldd, "grid3d-256", (dict(), dict(engine=1), dict(tail_vertices=-1), dict(engine=4)))
 
 
 # ------------------------------------------------------------------------------------------
