@@ -20,6 +20,7 @@ shifts, inputs resident in HBM.  Prints one JSON line.
   cpu_baseline the CPU oracle's bucketed search (single-threaded, one core) on the same graph and shifts
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rmat-24]
+                       [--engine E] [--blocks B] [--direction D] [--tail-vertices T]
                        [--no-batch] [--no-serve] [--no-grids] [--no-cpu-baseline] [--copy-probe]
 """
 import argparse
@@ -62,16 +63,19 @@ def kernel_sources_sha():
     return h.hexdigest()
 
 
-def measured_traffic(workload):
-    """HBM bytes per launch of the round kernel from the committed rocprofv3 counter runs,
-    or None when they were taken on other kernel sources or another workload."""
+def measured_traffic(workload, engine=0):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter runs
+    (profiles/traffic_rounds.json: one entry per workload and engine), or None when they were
+    taken on other kernel sources, another workload or another engine."""
     if not os.path.exists(TRAFFIC):
         return None
     with open(TRAFFIC) as f:
         t = json.load(f)
-    if t.get("kernel_sources_sha") != kernel_sources_sha() or t.get("workload") != workload:
-        return None
-    return t.get("bytes_per_launch")
+    sha = kernel_sources_sha()
+    for e in t.get("entries", []):
+        if e.get("workload") == workload and e.get("engine", 0) == engine and e.get("kernel_sources_sha") == sha:
+            return e.get("bytes_per_launch")
+    return None
 
 
 def sha_array(a):
@@ -463,8 +467,10 @@ def run_grid3d(ldd, steps=5):
            "steps": st["steps"], "us_per_step": round(st["ms_rounds"] * 1e3 / max(1, st["steps"]), 2),
            "arcs_examined": st["arcs_examined"],
            "stage_ms": {k: round(st[k], 4) for k in ("ms_prep", "ms_rounds", "ms_finalize", "ms_cut")},
-           "roofline": roofline_block(st, r["n"], {1: "k_rounds_persistent", 3: "k_block_decompose"}.get(
-               r["opts"].get("engine", 0), "k_round_step_lb"), measured_traffic("grid3d-256")),
+           "roofline": roofline_block(st, r["n"], {1: "k_rounds_persistent", 3: "k_block_decompose",
+                                                   4: "k_block_decompose"}.get(r["opts"].get("engine", 0),
+                                                                               "k_round_step_lb"),
+                                      measured_traffic("grid3d-256", r["opts"].get("engine", 0))),
            "tuned": r["opts"], "untuned_ms": round(rep["default_ms"], 3), "tuned_ms": round(rep["best_ms"], 3),
            "bit_exact": r["bit_exact"]}
     log(f"grid3d: {out}")
@@ -569,6 +575,7 @@ def main():
     ap.add_argument("--engine", type=int, default=0)
     ap.add_argument("--direction", type=int, default=0)
     ap.add_argument("--blocks", type=int, default=0)
+    ap.add_argument("--tail-vertices", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the decomposition of one graph "
@@ -580,7 +587,7 @@ def main():
 
     import paper_1307_3692_amd as ldd
 
-    opts = dict(engine=args.engine, direction=args.direction, blocks=args.blocks)
+    opts = dict(engine=args.engine, direction=args.direction, blocks=args.blocks, tail_vertices=args.tail_vertices)
     r = run_single(ldd, args.workload, args.steps, args.warmup, opts)
     stats, n, m = r["stats"], r["n"], r["m"]
     ms_step = r["ms_per_step"]
@@ -608,7 +615,8 @@ def main():
         "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "m": m, "beta": r["beta"], "graph_seed": 1, "shift_seed": 1,
-                   "engine": ["auto(launch)", "persistent", "launch"][args.engine], "parallelism": "single-gpu"},
+                   "engine": {0: "auto", 1: "persistent", 2: "launch", 3: "workgroup", 4: "team"}.get(args.engine, "?"),
+                   "parallelism": "single-gpu"},
         "decompositions_per_s": round(1e3 / ms_step, 3),
         "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 4),
         "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 4),
@@ -618,7 +626,8 @@ def main():
         "arcs_examined": stats["arcs_examined"],
         "examined_arcs_per_s": round(stats["arcs_examined"] / (ms_step * 1e-3), 1),
         "stage_ms": {k: round(stats[k], 4) for k in ("ms_prep", "ms_rounds", "ms_finalize", "ms_cut")},
-        "roofline": roofline_block(stats, n, "k_round_step_lb", measured_traffic(args.workload)),
+        "roofline": roofline_block(stats, n, {1: "k_rounds_persistent", 3: "k_block_decompose", 4: "k_block_decompose"}
+                                   .get(args.engine, "k_round_step_lb"), measured_traffic(args.workload, args.engine)),
     }
     if not args.no_grids:
         out["grid2d"] = run_grid2d(ldd)
