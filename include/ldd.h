@@ -50,7 +50,8 @@ typedef enum {
   LDD_OK = 0,
   LDD_ERR_INVALID_ARG = 1, /* bad pointer, size, CSR content or negative shift            */
   LDD_ERR_OOM = 2,         /* device workspace allocation failed                           */
-  LDD_ERR_OVERFLOW = 3,    /* (Delta + 2^20) << ceil(log2 n) does not fit 64 bits          */
+  LDD_ERR_OVERFLOW = 3,    /* (Delta + 2^20) << ceil(log2 n) does not fit 64 bits, or the */
+                           /* shifts span more rounds than the engine takes                */
   LDD_ERR_HIP = 4,         /* a HIP runtime call failed (text in ldd_last_error)           */
   LDD_ERR_BUDGET = 5,      /* server: request larger than the whole memory budget          */
   LDD_ERR_CANCELLED = 6,   /* server: request cancelled before it ran                      */

@@ -122,6 +122,7 @@ struct Workspace {
   std::vector<StepGraph> graphs;
   int num_cu = 0;
   int max_coresident = 0;  // co-resident blocks of the persistent round kernel
+  int lds_bytes = 0;       // dynamic LDS the workgroup engine may take (0: the device refused the size)
 };
 
 std::mutex g_ws_mu;
@@ -151,6 +152,12 @@ ldd_status ws_setup(Workspace& w) {
     // one block per CU at most: measured co-residency of large cooperative grids falls short
     // of what the occupancy query reports, and barrier cost grows with the block count
     w.max_coresident = w.num_cu * (per_cu < 1 ? 0 : 1);
+    // the workgroup engine's dynamic LDS for small graphs (beside its static LDS)
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(k_block_decompose), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            BLOCK_LDS_BYTES) == hipSuccess)
+      w.lds_bytes = BLOCK_LDS_BYTES;
+    else
+      (void)hipGetLastError();
   }
   ldd_status s;
   if ((s = grow(w.ctrl, sizeof(Ctrl))) || (s = grow(w.st, 2 * sizeof(RoundState))) ||
@@ -651,28 +658,6 @@ static ldd_status block_status(unsigned err, u64 delta, int n) {
   return LDD_OK;
 }
 
-__global__ void k_block_job_single(int n, long long nnz, const int* row_ptr, const int* col, const long long* shift,
-                                   int* centre, u64* P, int* wq, int tail_den, int team, TeamSync* sync,
-                                   BlockJob* job) {
-  if (threadIdx.x || blockIdx.x) return;
-  BlockJob j;
-  j.n = n;
-  j.nnz = nnz;
-  j.row_ptr = row_ptr;
-  j.col = col;
-  j.shift = shift;
-  j.centre = centre;
-  j.P = P;
-  j.wk = (u64*)wq;
-  j.wake = wq;
-  j.q0 = wq + 2 * (long long)n;
-  j.q1 = wq + 3 * (long long)n;
-  j.tail_den = tail_den;
-  j.team = team;
-  j.sync = team > 1 ? sync : nullptr;
-  *job = j;
-}
-
 static int tail_den_of(const ldd_options& o) {
   return o.tail_vertices < 0 ? 0 : (o.tail_vertices > 0 ? o.tail_vertices : 32);
 }
@@ -693,27 +678,60 @@ static ldd_status decompose_block(Workspace& w, const ldd_csr* g, const int64_t*
   }
   ldd_status s = ws_setup(w);
   if (s != LDD_OK) return s;
-  if ((s = grow(w.P, nv * 8)) || (s = grow(w.bk_wq, nv * 16)) || (s = grow(w.bk_jobs, sizeof(BlockJob))) ||
-      (s = grow(w.bk_out, sizeof(BlockOut))) || (s = grow(w.bk_cnt, 8)) || (s = grow(w.bk_sync, sizeof(TeamSync))))
+  if ((s = grow(w.P, nv * 8)) || (s = grow(w.bk_wq, nv * 16)) || (s = grow(w.bk_out, sizeof(BlockOut))) ||
+      (s = grow(w.bk_sync, sizeof(TeamSync))))
     return s;
+  // the job, by value: one kernel launch in all (a team's record is cleared by a fill before it)
+  BlockJob j{};
+  j.n = n;
+  j.nnz = g->nnz;
+  j.row_ptr = g->row_ptr;
+  j.col = g->col_idx;
+  j.shift = (const long long*)shift_fix;
+  j.centre = centre;
+  j.P = (u64*)w.P.p;
+  j.wk = (u64*)w.bk_wq.p;
+  j.wake = (int*)w.bk_wq.p;
+  j.q0 = (int*)w.bk_wq.p + 2 * (long long)n;
+  j.q1 = (int*)w.bk_wq.p + 3 * (long long)n;
+  j.tail_den = tail_den_of(opt);
+  j.team = K;
+  j.sync = K > 1 ? (TeamSync*)w.bk_sync.p : nullptr;
+  // the dynamic LDS the graph's mode needs (the label-correcting iteration, or the rounds in LDS)
+  long long lds = 0;
+  if (K == 1 && fix_lds_bytes(n, g->nnz) <= w.lds_bytes) lds = fix_lds_bytes(n, g->nnz);
+  else if (K == 1 && rounds_lds_bytes(n) <= w.lds_bytes) lds = rounds_lds_bytes(n);
+  const int lds_bytes = (int)((lds + 15) & ~15ll);
   HIP_TRY(hipStreamWaitEvent(st, w.ev[2], 0));  // after any step a previous call left queued
-  HIP_TRY(hipEventRecord(w.ev[0], st));
-  hipLaunchKernelGGL(k_block_job_single, dim3(1), dim3(64), 0, st, n, (long long)g->nnz, g->row_ptr, g->col_idx,
-                     (const long long*)shift_fix, centre, (u64*)w.P.p, (int*)w.bk_wq.p, tail_den_of(opt), K,
-                     (TeamSync*)w.bk_sync.p, (BlockJob*)w.bk_jobs.p);
-  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, (u64*)w.bk_cnt.p, 1ll, 0ull);
+  if (stats) HIP_TRY(hipEventRecord(w.ev[0], st));
   if (K > 1)
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(256), 0, st, (u64*)w.bk_sync.p, (long long)(sizeof(TeamSync) / 8),
                        0ull);
-  HIP_TRY(hipEventRecord(w.ev[1], st));
-  // no job list: job k is member k of graph 0
-  hipLaunchKernelGGL(k_block_decompose, dim3(K), dim3(1024), 0, st, (const BlockJob*)w.bk_jobs.p,
-                     (const TeamJob*)nullptr, K, (unsigned*)w.bk_cnt.p, (BlockOut*)w.bk_out.p);
+  if (stats) HIP_TRY(hipEventRecord(w.ev[1], st));
+  // the result record goes straight to mapped host memory; the host waits for its ready flag (or
+  // for the stream, if the kernel ended without setting it)
+  void* bout_dev = nullptr;
+  HIP_TRY(hipHostGetDevicePointer(&bout_dev, &w.host->bout, 0));
+  volatile BlockOut* vb = &w.host->bout;
+  vb->ready = 0;
+  hipLaunchKernelGGL(k_block_decompose, dim3(K), dim3(1024), (size_t)lds_bytes, st, (const BlockJob*)nullptr,
+                     (const TeamJob*)nullptr, K, (unsigned*)nullptr, (BlockOut*)bout_dev, j, lds_bytes);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipEventRecord(w.ev[2], st));
-  HIP_TRY(hipMemcpyAsync(&w.host->bout, w.bk_out.p, sizeof(BlockOut), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  const BlockOut o = w.host->bout;
+  for (unsigned spin = 0; !vb->ready; ++spin) {
+    if ((spin & 255) == 255) {
+      const hipError_t q = hipEventQuery(w.ev[2]);
+      if (q == hipSuccess) break;
+      if (q != hipErrorNotReady) HIP_TRY(q);
+    }
+  }
+  if (!vb->ready) {
+    ldd_set_error("the workgroup engine ended without a result");
+    return LDD_ERR_HIP;
+  }
+  if (stats) HIP_TRY(hipEventSynchronize(w.ev[2]));
+  BlockOut o;
+  std::memcpy(&o, (const void*)vb, sizeof(BlockOut));
   w.host->report.delta = o.delta;  // read by the verification pass
   s = block_status(o.err, o.delta, n);
   if (s != LDD_OK) return s;
@@ -940,8 +958,12 @@ ldd_status ldd_batch_workgroup(int32_t G, const int64_t* vtx_off, const int64_t*
       hipLaunchKernelGGL(k_fill_u64, dim3(grid_for((long long)nteams * sizeof(TeamSync) / 8, 256, 1024)), dim3(256), 0,
                          st, (u64*)w.bk_sync.p, (long long)nteams * (long long)(sizeof(TeamSync) / 8), 0ull);
     if (grid > njobs) grid = njobs;
-    hipLaunchKernelGGL(k_block_decompose, dim3(grid), dim3(1024), 0, st, (const BlockJob*)w.bk_jobs.p,
-                       (const TeamJob*)w.bk_order.p, njobs, (unsigned*)w.bk_cnt.p, (BlockOut*)w.bk_out.p);
+    // small graphs keep their state in LDS when the grid is one workgroup per CU (the LDS then costs
+    // no residency: one workgroup of 1024 threads per CU either way)
+    const int lds_bytes = grid <= w.num_cu ? w.lds_bytes : 0;
+    hipLaunchKernelGGL(k_block_decompose, dim3(grid), dim3(1024), (size_t)lds_bytes, st, (const BlockJob*)w.bk_jobs.p,
+                       (const TeamJob*)w.bk_order.p, njobs, (unsigned*)w.bk_cnt.p, (BlockOut*)w.bk_out.p, BlockJob{},
+                       lds_bytes);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(w.ev[2], st));
     std::vector<BlockOut> outs((size_t)G);

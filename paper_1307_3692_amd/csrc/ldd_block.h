@@ -9,6 +9,15 @@ namespace ldd {
 // or more (floor(Delta / 2^20) >= BLOCK_WCAP) are left to the multi-block engine
 constexpr int BLOCK_WCAP = 4096;
 
+// Dynamic LDS a launch of the workgroup engine may give each workgroup for a small graph run alone:
+// when its labels and CSR fit (8 B per vertex, 4 B per row offset and per arc) the whole
+// decomposition is a label-correcting iteration in LDS (block_graph_fix); else, when its labels,
+// wake order and queues fit (24 B per vertex), the rounds run on them in LDS (block_graph_lds).
+// Either way its labels are copied to the graph's label array at the end.
+constexpr int BLOCK_LDS_BYTES = 116 * 1024;
+__host__ __device__ constexpr long long fix_lds_bytes(long long n, long long nnz) { return 12 * n + 4 * nnz + 4; }
+__host__ __device__ constexpr long long rounds_lds_bytes(long long n) { return 24 * n; }
+
 // error bits of a workgroup job beyond ERR_*: the labels would not fit 64 bits; the shift range
 // needs more wake buckets than the workgroup sorts
 enum : unsigned { BLK_OVERFLOW = 64u, BLK_WIDE = 128u };
@@ -72,6 +81,7 @@ struct BlockOut {
   u64 examined;   // arcs read by the rounds, the seed and the sweeps
   u64 t_begin;    // device wall clock (constant-rate counter) when the workgroup took the graph
   u64 t_end;      // ... and when it finished it
+  unsigned ready; // one graph without a job list: set last, at system scope (the host waits for it)
 };
 
 // One job of the kernel's list: graph g, member m of its team.
@@ -79,7 +89,11 @@ struct TeamJob {
   int g, m;
 };
 
-__global__ void k_block_decompose(const BlockJob* jobs, const TeamJob* order, int njobs, unsigned* next_job, BlockOut* outs);
+// order != NULL: workgroups take jobs (order[k], njobs of them) from *next_job; order == NULL: one
+// job per workgroup, member blockIdx.x of the graph `single`.  lds_bytes: the launch's dynamic LDS
+// per workgroup (0: none).
+__global__ void k_block_decompose(const BlockJob* jobs, const TeamJob* order, int njobs, unsigned* next_job, BlockOut* outs,
+                                  BlockJob single, int lds_bytes);
 __global__ void k_block_jobs(int G, long long N, const long long* vo, const long long* ao, const int* row_ptr,
                              const int* col, const long long* shift, int* centre, u64* P, int* wq, int tail_den,
                              const int* team, TeamSync* sync, BlockJob* jobs);

@@ -545,6 +545,8 @@ __device__ __attribute__((noinline)) void block_output(const BlockJob& j, BlockS
   }
 }
 
+extern __shared__ __attribute__((aligned(16))) unsigned char blk_dyn[];  // the launch's dynamic LDS
+
 // One graph, the whole workgroup.
 __device__ void block_graph(const BlockJob& j, BlockShared& sh, BlockOut* out) {
   block_prepare(j, sh);
@@ -557,6 +559,134 @@ __device__ void block_graph(const BlockJob& j, BlockShared& sh, BlockOut* out) {
   }
   block_rounds(j, sh);
   block_output(j, sh, out);
+}
+
+// One small graph, the whole workgroup, with its labels, wake order and queues in the dynamic LDS
+// (P: 8 B, wake order: 8 B, queues: 2 x 4 B per vertex); the same code reaches them through
+// generic pointers.  The labels are copied to the graph's label array at the end.
+__device__ void block_graph_lds(const BlockJob& j, BlockShared& sh, BlockOut* out) {
+  const int n = j.n;
+  BlockJob l = j;
+  u64* base = reinterpret_cast<u64*>(blk_dyn);
+  l.P = base;
+  l.wk = base + n;
+  l.wake = reinterpret_cast<int*>(l.wk);
+  l.q0 = reinterpret_cast<int*>(base + 2 * (long long)n);
+  l.q1 = l.q0 + n;
+  block_graph(l, sh, out);
+  __syncthreads();
+  for (int v = threadIdx.x; v < n; v += BT) j.P[v] = l.P[v];
+}
+
+// One small graph whose labels and CSR fit the dynamic LDS, the whole workgroup: every vertex
+// starts from its own label ((Delta - shift) << B) | v and the labels are relaxed,
+// P(v) = min(P(v), min over arcs (v, u) of P(u) + unit), in place, until a pass lowers none.
+// That is the unique fixpoint the rounds reach (the minimum over centres of the shifted
+// distance, ties to the smaller centre; Sec. 5's search, by label correction from every source at
+// once), so the result is the same; no wake buckets, frontier or queue, and every access but
+// the first loads of the CSR and shifts stays in LDS.  A pass costs about n / 1024 vertices per
+// thread; there are at most as many passes as the largest number of hops from a vertex to its
+// centre, plus one (fewer, since labels lowered early in a pass are read later in the same pass).
+// Labels are 8-byte LDS words written whole, so a concurrent read sees the old or the new label.
+__device__ __attribute__((noinline)) void block_graph_fix(const BlockJob& j, BlockShared& sh, BlockOut* out) {
+  const int n = j.n;
+  const long long nnz = j.nnz;
+  const int* __restrict__ rp = j.row_ptr;
+  const int* __restrict__ col = j.col;
+  const long long* __restrict__ shift = j.shift;
+  const int tid = threadIdx.x;
+  u64* P = reinterpret_cast<u64*>(blk_dyn);
+  int* lrp = reinterpret_cast<int*>(P + n);
+  int* lcol = lrp + n + 1;
+  if (tid == 0) sh.err = 0;
+  __syncthreads();
+  unsigned err = 0;
+  u64 dmax = 0, active = 0;
+  if (tid == 0 && n > 0 && (rp[0] != 0 || (long long)rp[n] != nnz)) err |= ERR_BAD_ROWPTR;
+  for (int v = tid; v <= n; v += BT) {
+    const int a0 = rp[v];
+    lrp[v] = a0;
+    if (v == n) break;
+    const int a1 = rp[v + 1];
+    const long long s = shift[v];
+    if (s < 0 || s > (1ll << 52)) err |= ERR_BAD_SHIFT;
+    if (a1 < a0) err |= ERR_BAD_ROWPTR;
+    active += a1 > a0;
+    dmax = (u64)s > dmax ? (u64)s : dmax;
+  }
+  for (long long a = tid; a < nnz; a += BT) {
+    const int c = col[a];
+    if ((unsigned)c >= (unsigned)n) err |= ERR_BAD_COL;
+    lcol[a] = c;
+  }
+  if (err) atomicOr(&sh.err, err);
+  const u64 delta = block_max64(dmax, sh);
+  const u64 n_active = block_sum64(active, sh);
+  const int B = n > 1 ? 32 - __builtin_clz((unsigned)(n - 1)) : 1;
+  __syncthreads();
+  if (tid == 0) {
+    unsigned e = sh.err;
+    if (!e && (delta + ((u64)1 << FIX)) >= ((u64)1 << (64 - B))) e |= BLK_OVERFLOW;
+    sh.err = e;
+  }
+  __syncthreads();
+  if (sh.err) {
+    if (tid == 0) {
+      out->err = sh.err;
+      out->delta = delta;
+    }
+    return;
+  }
+  for (int v = tid; v < n; v += BT) P[v] = ((delta - (u64)shift[v]) << B) | (u64)v;
+  __syncthreads();
+  const u64 unit = (u64)1 << (FIX + B);
+  long long passes = 0;
+  for (;;) {
+    int changed = 0;
+    // every other pass walks the vertices from the top: a label then travels far in both
+    // directions of the id order within one pass
+    const bool down = passes & 1;
+    for (int i = tid; i < n; i += BT) {
+      const int v = down ? n - 1 - i : i;
+      const u64 p = P[v];
+      u64 best = p;
+      const int a1 = lrp[v + 1];
+      for (int a = lrp[v]; a < a1; ++a) {
+        const u64 q = P[lcol[a]] + unit;
+        best = q < best ? q : best;
+      }
+      if (best < p) {
+        P[v] = best;
+        changed = 1;
+      }
+    }
+    ++passes;
+    if (!__syncthreads_or(changed) || passes > (long long)n + 1) break;
+  }
+  // centres, pieces, cut; the labels to the graph's label array
+  const u64 mask = ((u64)1 << B) - 1;
+  u64 cut2 = 0, pieces = 0;
+  for (int v = tid; v < n; v += BT) {
+    const u64 p = P[v];
+    const int c = (int)(p & mask);
+    j.centre[v] = c;
+    j.P[v] = p;
+    pieces += c == v;
+    const int a1 = lrp[v + 1];
+    for (int a = lrp[v]; a < a1; ++a) cut2 += (int)(P[lcol[a]] & mask) != c;
+  }
+  cut2 = block_sum64(cut2, sh);
+  pieces = block_sum64(pieces, sh);
+  if (tid == 0) {
+    out->err = passes > (long long)n + 1 ? (unsigned)ERR_WATCHDOG : 0u;
+    out->cut_arcs = cut2;
+    out->pieces = pieces;
+    out->delta = delta;
+    out->n_active = n_active;
+    out->rounds = passes;
+    out->sweeps = 0;
+    out->examined = (u64)passes * (u64)nnz;
+  }
 }
 
 // ---- a team of workgroups on one graph ----------------------------------------------------
@@ -912,29 +1042,49 @@ __device__ void team_graph(const BlockJob& j, BlockShared& sh, BlockOut* out, in
 }  // namespace
 
 // (BT, 8): eight waves per SIMD, two workgroups per CU (at most 64 VGPRs).
-// Each workgroup takes the next job of `order` (a graph, or one member of a graph's team) from
-// the shared counter until none is left.
+// With a job list each workgroup takes the next job of `order` (a graph, or one member of a
+// graph's team) from the shared counter until none is left; without one, block b runs member b of
+// the single graph.
 // A team's members are consecutive jobs: a member that starts early waits at the team's first
 // barrier for workgroups that finish their current job, which every resident workgroup does, so
 // the team size must not exceed the resident workgroups (the host keeps it within the grid).
 __global__ __launch_bounds__(BT, 8) void k_block_decompose(const BlockJob* __restrict__ jobs,
                                                            const TeamJob* __restrict__ order, int njobs,
-                                                           unsigned* next_job, BlockOut* outs) {
+                                                           unsigned* next_job, BlockOut* outs, BlockJob single,
+                                                           int lds_bytes) {
   __shared__ BlockShared sh;
   for (;;) {
-    if (threadIdx.x == 0) sh.job = (int)atomicAdd(next_job, 1u);
-    __syncthreads();
-    const int k = sh.job;
-    __syncthreads();
-    if (k >= njobs) return;
-    const int g = order ? order[k].g : 0;  // no list: job k is member k of graph 0
-    const int m = order ? order[k].m : k;
+    int g = 0, m = (int)blockIdx.x;
+    if (order) {
+      if (threadIdx.x == 0) sh.job = (int)atomicAdd(next_job, 1u);
+      __syncthreads();
+      const int k = sh.job;
+      __syncthreads();
+      if (k >= njobs) return;
+      g = order[k].g;
+      m = order[k].m;
+    }
+    const BlockJob& j = order ? jobs[g] : single;
     const u64 t0 = wall_clock64();
-    if (jobs[g].team > 1) team_graph(jobs[g], sh, &outs[g], m);
-    else block_graph(jobs[g], sh, &outs[g]);
+    if (j.team > 1) team_graph(j, sh, &outs[g], m);
+    else if (fix_lds_bytes(j.n, j.nnz) <= lds_bytes) block_graph_fix(j, sh, &outs[g]);
+    else if (rounds_lds_bytes(j.n) <= lds_bytes) block_graph_lds(j, sh, &outs[g]);
+    else block_graph(j, sh, &outs[g]);
     if (threadIdx.x == 0 && m == 0) {
       outs[g].t_begin = t0;
       outs[g].t_end = wall_clock64();
+    }
+    if (!order) {
+      // one graph: member 0 announces the result once every write of its workgroup (centres,
+      // labels, the result record) has completed; the other members' writes completed before
+      // they arrived at the team's last barrier
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      if (threadIdx.x == 0 && m == 0) {
+        __threadfence_system();
+        __hip_atomic_store(&outs[0].ready, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
+      return;
     }
     __syncthreads();
   }
