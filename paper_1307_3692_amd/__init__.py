@@ -243,8 +243,11 @@ def decompose(row_ptr, col_idx, shift_fix, beta: float, *, centre=None, stream=N
     cut = ctypes.c_int64(0)
     st = Stats()
     o = make_options(**opts)
+    # statistics only when asked for: they add a pass over the labels (the largest distance to a
+    # centre) and a synchronisation
     _check(lib().ldd_decompose(ctypes.byref(g), shift_fix.data_ptr(), float(beta), centre.data_ptr(),
-                               ctypes.byref(cut), ctypes.byref(o), ctypes.byref(st), _stream_handle(stream)))
+                               ctypes.byref(cut), ctypes.byref(o), ctypes.byref(st) if stats else None,
+                               _stream_handle(stream)))
     if stats:
         return centre, int(cut.value), st.as_dict()
     return centre, int(cut.value)
