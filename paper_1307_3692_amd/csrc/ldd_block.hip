@@ -586,7 +586,8 @@ __device__ void block_graph_lds(const BlockJob& j, BlockShared& sh, BlockOut* ou
 // once), so the result is the same; no wake buckets, frontier or queue, and every access but
 // the first loads of the CSR and shifts stays in LDS.  A pass costs about n / 1024 vertices per
 // thread; there are at most as many passes as the largest number of hops from a vertex to its
-// centre, plus one (fewer, since labels lowered early in a pass are read later in the same pass).
+// centre, plus one block of passes (fewer, since labels lowered early in a pass are read later in
+// the same pass).
 // Labels are 8-byte LDS words written whole, so a concurrent read sees the old or the new label.
 __device__ __attribute__((noinline)) void block_graph_fix(const BlockJob& j, BlockShared& sh, BlockOut* out) {
   const int n = j.n;
@@ -640,28 +641,34 @@ __device__ __attribute__((noinline)) void block_graph_fix(const BlockJob& j, Blo
   for (int v = tid; v < n; v += BT) P[v] = ((delta - (u64)shift[v]) << B) | (u64)v;
   __syncthreads();
   const u64 unit = (u64)1 << (FIX + B);
+  // Passes run FIX_BLOCK at a time with no barrier between them (in-place relaxation is exact in
+  // any interleaving); a block of passes in which no thread lowered any label read only final
+  // labels, so the labels are the fixpoint.
+  constexpr int FIX_BLOCK = 4;
   long long passes = 0;
+  bool converged = false;
+  const int* __restrict__ rrp = lrp;   // the CSR in LDS is never written during the passes
+  const int* __restrict__ rcol = lcol;
   for (;;) {
     int changed = 0;
-    // every other pass walks the vertices from the top: a label then travels far in both
-    // directions of the id order within one pass
-    const bool down = passes & 1;
-    for (int i = tid; i < n; i += BT) {
-      const int v = down ? n - 1 - i : i;
-      const u64 p = P[v];
-      u64 best = p;
-      const int a1 = lrp[v + 1];
-      for (int a = lrp[v]; a < a1; ++a) {
-        const u64 q = P[lcol[a]] + unit;
-        best = q < best ? q : best;
-      }
-      if (best < p) {
-        P[v] = best;
-        changed = 1;
+    for (int k = 0; k < FIX_BLOCK; ++k) {
+      for (int v = tid; v < n; v += BT) {
+        const int a0 = rrp[v], a1 = rrp[v + 1];
+        const u64 p = P[v];
+        u64 best = p;
+        for (int a = a0; a < a1; ++a) {
+          const u64 q = P[rcol[a]] + unit;
+          best = q < best ? q : best;
+        }
+        if (best < p) {
+          P[v] = best;
+          changed = 1;
+        }
       }
     }
-    ++passes;
-    if (!__syncthreads_or(changed) || passes > (long long)n + 1) break;
+    passes += FIX_BLOCK;
+    converged = !__syncthreads_or(changed);
+    if (converged || passes > (long long)n + 1 + FIX_BLOCK) break;
   }
   // centres, pieces, cut; the labels to the graph's label array
   const u64 mask = ((u64)1 << B) - 1;
@@ -678,7 +685,7 @@ __device__ __attribute__((noinline)) void block_graph_fix(const BlockJob& j, Blo
   cut2 = block_sum64(cut2, sh);
   pieces = block_sum64(pieces, sh);
   if (tid == 0) {
-    out->err = passes > (long long)n + 1 ? (unsigned)ERR_WATCHDOG : 0u;
+    out->err = converged ? 0u : (unsigned)ERR_WATCHDOG;
     out->cut_arcs = cut2;
     out->pieces = pieces;
     out->delta = delta;
