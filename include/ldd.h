@@ -72,7 +72,7 @@ typedef struct {
 enum { LDD_DIR_AUTO = 0, LDD_DIR_TOP_DOWN = 1, LDD_DIR_BOTTOM_UP = 2 };
 /* Round engine: one persistent kernel with grid barriers, one launch per round step over the
  * whole GPU, one workgroup running every round of the graph (workgroup barriers only), or a team
- * of workgroups (blocks of them, default one per CU, at most two per CU) running every round with
+ * of workgroups (blocks of them, default one per CU, at most the workgroups that can be resident at once) running every round with
  * one barrier in device memory per round (top-down only: for large graphs of low degree and many
  * rounds, such as grids).  AUTO takes the workgroup engine for graphs of at most 2^15 arcs and
  * the launch engine otherwise; ldd_tune may pick any of them. */

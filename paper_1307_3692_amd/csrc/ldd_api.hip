@@ -122,6 +122,7 @@ struct Workspace {
   std::vector<StepGraph> graphs;
   int num_cu = 0;
   int max_coresident = 0;  // co-resident blocks of the persistent round kernel
+  int block_coresident = 0;  // co-resident workgroups of the workgroup engine (a team's bound)
   int lds_bytes = 0;       // dynamic LDS the workgroup engine may take (0: the device refused the size)
 };
 
@@ -152,6 +153,10 @@ ldd_status ws_setup(Workspace& w) {
     // one block per CU at most: measured co-residency of large cooperative grids falls short
     // of what the occupancy query reports, and barrier cost grows with the block count
     w.max_coresident = w.num_cu * (per_cu < 1 ? 0 : 1);
+    int per_cu_block = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_block, reinterpret_cast<const void*>(k_block_decompose),
+                                                         1024, 0));
+    w.block_coresident = w.num_cu * std::max(per_cu_block, 1);
     // the workgroup engine's dynamic LDS for small graphs (beside its static LDS)
     if (hipFuncSetAttribute(reinterpret_cast<const void*>(k_block_decompose), hipFuncAttributeMaxDynamicSharedMemorySize,
                             BLOCK_LDS_BYTES) == hipSuccess)
@@ -663,8 +668,8 @@ static int tail_den_of(const ldd_options& o) {
 }
 
 // One graph on the workgroup engine: one workgroup (WORKGROUP), or a team of K workgroups
-// (TEAM: blocks of them, default one per CU, at most the two per CU that can be resident, at least
-// 64 vertices per member) meeting at a device-memory barrier once per round.
+// (TEAM: blocks of them, default one per CU, at most the workgroups that can be resident at once, at
+// least 64 vertices per member) meeting at a device-memory barrier once per round.
 static ldd_status decompose_block(Workspace& w, const ldd_csr* g, const int64_t* shift_fix, int32_t* centre,
                                   int64_t* cut_edges, const ldd_options& opt, ldd_stats* stats, hipStream_t st) {
   const int n = g->n;
@@ -672,7 +677,7 @@ static ldd_status decompose_block(Workspace& w, const ldd_csr* g, const int64_t*
   int K = 1;
   if (opt.engine == LDD_ENGINE_TEAM) {
     K = opt.blocks > 0 ? opt.blocks : w.num_cu;
-    K = std::min(K, std::min(2 * w.num_cu, TEAM_GROUP * TEAM_GROUPS));
+    K = std::min(K, std::min(w.block_coresident, TEAM_GROUP * TEAM_GROUPS));
     K = std::min(K, n / 64);
     K = std::max(K, 1);
   }

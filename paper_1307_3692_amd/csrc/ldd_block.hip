@@ -1048,14 +1048,15 @@ __device__ void team_graph(const BlockJob& j, BlockShared& sh, BlockOut* out, in
 
 }  // namespace
 
-// (BT, 8): eight waves per SIMD, two workgroups per CU (at most 64 VGPRs).
+// (BT, 4): four waves per SIMD, one workgroup per CU, up to 128 VGPRs (at 64, the bound that two
+// workgroups per CU would need, the team and round loops spilled to scratch).
 // With a job list each workgroup takes the next job of `order` (a graph, or one member of a
 // graph's team) from the shared counter until none is left; without one, block b runs member b of
 // the single graph.
 // A team's members are consecutive jobs: a member that starts early waits at the team's first
 // barrier for workgroups that finish their current job, which every resident workgroup does, so
 // the team size must not exceed the resident workgroups (the host keeps it within the grid).
-__global__ __launch_bounds__(BT, 8) void k_block_decompose(const BlockJob* __restrict__ jobs,
+__global__ __launch_bounds__(BT, 4) void k_block_decompose(const BlockJob* __restrict__ jobs,
                                                            const TeamJob* __restrict__ order, int njobs,
                                                            unsigned* next_job, BlockOut* outs, BlockJob single,
                                                            int lds_bytes) {
