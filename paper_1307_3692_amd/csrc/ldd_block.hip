@@ -122,12 +122,18 @@ __device__ __forceinline__ int next_nonempty(BlockShared& sh, int r, int D) {
 
 // A graph's labels are touched by its own workgroup only while it runs, so their loads and atomics
 // need workgroup scope alone (all waves of a workgroup share one CU and its vector L1).  A team's
-// labels are shared by its members' CUs: their atomics (the claims) take device scope, while
-// their loads stay at workgroup scope and may hit the CU's caches.  A load that decides something
-// (an offer, a frontier test in the seed, a centre) reads a label that was final at the last team
-// barrier, whose acquire invalidated the caches; a load that only filters atomics (is the label
-// still larger than the offer?) may see an older value, which is never smaller (labels only
-// decrease), so at worst it lets through an atomic that finds nothing to do.
+// labels are shared by its members' CUs, which may sit on different XCDs, each with its own L2.
+// Within the rounds every access another member may read or write is itself coherent at device
+// scope: the claims are device-scope atomics, the queue entries device-scope stores and loads, and
+// the loads that decide something (an offer, a queue entry) device-scope loads; so the per-round
+// barrier only has to wait for the member's own accesses to complete, with no L2 writeback or
+// invalidation (which would also drop the cached CSR every round).  A label load that only filters
+// atomics (is the label still larger than the offer?) stays at workgroup scope and may see an
+// older value, which is never smaller (labels only decrease, and the preparation's barriers,
+// which do write back and invalidate, order every cached copy after the labels' initialisation),
+// so at worst it lets through an atomic that finds nothing to do.  The phases that use plain
+// loads and stores on shared data (preparation, the tail's seed, the output) are bracketed by
+// barriers or fences that do write back and invalidate.
 constexpr int WG = __HIP_MEMORY_SCOPE_WORKGROUP;
 constexpr int AG = __HIP_MEMORY_SCOPE_AGENT;
 
@@ -167,7 +173,8 @@ __device__ __forceinline__ void team_flush(BlockShared& sh, int* next, u64* gcnt
     sh.tcount += c;
   }
   __syncthreads();
-  for (unsigned i = threadIdx.x; i < c; i += BT) next[sh.tbase + i] = sh.tbuf[i];
+  for (unsigned i = threadIdx.x; i < c; i += BT)
+    __hip_atomic_store(&next[sh.tbase + i], sh.tbuf[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
   if (threadIdx.x == 0) sh.bn = 0;
   __syncthreads();
@@ -186,7 +193,8 @@ struct TeamAppend {
     if (i < TB_CAP) {
       sh->tbuf[i] = v;
     } else {
-      next[__hip_atomic_fetch_add(gcnt, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)] = v;
+      __hip_atomic_store(&next[__hip_atomic_fetch_add(gcnt, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)], v,
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       atomicAdd(&sh->tcount, 1u);
     }
   }
@@ -370,11 +378,19 @@ __device__ __forceinline__ u64 expand_frontier(const BlockJob& j, BlockShared& s
     const unsigned e = c0 + threadIdx.x;
     unsigned deg = 0;
     if (e < e1) {
-      const int u = cur[e];
-      const int a0 = rp[u], a1 = rp[u + 1];
-      deg = (unsigned)(a1 - a0);
-      sh.first[threadIdx.x] = a0;
-      sh.offer[threadIdx.x] = wg_load(&j.P[u]) + unit;
+      // a team's queue entries and offers: device-scope loads (the round's barrier invalidates nothing)
+      int u;
+      if constexpr (SC == AG) u = __hip_atomic_load(const_cast<int*>(&cur[e]), __ATOMIC_RELAXED, AG);
+      else u = cur[e];
+      if (SC == WG || (unsigned)u < (unsigned)j.n) {  // a team's entries are checked (never out of range)
+        const u64 pu = SC == AG ? lab_load<AG>(&j.P[u]) : wg_load(&j.P[u]);
+        const int a0 = rp[u], a1 = rp[u + 1];
+        deg = (unsigned)(a1 - a0);
+        sh.first[threadIdx.x] = a0;
+        sh.offer[threadIdx.x] = pu + unit;
+      } else {
+        atomicOr(&sh.err, ERR_QUEUE);
+      }
     }
     unsigned total;
     const unsigned ex = block_excl_scan(deg, sh, &total);
@@ -719,11 +735,17 @@ __device__ __forceinline__ void team_clear_next(BlockShared& sh) {
 // team's word, and the team's last arrival publishes the step's queue length (the sum of the
 // appends; 0xffffffff if any member had an error) with the barrier's number in gen, which the
 // others wait for.  In a team of at most TEAM_GROUP members the arrivals go to the team's word
-// directly.  Arrivals are acquire-release read-modify-writes and gen a release store, so every
-// write of the members before the barrier (labels, queue entries, stamps, counters) is visible
-// after the acquire that follows the wait.  A bounded wait raises ERR_BARRIER instead of hanging.
-// Returns the queue length; after an error every member ORs the team's error bits into sh.err.
+// directly.  full: arrivals are acquire-release read-modify-writes, gen a release store and the
+// wait ends with an acquire, so every plain write of the members before the barrier is visible to
+// plain loads after it (each member writes back and invalidates its L2).  Otherwise everything is
+// relaxed: the members' shared accesses are device-scope themselves and complete before the
+// arrival (the waits above), and every load after the barrier is issued after the wait observed
+// gen.  A bounded wait raises ERR_BARRIER instead of hanging.  Returns the queue length; after an
+// error every member ORs the team's error bits into sh.err.
+template <bool FULL>
 __device__ unsigned team_barrier(BlockShared& sh) {
+  constexpr int RMW = FULL ? __ATOMIC_ACQ_REL : __ATOMIC_RELAXED;
+  constexpr int PUB = FULL ? __ATOMIC_RELEASE : __ATOMIC_RELAXED;
   team_clear_next(sh);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
@@ -740,14 +762,14 @@ __device__ unsigned team_barrier(BlockShared& sh) {
     bool last = false;
     u64 sum = 0;
     if (ng == 1) {
-      const u64 old = __hip_atomic_fetch_add(&ts->tw[slot].v, mine, __ATOMIC_ACQ_REL, AG);
+      const u64 old = __hip_atomic_fetch_add(&ts->tw[slot].v, mine, RMW, AG);
       last = (old >> 42) + 1 == K;
       sum = (old & SUMS) + (mine & SUMS);
     } else {
-      const u64 old = __hip_atomic_fetch_add(&ts->gw[slot][g].v, mine, __ATOMIC_ACQ_REL, AG);
+      const u64 old = __hip_atomic_fetch_add(&ts->gw[slot][g].v, mine, RMW, AG);
       if ((old >> 42) + 1 == in_g) {
         const u64 grp = ONE | ((old & SUMS) + (mine & SUMS));
-        const u64 top = __hip_atomic_fetch_add(&ts->tw[slot].v, grp, __ATOMIC_ACQ_REL, AG);
+        const u64 top = __hip_atomic_fetch_add(&ts->tw[slot].v, grp, RMW, AG);
         last = (top >> 42) + 1 == ng;
         sum = (top & SUMS) + (grp & SUMS);
       }
@@ -756,7 +778,7 @@ __device__ unsigned team_barrier(BlockShared& sh) {
     if (last) {
       const unsigned nf = (sum >> 32) ? 0xffffffffu : (unsigned)sum;
       word = ((u64)nf << 32) | e1;
-      __hip_atomic_store(&ts->gen, word, __ATOMIC_RELEASE, AG);
+      __hip_atomic_store(&ts->gen, word, PUB, AG);
     } else {
       unsigned spins = 0;
       while ((unsigned)(word = __hip_atomic_load(&ts->gen, __ATOMIC_RELAXED, AG)) < e1) {
@@ -768,7 +790,7 @@ __device__ unsigned team_barrier(BlockShared& sh) {
         }
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (FULL) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     unsigned nf = (unsigned)(word >> 32);
     if (nf == 0xffffffffu) {
       const unsigned e = __hip_atomic_load(&ts->err, __ATOMIC_RELAXED, AG);
@@ -785,11 +807,19 @@ __device__ unsigned team_barrier(BlockShared& sh) {
 
 // End of a member's step: its staged appends go to the shared queue `next`, then the barrier,
 // which returns the queue's length, the same in every member (all threads call).
+template <bool FULL>
 __device__ unsigned team_round_end(BlockShared& sh, int* next, u64* gcnt) {
   __syncthreads();
   const unsigned c = sh.bn < TB_CAP ? sh.bn : TB_CAP;
   if (c) team_flush(sh, next, gcnt, c);
-  return team_barrier(sh);
+  return team_barrier<FULL>(sh);
+}
+
+// Before plain loads of labels that other members wrote since the last full barrier: an acquire
+// that invalidates this CU's L1 and its XCD's L2 (all threads call).
+__device__ __forceinline__ void team_acquire() {
+  if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  __syncthreads();
 }
 
 // The first non-empty wake bucket of the whole graph at or after r, from the bitmap sh.nz (D + n +
@@ -830,7 +860,7 @@ __device__ __attribute__((noinline)) void team_prepare(const BlockJob& j, BlockS
     if (active) __hip_atomic_fetch_add(&ts->active, active, __ATOMIC_RELAXED, AG);
     if (sh.err) __hip_atomic_fetch_or(&ts->err, sh.err, __ATOMIC_RELAXED, AG);
   }
-  team_barrier(sh);
+  team_barrier<true>(sh);
   const u64 delta = __hip_atomic_load(&ts->delta, __ATOMIC_RELAXED, AG);
   const u64 n_active = __hip_atomic_load(&ts->active, __ATOMIC_RELAXED, AG);
   unsigned e = __hip_atomic_load(&ts->err, __ATOMIC_RELAXED, AG);
@@ -852,7 +882,7 @@ __device__ __attribute__((noinline)) void team_prepare(const BlockJob& j, BlockS
     }
     if (bits) __hip_atomic_fetch_or(&ts->nz[tid], bits, __ATOMIC_RELAXED, AG);
   }
-  team_barrier(sh);
+  team_barrier<true>(sh);
   if (tid < BLOCK_WCAP / 64) sh.nz[tid] = __hip_atomic_load(&ts->nz[tid], __ATOMIC_RELAXED, AG);
   __syncthreads();
 }
@@ -899,7 +929,7 @@ __device__ __attribute__((noinline)) void team_rounds(const BlockJob& j, BlockSh
     }
     const unsigned e0 = (unsigned)((u64)nf * m / K), e1 = (unsigned)((u64)nf * (m + 1) / K);
     examined += expand_frontier<AG, false>(j, sh, cur, e0, e1, unit, 0, app);
-    nf = team_round_end(sh, nxt, gcnt);
+    nf = team_round_end<false>(sh, nxt, gcnt);
     if (sh.err) break;
     settled += nf;
     ++rounds;
@@ -919,6 +949,7 @@ __device__ __attribute__((noinline)) void team_rounds(const BlockJob& j, BlockSh
     u64* gcnt = &ts->qcnt[sh.epoch % 3];
     const TeamAppend app{&sh, nxt, gcnt};
     const u64 prev_round = (u64)(r - 1);
+    team_acquire();
     for (int v0 = lo; v0 < hi; v0 += BT) {  // the same passes in every thread (app.step)
       const int v = v0 + tid;
       const int a0 = v < hi ? rp[v] : 0, a1 = v < hi ? rp[v + 1] : 0;
@@ -940,7 +971,7 @@ __device__ __attribute__((noinline)) void team_rounds(const BlockJob& j, BlockSh
       }
       app.step();
     }
-    nf = team_round_end(sh, nxt, gcnt);
+    nf = team_round_end<true>(sh, nxt, gcnt);
     int* t = cur;
     cur = nxt;
     nxt = t;
@@ -948,7 +979,7 @@ __device__ __attribute__((noinline)) void team_rounds(const BlockJob& j, BlockSh
       gcnt = &ts->qcnt[sh.epoch % 3];
       const unsigned e0 = (unsigned)((u64)nf * m / K), e1 = (unsigned)((u64)nf * (m + 1) / K);
       examined += expand_frontier<AG, true>(j, sh, cur, e0, e1, unit, -(k + 1), TeamAppend{&sh, nxt, gcnt});
-      nf = team_round_end(sh, nxt, gcnt);
+      nf = team_round_end<false>(sh, nxt, gcnt);
       ++sweeps;
       t = cur;
       cur = nxt;
@@ -980,6 +1011,7 @@ __device__ __attribute__((noinline)) void team_output(const BlockJob& j, BlockSh
   const u64 mask = ((u64)1 << B) - 1;
   const unsigned e0 = sh.err | (sh.settled < sh.n_active ? ERR_WATCHDOG : 0u);
   u64 cut2 = 0, pieces = 0;
+  team_acquire();
   if (!e0) {
     for (int v = sh.tlo + tid; v < sh.thi; v += BT) {
       const u64 p = wg_load(&P[v]);
@@ -1007,7 +1039,7 @@ __device__ __attribute__((noinline)) void team_output(const BlockJob& j, BlockSh
     if (sh.examined) __hip_atomic_fetch_add(&ts->examined, sh.examined, __ATOMIC_RELAXED, AG);
     if (e0 | sh.err) __hip_atomic_fetch_or(&ts->err, e0 | sh.err, __ATOMIC_RELAXED, AG);
   }
-  team_barrier(sh);
+  team_barrier<true>(sh);
   if (tid == 0 && sh.tm == 0) {
     out->err = __hip_atomic_load(&ts->err, __ATOMIC_RELAXED, AG) | sh.err;
     out->cut_arcs = __hip_atomic_load(&ts->cut, __ATOMIC_RELAXED, AG);
