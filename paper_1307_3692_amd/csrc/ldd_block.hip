@@ -205,6 +205,34 @@ struct TeamAppend {
   }
 };
 
+// The slice loops (preparation, wake sort, output) are latency-bound with one vertex per thread at a
+// time: a thread takes VU vertices at once (v, v + BT, ...), and in the output AU arcs of each,
+// so that each of its loads has others in flight.
+constexpr int VU = 4, AU = 2;
+
+// Vertices v0 + k * BT (k < VU) below hi: has[k] when the vertex has arcs, key[k] = Delta - shift.
+__device__ __forceinline__ void slice_load(const int* __restrict__ rp, const long long* __restrict__ shift, int v0,
+                                           int hi, u64 delta, u64 (&key)[VU], bool (&has)[VU]) {
+  int a0[VU], a1[VU];
+  long long sv[VU];
+#pragma unroll
+  for (int k = 0; k < VU; ++k) {
+    const int v = v0 + k * BT;
+    a0[k] = a1[k] = 0;
+    sv[k] = 0;
+    if (v < hi) {
+      a0[k] = rp[v];
+      a1[k] = rp[v + 1];
+      sv[k] = shift[v];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < VU; ++k) {
+    has[k] = a1[k] > a0[k];
+    key[k] = delta - (u64)sv[k];
+  }
+}
+
 // Wake buckets of the vertices with arcs in [lo, hi): counting sort by w(v) = (Delta - shift) >> 20
 // in LDS; the vertices' own labels ((Delta - shift[v]) << B) | v go to wk[lo ...] in bucket order
 // (a wake then needs no shift load) and sh.woff[q] is bucket q's offset from lo (all threads call).
@@ -215,8 +243,14 @@ __device__ __forceinline__ void wake_sort(const BlockJob& j, BlockShared& sh, in
   const int B = j.n > 1 ? 32 - __builtin_clz((unsigned)(j.n - 1)) : 1;
   for (int q = tid; q <= BLOCK_WCAP; q += BT) sh.woff[q] = 0;
   __syncthreads();
-  for (int v = lo + tid; v < hi; v += BT)
-    if (rp[v + 1] > rp[v]) atomicAdd(&sh.woff[(int)((delta - (u64)shift[v]) >> FIX)], 1);
+  for (int v0 = lo + tid; v0 < hi; v0 += VU * BT) {
+    u64 key[VU];
+    bool has[VU];
+    slice_load(rp, shift, v0, hi, delta, key, has);
+#pragma unroll
+    for (int k = 0; k < VU; ++k)
+      if (has[k]) atomicAdd(&sh.woff[(int)(key[k] >> FIX)], 1);
+  }
   __syncthreads();
   {
     unsigned loc[WPT], sum = 0;
@@ -239,11 +273,13 @@ __device__ __forceinline__ void wake_sort(const BlockJob& j, BlockShared& sh, in
   __syncthreads();
   // scatter: woff[q] serves as bucket q's cursor (it ends at the start of bucket q + 1) and is
   // shifted back by one bucket afterwards
-  for (int v = lo + tid; v < hi; v += BT) {
-    if (rp[v + 1] > rp[v]) {
-      const int q = (int)((delta - (u64)shift[v]) >> FIX);
-      j.wk[lo + atomicAdd(&sh.woff[q], 1)] = ((delta - (u64)shift[v]) << B) | (u64)v;
-    }
+  for (int v0 = lo + tid; v0 < hi; v0 += VU * BT) {
+    u64 key[VU];
+    bool has[VU];
+    slice_load(rp, shift, v0, hi, delta, key, has);
+#pragma unroll
+    for (int k = 0; k < VU; ++k)
+      if (has[k]) j.wk[lo + atomicAdd(&sh.woff[(int)(key[k] >> FIX)], 1)] = (key[k] << B) | (u64)(v0 + k * BT);
   }
   __syncthreads();
   {
@@ -274,14 +310,31 @@ __device__ __forceinline__ void prepare_scan(const BlockJob& j, BlockShared& sh,
   unsigned err = 0;
   u64 dmax = 0, active = 0;
   if (ends && n > 0 && (rp[0] != 0 || (long long)rp[n] != nnz) && tid == 0) err |= ERR_BAD_ROWPTR;
-  for (int v = lo + tid; v < hi; v += BT) {
-    const long long s = shift[v];
-    if (s < 0 || s > (1ll << 52)) err |= ERR_BAD_SHIFT;
-    const int a0 = rp[v], a1 = rp[v + 1];
-    if (a1 < a0) err |= ERR_BAD_ROWPTR;
-    active += a1 > a0;
-    dmax = (u64)s > dmax ? (u64)s : dmax;
-    P[v] = INF;
+  for (int v0 = lo + tid; v0 < hi; v0 += VU * BT) {
+    long long sv[VU];
+    int a0[VU], a1[VU];
+#pragma unroll
+    for (int k = 0; k < VU; ++k) {
+      const int v = v0 + k * BT;
+      sv[k] = 0;
+      a0[k] = a1[k] = 0;
+      if (v < hi) {
+        sv[k] = shift[v];
+        a0[k] = rp[v];
+        a1[k] = rp[v + 1];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < VU; ++k) {
+      const int v = v0 + k * BT;
+      if (v < hi) {
+        if (sv[k] < 0 || sv[k] > (1ll << 52)) err |= ERR_BAD_SHIFT;
+        if (a1[k] < a0[k]) err |= ERR_BAD_ROWPTR;
+        active += a1[k] > a0[k];
+        dmax = (u64)sv[k] > dmax ? (u64)sv[k] : dmax;
+        P[v] = INF;
+      }
+    }
   }
   if (err) atomicOr(&sh.err, err);
   *dmax_out = block_max64(dmax, sh);
@@ -519,34 +572,81 @@ __device__ __attribute__((noinline)) void block_rounds(const BlockJob& j, BlockS
 }
 
 // Centres (INF: an isolated vertex, its own centre) and the cut, from the final labels.
-__device__ __attribute__((noinline)) void block_output(const BlockJob& j, BlockShared& sh, BlockOut* out) {
+// Centres and cut arcs of the vertices [lo, hi), added to *cut2 and *pieces; an arc to a vertex out
+// of range (arcs of the last frontier were not read by a round) sets ERR_BAD_COL.
+__device__ __forceinline__ void output_slice(const BlockJob& j, BlockShared& sh, int lo, int hi, u64 mask, u64* cut2,
+                                             u64* pieces) {
   const int n = j.n;
   const int* __restrict__ rp = j.row_ptr;
   const int* __restrict__ col = j.col;
-  u64* P = j.P;
+  const u64* P = j.P;
+  for (int v0 = lo + (int)threadIdx.x; v0 < hi; v0 += VU * BT) {
+    int a[VU], a1[VU], c[VU];
+    u64 p[VU];
+#pragma unroll
+    for (int k = 0; k < VU; ++k) {
+      const int v = v0 + k * BT;
+      a[k] = a1[k] = 0;
+      p[k] = INF;
+      if (v < hi) {
+        a[k] = rp[v];
+        a1[k] = rp[v + 1];
+        p[k] = wg_load(&P[v]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < VU; ++k) {
+      const int v = v0 + k * BT;
+      c[k] = p[k] == INF ? v : (int)(p[k] & mask);
+      if (v < hi) {
+        j.centre[v] = c[k];
+        *pieces += c[k] == v;
+      }
+    }
+    for (bool more = true; more;) {  // AU arcs of each vertex per pass
+      int w[VU][AU];
+      bool has[VU][AU];
+#pragma unroll
+      for (int k = 0; k < VU; ++k)
+#pragma unroll
+        for (int t = 0; t < AU; ++t) {
+          has[k][t] = a[k] + t < a1[k];
+          w[k][t] = has[k][t] ? col[a[k] + t] : 0;
+        }
+      u64 pw[VU][AU];
+#pragma unroll
+      for (int k = 0; k < VU; ++k)
+#pragma unroll
+        for (int t = 0; t < AU; ++t) pw[k][t] = has[k][t] && (unsigned)w[k][t] < (unsigned)n ? wg_load(&P[w[k][t]]) : 0;
+      more = false;
+#pragma unroll
+      for (int k = 0; k < VU; ++k) {
+#pragma unroll
+        for (int t = 0; t < AU; ++t) {
+          if (!has[k][t]) continue;
+          if ((unsigned)w[k][t] >= (unsigned)n) {
+            atomicOr(&sh.err, ERR_BAD_COL);
+            a1[k] = a[k];
+            break;
+          }
+          const int cw = pw[k][t] == INF ? w[k][t] : (int)(pw[k][t] & mask);
+          *cut2 += cw != c[k];
+        }
+        a[k] += AU;
+        more |= a[k] < a1[k];
+      }
+    }
+  }
+}
+
+__device__ __attribute__((noinline)) void block_output(const BlockJob& j, BlockShared& sh, BlockOut* out) {
+  const int n = j.n;
   const int tid = threadIdx.x;
   const int B = n > 1 ? 32 - __builtin_clz((unsigned)(n - 1)) : 1;
   const u64 mask = ((u64)1 << B) - 1;
   const unsigned e0 = sh.err | (sh.settled < sh.n_active ? ERR_WATCHDOG : 0u);
   u64 cut2 = 0, pieces = 0;
-  if (!e0) {
-    for (int v = tid; v < n; v += BT) {
-      const u64 p = wg_load(&P[v]);
-      const int c = p == INF ? v : (int)(p & mask);
-      j.centre[v] = c;
-      pieces += c == v;
-      for (int a = rp[v]; a < rp[v + 1]; ++a) {
-        const int w = col[a];
-        if ((unsigned)w >= (unsigned)n) {  // arcs of the last frontier were not read by a round
-          atomicOr(&sh.err, ERR_BAD_COL);
-          break;
-        }
-        const u64 pw = wg_load(&P[w]);
-        const int cw = pw == INF ? w : (int)(pw & mask);
-        cut2 += cw != c;
-      }
-    }
-  }
+  if (!e0) output_slice(j, sh, 0, n, mask, &cut2, &pieces);
   cut2 = block_sum64(cut2, sh);
   pieces = block_sum64(pieces, sh);
   if (tid == 0) {
@@ -1002,9 +1102,6 @@ __device__ __attribute__((noinline)) void team_rounds(const BlockJob& j, BlockSh
 // member 0 writes the graph's result.
 __device__ __attribute__((noinline)) void team_output(const BlockJob& j, BlockShared& sh, BlockOut* out) {
   const int n = j.n;
-  const int* __restrict__ rp = j.row_ptr;
-  const int* __restrict__ col = j.col;
-  u64* P = j.P;
   TeamSync* ts = sh.ts;
   const int tid = threadIdx.x;
   const int B = n > 1 ? 32 - __builtin_clz((unsigned)(n - 1)) : 1;
@@ -1012,24 +1109,7 @@ __device__ __attribute__((noinline)) void team_output(const BlockJob& j, BlockSh
   const unsigned e0 = sh.err | (sh.settled < sh.n_active ? ERR_WATCHDOG : 0u);
   u64 cut2 = 0, pieces = 0;
   team_acquire();
-  if (!e0) {
-    for (int v = sh.tlo + tid; v < sh.thi; v += BT) {
-      const u64 p = wg_load(&P[v]);
-      const int c = p == INF ? v : (int)(p & mask);
-      j.centre[v] = c;
-      pieces += c == v;
-      for (int a = rp[v]; a < rp[v + 1]; ++a) {
-        const int w = col[a];
-        if ((unsigned)w >= (unsigned)n) {
-          atomicOr(&sh.err, ERR_BAD_COL);
-          break;
-        }
-        const u64 pw = wg_load(&P[w]);
-        const int cw = pw == INF ? w : (int)(pw & mask);
-        cut2 += cw != c;
-      }
-    }
-  }
+  if (!e0) output_slice(j, sh, sh.tlo, sh.thi, mask, &cut2, &pieces);
   cut2 = block_sum64(cut2, sh);
   pieces = block_sum64(pieces, sh);
   __syncthreads();
