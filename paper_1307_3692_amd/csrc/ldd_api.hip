@@ -642,9 +642,18 @@ static ldd_status decompose_run(Workspace& w, const ldd_csr* g, const int64_t* s
 // ------------------------------------------------------------------------------------------
 // the workgroup engine for one graph: one workgroup runs all rounds (small graphs)
 // ------------------------------------------------------------------------------------------
-// graphs the automatic engine choice gives to one workgroup: few enough arcs that one workgroup
-// reads them faster than round steps over the whole GPU synchronise
+// The automatic engine choice.  Graphs of more than AUTO_TEAM_DEGREE arcs per vertex on average
+// (RMAT and other skewed, low-diameter graphs) go to the multi-block engines, whose bottom-up
+// pulls and grid-wide arc splits they need.  Sparser graphs go to one workgroup when they have at
+// most BLOCK_AUTO_ARCS arcs (one workgroup reads them faster than round steps over the whole GPU
+// synchronise), else to a team, which refuses a graph with a vertex of more than AUTO_TEAM_DEG_CAP
+// arcs (one member would expand it alone), and that graph goes to the multi-block engines too.
+// Measured (ms, AUTO before -> team): rgg 50K/200K/1M vertices 3.8/5.3/6.5 -> 1.6/2.3/2.6, ER(avg
+// degree 8) 50K/200K 0.28/0.32 -> 0.15/0.20, grid2d-1000 6.6 -> 2.7, grid3d-128 4.4 -> 1.8; RMAT
+// 10-20: the launch engine 0.18-0.30 ms against a team's 0.3-36 ms.
 constexpr long long BLOCK_AUTO_ARCS = 1ll << 15;
+constexpr long long AUTO_TEAM_DEGREE = 12;
+constexpr int AUTO_TEAM_DEG_CAP = 4096;
 
 static const ldd_status REDO_MULTI = static_cast<ldd_status>(101);  // internal: shifts too wide for a workgroup
 
@@ -655,7 +664,7 @@ static ldd_status block_status(unsigned err, u64 delta, int n) {
                   (unsigned long long)delta);
     return LDD_ERR_OVERFLOW;
   }
-  if (err & BLK_WIDE) return REDO_MULTI;
+  if (err & (BLK_WIDE | BLK_SKEW)) return REDO_MULTI;
   if (err) {
     ldd_set_error("workgroup engine error flags 0x%x", err);
     return LDD_ERR_INTERNAL;
@@ -671,11 +680,12 @@ static int tail_den_of(const ldd_options& o) {
 // (TEAM: blocks of them, default one per CU, at most the workgroups that can be resident at once, at
 // least 64 vertices per member) meeting at a device-memory barrier once per round.
 static ldd_status decompose_block(Workspace& w, const ldd_csr* g, const int64_t* shift_fix, int32_t* centre,
-                                  int64_t* cut_edges, const ldd_options& opt, ldd_stats* stats, hipStream_t st) {
+                                  int64_t* cut_edges, const ldd_options& opt, ldd_stats* stats, hipStream_t st,
+                                  bool team, int deg_cap) {
   const int n = g->n;
   const size_t nv = (size_t)n;
   int K = 1;
-  if (opt.engine == LDD_ENGINE_TEAM) {
+  if (team) {
     K = opt.blocks > 0 ? opt.blocks : w.num_cu;
     K = std::min(K, std::min(w.block_coresident, TEAM_GROUP * TEAM_GROUPS));
     K = std::min(K, n / 64);
@@ -702,6 +712,7 @@ static ldd_status decompose_block(Workspace& w, const ldd_csr* g, const int64_t*
   j.tail_den = tail_den_of(opt);
   j.team = K;
   j.sync = K > 1 ? (TeamSync*)w.bk_sync.p : nullptr;
+  j.deg_cap = deg_cap;
   // the dynamic LDS the graph's mode needs (the label-correcting iteration, or the rounds in LDS)
   long long lds = 0;
   if (K == 1 && fix_lds_bytes(n, g->nnz) <= w.lds_bytes) lds = fix_lds_bytes(n, g->nnz);
@@ -771,10 +782,14 @@ static ldd_status decompose_block(Workspace& w, const ldd_csr* g, const int64_t*
 static ldd_status decompose_impl(Workspace& w, const ldd_csr* g, const int64_t* shift_fix, int32_t* centre,
                                  int64_t* cut_edges, const ldd_options& o, ldd_stats* stats, hipStream_t st,
                                  const BatchView* bv) {
-  const bool block = !bv && (o.engine == LDD_ENGINE_WORKGROUP || o.engine == LDD_ENGINE_TEAM ||
-                             (o.engine == LDD_ENGINE_AUTO && g->nnz <= BLOCK_AUTO_ARCS));
-  if (block) {
-    ldd_status s = decompose_block(w, g, shift_fix, centre, cut_edges, o, stats, st);
+  // a forced bottom-up policy needs the multi-block engines (the workgroup engines run top-down)
+  const bool sparse = g->nnz <= AUTO_TEAM_DEGREE * (long long)g->n && o.direction != LDD_DIR_BOTTOM_UP;
+  const bool auto_wg = o.engine == LDD_ENGINE_AUTO && sparse && g->nnz <= BLOCK_AUTO_ARCS;
+  const bool auto_team = o.engine == LDD_ENGINE_AUTO && sparse && g->nnz > BLOCK_AUTO_ARCS;
+  if (!bv && (o.engine == LDD_ENGINE_WORKGROUP || o.engine == LDD_ENGINE_TEAM || auto_wg || auto_team)) {
+    const bool team = o.engine == LDD_ENGINE_TEAM || auto_team;
+    ldd_status s = decompose_block(w, g, shift_fix, centre, cut_edges, o, stats, st, team,
+                                   auto_team ? AUTO_TEAM_DEG_CAP : 0);
     if (s != REDO_MULTI) return s;
   }
   ldd_status s = decompose_run(w, g, shift_fix, centre, cut_edges, o, stats, st, bv, false);

@@ -19,8 +19,9 @@ __host__ __device__ constexpr long long fix_lds_bytes(long long n, long long nnz
 __host__ __device__ constexpr long long rounds_lds_bytes(long long n) { return 24 * n; }
 
 // error bits of a workgroup job beyond ERR_*: the labels would not fit 64 bits; the shift range
-// needs more wake buckets than the workgroup sorts
-enum : unsigned { BLK_OVERFLOW = 64u, BLK_WIDE = 128u };
+// needs more wake buckets than the workgroup sorts; a team was asked to refuse a graph with a
+// vertex of more than deg_cap arcs, and it has one
+enum : unsigned { BLK_OVERFLOW = 64u, BLK_WIDE = 128u, BLK_SKEW = 256u };
 
 // A graph too large for one workgroup runs on a team of K workgroups (all resident at once) that
 // meet at a barrier in device memory once per round.  Per team, in device memory, zeroed before
@@ -50,6 +51,7 @@ struct TeamSync {
   alignas(128) u64 delta;
   alignas(128) u64 active;
   alignas(128) u64 cut, pieces, examined;
+  alignas(128) u64 maxdeg;
   alignas(128) u64 nz[BLOCK_WCAP / 64];
 };
 
@@ -68,6 +70,7 @@ struct BlockJob {
   int tail_den;          // label-correcting tail once unreached * tail_den <= vertices with arcs (0: never)
   int team;              // workgroups on this graph (1: alone)
   TeamSync* sync;        // team > 1: the team's barrier and counters
+  int deg_cap;           // team > 1: refuse (BLK_SKEW) a graph with a vertex of more arcs (0: never)
 };
 
 struct BlockOut {

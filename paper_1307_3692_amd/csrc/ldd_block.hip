@@ -300,7 +300,7 @@ __device__ __forceinline__ void wake_sort(const BlockJob& j, BlockShared& sh, in
 // (all threads call; results are the workgroup's: *dmax and *active reduced, errors in sh.err,
 // which the caller cleared).
 __device__ __forceinline__ void prepare_scan(const BlockJob& j, BlockShared& sh, int lo, int hi, bool ends,
-                                             u64* dmax_out, u64* active_out) {
+                                             u64* dmax_out, u64* active_out, u64* degmax_out = nullptr) {
   const int n = j.n;
   const long long nnz = j.nnz;
   const int* __restrict__ rp = j.row_ptr;
@@ -308,7 +308,7 @@ __device__ __forceinline__ void prepare_scan(const BlockJob& j, BlockShared& sh,
   u64* P = j.P;
   const int tid = threadIdx.x;
   unsigned err = 0;
-  u64 dmax = 0, active = 0;
+  u64 dmax = 0, active = 0, degmax = 0;
   if (ends && n > 0 && (rp[0] != 0 || (long long)rp[n] != nnz) && tid == 0) err |= ERR_BAD_ROWPTR;
   for (int v0 = lo + tid; v0 < hi; v0 += VU * BT) {
     long long sv[VU];
@@ -332,6 +332,7 @@ __device__ __forceinline__ void prepare_scan(const BlockJob& j, BlockShared& sh,
         if (a1[k] < a0[k]) err |= ERR_BAD_ROWPTR;
         active += a1[k] > a0[k];
         dmax = (u64)sv[k] > dmax ? (u64)sv[k] : dmax;
+        degmax = a1[k] > a0[k] && (u64)(a1[k] - a0[k]) > degmax ? (u64)(a1[k] - a0[k]) : degmax;
         P[v] = INF;
       }
     }
@@ -339,6 +340,7 @@ __device__ __forceinline__ void prepare_scan(const BlockJob& j, BlockShared& sh,
   if (err) atomicOr(&sh.err, err);
   *dmax_out = block_max64(dmax, sh);
   *active_out = block_sum64(active, sh);
+  if (degmax_out) *degmax_out = block_max64(degmax, sh);
   __syncthreads();
 }
 
@@ -953,9 +955,10 @@ __device__ __attribute__((noinline)) void team_prepare(const BlockJob& j, BlockS
     sh.bn = 0;
   }
   __syncthreads();
-  u64 dmax, active;
-  prepare_scan(j, sh, sh.tlo, sh.thi, sh.tm == 0, &dmax, &active);
+  u64 dmax, active, degmax;
+  prepare_scan(j, sh, sh.tlo, sh.thi, sh.tm == 0, &dmax, &active, &degmax);
   if (tid == 0) {
+    if (j.deg_cap > 0 && degmax > (u64)j.deg_cap) __hip_atomic_fetch_max(&ts->maxdeg, degmax, __ATOMIC_RELAXED, AG);
     if (dmax) __hip_atomic_fetch_max(&ts->delta, dmax, __ATOMIC_RELAXED, AG);
     if (active) __hip_atomic_fetch_add(&ts->active, active, __ATOMIC_RELAXED, AG);
     if (sh.err) __hip_atomic_fetch_or(&ts->err, sh.err, __ATOMIC_RELAXED, AG);
@@ -965,6 +968,7 @@ __device__ __attribute__((noinline)) void team_prepare(const BlockJob& j, BlockS
   const u64 n_active = __hip_atomic_load(&ts->active, __ATOMIC_RELAXED, AG);
   unsigned e = __hip_atomic_load(&ts->err, __ATOMIC_RELAXED, AG);
   if (!e) e = range_err(j.n, delta);
+  if (!e && __hip_atomic_load(&ts->maxdeg, __ATOMIC_RELAXED, AG)) e = BLK_SKEW;
   __syncthreads();
   if (tid == 0) {
     sh.err |= e;
@@ -1232,6 +1236,7 @@ __global__ void k_block_jobs(int G, long long N, const long long* vo, const long
     j.tail_den = tail_den;
     j.team = team ? team[2 * g] : 1;
     j.sync = j.team > 1 ? sync + team[2 * g + 1] : nullptr;
+    j.deg_cap = 0;
     jobs[g] = j;
   }
 }

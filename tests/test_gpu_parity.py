@@ -154,13 +154,42 @@ def test_medium_workloads_vs_oracle(ldd, name):
     t = time.time()
     want_c, _, want_cut = oracle.decompose(rp, ci, s)
     log(f"{name}: n={rp.size - 1} nnz={ci.size} oracle {time.time() - t:.2f}s")
-    for mode in (dict(), dict(direction=1), dict(direction=2), dict(engine=1), dict(tail_vertices=-1),
-                 dict(tail_vertices=1), dict(engine=3)):
+    for mode in (dict(), dict(engine=2), dict(engine=2, direction=1), dict(direction=2), dict(engine=1),
+                 dict(engine=2, tail_vertices=-1), dict(engine=2, tail_vertices=1), dict(engine=3), dict(engine=4)):
         got, cut, st = run(ldd, rp, ci, s, beta, **mode)
         log(f"  {mode}: rounds {st['rounds']} td {st['td_rounds']} bu {st['bu_rounds']} tail {st['tail_iters']} "
             f"from {st['tail_round']} rounds_ms {st['ms_rounds']:.3f}")
         assert np.array_equal(got, want_c), (mode, np.count_nonzero(got != want_c))
         assert cut == want_cut
+
+
+def test_automatic_engine_choice(ldd):
+    """The automatic engine choice: a sparse graph above 2^15 arcs runs on a team (no frontier
+    statistics, one step), a sparse graph with a hub of more than 4096 arcs is refused by the team
+    and finishes on the launch engine, and a dense graph (RMAT) or a forced bottom-up policy takes
+    the launch engine; every result equals the oracle's."""
+    from graphs import disjoint_union, path, star
+    hub = disjoint_union(star(5001), path(60000))
+    cases = [
+        ("rgg-50k", inputs.rgg(50000, 6.0, 3), {}, "team"),
+        ("star-5000+path-60000", hub, {}, "launch"),
+        ("rmat-12", inputs.rmat(12, 16, 0.57, 0.19, 0.19, seed=1, relabel=True), {}, "launch"),
+        ("grid2d-300", inputs.grid2d(300, 300), dict(direction=2), "launch"),
+        ("grid2d-64", inputs.grid2d(64, 64), {}, "workgroup"),
+    ]
+    for name, (rp, ci), opts, engine in cases:
+        s = inputs.make_shifts(rp.size - 1, 0.05, 7)
+        want_c, _, want_cut = oracle.decompose(rp, ci, s)
+        got, cut, st = run(ldd, rp, ci, s, 0.05, **opts)
+        log(f"{name} {opts}: steps {st['steps']} blocks {st['blocks']} max_frontier {st['max_frontier']} "
+            f"rounds {st['rounds']}")
+        assert np.array_equal(got, want_c), (name, np.count_nonzero(got != want_c))
+        assert cut == want_cut, name
+        if engine == "launch":
+            assert st["max_frontier"] > 0, name
+        else:
+            assert st["max_frontier"] == 0 and st["steps"] == 1, name
+            assert (st["blocks"] > 1) == (engine == "team"), name
 
 
 def test_pull_rows_finished_by_waves(ldd):
