@@ -372,6 +372,14 @@ def golden(name):
         return json.load(f).get(name)
 
 
+def round_kernel(stats, engine):
+    """The dominant kernel of a decomposition: the workgroup engines (one step, no frontier
+    statistics, also when the automatic choice took them) run everything in k_block_decompose."""
+    if engine in (3, 4) or (stats["steps"] == 1 and stats["max_frontier"] == 0):
+        return "k_block_decompose"
+    return "k_rounds_persistent" if engine == 1 else "k_round_step_lb"
+
+
 def roofline_block(stats, n, kernel, traffic=None):
     """The round kernel's algorithmic bytes per launch over its average launch duration (HIP
     events around the launches on their stream, idle launches included)."""
@@ -471,9 +479,7 @@ def run_grid3d(ldd, steps=5):
            "steps": st["steps"], "us_per_step": round(st["ms_rounds"] * 1e3 / max(1, st["steps"]), 2),
            "arcs_examined": st["arcs_examined"],
            "stage_ms": {k: round(st[k], 4) for k in ("ms_prep", "ms_rounds", "ms_finalize", "ms_cut")},
-           "roofline": roofline_block(st, r["n"], {1: "k_rounds_persistent", 3: "k_block_decompose",
-                                                   4: "k_block_decompose"}.get(r["opts"].get("engine", 0),
-                                                                               "k_round_step_lb"),
+           "roofline": roofline_block(st, r["n"], round_kernel(st, r["opts"].get("engine", 0)),
                                       measured_traffic("grid3d-256", r["opts"].get("engine", 0))),
            "tuned": r["opts"], "untuned_ms": round(rep["default_ms"], 3), "tuned_ms": round(rep["best_ms"], 3),
            "bit_exact": r["bit_exact"]}
@@ -630,8 +636,8 @@ def main():
         "arcs_examined": stats["arcs_examined"],
         "examined_arcs_per_s": round(stats["arcs_examined"] / (ms_step * 1e-3), 1),
         "stage_ms": {k: round(stats[k], 4) for k in ("ms_prep", "ms_rounds", "ms_finalize", "ms_cut")},
-        "roofline": roofline_block(stats, n, {1: "k_rounds_persistent", 3: "k_block_decompose", 4: "k_block_decompose"}
-                                   .get(args.engine, "k_round_step_lb"), measured_traffic(args.workload, args.engine)),
+        "roofline": roofline_block(stats, n, round_kernel(stats, args.engine),
+                                   measured_traffic(args.workload, args.engine)),
     }
     if not args.no_grids:
         out["grid2d"] = run_grid2d(ldd)

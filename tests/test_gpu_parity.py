@@ -192,6 +192,28 @@ def test_automatic_engine_choice(ldd):
             assert (st["blocks"] > 1) == (engine == "team"), name
 
 
+@pytest.mark.parametrize("kind", ["rgg", "er", "grid"])
+def test_team_sizes_and_seeds_vs_oracle(ldd, kind):
+    """Teams of 2 to 256 workgroups (their per-round barrier is relaxed: every access another
+    member may see in a round is device-scope by itself) on mid-size sparse graphs over several
+    graph and shift seeds, with and without the label-correcting tail: every result equals the
+    oracle's."""
+    for seed in range(3):
+        if kind == "rgg":
+            rp, ci = inputs.rgg(40000 + 7000 * seed, 6.0, 20 + seed)
+        elif kind == "er":
+            rp, ci = inputs.er(60000 + 9000 * seed, 5.0, 30 + seed)
+        else:
+            rp, ci = inputs.grid2d(150 + 31 * seed, 170 + 17 * seed)
+        s = inputs.make_shifts(rp.size - 1, 0.03, 40 + seed)
+        want_c, _, want_cut = oracle.decompose(rp, ci, s)
+        for k, tail in ((2, 0), (5, -1), (37, 1), (128, 0), (256, -1)):
+            got, cut, st = run(ldd, rp, ci, s, 0.03, engine=4, blocks=k, tail_vertices=tail)
+            assert np.array_equal(got, want_c), (kind, seed, k, tail, np.count_nonzero(got != want_c))
+            assert cut == want_cut, (kind, seed, k, tail)
+        log(f"{kind} seed {seed}: n={rp.size - 1} rounds {st['rounds']} sweeps {st['tail_iters']}")
+
+
 def test_pull_rows_finished_by_waves(ldd):
     """An RMAT graph and shifts on which the bottom-up early exit rarely fires (several centres'
     waves meet): most pulled rows run past the per-thread cap and are finished by their wave.
