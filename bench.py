@@ -63,17 +63,17 @@ def kernel_sources_sha():
     return h.hexdigest()
 
 
-def measured_traffic(workload, engine=0):
+def measured_traffic(workload, kernel):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter runs
-    (profiles/traffic_rounds.json: one entry per workload and engine), or None when they were
-    taken on other kernel sources, another workload or another engine."""
+    (profiles/traffic_rounds.json: one entry per workload and kernel), or None when they were
+    taken on other kernel sources, another workload or another kernel."""
     if not os.path.exists(TRAFFIC):
         return None
     with open(TRAFFIC) as f:
         t = json.load(f)
     sha = kernel_sources_sha()
     for e in t.get("entries", []):
-        if e.get("workload") == workload and e.get("engine", 0) == engine and e.get("kernel_sources_sha") == sha:
+        if e.get("workload") == workload and e.get("kernel") == kernel and e.get("kernel_sources_sha") == sha:
             return e.get("bytes_per_launch")
     return None
 
@@ -480,7 +480,7 @@ def run_grid3d(ldd, steps=5):
            "arcs_examined": st["arcs_examined"],
            "stage_ms": {k: round(st[k], 4) for k in ("ms_prep", "ms_rounds", "ms_finalize", "ms_cut")},
            "roofline": roofline_block(st, r["n"], round_kernel(st, r["opts"].get("engine", 0)),
-                                      measured_traffic("grid3d-256", r["opts"].get("engine", 0))),
+                                      measured_traffic("grid3d-256", round_kernel(st, r["opts"].get("engine", 0)))),
            "tuned": r["opts"], "untuned_ms": round(rep["default_ms"], 3), "tuned_ms": round(rep["best_ms"], 3),
            "bit_exact": r["bit_exact"]}
     log(f"grid3d: {out}")
@@ -637,7 +637,7 @@ def main():
         "examined_arcs_per_s": round(stats["arcs_examined"] / (ms_step * 1e-3), 1),
         "stage_ms": {k: round(stats[k], 4) for k in ("ms_prep", "ms_rounds", "ms_finalize", "ms_cut")},
         "roofline": roofline_block(stats, n, round_kernel(stats, args.engine),
-                                   measured_traffic(args.workload, args.engine)),
+                                   measured_traffic(args.workload, round_kernel(stats, args.engine))),
     }
     if not args.no_grids:
         out["grid2d"] = run_grid2d(ldd)
