@@ -26,9 +26,10 @@ enum : unsigned { BLK_OVERFLOW = 64u, BLK_WIDE = 128u, BLK_SKEW = 256u };
 // A graph too large for one workgroup runs on a team of K workgroups (all resident at once) that
 // meet at a barrier in device memory once per round.  Per team, in device memory, zeroed before
 // the launch: the barrier's words (below), the OR of the members' error bits, the append counters
-// of the shared frontier queue, the preparation's and the output's sums, and the OR of the
-// members' non-empty wake buckets.  Its size does not depend on K.  A batch gives a team at most
-// TEAM_MAX workgroups; one graph alone may take every resident workgroup.
+// of the shared frontier queue, the preparation's and the output's sums, the largest degree found
+// above deg_cap (0: none), and the OR of the members' non-empty wake buckets.  Its size does not
+// depend on K.  A batch gives a team at most TEAM_MAX workgroups; one graph alone may take every
+// resident workgroup.
 constexpr int TEAM_MAX = 16;
 
 constexpr int TEAM_GROUP = 16;   // barrier arrivals are counted per group of 16 members, then per group
