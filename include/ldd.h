@@ -74,7 +74,7 @@ enum { LDD_DIR_AUTO = 0, LDD_DIR_TOP_DOWN = 1, LDD_DIR_BOTTOM_UP = 2 };
  * whole GPU, one workgroup running every round of the graph (workgroup barriers only), or a team
  * of workgroups (blocks of them, default one per CU, at most the workgroups that can be resident
  * at once) running every round with one barrier in device memory per round (top-down only: for
- * large graphs of low degree and many rounds, such as grids).  AUTO: a graph of more than 12 arcs
+ * large graphs of low degree and many rounds, such as grids).  AUTO: a graph of more than 7 arcs
  * per vertex on average, or a call with direction LDD_DIR_BOTTOM_UP, takes the launch engine; a
  * sparser graph takes one workgroup when it has at most 2^15 arcs, else a team, unless a vertex
  * has more than 4096 arcs (the team finds it in its preparation and the call continues on the

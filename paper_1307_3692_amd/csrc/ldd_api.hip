@@ -643,16 +643,19 @@ static ldd_status decompose_run(Workspace& w, const ldd_csr* g, const int64_t* s
 // the workgroup engine for one graph: one workgroup runs all rounds (small graphs)
 // ------------------------------------------------------------------------------------------
 // The automatic engine choice.  Graphs of more than AUTO_TEAM_DEGREE arcs per vertex on average
-// (RMAT and other skewed, low-diameter graphs) go to the multi-block engines, whose bottom-up
-// pulls and grid-wide arc splits they need.  Sparser graphs go to one workgroup when they have at
-// most BLOCK_AUTO_ARCS arcs (one workgroup reads them faster than round steps over the whole GPU
+// (RMAT and other skewed graphs, random graphs of small diameter) go to the multi-block engines,
+// whose bottom-up pulls and grid-wide arc splits they need.  Sparser graphs (meshes, geometric and
+// road-like graphs: many rounds with small frontiers) go to one workgroup when they have at most
+// BLOCK_AUTO_ARCS arcs (one workgroup reads them faster than round steps over the whole GPU
 // synchronise), else to a team, which refuses a graph with a vertex of more than AUTO_TEAM_DEG_CAP
 // arcs (one member would expand it alone), and that graph goes to the multi-block engines too.
-// Measured (ms, AUTO before -> team): rgg 50K/200K/1M vertices 3.8/5.3/6.5 -> 1.6/2.3/2.6, ER(avg
-// degree 8) 50K/200K 0.28/0.32 -> 0.15/0.20, grid2d-1000 6.6 -> 2.7, grid3d-128 4.4 -> 1.8; RMAT
-// 10-20: the launch engine 0.18-0.30 ms against a team's 0.3-36 ms.
+// Measured (ms, launch engine -> team): rgg (6 arcs per vertex) 50K/200K/1M/4M vertices
+// 3.8/5.3/6.5/10.3 -> 1.6/2.3/2.6/4.5, grid2d-1000/3000 6.6/12.5 -> 2.7/5.3, grid3d-128 4.4 -> 1.8,
+// ER with 4 arcs per vertex, 2M vertices 0.69 -> 0.63; but ER with 8-10 arcs per vertex (small
+// diameter, huge frontiers, where the top-down team reads every arc) 4M/8M vertices 1.0/1.3 ->
+// 1.4/3.6 (50K/200K: 0.28/0.32 -> 0.16/0.20), and RMAT 10-20 0.18-0.30 -> 0.3-36.
 constexpr long long BLOCK_AUTO_ARCS = 1ll << 15;
-constexpr long long AUTO_TEAM_DEGREE = 12;
+constexpr long long AUTO_TEAM_DEGREE = 7;
 constexpr int AUTO_TEAM_DEG_CAP = 4096;
 
 static const ldd_status REDO_MULTI = static_cast<ldd_status>(101);  // internal: shifts too wide for a workgroup
