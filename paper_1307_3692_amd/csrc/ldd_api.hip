@@ -687,6 +687,8 @@ static ldd_status decompose_block(Workspace& w, const ldd_csr* g, const int64_t*
                                   bool team, int deg_cap) {
   const int n = g->n;
   const size_t nv = (size_t)n;
+  ldd_status s = ws_setup(w);  // first: it reads the device's CU count and residency
+  if (s != LDD_OK) return s;
   int K = 1;
   if (team) {
     K = opt.blocks > 0 ? opt.blocks : w.num_cu;
@@ -694,8 +696,6 @@ static ldd_status decompose_block(Workspace& w, const ldd_csr* g, const int64_t*
     K = std::min(K, n / 64);
     K = std::max(K, 1);
   }
-  ldd_status s = ws_setup(w);
-  if (s != LDD_OK) return s;
   if ((s = grow(w.P, nv * 8)) || (s = grow(w.bk_wq, nv * 16)) || (s = grow(w.bk_out, sizeof(BlockOut))) ||
       (s = grow(w.bk_sync, sizeof(TeamSync))))
     return s;

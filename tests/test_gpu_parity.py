@@ -167,7 +167,9 @@ def test_automatic_engine_choice(ldd):
     """The automatic engine choice: a sparse graph above 2^15 arcs runs on a team (no frontier
     statistics, one step), a sparse graph with a hub of more than 4096 arcs is refused by the team
     and finishes on the launch engine, and a dense graph (RMAT) or a forced bottom-up policy takes
-    the launch engine; every result equals the oracle's."""
+    the launch engine; every result equals the oracle's.  Run in a process of its own (first
+    decompositions of the process) it also checks that the team is sized from the device's
+    residency on its first call."""
     from graphs import disjoint_union, path, star
     hub = disjoint_union(star(5001), path(60000))
     cases = [
@@ -190,6 +192,13 @@ def test_automatic_engine_choice(ldd):
         else:
             assert st["max_frontier"] == 0 and st["steps"] == 1, name
             assert (st["blocks"] > 1) == (engine == "team"), name
+    # asked for explicitly, a team keeps the hub graph (no degree cap) and still gives the oracle's result
+    rp, ci = hub
+    s = inputs.make_shifts(rp.size - 1, 0.05, 7)
+    want_c, _, want_cut = oracle.decompose(rp, ci, s)
+    got, cut, st = run(ldd, rp, ci, s, 0.05, engine=4)
+    assert st["max_frontier"] == 0 and st["steps"] == 1 and st["blocks"] > 1
+    assert np.array_equal(got, want_c) and cut == want_cut
 
 
 @pytest.mark.parametrize("kind", ["rgg", "er", "grid"])
