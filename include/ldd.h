@@ -91,8 +91,9 @@ typedef struct {
   int32_t direction;      /* LDD_DIR_*                                                    */
   int32_t engine;         /* LDD_ENGINE_*                                                 */
   int32_t validate;       /* 1: check CSR monotonicity on the device before running       */
-  int32_t blocks;         /* workgroups of the round kernel (0 = 2 per CU; the workgroup batch engine:
-                             1 per CU; at most 1024)                                                          */
+  int32_t blocks;         /* workgroups of the round kernel (0 = 2 per CU; the workgroup batch engine
+                             and a team: 1 per CU, a team at most the workgroups that can be resident
+                             at once, one per CU; at most 1024)                                               */
   int32_t td_to_bu;       /* switch to bottom-up when frontier arcs * td_to_bu > unsettled arcs (0 = default 14) */
   int32_t bu_to_td;       /* switch back when frontier vertices * bu_to_td < n (0 = default 24)                 */
   int32_t tail_vertices;  /* finish by label correction once unsettled vertices * this <= active vertices
