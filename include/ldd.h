@@ -172,7 +172,7 @@ ldd_status ldd_decompose_batch(int32_t num_graphs, const int64_t* vtx_off, const
 /*
  * Tune the engine and its mapping for a workload: the engine (one graph: engine = LAUNCH,
  * PERSISTENT, TEAM, or WORKGROUP when nnz <= 2^22; a batch: batch_mode = WORKGROUP or UNION), grid
- * size (blocks), the top-down / bottom-up switching thresholds (td_to_bu, bu_to_td; not for the
+ * size (blocks: a quarter of the CU count up to four per CU), the top-down / bottom-up switching thresholds (td_to_bu, bu_to_td; not for the
  * workgroup engine and its teams, which run top-down only), the tail threshold (tail_vertices) and, for the
  * workgroup batch engine, the arcs per team member (team_arcs), searched one knob at a time by
  * timing whole decompositions of the given inputs (median of three, HIP events on hip_stream).  The inputs are those of ldd_decompose_batch (num_graphs = 1: one graph,

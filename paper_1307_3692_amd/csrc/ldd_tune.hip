@@ -187,7 +187,9 @@ extern "C" ldd_status ldd_tune(int32_t num_graphs, const int64_t* vtx_off, const
   } else {
     modes = {LDD_BATCH_WORKGROUP, LDD_BATCH_UNION};
   }
-  const std::vector<int> blocks = {ncu, 2 * ncu, 3 * ncu, 4 * ncu};
+  // fewer than one per CU too: smaller teams, and persistent grids whose barriers cost less
+  const std::vector<int> blocks = {std::max(1, ncu / 4), std::max(1, ncu / 2), std::max(1, 3 * ncu / 4), ncu,
+                                   2 * ncu, 3 * ncu, 4 * ncu};
   const std::vector<int> td_to_bu = {6, 10, 14, 20, 30};
   const std::vector<int> bu_to_td = {12, 24, 48};
   const std::vector<int> tail = {16, 32, 64, 128, 256, -1};
