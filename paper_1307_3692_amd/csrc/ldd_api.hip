@@ -214,10 +214,13 @@ extern "C" size_t ldd_workspace_bytes(int32_t n, int64_t nnz) {
   const size_t nv = n > 0 ? (size_t)n : 1;
   // labels 8 + two queues (4 + 4 each) + wake order 4 + tail stamp 4 = 32 bytes per vertex, the
   // piece bitmap, the preparation's per-block bucket counts and window lists, rounds arrays
-  // sized by the shift range (bounded here by 2^16 rounds) and the control block
+  // sized by the shift range (bounded here by 2^16 rounds) and the control block; and the
+  // workgroup engines' wake list and queues (16 bytes per vertex) with a team's record and the
+  // result record, which one call may hold beside the rest (a team that refuses a graph)
   const size_t gp = std::min<size_t>(1024, std::max<size_t>(1, nv / 16384));
-  return nv * 32 + (nv + 63) / 64 * 8 + gp * ((size_t)QCAP * 4 + (size_t)CAND * 8 + 8) +
-         (size_t)(65536 + 2) * (4 * 4) + sizeof(Ctrl) + 2 * sizeof(RoundState) + 3 * 16 * 8 + 2 * (size_t)RT * 8;
+  return nv * 48 + (nv + 63) / 64 * 8 + gp * ((size_t)QCAP * 4 + (size_t)CAND * 8 + 8) +
+         (size_t)(65536 + 2) * (4 * 4) + sizeof(Ctrl) + 2 * sizeof(RoundState) + 3 * 16 * 8 + 2 * (size_t)RT * 8 +
+         sizeof(TeamSync) + sizeof(BlockOut);
 }
 
 extern "C" void ldd_release_workspace(void) {

@@ -60,7 +60,8 @@ def test_argument_errors_answer_before_device_work():
 def test_workspace_bytes_grows_with_n():
     L = ldd.lib()
     a, b = L.ldd_workspace_bytes(1000, 16000), L.ldd_workspace_bytes(2000, 32000)
-    assert 0 < a < b and b - a >= 1000 * 32
+    # 32 B per vertex for the round engines, 16 more for the workgroup engines beside them
+    assert 0 < a < b and b - a >= 1000 * 48
 
 
 def test_host_shift_sampler_equals_the_input_generator():
